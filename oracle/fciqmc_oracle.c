@@ -1,0 +1,1156 @@
+/*
+ * Plain, slow CPU oracle for one FCIQMC imaginary-time step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, calls or
+ * includes this file; only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark load it.  It shares no code with the HIP path.
+ *
+ * Every routine follows the paper (Guther et al., "NECI: N-Electron
+ * Configuration Interaction with an emphasis on state-of-the-art stochastic
+ * methods", J. Chem. Phys. 2020) or a textbook definition it relies on, and
+ * says which.  Readings of passages that the paper leaves open are marked
+ * "Reading:".  Floating point is IEEE binary64 evaluated one operation at a
+ * time (built with -ffp-contract=off, no fast-math): every `x = y op z` below
+ * is one rounding, in the order written.
+ *
+ * Determinants.  A determinant is an occupation bit string over 2N spin
+ * orbitals (Appendix A, "Stochastic excitation generation").  Internally the
+ * oracle keeps it as two spatial-orbital masks (alpha, beta).  Canonical
+ * spin-orbital order (Reading: the paper fixes no order) is all alpha
+ * orbitals 0..N-1 first, then all beta orbitals (canonical index N+p).
+ * Two storage layouts are used to key the random numbers:
+ *   1 word  (N <= 32): alpha in bits 0..31, beta in bits 32..63;
+ *   2 words (N <= 64): word 0 = alpha, word 1 = beta.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x64-10 counter-based generator (Salmon, Moraes, Dror, Shaw,        */
+/* "Parallel random numbers: as easy as 1, 2, 3", SC'11).  The paper uses a   */
+/* sequential Mersenne twister (dSFMT, Sec. I); Reading: a counter-based     */
+/* stream keyed by the walker's identity replaces it so that the result does */
+/* not depend on how walkers are distributed over threads.                   */
+/* ------------------------------------------------------------------------- */
+#define PHILOX_M0 0xD2E7470EE14C6C93ULL
+#define PHILOX_M1 0xCA5A826395121157ULL
+#define PHILOX_W0 0x9E3779B97F4A7C15ULL
+#define PHILOX_W1 0xBB67AE8584CAA73BULL
+
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        u128 p0 = (u128)PHILOX_M0 * c0;
+        u128 p1 = (u128)PHILOX_M1 * c2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Discrete choice in [0, m): floor(x * m / 2^64). */
+static uint64_t pick(uint64_t x, uint64_t m)
+{
+    return (uint64_t)(((u128)x * (u128)m) >> 64);
+}
+
+/* Uniform double in [0, 1) with 53 random bits. */
+static double unif(uint64_t x)
+{
+    return (double)(x >> 11) * (1.0 / 9007199254740992.0);
+}
+
+enum { PURPOSE_SPAWN = 0, PURPOSE_SPAWN2 = 1, PURPOSE_DEATH = 2, PURPOSE_ANN = 4 };
+
+/* ------------------------------------------------------------------------- */
+/* System: integrals and derived tables.                                      */
+/* ------------------------------------------------------------------------- */
+typedef struct { uint64_t a, b; } det_t;
+
+typedef struct {
+    int N, na, nb, words;
+    double e_core;
+    double *h;      /* N*N, h[p*N+q] */
+    double *eri4;   /* N^4 chemists' (pq|rs) at ((p*N+q)*N+r)*N+s */
+    int *deg;       /* lattice degree per site */
+    int *nbr;       /* N*N: ascending neighbour list of each site */
+    /* pre-computed heat-bath tables (Appendix, pre-computed heat-bath sampling) */
+    double *hb_w_same;   /* [pair I<J][pair A<B] weights over spatial indices */
+    double *hb_w_opp;    /* [I*N+J][A*N+B] weights */
+    double *hb_sum_same; /* per (i<j) */
+    double *hb_sum_opp;  /* per (I,J) */
+    double *hb_p_same, *hb_p_opp; /* alias keep-probabilities */
+    int *hb_a_same, *hb_a_opp;    /* alias columns */
+} orc_sys;
+
+static double eri(const orc_sys *s, int p, int q, int r, int t)
+{
+    int N = s->N;
+    return s->eri4[((size_t)(p * N + q) * N + r) * N + t];
+}
+
+static int tri(int p, int q) { return p >= q ? p * (p + 1) / 2 + q : q * (q + 1) / 2 + p; }
+
+/* Load integrals: h (N*N) and the 8-fold packed (pq|rs). The full tensor is
+ * filled by copying packed values to every permutation (no arithmetic). */
+orc_sys *orc_sys_create(int N, int na, int nb, double e_core, const double *h,
+                        const double *eri_packed)
+{
+    orc_sys *s = (orc_sys *)calloc(1, sizeof(orc_sys));
+    s->N = N; s->na = na; s->nb = nb; s->e_core = e_core;
+    s->words = (N <= 32) ? 1 : 2;
+    s->h = (double *)malloc(sizeof(double) * N * N);
+    memcpy(s->h, h, sizeof(double) * N * N);
+    s->eri4 = (double *)malloc(sizeof(double) * (size_t)N * N * N * N);
+    for (int p = 0; p < N; ++p)
+        for (int q = 0; q < N; ++q)
+            for (int r = 0; r < N; ++r)
+                for (int t = 0; t < N; ++t) {
+                    int P = tri(p, q), Q = tri(r, t);
+                    int PQ = tri(P, Q);
+                    s->eri4[((size_t)(p * N + q) * N + r) * N + t] = eri_packed[PQ];
+                }
+    /* lattice neighbours: the distinct q != p with h_pq != 0, ascending */
+    s->deg = (int *)calloc(N, sizeof(int));
+    s->nbr = (int *)calloc((size_t)N * N, sizeof(int));
+    for (int p = 0; p < N; ++p)
+        for (int q = 0; q < N; ++q)
+            if (q != p && h[p * N + q] != 0.0)
+                s->nbr[p * N + s->deg[p]++] = q;
+    return s;
+}
+
+void orc_sys_set_words(orc_sys *s, int words) { s->words = words; }
+
+void orc_sys_free(orc_sys *s)
+{
+    if (!s) return;
+    free(s->h); free(s->eri4); free(s->deg); free(s->nbr);
+    free(s->hb_w_same); free(s->hb_w_opp); free(s->hb_sum_same); free(s->hb_sum_opp);
+    free(s->hb_p_same); free(s->hb_p_opp); free(s->hb_a_same); free(s->hb_a_opp);
+    free(s);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Determinant helpers, by explicit loops over spin orbitals.                */
+/* ------------------------------------------------------------------------- */
+static int so_spin(const orc_sys *s, int so) { return so >= s->N; }        /* 0 alpha, 1 beta */
+static int so_orb(const orc_sys *s, int so) { return so >= s->N ? so - s->N : so; }
+
+static int det_occ(const orc_sys *s, det_t d, int so)
+{
+    int p = so_orb(s, so);
+    return so_spin(s, so) ? (int)((d.b >> p) & 1) : (int)((d.a >> p) & 1);
+}
+
+static void det_set(const orc_sys *s, det_t *d, int so, int v)
+{
+    int p = so_orb(s, so);
+    uint64_t *w = so_spin(s, so) ? &d->b : &d->a;
+    if (v) *w |= (1ULL << p); else *w &= ~(1ULL << p);
+}
+
+/* Occupied spin orbitals in canonical order. */
+static int det_occ_list(const orc_sys *s, det_t d, int *occ)
+{
+    int n = 0;
+    for (int so = 0; so < 2 * s->N; ++so)
+        if (det_occ(s, d, so)) occ[n++] = so;
+    return n;
+}
+
+/* Number of occupied spin orbitals with canonical index below `so`. */
+static int det_below(const orc_sys *s, det_t d, int so)
+{
+    int c = 0;
+    for (int x = 0; x < so; ++x) c += det_occ(s, d, x);
+    return c;
+}
+
+/* Second-quantised operators applied to a determinant, right to left: each
+ * contributes (-1)^(occupied orbitals below it in the current string). */
+static int op_annihilate(const orc_sys *s, det_t *d, int so)
+{
+    int par = det_below(s, *d, so) & 1;
+    det_set(s, d, so, 0);
+    return par;
+}
+
+static int op_create(const orc_sys *s, det_t *d, int so)
+{
+    int par = det_below(s, *d, so) & 1;
+    det_set(s, d, so, 1);
+    return par;
+}
+
+static void layout_words(const orc_sys *s, det_t d, uint64_t *c0, uint64_t *c1)
+{
+    if (s->words == 1) { *c0 = d.a | (d.b << 32); *c1 = 0; }
+    else { *c0 = d.a; *c1 = d.b; }
+}
+
+static det_t from_layout(const orc_sys *s, uint64_t w0, uint64_t w1)
+{
+    det_t d;
+    if (s->words == 1) { d.a = w0 & 0xFFFFFFFFULL; d.b = w0 >> 32; }
+    else { d.a = w0; d.b = w1; }
+    return d;
+}
+
+static int det_cmp(det_t x, det_t y)
+{
+    if (x.a != y.a) return x.a < y.a ? -1 : 1;
+    if (x.b != y.b) return x.b < y.b ? -1 : 1;
+    return 0;
+}
+
+static int det_eq(det_t x, det_t y) { return x.a == y.a && x.b == y.b; }
+
+/* ------------------------------------------------------------------------- */
+/* Slater-Condon matrix elements.  The paper gives the double-excitation     */
+/* element <ij||ab> = <ij|ab> - <ij|ba> (Appendix, uniform excitation        */
+/* generation) and notes that the exchange part vanishes for opposite spins  */
+/* (Appendix, Cauchy-Schwarz doubles).  The remaining rules are the textbook */
+/* Slater-Condon rules for H = sum h_pq a+_p a_q + 1/2 sum <pq|rs>           */
+/* a+_p a+_q a_s a_r with <pq|rs> = (pr|qs) d(s_p,s_r) d(s_q,s_s).           */
+/* ------------------------------------------------------------------------- */
+
+/* Diagonal element: sum_p h_pp + sum_{p<q} [(pp|qq) - d(s_p,s_q)(pq|qp)]. */
+double orc_hdiag_det(const orc_sys *s, det_t d)
+{
+    int occ[128];
+    int n = det_occ_list(s, d, occ);
+    double acc = 0.0;
+    for (int x = 0; x < n; ++x) {
+        int p = so_orb(s, occ[x]);
+        acc = acc + s->h[p * s->N + p];
+    }
+    for (int x = 0; x < n; ++x)
+        for (int y = x + 1; y < n; ++y) {
+            int p = so_orb(s, occ[x]), q = so_orb(s, occ[y]);
+            if (so_spin(s, occ[x]) != so_spin(s, occ[y])) {
+                acc = acc + eri(s, p, p, q, q);
+            } else {
+                double v = eri(s, p, p, q, q) - eri(s, p, q, q, p);
+                acc = acc + v;
+            }
+        }
+    return acc;
+}
+
+/* <D_j|H|D_i> for D_j = sgn a+_a a_i D_i (same spin), summing over the
+ * electrons of D_i other than i in canonical order. */
+static double hsingle(const orc_sys *s, det_t d, int i, int a)
+{
+    int occ[128];
+    int n = det_occ_list(s, d, occ);
+    int pi = so_orb(s, i), pa = so_orb(s, a), sig = so_spin(s, i);
+    double v = s->h[pi * s->N + pa];
+    for (int x = 0; x < n; ++x) {
+        int k = occ[x];
+        if (k == i) continue;
+        int pk = so_orb(s, k);
+        if (so_spin(s, k) != sig) {
+            v = v + eri(s, pi, pa, pk, pk);
+        } else {
+            double t = eri(s, pi, pa, pk, pk) - eri(s, pi, pk, pk, pa);
+            v = v + t;
+        }
+    }
+    det_t t = d;
+    int par = op_annihilate(s, &t, i);
+    par ^= op_create(s, &t, a);
+    return par ? -v : v;
+}
+
+/* <D_j|H|D_i> for D_j = sgn a+_a a+_b a_j a_i D_i, i<j and a<b canonical.
+ * The coefficient of that operator string in H is <ab||ij>:
+ * (ai|bj) d(s_a,s_i) d(s_b,s_j) - (aj|bi) d(s_a,s_j) d(s_b,s_i). */
+static double hdouble(const orc_sys *s, det_t d, int i, int j, int a, int b)
+{
+    int pi = so_orb(s, i), pj = so_orb(s, j), pa = so_orb(s, a), pb = so_orb(s, b);
+    int si = so_spin(s, i), sj = so_spin(s, j), sa = so_spin(s, a), sb = so_spin(s, b);
+    double direct = (sa == si && sb == sj) ? eri(s, pa, pi, pb, pj) : 0.0;
+    double exch = (sa == sj && sb == si) ? eri(s, pa, pj, pb, pi) : 0.0;
+    double v;
+    if (si == sj) v = direct - exch;     /* same spin: both terms */
+    else v = (sa == si) ? direct : -exch; /* opposite spin: one term survives */
+    det_t t = d;
+    int par = op_annihilate(s, &t, i);
+    par ^= op_annihilate(s, &t, j);
+    par ^= op_create(s, &t, b);
+    par ^= op_create(s, &t, a);
+    return par ? -v : v;
+}
+
+/* Generic <D2|H|D1> by excitation level (0, 1, 2; zero beyond). */
+double orc_hij_det(const orc_sys *s, det_t d1, det_t d2)
+{
+    int rem[4], add[4], nr = 0, na = 0;
+    for (int so = 0; so < 2 * s->N; ++so) {
+        int o1 = det_occ(s, d1, so), o2 = det_occ(s, d2, so);
+        if (o1 && !o2) { if (nr < 4) rem[nr] = so; nr++; }
+        if (!o1 && o2) { if (na < 4) add[na] = so; na++; }
+    }
+    if (nr != na) return 0.0;
+    if (nr == 0) return orc_hdiag_det(s, d1);
+    if (nr == 1) {
+        if (so_spin(s, rem[0]) != so_spin(s, add[0])) return 0.0;
+        return hsingle(s, d1, rem[0], add[0]);
+    }
+    if (nr == 2) {
+        int sr = so_spin(s, rem[0]) + so_spin(s, rem[1]);
+        int sa = so_spin(s, add[0]) + so_spin(s, add[1]);
+        if (sr != sa) return 0.0;
+        return hdouble(s, d1, rem[0], rem[1], add[0], add[1]);
+    }
+    return 0.0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Excitation generators.  Each returns 1 and fills (target, p_gen, H) or    */
+/* returns 0 for a null draw.  p_gen is the exact probability of producing   */
+/* the target from this determinant (Sec. II; the spawn is unbiased if       */
+/* p_gen > 0 wherever H != 0).                                               */
+/* ------------------------------------------------------------------------- */
+
+/* Unoccupied spin orbitals of spin sigma, ascending. */
+static int holes_of_spin(const orc_sys *s, det_t d, int sigma, int *out)
+{
+    int h = 0;
+    for (int p = 0; p < s->N; ++p) {
+        int so = sigma ? s->N + p : p;
+        if (!det_occ(s, d, so)) out[h++] = so;
+    }
+    return h;
+}
+
+/* Count of choices for the uniform generator's second index, given the first. */
+uint64_t orc_uniform_count2(const orc_sys *s, det_t d, int single, uint64_t idx1)
+{
+    int occ[128], hol[64], hb[64];
+    int n = det_occ_list(s, d, occ);
+    if (single) {
+        int sig = so_spin(s, occ[idx1]);
+        return (uint64_t)holes_of_spin(s, d, sig, hol);
+    }
+    int e1 = -1, e2 = -1;
+    uint64_t c = 0;
+    for (int x = 0; x < n && e1 < 0; ++x)
+        for (int y = x + 1; y < n; ++y) {
+            if (c == idx1) { e1 = x; e2 = y; break; }
+            c++;
+        }
+    int i = occ[e1], j = occ[e2];
+    if (so_spin(s, i) == so_spin(s, j)) {
+        uint64_t h = (uint64_t)holes_of_spin(s, d, so_spin(s, i), hol);
+        return h * (h - (h > 0)) / 2;
+    }
+    uint64_t ha = (uint64_t)holes_of_spin(s, d, 0, hol);
+    uint64_t hbeta = (uint64_t)holes_of_spin(s, d, 1, hb);
+    return ha * hbeta;
+}
+
+/* Uniform generator after the random indices have been drawn (Appendix,
+ * uniform generation with spin imposed through conditional probabilities):
+ *   single: electron idx1 of the n occupied (canonical order), hole idx2 of
+ *           the same-spin holes (ascending);
+ *           p_gen = p_single / (n * h_sigma);
+ *   double: electron pair idx1 of the C(n,2) pairs (lexicographic);
+ *           same spin: hole pair idx2 of C(h_sigma,2) same-spin pairs (lexicographic);
+ *           opposite:  idx2 = A*h_beta + B picks alpha hole A and beta hole B;
+ *           p_gen = (1 - p_single) / (C(n,2) * #hole pairs). */
+int orc_uniform_apply(const orc_sys *s, det_t d, int single, uint64_t idx1, uint64_t idx2,
+                      double p_single, det_t *tgt, double *pgen)
+{
+    int occ[128], hol[64], ha[64], hb[64];
+    int n = det_occ_list(s, d, occ);
+    if (single) {
+        int i = occ[idx1];
+        int h = holes_of_spin(s, d, so_spin(s, i), hol);
+        if (h == 0) return 0;
+        int a = hol[idx2];
+        det_t t = d; det_set(s, &t, i, 0); det_set(s, &t, a, 1);
+        *tgt = t;
+        *pgen = p_single / (double)((uint64_t)n * (uint64_t)h);
+        return 1;
+    }
+    uint64_t npair = (uint64_t)n * (uint64_t)(n - 1) / 2;
+    int e1 = -1, e2 = -1;
+    uint64_t c = 0;
+    for (int x = 0; x < n && e1 < 0; ++x)
+        for (int y = x + 1; y < n; ++y) {
+            if (c == idx1) { e1 = x; e2 = y; break; }
+            c++;
+        }
+    int i = occ[e1], j = occ[e2];
+    int a, b;
+    uint64_t nh;
+    if (so_spin(s, i) == so_spin(s, j)) {
+        int h = holes_of_spin(s, d, so_spin(s, i), hol);
+        if (h < 2) return 0;
+        nh = (uint64_t)h * (uint64_t)(h - 1) / 2;
+        int f1 = -1, f2 = -1;
+        uint64_t cc = 0;
+        for (int x = 0; x < h && f1 < 0; ++x)
+            for (int y = x + 1; y < h; ++y) {
+                if (cc == idx2) { f1 = x; f2 = y; break; }
+                cc++;
+            }
+        a = hol[f1]; b = hol[f2];
+    } else {
+        int nha = holes_of_spin(s, d, 0, ha);
+        int nhb = holes_of_spin(s, d, 1, hb);
+        nh = (uint64_t)nha * (uint64_t)nhb;
+        if (nh == 0) return 0;
+        a = ha[idx2 / (uint64_t)nhb];
+        b = hb[idx2 % (uint64_t)nhb];
+    }
+    det_t t = d;
+    det_set(s, &t, i, 0); det_set(s, &t, j, 0); det_set(s, &t, a, 1); det_set(s, &t, b, 1);
+    *tgt = t;
+    double pd = 1.0 - p_single;
+    *pgen = pd / (double)(npair * nh);
+    return 1;
+}
+
+/* Uniform generator from one Philox block r[4]: lane 0 decides single vs
+ * double, lane 1 the electron(s), lane 2 the hole(s). */
+static int gen_uniform(const orc_sys *s, det_t d, const uint64_t r[4], double p_single,
+                       det_t *tgt, double *pgen)
+{
+    int n = s->na + s->nb;
+    int single = unif(r[0]) < p_single;
+    if (single) {
+        uint64_t idx1 = pick(r[1], (uint64_t)n);
+        uint64_t c2 = orc_uniform_count2(s, d, 1, idx1);
+        if (c2 == 0) return 0;
+        return orc_uniform_apply(s, d, 1, idx1, pick(r[2], c2), p_single, tgt, pgen);
+    }
+    if (n < 2) return 0;
+    uint64_t npair = (uint64_t)n * (uint64_t)(n - 1) / 2;
+    uint64_t idx1 = pick(r[1], npair);
+    uint64_t c2 = orc_uniform_count2(s, d, 0, idx1);
+    if (c2 == 0) return 0;
+    return orc_uniform_apply(s, d, 0, idx1, pick(r[2], c2), p_single, tgt, pgen);
+}
+
+/* Real-space lattice generator.  The paper names it (Sec. II) without an
+ * algorithm.  Reading: pick one of the n electrons uniformly, then one of the
+ * z_p lattice neighbours of its site (the distinct q with h_pq != 0,
+ * ascending), same spin; null if that orbital is occupied.
+ * p_gen = 1 / (n * z_p).  Exact for Hubbard-type Hamiltonians, whose only
+ * off-diagonal elements are hoppings along bonds. */
+int orc_lattice_apply(const orc_sys *s, det_t d, uint64_t idx1, uint64_t idx2,
+                      det_t *tgt, double *pgen)
+{
+    int occ[128];
+    int n = det_occ_list(s, d, occ);
+    int i = occ[idx1];
+    int p = so_orb(s, i);
+    int z = s->deg[p];
+    if (z == 0) return 0;
+    int q = s->nbr[p * s->N + (int)idx2];
+    int a = so_spin(s, i) ? s->N + q : q;
+    if (det_occ(s, d, a)) return 0;
+    det_t t = d; det_set(s, &t, i, 0); det_set(s, &t, a, 1);
+    *tgt = t;
+    *pgen = 1.0 / (double)((uint64_t)n * (uint64_t)z);
+    return 1;
+}
+
+static int gen_lattice(const orc_sys *s, det_t d, const uint64_t r[4], det_t *tgt, double *pgen)
+{
+    int occ[128];
+    int n = det_occ_list(s, d, occ);
+    uint64_t idx1 = pick(r[1], (uint64_t)n);
+    int p = so_orb(s, occ[idx1]);
+    int z = s->deg[p];
+    if (z == 0) return 0;
+    return orc_lattice_apply(s, d, idx1, pick(r[2], (uint64_t)z), tgt, pgen);
+}
+
+int orc_lattice_degree(const orc_sys *s, int p) { return s->deg[p]; }
+
+/* ------------------------------------------------------------------------- */
+/* Walker population and the step.                                            */
+/* ------------------------------------------------------------------------- */
+enum { MODE_INTEGER = 0, MODE_REAL = 1 };
+enum { GEN_UNIFORM = 0, GEN_LATTICE = 1, GEN_PCHB = 2 };
+
+typedef struct {
+    det_t d;
+    double v;
+    double diag; /* H_ii - H_00 */
+} ent_t;
+
+typedef struct {
+    det_t d;
+    double v;
+    int init;
+} rec_t;
+
+typedef struct {
+    double tau, target, n_a, c_min, zeta, p_single, p_opp;
+    int interval, mode, gen;
+    uint64_t seed, replica;
+} orc_params;
+
+typedef struct {
+    double nw, nref, enum_, shift;
+    int64_t ndets, attempts, spawns;
+    int vary, bloom;
+} orc_stats;
+
+typedef struct {
+    const orc_sys *s;
+    orc_params p;
+    det_t ref;
+    double h00;
+    int64_t t;
+    double S;
+    int vary;
+    int64_t t_last;
+    double nw_last;
+    ent_t *list;
+    int64_t n, cap;
+} orc_run;
+
+static int ent_cmp(const void *x, const void *y)
+{
+    return det_cmp(((const ent_t *)x)->d, ((const ent_t *)y)->d);
+}
+
+/* Records sort by target; ties keep emission order (parent order, then k). */
+typedef struct { rec_t r; int64_t seq; } srec_t;
+static int srec_cmp(const void *x, const void *y)
+{
+    const srec_t *a = (const srec_t *)x, *b = (const srec_t *)y;
+    int c = det_cmp(a->r.d, b->r.d);
+    if (c) return c;
+    return a->seq < b->seq ? -1 : (a->seq > b->seq);
+}
+
+static void draw(const orc_run *r, det_t d, int64_t t, uint64_t k, int purpose, uint64_t out[4])
+{
+    uint64_t ctr[4], key[2] = {r->p.seed, r->p.replica};
+    layout_words(r->s, d, &ctr[0], &ctr[1]);
+    ctr[2] = (uint64_t)t;
+    ctr[3] = (k << 8) | (uint64_t)purpose;
+    orc_philox4x64_10(ctr, key, out);
+}
+
+orc_run *orc_run_create(const orc_sys *s, const orc_params *p, uint64_t ref_a, uint64_t ref_b)
+{
+    orc_run *r = (orc_run *)calloc(1, sizeof(orc_run));
+    r->s = s;
+    r->p = *p;
+    if (r->p.p_single < 0.0) {
+        /* Appendix, "Preparing for excitation generation": p_sing ~ nN/(nN + n^2 N^2) */
+        double n = (double)(s->na + s->nb), N = (double)s->N;
+        double nN = n * N;
+        double n2N2 = nN * nN;
+        r->p.p_single = nN / (nN + n2N2);
+    }
+    if (ref_a == 0 && ref_b == 0) {
+        ref_a = (s->na == 64) ? ~0ULL : ((1ULL << s->na) - 1);
+        ref_b = (s->nb == 64) ? ~0ULL : ((1ULL << s->nb) - 1);
+    }
+    r->ref.a = ref_a; r->ref.b = ref_b;
+    r->h00 = orc_hdiag_det(s, r->ref);
+    r->cap = 16;
+    r->list = (ent_t *)malloc(sizeof(ent_t) * r->cap);
+    return r;
+}
+
+void orc_run_free(orc_run *r)
+{
+    if (!r) return;
+    free(r->list);
+    free(r);
+}
+
+double orc_run_h00(const orc_run *r) { return r->h00; }
+double orc_run_p_single(const orc_run *r) { return r->p.p_single; }
+
+/* Replace the population; values are stored as given, zero entries dropped. */
+void orc_run_set_walkers(orc_run *r, const uint64_t *a, const uint64_t *b, const double *v, int64_t n)
+{
+    free(r->list);
+    r->cap = n > 16 ? n : 16;
+    r->list = (ent_t *)malloc(sizeof(ent_t) * r->cap);
+    r->n = 0;
+    for (int64_t x = 0; x < n; ++x) {
+        if (v[x] == 0.0) continue;
+        ent_t e;
+        e.d.a = a[x]; e.d.b = b[x]; e.v = v[x];
+        e.diag = orc_hdiag_det(r->s, e.d) - r->h00;
+        r->list[r->n++] = e;
+    }
+    qsort(r->list, r->n, sizeof(ent_t), ent_cmp);
+}
+
+void orc_run_set_state(orc_run *r, int64_t t, double S, int vary, int64_t t_last, double nw_last)
+{
+    r->t = t; r->S = S; r->vary = vary; r->t_last = t_last; r->nw_last = nw_last;
+}
+
+void orc_run_get_state(const orc_run *r, int64_t *t, double *S, int *vary, int64_t *t_last,
+                       double *nw_last)
+{
+    *t = r->t; *S = r->S; *vary = r->vary; *t_last = r->t_last; *nw_last = r->nw_last;
+}
+
+int64_t orc_run_size(const orc_run *r) { return r->n; }
+
+void orc_run_get_walkers(const orc_run *r, uint64_t *a, uint64_t *b, double *v, double *diag)
+{
+    for (int64_t x = 0; x < r->n; ++x) {
+        a[x] = r->list[x].d.a; b[x] = r->list[x].d.b; v[x] = r->list[x].v;
+        if (diag) diag[x] = r->list[x].diag;
+    }
+}
+
+static int64_t find(const ent_t *list, int64_t n, det_t d)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        int c = det_cmp(list[mid].d, d);
+        if (c == 0) return mid;
+        if (c < 0) lo = mid + 1; else hi = mid;
+    }
+    return -1;
+}
+
+/* Stochastic compression to C_min (Sec. II, the compressed storage rule):
+ * keep |x| >= C_min, else sign(x) C_min with probability |x|/C_min, else 0. */
+static double round_cmin(double x, double cmin, double u)
+{
+    double ax = fabs(x);
+    if (ax >= cmin || x == 0.0) return x;
+    double pr = ax / cmin;
+    if (u < pr) return x < 0.0 ? -cmin : cmin;
+    return 0.0;
+}
+
+int orc_pchb_gen(const orc_sys *s, det_t d, const uint64_t r1[4], const uint64_t r2[4],
+                 double p_single, double p_opp, det_t *tgt, double *pgen);
+
+/* One imaginary-time step, Eq. (projector) split as Eq. (fciqmc_dyn):
+ * (a) spawning from C(tau), (b) death in place, (c) annihilation with the
+ * initiator rule; then the estimators and the shift update. */
+int orc_run_step(orc_run *r, orc_stats *st)
+{
+    const orc_sys *s = r->s;
+    const orc_params *p = &r->p;
+    int64_t t = r->t;
+    int integer = p->mode == MODE_INTEGER;
+    memset(st, 0, sizeof(*st));
+
+    /* (a) spawning.  Every walker of every occupied determinant makes one
+     * attempt (integer mode: |C_i| attempts; real mode: ceil(|C_i|)).
+     * Attempt k of determinant D_i draws Philox block (D_i, t, k, SPAWN). */
+    int64_t rcap = 1024, nrec = 0;
+    srec_t *recs = (srec_t *)malloc(sizeof(srec_t) * rcap);
+    for (int64_t x = 0; x < r->n; ++x) {
+        const ent_t *e = &r->list[x];
+        double C = e->v;
+        double aC = fabs(C);
+        int64_t m = integer ? (int64_t)aC : (int64_t)ceil(aC);
+        /* initiator: |C_i| above n_a (Sec. II); Reading: the reference always
+         * counts as one; a negative n_a switches the approximation off. */
+        int init = (p->n_a < 0.0) || (aC > p->n_a) || det_eq(e->d, r->ref);
+        st->attempts += m;
+        for (int64_t k = 0; k < m; ++k) {
+            uint64_t rr[4];
+            draw(r, e->d, t, (uint64_t)k, PURPOSE_SPAWN, rr);
+            det_t tgt;
+            double pgen;
+            int ok;
+            if (p->gen == GEN_UNIFORM) ok = gen_uniform(s, e->d, rr, p->p_single, &tgt, &pgen);
+            else if (p->gen == GEN_LATTICE) ok = gen_lattice(s, e->d, rr, &tgt, &pgen);
+            else {
+                uint64_t r2[4];
+                draw(r, e->d, t, (uint64_t)k, PURPOSE_SPAWN2, r2);
+                ok = orc_pchb_gen(s, e->d, rr, r2, p->p_single, p->p_opp, &tgt, &pgen);
+            }
+            if (!ok) continue;
+            double H = orc_hij_det(s, e->d, tgt);
+            if (H == 0.0) continue;
+            double amt;
+            if (integer) {
+                /* p_s = dtau |H_ij| / p_gen (Sec. II); the integer part spawns
+                 * deterministically, the fraction with that probability. */
+                double num = p->tau * fabs(H);
+                double ps = num / pgen;
+                double fl = floor(ps);
+                double fr = ps - fl;
+                double nn = fl + (unif(rr[3]) < fr ? 1.0 : 0.0);
+                if (nn == 0.0) continue;
+                if (nn > 1073741824.0) st->bloom = 1;
+                /* Reading: the child's sign is -sgn(H_ji) sgn(C_i), the sign of
+                 * the off-diagonal term -dtau H_ji C_i of Eq. (projector); the
+                 * "+" printed under the spawn term of Eq. (fciqmc_dyn) is taken
+                 * as a typo. */
+                amt = ((H > 0.0) == (C > 0.0)) ? -nn : nn;
+            } else {
+                double x1 = p->tau * H;
+                double x2 = x1 * C;
+                double d1 = pgen * (double)m;
+                double amp = -(x2 / d1);
+                amt = round_cmin(amp, p->c_min, unif(rr[3]));
+                if (amt == 0.0) continue;
+            }
+            if (nrec == rcap) {
+                rcap *= 2;
+                recs = (srec_t *)realloc(recs, sizeof(srec_t) * rcap);
+            }
+            recs[nrec].r.d = tgt;
+            recs[nrec].r.v = amt;
+            recs[nrec].r.init = init;
+            recs[nrec].seq = nrec;
+            nrec++;
+        }
+    }
+    st->spawns = nrec;
+
+    /* (b) death: C_i <- (1 - dtau (H_ii - S)) C_i, then stochastic rounding
+     * (integer mode: to the neighbouring integers; real mode: the C_min rule). */
+    double *post = (double *)malloc(sizeof(double) * (r->n > 0 ? r->n : 1));
+    for (int64_t x = 0; x < r->n; ++x) {
+        const ent_t *e = &r->list[x];
+        double t1 = e->diag - r->S;
+        double t2 = p->tau * t1;
+        double f = 1.0 - t2;
+        double xv = f * e->v;
+        uint64_t rr[4];
+        draw(r, e->d, t, 0, PURPOSE_DEATH, rr);
+        double u = unif(rr[0]);
+        if (integer) {
+            double ax = fabs(xv);
+            double fl = floor(ax);
+            double fr = ax - fl;
+            double nn = fl + (u < fr ? 1.0 : 0.0);
+            post[x] = xv < 0.0 ? -nn : nn;
+        } else {
+            post[x] = round_cmin(xv, p->c_min, u);
+        }
+    }
+
+    /* (c) annihilation.  Sum all contributions per target.  Initiator rule
+     * (Sec. II): matrix elements between non-initiators and determinants with
+     * C(tau) = 0 are zeroed, i.e. a target unoccupied at tau only receives the
+     * contributions of initiator parents; an occupied target receives all. */
+    qsort(recs, nrec, sizeof(srec_t), srec_cmp);
+    int64_t ncap = r->n + nrec + 1;
+    ent_t *next = (ent_t *)malloc(sizeof(ent_t) * ncap);
+    int64_t nn = 0;
+    for (int64_t x = 0; x < r->n; ++x) {
+        next[nn] = r->list[x];
+        next[nn].v = post[x];
+        nn++;
+    }
+    int64_t n_old = nn;
+    for (int64_t x = 0; x < nrec;) {
+        int64_t y = x;
+        double sum_all = 0.0, sum_init = 0.0;
+        while (y < nrec && det_eq(recs[y].r.d, recs[x].r.d)) {
+            sum_all = sum_all + recs[y].r.v;
+            if (recs[y].r.init) sum_init = sum_init + recs[y].r.v;
+            y++;
+        }
+        int64_t at = find(r->list, r->n, recs[x].r.d);
+        if (at >= 0) {
+            next[at].v = next[at].v + sum_all;
+        } else if (sum_init != 0.0) {
+            next[nn].d = recs[x].r.d;
+            next[nn].v = sum_init;
+            next[nn].diag = orc_hdiag_det(s, recs[x].r.d) - r->h00;
+            nn++;
+        }
+        x = y;
+    }
+    (void)n_old;
+    if (!integer) {
+        for (int64_t x = 0; x < nn; ++x) {
+            double v = next[x].v;
+            if (v != 0.0 && fabs(v) < p->c_min) {
+                uint64_t rr[4];
+                draw(r, next[x].d, t, 0, PURPOSE_ANN, rr);
+                next[x].v = round_cmin(v, p->c_min, unif(rr[0]));
+            }
+        }
+    }
+    int64_t m = 0;
+    for (int64_t x = 0; x < nn; ++x)
+        if (next[x].v != 0.0) next[m++] = next[x];
+    qsort(next, m, sizeof(ent_t), ent_cmp);
+    free(r->list);
+    free(post);
+    free(recs);
+    r->list = next;
+    r->n = m;
+    r->cap = ncap;
+    r->t = t + 1;
+
+    /* Estimators: walker number N_w = sum |C_i|; projected energy
+     * E_Ref = <D_ref|H|Psi>/<D_ref|Psi> (Sec. "Trial wave functions"), kept as
+     * numerator sum_{j != ref} H_ref,j C_j and denominator C_ref. */
+    double nw = 0.0, nref = 0.0, en = 0.0;
+    for (int64_t x = 0; x < r->n; ++x) {
+        const ent_t *e = &r->list[x];
+        nw = nw + fabs(e->v);
+        if (det_eq(e->d, r->ref)) { nref = e->v; continue; }
+        int lvl = __builtin_popcountll(e->d.a ^ r->ref.a) + __builtin_popcountll(e->d.b ^ r->ref.b);
+        if (lvl == 2 || lvl == 4) {
+            double h = orc_hij_det(s, r->ref, e->d);
+            double c = h * e->v;
+            en = en + c;
+        }
+    }
+
+    /* Shift update.  The paper only says S is updated to match the ground-state
+     * energy (Sec. II).  Reading (original FCIQMC population control): S is 0
+     * (relative to H_00) until N_w first reaches the target; from then on every
+     * A steps S <- S - zeta/(A dtau) ln(N_w(t)/N_w(t-A)). */
+    int64_t T = r->t;
+    if (!r->vary) {
+        if (nw >= p->target) {
+            r->vary = 1;
+            r->t_last = T;
+            r->nw_last = nw;
+        }
+    } else if (T - r->t_last == (int64_t)p->interval) {
+        double c = p->zeta / ((double)p->interval * p->tau);
+        double ratio = nw / r->nw_last;
+        double l = log(ratio);
+        double dS = c * l;
+        r->S = r->S - dS;
+        r->t_last = T;
+        r->nw_last = nw;
+    }
+
+    st->nw = nw; st->nref = nref; st->enum_ = en; st->shift = r->S;
+    st->ndets = r->n; st->vary = r->vary;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Pre-computed heat-bath (PCHB) doubles (Appendix, pre-computed heat-bath     */
+/* sampling), Eq. (hbs): p(ab|ij) = |H_ij^ab| / sum_a'b' |H_ij^a'b'|, drawn by */
+/* Walker's alias method in O(1).                                             */
+/* Reading, over spatial orbitals (no p_exch split):                          */
+/*   opposite spin, electrons (I alpha, J beta) -> holes (A alpha, B beta):   */
+/*       row (I,J), column A*N+B, weight |(AI|BJ)|, zero if A=I or B=J;       */
+/*   same spin, electrons I<J -> holes A<B of the same spin:                  */
+/*       row and column lexicographic pairs, weight |(AI|BJ) - (AJ|BI)|,      */
+/*       zero if {A,B} meets {I,J}.                                           */
+/* Electron pairs are uniform within their class; the class is opposite spin */
+/* with probability p_opp.  A draw is null if a hole is occupied or if the    */
+/* row sums to zero.  Singles are uniform, as in the uniform generator.       */
+/* Random lanes: block SPAWN [0] single/double, [1] electron pair,            */
+/* [2] alias column, [3] acceptance; block SPAWN2 [0] alias coin, [1] class.  */
+/* ------------------------------------------------------------------------- */
+
+/* Alias table by Vose's construction with LIFO work lists filled in
+ * ascending column order:  scaled_c = (w_c K) / sum; while both lists are
+ * non-empty pop s (small) and l (large): prob_s = scaled_s, alias_s = l,
+ * scaled_l = (scaled_l + scaled_s) - 1, and l goes back to the small list if
+ * scaled_l < 1, else to the large list.  Left-overs get prob 1. */
+static void alias_build(const double *w, int K, double sum, double *prob, int *alias,
+                        int *small, int *large, double *scaled)
+{
+    int ns = 0, nl = 0;
+    if (sum == 0.0) {
+        for (int c = 0; c < K; ++c) { prob[c] = 0.0; alias[c] = c; }
+        return;
+    }
+    for (int c = 0; c < K; ++c) {
+        double x = w[c] * (double)K;
+        scaled[c] = x / sum;
+        alias[c] = c;
+        if (scaled[c] < 1.0) small[ns++] = c; else large[nl++] = c;
+    }
+    while (ns > 0 && nl > 0) {
+        int s_ = small[--ns];
+        int l = large[--nl];
+        prob[s_] = scaled[s_];
+        alias[s_] = l;
+        double t = scaled[l] + scaled[s_];
+        scaled[l] = t - 1.0;
+        if (scaled[l] < 1.0) small[ns++] = l; else large[nl++] = l;
+    }
+    while (nl > 0) { int l = large[--nl]; prob[l] = 1.0; alias[l] = l; }
+    while (ns > 0) { int s_ = small[--ns]; prob[s_] = 1.0; alias[s_] = s_; }
+}
+
+void orc_pchb_build(orc_sys *s)
+{
+    int N = s->N;
+    int np = N * (N - 1) / 2;
+    int NN = N * N;
+    free(s->hb_w_same); free(s->hb_w_opp); free(s->hb_sum_same); free(s->hb_sum_opp);
+    free(s->hb_p_same); free(s->hb_p_opp); free(s->hb_a_same); free(s->hb_a_opp);
+    s->hb_w_same = (double *)calloc((size_t)np * np + 1, sizeof(double));
+    s->hb_p_same = (double *)calloc((size_t)np * np + 1, sizeof(double));
+    s->hb_a_same = (int *)calloc((size_t)np * np + 1, sizeof(int));
+    s->hb_sum_same = (double *)calloc(np + 1, sizeof(double));
+    s->hb_w_opp = (double *)calloc((size_t)NN * NN, sizeof(double));
+    s->hb_p_opp = (double *)calloc((size_t)NN * NN, sizeof(double));
+    s->hb_a_opp = (int *)calloc((size_t)NN * NN, sizeof(int));
+    s->hb_sum_opp = (double *)calloc(NN, sizeof(double));
+    int kmax = NN > np ? NN : np;
+    int *small = (int *)malloc(sizeof(int) * kmax);
+    int *large = (int *)malloc(sizeof(int) * kmax);
+    double *scaled = (double *)malloc(sizeof(double) * kmax);
+    int ij = 0;
+    for (int I = 0; I < N; ++I)
+        for (int J = I + 1; J < N; ++J, ++ij) {
+            double sum = 0.0;
+            double *w = s->hb_w_same + (size_t)ij * np;
+            int ab = 0;
+            for (int A = 0; A < N; ++A)
+                for (int B = A + 1; B < N; ++B, ++ab) {
+                    double v = eri(s, A, I, B, J) - eri(s, A, J, B, I);
+                    double x = fabs(v);
+                    if (A == I || A == J || B == I || B == J) x = 0.0;
+                    w[ab] = x;
+                    sum = sum + x;
+                }
+            s->hb_sum_same[ij] = sum;
+            alias_build(w, np, sum, s->hb_p_same + (size_t)ij * np, s->hb_a_same + (size_t)ij * np,
+                        small, large, scaled);
+        }
+    for (int I = 0; I < N; ++I)
+        for (int J = 0; J < N; ++J) {
+            double sum = 0.0;
+            double *w = s->hb_w_opp + (size_t)(I * N + J) * NN;
+            for (int A = 0; A < N; ++A)
+                for (int B = 0; B < N; ++B) {
+                    double x = fabs(eri(s, A, I, B, J));
+                    if (A == I || B == J) x = 0.0;
+                    w[A * N + B] = x;
+                    sum = sum + x;
+                }
+            s->hb_sum_opp[I * N + J] = sum;
+            alias_build(w, NN, sum, s->hb_p_opp + (size_t)(I * N + J) * NN,
+                        s->hb_a_opp + (size_t)(I * N + J) * NN, small, large, scaled);
+        }
+    free(small); free(large); free(scaled);
+}
+
+/* Alias draw: column c uniform, kept with probability prob_c, else alias_c. */
+static int alias_draw(const double *prob, const int *alias, int K, uint64_t xc, double coin)
+{
+    int c = (int)pick(xc, (uint64_t)K);
+    return coin < prob[c] ? c : alias[c];
+}
+
+int orc_pchb_gen(const orc_sys *s, det_t d, const uint64_t r1[4], const uint64_t r2[4],
+                 double p_single, double p_opp, det_t *tgt, double *pgen)
+{
+    int N = s->N;
+    int n = s->na + s->nb;
+    if (unif(r1[0]) < p_single) {
+        uint64_t idx1 = pick(r1[1], (uint64_t)n);
+        uint64_t c2 = orc_uniform_count2(s, d, 1, idx1);
+        if (c2 == 0) return 0;
+        return orc_uniform_apply(s, d, 1, idx1, pick(r1[2], c2), p_single, tgt, pgen);
+    }
+    int occa[64], occb[64], na = 0, nb = 0;
+    for (int p = 0; p < N; ++p) {
+        if ((d.a >> p) & 1) occa[na++] = p;
+        if ((d.b >> p) & 1) occb[nb++] = p;
+    }
+    uint64_t n_opp = (uint64_t)na * (uint64_t)nb;
+    uint64_t npa = (uint64_t)na * (uint64_t)(na - (na > 0)) / 2;
+    uint64_t npb = (uint64_t)nb * (uint64_t)(nb - (nb > 0)) / 2;
+    uint64_t n_same = npa + npb;
+    double pd = 1.0 - p_single;
+    int opp = unif(r2[1]) < p_opp;
+    double coin = unif(r2[0]);
+    if (opp) {
+        if (n_opp == 0) return 0;
+        uint64_t q = pick(r1[1], n_opp);
+        int I = occa[q / (uint64_t)nb], J = occb[q % (uint64_t)nb];
+        double sum = s->hb_sum_opp[I * N + J];
+        if (sum == 0.0) return 0;
+        size_t row = (size_t)(I * N + J) * N * N;
+        int c = alias_draw(s->hb_p_opp + row, s->hb_a_opp + row, N * N, r1[2], coin);
+        double wc = s->hb_w_opp[row + c];
+        if (wc == 0.0) return 0;
+        int A = c / N, B = c % N;
+        if (((d.a >> A) & 1) || ((d.b >> B) & 1)) return 0;
+        det_t t = d;
+        t.a &= ~(1ULL << I); t.b &= ~(1ULL << J); t.a |= 1ULL << A; t.b |= 1ULL << B;
+        *tgt = t;
+        double p1 = pd * p_opp;
+        double p2 = p1 / (double)n_opp;
+        double pab = wc / sum;
+        *pgen = p2 * pab;
+        return 1;
+    }
+    if (n_same == 0) return 0;
+    uint64_t q = pick(r1[1], n_same);
+    int sig = q >= npa;
+    if (sig) q -= npa;
+    const int *occ = sig ? occb : occa;
+    int no = sig ? nb : na;
+    int e1 = -1, e2 = -1;
+    uint64_t cc = 0;
+    for (int x = 0; x < no && e1 < 0; ++x)
+        for (int y = x + 1; y < no; ++y) {
+            if (cc == q) { e1 = x; e2 = y; break; }
+            cc++;
+        }
+    int I = occ[e1], J = occ[e2];
+    int np = N * (N - 1) / 2;
+    int ij = I * (2 * N - I - 1) / 2 + (J - I - 1);
+    double sum = s->hb_sum_same[ij];
+    if (sum == 0.0) return 0;
+    size_t row = (size_t)ij * np;
+    int c = alias_draw(s->hb_p_same + row, s->hb_a_same + row, np, r1[2], coin);
+    double wc = s->hb_w_same[row + c];
+    if (wc == 0.0) return 0;
+    int A = -1, B = -1, cnt = 0;
+    for (int x = 0; x < N && A < 0; ++x)
+        for (int y = x + 1; y < N; ++y) {
+            if (cnt == c) { A = x; B = y; break; }
+            cnt++;
+        }
+    uint64_t mask = sig ? d.b : d.a;
+    if (((mask >> A) & 1) || ((mask >> B) & 1)) return 0;
+    mask &= ~(1ULL << I); mask &= ~(1ULL << J); mask |= 1ULL << A; mask |= 1ULL << B;
+    det_t t = d;
+    if (sig) t.b = mask; else t.a = mask;
+    *tgt = t;
+    double p1 = pd * (1.0 - p_opp);
+    double p2 = p1 / (double)n_same;
+    double pab = wc / sum;
+    *pgen = p2 * pab;
+    return 1;
+}
+
+/* Alias-table access for the reconstruction test: row of class `opp`. */
+void orc_pchb_row(const orc_sys *s, int opp, int row, double *w, double *prob, int *alias,
+                  double *sum)
+{
+    int N = s->N;
+    int K = opp ? N * N : N * (N - 1) / 2;
+    const double *W = opp ? s->hb_w_opp : s->hb_w_same;
+    const double *P = opp ? s->hb_p_opp : s->hb_p_same;
+    const int *A = opp ? s->hb_a_opp : s->hb_a_same;
+    for (int c = 0; c < K; ++c) {
+        w[c] = W[(size_t)row * K + c];
+        prob[c] = P[(size_t)row * K + c];
+        alias[c] = A[(size_t)row * K + c];
+    }
+    *sum = opp ? s->hb_sum_opp[row] : s->hb_sum_same[row];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Flat entry points for the Python wrapper (dets as alpha/beta mask pairs).  */
+/* ------------------------------------------------------------------------- */
+double orc_hdiag(const orc_sys *s, uint64_t a, uint64_t b)
+{
+    det_t d = {a, b};
+    return orc_hdiag_det(s, d);
+}
+
+double orc_hij(const orc_sys *s, uint64_t a1, uint64_t b1, uint64_t a2, uint64_t b2)
+{
+    det_t d1 = {a1, b1}, d2 = {a2, b2};
+    return orc_hij_det(s, d1, d2);
+}
+
+/* Draw-level generator entry (for frequency tests): returns 1 and the target
+ * for a null-free draw from the Philox block of (det, t, k). */
+int orc_generate(const orc_run *r, uint64_t a, uint64_t b, int64_t t, uint64_t k,
+                 uint64_t *ta, uint64_t *tb, double *pgen, double *H)
+{
+    det_t d = {a, b}, tgt;
+    uint64_t rr[4];
+    draw(r, d, t, k, PURPOSE_SPAWN, rr);
+    int ok;
+    if (r->p.gen == GEN_UNIFORM) ok = gen_uniform(r->s, d, rr, r->p.p_single, &tgt, pgen);
+    else if (r->p.gen == GEN_LATTICE) ok = gen_lattice(r->s, d, rr, &tgt, pgen);
+    else {
+        uint64_t r2[4];
+        draw(r, d, t, k, PURPOSE_SPAWN2, r2);
+        ok = orc_pchb_gen(r->s, d, rr, r2, r->p.p_single, r->p.p_opp, &tgt, pgen);
+    }
+    if (!ok) return 0;
+    *ta = tgt.a; *tb = tgt.b;
+    *H = orc_hij_det(r->s, d, tgt);
+    return 1;
+}
+
+int orc_uniform_apply_flat(const orc_sys *s, uint64_t a, uint64_t b, int single, uint64_t idx1,
+                           uint64_t idx2, double p_single, uint64_t *ta, uint64_t *tb, double *pgen)
+{
+    det_t d = {a, b}, t;
+    int ok = orc_uniform_apply(s, d, single, idx1, idx2, p_single, &t, pgen);
+    if (ok) { *ta = t.a; *tb = t.b; }
+    return ok;
+}
+
+uint64_t orc_uniform_count2_flat(const orc_sys *s, uint64_t a, uint64_t b, int single, uint64_t idx1)
+{
+    det_t d = {a, b};
+    return orc_uniform_count2(s, d, single, idx1);
+}
+
+int orc_lattice_apply_flat(const orc_sys *s, uint64_t a, uint64_t b, uint64_t idx1, uint64_t idx2,
+                           uint64_t *ta, uint64_t *tb, double *pgen)
+{
+    det_t d = {a, b}, t;
+    int ok = orc_lattice_apply(s, d, idx1, idx2, &t, pgen);
+    if (ok) { *ta = t.a; *tb = t.b; }
+    return ok;
+}
+
+/* Estimators of the current population (Sec. "Trial wave functions",
+ * Eq. (proje)): N_w = sum |C_i|, C_ref and sum_{j != ref} H_ref,j C_j. */
+void orc_run_estimate(const orc_run *r, double *nw_out, double *nref_out, double *enum_out)
+{
+    double nw = 0.0, nref = 0.0, en = 0.0;
+    for (int64_t x = 0; x < r->n; ++x) {
+        const ent_t *e = &r->list[x];
+        nw = nw + fabs(e->v);
+        if (det_eq(e->d, r->ref)) { nref = e->v; continue; }
+        int lvl = __builtin_popcountll(e->d.a ^ r->ref.a) + __builtin_popcountll(e->d.b ^ r->ref.b);
+        if (lvl == 2 || lvl == 4) {
+            double h = orc_hij_det(r->s, r->ref, e->d);
+            double c = h * e->v;
+            en = en + c;
+        }
+    }
+    *nw_out = nw; *nref_out = nref; *enum_out = en;
+}
+
+void orc_layout(const orc_sys *s, uint64_t a, uint64_t b, uint64_t *w0, uint64_t *w1)
+{
+    det_t d = {a, b};
+    layout_words(s, d, w0, w1);
+}
+
+void orc_unlayout(const orc_sys *s, uint64_t w0, uint64_t w1, uint64_t *a, uint64_t *b)
+{
+    det_t d = from_layout(s, w0, w1);
+    *a = d.a; *b = d.b;
+}
