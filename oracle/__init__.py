@@ -83,7 +83,8 @@ class OrcParams(C.Structure):
     _fields_ = [("tau", C.c_double), ("target", C.c_double), ("n_a", C.c_double),
                 ("c_min", C.c_double), ("zeta", C.c_double), ("p_single", C.c_double),
                 ("p_opp", C.c_double), ("interval", C.c_int), ("mode", C.c_int),
-                ("gen", C.c_int), ("seed", C.c_uint64), ("replica", C.c_uint64)]
+                ("gen", C.c_int), ("seed", C.c_uint64), ("replica", C.c_uint64),
+                ("xi", C.c_double)]
 
 
 class OrcStats(C.Structure):
@@ -184,7 +185,8 @@ class System:
 
 
 DEFAULTS = dict(tau=0.01, target=1e4, n_a=-1.0, c_min=1.0, zeta=0.05, p_single=-1.0,
-                p_opp=-1.0, interval=10, mode=MODE_INTEGER, gen=GEN_UNIFORM, seed=1, replica=0)
+                p_opp=-1.0, interval=10, mode=MODE_INTEGER, gen=GEN_UNIFORM, seed=1, replica=0,
+                xi=-1.0)
 
 
 class Run:

@@ -14,7 +14,7 @@
  * is one rounding, in the order written.
  *
  * Determinants.  A determinant is an occupation bit string over 2N spin
- * orbitals (Appendix A, "Stochastic excitation generation").  Internally the
+ * orbitals (Appendix A, "Stochastic excitation generation and p_gen").  Internally the
  * oracle keeps it as two spatial-orbital masks (alpha, beta).  Canonical
  * spin-orbital order (Reading: the paper fixes no order) is all alpha
  * orbitals 0..N-1 first, then all beta orbitals (canonical index N+p).
@@ -88,7 +88,7 @@ typedef struct {
     double *eri4;   /* N^4 chemists' (pq|rs) at ((p*N+q)*N+r)*N+s */
     int *deg;       /* lattice degree per site */
     int *nbr;       /* N*N: ascending neighbour list of each site */
-    /* pre-computed heat-bath tables (Appendix, pre-computed heat-bath sampling) */
+    /* pre-computed heat-bath tables (Appendix A.3) */
     double *hb_w_same;   /* [pair I<J][pair A<B] weights over spatial indices */
     double *hb_w_opp;    /* [I*N+J][A*N+B] weights */
     double *hb_sum_same; /* per (i<j) */
@@ -224,7 +224,7 @@ static int det_eq(det_t x, det_t y) { return x.a == y.a && x.b == y.b; }
 /* Slater-Condon matrix elements.  The paper gives the double-excitation     */
 /* element <ij||ab> = <ij|ab> - <ij|ba> (Appendix, uniform excitation        */
 /* generation) and notes that the exchange part vanishes for opposite spins  */
-/* (Appendix, Cauchy-Schwarz doubles).  The remaining rules are the textbook */
+/* (Appendix A.2, Cauchy-Schwarz doubles).  The remaining rules are the textbook */
 /* Slater-Condon rules for H = sum h_pq a+_p a_q + 1/2 sum <pq|rs>           */
 /* a+_p a+_q a_s a_r with <pq|rs> = (pr|qs) d(s_p,s_r) d(s_q,s_s).           */
 /* ------------------------------------------------------------------------- */
@@ -365,7 +365,7 @@ uint64_t orc_uniform_count2(const orc_sys *s, det_t d, int single, uint64_t idx1
     return ha * hbeta;
 }
 
-/* Uniform generator after the random indices have been drawn (Appendix,
+/* Uniform generator after the random indices have been drawn (Appendix A.1,
  * uniform generation with spin imposed through conditional probabilities):
  *   single: electron idx1 of the n occupied (canonical order), hole idx2 of
  *           the same-spin holes (ascending);
@@ -508,6 +508,7 @@ typedef struct {
     double tau, target, n_a, c_min, zeta, p_single, p_opp;
     int interval, mode, gen;
     uint64_t seed, replica;
+    double xi; /* restoring strength of the shift update; < 0: zeta^2/4 */
 } orc_params;
 
 typedef struct {
@@ -526,6 +527,8 @@ typedef struct {
     int vary;
     int64_t t_last;
     double nw_last;
+    double *nw_ring;   /* N_w(t) of the last A+1 steps, indexed t mod (A+1) */
+    int64_t t_set;     /* step at which the population was last set */
     ent_t *list;
     int64_t n, cap;
 } orc_run;
@@ -574,6 +577,7 @@ orc_run *orc_run_create(const orc_sys *s, const orc_params *p, uint64_t ref_a, u
     r->h00 = orc_hdiag_det(s, r->ref);
     r->cap = 16;
     r->list = (ent_t *)malloc(sizeof(ent_t) * r->cap);
+    r->nw_ring = (double *)calloc((size_t)r->p.interval + 1, sizeof(double));
     return r;
 }
 
@@ -581,6 +585,7 @@ void orc_run_free(orc_run *r)
 {
     if (!r) return;
     free(r->list);
+    free(r->nw_ring);
     free(r);
 }
 
@@ -602,11 +607,19 @@ void orc_run_set_walkers(orc_run *r, const uint64_t *a, const uint64_t *b, const
         r->list[r->n++] = e;
     }
     qsort(r->list, r->n, sizeof(ent_t), ent_cmp);
+    double nw = 0.0;
+    for (int64_t x = 0; x < r->n; ++x) nw = nw + fabs(r->list[x].v);
+    r->t_set = r->t;
+    r->nw_ring[r->t % (r->p.interval + 1)] = nw;
 }
 
 void orc_run_set_state(orc_run *r, int64_t t, double S, int vary, int64_t t_last, double nw_last)
 {
+    /* re-key the growth history to the new step counter */
+    double nw0 = r->nw_ring[r->t % (r->p.interval + 1)];
     r->t = t; r->S = S; r->vary = vary; r->t_last = t_last; r->nw_last = nw_last;
+    r->t_set = t;
+    r->nw_ring[t % (r->p.interval + 1)] = nw0;
 }
 
 void orc_run_get_state(const orc_run *r, int64_t *t, double *S, int *vary, int64_t *t_last,
@@ -637,7 +650,7 @@ static int64_t find(const ent_t *list, int64_t n, det_t d)
     return -1;
 }
 
-/* Stochastic compression to C_min (Sec. II, the compressed storage rule):
+/* Stochastic compression to C_min (Sec. I, the compressed storage rule):
  * keep |x| >= C_min, else sign(x) C_min with probability |x|/C_min, else 0. */
 static double round_cmin(double x, double cmin, double u)
 {
@@ -672,7 +685,7 @@ int orc_run_step(orc_run *r, orc_stats *st)
         double C = e->v;
         double aC = fabs(C);
         int64_t m = integer ? (int64_t)aC : (int64_t)ceil(aC);
-        /* initiator: |C_i| above n_a (Sec. II); Reading: the reference always
+        /* initiator: |C_i| above n_a (Sec. I); Reading: the reference always
          * counts as one; a negative n_a switches the approximation off. */
         int init = (p->n_a < 0.0) || (aC > p->n_a) || det_eq(e->d, r->ref);
         st->attempts += m;
@@ -753,7 +766,7 @@ int orc_run_step(orc_run *r, orc_stats *st)
     }
 
     /* (c) annihilation.  Sum all contributions per target.  Initiator rule
-     * (Sec. II): matrix elements between non-initiators and determinants with
+     * (Sec. I): matrix elements between non-initiators and determinants with
      * C(tau) = 0 are zeroed, i.e. a target unoccupied at tau only receives the
      * contributions of initiator parents; an occupied target receives all. */
     qsort(recs, nrec, sizeof(srec_t), srec_cmp);
@@ -809,7 +822,7 @@ int orc_run_step(orc_run *r, orc_stats *st)
     r->t = t + 1;
 
     /* Estimators: walker number N_w = sum |C_i|; projected energy
-     * E_Ref = <D_ref|H|Psi>/<D_ref|Psi> (Sec. "Trial wave functions"), kept as
+     * E_Ref = <D_ref|H|Psi>/<D_ref|Psi> (Sec. IV, Eq. (proje)), kept as
      * numerator sum_{j != ref} H_ref,j C_j and denominator C_ref. */
     double nw = 0.0, nref = 0.0, en = 0.0;
     for (int64_t x = 0; x < r->n; ++x) {
@@ -825,25 +838,47 @@ int orc_run_step(orc_run *r, orc_stats *st)
     }
 
     /* Shift update.  The paper only says S is updated to match the ground-state
-     * energy (Sec. II).  Reading (original FCIQMC population control): S is 0
-     * (relative to H_00) until N_w first reaches the target; from then on every
-     * A steps S <- S - zeta/(A dtau) ln(N_w(t)/N_w(t-A)). */
+     * energy (Sec. I).  Reading: S is 0 (relative to H_00) until N_w first
+     * reaches the target N_t.  At that step T, S is set from the measured
+     * growth rate, S = -ln(N_w(T)/N_w(T-L))/(L dtau), with L = min(A, steps
+     * since the population was set).  From then on, every A steps,
+     *   S <- S - zeta/(A dtau) ln(N_w(t)/N_w(t-A)) - xi/(A dtau) ln(N_w(t)/N_t),
+     * the damped population control of the original FCIQMC method with the
+     * restoring term of Yang, Pahl and Brand (J. Chem. Phys. 153, 174103
+     * (2020)), xi = zeta^2/4 by default.  An extinct population (N_w = 0)
+     * leaves S unchanged. */
     int64_t T = r->t;
+    int64_t A = (int64_t)p->interval;
     if (!r->vary) {
         if (nw >= p->target) {
             r->vary = 1;
+            int64_t L = T - r->t_set;
+            if (L > A) L = A;
+            if (L > 0) {
+                double nw_prev = r->nw_ring[(T - L) % (A + 1)];
+                double c = 1.0 / ((double)L * p->tau);
+                double ratio = nw / nw_prev;
+                double l = log(ratio);
+                double dS = c * l;
+                r->S = 0.0 - dS;
+            }
             r->t_last = T;
             r->nw_last = nw;
         }
-    } else if (T - r->t_last == (int64_t)p->interval) {
-        double c = p->zeta / ((double)p->interval * p->tau);
-        double ratio = nw / r->nw_last;
-        double l = log(ratio);
-        double dS = c * l;
-        r->S = r->S - dS;
+    } else if (T - r->t_last == A && nw > 0.0) {
+        double at = (double)p->interval * p->tau;
+        double c1 = p->zeta / at;
+        double c2 = r->p.xi / at;
+        double l1 = log(nw / r->nw_last);
+        double l2 = log(nw / p->target);
+        double d1 = c1 * l1;
+        double d2 = c2 * l2;
+        double s1 = r->S - d1;
+        r->S = s1 - d2;
         r->t_last = T;
         r->nw_last = nw;
     }
+    r->nw_ring[T % (A + 1)] = nw;
 
     st->nw = nw; st->nref = nref; st->enum_ = en; st->shift = r->S;
     st->ndets = r->n; st->vary = r->vary;
@@ -851,7 +886,7 @@ int orc_run_step(orc_run *r, orc_stats *st)
 }
 
 /* ------------------------------------------------------------------------- */
-/* Pre-computed heat-bath (PCHB) doubles (Appendix, pre-computed heat-bath     */
+/* Pre-computed heat-bath (PCHB) doubles (Appendix A.3, pre-computed heat-bath  */
 /* sampling), Eq. (hbs): p(ab|ij) = |H_ij^ab| / sum_a'b' |H_ij^a'b'|, drawn by */
 /* Walker's alias method in O(1).                                             */
 /* Reading, over spatial orbitals (no p_exch split):                          */
@@ -1124,8 +1159,7 @@ int orc_lattice_apply_flat(const orc_sys *s, uint64_t a, uint64_t b, uint64_t id
     return ok;
 }
 
-/* Estimators of the current population (Sec. "Trial wave functions",
- * Eq. (proje)): N_w = sum |C_i|, C_ref and sum_{j != ref} H_ref,j C_j. */
+/* Estimators of the current population (Sec. IV, Eq. (proje)): N_w = sum |C_i|, C_ref and sum_{j != ref} H_ref,j C_j. */
 void orc_run_estimate(const orc_run *r, double *nw_out, double *nref_out, double *enum_out)
 {
     double nw = 0.0, nref = 0.0, en = 0.0;
