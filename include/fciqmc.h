@@ -1,0 +1,177 @@
+/*
+ * fciqmc.h -- C ABI of the MI355X FCIQMC library (libfciqmc.so).
+ *
+ * One imaginary-time step of Full Configuration Interaction Quantum Monte
+ * Carlo (Guther et al., J. Chem. Phys. 153, 034107 (2020), "NECI"):
+ * the projector of Eq. (projector), psi(tau+dtau) = (1 - dtau (H - S)) psi(tau),
+ * applied stochastically as the spawn / death / annihilation split of
+ * Eq. (fciqmc_dyn), with the initiator rule (Sec. I), the shift S and the
+ * reference-projected energy of Eq. (proje) (Sec. IV).
+ *
+ * Conventions used throughout this header:
+ *   - N spatial orbitals, n_alpha + n_beta electrons, 2N spin orbitals;
+ *     a determinant is handed over as two uint64 spatial-orbital masks,
+ *     alpha first then beta (bit p set = orbital p occupied).
+ *   - Integrals are FP64 in chemists' notation: h1 is N*N row-major and
+ *     symmetric; (pq|rs) is 8-fold packed with P = p(p+1)/2 + q (p >= q) and
+ *     element index P(P+1)/2 + Q (P >= Q).
+ *   - Every entry point returns 0 on success or a negative FCIQMC_E* code;
+ *     fciqmc_last_error() then describes the failure.  No C++ exception
+ *     crosses this boundary.
+ *   - Pointers marked "host" are read or written by the call and may be
+ *     reused by the caller as soon as it returns.  All device memory is
+ *     allocated and owned by the library and released by the free calls.
+ *   - A run borrows its system: free every run before its system.  Calls on
+ *     one run are serialised by the caller; different runs may be stepped
+ *     from different host threads on different streams.
+ */
+#ifndef FCIQMC_H
+#define FCIQMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FCIQMC_OK 0
+#define FCIQMC_EINVAL (-1)    /* invalid argument or inconsistent input       */
+#define FCIQMC_ENOMEM (-2)    /* device allocation failed or over HBM budget  */
+#define FCIQMC_EOVERFLOW (-3) /* capacity could not grow; state is unchanged  */
+#define FCIQMC_EDEVICE (-4)   /* HIP runtime error                            */
+#define FCIQMC_ESTATE (-5)    /* call out of order                            */
+
+#define FCIQMC_MODE_INTEGER 0 /* signed integer walker numbers                */
+#define FCIQMC_MODE_REAL 1    /* real coefficients compressed at c_min        */
+
+#define FCIQMC_GEN_UNIFORM 0  /* uniform singles and doubles (Appendix A.1)   */
+#define FCIQMC_GEN_LATTICE 1  /* real-space lattice hopping (Sec. II)         */
+#define FCIQMC_GEN_PCHB 2     /* pre-computed heat-bath doubles (App. A.3)    */
+
+typedef struct fciqmc_system fciqmc_system;
+typedef struct fciqmc_run fciqmc_run;
+
+/* Parameters of one walker population.  fciqmc_params_default() fills every
+ * field; callers then override what they need. */
+typedef struct fciqmc_params {
+    double tau;             /* time step dtau; must satisfy dtau < 2/W (Sec. I)           */
+    double walker_target;   /* N_w at which the shift starts to vary                      */
+    double n_initial;       /* walkers placed on the reference determinant at init        */
+    double initiator_na;    /* initiator threshold n_a (|C_i| > n_a); < 0 switches it off */
+    int mode;               /* FCIQMC_MODE_*                                              */
+    double c_min;           /* real mode: compression threshold C_min (Sec. I)           */
+    int excitgen;           /* FCIQMC_GEN_*                                               */
+    double p_single;        /* probability of a single excitation; < 0: nN/(nN + n^2N^2)  */
+    double p_opp;           /* PCHB: prob. of an opposite-spin pair; < 0: n_a n_b/C(n,2)  */
+    uint64_t seed;          /* Philox key word 0                                          */
+    uint64_t replica_id;    /* Philox key word 1                                          */
+    double shift_damping;   /* zeta of the shift update                                   */
+    double shift_restore;   /* xi: pull of S towards the target N_w; < 0: zeta^2/4        */
+    int shift_interval;     /* A: steps between shift updates                             */
+    uint64_t ref_alpha;     /* reference determinant masks; both 0 = aufbau               */
+    uint64_t ref_beta;
+    int64_t max_dets;       /* capacity hint for occupied determinants (0 = from target)  */
+    int64_t max_spawns;     /* capacity hint for spawn records per step (0 = from target) */
+    int64_t hbm_budget_bytes; /* device memory this run may hold (0 = no limit)           */
+    int buckets_log2;       /* hash-partition count 2^k of the walker store (0 = auto)    */
+    int det_words;          /* 1 (N <= 32) or 2 (N <= 63) uint64 per determinant; 0 auto  */
+    double conv_tol;        /* energy agreement tolerance for the report (Hartree)        */
+    int equil_steps;        /* steps after the shift starts varying that the report drops */
+} fciqmc_params;
+
+/* Per-step diagnostics (after the step). */
+typedef struct fciqmc_step_stats {
+    int64_t iter;           /* number of completed steps                                  */
+    double nw;              /* walker number N_w = sum |C_i|                              */
+    double nref;            /* C_ref, the reference coefficient                           */
+    double enum_;           /* sum_{j != ref} H_ref,j C_j                                 */
+    double shift;           /* S after this step's update (relative to H_00)              */
+    double e_proj;          /* H_00 + e_core + enum_/nref (absolute)                      */
+    int64_t ndets;          /* occupied determinants                                      */
+    int64_t attempts;       /* spawn attempts made in this step                           */
+    int64_t spawns;         /* spawn records emitted in this step                         */
+    int vary_shift;         /* 1 once the shift varies                                    */
+    int retries;            /* capacity growths this step needed (trajectory unchanged)   */
+} fciqmc_step_stats;
+
+/* Energy report from the recorded steps (Flyvbjerg-Petersen blocking). */
+typedef struct fciqmc_energy_report {
+    double e_proj, e_proj_err;   /* absolute projected energy and its error            */
+    double shift, shift_err;     /* absolute shift H_00 + e_core + <S> and its error   */
+    double e_ref;                /* H_00 + e_core                                      */
+    int64_t n_samples;           /* steps used                                         */
+    int64_t first_step;          /* first step used                                    */
+    int64_t steps_done;          /* all completed steps                                */
+    int converged;               /* |shift - e_proj| < conv_tol and both errors < tol  */
+} fciqmc_energy_report;
+
+/* Walker-state scalars that, with the walker list, form a full checkpoint. */
+typedef struct fciqmc_checkpoint {
+    int64_t iter;
+    double shift;
+    int vary_shift;
+    int64_t last_update_iter;
+    double last_update_nw;
+} fciqmc_checkpoint;
+
+void fciqmc_params_default(fciqmc_params *p);
+
+/* Load integrals (Sec. XIV, "Interfacing NECI": the method consumes one- and
+ * two-electron integrals).  h1: host, n_orb*n_orb; eri_packed: host,
+ * eri_len = M(M+1)/2 with M = n_orb(n_orb+1)/2.  Copies both to the device
+ * and derives the tables the generators need.  EINVAL if h1 is not
+ * symmetric, lengths disagree, n_orb > 63, n_alpha or n_beta > n_orb, or the
+ * determinant space holds a single determinant. */
+int fciqmc_load_integrals(int n_orb, int n_alpha, int n_beta, double e_core,
+                          const double *h1, const double *eri_packed, int64_t eri_len,
+                          fciqmc_system **out);
+
+/* Create a walker population: n_initial walkers on the reference.  stream:
+ * a hipStream_t to launch on (e.g. torch.cuda.current_stream().cuda_stream),
+ * NULL for a library-owned stream.  Builds PCHB tables on first use. */
+int fciqmc_init(const fciqmc_system *sys, const fciqmc_params *p, void *stream,
+                fciqmc_run **out);
+
+/* Advance n_steps imaginary-time steps (Eq. fciqmc_dyn: spawn, death,
+ * annihilation with the initiator rule, Sec. I; then estimators and shift).  stats:
+ * host array of n_steps entries or NULL.  Capacity overflows grow the
+ * buffers and replay the step, which reproduces it exactly. */
+int fciqmc_step(fciqmc_run *run, int n_steps, fciqmc_step_stats *stats);
+
+/* Blocking analysis of the recorded per-step estimators (host only). */
+int fciqmc_energy(const fciqmc_run *run, fciqmc_energy_report *out);
+
+/* Diagnostics / checkpoint.  dets: host, 2 uint64 per determinant (alpha,
+ * beta masks); vals: host.  get: at most cap entries, *n receives the count
+ * (ENOMEM-free: returns EOVERFLOW with *n set when cap is too small). */
+int fciqmc_get_walkers(const fciqmc_run *run, uint64_t *dets, double *vals, int64_t cap,
+                       int64_t *n);
+/* Replace the population (values must be non-zero; integer mode: integers). */
+int fciqmc_set_walkers(fciqmc_run *run, const uint64_t *dets, const double *vals, int64_t n);
+int fciqmc_get_checkpoint(const fciqmc_run *run, fciqmc_checkpoint *out);
+int fciqmc_set_checkpoint(fciqmc_run *run, const fciqmc_checkpoint *in);
+
+/* Device Slater-Condon matrix elements <D_j|H|D_i> for n host pairs
+ * (dets_i, dets_j: 2 uint64 each; out: host), for parity checks. */
+int fciqmc_matrix_elements(const fciqmc_system *sys, const uint64_t *dets_i,
+                           const uint64_t *dets_j, int64_t n, double *out);
+
+/* Device memory currently held by a run (bytes). */
+int64_t fciqmc_run_device_bytes(const fciqmc_run *run);
+
+/* Per-kernel timing.  enable != 0 starts recording HIP events around each
+ * kernel of every later step (on the run's stream).  ms: host, 5 entries
+ * receive the accumulated milliseconds of the spawn, record-scan, scatter,
+ * annihilation and post kernels; *steps the number of steps timed.
+ * layout: host, 2 entries receive the bucket count of the walker store and
+ * the spawn-record capacity (either output may be NULL). */
+int fciqmc_profile(fciqmc_run *run, int enable, double *ms, int64_t *steps, int64_t *layout);
+
+void fciqmc_free_run(fciqmc_run *run);
+void fciqmc_free_system(fciqmc_system *sys);
+const char *fciqmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FCIQMC_H */

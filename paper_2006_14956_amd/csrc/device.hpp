@@ -1,0 +1,470 @@
+// Device building blocks of the FCIQMC step for CDNA4 (gfx950, wave64).
+//
+// Determinant layouts (W = 64-bit words per determinant):
+//   W = 1 (N <= 32): alpha orbital p at bit p, beta orbital p at bit 32 + p;
+//   W = 2 (N <= 63): word 0 = alpha mask, word 1 = beta mask.
+// In both, bit order equals the canonical spin-orbital order (all alpha
+// orbitals, then all beta orbitals), which fixes the fermionic signs.
+//
+// Floating point: every expression is written as the sequence of IEEE
+// binary64 operations it stands for; the library is built with
+// -ffp-contract=off so no multiply-add is fused.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fq {
+
+constexpr uint64_t kEmpty = ~0ULL;       // unused hash slot
+constexpr uint64_t kLocked = ~0ULL - 1;  // slot being claimed (2-word keys only)
+
+// Philox purposes (low byte of counter word 3).
+enum : uint64_t { kSpawn = 0, kSpawn2 = 1, kDeath = 2, kAnn = 4 };
+
+// Error / overflow flags raised on the device, read back by the host.
+enum : unsigned { kFlagSpawnCap = 1u, kFlagTable = 2u, kFlagStore = 4u, kFlagBloom = 8u,
+                  kFlagSpin = 16u, kFlagPop = 32u };
+
+// --------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11): ten rounds of two 64x64->128
+// multiplies with a Weyl-sequence key schedule.
+// --------------------------------------------------------------------------
+struct R4 { uint64_t x[4]; };
+
+__device__ __forceinline__ R4 philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                     uint64_t k0, uint64_t k1) {
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t h0 = __umul64hi(M0, c0), l0 = M0 * c0;
+        const uint64_t h1 = __umul64hi(M1, c2), l1 = M1 * c2;
+        const uint64_t n0 = h1 ^ c1 ^ k0;
+        const uint64_t n2 = h0 ^ c3 ^ k1;
+        c0 = n0; c1 = l1; c2 = n2; c3 = l0;
+        k0 += W0; k1 += W1;
+    }
+    R4 o;
+    o.x[0] = c0; o.x[1] = c1; o.x[2] = c2; o.x[3] = c3;
+    return o;
+}
+
+// Choice in [0, m): floor(x m / 2^64).
+__device__ __forceinline__ uint64_t pick(uint64_t x, uint64_t m) { return __umul64hi(x, m); }
+// Uniform in [0,1) from the top 53 bits.
+__device__ __forceinline__ double unif(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
+
+// --------------------------------------------------------------------------
+// Determinant keys.
+// --------------------------------------------------------------------------
+template <int W> struct Key { uint64_t w[W]; };
+
+template <int W> __device__ __forceinline__ uint64_t key_alpha(const Key<W>& k) {
+    if constexpr (W == 1) return k.w[0] & 0xFFFFFFFFULL; else return k.w[0];
+}
+template <int W> __device__ __forceinline__ uint64_t key_beta(const Key<W>& k) {
+    if constexpr (W == 1) return k.w[0] >> 32; else return k.w[1];
+}
+template <int W> __device__ __forceinline__ Key<W> make_key(uint64_t a, uint64_t b) {
+    Key<W> k;
+    if constexpr (W == 1) { k.w[0] = a | (b << 32); } else { k.w[0] = a; k.w[1] = b; }
+    return k;
+}
+template <int W> __device__ __forceinline__ bool key_eq(const Key<W>& x, const Key<W>& y) {
+    if constexpr (W == 1) return x.w[0] == y.w[0]; else return x.w[0] == y.w[0] && x.w[1] == y.w[1];
+}
+template <int W> __device__ __forceinline__ Key<W> load_key(const uint64_t* p) {
+    Key<W> k;
+    if constexpr (W == 1) { k.w[0] = p[0]; }
+    else { const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(p); k.w[0] = v.x; k.w[1] = v.y; }
+    return k;
+}
+template <int W> __device__ __forceinline__ void store_key(uint64_t* p, const Key<W>& k) {
+    if constexpr (W == 1) { p[0] = k.w[0]; }
+    else { ulonglong2 v; v.x = k.w[0]; v.y = k.w[1]; *reinterpret_cast<ulonglong2*>(p) = v; }
+}
+
+// Random block of (determinant, iteration, ordinal, purpose).
+template <int W> __device__ __forceinline__ R4 draw(const Key<W>& k, int64_t t, uint64_t ord,
+                                                    uint64_t purpose, uint64_t seed, uint64_t rep) {
+    return philox(k.w[0], W == 2 ? k.w[W - 1] : 0ULL, (uint64_t)t, (ord << 8) | purpose, seed, rep);
+}
+
+// splitmix64 finaliser; partitions determinants into buckets (high bits) and
+// places them in the per-bucket LDS table (low bits).
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    x ^= x >> 30; x *= 0xBF58476D1CE4E5B9ULL;
+    x ^= x >> 27; x *= 0x94D049BB133111EBULL;
+    x ^= x >> 31;
+    return x;
+}
+template <int W> __device__ __forceinline__ uint64_t key_hash(const Key<W>& k) {
+    if constexpr (W == 1) return mix64(k.w[0] + 0x632BE59BD9B4E019ULL);
+    else return mix64(k.w[0] ^ mix64(k.w[1] + 0x632BE59BD9B4E019ULL));
+}
+__device__ __forceinline__ uint32_t bucket_of(uint64_t h, uint32_t B) { return (uint32_t)__umul64hi(h, B); }
+
+// --------------------------------------------------------------------------
+// Bit helpers.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int ctz64(uint64_t x) { return __builtin_ctzll(x); }
+__device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
+__device__ __forceinline__ uint64_t low_mask(int p) { return (1ULL << p) - 1ULL; }
+
+// Position of the k-th (0-based) set bit of x; x must have more than k bits set.
+__device__ __forceinline__ int select64(uint64_t x, int k) {
+    int pos = 0;
+    int c = __popc((uint32_t)x);
+    if (k >= c) { k -= c; x >>= 32; pos = 32; }
+    uint32_t w = (uint32_t)x;
+    c = __popc(w & 0xFFFFu); if (k >= c) { k -= c; w >>= 16; pos += 16; }
+    c = __popc(w & 0xFFu);   if (k >= c) { k -= c; w >>= 8;  pos += 8; }
+    c = __popc(w & 0xFu);    if (k >= c) { k -= c; w >>= 4;  pos += 4; }
+    c = __popc(w & 0x3u);    if (k >= c) { k -= c; w >>= 2;  pos += 2; }
+    c = (int)(w & 1u);       if (k >= c) { pos += 1; }
+    return pos;
+}
+
+// Occupied spin orbitals below (spin s, orbital p) in canonical order.
+__device__ __forceinline__ int below(uint64_t A, uint64_t B, int s, int p) {
+    return s == 0 ? popc64(A & low_mask(p)) : popc64(A) + popc64(B & low_mask(p));
+}
+__device__ __forceinline__ void clear_so(uint64_t& A, uint64_t& B, int s, int p) {
+    if (s == 0) A &= ~(1ULL << p); else B &= ~(1ULL << p);
+}
+__device__ __forceinline__ void set_so(uint64_t& A, uint64_t& B, int s, int p) {
+    if (s == 0) A |= (1ULL << p); else B |= (1ULL << p);
+}
+
+// Decode a lexicographic pair index q over C(n,2) pairs (x<y) of n items.
+__device__ __forceinline__ void pair_decode(uint64_t q, int n, int& x, int& y) {
+    int e = 0;
+    uint64_t row = (uint64_t)(n - 1);
+    while (row > 0 && q >= row) { q -= row; ++e; --row; }
+    x = e; y = e + 1 + (int)q;
+}
+
+// --------------------------------------------------------------------------
+// Integrals.
+// --------------------------------------------------------------------------
+struct SysView {
+    int N, na, nb, n;
+    int onsite;           // two-electron integrals vanish except (pp|pp)
+    const double* h1;     // N*N
+    const double* eri;    // 8-fold packed
+    const double* J;      // J[p*N+q] = (pp|qq)
+    const double* K;      // K[p*N+q] = (pq|qp)
+    const double* U;      // U[p] = (pp|pp)
+    const int* deg;       // lattice degree
+    const int* nbr;       // N*N ascending neighbour lists
+    // pre-computed heat-bath tables (see the PCHB generator)
+    const double* hb_w_opp; const double* hb_p_opp; const int* hb_a_opp; const double* hb_s_opp;
+    const double* hb_w_same; const double* hb_p_same; const int* hb_a_same; const double* hb_s_same;
+    const int* pair_of;   // same-spin column index -> A*64+B
+};
+
+__device__ __forceinline__ int tri(int p, int q) { return p >= q ? p * (p + 1) / 2 + q : q * (q + 1) / 2 + p; }
+__device__ __forceinline__ double eri(const SysView& s, int p, int q, int r, int t) {
+    const int P = tri(p, q), Q = tri(r, t);
+    return s.eri[tri(P, Q)];
+}
+
+// <D_j|H|D_i>, D_j = sgn a+_a a_i D_i, electron (sg, pi) -> hole (sg, pa).
+// Sum over the other electrons of D_i in canonical order.
+__device__ __forceinline__ double h_single(const SysView& s, uint64_t a, uint64_t b, int sg, int pi,
+                                           int pa) {
+    const int N = s.N;
+    double v = s.h1[pi * N + pa];
+    if (!s.onsite) {
+        for (uint64_t x = a; x; x &= x - 1) {
+            const int k = ctz64(x);
+            if (sg == 0 && k == pi) continue;
+            const double d = eri(s, pi, pa, k, k);
+            if (sg == 0) { const double e = eri(s, pi, k, k, pa); const double t = d - e; v = v + t; }
+            else v = v + d;
+        }
+        for (uint64_t x = b; x; x &= x - 1) {
+            const int k = ctz64(x);
+            if (sg == 1 && k == pi) continue;
+            const double d = eri(s, pi, pa, k, k);
+            if (sg == 1) { const double e = eri(s, pi, k, k, pa); const double t = d - e; v = v + t; }
+            else v = v + d;
+        }
+    }
+    uint64_t A = a, B = b;
+    int par = below(A, B, sg, pi);
+    clear_so(A, B, sg, pi);
+    par += below(A, B, sg, pa);
+    return (par & 1) ? -v : v;
+}
+
+// <D_j|H|D_i>, D_j = sgn a+_a a+_b a_j a_i D_i with i<j and a<b canonical;
+// the operator's coefficient is <ab||ij> = (ai|bj) - (aj|bi) on matching spins.
+__device__ __forceinline__ double h_double(const SysView& s, uint64_t a, uint64_t b, int si, int pi,
+                                           int sj, int pj, int sa, int pa, int sb, int pb) {
+    const double direct = (sa == si && sb == sj) ? eri(s, pa, pi, pb, pj) : 0.0;
+    const double exch = (sa == sj && sb == si) ? eri(s, pa, pj, pb, pi) : 0.0;
+    double v;
+    if (si == sj) v = direct - exch;
+    else v = (sa == si) ? direct : -exch;
+    uint64_t A = a, B = b;
+    int par = below(A, B, si, pi);
+    clear_so(A, B, si, pi);
+    par += below(A, B, sj, pj);
+    clear_so(A, B, sj, pj);
+    par += below(A, B, sb, pb);
+    set_so(A, B, sb, pb);
+    par += below(A, B, sa, pa);
+    return (par & 1) ? -v : v;
+}
+
+// H_ii: sum_p h_pp + sum_{p<q} [(pp|qq) - delta(spin)(pq|qp)], canonical order.
+__device__ __forceinline__ double h_diag(const SysView& s, uint64_t a, uint64_t b) {
+    const int N = s.N;
+    double acc = 0.0;
+    for (uint64_t x = a; x; x &= x - 1) { const int p = ctz64(x); acc = acc + s.h1[p * N + p]; }
+    for (uint64_t x = b; x; x &= x - 1) { const int p = ctz64(x); acc = acc + s.h1[p * N + p]; }
+    if (s.onsite) {
+        // only opposite-spin pairs on one site contribute; they occur in
+        // ascending site order in the canonical pair loop
+        for (uint64_t x = a & b; x; x &= x - 1) { const int p = ctz64(x); acc = acc + s.U[p]; }
+        return acc;
+    }
+    for (uint64_t x = a; x; x &= x - 1) {
+        const int p = ctz64(x);
+        for (uint64_t y = x & (x - 1); y; y &= y - 1) {
+            const int q = ctz64(y);
+            const double t = s.J[p * N + q] - s.K[p * N + q];
+            acc = acc + t;
+        }
+        for (uint64_t y = b; y; y &= y - 1) { const int q = ctz64(y); acc = acc + s.J[p * N + q]; }
+    }
+    for (uint64_t x = b; x; x &= x - 1) {
+        const int p = ctz64(x);
+        for (uint64_t y = x & (x - 1); y; y &= y - 1) {
+            const int q = ctz64(y);
+            const double t = s.J[p * N + q] - s.K[p * N + q];
+            acc = acc + t;
+        }
+    }
+    return acc;
+}
+
+// <D2|H|D1> for D1 != D2 by excitation level (zero beyond doubles).
+__device__ __forceinline__ double h_offdiag(const SysView& s, uint64_t a1, uint64_t b1, uint64_t a2,
+                                            uint64_t b2) {
+    const uint64_t ra = a1 & ~a2, rb = b1 & ~b2, xa = a2 & ~a1, xb = b2 & ~b1;
+    const int nra = popc64(ra), nrb = popc64(rb);
+    if (nra + nrb == 1) {
+        if (nra == 1) return h_single(s, a1, b1, 0, ctz64(ra), ctz64(xa));
+        return h_single(s, a1, b1, 1, ctz64(rb), ctz64(xb));
+    }
+    if (nra + nrb != 2) return 0.0;
+    int si, pi, sj, pj, sa, pa, sb, pb;
+    if (nra == 2) { si = 0; pi = ctz64(ra); sj = 0; pj = ctz64(ra & (ra - 1)); }
+    else if (nra == 1) { si = 0; pi = ctz64(ra); sj = 1; pj = ctz64(rb); }
+    else { si = 1; pi = ctz64(rb); sj = 1; pj = ctz64(rb & (rb - 1)); }
+    const int nxa = popc64(xa);
+    if (nxa == 2) { sa = 0; pa = ctz64(xa); sb = 0; pb = ctz64(xa & (xa - 1)); }
+    else if (nxa == 1) { sa = 0; pa = ctz64(xa); sb = 1; pb = ctz64(xb); }
+    else { sa = 1; pa = ctz64(xb); sb = 1; pb = ctz64(xb & (xb - 1)); }
+    return h_double(s, a1, b1, si, pi, sj, pj, sa, pa, sb, pb);
+}
+
+// --------------------------------------------------------------------------
+// Excitation generators.  Return false for a null draw; otherwise the target
+// masks, the generation probability and H_ji.
+// --------------------------------------------------------------------------
+struct Exc { uint64_t ta, tb; double pgen, H; };
+
+// Uniform singles/doubles with spin imposed by conditional probabilities
+// (Appendix A.1).  Random lanes: 0 single/double, 1 electron(s), 2 hole(s).
+__device__ __forceinline__ bool gen_uniform(const SysView& s, uint64_t a, uint64_t b, const R4& r,
+                                            double p_single, double p_double, Exc& out) {
+    const int N = s.N, na = s.na, nb = s.nb, n = s.n;
+    const uint64_t full = (N >= 64) ? ~0ULL : low_mask(N);
+    if (unif(r.x[0]) < p_single) {
+        const int e = (int)pick(r.x[1], (uint64_t)n);
+        const int sg = e < na ? 0 : 1;
+        const uint64_t occ = sg ? b : a;
+        const int pi = select64(occ, sg ? e - na : e);
+        const int h = N - (sg ? nb : na);
+        if (h == 0) return false;
+        const int pa = select64(~occ & full, (int)pick(r.x[2], (uint64_t)h));
+        out.pgen = p_single / (double)((uint64_t)n * (uint64_t)h);
+        out.H = h_single(s, a, b, sg, pi, pa);
+        uint64_t A = a, B = b;
+        clear_so(A, B, sg, pi); set_so(A, B, sg, pa);
+        out.ta = A; out.tb = B;
+        return true;
+    }
+    if (n < 2) return false;
+    const uint64_t npair = (uint64_t)n * (uint64_t)(n - 1) / 2;
+    int e1, e2;
+    pair_decode(pick(r.x[1], npair), n, e1, e2);
+    const int s1 = e1 < na ? 0 : 1, s2 = e2 < na ? 0 : 1;
+    const int p1 = select64(s1 ? b : a, s1 ? e1 - na : e1);
+    const int p2 = select64(s2 ? b : a, s2 ? e2 - na : e2);
+    int sa, pa, sb, pb;
+    uint64_t nh;
+    if (s1 == s2) {
+        const uint64_t holes = ~(s1 ? b : a) & full;
+        const int h = N - (s1 ? nb : na);
+        if (h < 2) return false;
+        nh = (uint64_t)h * (uint64_t)(h - 1) / 2;
+        int f1, f2;
+        pair_decode(pick(r.x[2], nh), h, f1, f2);
+        sa = s1; pa = select64(holes, f1); sb = s1; pb = select64(holes, f2);
+    } else {
+        const int ha = N - na, hb = N - nb;
+        nh = (uint64_t)ha * (uint64_t)hb;
+        if (nh == 0) return false;
+        const uint64_t q = pick(r.x[2], nh);
+        sa = 0; pa = select64(~a & full, (int)(q / (uint64_t)hb));
+        sb = 1; pb = select64(~b & full, (int)(q % (uint64_t)hb));
+    }
+    out.pgen = p_double / (double)(npair * nh);
+    out.H = h_double(s, a, b, s1, p1, s2, p2, sa, pa, sb, pb);
+    uint64_t A = a, B = b;
+    clear_so(A, B, s1, p1); clear_so(A, B, s2, p2); set_so(A, B, sa, pa); set_so(A, B, sb, pb);
+    out.ta = A; out.tb = B;
+    return true;
+}
+
+// Real-space lattice hopping: one of the n electrons, one of the z_p
+// neighbours of its site (same spin); null if occupied; p_gen = 1/(n z_p).
+__device__ __forceinline__ bool gen_lattice(const SysView& s, uint64_t a, uint64_t b, const R4& r,
+                                            Exc& out) {
+    const int N = s.N, na = s.na, n = s.n;
+    const int e = (int)pick(r.x[1], (uint64_t)n);
+    const int sg = e < na ? 0 : 1;
+    const uint64_t occ = sg ? b : a;
+    const int pi = select64(occ, sg ? e - na : e);
+    const int z = s.deg[pi];
+    if (z == 0) return false;
+    const int q = s.nbr[pi * N + (int)pick(r.x[2], (uint64_t)z)];
+    if ((occ >> q) & 1ULL) return false;
+    out.pgen = 1.0 / (double)((uint64_t)n * (uint64_t)z);
+    out.H = h_single(s, a, b, sg, pi, q);
+    uint64_t A = a, B = b;
+    clear_so(A, B, sg, pi); set_so(A, B, sg, q);
+    out.ta = A; out.tb = B;
+    return true;
+}
+
+// Pre-computed heat-bath doubles (Appendix A.3, Eq. (hbs)) with Walker alias
+// tables; uniform singles.  Block r: 0 single/double, 1 electrons, 2 alias
+// column, 3 acceptance; block r2: 0 alias coin, 1 pair class.
+__device__ __forceinline__ bool gen_pchb(const SysView& s, uint64_t a, uint64_t b, const R4& r,
+                                         const R4& r2, double p_single, double p_double,
+                                         double p_opp, Exc& out) {
+    const int N = s.N, na = s.na, nb = s.nb;
+    if (unif(r.x[0]) < p_single) return gen_uniform(s, a, b, r, p_single, p_double, out);
+    const uint64_t n_opp = (uint64_t)na * (uint64_t)nb;
+    const uint64_t npa = (uint64_t)na * (uint64_t)(na > 0 ? na - 1 : 0) / 2;
+    const uint64_t npb = (uint64_t)nb * (uint64_t)(nb > 0 ? nb - 1 : 0) / 2;
+    const uint64_t n_same = npa + npb;
+    const bool opp = unif(r2.x[1]) < p_opp;
+    const double coin = unif(r2.x[0]);
+    if (opp) {
+        if (n_opp == 0) return false;
+        const uint64_t q = pick(r.x[1], n_opp);
+        const int I = select64(a, (int)(q / (uint64_t)nb));
+        const int J = select64(b, (int)(q % (uint64_t)nb));
+        const int row = I * N + J;
+        const double sum = s.hb_s_opp[row];
+        if (sum == 0.0) return false;
+        const int K = N * N;
+        const size_t base = (size_t)row * (size_t)K;
+        const int c0 = (int)pick(r.x[2], (uint64_t)K);
+        const int c = coin < s.hb_p_opp[base + c0] ? c0 : s.hb_a_opp[base + c0];
+        const double wc = s.hb_w_opp[base + c];
+        if (wc == 0.0) return false;
+        const int A = c / N, Bo = c % N;
+        if (((a >> A) & 1ULL) || ((b >> Bo) & 1ULL)) return false;
+        const double p1 = p_double * p_opp;
+        const double p2 = p1 / (double)n_opp;
+        const double pab = wc / sum;
+        out.pgen = p2 * pab;
+        out.H = h_double(s, a, b, 0, I, 1, J, 0, A, 1, Bo);
+        out.ta = (a & ~(1ULL << I)) | (1ULL << A);
+        out.tb = (b & ~(1ULL << J)) | (1ULL << Bo);
+        return true;
+    }
+    if (n_same == 0) return false;
+    uint64_t q = pick(r.x[1], n_same);
+    const int sg = q >= npa ? 1 : 0;
+    if (sg) q -= npa;
+    const uint64_t occ = sg ? b : a;
+    int e1, e2;
+    pair_decode(q, sg ? nb : na, e1, e2);
+    const int I = select64(occ, e1), J = select64(occ, e2);
+    const int row = I * (2 * N - I - 1) / 2 + (J - I - 1);
+    const double sum = s.hb_s_same[row];
+    if (sum == 0.0) return false;
+    const int K = N * (N - 1) / 2;
+    const size_t base = (size_t)row * (size_t)K;
+    const int c0 = (int)pick(r.x[2], (uint64_t)K);
+    const int c = coin < s.hb_p_same[base + c0] ? c0 : s.hb_a_same[base + c0];
+    const double wc = s.hb_w_same[base + c];
+    if (wc == 0.0) return false;
+    const int ab = s.pair_of[c];
+    const int A = ab >> 6, Bo = ab & 63;
+    if (((occ >> A) & 1ULL) || ((occ >> Bo) & 1ULL)) return false;
+    const double p1 = p_double * (1.0 - p_opp);
+    const double p2 = p1 / (double)n_same;
+    const double pab = wc / sum;
+    out.pgen = p2 * pab;
+    out.H = h_double(s, a, b, sg, I, sg, J, sg, A, sg, Bo);
+    const uint64_t m = (occ & ~(1ULL << I) & ~(1ULL << J)) | (1ULL << A) | (1ULL << Bo);
+    out.ta = sg ? a : m;
+    out.tb = sg ? m : b;
+    return true;
+}
+
+// --------------------------------------------------------------------------
+// Wave / block collectives (wave64, 256-thread blocks).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+// Number of set bits of mask in lanes below this one.
+__device__ __forceinline__ int lane_rank(uint64_t mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <class T> __device__ __forceinline__ T wave_incl_scan(T v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T n = __shfl_up(v, (unsigned)o);
+        if (l >= o) v += n;
+    }
+    return v;
+}
+
+template <class T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Exclusive scan over a block of NT threads; `sh` holds NT/64 values.
+template <int NT, class T> __device__ __forceinline__ T block_excl_scan(T v, T& total, T* sh) {
+    const int w = (int)(threadIdx.x >> 6);
+    const T inc = wave_incl_scan(v);
+    if (lane_id() == 63) sh[w] = inc;
+    __syncthreads();
+    T off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) {
+        const T x = sh[i];
+        if (i < w) off += x;
+        tot += x;
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - v;
+}
+
+}  // namespace fq

@@ -1,0 +1,995 @@
+// Host side of libfciqmc: the C ABI declared in include/fciqmc.h.
+//
+// The host validates inputs, owns device memory, launches the kernels of
+// kernels.hpp on the caller's HIP stream and performs the only scalar
+// bookkeeping the method needs between steps: the shift update (Sec. I),
+// which uses the natural logarithm and is therefore evaluated on the host,
+// and the blocking analysis of the recorded estimators.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/fciqmc.h"
+#include "kernels.hpp"
+
+using namespace fq;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(FCIQMC_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                   \
+    } while (0)
+
+#define CHECK(expr)              \
+    do {                         \
+        int rc_ = (expr);        \
+        if (rc_ != 0) return rc_; \
+    } while (0)
+
+// Device allocation tracked against a byte budget.
+struct Arena {
+    int64_t bytes = 0;
+    int64_t budget = 0;  // 0 = unlimited
+    std::vector<void*> live;
+    int alloc(void** p, size_t n) {
+        n = std::max<size_t>(n, 256);
+        if (budget > 0 && bytes + (int64_t)n > budget)
+            return fail(FCIQMC_ENOMEM, "device memory budget exceeded (%lld + %zu > %lld bytes)",
+                        (long long)bytes, n, (long long)budget);
+        hipError_t e = hipMalloc(p, n);
+        if (e != hipSuccess) return fail(FCIQMC_ENOMEM, "hipMalloc(%zu) failed: %s", n, hipGetErrorString(e));
+        bytes += (int64_t)n;
+        live.push_back(*p);
+        sizes.push_back((int64_t)n);
+        return 0;
+    }
+    void release(void* p) {
+        if (!p) return;
+        for (size_t i = 0; i < live.size(); ++i)
+            if (live[i] == p) {
+                (void)hipFree(p);
+                bytes -= sizes[i];
+                live.erase(live.begin() + i);
+                sizes.erase(sizes.begin() + i);
+                return;
+            }
+    }
+    void clear() {
+        for (void* p : live) (void)hipFree(p);
+        live.clear();
+        sizes.clear();
+        bytes = 0;
+    }
+    std::vector<int64_t> sizes;
+};
+
+template <class T> int dalloc(Arena& a, T** p, size_t count) {
+    return a.alloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+uint64_t next_pow2(uint64_t x) {
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// System: integrals and derived tables on the device.
+// ---------------------------------------------------------------------------
+struct fciqmc_system {
+    int N = 0, na = 0, nb = 0;
+    double e_core = 0.0;
+    bool onsite = false;
+    Arena arena;
+    double *h1 = nullptr, *eri = nullptr, *J = nullptr, *K = nullptr, *U = nullptr;
+    int *deg = nullptr, *nbr = nullptr, *pair_of = nullptr;
+    bool pchb = false;
+    double *hb_w_opp = nullptr, *hb_p_opp = nullptr, *hb_s_opp = nullptr;
+    int* hb_a_opp = nullptr;
+    double *hb_w_same = nullptr, *hb_p_same = nullptr, *hb_s_same = nullptr;
+    int* hb_a_same = nullptr;
+    int device = 0;
+
+    SysView view() const {
+        SysView v{};
+        v.N = N; v.na = na; v.nb = nb; v.n = na + nb;
+        v.onsite = onsite ? 1 : 0;
+        v.h1 = h1; v.eri = eri; v.J = J; v.K = K; v.U = U;
+        v.deg = deg; v.nbr = nbr;
+        v.hb_w_opp = hb_w_opp; v.hb_p_opp = hb_p_opp; v.hb_a_opp = hb_a_opp; v.hb_s_opp = hb_s_opp;
+        v.hb_w_same = hb_w_same; v.hb_p_same = hb_p_same; v.hb_a_same = hb_a_same; v.hb_s_same = hb_s_same;
+        v.pair_of = pair_of;
+        return v;
+    }
+    ~fciqmc_system() { arena.clear(); }
+};
+
+static int build_pchb(fciqmc_system* s, hipStream_t stream) {
+    if (s->pchb) return 0;
+    const int N = s->N, NN = N * N, np = N * (N - 1) / 2;
+    const size_t ko = (size_t)NN * NN, ks = (size_t)np * np;
+    CHECK(dalloc(s->arena, &s->hb_w_opp, ko));
+    CHECK(dalloc(s->arena, &s->hb_p_opp, ko));
+    CHECK(dalloc(s->arena, &s->hb_a_opp, ko));
+    CHECK(dalloc(s->arena, &s->hb_s_opp, NN));
+    CHECK(dalloc(s->arena, &s->hb_w_same, ks + 1));
+    CHECK(dalloc(s->arena, &s->hb_p_same, ks + 1));
+    CHECK(dalloc(s->arena, &s->hb_a_same, ks + 1));
+    CHECK(dalloc(s->arena, &s->hb_s_same, np + 1));
+    // scratch of the alias construction (released afterwards)
+    Arena tmp;
+    double* scaled = nullptr;
+    int *small = nullptr, *large = nullptr;
+    const size_t kw = ko + ks + 1;
+    CHECK(dalloc(tmp, &scaled, kw));
+    CHECK(dalloc(tmp, &small, kw));
+    CHECK(dalloc(tmp, &large, kw));
+    // the same-spin rows use their own offsets into the scratch after the opposite rows:
+    // row r of K columns uses [r*K, (r+1)*K) of a region sized for its class
+    SysView v = s->view();
+    const int rows = NN + np;
+    hipLaunchKernelGGL(k_pchb_build, dim3((rows + 63) / 64), dim3(64), 0, stream, v, s->hb_w_opp,
+                       s->hb_p_opp, s->hb_a_opp, s->hb_s_opp, s->hb_w_same, s->hb_p_same,
+                       s->hb_a_same, s->hb_s_same, scaled, small, large);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(stream));
+    tmp.clear();
+    s->pchb = true;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Engine: the device state of one walker population for a fixed determinant
+// width W and value type V (int32 walker numbers or FP64 coefficients).
+// ---------------------------------------------------------------------------
+struct EngineBase {
+    virtual ~EngineBase() {}
+    virtual int step_once(int64_t t, double S, Ctl& out, int& retries, int64_t& attempts) = 0;
+    virtual int set_walkers(const uint64_t* dets, const double* vals, int64_t n) = 0;
+    virtual int get_walkers(std::vector<uint64_t>& ab, std::vector<double>& vals) = 0;
+    virtual int64_t attempts_next() const = 0;
+    virtual double last_nw() const = 0;
+    virtual int64_t bytes() const = 0;
+    virtual int enable_profile() = 0;
+    virtual void kernel_times(double* ms, int64_t* launches) const = 0;
+    virtual int64_t buckets() const = 0;
+    virtual int64_t spawn_capacity() const = 0;
+};
+
+// kernels of one step, in launch order: spawn, record scan, scatter,
+// annihilation, post
+constexpr int kKernels = 5;
+
+struct RunScalars {
+    double tau, p_single, p_double, p_opp, n_a, c_min, h00;
+    uint64_t seed, replica, ref_a, ref_b;
+    int gen;
+};
+
+template <int W, class V> struct Engine : EngineBase {
+    fciqmc_system* sys;
+    hipStream_t stream;
+    RunScalars rs;
+    Arena arena;
+    int B = 1, R = 1024;
+    Store<V> st[2]{};
+    int cur = 0;
+    Rec<W, V>* rec = nullptr;
+    Rec<W, V>* rec2 = nullptr;
+    long long cap = 0;
+    int32_t *scount = nullptr, *scur = nullptr;
+    int64_t* soff = nullptr;
+    double *nw_b = nullptr, *en_b = nullptr;
+    Ctl* ctl = nullptr;
+    Ctl* hctl = nullptr;  // pinned
+    int64_t att_next = 0;
+    int64_t max_b = 1 << 22;
+    // optional per-kernel timing (HIP events around each launch of a step)
+    bool profile = false;
+    hipEvent_t ev[kKernels + 1]{};
+    double kms[kKernels]{};
+    int64_t klaunch = 0;
+
+    Engine(fciqmc_system* s, hipStream_t st_, const RunScalars& r) : sys(s), stream(st_), rs(r) {}
+    ~Engine() override {
+        (void)hipStreamSynchronize(stream);
+        arena.clear();
+        if (hctl) (void)hipHostFree(hctl);
+        if (profile)
+            for (auto& e : ev) (void)hipEventDestroy(e);
+    }
+    int enable_profile() {
+        if (profile) return 0;
+        for (auto& e : ev) HIP_OK(hipEventCreate(&e));
+        profile = true;
+        return 0;
+    }
+    void mark(int i) {
+        if (profile) (void)hipEventRecord(ev[i], stream);
+    }
+    int collect() {
+        if (!profile) return 0;
+        for (int i = 0; i < kKernels; ++i) {
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            kms[i] += ms;
+        }
+        ++klaunch;
+        return 0;
+    }
+    int64_t bytes() const override { return arena.bytes; }
+    void kernel_times(double* ms, int64_t* launches) const override {
+        for (int i = 0; i < kKernels; ++i) ms[i] = kms[i];
+        *launches = klaunch;
+    }
+    int64_t buckets() const override { return B; }
+    int64_t spawn_capacity() const override { return cap; }
+    int64_t attempts_next() const override { return att_next; }
+    double last_nw() const override { return hctl ? hctl->nw : 0.0; }
+
+    int alloc_store(Store<V>& s) {
+        const size_t n = (size_t)B * R;
+        CHECK(dalloc(arena, &s.keys, n * W));
+        CHECK(dalloc(arena, &s.vals, n));
+        CHECK(dalloc(arena, &s.diag, n));
+        CHECK(dalloc(arena, &s.mpre, n));
+        CHECK(dalloc(arena, &s.count, (size_t)B));
+        CHECK(dalloc(arena, &s.batt, (size_t)B));
+        CHECK(dalloc(arena, &s.aoff, (size_t)B + 1));
+        HIP_OK(hipMemsetAsync(s.count, 0, sizeof(int32_t) * B, stream));
+        HIP_OK(hipMemsetAsync(s.batt, 0, sizeof(int64_t) * B, stream));
+        HIP_OK(hipMemsetAsync(s.aoff, 0, sizeof(int64_t) * (B + 1), stream));
+        return 0;
+    }
+    void free_store(Store<V>& s) {
+        arena.release(s.keys); arena.release(s.vals); arena.release(s.diag); arena.release(s.mpre);
+        arena.release(s.count); arena.release(s.batt); arena.release(s.aoff);
+        s = Store<V>{};
+    }
+    int alloc_buckets() {
+        CHECK(alloc_store(st[0]));
+        CHECK(alloc_store(st[1]));
+        CHECK(dalloc(arena, &scount, (size_t)B));
+        CHECK(dalloc(arena, &scur, (size_t)B));
+        CHECK(dalloc(arena, &soff, (size_t)B + 1));
+        CHECK(dalloc(arena, &nw_b, (size_t)B));
+        CHECK(dalloc(arena, &en_b, (size_t)B));
+        return 0;
+    }
+    void free_buckets() {
+        free_store(st[0]);
+        free_store(st[1]);
+        arena.release(scount); arena.release(scur); arena.release(soff);
+        arena.release(nw_b); arena.release(en_b);
+        scount = scur = nullptr; soff = nullptr; nw_b = en_b = nullptr;
+    }
+    int alloc_records(long long c) {
+        arena.release(rec);
+        arena.release(rec2);
+        rec = rec2 = nullptr;
+        cap = c;
+        CHECK(dalloc(arena, &rec, (size_t)cap));
+        CHECK(dalloc(arena, &rec2, (size_t)cap));
+        return 0;
+    }
+
+    int init(int buckets, long long spawn_cap, int64_t budget) {
+        arena.budget = budget;
+        B = buckets;
+        HIP_OK(hipHostMalloc((void**)&hctl, sizeof(Ctl), hipHostMallocDefault));
+        CHECK(dalloc(arena, &ctl, 1));
+        HIP_OK(hipMemsetAsync(ctl, 0, sizeof(Ctl), stream));
+        CHECK(alloc_buckets());
+        CHECK(alloc_records(spawn_cap));
+        return 0;
+    }
+
+    StepScalars scalars(int64_t t, double S, int import_mode) const {
+        StepScalars sc{};
+        sc.t = t; sc.seed = rs.seed; sc.replica = rs.replica;
+        sc.tau = rs.tau; sc.p_single = rs.p_single; sc.p_double = rs.p_double; sc.p_opp = rs.p_opp;
+        sc.n_a = rs.n_a; sc.c_min = rs.c_min; sc.S = S; sc.h00 = rs.h00;
+        sc.ref_a = rs.ref_a; sc.ref_b = rs.ref_b;
+        sc.B = B; sc.R = R; sc.spawn_cap = cap; sc.import_mode = import_mode;
+        return sc;
+    }
+
+    // Group the records of the current step by bucket and run the per-bucket
+    // kernel from st[cur] into st[1-cur], then the global sums.
+    int merge_and_post(const StepScalars& sc) {
+        const SysView v = sys->view();
+        Store<V> in = st[cur], out = st[1 - cur];
+        hipLaunchKernelGGL(k_scan_count, dim3(1), dim3(1024), 0, stream, scount, B, soff, ctl);
+        mark(2);
+        hipLaunchKernelGGL((k_scatter<W, V>), dim3(1024), dim3(kThreads), 0, stream, rec, rec2, soff,
+                           scur, ctl, cap);
+        mark(3);
+        const int gb = std::min(B, 32768);
+        hipLaunchKernelGGL((k_annihilate<W, V>), dim3(gb), dim3(kThreads), 0, stream, v, in, out, sc,
+                           rec2, soff, nw_b, en_b, ctl);
+        mark(4);
+        hipLaunchKernelGGL(k_post, dim3(1), dim3(1024), 0, stream, out.batt, out.count, nw_b, en_b,
+                           B, out.aoff, ctl);
+        mark(5);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipStreamSynchronize(stream));
+        return 0;
+    }
+
+    int reset_step_counters() {
+        HIP_OK(hipMemsetAsync(ctl, 0, offsetof(Ctl, nw), stream));
+        HIP_OK(hipMemsetAsync(scount, 0, sizeof(int32_t) * B, stream));
+        HIP_OK(hipMemsetAsync(scur, 0, sizeof(int32_t) * B, stream));
+        return 0;
+    }
+
+    int grow_buckets() {
+        if ((int64_t)B * 2 > max_b) return fail(FCIQMC_EOVERFLOW, "walker store cannot grow beyond %d buckets", B);
+        std::vector<uint64_t> ab;
+        std::vector<double> vals;
+        CHECK(get_walkers(ab, vals));
+        free_buckets();
+        B *= 2;
+        CHECK(alloc_buckets());
+        cur = 0;
+        return import(ab.data(), vals.data(), (int64_t)vals.size());
+    }
+
+    // Load a population through the per-bucket merge with death and rounding off.
+    int import(const uint64_t* ab, const double* vals, int64_t n) {
+        for (int attempt = 0; attempt < 24; ++attempt) {
+            if (n > cap) CHECK(alloc_records((long long)std::max<int64_t>(n, cap)));
+            std::vector<Rec<W, V>> h((size_t)std::max<int64_t>(n, 1));
+            for (int64_t i = 0; i < n; ++i) {
+                const uint64_t a = ab[2 * i], b = ab[2 * i + 1];
+                if constexpr (W == 1) h[i].k[0] = a | (b << 32);
+                else { h[i].k[0] = a; h[i].k[W - 1] = b; }
+                h[i].v = (V)vals[i];
+                h[i].flag = 1u;
+            }
+            CHECK(reset_step_counters());
+            if (n > 0)
+                HIP_OK(hipMemcpyAsync(rec, h.data(), sizeof(Rec<W, V>) * n, hipMemcpyHostToDevice, stream));
+            Ctl c{};
+            c.nrec = (unsigned long long)n;
+            HIP_OK(hipMemcpyAsync(ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, stream));
+            if (n > 0)
+                hipLaunchKernelGGL((k_bucketize<W, V>), dim3(std::min<long long>(1024, (n + 255) / 256)),
+                                   dim3(kThreads), 0, stream, rec, (long long)n, B, scount);
+            HIP_OK(hipGetLastError());
+            StepScalars sc = scalars(0, 0.0, 1);
+            CHECK(merge_and_post(sc));
+            const unsigned flags = hctl->flags;
+            if (flags == 0) {
+                cur = 1 - cur;
+                att_next = hctl->attempts;
+                return 0;
+            }
+            if (flags & (kFlagTable | kFlagStore)) {
+                if ((int64_t)B * 2 > max_b) return fail(FCIQMC_EOVERFLOW, "population does not fit the walker store");
+                free_buckets();
+                B *= 2;
+                CHECK(alloc_buckets());
+                cur = 0;
+                continue;
+            }
+            return fail(FCIQMC_EDEVICE, "population import failed (device flags 0x%x)", flags);
+        }
+        return fail(FCIQMC_EOVERFLOW, "population import did not converge");
+    }
+
+    int set_walkers(const uint64_t* ab, const double* vals, int64_t n) override {
+        cur = 0;
+        return import(ab, vals, n);
+    }
+
+    int get_walkers(std::vector<uint64_t>& ab, std::vector<double>& vals) override {
+        const Store<V>& s = st[cur];
+        int64_t* off = nullptr;
+        uint64_t* keys = nullptr;
+        double* dv = nullptr;
+        Arena tmp;
+        CHECK(dalloc(tmp, &off, (size_t)B + 1));
+        hipLaunchKernelGGL(k_scan_count, dim3(1), dim3(1024), 0, stream, s.count, B, off, (Ctl*)nullptr);
+        int64_t n = 0;
+        HIP_OK(hipMemcpyAsync(&n, off + B, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipStreamSynchronize(stream));
+        CHECK(dalloc(tmp, &keys, (size_t)std::max<int64_t>(n, 1) * W));
+        CHECK(dalloc(tmp, &dv, (size_t)std::max<int64_t>(n, 1)));
+        hipLaunchKernelGGL((k_extract<W, V>), dim3(std::min(B, 4096)), dim3(kThreads), 0, stream, s, R, off,
+                           keys, dv, B);
+        HIP_OK(hipGetLastError());
+        std::vector<uint64_t> hk((size_t)n * W);
+        vals.resize((size_t)n);
+        if (n > 0) {
+            HIP_OK(hipMemcpyAsync(hk.data(), keys, sizeof(uint64_t) * W * n, hipMemcpyDeviceToHost, stream));
+            HIP_OK(hipMemcpyAsync(vals.data(), dv, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
+        }
+        HIP_OK(hipStreamSynchronize(stream));
+        tmp.clear();
+        ab.resize((size_t)n * 2);
+        for (int64_t i = 0; i < n; ++i) {
+            if constexpr (W == 1) { ab[2 * i] = hk[i] & 0xFFFFFFFFULL; ab[2 * i + 1] = hk[i] >> 32; }
+            else { ab[2 * i] = hk[2 * i]; ab[2 * i + 1] = hk[2 * i + 1]; }
+        }
+        return 0;
+    }
+
+    int launch_spawn(const StepScalars& sc) {
+        const SysView v = sys->view();
+        const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((att_next + kThreads - 1) / kThreads, 8192));
+        const Store<V> in = st[cur];
+        switch (rs.gen) {
+            case FCIQMC_GEN_UNIFORM:
+                hipLaunchKernelGGL((k_spawn<W, V, 0>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec,
+                                   scount, ctl);
+                break;
+            case FCIQMC_GEN_LATTICE:
+                hipLaunchKernelGGL((k_spawn<W, V, 1>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec,
+                                   scount, ctl);
+                break;
+            default:
+                hipLaunchKernelGGL((k_spawn<W, V, 2>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec,
+                                   scount, ctl);
+                break;
+        }
+        HIP_OK(hipGetLastError());
+        return 0;
+    }
+
+    int step_once(int64_t t, double S, Ctl& out, int& retries, int64_t& attempts) override {
+        retries = 0;
+        attempts = att_next;
+        for (;;) {
+            const StepScalars sc = scalars(t, S, 0);
+            CHECK(reset_step_counters());
+            mark(0);
+            CHECK(launch_spawn(sc));
+            mark(1);
+            CHECK(merge_and_post(sc));
+            const unsigned flags = hctl->flags;
+            if (flags == 0) {
+                CHECK(collect());
+                break;
+            }
+            if (flags & kFlagBloom)
+                return fail(FCIQMC_EOVERFLOW, "a spawn exceeded 2^30 walkers at step %lld (time step too large)",
+                            (long long)t);
+            if (flags & kFlagPop)
+                return fail(FCIQMC_EOVERFLOW, "a walker number exceeded the int32 range at step %lld", (long long)t);
+            if (flags & kFlagSpin) return fail(FCIQMC_EDEVICE, "LDS hash claim did not complete");
+            ++retries;
+            if (retries > 24) return fail(FCIQMC_EOVERFLOW, "step %lld did not fit after 24 capacity growths", (long long)t);
+            if (flags & kFlagSpawnCap) {
+                const long long need = (long long)hctl->nrec;
+                CHECK(alloc_records(std::max<long long>(cap * 2, need + need / 4 + 1024)));
+                continue;
+            }
+            if (flags & (kFlagTable | kFlagStore)) {
+                CHECK(grow_buckets());
+                continue;
+            }
+            return fail(FCIQMC_EDEVICE, "device flags 0x%x", flags);
+        }
+        cur = 1 - cur;
+        att_next = hctl->attempts;
+        out = *hctl;
+        return 0;
+    }
+};
+
+struct fciqmc_run {
+    fciqmc_system* sys = nullptr;
+    fciqmc_params p{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::unique_ptr<EngineBase> eng;
+    double h00 = 0.0;
+    uint64_t ref_a = 0, ref_b = 0;
+    int64_t t = 0;
+    double S = 0.0;
+    int vary = 0;
+    int64_t t_last = 0;
+    double nw_last = 0.0;
+    int64_t t_vary = -1;
+    int64_t t_set = 0;              // step at which the population was last set
+    double xi = 0.0;                // restoring strength of the shift update
+    std::vector<double> nw_ring;    // N_w(t) of the last A+1 steps, indexed t mod (A+1)
+    std::vector<fciqmc_step_stats> hist;
+    ~fciqmc_run() {
+        eng.reset();
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+extern "C" {
+
+const char* fciqmc_last_error(void) { return g_err.c_str(); }
+
+void fciqmc_params_default(fciqmc_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->tau = 0.01;
+    p->walker_target = 1e4;
+    p->n_initial = 10.0;
+    p->initiator_na = -1.0;
+    p->mode = FCIQMC_MODE_INTEGER;
+    p->c_min = 1.0;
+    p->excitgen = FCIQMC_GEN_UNIFORM;
+    p->p_single = -1.0;
+    p->p_opp = -1.0;
+    p->seed = 1;
+    p->replica_id = 0;
+    p->shift_damping = 0.05;
+    p->shift_restore = -1.0;
+    p->shift_interval = 10;
+    p->conv_tol = 1e-3;
+    p->equil_steps = -1;
+}
+
+int fciqmc_load_integrals(int n_orb, int n_alpha, int n_beta, double e_core, const double* h1,
+                          const double* eri_packed, int64_t eri_len, fciqmc_system** out) {
+    if (!out || !h1 || !eri_packed) return fail(FCIQMC_EINVAL, "null argument");
+    *out = nullptr;
+    if (n_orb < 1 || n_orb > 63) return fail(FCIQMC_EINVAL, "n_orb must be in [1, 63] (got %d)", n_orb);
+    if (n_alpha < 0 || n_beta < 0 || n_alpha > n_orb || n_beta > n_orb)
+        return fail(FCIQMC_EINVAL, "electron counts must lie in [0, n_orb]");
+    if (n_alpha + n_beta < 1) return fail(FCIQMC_EINVAL, "no electrons");
+    if ((n_alpha == 0 || n_alpha == n_orb) && (n_beta == 0 || n_beta == n_orb))
+        return fail(FCIQMC_EINVAL, "the determinant space holds a single determinant");
+    const int64_t M = (int64_t)n_orb * (n_orb + 1) / 2;
+    if (eri_len != M * (M + 1) / 2)
+        return fail(FCIQMC_EINVAL, "eri_len must be M(M+1)/2 = %lld for n_orb = %d", (long long)(M * (M + 1) / 2), n_orb);
+    for (int p = 0; p < n_orb; ++p)
+        for (int q = 0; q < n_orb; ++q) {
+            if (!std::isfinite(h1[p * n_orb + q])) return fail(FCIQMC_EINVAL, "h1 has a non-finite entry");
+            if (h1[p * n_orb + q] != h1[q * n_orb + p]) return fail(FCIQMC_EINVAL, "h1 is not symmetric at (%d,%d)", p, q);
+        }
+    for (int64_t i = 0; i < eri_len; ++i)
+        if (!std::isfinite(eri_packed[i])) return fail(FCIQMC_EINVAL, "eri has a non-finite entry");
+    std::unique_ptr<fciqmc_system> s(new fciqmc_system());
+    s->N = n_orb; s->na = n_alpha; s->nb = n_beta; s->e_core = e_core;
+    HIP_OK(hipGetDevice(&s->device));
+    // input structure: which two-electron integrals are non-zero
+    bool onsite = true;
+    for (int64_t P = 0, idx = 0; P < M && onsite; ++P)
+        for (int64_t Q = 0; Q <= P; ++Q, ++idx) {
+            if (eri_packed[idx] == 0.0) continue;
+            // P = p(p+1)/2 + p is a diagonal pair; both pairs must be the same diagonal pair
+            int64_t p = 0;
+            while ((p + 1) * (p + 2) / 2 <= P) ++p;
+            const bool pdiag = (P == p * (p + 1) / 2 + p);
+            if (!(P == Q && pdiag)) onsite = false;
+        }
+    s->onsite = onsite;
+    const int N = n_orb;
+    CHECK(dalloc(s->arena, &s->h1, (size_t)N * N));
+    CHECK(dalloc(s->arena, &s->eri, (size_t)eri_len));
+    CHECK(dalloc(s->arena, &s->J, (size_t)N * N));
+    CHECK(dalloc(s->arena, &s->K, (size_t)N * N));
+    CHECK(dalloc(s->arena, &s->U, (size_t)N));
+    CHECK(dalloc(s->arena, &s->deg, (size_t)N));
+    CHECK(dalloc(s->arena, &s->nbr, (size_t)N * N));
+    const int np = N * (N - 1) / 2;
+    CHECK(dalloc(s->arena, &s->pair_of, (size_t)std::max(np, 1)));
+    HIP_OK(hipMemcpy(s->h1, h1, sizeof(double) * N * N, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(s->eri, eri_packed, sizeof(double) * eri_len, hipMemcpyHostToDevice));
+    // lattice neighbour lists: the distinct q != p with h_pq != 0, ascending
+    std::vector<int> deg(N, 0), nbr((size_t)N * N, 0);
+    for (int p = 0; p < N; ++p)
+        for (int q = 0; q < N; ++q)
+            if (q != p && h1[p * N + q] != 0.0) nbr[(size_t)p * N + deg[p]++] = q;
+    HIP_OK(hipMemcpy(s->deg, deg.data(), sizeof(int) * N, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(s->nbr, nbr.data(), sizeof(int) * N * N, hipMemcpyHostToDevice));
+    std::vector<int> po((size_t)std::max(np, 1), 0);
+    for (int A = 0, c = 0; A < N; ++A)
+        for (int B = A + 1; B < N; ++B, ++c) po[c] = A * 64 + B;
+    HIP_OK(hipMemcpy(s->pair_of, po.data(), sizeof(int) * po.size(), hipMemcpyHostToDevice));
+    SysView v = s->view();
+    hipLaunchKernelGGL(k_build_jk, dim3((N * N + 255) / 256), dim3(256), 0, 0, v, s->J, s->K, s->U);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipDeviceSynchronize());
+    *out = s.release();
+    return 0;
+}
+
+void fciqmc_free_system(fciqmc_system* sys) { delete sys; }
+
+static int device_diag(const fciqmc_system* sys, hipStream_t stream, uint64_t a, uint64_t b, double* out) {
+    Arena tmp;
+    uint64_t* d = nullptr;
+    double* o = nullptr;
+    CHECK(dalloc(tmp, &d, 2));
+    CHECK(dalloc(tmp, &o, 1));
+    uint64_t h[2] = {a, b};
+    HIP_OK(hipMemcpyAsync(d, h, sizeof(h), hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(k_hij, dim3(1), dim3(64), 0, stream, sys->view(), d, d, 1LL, o);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(out, o, sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    tmp.clear();
+    return 0;
+}
+
+static bool valid_det(const fciqmc_system* s, uint64_t a, uint64_t b) {
+    const uint64_t full = (s->N >= 64) ? ~0ULL : ((1ULL << s->N) - 1);
+    return (a & ~full) == 0 && (b & ~full) == 0 && __builtin_popcountll(a) == s->na &&
+           __builtin_popcountll(b) == s->nb;
+}
+
+int fciqmc_init(const fciqmc_system* csys, const fciqmc_params* p, void* stream, fciqmc_run** out) {
+    if (!csys || !p || !out) return fail(FCIQMC_EINVAL, "null argument");
+    *out = nullptr;
+    fciqmc_system* sys = const_cast<fciqmc_system*>(csys);
+    if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return fail(FCIQMC_EINVAL, "tau must be positive");
+    if (p->mode != FCIQMC_MODE_INTEGER && p->mode != FCIQMC_MODE_REAL) return fail(FCIQMC_EINVAL, "unknown mode");
+    if (p->excitgen < 0 || p->excitgen > 2) return fail(FCIQMC_EINVAL, "unknown excitation generator");
+    if (p->excitgen == FCIQMC_GEN_LATTICE && !sys->onsite)
+        return fail(FCIQMC_EINVAL, "the lattice generator needs on-site-only two-electron integrals");
+    if (p->mode == FCIQMC_MODE_REAL && !(p->c_min > 0.0)) return fail(FCIQMC_EINVAL, "c_min must be positive");
+    if (p->shift_interval < 1) return fail(FCIQMC_EINVAL, "shift_interval must be >= 1");
+    if (!(p->n_initial > 0.0)) return fail(FCIQMC_EINVAL, "n_initial must be positive");
+    if (p->mode == FCIQMC_MODE_INTEGER && (p->n_initial != std::floor(p->n_initial) || p->n_initial > 2e9))
+        return fail(FCIQMC_EINVAL, "integer mode needs an integral n_initial below 2e9");
+    const int N = sys->N;
+    int W = p->det_words;
+    if (W == 0) W = N <= 32 ? 1 : 2;
+    if (W != 1 && W != 2) return fail(FCIQMC_EINVAL, "det_words must be 0, 1 or 2");
+    if (W == 1 && N > 32) return fail(FCIQMC_EINVAL, "one-word determinants need n_orb <= 32");
+    std::unique_ptr<fciqmc_run> r(new fciqmc_run());
+    r->sys = sys;
+    r->p = *p;
+    if (stream) r->stream = (hipStream_t)stream;
+    else { HIP_OK(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking)); r->own_stream = true; }
+    uint64_t ra = p->ref_alpha, rb = p->ref_beta;
+    if (ra == 0 && rb == 0) {
+        ra = sys->na >= 64 ? ~0ULL : ((1ULL << sys->na) - 1);
+        rb = sys->nb >= 64 ? ~0ULL : ((1ULL << sys->nb) - 1);
+    }
+    if (!valid_det(sys, ra, rb)) return fail(FCIQMC_EINVAL, "reference determinant is not a valid determinant");
+    r->ref_a = ra; r->ref_b = rb;
+    if (p->excitgen == FCIQMC_GEN_PCHB) CHECK(build_pchb(sys, r->stream));
+    CHECK(device_diag(sys, r->stream, ra, rb, &r->h00));
+    RunScalars rs{};
+    rs.tau = p->tau;
+    const int n = sys->na + sys->nb;
+    if (p->p_single >= 0.0) rs.p_single = p->p_single;
+    else {
+        // Appendix A.2: p_sing ~ nN/(nN + n^2 N^2)
+        const double nN = (double)n * (double)N;
+        const double n2N2 = nN * nN;
+        rs.p_single = nN / (nN + n2N2);
+    }
+    if (p->excitgen == FCIQMC_GEN_LATTICE) rs.p_single = 1.0;
+    rs.p_double = 1.0 - rs.p_single;
+    if (p->p_opp >= 0.0) rs.p_opp = p->p_opp;
+    else {
+        const int64_t npair = (int64_t)n * (n - 1) / 2;
+        rs.p_opp = npair > 0 ? (double)((int64_t)sys->na * sys->nb) / (double)npair : 0.0;
+    }
+    rs.n_a = p->initiator_na;
+    rs.c_min = p->c_min;
+    rs.h00 = r->h00;
+    rs.seed = p->seed; rs.replica = p->replica_id;
+    rs.ref_a = ra; rs.ref_b = rb;
+    rs.gen = p->excitgen;
+    const double target = std::max(1.0, p->walker_target);
+    // capacities start from the hints (or the target) and grow on demand
+    int64_t max_dets = p->max_dets > 0 ? p->max_dets : (int64_t)std::min(target, 16777216.0);
+    max_dets = std::max<int64_t>(max_dets, 1024);
+    int B = p->buckets_log2 > 0 ? (1 << std::min(p->buckets_log2, 22)) : (int)next_pow2((uint64_t)((max_dets + 255) / 256));
+    long long spawn_cap = p->max_spawns > 0 ? p->max_spawns
+                                            : (long long)std::min(std::max(65536.0, 2.0 * target), 33554432.0);
+    if (W == 1 && p->mode == FCIQMC_MODE_INTEGER) r->eng.reset(new Engine<1, int32_t>(sys, r->stream, rs));
+    else if (W == 1) r->eng.reset(new Engine<1, double>(sys, r->stream, rs));
+    else if (p->mode == FCIQMC_MODE_INTEGER) r->eng.reset(new Engine<2, int32_t>(sys, r->stream, rs));
+    else r->eng.reset(new Engine<2, double>(sys, r->stream, rs));
+    int rc;
+    if (W == 1 && p->mode == FCIQMC_MODE_INTEGER) rc = static_cast<Engine<1, int32_t>*>(r->eng.get())->init(B, spawn_cap, p->hbm_budget_bytes);
+    else if (W == 1) rc = static_cast<Engine<1, double>*>(r->eng.get())->init(B, spawn_cap, p->hbm_budget_bytes);
+    else if (p->mode == FCIQMC_MODE_INTEGER) rc = static_cast<Engine<2, int32_t>*>(r->eng.get())->init(B, spawn_cap, p->hbm_budget_bytes);
+    else rc = static_cast<Engine<2, double>*>(r->eng.get())->init(B, spawn_cap, p->hbm_budget_bytes);
+    if (rc) return rc;
+    uint64_t ab[2] = {ra, rb};
+    double v0 = p->n_initial;
+    CHECK(r->eng->set_walkers(ab, &v0, 1));
+    if (p->shift_restore >= 0.0) r->xi = p->shift_restore;
+    else {
+        const double z2 = p->shift_damping * p->shift_damping;
+        r->xi = z2 / 4.0;
+    }
+    r->nw_ring.assign((size_t)p->shift_interval + 1, 0.0);
+    r->t_set = 0;
+    r->nw_ring[0] = r->eng->last_nw();
+    *out = r.release();
+    return 0;
+}
+
+void fciqmc_free_run(fciqmc_run* run) { delete run; }
+
+int64_t fciqmc_run_device_bytes(const fciqmc_run* run) { return run && run->eng ? run->eng->bytes() : 0; }
+
+int fciqmc_profile(fciqmc_run* run, int enable, double* ms, int64_t* steps, int64_t* layout) {
+    if (!run || !run->eng) return fail(FCIQMC_ESTATE, "run not initialised");
+    if (enable) CHECK(run->eng->enable_profile());
+    if (ms && steps) run->eng->kernel_times(ms, steps);
+    if (layout) {
+        layout[0] = run->eng->buckets();
+        layout[1] = run->eng->spawn_capacity();
+    }
+    return 0;
+}
+
+// Population control (Sec. I leaves the update open).  Reading: S stays 0
+// (relative to H_00) until N_w first reaches the target N_t.  At that step T
+// the shift is set from the measured growth rate,
+// S = -ln(N_w(T)/N_w(T-L))/(L dtau), L = min(A, steps since the population was
+// set).  From then on, every A steps,
+//   S <- S - zeta/(A dtau) ln(N_w(t)/N_w(t-A)) - xi/(A dtau) ln(N_w(t)/N_t),
+// the damped control of the original method plus the restoring term of
+// Yang, Pahl and Brand (J. Chem. Phys. 153, 174103 (2020)); xi = zeta^2/4 by
+// default.  An extinct population (N_w = 0) leaves S unchanged.
+static void shift_update(fciqmc_run* r, double nw) {
+    const int64_t T = r->t;
+    const int64_t A = (int64_t)r->p.shift_interval;
+    if (!r->vary) {
+        if (nw >= r->p.walker_target) {
+            r->vary = 1;
+            int64_t L = std::min<int64_t>(T - r->t_set, A);
+            if (L > 0) {
+                const double nw_prev = r->nw_ring[(size_t)((T - L) % (A + 1))];
+                const double c = 1.0 / ((double)L * r->p.tau);
+                const double ratio = nw / nw_prev;
+                const double l = std::log(ratio);
+                const double dS = c * l;
+                r->S = 0.0 - dS;
+            }
+            r->t_last = T;
+            r->nw_last = nw;
+            r->t_vary = T;
+        }
+    } else if (T - r->t_last == A && nw > 0.0) {
+        const double at = (double)r->p.shift_interval * r->p.tau;
+        const double c1 = r->p.shift_damping / at;
+        const double c2 = r->xi / at;
+        const double l1 = std::log(nw / r->nw_last);
+        const double l2 = std::log(nw / r->p.walker_target);
+        const double d1 = c1 * l1;
+        const double d2 = c2 * l2;
+        const double s1 = r->S - d1;
+        r->S = s1 - d2;
+        r->t_last = T;
+        r->nw_last = nw;
+    }
+    r->nw_ring[(size_t)(T % (A + 1))] = nw;
+}
+
+int fciqmc_step(fciqmc_run* run, int n_steps, fciqmc_step_stats* stats) {
+    if (!run || !run->eng) return fail(FCIQMC_ESTATE, "run not initialised");
+    if (n_steps < 0) return fail(FCIQMC_EINVAL, "n_steps must be >= 0");
+    for (int i = 0; i < n_steps; ++i) {
+        Ctl c{};
+        int retries = 0;
+        int64_t attempts = 0;
+        CHECK(run->eng->step_once(run->t, run->S, c, retries, attempts));
+        run->t += 1;
+        shift_update(run, c.nw);
+        fciqmc_step_stats s{};
+        s.iter = run->t;
+        s.nw = c.nw;
+        s.nref = c.nref;
+        s.enum_ = c.enum_;
+        s.shift = run->S;
+        const double eref = run->h00 + run->sys->e_core;
+        const double q = c.enum_ / c.nref;
+        s.e_proj = eref + q;
+        s.ndets = c.ndets;
+        s.attempts = attempts;
+        s.spawns = c.nrec_out;
+        s.vary_shift = run->vary;
+        s.retries = retries;
+        run->hist.push_back(s);
+        if (stats) stats[i] = s;
+    }
+    return 0;
+}
+
+// Flyvbjerg-Petersen blocking of a mean and of a ratio of means.
+namespace {
+struct Level { double err, derr; };
+
+double plateau(const std::vector<Level>& lv) {
+    const int n = (int)lv.size();
+    for (int i = 0; i + 4 <= n; ++i) {
+        bool ok = true;
+        for (int j = i + 1; j <= i + 3; ++j)
+            if (std::fabs(lv[j].err - lv[i].err) > 2.0 * (lv[i].derr + lv[j].derr)) ok = false;
+        if (ok) return lv[i].err;
+    }
+    double m = 0.0;
+    for (int i = 0; i < std::max(1, n - 3); ++i) m = std::max(m, lv[i].err);
+    return m;
+}
+
+void blocking(std::vector<double> x, std::vector<double> y, double& mx, double& ex, double& my,
+              double& ratio, double& eratio) {
+    const size_t n0 = x.size();
+    mx = 0.0; my = 0.0;
+    for (size_t i = 0; i < n0; ++i) { mx += x[i]; my += y[i]; }
+    mx /= (double)n0; my /= (double)n0;
+    ratio = my != 0.0 ? mx / my : NAN;
+    std::vector<Level> lx, lr;
+    while (x.size() >= 2) {
+        const size_t n = x.size();
+        double vx = 0.0, vy = 0.0, cxy = 0.0;
+        for (size_t i = 0; i < n; ++i) {
+            vx += (x[i] - mx) * (x[i] - mx);
+            vy += (y[i] - my) * (y[i] - my);
+            cxy += (x[i] - mx) * (y[i] - my);
+        }
+        vx /= (double)n; vy /= (double)n; cxy /= (double)n;
+        const double e = std::sqrt(vx / (double)(n - 1));
+        const double de = e / std::sqrt(2.0 * (double)(n - 1));
+        lx.push_back({e, de});
+        const double vr = (vx / (my * my) - 2.0 * mx * cxy / (my * my * my) + mx * mx * vy / (my * my * my * my)) /
+                          (double)(n - 1);
+        const double er = std::sqrt(std::max(vr, 0.0));
+        lr.push_back({er, er / std::sqrt(2.0 * (double)(n - 1))});
+        const size_t m = n / 2;
+        for (size_t i = 0; i < m; ++i) {
+            x[i] = 0.5 * (x[2 * i] + x[2 * i + 1]);
+            y[i] = 0.5 * (y[2 * i] + y[2 * i + 1]);
+        }
+        x.resize(m);
+        y.resize(m);
+    }
+    ex = lx.empty() ? NAN : plateau(lx);
+    eratio = lr.empty() ? NAN : plateau(lr);
+}
+}  // namespace
+
+int fciqmc_energy(const fciqmc_run* run, fciqmc_energy_report* out) {
+    if (!run || !out) return fail(FCIQMC_EINVAL, "null argument");
+    std::memset(out, 0, sizeof(*out));
+    const double eref = run->h00 + run->sys->e_core;
+    out->e_ref = eref;
+    out->steps_done = run->t;
+    out->e_proj = out->e_proj_err = out->shift = out->shift_err = NAN;
+    if (run->t_vary < 0) return 0;
+    const int64_t after = run->t - run->t_vary;
+    int64_t equil = run->p.equil_steps;
+    if (equil < 0) equil = std::max<int64_t>((int64_t)std::ceil(1.0 / run->p.tau), after / 5);
+    const int64_t first = run->t_vary + equil;  // first step number used
+    std::vector<double> S, E, Nr;
+    for (const auto& h : run->hist)
+        if (h.iter > first) { S.push_back(h.shift); E.push_back(h.enum_); Nr.push_back(h.nref); }
+    out->first_step = first + 1;
+    out->n_samples = (int64_t)S.size();
+    if (S.size() < 16) return 0;
+    double ms, es, me, mn, r, er, dummy;
+    std::vector<double> ones(S.size(), 1.0);
+    blocking(S, ones, ms, es, dummy, r, er);
+    blocking(E, Nr, me, dummy, mn, r, er);
+    out->shift = eref + ms;
+    out->shift_err = es;
+    out->e_proj = eref + r;
+    out->e_proj_err = er;
+    out->converged = std::fabs(out->shift - out->e_proj) < run->p.conv_tol && es < run->p.conv_tol &&
+                     er < run->p.conv_tol;
+    return 0;
+}
+
+int fciqmc_get_walkers(const fciqmc_run* run, uint64_t* dets, double* vals, int64_t cap, int64_t* n) {
+    if (!run || !run->eng || !n) return fail(FCIQMC_EINVAL, "null argument");
+    std::vector<uint64_t> ab;
+    std::vector<double> v;
+    CHECK(run->eng->get_walkers(ab, v));
+    *n = (int64_t)v.size();
+    if (*n > cap) return fail(FCIQMC_EOVERFLOW, "need room for %lld determinants", (long long)*n);
+    if (*n > 0) {
+        if (!dets || !vals) return fail(FCIQMC_EINVAL, "null output array");
+        std::memcpy(dets, ab.data(), sizeof(uint64_t) * ab.size());
+        std::memcpy(vals, v.data(), sizeof(double) * v.size());
+    }
+    return 0;
+}
+
+int fciqmc_set_walkers(fciqmc_run* run, const uint64_t* dets, const double* vals, int64_t n) {
+    if (!run || !run->eng) return fail(FCIQMC_ESTATE, "run not initialised");
+    if (n < 0 || (n > 0 && (!dets || !vals))) return fail(FCIQMC_EINVAL, "bad walker arrays");
+    std::vector<std::pair<uint64_t, uint64_t>> keys((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        if (!valid_det(run->sys, dets[2 * i], dets[2 * i + 1]))
+            return fail(FCIQMC_EINVAL, "entry %lld is not a valid determinant", (long long)i);
+        const double v = vals[i];
+        if (!(v != 0.0) || !std::isfinite(v)) return fail(FCIQMC_EINVAL, "entry %lld has a zero or non-finite value", (long long)i);
+        if (run->p.mode == FCIQMC_MODE_INTEGER && (v != std::floor(v) || std::fabs(v) > 2e9))
+            return fail(FCIQMC_EINVAL, "integer mode needs integral values (entry %lld)", (long long)i);
+        keys[(size_t)i] = {dets[2 * i], dets[2 * i + 1]};
+    }
+    std::sort(keys.begin(), keys.end());
+    if (std::adjacent_find(keys.begin(), keys.end()) != keys.end()) return fail(FCIQMC_EINVAL, "duplicate determinants");
+    CHECK(run->eng->set_walkers(dets, vals, n));
+    const int64_t A = run->p.shift_interval;
+    run->t_set = run->t;
+    run->nw_ring[(size_t)(run->t % (A + 1))] = run->eng->last_nw();
+    return 0;
+}
+
+int fciqmc_get_checkpoint(const fciqmc_run* run, fciqmc_checkpoint* out) {
+    if (!run || !out) return fail(FCIQMC_EINVAL, "null argument");
+    out->iter = run->t;
+    out->shift = run->S;
+    out->vary_shift = run->vary;
+    out->last_update_iter = run->t_last;
+    out->last_update_nw = run->nw_last;
+    return 0;
+}
+
+int fciqmc_set_checkpoint(fciqmc_run* run, const fciqmc_checkpoint* in) {
+    if (!run || !in) return fail(FCIQMC_EINVAL, "null argument");
+    if (in->iter < 0) return fail(FCIQMC_EINVAL, "negative iteration");
+    const int64_t A = run->p.shift_interval;
+    const double nw0 = run->nw_ring[(size_t)(run->t % (A + 1))];
+    run->t = in->iter;
+    run->t_set = in->iter;
+    run->nw_ring[(size_t)(run->t % (A + 1))] = nw0;
+    run->S = in->shift;
+    run->vary = in->vary_shift ? 1 : 0;
+    run->t_last = in->last_update_iter;
+    run->nw_last = in->last_update_nw;
+    run->t_vary = run->vary ? in->last_update_iter : -1;
+    run->hist.clear();
+    return 0;
+}
+
+int fciqmc_matrix_elements(const fciqmc_system* sys, const uint64_t* di, const uint64_t* dj, int64_t n,
+                           double* out) {
+    if (!sys || (n > 0 && (!di || !dj || !out))) return fail(FCIQMC_EINVAL, "null argument");
+    if (n == 0) return 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (!valid_det(sys, di[2 * i], di[2 * i + 1]) || !valid_det(sys, dj[2 * i], dj[2 * i + 1]))
+            return fail(FCIQMC_EINVAL, "pair %lld holds an invalid determinant", (long long)i);
+    Arena tmp;
+    uint64_t *a = nullptr, *b = nullptr;
+    double* o = nullptr;
+    CHECK(dalloc(tmp, &a, (size_t)n * 2));
+    CHECK(dalloc(tmp, &b, (size_t)n * 2));
+    CHECK(dalloc(tmp, &o, (size_t)n));
+    HIP_OK(hipMemcpy(a, di, sizeof(uint64_t) * 2 * n, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(b, dj, sizeof(uint64_t) * 2 * n, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_hij, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, 0,
+                       sys->view(), a, b, (long long)n, o);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpy(out, o, sizeof(double) * n, hipMemcpyDeviceToHost));
+    tmp.clear();
+    return 0;
+}
+
+}  // extern "C"

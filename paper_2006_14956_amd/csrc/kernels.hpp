@@ -1,0 +1,616 @@
+// Kernels of one FCIQMC step (Eq. fciqmc_dyn: spawn, death, annihilation
+// with the initiator rule) on a hash-partitioned walker store.
+//
+// Walker store: B buckets; determinant D lives in bucket
+// floor(hash(D) * B / 2^64).  Bucket b owns R consecutive entries (keys,
+// values, cached H_ii - H_00, and the exclusive prefix of the attempt counts)
+// plus a count.  Each step reads one store and writes the other.
+//
+// Per step:
+//   k_spawn      one lane per spawn attempt -> spawn records (global append)
+//                and per-bucket record counts
+//   k_scan_count per-bucket record offsets
+//   k_scatter    records grouped by target bucket
+//   k_annihilate one workgroup per bucket: death of the bucket's walkers,
+//                LDS hash merge of its spawn records under the initiator
+//                rule, stochastic rounding, compaction into the other store,
+//                estimator partial sums
+//   k_post       attempt offsets for the next step, global sums
+#pragma once
+#include "device.hpp"
+
+namespace fq {
+
+constexpr int kThreads = 256;
+constexpr int kSlots = 2048;        // LDS hash slots per bucket
+constexpr int kSlotsPerThread = kSlots / kThreads;
+
+template <int W, class V> struct Rec {
+    uint64_t k[W];
+    V v;
+    uint32_t flag;  // bit 0: parent is an initiator; bits 1..: target bucket
+};
+
+template <class V> struct Store {
+    uint64_t* keys;   // B*R*W
+    V* vals;          // B*R
+    double* diag;     // B*R
+    int32_t* mpre;    // B*R: exclusive prefix of attempts within the bucket
+    int32_t* count;   // B
+    int64_t* batt;    // B: attempts of the bucket
+    int64_t* aoff;    // B+1: exclusive prefix of batt
+};
+
+struct Ctl {
+    unsigned long long nrec;   // spawn records emitted this step (may exceed capacity)
+    unsigned int flags;        // kFlag*
+    unsigned int pad0;
+    double nref;               // C_ref after the step
+    // written by k_post
+    double nw;
+    double enum_;
+    long long ndets;
+    long long attempts;        // attempts of the next step
+    long long nrec_out;
+    long long max_count;       // fullest bucket
+};
+
+template <class V> __device__ __forceinline__ double vabs(V v) { return v < 0 ? -(double)v : (double)v; }
+
+// Attempts a determinant makes: |C| walkers (integer) or ceil(|C|) (real).
+template <class V> __device__ __forceinline__ int64_t n_attempts(V v) {
+    if constexpr (sizeof(V) == 4) return v < 0 ? -(int64_t)v : (int64_t)v;
+    else return (int64_t)ceil(fabs((double)v));
+}
+
+struct StepScalars {
+    int64_t t;
+    uint64_t seed, replica;
+    double tau, p_single, p_double, p_opp, n_a, c_min, S, h00;
+    uint64_t ref_a, ref_b;
+    int B, R;
+    long long spawn_cap;
+    int import_mode;
+};
+
+// ---------------------------------------------------------------------------
+// Spawn (Sec. I, step (a)): attempt k of determinant D_i draws an excitation
+// D_j with probability p_gen, computes H_ji and spawns with p_s = dtau|H|/p_gen
+// (Sec. II).  Attempts are numbered globally by the prefix sums of the
+// attempt counts; each lane finds its (bucket, entry, k) by binary search.
+// ---------------------------------------------------------------------------
+template <int W, class V, int GEN>
+__global__ __launch_bounds__(kThreads) void k_spawn(SysView sys, Store<V> st, StepScalars sc,
+                                                    Rec<W, V>* __restrict__ rec,
+                                                    int32_t* __restrict__ scount, Ctl* ctl) {
+    const int64_t total = st.aoff[sc.B];
+    const Key<W> ref = make_key<W>(sc.ref_a, sc.ref_b);
+    for (int64_t base = (int64_t)blockIdx.x * kThreads; base < total;
+         base += (int64_t)gridDim.x * kThreads) {
+        const int64_t at = base + threadIdx.x;
+        bool emit = false;
+        Rec<W, V> out;
+        if (at < total) {
+            int lo = 0, hi = sc.B;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (st.aoff[mid] <= at) lo = mid; else hi = mid;
+            }
+            const int b = lo;
+            const int64_t local = at - st.aoff[b];
+            const int64_t eb = (int64_t)b * sc.R;
+            int elo = 0, ehi = st.count[b];
+            while (ehi - elo > 1) {
+                const int mid = (elo + ehi) >> 1;
+                if ((int64_t)st.mpre[eb + mid] <= local) elo = mid; else ehi = mid;
+            }
+            const int64_t e = eb + elo;
+            const uint64_t k = (uint64_t)(local - st.mpre[e]);
+            const Key<W> key = load_key<W>(st.keys + e * W);
+            const V C = st.vals[e];
+            const double aC = vabs(C);
+            const bool init = (sc.n_a < 0.0) || (aC > sc.n_a) || key_eq<W>(key, ref);
+            const uint64_t da = key_alpha<W>(key), db = key_beta<W>(key);
+            const R4 r = draw<W>(key, sc.t, k, kSpawn, sc.seed, sc.replica);
+            Exc x;
+            bool ok;
+            if constexpr (GEN == 0) ok = gen_uniform(sys, da, db, r, sc.p_single, sc.p_double, x);
+            else if constexpr (GEN == 1) ok = gen_lattice(sys, da, db, r, x);
+            else {
+                const R4 r2 = draw<W>(key, sc.t, k, kSpawn2, sc.seed, sc.replica);
+                ok = gen_pchb(sys, da, db, r, r2, sc.p_single, sc.p_double, sc.p_opp, x);
+            }
+            if (ok && x.H != 0.0) {
+                const double u = unif(r.x[3]);
+                if constexpr (sizeof(V) == 4) {
+                    const double num = sc.tau * fabs(x.H);
+                    const double ps = num / x.pgen;
+                    const double fl = floor(ps);
+                    const double fr = ps - fl;
+                    const double nn = fl + (u < fr ? 1.0 : 0.0);
+                    if (nn != 0.0) {
+                        if (nn > 1073741824.0) atomicOr(&ctl->flags, kFlagBloom);
+                        const int32_t m = (int32_t)fmin(nn, 1073741824.0);
+                        // child sign -sgn(H) sgn(C): the -dtau H_ji C_i term of Eq. (projector)
+                        out.v = ((x.H > 0.0) == (C > 0)) ? -m : m;
+                        emit = true;
+                    }
+                } else {
+                    const double x1 = sc.tau * x.H;
+                    const double x2 = x1 * (double)C;
+                    const double d1 = x.pgen * (double)n_attempts(C);
+                    double amp = -(x2 / d1);
+                    const double aa = fabs(amp);
+                    if (aa < sc.c_min) {
+                        const double pr = aa / sc.c_min;
+                        amp = (u < pr) ? (amp < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
+                    }
+                    if (amp != 0.0) { out.v = (V)amp; emit = true; }
+                }
+                if (emit) {
+                    const Key<W> tk = make_key<W>(x.ta, x.tb);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) out.k[w] = tk.w[w];
+                    const uint32_t bk = bucket_of(key_hash<W>(tk), (uint32_t)sc.B);
+                    out.flag = (init ? 1u : 0u) | (bk << 1);
+                }
+            }
+        }
+        // wave-aggregated append
+        const uint64_t mask = __ballot(emit);
+        if (mask) {
+            const int leader = __ffsll((unsigned long long)mask) - 1;
+            unsigned long long pos0 = 0;
+            if (lane_id() == leader) pos0 = atomicAdd(&ctl->nrec, (unsigned long long)popc64(mask));
+            pos0 = __shfl(pos0, leader);
+            if (emit) {
+                const unsigned long long pos = pos0 + (unsigned long long)lane_rank(mask);
+                if (pos < (unsigned long long)sc.spawn_cap) {
+                    rec[pos] = out;
+                    atomicAdd(&scount[out.flag >> 1], 1);
+                } else {
+                    atomicOr(&ctl->flags, kFlagSpawnCap);
+                }
+            }
+        }
+    }
+}
+
+// Records uploaded from the host (population import): assign buckets.
+template <int W, class V>
+__global__ __launch_bounds__(kThreads) void k_bucketize(Rec<W, V>* rec, long long n, int B,
+                                                        int32_t* scount) {
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kThreads) {
+        Key<W> k;
+#pragma unroll
+        for (int w = 0; w < W; ++w) k.w[w] = rec[i].k[w];
+        const uint32_t b = bucket_of(key_hash<W>(k), (uint32_t)B);
+        rec[i].flag = (rec[i].flag & 1u) | (b << 1);
+        atomicAdd(&scount[b], 1);
+    }
+}
+
+// Exclusive prefix of per-bucket int32 counts into int64 offsets (B+1),
+// single workgroup of 1024 threads, each scanning a contiguous segment.
+__global__ __launch_bounds__(1024) void k_scan_count(const int32_t* __restrict__ cnt, int B,
+                                                     int64_t* __restrict__ off, Ctl* ctl) {
+    if (ctl && ctl->flags) return;
+    __shared__ int64_t sh[16];
+    const int T = 1024;
+    const int per = (B + T - 1) / T;
+    const int s0 = threadIdx.x * per;
+    const int s1 = min(B, s0 + per);
+    int64_t loc = 0;
+    for (int i = s0; i < s1; ++i) loc += cnt[i];
+    int64_t tot;
+    int64_t run = block_excl_scan<1024, int64_t>(loc, tot, sh);
+    for (int i = s0; i < s1; ++i) { off[i] = run; run += cnt[i]; }
+    if (threadIdx.x == 0) off[B] = tot;
+}
+
+template <int W, class V>
+__global__ __launch_bounds__(kThreads) void k_scatter(const Rec<W, V>* __restrict__ rec,
+                                                      Rec<W, V>* __restrict__ rec2,
+                                                      const int64_t* __restrict__ soff,
+                                                      int32_t* __restrict__ scur, Ctl* ctl,
+                                                      long long cap) {
+    if (ctl->flags) return;
+    const long long n = min((long long)ctl->nrec, cap);
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kThreads) {
+        const Rec<W, V> r = rec[i];
+        const uint32_t b = r.flag >> 1;
+        const int64_t pos = soff[b] + atomicAdd(&scur[b], 1);
+        rec2[pos] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LDS hash table of one bucket.
+// ---------------------------------------------------------------------------
+template <int W, class V> struct Lds {
+    uint64_t key0[kSlots];
+    uint64_t key1[W == 2 ? kSlots : 1];
+    V val[kSlots];
+    int32_t idx[kSlots];   // entry index in the input store, -1 for a new determinant
+    int64_t sh64[8];
+    double shd[8];
+};
+
+template <int W> __device__ __forceinline__ uint64_t lds_load(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Find the slot of `key`; insert it if absent and `insert` is set.
+// Returns the slot, -1 if absent (not inserted), -2 if the table is full,
+// -3 if a claimed slot never became readable.
+template <int W, class V>
+__device__ __forceinline__ int lds_find(Lds<W, V>& L, const Key<W>& key, uint64_t h, bool insert) {
+    int s = (int)(h & (uint64_t)(kSlots - 1));
+    int probes = 0;
+    int spins = 0;
+    while (true) {
+        uint64_t w0 = lds_load<W>(&L.key0[s]);
+        if (w0 == kEmpty) {
+            if (!insert) return -1;
+            if constexpr (W == 1) {
+                const uint64_t old = atomicCAS((unsigned long long*)&L.key0[s], kEmpty, key.w[0]);
+                if (old == kEmpty || old == key.w[0]) return s;
+                w0 = old;
+            } else {
+                const uint64_t old = atomicCAS((unsigned long long*)&L.key0[s], kEmpty, kLocked);
+                if (old == kEmpty) {
+                    __hip_atomic_store(&L.key1[s], key.w[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    __hip_atomic_store(&L.key0[s], key.w[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    return s;
+                }
+                w0 = old;
+            }
+        }
+        if constexpr (W == 2) {
+            if (w0 == kLocked) {
+                // retry the same slot in the next pass of this loop, so the
+                // claiming lane (possibly in this wave) publishes first
+                if (++spins > (1 << 22)) return -3;
+                continue;
+            }
+            if (w0 == key.w[0]) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                if (lds_load<W>(&L.key1[s]) == key.w[1]) return s;
+            }
+        } else {
+            if (w0 == key.w[0]) return s;
+        }
+        s = (s + 1) & (kSlots - 1);
+        if (++probes >= kSlots) return -2;
+    }
+}
+
+template <class V> __device__ __forceinline__ void lds_add(V* p, V v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// ---------------------------------------------------------------------------
+// Death, annihilation with the initiator rule, compaction and estimators,
+// one workgroup per bucket (Sec. I steps (b) and (c); Sec. IV Eq. (proje)).
+// ---------------------------------------------------------------------------
+template <int W, class V>
+__global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> in, Store<V> out,
+                                                         StepScalars sc,
+                                                         const Rec<W, V>* __restrict__ rec2,
+                                                         const int64_t* __restrict__ soff,
+                                                         double* __restrict__ nw_b,
+                                                         double* __restrict__ en_b, Ctl* ctl) {
+    if (ctl->flags) return;
+    __shared__ Lds<W, V> L;
+    const Key<W> ref = make_key<W>(sc.ref_a, sc.ref_b);
+    constexpr bool kInt = sizeof(V) == 4;
+    for (int b = blockIdx.x; b < sc.B; b += gridDim.x) {
+        for (int i = threadIdx.x; i < kSlots; i += kThreads) {
+            L.key0[i] = kEmpty;
+            if constexpr (W == 2) L.key1[i] = kEmpty;
+            L.val[i] = (V)0;
+            L.idx[i] = -1;
+        }
+        __syncthreads();
+        const int64_t eb = (int64_t)b * sc.R;
+        // (b) death of the walkers occupied at tau: x = (1 - dtau (d_i - S)) C_i,
+        // stochastically rounded; the slot is marked as occupied at tau.
+        if (!sc.import_mode) {
+            const int cnt = in.count[b];
+            for (int e = threadIdx.x; e < cnt; e += kThreads) {
+                const Key<W> key = load_key<W>(in.keys + (eb + e) * W);
+                const V C = in.vals[eb + e];
+                const double d = in.diag[eb + e];
+                const double t1 = d - sc.S;
+                const double t2 = sc.tau * t1;
+                const double f = 1.0 - t2;
+                const double xv = f * (double)C;
+                const double u = unif(draw<W>(key, sc.t, 0, kDeath, sc.seed, sc.replica).x[0]);
+                V post;
+                if constexpr (kInt) {
+                    const double ax = fabs(xv);
+                    const double fl = floor(ax);
+                    const double fr = ax - fl;
+                    const double nn = fl + (u < fr ? 1.0 : 0.0);
+                    if (nn > 2147483000.0) atomicOr(&ctl->flags, kFlagPop);
+                    post = (V)(xv < 0.0 ? -nn : nn);
+                } else {
+                    const double ax = fabs(xv);
+                    double y = xv;
+                    if (ax < sc.c_min && xv != 0.0) {
+                        const double pr = ax / sc.c_min;
+                        y = (u < pr) ? (xv < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
+                    }
+                    post = (V)y;
+                }
+                const int s = lds_find<W, V>(L, key, key_hash<W>(key), true);
+                if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); continue; }
+                L.val[s] = post;
+                L.idx[s] = e;
+            }
+        }
+        __syncthreads();
+        // (c) annihilation: a target occupied at tau takes every contribution;
+        // an unoccupied one only those of initiator parents (Sec. I).
+        const int64_t r0 = soff[b], r1 = soff[b + 1];
+        for (int64_t r = r0 + threadIdx.x; r < r1; r += kThreads) {
+            const Rec<W, V> x = rec2[r];
+            Key<W> key;
+#pragma unroll
+            for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
+            const bool init = (x.flag & 1u) != 0;
+            const int s = lds_find<W, V>(L, key, key_hash<W>(key), init);
+            if (s == -1) continue;
+            if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); continue; }
+            if (init || L.idx[s] >= 0) lds_add<V>(&L.val[s], x.v);
+        }
+        __syncthreads();
+        // compaction, stochastic rounding of small real amplitudes, estimators
+        int nkeep = 0;
+        int64_t mloc = 0;
+        const int s0 = threadIdx.x * kSlotsPerThread;
+#pragma unroll
+        for (int j = 0; j < kSlotsPerThread; ++j) {
+            const int s = s0 + j;
+            if (L.key0[s] == kEmpty) continue;
+            V v = L.val[s];
+            if constexpr (!kInt) {
+                if (!sc.import_mode) {
+                    const double av = fabs((double)v);
+                    if (v != 0.0 && av < sc.c_min) {
+                        Key<W> key;
+                        key.w[0] = L.key0[s];
+                        if constexpr (W == 2) key.w[1] = L.key1[s];
+                        const double u = unif(draw<W>(key, sc.t, 0, kAnn, sc.seed, sc.replica).x[0]);
+                        const double pr = av / sc.c_min;
+                        v = (u < pr) ? (v < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
+                        L.val[s] = v;
+                    }
+                }
+            }
+            if (v != (V)0) { ++nkeep; mloc += n_attempts(v); }
+        }
+        int nkeep_tot;
+        int pos = block_excl_scan<kThreads, int>(nkeep, nkeep_tot, (int*)L.sh64);
+        int64_t m_tot;
+        int64_t mpos = block_excl_scan<kThreads, int64_t>(mloc, m_tot, L.sh64);
+        if (nkeep_tot > sc.R || m_tot >= (int64_t)0x7FFFFFFF) {
+            if (threadIdx.x == 0) atomicOr(&ctl->flags, kFlagStore);
+            __syncthreads();
+            continue;
+        }
+        double nw = 0.0, en = 0.0;
+#pragma unroll
+        for (int j = 0; j < kSlotsPerThread; ++j) {
+            const int s = s0 + j;
+            if (L.key0[s] == kEmpty) continue;
+            const V v = L.val[s];
+            if (v == (V)0) continue;
+            Key<W> key;
+            key.w[0] = L.key0[s];
+            if constexpr (W == 2) key.w[1] = L.key1[s];
+            const int64_t o = eb + pos;
+            store_key<W>(out.keys + o * W, key);
+            out.vals[o] = v;
+            const int oi = L.idx[s];
+            const uint64_t ka = key_alpha<W>(key), kb = key_beta<W>(key);
+            double d;
+            if (oi >= 0) d = in.diag[eb + oi];
+            else { const double hd = h_diag(sys, ka, kb); d = hd - sc.h00; }
+            out.diag[o] = d;
+            out.mpre[o] = (int32_t)mpos;
+            ++pos;
+            mpos += n_attempts(v);
+            const double av = vabs(v);
+            nw = nw + av;
+            if (key_eq<W>(key, ref)) {
+                ctl->nref = (double)v;
+            } else {
+                const int lvl = popc64(ka ^ sc.ref_a) + popc64(kb ^ sc.ref_b);
+                if (lvl == 2 || lvl == 4) {
+                    const double h = h_offdiag(sys, sc.ref_a, sc.ref_b, ka, kb);
+                    const double c = h * (double)v;
+                    en = en + c;
+                }
+            }
+        }
+        nw = wave_sum(nw);
+        en = wave_sum(en);
+        if (lane_id() == 0) { L.shd[threadIdx.x >> 6] = nw; L.shd[4 + (threadIdx.x >> 6)] = en; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            nw_b[b] = ((L.shd[0] + L.shd[1]) + L.shd[2]) + L.shd[3];
+            en_b[b] = ((L.shd[4] + L.shd[5]) + L.shd[6]) + L.shd[7];
+            out.count[b] = nkeep_tot;
+            out.batt[b] = m_tot;
+        }
+        __syncthreads();
+    }
+}
+
+// Attempt offsets for the next step and global sums (one workgroup).
+__global__ __launch_bounds__(1024) void k_post(const int64_t* __restrict__ batt,
+                                               const int32_t* __restrict__ count,
+                                               const double* __restrict__ nw_b,
+                                               const double* __restrict__ en_b, int B,
+                                               int64_t* __restrict__ aoff, Ctl* ctl) {
+    if (ctl->flags) return;
+    __shared__ int64_t sh[16];
+    __shared__ double shd[32];
+    const int T = 1024;
+    const int per = (B + T - 1) / T;
+    const int s0 = threadIdx.x * per;
+    const int s1 = min(B, s0 + per);
+    int64_t loc = 0, cnt = 0, mx = 0;
+    double nw = 0.0, en = 0.0;
+    for (int i = s0; i < s1; ++i) {
+        loc += batt[i];
+        cnt += count[i];
+        mx = max(mx, (int64_t)count[i]);
+        nw = nw + nw_b[i];
+        en = en + en_b[i];
+    }
+    int64_t tot;
+    int64_t run = block_excl_scan<1024, int64_t>(loc, tot, sh);
+    for (int i = s0; i < s1; ++i) { aoff[i] = run; run += batt[i]; }
+    int64_t ctot;
+    (void)block_excl_scan<1024, int64_t>(cnt, ctot, sh);
+    // fixed-order reductions: wave tree, then the 16 wave sums in order
+    nw = wave_sum(nw);
+    en = wave_sum(en);
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, (int64_t)__shfl_xor(mx, o));
+    __shared__ int64_t shm[16];
+    if (lane_id() == 0) { shd[threadIdx.x >> 6] = nw; shd[16 + (threadIdx.x >> 6)] = en; shm[threadIdx.x >> 6] = mx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, c = 0.0;
+        int64_t m = 0;
+        for (int i = 0; i < 16; ++i) { a = a + shd[i]; c = c + shd[16 + i]; m = max(m, shm[i]); }
+        aoff[B] = tot;
+        ctl->nw = a;
+        ctl->enum_ = c;
+        ctl->ndets = ctot;
+        ctl->attempts = tot;
+        ctl->nrec_out = (long long)ctl->nrec;
+        ctl->max_count = m;
+    }
+}
+
+// Copy the store to flat arrays (offsets from a count scan).
+template <int W, class V>
+__global__ __launch_bounds__(kThreads) void k_extract(Store<V> st, int R, const int64_t* __restrict__ off,
+                                                      uint64_t* __restrict__ keys,
+                                                      double* __restrict__ vals, int B) {
+    for (int b = blockIdx.x; b < B; b += gridDim.x) {
+        const int cnt = st.count[b];
+        const int64_t o = off[b];
+        for (int e = threadIdx.x; e < cnt; e += kThreads) {
+            const int64_t src = (int64_t)b * R + e;
+            for (int w = 0; w < W; ++w) keys[(o + e) * W + w] = st.keys[src * W + w];
+            vals[o + e] = (double)st.vals[src];
+        }
+    }
+}
+
+// Matrix elements for parity checks: out[i] = <D_j|H|D_i>.
+__global__ void k_hij(SysView sys, const uint64_t* __restrict__ di, const uint64_t* __restrict__ dj,
+                      long long n, double* __restrict__ out) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const uint64_t a1 = di[2 * i], b1 = di[2 * i + 1], a2 = dj[2 * i], b2 = dj[2 * i + 1];
+        if (a1 == a2 && b1 == b2) out[i] = h_diag(sys, a1, b1);
+        else out[i] = h_offdiag(sys, a1, b1, a2, b2);
+    }
+}
+
+// J/K/U tables copied out of the packed integrals.
+__global__ void k_build_jk(SysView sys, double* J, double* K, double* U) {
+    const int N = sys.N;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N * N; i += gridDim.x * blockDim.x) {
+        const int p = i / N, q = i % N;
+        J[i] = eri(sys, p, p, q, q);
+        K[i] = eri(sys, p, q, q, p);
+        if (p == q) U[p] = eri(sys, p, p, p, p);
+    }
+}
+
+// PCHB weights and alias tables, one thread per row (rows: opposite-spin
+// (I,J) first, then same-spin I<J).  Weights per Eq. (hbs) over spatial
+// orbitals; alias tables by Vose's construction with LIFO work lists filled
+// in ascending column order.
+__global__ void k_pchb_build(SysView sys, double* w_opp, double* p_opp, int* a_opp, double* s_opp,
+                             double* w_same, double* p_same, int* a_same, double* s_same,
+                             double* scaled_ws, int* small_ws, int* large_ws) {
+    const int N = sys.N;
+    const int NN = N * N, np = N * (N - 1) / 2;
+    const int rows = NN + np;
+    for (int row = blockIdx.x * blockDim.x + threadIdx.x; row < rows; row += gridDim.x * blockDim.x) {
+        const bool opp = row < NN;
+        const int K = opp ? NN : np;
+        double* w;
+        double* prob;
+        int* alias;
+        double sum = 0.0;
+        if (opp) {
+            const int I = row / N, J = row % N;
+            w = w_opp + (size_t)row * NN; prob = p_opp + (size_t)row * NN; alias = a_opp + (size_t)row * NN;
+            for (int A = 0; A < N; ++A)
+                for (int B = 0; B < N; ++B) {
+                    double x = fabs(eri(sys, A, I, B, J));
+                    if (A == I || B == J) x = 0.0;
+                    w[A * N + B] = x;
+                    sum = sum + x;
+                }
+            s_opp[row] = sum;
+        } else {
+            const int ij = row - NN;
+            int I = 0, J = 0;
+            pair_decode((uint64_t)ij, N, I, J);
+            w = w_same + (size_t)ij * np; prob = p_same + (size_t)ij * np; alias = a_same + (size_t)ij * np;
+            int ab = 0;
+            for (int A = 0; A < N; ++A)
+                for (int B = A + 1; B < N; ++B, ++ab) {
+                    const double d = eri(sys, A, I, B, J);
+                    const double e = eri(sys, A, J, B, I);
+                    const double v = d - e;
+                    double x = fabs(v);
+                    if (A == I || A == J || B == I || B == J) x = 0.0;
+                    w[ab] = x;
+                    sum = sum + x;
+                }
+            s_same[ij] = sum;
+        }
+        // private work lists: opposite-spin rows first, same-spin rows after them
+        const size_t wb = opp ? (size_t)row * NN : (size_t)NN * NN + (size_t)(row - NN) * np;
+        double* scaled = scaled_ws + wb;
+        int* small = small_ws + wb;
+        int* large = large_ws + wb;
+        if (sum == 0.0) {
+            for (int c = 0; c < K; ++c) { prob[c] = 0.0; alias[c] = c; }
+            continue;
+        }
+        int ns = 0, nl = 0;
+        for (int c = 0; c < K; ++c) {
+            const double x = w[c] * (double)K;
+            scaled[c] = x / sum;
+            alias[c] = c;
+            if (scaled[c] < 1.0) small[ns++] = c; else large[nl++] = c;
+        }
+        while (ns > 0 && nl > 0) {
+            const int s_ = small[--ns];
+            const int l = large[--nl];
+            prob[s_] = scaled[s_];
+            alias[s_] = l;
+            const double t = scaled[l] + scaled[s_];
+            scaled[l] = t - 1.0;
+            if (scaled[l] < 1.0) small[ns++] = l; else large[nl++] = l;
+        }
+        while (nl > 0) { const int l = large[--nl]; prob[l] = 1.0; alias[l] = l; }
+        while (ns > 0) { const int s_ = small[--ns]; prob[s_] = 1.0; alias[s_] = s_; }
+    }
+}
+
+}  // namespace fq

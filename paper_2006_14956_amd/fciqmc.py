@@ -1,0 +1,264 @@
+"""Thin ctypes binding of libfciqmc.so with the C entry points' names.
+
+Argument marshalling only: every step of the FCIQMC path runs in the HIP
+library.  Importing this module does not load the library; the first call
+does, and it raises if the library has not been built -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libfciqmc.so")
+
+OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
+MODE_INTEGER, MODE_REAL = 0, 1
+GEN_UNIFORM, GEN_LATTICE, GEN_PCHB = 0, 1, 2
+
+
+class FciqmcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fciqmc error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("tau", C.c_double), ("walker_target", C.c_double), ("n_initial", C.c_double),
+                ("initiator_na", C.c_double), ("mode", C.c_int), ("c_min", C.c_double),
+                ("excitgen", C.c_int), ("p_single", C.c_double), ("p_opp", C.c_double),
+                ("seed", C.c_uint64), ("replica_id", C.c_uint64), ("shift_damping", C.c_double),
+                ("shift_restore", C.c_double),
+                ("shift_interval", C.c_int), ("ref_alpha", C.c_uint64), ("ref_beta", C.c_uint64),
+                ("max_dets", C.c_int64), ("max_spawns", C.c_int64),
+                ("hbm_budget_bytes", C.c_int64), ("buckets_log2", C.c_int), ("det_words", C.c_int),
+                ("conv_tol", C.c_double), ("equil_steps", C.c_int)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("iter", C.c_int64), ("nw", C.c_double), ("nref", C.c_double),
+                ("enum_", C.c_double), ("shift", C.c_double), ("e_proj", C.c_double),
+                ("ndets", C.c_int64), ("attempts", C.c_int64), ("spawns", C.c_int64),
+                ("vary_shift", C.c_int), ("retries", C.c_int)]
+
+
+class EnergyReport(C.Structure):
+    _fields_ = [("e_proj", C.c_double), ("e_proj_err", C.c_double), ("shift", C.c_double),
+                ("shift_err", C.c_double), ("e_ref", C.c_double), ("n_samples", C.c_int64),
+                ("first_step", C.c_int64), ("steps_done", C.c_int64), ("converged", C.c_int)]
+
+
+class Checkpoint(C.Structure):
+    _fields_ = [("iter", C.c_int64), ("shift", C.c_double), ("vary_shift", C.c_int),
+                ("last_update_iter", C.c_int64), ("last_update_nw", C.c_double)]
+
+
+EXPORTS = ["fciqmc_params_default", "fciqmc_load_integrals", "fciqmc_init", "fciqmc_step",
+           "fciqmc_energy", "fciqmc_get_walkers", "fciqmc_set_walkers", "fciqmc_get_checkpoint",
+           "fciqmc_set_checkpoint", "fciqmc_matrix_elements", "fciqmc_run_device_bytes",
+           "fciqmc_profile",
+           "fciqmc_free_run", "fciqmc_free_system", "fciqmc_last_error"]
+
+_lib = None
+
+
+def lib():
+    """Load libfciqmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FciqmcError(ESTATE, f"{LIB_PATH} is missing: build it with "
+                                      "`python paper_2006_14956_amd/build.py`")
+        # torch ships its own HIP runtime under the same soname as ROCm's; load
+        # it first so the process holds one runtime and torch streams are valid
+        # handles inside the library
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        vp, i64, u64, dbl = C.c_void_p, C.c_int64, C.c_uint64, C.c_double
+        pu64, pdbl = C.POINTER(u64), C.POINTER(dbl)
+        L.fciqmc_params_default.argtypes = [C.POINTER(Params)]
+        L.fciqmc_params_default.restype = None
+        L.fciqmc_load_integrals.argtypes = [C.c_int, C.c_int, C.c_int, dbl, pdbl, pdbl, i64,
+                                            C.POINTER(vp)]
+        L.fciqmc_init.argtypes = [vp, C.POINTER(Params), vp, C.POINTER(vp)]
+        L.fciqmc_step.argtypes = [vp, C.c_int, C.POINTER(StepStats)]
+        L.fciqmc_energy.argtypes = [vp, C.POINTER(EnergyReport)]
+        L.fciqmc_get_walkers.argtypes = [vp, pu64, pdbl, i64, C.POINTER(i64)]
+        L.fciqmc_set_walkers.argtypes = [vp, pu64, pdbl, i64]
+        L.fciqmc_get_checkpoint.argtypes = [vp, C.POINTER(Checkpoint)]
+        L.fciqmc_set_checkpoint.argtypes = [vp, C.POINTER(Checkpoint)]
+        L.fciqmc_matrix_elements.argtypes = [vp, pu64, pu64, i64, pdbl]
+        L.fciqmc_run_device_bytes.argtypes = [vp]
+        L.fciqmc_run_device_bytes.restype = i64
+        L.fciqmc_profile.argtypes = [vp, C.c_int, pdbl, C.POINTER(i64), C.POINTER(i64)]
+        L.fciqmc_free_run.argtypes = [vp]
+        L.fciqmc_free_run.restype = None
+        L.fciqmc_free_system.argtypes = [vp]
+        L.fciqmc_free_system.restype = None
+        L.fciqmc_last_error.argtypes = []
+        L.fciqmc_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def fciqmc_last_error() -> str:
+    return lib().fciqmc_last_error().decode()
+
+
+def _check(rc):
+    if rc != 0:
+        raise FciqmcError(rc, fciqmc_last_error())
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def fciqmc_params_default(**overrides) -> Params:
+    p = Params()
+    lib().fciqmc_params_default(C.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+class System:
+    def __init__(self, handle):
+        self.handle = handle
+
+    def free(self):
+        if self.handle:
+            lib().fciqmc_free_system(self.handle)
+            self.handle = None
+
+
+class Run:
+    def __init__(self, handle, system):
+        self.handle = handle
+        self.system = system  # keep the system alive
+
+    def free(self):
+        if self.handle:
+            lib().fciqmc_free_run(self.handle)
+            self.handle = None
+
+
+def fciqmc_load_integrals(n_orb, n_alpha, n_beta, e_core, h1, eri) -> System:
+    h = np.ascontiguousarray(h1, dtype=np.float64)
+    e = np.ascontiguousarray(eri, dtype=np.float64)
+    out = C.c_void_p()
+    _check(lib().fciqmc_load_integrals(int(n_orb), int(n_alpha), int(n_beta), float(e_core),
+                                       _p(h, C.c_double), _p(e, C.c_double), len(e),
+                                       C.byref(out)))
+    return System(out.value)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def fciqmc_init(system: System, params: Params, stream=None) -> Run:
+    out = C.c_void_p()
+    _check(lib().fciqmc_init(system.handle, C.byref(params), _stream_ptr(stream), C.byref(out)))
+    return Run(out.value, system)
+
+
+STATS_DTYPE = np.dtype([(n, np.int64 if t in (C.c_int64,) else (np.int32 if t is C.c_int else np.float64))
+                        for n, t in StepStats._fields_])
+
+
+def fciqmc_step(run: Run, n_steps: int = 1):
+    """Advance n_steps; returns a list of per-step stats dicts."""
+    arr = (StepStats * max(1, n_steps))()
+    _check(lib().fciqmc_step(run.handle, int(n_steps), arr))
+    return [{k: getattr(arr[i], k) for k, _ in StepStats._fields_} for i in range(n_steps)]
+
+
+def fciqmc_energy(run: Run) -> dict:
+    r = EnergyReport()
+    _check(lib().fciqmc_energy(run.handle, C.byref(r)))
+    return {k: getattr(r, k) for k, _ in EnergyReport._fields_}
+
+
+def fciqmc_get_walkers(run: Run):
+    """Returns (alpha_masks, beta_masks, values) as numpy arrays."""
+    n = C.c_int64()
+    rc = lib().fciqmc_get_walkers(run.handle, None, None, 0, C.byref(n))
+    if rc not in (0, EOVERFLOW):
+        _check(rc)
+    cap = max(1, n.value)
+    dets = np.zeros(2 * cap, dtype=np.uint64)
+    vals = np.zeros(cap, dtype=np.float64)
+    _check(lib().fciqmc_get_walkers(run.handle, _p(dets, C.c_uint64), _p(vals, C.c_double), cap,
+                                    C.byref(n)))
+    m = n.value
+    return dets[0:2 * m:2].copy(), dets[1:2 * m:2].copy(), vals[:m].copy()
+
+
+def fciqmc_set_walkers(run: Run, alpha, beta, vals):
+    a = np.asarray(alpha, dtype=np.uint64)
+    b = np.asarray(beta, dtype=np.uint64)
+    d = np.ascontiguousarray(np.stack([a, b], axis=1).reshape(-1))
+    v = np.ascontiguousarray(vals, dtype=np.float64)
+    _check(lib().fciqmc_set_walkers(run.handle, _p(d, C.c_uint64), _p(v, C.c_double), len(v)))
+
+
+def fciqmc_get_checkpoint(run: Run) -> dict:
+    c = Checkpoint()
+    _check(lib().fciqmc_get_checkpoint(run.handle, C.byref(c)))
+    return {k: getattr(c, k) for k, _ in Checkpoint._fields_}
+
+
+def fciqmc_set_checkpoint(run: Run, iter, shift, vary_shift, last_update_iter, last_update_nw):
+    c = Checkpoint(int(iter), float(shift), int(vary_shift), int(last_update_iter),
+                   float(last_update_nw))
+    _check(lib().fciqmc_set_checkpoint(run.handle, C.byref(c)))
+
+
+def fciqmc_matrix_elements(system: System, dets_i, dets_j) -> np.ndarray:
+    """dets_i, dets_j: (n, 2) uint64 arrays of (alpha, beta) masks."""
+    di = np.ascontiguousarray(dets_i, dtype=np.uint64).reshape(-1)
+    dj = np.ascontiguousarray(dets_j, dtype=np.uint64).reshape(-1)
+    n = len(di) // 2
+    out = np.zeros(max(n, 1))
+    _check(lib().fciqmc_matrix_elements(system.handle, _p(di, C.c_uint64), _p(dj, C.c_uint64), n,
+                                        _p(out, C.c_double)))
+    return out[:n]
+
+
+def fciqmc_run_device_bytes(run: Run) -> int:
+    return int(lib().fciqmc_run_device_bytes(run.handle))
+
+
+KERNELS = ("spawn", "record_scan", "scatter", "annihilate", "post")
+
+
+def fciqmc_profile(run: Run, enable: bool = True):
+    """Enable per-kernel event timing; returns (ms per kernel dict, steps, layout)."""
+    ms = np.zeros(5)
+    steps = C.c_int64()
+    layout = np.zeros(2, dtype=np.int64)
+    _check(lib().fciqmc_profile(run.handle, int(enable), _p(ms, C.c_double), C.byref(steps),
+                                _p(layout, C.c_int64)))
+    return dict(zip(KERNELS, ms.tolist())), steps.value, {"buckets": int(layout[0]),
+                                                           "spawn_capacity": int(layout[1])}
+
+
+def fciqmc_free_run(run: Run):
+    run.free()
+
+
+def fciqmc_free_system(system: System):
+    system.free()

@@ -1,0 +1,80 @@
+"""Shared helpers of the GPU parity tests: run the HIP library and the oracle
+side by side on the same seeded inputs and compare."""
+import numpy as np
+
+import oracle
+from paper_2006_14956_amd import fciqmc as F
+
+GEN = {"uniform": (F.GEN_UNIFORM, oracle.GEN_UNIFORM),
+       "lattice": (F.GEN_LATTICE, oracle.GEN_LATTICE),
+       "pchb": (F.GEN_PCHB, oracle.GEN_PCHB)}
+
+
+def ref_of(s):
+    if s.ref_alpha or s.ref_beta:
+        return int(s.ref_alpha), int(s.ref_beta)
+    return (1 << s.n_alpha) - 1, (1 << s.n_beta) - 1
+
+
+def make_pair(s, tau, target, gen="uniform", n_a=-1.0, mode="integer", seed=1, zeta=0.05,
+              interval=10, c_min=1.0, det_words=0, n_initial=10.0, p_single=-1.0, p_opp=-1.0,
+              buckets_log2=0, max_spawns=0, stream=None, replica=0):
+    """(gpu_run, oracle_run) started from n_initial walkers on the reference."""
+    g, o = GEN[gen]
+    m = F.MODE_INTEGER if mode == "integer" else F.MODE_REAL
+    sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
+    ra, rb = ref_of(s)
+    p = F.fciqmc_params_default(tau=tau, walker_target=target, initiator_na=n_a, mode=m,
+                                excitgen=g, seed=seed, shift_damping=zeta, shift_interval=interval,
+                                c_min=c_min, det_words=det_words, n_initial=n_initial,
+                                ref_alpha=ra, ref_beta=rb, p_single=p_single, p_opp=p_opp,
+                                buckets_log2=buckets_log2, max_spawns=max_spawns,
+                                replica_id=replica)
+    run = F.fciqmc_init(sysd, p, stream=stream)
+    words = det_words if det_words else (1 if s.n_orb <= 32 else 2)
+    osys = oracle.System.from_inputs(s, words=words)
+    orun = oracle.Run(osys, ref=(ra, rb), tau=tau, target=target, n_a=n_a, c_min=c_min,
+                      zeta=zeta, p_single=p_single, p_opp=p_opp, interval=interval,
+                      mode=oracle.MODE_INTEGER if mode == "integer" else oracle.MODE_REAL,
+                      gen=o, seed=seed, replica=replica)
+    orun.set_walkers([ra], [rb], [n_initial])
+    return sysd, run, orun
+
+
+def sorted_walkers(a, b, v):
+    i = np.lexsort((b, a))
+    return a[i], b[i], v[i]
+
+
+def gpu_walkers(run):
+    return sorted_walkers(*F.fciqmc_get_walkers(run))
+
+
+def oracle_walkers(orun):
+    a, b, v, _ = orun.get_walkers()
+    return sorted_walkers(a, b, v)
+
+
+def assert_same_walkers(run, orun, exact=True, rtol=0.0):
+    ga, gb, gv = gpu_walkers(run)
+    oa, ob, ov = oracle_walkers(orun)
+    assert len(ga) == len(oa), (len(ga), len(oa))
+    assert np.array_equal(ga, oa) and np.array_equal(gb, ob)
+    if exact:
+        assert np.array_equal(gv, ov), np.max(np.abs(gv - ov))
+    else:
+        assert np.allclose(gv, ov, rtol=rtol, atol=0.0), np.max(np.abs(gv - ov) / np.abs(ov))
+
+
+def enum_tol(x):
+    # estimator sums run in different orders; see the design doc (tolerances)
+    return 1e-10 * max(1.0, abs(x))
+
+
+def assert_same_stats(g, o, exact_shift=True):
+    for k in ("nw", "nref", "ndets", "attempts", "spawns"):
+        assert g[k] == o[k], (k, g[k], o[k], g, o)
+    assert g["vary_shift"] == o["vary"]
+    if exact_shift:
+        assert g["shift"] == o["shift"], (g["shift"], o["shift"])
+    assert abs(g["enum_"] - o["enum_"]) <= enum_tol(o["enum_"]), (g["enum_"], o["enum_"])

@@ -1,0 +1,218 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded inputs.
+
+Integer-walker mode must agree bit for bit (determinant lists, populations,
+N_w, shift, attempt and spawn counts); estimator sums agree to the rounding
+bound of a reordered sum; matrix elements agree bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_14956_amd import fciqmc as F
+from paper_2006_14956_amd import inputs
+from tests import brute
+from tests.gpu_helpers import (assert_same_stats, assert_same_walkers, make_pair, ref_of,
+                               gpu_walkers, oracle_walkers)
+
+pytestmark = pytest.mark.gpu
+
+
+def _random_pairs(s, n, rng, max_level=3):
+    """Random determinant pairs at excitation levels 0..max_level."""
+    N = s.n_orb
+    out_i, out_j = [], []
+    while len(out_i) < n:
+        a = rng.choice(N, size=s.n_alpha, replace=False)
+        b = rng.choice(N, size=s.n_beta, replace=False)
+        am = int(sum(1 << int(x) for x in a))
+        bm = int(sum(1 << int(x) for x in b))
+        lvl = int(rng.integers(0, max_level + 1))
+        a2, b2 = am, bm
+        for _ in range(lvl):
+            if rng.random() < 0.5 and 0 < s.n_alpha < N:
+                occ = [p for p in range(N) if (a2 >> p) & 1]
+                emp = [p for p in range(N) if not (a2 >> p) & 1]
+                a2 = (a2 & ~(1 << int(rng.choice(occ)))) | (1 << int(rng.choice(emp)))
+            elif 0 < s.n_beta < N:
+                occ = [p for p in range(N) if (b2 >> p) & 1]
+                emp = [p for p in range(N) if not (b2 >> p) & 1]
+                b2 = (b2 & ~(1 << int(rng.choice(occ)))) | (1 << int(rng.choice(emp)))
+        out_i.append((am, bm))
+        out_j.append((a2, b2))
+    return np.array(out_i, dtype=np.uint64), np.array(out_j, dtype=np.uint64)
+
+
+@pytest.mark.parametrize("case", ["mol8", "mol40", "hubbard", "mol24"])
+def test_matrix_elements_bitexact(case):
+    rng = np.random.default_rng(11)
+    if case == "mol8":
+        s = inputs.molecule_8o8e()
+    elif case == "mol40":
+        s = inputs.molecule_40o26e()
+    elif case == "mol24":
+        s = inputs.synthetic_molecule(24, 12, 12, seed=3)
+    else:
+        s = inputs.hubbard_4x4()
+    di, dj = _random_pairs(s, 3000, rng)
+    sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
+    got = F.fciqmc_matrix_elements(sysd, di, dj)
+    osys = oracle.System.from_inputs(s)
+    want = np.array([osys.hij(a1, b1, a2, b2) if (a1, b1) != (a2, b2) else osys.hdiag(a1, b1)
+                     for (a1, b1), (a2, b2) in zip(di.tolist(), dj.tolist())])
+    assert np.array_equal(got, want), np.max(np.abs(got - want))
+    F.fciqmc_free_system(sysd)
+
+
+def test_c0_trajectory_bitexact():
+    """8 electrons in 8 orbitals, integer walkers, target 1e4, dtau 0.01,
+    uniform generator, 1000 steps: every step identical."""
+    s = inputs.molecule_8o8e()
+    sysd, run, orun = make_pair(s, tau=0.01, target=1e4, seed=1)
+    for block in range(10):
+        g = F.fciqmc_step(run, 100)
+        o = orun.step(100)
+        for gg, oo in zip(g, o):
+            assert_same_stats(gg, oo)
+        assert_same_walkers(run, orun)
+    assert g[-1]["vary_shift"] == 1
+    F.fciqmc_free_run(run)
+    F.fciqmc_free_system(sysd)
+
+
+def test_hubbard_small_target_trajectory_bitexact():
+    """4x4 Hubbard, U=4, initiator n_a=3, lattice generator, Neel reference,
+    walker target 2e4 (reduced so the oracle keeps up), 300 steps."""
+    s = inputs.hubbard_4x4()
+    sysd, run, orun = make_pair(s, tau=0.005, target=2e4, gen="lattice", n_a=3.0, zeta=0.3)
+    for block in range(6):
+        g = F.fciqmc_step(run, 50)
+        o = orun.step(50)
+        for gg, oo in zip(g, o):
+            assert_same_stats(gg, oo)
+        assert_same_walkers(run, orun)
+    F.fciqmc_free_run(run)
+    F.fciqmc_free_system(sysd)
+
+
+@pytest.mark.parametrize("words,gen", [(1, "uniform"), (2, "uniform"), (2, "pchb"), (1, "pchb")])
+def test_one_step_from_random_state(words, gen):
+    """A random sparse population on a 10-orbital molecule: one step, then
+    twenty more, identical on both sides (two-word layout forced for words=2)."""
+    s = inputs.synthetic_molecule(10, 4, 3, seed=7)
+    sysd, run, orun = make_pair(s, tau=0.02, target=1e9, gen=gen, det_words=words, seed=9,
+                                n_a=2.0)
+    ra, rb = ref_of(s)
+    a, b, v = inputs.random_walker_state(10, 4, 3, 300, seed=3, max_pop=30, include=(ra, rb))
+    F.fciqmc_set_walkers(run, a, b, v)
+    orun.set_walkers(a, b, v)
+    assert_same_walkers(run, orun)
+    g = F.fciqmc_step(run, 1)
+    o = orun.step(1)
+    assert_same_stats(g[0], o[0])
+    assert_same_walkers(run, orun)
+    g = F.fciqmc_step(run, 20)
+    o = orun.step(20)
+    for gg, oo in zip(g, o):
+        assert_same_stats(gg, oo)
+    assert_same_walkers(run, orun)
+    F.fciqmc_free_run(run)
+    F.fciqmc_free_system(sysd)
+
+
+def test_real_mode_one_step():
+    """Real coefficients with C_min = 1: the spawned amplitudes are summed in a
+    different order on the GPU, so values agree to rounding; the sets of
+    surviving determinants agree unless a rounding decision sits within an
+    ulp of its threshold (not the case for this seed)."""
+    s = inputs.synthetic_molecule(10, 4, 4, seed=2)
+    sysd, run, orun = make_pair(s, tau=0.02, target=1e9, mode="real", seed=4)
+    ra, rb = ref_of(s)
+    a, b, v = inputs.random_walker_state(10, 4, 4, 400, seed=5, max_pop=10, integer=False,
+                                         include=(ra, rb))
+    F.fciqmc_set_walkers(run, a, b, v)
+    orun.set_walkers(a, b, v)
+    g = F.fciqmc_step(run, 1)
+    o = orun.step(1)
+    assert g[0]["ndets"] == o[0]["ndets"] and g[0]["spawns"] == o[0]["spawns"]
+    assert abs(g[0]["nw"] - o[0]["nw"]) <= 1e-12 * o[0]["nw"]
+    assert_same_walkers(run, orun, exact=False, rtol=1e-12)
+    F.fciqmc_free_run(run)
+    F.fciqmc_free_system(sysd)
+
+
+def test_capacity_growth_keeps_trajectory():
+    """Two buckets and a 100-record spawn buffer force repeated growth of the
+    walker store and of the spawn buffer; the trajectory is unchanged."""
+    s = inputs.molecule_8o8e()
+    sysd, run, orun = make_pair(s, tau=0.01, target=1e4, seed=3, buckets_log2=1, max_spawns=100)
+    g = F.fciqmc_step(run, 200)
+    o = orun.step(200)
+    for gg, oo in zip(g, o):
+        assert_same_stats(gg, oo)
+    assert sum(x["retries"] for x in g) > 0
+    assert_same_walkers(run, orun)
+    F.fciqmc_free_run(run)
+    F.fciqmc_free_system(sysd)
+
+
+def test_set_walkers_validation():
+    s = inputs.molecule_8o8e()
+    sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
+    run = F.fciqmc_init(sysd, F.fciqmc_params_default())
+    with pytest.raises(F.FciqmcError) as e:
+        F.fciqmc_set_walkers(run, [0b111], [0b1111], [1.0])      # wrong electron count
+    assert e.value.code == F.EINVAL
+    with pytest.raises(F.FciqmcError):
+        F.fciqmc_set_walkers(run, [0b1111, 0b1111], [0b1111, 0b1111], [1.0, 2.0])  # duplicate
+    with pytest.raises(F.FciqmcError):
+        F.fciqmc_set_walkers(run, [0b1111], [0b1111], [0.5])     # non-integer in integer mode
+    # an empty population is legal and stays empty
+    F.fciqmc_set_walkers(run, [], [], [])
+    st = F.fciqmc_step(run, 2)
+    assert st[-1]["nw"] == 0 and st[-1]["ndets"] == 0
+    F.fciqmc_free_run(run)
+    F.fciqmc_free_system(sysd)
+
+
+def test_load_integrals_validation():
+    s = inputs.molecule_8o8e()
+    h = s.h1.copy()
+    h[0, 1] += 1e-3
+    with pytest.raises(F.FciqmcError) as e:
+        F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, h, s.eri)
+    assert e.value.code == F.EINVAL
+    with pytest.raises(F.FciqmcError):
+        F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri[:-1])
+    with pytest.raises(F.FciqmcError):
+        F.fciqmc_load_integrals(8, 9, 4, 0.0, s.h1, s.eri)
+    sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
+    with pytest.raises(F.FciqmcError):   # lattice generator needs on-site-only integrals
+        F.fciqmc_init(sysd, F.fciqmc_params_default(excitgen=F.GEN_LATTICE))
+    F.fciqmc_free_system(sysd)
+
+
+def test_hubbard_full_size_one_step():
+    """4x4 Hubbard at the full 1e6-walker target, in the benchmark's launch
+    configuration: grow on the GPU until the shift varies, then one step from
+    that state on both sides must agree bit for bit."""
+    import torch
+    s = inputs.hubbard_4x4()
+    stream = torch.cuda.current_stream()
+    sysd, run, orun = make_pair(s, tau=0.005, target=1e6, gen="lattice", n_a=3.0, stream=stream)
+    for _ in range(300):
+        st = F.fciqmc_step(run, 10)
+        if st[-1]["vary_shift"]:
+            break
+    st = F.fciqmc_step(run, 20)
+    assert st[-1]["nw"] > 3e5
+    a, b, v = F.fciqmc_get_walkers(run)
+    ck = F.fciqmc_get_checkpoint(run)
+    orun.set_walkers(a, b, v)
+    orun.set_state(ck["iter"], ck["shift"], ck["vary_shift"], ck["last_update_iter"],
+                   ck["last_update_nw"])
+    g = F.fciqmc_step(run, 1)
+    o = orun.step(1)
+    assert_same_stats(g[0], o[0])
+    assert_same_walkers(run, orun)
+    F.fciqmc_free_run(run)
+    F.fciqmc_free_system(sysd)
