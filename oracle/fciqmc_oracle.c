@@ -562,8 +562,12 @@ orc_run *orc_run_create(const orc_sys *s, const orc_params *p, uint64_t ref_a, u
     orc_run *r = (orc_run *)calloc(1, sizeof(orc_run));
     r->s = s;
     r->p = *p;
+    if (r->p.xi < 0.0) {
+        double z2 = r->p.zeta * r->p.zeta;
+        r->p.xi = z2 / 4.0;
+    }
     if (r->p.p_single < 0.0) {
-        /* Appendix, "Preparing for excitation generation": p_sing ~ nN/(nN + n^2 N^2) */
+        /* Appendix A.2, "Preparing for excitation generation": p_sing ~ nN/(nN + n^2 N^2) */
         double n = (double)(s->na + s->nb), N = (double)s->N;
         double nN = n * N;
         double n2N2 = nN * nN;

@@ -407,3 +407,37 @@ def test_blocking_on_ar1():
     tau_int = (1 + phi) / (1 - phi)
     exact = math.sqrt(var * tau_int / n)
     assert 0.7 * exact < err < 1.3 * exact
+
+
+def test_long_run_matches_exact_diagonalisation(oracle_mod):
+    """Without initiators FCIQMC is exact in the long-time limit (Sec. I): the
+    blocked averages of the shift and of the projected energy equal the exact
+    ground-state energy within their error bars."""
+    s = inputs.synthetic_molecule(6, 3, 3, seed=14)
+    osys = oracle_mod.System.from_inputs(s)
+    dets = brute.basis(6, 3, 3)
+    e0 = np.linalg.eigvalsh(brute.oracle_dense_h(osys, dets))[0]
+    run = oracle_mod.Run(osys, tau=0.01, target=3000.0, seed=2, zeta=0.1)
+    run.set_walkers([0b111], [0b111], [10.0])
+    st = []
+    for _ in range(12):
+        st += run.step(1000)
+        # population control must hold the walker number near the target
+        assert st[-1]["nw"] < 50 * 3000, "population control failed"
+    h00 = run.h00
+    t_vary = next(i for i, x in enumerate(st) if x["vary"])
+    keep = st[t_vary + 2000:]
+    S = np.array([x["shift"] for x in keep])
+    En = np.array([x["enum_"] for x in keep])
+    Nr = np.array([x["nref"] for x in keep])
+    ms, es = brute.blocked_error(S)
+    assert abs(h00 + ms - e0) < 4 * es + 1e-3, (h00 + ms, e0, es)
+    # projected energy as a ratio of means, error from the blocked ratio series
+    ratio = En.mean() / Nr.mean()
+    blk = len(En) // 32
+    rs = [En[i * blk:(i + 1) * blk].mean() / Nr[i * blk:(i + 1) * blk].mean() for i in range(32)]
+    er = np.std(rs, ddof=1) / np.sqrt(32)
+    assert abs(h00 + ratio - e0) < 4 * er + 1e-3, (h00 + ratio, e0, er)
+    # the population is held at the target
+    nw = np.array([x["nw"] for x in keep])
+    assert 0.5 * 3000 < nw.mean() < 2.0 * 3000
