@@ -59,8 +59,6 @@ def algorithmic_bytes(kernel, d_in, d_out, recs, words, vbytes):
         return d_in * (key + vbytes + 4) + recs * rec
     if kernel == "annihilate":   # entries in (key, value, diagonal), records in, entries out
         return d_in * (key + vbytes + 8) + recs * rec + d_out * (key + vbytes + 8 + 4)
-    if kernel == "scatter":
-        return 2 * recs * rec
     return 0
 
 
@@ -125,7 +123,7 @@ def main():
     d_in = float(np.mean([st[0]["ndets"]] + dets[:-1]))
     d_out = float(np.mean(dets))
     recs = spawns / len(st)
-    dom = max(("spawn", "annihilate", "scatter"), key=lambda k: ms[k])
+    dom = max(("spawn", "annihilate"), key=lambda k: ms[k])
     per_launch_ms = ms[dom] / nsteps
     ab = algorithmic_bytes(dom, d_in, d_out, recs, words, vbytes)
     achieved = ab / (per_launch_ms * 1e-3) / 1e9

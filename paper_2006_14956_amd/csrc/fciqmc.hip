@@ -181,9 +181,8 @@ struct EngineBase {
     virtual int64_t spawn_capacity() const = 0;
 };
 
-// kernels of one step, in launch order: spawn, record scan, scatter,
-// annihilation, post
-constexpr int kKernels = 5;
+// kernels of one step, in launch order: spawn, annihilation, post
+constexpr int kKernels = 3;
 
 struct RunScalars {
     double tau, p_single, p_double, p_opp, n_a, c_min, h00;
@@ -199,16 +198,19 @@ template <int W, class V> struct Engine : EngineBase {
     int B = 1, R = 1024;
     Store<V> st[2]{};
     int cur = 0;
-    Rec<W, V>* rec = nullptr;
-    Rec<W, V>* rec2 = nullptr;
+    Rec<W, V>* rec = nullptr;   // staging of imported populations
+    long long cap_stage = 0;
+    Rec<W, V>* rec2 = nullptr;  // per-bucket record slabs
     long long cap = 0;
-    int32_t *scount = nullptr, *scur = nullptr;
-    int64_t* soff = nullptr;
+    long long rec_need = 0;     // slab capacity the next step reserves
+    int32_t* scount = nullptr;  // records per bucket (zero between steps)
+    int64_t* soff = nullptr;    // slab offsets, B+1
     double *nw_b = nullptr, *en_b = nullptr;
     Ctl* ctl = nullptr;
     Ctl* hctl = nullptr;  // pinned
     int64_t att_next = 0;
     int64_t max_b = 1 << 22;
+    bool dirty = false;  // a step stopped on a flag; counters need rebuilding
     // optional per-kernel timing (HIP events around each launch of a step)
     bool profile = false;
     hipEvent_t ev[kKernels + 1]{};
@@ -223,7 +225,7 @@ template <int W, class V> struct Engine : EngineBase {
         if (profile)
             for (auto& e : ev) (void)hipEventDestroy(e);
     }
-    int enable_profile() {
+    int enable_profile() override {
         if (profile) return 0;
         for (auto& e : ev) HIP_OK(hipEventCreate(&e));
         profile = true;
@@ -275,8 +277,9 @@ template <int W, class V> struct Engine : EngineBase {
         CHECK(alloc_store(st[0]));
         CHECK(alloc_store(st[1]));
         CHECK(dalloc(arena, &scount, (size_t)B));
-        CHECK(dalloc(arena, &scur, (size_t)B));
         CHECK(dalloc(arena, &soff, (size_t)B + 1));
+        HIP_OK(hipMemsetAsync(scount, 0, sizeof(int32_t) * B, stream));
+        HIP_OK(hipMemsetAsync(soff, 0, sizeof(int64_t) * (B + 1), stream));
         CHECK(dalloc(arena, &nw_b, (size_t)B));
         CHECK(dalloc(arena, &en_b, (size_t)B));
         return 0;
@@ -284,17 +287,25 @@ template <int W, class V> struct Engine : EngineBase {
     void free_buckets() {
         free_store(st[0]);
         free_store(st[1]);
-        arena.release(scount); arena.release(scur); arena.release(soff);
+        arena.release(scount); arena.release(soff);
         arena.release(nw_b); arena.release(en_b);
-        scount = scur = nullptr; soff = nullptr; nw_b = en_b = nullptr;
+        scount = nullptr; soff = nullptr; nw_b = en_b = nullptr;
     }
-    int alloc_records(long long c) {
-        arena.release(rec);
+    // Grow the slab buffer to hold c records (contents are not kept).
+    int ensure_slabs(long long c) {
+        if (c <= cap) return 0;
         arena.release(rec2);
-        rec = rec2 = nullptr;
-        cap = c;
-        CHECK(dalloc(arena, &rec, (size_t)cap));
+        rec2 = nullptr;
+        cap = c + c / 4;
         CHECK(dalloc(arena, &rec2, (size_t)cap));
+        return 0;
+    }
+    int ensure_stage(long long c) {
+        if (c <= cap_stage) return 0;
+        arena.release(rec);
+        rec = nullptr;
+        cap_stage = c;
+        CHECK(dalloc(arena, &rec, (size_t)cap_stage));
         return 0;
     }
 
@@ -305,7 +316,7 @@ template <int W, class V> struct Engine : EngineBase {
         CHECK(dalloc(arena, &ctl, 1));
         HIP_OK(hipMemsetAsync(ctl, 0, sizeof(Ctl), stream));
         CHECK(alloc_buckets());
-        CHECK(alloc_records(spawn_cap));
+        CHECK(ensure_slabs(spawn_cap));
         return 0;
     }
 
@@ -319,34 +330,35 @@ template <int W, class V> struct Engine : EngineBase {
         return sc;
     }
 
-    // Group the records of the current step by bucket and run the per-bucket
-    // kernel from st[cur] into st[1-cur], then the global sums.
+    // Run the per-bucket kernel from st[cur] into st[1-cur] on the records in
+    // the slabs, then the global sums; read the step's scalars back.
     int merge_and_post(const StepScalars& sc) {
         const SysView v = sys->view();
         Store<V> in = st[cur], out = st[1 - cur];
-        hipLaunchKernelGGL(k_scan_count, dim3(1), dim3(1024), 0, stream, scount, B, soff, ctl);
-        mark(2);
-        hipLaunchKernelGGL((k_scatter<W, V>), dim3(1024), dim3(kThreads), 0, stream, rec, rec2, soff,
-                           scur, ctl, cap);
-        mark(3);
         const int gb = std::min(B, 32768);
         hipLaunchKernelGGL((k_annihilate<W, V>), dim3(gb), dim3(kThreads), 0, stream, v, in, out, sc,
-                           rec2, soff, nw_b, en_b, ctl);
-        mark(4);
+                           rec2, soff, scount, nw_b, en_b, ctl);
+        mark(2);
         hipLaunchKernelGGL(k_post, dim3(1), dim3(1024), 0, stream, out.batt, out.count, nw_b, en_b,
-                           B, out.aoff, ctl);
-        mark(5);
+                           B, out.aoff, scount, soff, ctl);
+        mark(3);
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
         HIP_OK(hipStreamSynchronize(stream));
         return 0;
     }
 
-    int reset_step_counters() {
+    // After a step that stopped on a flag: clear the per-step accumulators and
+    // rebuild the slabs from the counts the stopped step reached (the exact
+    // record numbers per bucket), which leaves scount zero again.
+    int recover() {
         HIP_OK(hipMemsetAsync(ctl, 0, offsetof(Ctl, nw), stream));
-        HIP_OK(hipMemsetAsync(scount, 0, sizeof(int32_t) * B, stream));
-        HIP_OK(hipMemsetAsync(scur, 0, sizeof(int32_t) * B, stream));
-        return 0;
+        hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, stream, scount, B, 1, soff, ctl);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipStreamSynchronize(stream));
+        rec_need = hctl->rec_need;
+        return ensure_slabs(rec_need);
     }
 
     int grow_buckets() {
@@ -364,7 +376,8 @@ template <int W, class V> struct Engine : EngineBase {
     // Load a population through the per-bucket merge with death and rounding off.
     int import(const uint64_t* ab, const double* vals, int64_t n) {
         for (int attempt = 0; attempt < 24; ++attempt) {
-            if (n > cap) CHECK(alloc_records((long long)std::max<int64_t>(n, cap)));
+            CHECK(ensure_stage(std::max<int64_t>(n, 1)));
+            CHECK(ensure_slabs(std::max<int64_t>(n, 1)));
             std::vector<Rec<W, V>> h((size_t)std::max<int64_t>(n, 1));
             for (int64_t i = 0; i < n; ++i) {
                 const uint64_t a = ab[2 * i], b = ab[2 * i + 1];
@@ -373,15 +386,20 @@ template <int W, class V> struct Engine : EngineBase {
                 h[i].v = (V)vals[i];
                 h[i].flag = 1u;
             }
-            CHECK(reset_step_counters());
             if (n > 0)
                 HIP_OK(hipMemcpyAsync(rec, h.data(), sizeof(Rec<W, V>) * n, hipMemcpyHostToDevice, stream));
             Ctl c{};
             c.nrec = (unsigned long long)n;
             HIP_OK(hipMemcpyAsync(ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, stream));
+            HIP_OK(hipMemsetAsync(scount, 0, sizeof(int32_t) * B, stream));
+            const unsigned gs = (unsigned)std::max<long long>(1, std::min<long long>(1024, (n + 255) / 256));
             if (n > 0)
-                hipLaunchKernelGGL((k_bucketize<W, V>), dim3(std::min<long long>(1024, (n + 255) / 256)),
-                                   dim3(kThreads), 0, stream, rec, (long long)n, B, scount);
+                hipLaunchKernelGGL((k_bucketize<W, V>), dim3(gs), dim3(kThreads), 0, stream, rec, (long long)n, B,
+                                   scount);
+            hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, stream, scount, B, 0, soff, ctl);
+            if (n > 0)
+                hipLaunchKernelGGL((k_scatter<W, V>), dim3(gs), dim3(kThreads), 0, stream, rec, (long long)n, rec2,
+                                   soff, scount);
             HIP_OK(hipGetLastError());
             StepScalars sc = scalars(0, 0.0, 1);
             CHECK(merge_and_post(sc));
@@ -389,7 +407,8 @@ template <int W, class V> struct Engine : EngineBase {
             if (flags == 0) {
                 cur = 1 - cur;
                 att_next = hctl->attempts;
-                return 0;
+                rec_need = hctl->rec_need;
+                return ensure_slabs(rec_need);
             }
             if (flags & (kFlagTable | kFlagStore)) {
                 if ((int64_t)B * 2 > max_b) return fail(FCIQMC_EOVERFLOW, "population does not fit the walker store");
@@ -406,6 +425,7 @@ template <int W, class V> struct Engine : EngineBase {
 
     int set_walkers(const uint64_t* ab, const double* vals, int64_t n) override {
         cur = 0;
+        dirty = false;
         return import(ab, vals, n);
     }
 
@@ -416,7 +436,7 @@ template <int W, class V> struct Engine : EngineBase {
         double* dv = nullptr;
         Arena tmp;
         CHECK(dalloc(tmp, &off, (size_t)B + 1));
-        hipLaunchKernelGGL(k_scan_count, dim3(1), dim3(1024), 0, stream, s.count, B, off, (Ctl*)nullptr);
+        hipLaunchKernelGGL(k_count_offsets, dim3(1), dim3(1024), 0, stream, s.count, B, off);
         int64_t n = 0;
         HIP_OK(hipMemcpyAsync(&n, off + B, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
         HIP_OK(hipStreamSynchronize(stream));
@@ -443,20 +463,20 @@ template <int W, class V> struct Engine : EngineBase {
 
     int launch_spawn(const StepScalars& sc) {
         const SysView v = sys->view();
-        const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((att_next + kThreads - 1) / kThreads, 8192));
+        const int64_t blocks = std::max<int64_t>(1, (att_next + kChunk - 1) / kChunk);
         const Store<V> in = st[cur];
         switch (rs.gen) {
             case FCIQMC_GEN_UNIFORM:
-                hipLaunchKernelGGL((k_spawn<W, V, 0>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec,
-                                   scount, ctl);
+                hipLaunchKernelGGL((k_spawn<W, V, 0>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
+                                   soff, scount, ctl);
                 break;
             case FCIQMC_GEN_LATTICE:
-                hipLaunchKernelGGL((k_spawn<W, V, 1>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec,
-                                   scount, ctl);
+                hipLaunchKernelGGL((k_spawn<W, V, 1>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
+                                   soff, scount, ctl);
                 break;
             default:
-                hipLaunchKernelGGL((k_spawn<W, V, 2>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec,
-                                   scount, ctl);
+                hipLaunchKernelGGL((k_spawn<W, V, 2>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
+                                   soff, scount, ctl);
                 break;
         }
         HIP_OK(hipGetLastError());
@@ -466,9 +486,12 @@ template <int W, class V> struct Engine : EngineBase {
     int step_once(int64_t t, double S, Ctl& out, int& retries, int64_t& attempts) override {
         retries = 0;
         attempts = att_next;
+        if (dirty) {
+            CHECK(recover());
+            dirty = false;
+        }
         for (;;) {
             const StepScalars sc = scalars(t, S, 0);
-            CHECK(reset_step_counters());
             mark(0);
             CHECK(launch_spawn(sc));
             mark(1);
@@ -478,6 +501,7 @@ template <int W, class V> struct Engine : EngineBase {
                 CHECK(collect());
                 break;
             }
+            dirty = true;
             if (flags & kFlagBloom)
                 return fail(FCIQMC_EOVERFLOW, "a spawn exceeded 2^30 walkers at step %lld (time step too large)",
                             (long long)t);
@@ -486,20 +510,24 @@ template <int W, class V> struct Engine : EngineBase {
             if (flags & kFlagSpin) return fail(FCIQMC_EDEVICE, "LDS hash claim did not complete");
             ++retries;
             if (retries > 24) return fail(FCIQMC_EOVERFLOW, "step %lld did not fit after 24 capacity growths", (long long)t);
-            if (flags & kFlagSpawnCap) {
-                const long long need = (long long)hctl->nrec;
-                CHECK(alloc_records(std::max<long long>(cap * 2, need + need / 4 + 1024)));
-                continue;
-            }
             if (flags & (kFlagTable | kFlagStore)) {
                 CHECK(grow_buckets());
+                dirty = false;
+                continue;
+            }
+            if (flags & kFlagSpawnCap) {
+                CHECK(recover());
+                dirty = false;
                 continue;
             }
             return fail(FCIQMC_EDEVICE, "device flags 0x%x", flags);
         }
         cur = 1 - cur;
         att_next = hctl->attempts;
+        rec_need = hctl->rec_need;
+        CHECK(ensure_slabs(rec_need));
         out = *hctl;
+        out.nref = hctl->nref_out;
         return 0;
     }
 };
@@ -703,9 +731,12 @@ int fciqmc_init(const fciqmc_system* csys, const fciqmc_params* p, void* stream,
     // capacities start from the hints (or the target) and grow on demand
     int64_t max_dets = p->max_dets > 0 ? p->max_dets : (int64_t)std::min(target, 16777216.0);
     max_dets = std::max<int64_t>(max_dets, 1024);
-    int B = p->buckets_log2 > 0 ? (1 << std::min(p->buckets_log2, 22)) : (int)next_pow2((uint64_t)((max_dets + 255) / 256));
+    // about 1024 determinants of the capacity hint per bucket (the store holds
+    // R = 1024 per bucket; buckets double when one overflows)
+    int B = p->buckets_log2 > 0 ? (1 << std::min(p->buckets_log2, 22))
+                                : (int)next_pow2((uint64_t)((max_dets + 1023) / 1024));
     long long spawn_cap = p->max_spawns > 0 ? p->max_spawns
-                                            : (long long)std::min(std::max(65536.0, 2.0 * target), 33554432.0);
+                                            : (long long)std::min(std::max(65536.0, 1.0 * target), 33554432.0);
     if (W == 1 && p->mode == FCIQMC_MODE_INTEGER) r->eng.reset(new Engine<1, int32_t>(sys, r->stream, rs));
     else if (W == 1) r->eng.reset(new Engine<1, double>(sys, r->stream, rs));
     else if (p->mode == FCIQMC_MODE_INTEGER) r->eng.reset(new Engine<2, int32_t>(sys, r->stream, rs));

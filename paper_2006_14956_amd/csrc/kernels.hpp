@@ -7,21 +7,23 @@
 // plus a count.  Each step reads one store and writes the other.
 //
 // Per step:
-//   k_spawn      one lane per spawn attempt -> spawn records (global append)
-//                and per-bucket record counts
-//   k_scan_count per-bucket record offsets
-//   k_scatter    records grouped by target bucket
+//   k_spawn      one lane per spawn attempt; each record goes straight into
+//                the slab of its target bucket (slab sizes reserved from the
+//                previous step's counts plus headroom; an overflow replays
+//                the step with exact sizes)
 //   k_annihilate one workgroup per bucket: death of the bucket's walkers,
 //                LDS hash merge of its spawn records under the initiator
 //                rule, stochastic rounding, compaction into the other store,
 //                estimator partial sums
-//   k_post       attempt offsets for the next step, global sums
+//   k_post       attempt offsets and record slabs for the next step, global
+//                sums, reset of the per-step counters
 #pragma once
 #include "device.hpp"
 
 namespace fq {
 
 constexpr int kThreads = 256;
+constexpr int kChunk = 1024;         // spawn attempts per workgroup
 constexpr int kSlots = 2048;        // LDS hash slots per bucket
 constexpr int kSlotsPerThread = kSlots / kThreads;
 
@@ -42,7 +44,8 @@ template <class V> struct Store {
 };
 
 struct Ctl {
-    unsigned long long nrec;   // spawn records emitted this step (may exceed capacity)
+    // accumulated during a step, reset by k_post (or by the host after a failed step)
+    unsigned long long nrec;   // spawn records emitted this step
     unsigned int flags;        // kFlag*
     unsigned int pad0;
     double nref;               // C_ref after the step
@@ -53,7 +56,12 @@ struct Ctl {
     long long attempts;        // attempts of the next step
     long long nrec_out;
     long long max_count;       // fullest bucket
+    double nref_out;
+    long long rec_need;        // record slab capacity the next step reserves
 };
+
+// Record slab of bucket b for the next step: this step's count plus headroom.
+__device__ __forceinline__ int64_t slab_size(int32_t c) { return (int64_t)c + (c >> 2) + 64; }
 
 template <class V> __device__ __forceinline__ double vabs(V v) { return v < 0 ? -(double)v : (double)v; }
 
@@ -81,13 +89,18 @@ struct StepScalars {
 // ---------------------------------------------------------------------------
 template <int W, class V, int GEN>
 __global__ __launch_bounds__(kThreads) void k_spawn(SysView sys, Store<V> st, StepScalars sc,
-                                                    Rec<W, V>* __restrict__ rec,
+                                                    Rec<W, V>* __restrict__ rec2,
+                                                    const int64_t* __restrict__ soff,
                                                     int32_t* __restrict__ scount, Ctl* ctl) {
+    // Workgroup g owns attempts [g*kChunk, (g+1)*kChunk).  A record takes the
+    // next place of its target bucket's slab rec2[soff[b] .. soff[b+1]).
+    __shared__ int wsum[kThreads / 64];
     const int64_t total = st.aoff[sc.B];
     const Key<W> ref = make_key<W>(sc.ref_a, sc.ref_b);
-    for (int64_t base = (int64_t)blockIdx.x * kThreads; base < total;
-         base += (int64_t)gridDim.x * kThreads) {
-        const int64_t at = base + threadIdx.x;
+    const int64_t g0 = (int64_t)blockIdx.x * kChunk;
+    int written = 0;
+    for (int pass = 0; pass < kChunk / kThreads; ++pass) {
+        const int64_t at = g0 + (int64_t)pass * kThreads + threadIdx.x;
         bool emit = false;
         Rec<W, V> out;
         if (at < total) {
@@ -156,24 +169,22 @@ __global__ __launch_bounds__(kThreads) void k_spawn(SysView sys, Store<V> st, St
                 }
             }
         }
-        // wave-aggregated append
-        const uint64_t mask = __ballot(emit);
-        if (mask) {
-            const int leader = __ffsll((unsigned long long)mask) - 1;
-            unsigned long long pos0 = 0;
-            if (lane_id() == leader) pos0 = atomicAdd(&ctl->nrec, (unsigned long long)popc64(mask));
-            pos0 = __shfl(pos0, leader);
-            if (emit) {
-                const unsigned long long pos = pos0 + (unsigned long long)lane_rank(mask);
-                if (pos < (unsigned long long)sc.spawn_cap) {
-                    rec[pos] = out;
-                    atomicAdd(&scount[out.flag >> 1], 1);
-                } else {
-                    atomicOr(&ctl->flags, kFlagSpawnCap);
-                }
-            }
+        if (emit) {
+            const uint32_t b = out.flag >> 1;
+            const int64_t pos = (int64_t)atomicAdd(&scount[b], 1);
+            if (soff[b] + pos < soff[b + 1]) rec2[soff[b] + pos] = out;
+            else atomicOr(&ctl->flags, kFlagSpawnCap);
         }
+        const uint64_t mask = __ballot(emit);
+        if (lane_id() == 0) wsum[threadIdx.x >> 6] = popc64(mask);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int w = 0; w < kThreads / 64; ++w) written += wsum[w];
+        }
+        __syncthreads();
     }
+    if (threadIdx.x == 0 && written) atomicAdd(&ctl->nrec, (unsigned long long)written);
 }
 
 // Records uploaded from the host (population import): assign buckets.
@@ -191,11 +202,37 @@ __global__ __launch_bounds__(kThreads) void k_bucketize(Rec<W, V>* rec, long lon
     }
 }
 
-// Exclusive prefix of per-bucket int32 counts into int64 offsets (B+1),
-// single workgroup of 1024 threads, each scanning a contiguous segment.
-__global__ __launch_bounds__(1024) void k_scan_count(const int32_t* __restrict__ cnt, int B,
-                                                     int64_t* __restrict__ off, Ctl* ctl) {
-    if (ctl && ctl->flags) return;
+// Record slabs from per-bucket counts (one workgroup of 1024 threads, each
+// scanning a contiguous segment): soff = exclusive prefix of the counts, or
+// of slab_size(count) when `headroom` is set; the counts are then zeroed.
+__device__ __forceinline__ void offsets_from_counts(int32_t* __restrict__ cnt, int B, int headroom,
+                                                    int64_t* __restrict__ off, long long* total_out,
+                                                    int64_t* sh) {
+    const int T = 1024;
+    const int per = (B + T - 1) / T;
+    const int s0 = threadIdx.x * per;
+    const int s1 = min(B, s0 + per);
+    int64_t loc = 0;
+    for (int i = s0; i < s1; ++i) loc += headroom ? slab_size(cnt[i]) : (int64_t)cnt[i];
+    int64_t tot;
+    int64_t run = block_excl_scan<1024, int64_t>(loc, tot, sh);
+    for (int i = s0; i < s1; ++i) {
+        off[i] = run;
+        run += headroom ? slab_size(cnt[i]) : (int64_t)cnt[i];
+        cnt[i] = 0;
+    }
+    if (threadIdx.x == 0) { off[B] = tot; *total_out = tot; }
+}
+
+__global__ __launch_bounds__(1024) void k_offsets(int32_t* __restrict__ cnt, int B, int headroom,
+                                                  int64_t* __restrict__ off, Ctl* ctl) {
+    __shared__ int64_t sh[16];
+    offsets_from_counts(cnt, B, headroom, off, &ctl->rec_need, sh);
+}
+
+// Exclusive prefix of counts into offsets without modifying the counts.
+__global__ __launch_bounds__(1024) void k_count_offsets(const int32_t* __restrict__ cnt, int B,
+                                                        int64_t* __restrict__ off) {
     __shared__ int64_t sh[16];
     const int T = 1024;
     const int per = (B + T - 1) / T;
@@ -209,19 +246,17 @@ __global__ __launch_bounds__(1024) void k_scan_count(const int32_t* __restrict__
     if (threadIdx.x == 0) off[B] = tot;
 }
 
+// Imported records (flat array, buckets assigned) into their slabs.
 template <int W, class V>
-__global__ __launch_bounds__(kThreads) void k_scatter(const Rec<W, V>* __restrict__ rec,
+__global__ __launch_bounds__(kThreads) void k_scatter(const Rec<W, V>* __restrict__ rec, long long n,
                                                       Rec<W, V>* __restrict__ rec2,
                                                       const int64_t* __restrict__ soff,
-                                                      int32_t* __restrict__ scur, Ctl* ctl,
-                                                      long long cap) {
-    if (ctl->flags) return;
-    const long long n = min((long long)ctl->nrec, cap);
+                                                      int32_t* __restrict__ scount) {
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n;
          i += (long long)gridDim.x * kThreads) {
         const Rec<W, V> r = rec[i];
         const uint32_t b = r.flag >> 1;
-        const int64_t pos = soff[b] + atomicAdd(&scur[b], 1);
+        const int64_t pos = soff[b] + atomicAdd(&scount[b], 1);
         rec2[pos] = r;
     }
 }
@@ -301,6 +336,7 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
                                                          StepScalars sc,
                                                          const Rec<W, V>* __restrict__ rec2,
                                                          const int64_t* __restrict__ soff,
+                                                         const int32_t* __restrict__ scount,
                                                          double* __restrict__ nw_b,
                                                          double* __restrict__ en_b, Ctl* ctl) {
     if (ctl->flags) return;
@@ -355,7 +391,7 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
         __syncthreads();
         // (c) annihilation: a target occupied at tau takes every contribution;
         // an unoccupied one only those of initiator parents (Sec. I).
-        const int64_t r0 = soff[b], r1 = soff[b + 1];
+        const int64_t r0 = soff[b], r1 = soff[b] + scount[b];
         for (int64_t r = r0 + threadIdx.x; r < r1; r += kThreads) {
             const Rec<W, V> x = rec2[r];
             Key<W> key;
@@ -456,9 +492,13 @@ __global__ __launch_bounds__(1024) void k_post(const int64_t* __restrict__ batt,
                                                const int32_t* __restrict__ count,
                                                const double* __restrict__ nw_b,
                                                const double* __restrict__ en_b, int B,
-                                               int64_t* __restrict__ aoff, Ctl* ctl) {
+                                               int64_t* __restrict__ aoff,
+                                               int32_t* __restrict__ scount,
+                                               int64_t* __restrict__ soff, Ctl* ctl) {
     if (ctl->flags) return;
     __shared__ int64_t sh[16];
+    __shared__ long long rec_need;
+    offsets_from_counts(scount, B, 1, soff, &rec_need, sh);
     __shared__ double shd[32];
     const int T = 1024;
     const int per = (B + T - 1) / T;
@@ -496,6 +536,10 @@ __global__ __launch_bounds__(1024) void k_post(const int64_t* __restrict__ batt,
         ctl->attempts = tot;
         ctl->nrec_out = (long long)ctl->nrec;
         ctl->max_count = m;
+        ctl->nref_out = ctl->nref;
+        ctl->rec_need = rec_need;
+        ctl->nrec = 0;
+        ctl->nref = 0.0;
     }
 }
 

@@ -242,12 +242,12 @@ def fciqmc_run_device_bytes(run: Run) -> int:
     return int(lib().fciqmc_run_device_bytes(run.handle))
 
 
-KERNELS = ("spawn", "record_scan", "scatter", "annihilate", "post")
+KERNELS = ("spawn", "annihilate", "post")
 
 
 def fciqmc_profile(run: Run, enable: bool = True):
     """Enable per-kernel event timing; returns (ms per kernel dict, steps, layout)."""
-    ms = np.zeros(5)
+    ms = np.zeros(len(KERNELS))
     steps = C.c_int64()
     layout = np.zeros(2, dtype=np.int64)
     _check(lib().fciqmc_profile(run.handle, int(enable), _p(ms, C.c_double), C.byref(steps),
