@@ -203,8 +203,11 @@ template <int W, class V> struct Engine : EngineBase {
     Rec<W, V>* rec2 = nullptr;  // per-bucket record slabs
     long long cap = 0;
     long long rec_need = 0;     // slab capacity the next step reserves
-    int32_t* scount = nullptr;  // records per bucket (zero between steps)
-    int64_t* soff = nullptr;    // slab offsets, B+1
+    int32_t* scount = nullptr;  // records per sub-slab, B*kSub (zero between steps)
+    int64_t* soff = nullptr;    // sub-slab offsets, B*kSub+1
+    int64_t* rel = nullptr;     // next step's sub-slab offsets within their bucket, B*kSub
+    int64_t* need_b = nullptr;  // next step's slab size per bucket, B
+    int64_t* recs_b = nullptr;  // records per bucket this step, B
     double *nw_b = nullptr, *en_b = nullptr;
     Ctl* ctl = nullptr;
     Ctl* hctl = nullptr;  // pinned
@@ -276,10 +279,13 @@ template <int W, class V> struct Engine : EngineBase {
     int alloc_buckets() {
         CHECK(alloc_store(st[0]));
         CHECK(alloc_store(st[1]));
-        CHECK(dalloc(arena, &scount, (size_t)B));
-        CHECK(dalloc(arena, &soff, (size_t)B + 1));
-        HIP_OK(hipMemsetAsync(scount, 0, sizeof(int32_t) * B, stream));
-        HIP_OK(hipMemsetAsync(soff, 0, sizeof(int64_t) * (B + 1), stream));
+        CHECK(dalloc(arena, &scount, (size_t)B * kSub));
+        CHECK(dalloc(arena, &rel, (size_t)B * kSub));
+        CHECK(dalloc(arena, &need_b, (size_t)B));
+        CHECK(dalloc(arena, &recs_b, (size_t)B));
+        CHECK(dalloc(arena, &soff, (size_t)B * kSub + 1));
+        HIP_OK(hipMemsetAsync(scount, 0, sizeof(int32_t) * B * kSub, stream));
+        HIP_OK(hipMemsetAsync(soff, 0, sizeof(int64_t) * (B * kSub + 1), stream));
         CHECK(dalloc(arena, &nw_b, (size_t)B));
         CHECK(dalloc(arena, &en_b, (size_t)B));
         return 0;
@@ -288,6 +294,8 @@ template <int W, class V> struct Engine : EngineBase {
         free_store(st[0]);
         free_store(st[1]);
         arena.release(scount); arena.release(soff);
+        arena.release(rel); arena.release(need_b); arena.release(recs_b);
+        rel = nullptr; need_b = nullptr; recs_b = nullptr;
         arena.release(nw_b); arena.release(en_b);
         scount = nullptr; soff = nullptr; nw_b = en_b = nullptr;
     }
@@ -337,10 +345,15 @@ template <int W, class V> struct Engine : EngineBase {
         Store<V> in = st[cur], out = st[1 - cur];
         const int gb = std::min(B, 32768);
         hipLaunchKernelGGL((k_annihilate<W, V>), dim3(gb), dim3(kThreads), 0, stream, v, in, out, sc,
-                           rec2, soff, scount, nw_b, en_b, ctl);
+                           rec2, soff, scount, rel, need_b, recs_b, nw_b, en_b, ctl);
         mark(2);
+        if (sc.import_mode) {
+            // slabs of the first step after an import: from the imported counts
+            hipLaunchKernelGGL(k_import_slabs, dim3((B + 255) / 256), dim3(256), 0, stream, scount, B, rel,
+                               need_b);
+        }
         hipLaunchKernelGGL(k_post, dim3(1), dim3(1024), 0, stream, out.batt, out.count, nw_b, en_b,
-                           B, out.aoff, scount, soff, ctl);
+                           B, out.aoff, rel, need_b, recs_b, soff, ctl);
         mark(3);
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
@@ -353,7 +366,7 @@ template <int W, class V> struct Engine : EngineBase {
     // record numbers per bucket), which leaves scount zero again.
     int recover() {
         HIP_OK(hipMemsetAsync(ctl, 0, offsetof(Ctl, nw), stream));
-        hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, stream, scount, B, 1, soff, ctl);
+        hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, stream, scount, B * kSub, 1, soff, ctl);
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
         HIP_OK(hipStreamSynchronize(stream));
@@ -391,12 +404,12 @@ template <int W, class V> struct Engine : EngineBase {
             Ctl c{};
             c.nrec = (unsigned long long)n;
             HIP_OK(hipMemcpyAsync(ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, stream));
-            HIP_OK(hipMemsetAsync(scount, 0, sizeof(int32_t) * B, stream));
+            HIP_OK(hipMemsetAsync(scount, 0, sizeof(int32_t) * B * kSub, stream));
             const unsigned gs = (unsigned)std::max<long long>(1, std::min<long long>(1024, (n + 255) / 256));
             if (n > 0)
                 hipLaunchKernelGGL((k_bucketize<W, V>), dim3(gs), dim3(kThreads), 0, stream, rec, (long long)n, B,
                                    scount);
-            hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, stream, scount, B, 0, soff, ctl);
+            hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, stream, scount, B * kSub, 0, soff, ctl);
             if (n > 0)
                 hipLaunchKernelGGL((k_scatter<W, V>), dim3(gs), dim3(kThreads), 0, stream, rec, (long long)n, rec2,
                                    soff, scount);

@@ -23,7 +23,11 @@
 namespace fq {
 
 constexpr int kThreads = 256;
-constexpr int kChunk = 1024;         // spawn attempts per workgroup
+constexpr int kChunk = kThreads;     // spawn attempts per workgroup
+// Each bucket's record slab is split into kSub sub-slabs, each with its own
+// counter; workgroup g appends to sub-slab g mod kSub, which divides the
+// contention on any one counter by kSub.
+constexpr int kSub = 8;
 constexpr int kSlots = 2048;        // LDS hash slots per bucket
 constexpr int kSlotsPerThread = kSlots / kThreads;
 
@@ -60,8 +64,12 @@ struct Ctl {
     long long rec_need;        // record slab capacity the next step reserves
 };
 
-// Record slab of bucket b for the next step: this step's count plus headroom.
-__device__ __forceinline__ int64_t slab_size(int32_t c) { return (int64_t)c + (c >> 2) + 64; }
+// Record sub-slab for the next step: this step's count plus headroom for
+// drift (c/8) and for Poisson fluctuations of the count (4 sqrt(c) + 32), so
+// that an overflow (and the replay it costs) stays rare across many slabs.
+__device__ __forceinline__ int64_t slab_size(int32_t c) {
+    return (int64_t)c + (c >> 3) + (int64_t)(4.0 * sqrt((double)c)) + 32;
+}
 
 template <class V> __device__ __forceinline__ double vabs(V v) { return v < 0 ? -(double)v : (double)v; }
 
@@ -92,19 +100,30 @@ __global__ __launch_bounds__(kThreads) void k_spawn(SysView sys, Store<V> st, St
                                                     Rec<W, V>* __restrict__ rec2,
                                                     const int64_t* __restrict__ soff,
                                                     int32_t* __restrict__ scount, Ctl* ctl) {
-    // Workgroup g owns attempts [g*kChunk, (g+1)*kChunk).  A record takes the
-    // next place of its target bucket's slab rec2[soff[b] .. soff[b+1]).
-    __shared__ int wsum[kThreads / 64];
+    // Workgroup g owns attempts [g*kChunk, (g+1)*kChunk).  Two lanes find the
+    // buckets of its first and last attempt; the others search between them.
+    // A record takes the next place of sub-slab j = b*kSub + g mod kSub of its
+    // target bucket b, rec2[soff[j] .. soff[j+1]).
+    __shared__ int bspan[2];
     const int64_t total = st.aoff[sc.B];
     const Key<W> ref = make_key<W>(sc.ref_a, sc.ref_b);
     const int64_t g0 = (int64_t)blockIdx.x * kChunk;
-    int written = 0;
-    for (int pass = 0; pass < kChunk / kThreads; ++pass) {
-        const int64_t at = g0 + (int64_t)pass * kThreads + threadIdx.x;
+    if (threadIdx.x < 2) {
+        const int64_t a0 = threadIdx.x == 0 ? g0 : min(g0 + kChunk, total) - 1;
+        int lo = 0, hi = sc.B;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (st.aoff[mid] <= a0) lo = mid; else hi = mid;
+        }
+        bspan[threadIdx.x] = lo;
+    }
+    __syncthreads();
+    {
+        const int64_t at = g0 + threadIdx.x;
         bool emit = false;
         Rec<W, V> out;
         if (at < total) {
-            int lo = 0, hi = sc.B;
+            int lo = bspan[0], hi = bspan[1] + 1;
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
                 if (st.aoff[mid] <= at) lo = mid; else hi = mid;
@@ -170,21 +189,12 @@ __global__ __launch_bounds__(kThreads) void k_spawn(SysView sys, Store<V> st, St
             }
         }
         if (emit) {
-            const uint32_t b = out.flag >> 1;
-            const int64_t pos = (int64_t)atomicAdd(&scount[b], 1);
-            if (soff[b] + pos < soff[b + 1]) rec2[soff[b] + pos] = out;
+            const uint32_t j = (out.flag >> 1) * kSub + (blockIdx.x & (kSub - 1));
+            const int64_t pos = (int64_t)atomicAdd(&scount[j], 1);
+            if (soff[j] + pos < soff[j + 1]) rec2[soff[j] + pos] = out;
             else atomicOr(&ctl->flags, kFlagSpawnCap);
         }
-        const uint64_t mask = __ballot(emit);
-        if (lane_id() == 0) wsum[threadIdx.x >> 6] = popc64(mask);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int w = 0; w < kThreads / 64; ++w) written += wsum[w];
-        }
-        __syncthreads();
     }
-    if (threadIdx.x == 0 && written) atomicAdd(&ctl->nrec, (unsigned long long)written);
 }
 
 // Records uploaded from the host (population import): assign buckets.
@@ -198,7 +208,7 @@ __global__ __launch_bounds__(kThreads) void k_bucketize(Rec<W, V>* rec, long lon
         for (int w = 0; w < W; ++w) k.w[w] = rec[i].k[w];
         const uint32_t b = bucket_of(key_hash<W>(k), (uint32_t)B);
         rec[i].flag = (rec[i].flag & 1u) | (b << 1);
-        atomicAdd(&scount[b], 1);
+        atomicAdd(&scount[b * kSub + (uint32_t)(i & (kSub - 1))], 1);
     }
 }
 
@@ -207,27 +217,36 @@ __global__ __launch_bounds__(kThreads) void k_bucketize(Rec<W, V>* rec, long lon
 // of slab_size(count) when `headroom` is set; the counts are then zeroed.
 __device__ __forceinline__ void offsets_from_counts(int32_t* __restrict__ cnt, int B, int headroom,
                                                     int64_t* __restrict__ off, long long* total_out,
-                                                    int64_t* sh) {
+                                                    long long* count_out, int64_t* sh) {
     const int T = 1024;
     const int per = (B + T - 1) / T;
     const int s0 = threadIdx.x * per;
     const int s1 = min(B, s0 + per);
-    int64_t loc = 0;
-    for (int i = s0; i < s1; ++i) loc += headroom ? slab_size(cnt[i]) : (int64_t)cnt[i];
+    int64_t loc = 0, raw = 0;
+    for (int i = s0; i < s1; ++i) {
+        loc += headroom ? slab_size(cnt[i]) : (int64_t)cnt[i];
+        raw += cnt[i];
+    }
     int64_t tot;
     int64_t run = block_excl_scan<1024, int64_t>(loc, tot, sh);
+    int64_t rtot;
+    (void)block_excl_scan<1024, int64_t>(raw, rtot, sh);
     for (int i = s0; i < s1; ++i) {
         off[i] = run;
         run += headroom ? slab_size(cnt[i]) : (int64_t)cnt[i];
         cnt[i] = 0;
     }
-    if (threadIdx.x == 0) { off[B] = tot; *total_out = tot; }
+    if (threadIdx.x == 0) {
+        off[B] = tot;
+        *total_out = tot;
+        if (count_out) *count_out = rtot;
+    }
 }
 
 __global__ __launch_bounds__(1024) void k_offsets(int32_t* __restrict__ cnt, int B, int headroom,
                                                   int64_t* __restrict__ off, Ctl* ctl) {
     __shared__ int64_t sh[16];
-    offsets_from_counts(cnt, B, headroom, off, &ctl->rec_need, sh);
+    offsets_from_counts(cnt, B, headroom, off, &ctl->rec_need, (long long*)nullptr, sh);
 }
 
 // Exclusive prefix of counts into offsets without modifying the counts.
@@ -255,8 +274,8 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const Rec<W, V>* __restric
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n;
          i += (long long)gridDim.x * kThreads) {
         const Rec<W, V> r = rec[i];
-        const uint32_t b = r.flag >> 1;
-        const int64_t pos = soff[b] + atomicAdd(&scount[b], 1);
+        const uint32_t j = (r.flag >> 1) * kSub + (uint32_t)(i & (kSub - 1));
+        const int64_t pos = soff[j] + atomicAdd(&scount[j], 1);
         rec2[pos] = r;
     }
 }
@@ -336,7 +355,10 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
                                                          StepScalars sc,
                                                          const Rec<W, V>* __restrict__ rec2,
                                                          const int64_t* __restrict__ soff,
-                                                         const int32_t* __restrict__ scount,
+                                                         int32_t* __restrict__ scount,
+                                                         int64_t* __restrict__ rel,
+                                                         int64_t* __restrict__ need_b,
+                                                         int64_t* __restrict__ recs_b,
                                                          double* __restrict__ nw_b,
                                                          double* __restrict__ en_b, Ctl* ctl) {
     if (ctl->flags) return;
@@ -391,9 +413,23 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
         __syncthreads();
         // (c) annihilation: a target occupied at tau takes every contribution;
         // an unoccupied one only those of initiator parents (Sec. I).
-        const int64_t r0 = soff[b], r1 = soff[b] + scount[b];
-        for (int64_t r = r0 + threadIdx.x; r < r1; r += kThreads) {
-            const Rec<W, V> x = rec2[r];
+        // the bucket's records: its kSub sub-slabs, walked as one sequence
+        // (cumulative counts and starts held in registers, selected unrolled)
+        int64_t cum[kSub + 1], lo[kSub];
+        int32_t cnt[kSub];
+        cum[0] = 0;
+#pragma unroll
+        for (int j = 0; j < kSub; ++j) {
+            lo[j] = soff[(int64_t)b * kSub + j];
+            cnt[j] = scount[(int64_t)b * kSub + j];
+            cum[j + 1] = cum[j] + cnt[j];
+        }
+        for (int64_t q = threadIdx.x; q < cum[kSub]; q += kThreads) {
+            int64_t src = 0;
+#pragma unroll
+            for (int j = 0; j < kSub; ++j)
+                if (q >= cum[j] && q < cum[j + 1]) src = lo[j] + (q - cum[j]);
+            const Rec<W, V> x = rec2[src];
             Key<W> key;
 #pragma unroll
             for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
@@ -404,6 +440,19 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
             if (init || L.idx[s] >= 0) lds_add<V>(&L.val[s], x.v);
         }
         __syncthreads();
+        // slabs of the next step: this step's counts plus headroom, relative
+        // to the bucket's base (set by k_post); the counters restart at zero
+        if (!sc.import_mode && threadIdx.x == 0) {
+            int64_t acc = 0;
+#pragma unroll
+            for (int j = 0; j < kSub; ++j) {
+                rel[(int64_t)b * kSub + j] = acc;
+                acc += slab_size(cnt[j]);
+                scount[(int64_t)b * kSub + j] = 0;
+            }
+            need_b[b] = acc;
+        }
+        if (threadIdx.x == 0) recs_b[b] = cum[kSub];
         // compaction, stochastic rounding of small real amplitudes, estimators
         int nkeep = 0;
         int64_t mloc = 0;
@@ -487,18 +536,53 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
     }
 }
 
+// After an import the per-bucket kernel leaves the counters alone; size the
+// next step's slabs from the imported counts and restart the counters.
+__global__ void k_import_slabs(int32_t* __restrict__ scount, int B, int64_t* __restrict__ rel,
+                               int64_t* __restrict__ need_b) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    int64_t acc = 0;
+    for (int j = 0; j < kSub; ++j) {
+        rel[(int64_t)b * kSub + j] = acc;
+        acc += slab_size(scount[(int64_t)b * kSub + j]);
+        scount[(int64_t)b * kSub + j] = 0;
+    }
+    need_b[b] = acc;
+}
+
 // Attempt offsets for the next step and global sums (one workgroup).
 __global__ __launch_bounds__(1024) void k_post(const int64_t* __restrict__ batt,
                                                const int32_t* __restrict__ count,
                                                const double* __restrict__ nw_b,
                                                const double* __restrict__ en_b, int B,
                                                int64_t* __restrict__ aoff,
-                                               int32_t* __restrict__ scount,
+                                               const int64_t* __restrict__ rel,
+                                               const int64_t* __restrict__ need_b,
+                                               const int64_t* __restrict__ recs_b,
                                                int64_t* __restrict__ soff, Ctl* ctl) {
     if (ctl->flags) return;
     __shared__ int64_t sh[16];
-    __shared__ long long rec_need;
-    offsets_from_counts(scount, B, 1, soff, &rec_need, sh);
+    __shared__ long long rec_need, nrs;
+    {
+        // sub-slab offsets of the next step: bucket base + relative offset
+        const int per = (B + 1023) / 1024;
+        const int b0 = threadIdx.x * per, b1 = min(B, b0 + per);
+        int64_t loc = 0;
+        for (int b = b0; b < b1; ++b) loc += need_b[b];
+        int64_t tot;
+        int64_t base = block_excl_scan<1024, int64_t>(loc, tot, sh);
+        for (int b = b0; b < b1; ++b) {
+            for (int j = 0; j < kSub; ++j) soff[(int64_t)b * kSub + j] = base + rel[(int64_t)b * kSub + j];
+            base += need_b[b];
+        }
+        if (threadIdx.x == 0) { soff[(int64_t)B * kSub] = tot; rec_need = tot; }
+        int64_t rl = 0;
+        for (int b = b0; b < b1; ++b) rl += recs_b[b];
+        int64_t rtot;
+        (void)block_excl_scan<1024, int64_t>(rl, rtot, sh);
+        if (threadIdx.x == 0) nrs = rtot;
+    }
     __shared__ double shd[32];
     const int T = 1024;
     const int per = (B + T - 1) / T;
@@ -534,7 +618,7 @@ __global__ __launch_bounds__(1024) void k_post(const int64_t* __restrict__ batt,
         ctl->enum_ = c;
         ctl->ndets = ctot;
         ctl->attempts = tot;
-        ctl->nrec_out = (long long)ctl->nrec;
+        ctl->nrec_out = nrs;
         ctl->max_count = m;
         ctl->nref_out = ctl->nref;
         ctl->rec_need = rec_need;
