@@ -154,6 +154,7 @@ struct SysView {
     const double* eri;    // 8-fold packed
     const double* J;      // J[p*N+q] = (pp|qq)
     const double* K;      // K[p*N+q] = (pq|qp)
+    const double* X;      // X[p*N+q] = (pp|qq) - (pq|qp), the same-spin pair term
     const double* U;      // U[p] = (pp|pp)
     const int* deg;       // lattice degree
     const int* nbr;       // N*N ascending neighbour lists
@@ -232,20 +233,14 @@ __device__ __forceinline__ double h_diag(const SysView& s, uint64_t a, uint64_t 
     }
     for (uint64_t x = a; x; x &= x - 1) {
         const int p = ctz64(x);
-        for (uint64_t y = x & (x - 1); y; y &= y - 1) {
-            const int q = ctz64(y);
-            const double t = s.J[p * N + q] - s.K[p * N + q];
-            acc = acc + t;
-        }
-        for (uint64_t y = b; y; y &= y - 1) { const int q = ctz64(y); acc = acc + s.J[p * N + q]; }
+        const double* xr = s.X + p * N;
+        const double* jr = s.J + p * N;
+        for (uint64_t y = x & (x - 1); y; y &= y - 1) acc = acc + xr[ctz64(y)];
+        for (uint64_t y = b; y; y &= y - 1) acc = acc + jr[ctz64(y)];
     }
     for (uint64_t x = b; x; x &= x - 1) {
-        const int p = ctz64(x);
-        for (uint64_t y = x & (x - 1); y; y &= y - 1) {
-            const int q = ctz64(y);
-            const double t = s.J[p * N + q] - s.K[p * N + q];
-            acc = acc + t;
-        }
+        const double* xr = s.X + ctz64(x) * N;
+        for (uint64_t y = x & (x - 1); y; y &= y - 1) acc = acc + xr[ctz64(y)];
     }
     return acc;
 }

@@ -30,6 +30,7 @@ constexpr int kChunk = kThreads;     // spawn attempts per workgroup
 constexpr int kSub = 8;
 constexpr int kSlots = 2048;        // LDS hash slots per bucket
 constexpr int kSlotsPerThread = kSlots / kThreads;
+constexpr int kFresh = 512;         // new determinants per bucket whose diagonal is spread over the workgroup
 
 template <int W, class V> struct Rec {
     uint64_t k[W];
@@ -288,6 +289,8 @@ template <int W, class V> struct Lds {
     uint64_t key1[W == 2 ? kSlots : 1];
     V val[kSlots];
     int32_t idx[kSlots];   // entry index in the input store, -1 for a new determinant
+    int32_t fresh[kFresh]; // new survivors awaiting their diagonal: slot | out position << 11
+    int nfresh;
     int64_t sh64[8];
     double shd[8];
 };
@@ -372,6 +375,7 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
             L.val[i] = (V)0;
             L.idx[i] = -1;
         }
+        if (threadIdx.x == 0) L.nfresh = 0;
         __syncthreads();
         const int64_t eb = (int64_t)b * sc.R;
         // (b) death of the walkers occupied at tau: x = (1 - dtau (d_i - S)) C_i,
@@ -502,10 +506,14 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
             out.vals[o] = v;
             const int oi = L.idx[s];
             const uint64_t ka = key_alpha<W>(key), kb = key_beta<W>(key);
-            double d;
-            if (oi >= 0) d = in.diag[eb + oi];
-            else { const double hd = h_diag(sys, ka, kb); d = hd - sc.h00; }
-            out.diag[o] = d;
+            if (oi >= 0) {
+                out.diag[o] = in.diag[eb + oi];
+            } else {
+                // new determinant: its diagonal is computed below, one per lane
+                const int f = atomicAdd(&L.nfresh, 1);
+                if (f < kFresh) L.fresh[f] = s | (pos << 11);
+                else { const double hd = h_diag(sys, ka, kb); out.diag[o] = hd - sc.h00; }
+            }
             out.mpre[o] = (int32_t)mpos;
             ++pos;
             mpos += n_attempts(v);
@@ -526,6 +534,17 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
         en = wave_sum(en);
         if (lane_id() == 0) { L.shd[threadIdx.x >> 6] = nw; L.shd[4 + (threadIdx.x >> 6)] = en; }
         __syncthreads();
+        // diagonals of the new determinants, spread over the workgroup
+        const int nf = min(L.nfresh, kFresh);
+        for (int f = threadIdx.x; f < nf; f += kThreads) {
+            const int s = L.fresh[f] & 2047;
+            const int64_t o = eb + (L.fresh[f] >> 11);
+            Key<W> key;
+            key.w[0] = L.key0[s];
+            if constexpr (W == 2) key.w[1] = L.key1[s];
+            const double hd = h_diag(sys, key_alpha<W>(key), key_beta<W>(key));
+            out.diag[o] = hd - sc.h00;
+        }
         if (threadIdx.x == 0) {
             nw_b[b] = ((L.shd[0] + L.shd[1]) + L.shd[2]) + L.shd[3];
             en_b[b] = ((L.shd[4] + L.shd[5]) + L.shd[6]) + L.shd[7];
@@ -654,13 +673,17 @@ __global__ void k_hij(SysView sys, const uint64_t* __restrict__ di, const uint64
     }
 }
 
-// J/K/U tables copied out of the packed integrals.
-__global__ void k_build_jk(SysView sys, double* J, double* K, double* U) {
+// J/K/U tables copied out of the packed integrals, and the same-spin pair
+// term X = J - K of the diagonal (one rounding, as in the diagonal's sum).
+__global__ void k_build_jk(SysView sys, double* J, double* K, double* X, double* U) {
     const int N = sys.N;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N * N; i += gridDim.x * blockDim.x) {
         const int p = i / N, q = i % N;
-        J[i] = eri(sys, p, p, q, q);
-        K[i] = eri(sys, p, q, q, p);
+        const double j = eri(sys, p, p, q, q);
+        const double k = eri(sys, p, q, q, p);
+        J[i] = j;
+        K[i] = k;
+        X[i] = j - k;
         if (p == q) U[p] = eri(sys, p, p, p, p);
     }
 }
