@@ -183,6 +183,11 @@ struct EngineBase {
 
 // kernels of one step, in launch order: spawn, annihilation, post
 constexpr int kKernels = 3;
+#ifndef FQ_OCCUPANCY
+#define FQ_OCCUPANCY 1024
+#endif
+// determinants of the capacity hint per bucket of the walker store
+constexpr int kBucketOccupancy = FQ_OCCUPANCY;
 
 struct RunScalars {
     double tau, p_single, p_double, p_opp, n_a, c_min, h00;
@@ -352,7 +357,7 @@ template <int W, class V> struct Engine : EngineBase {
             hipLaunchKernelGGL(k_import_slabs, dim3((B + 255) / 256), dim3(256), 0, stream, scount, B, rel,
                                need_b);
         }
-        hipLaunchKernelGGL(k_post, dim3(1), dim3(1024), 0, stream, out.batt, out.count, nw_b, en_b,
+        hipLaunchKernelGGL(k_post, dim3(1), dim3(kPostThreads), 0, stream, out.batt, out.count, nw_b, en_b,
                            B, out.aoff, rel, need_b, recs_b, soff, ctl);
         mark(3);
         HIP_OK(hipGetLastError());
@@ -745,10 +750,10 @@ int fciqmc_init(const fciqmc_system* csys, const fciqmc_params* p, void* stream,
     // capacities start from the hints (or the target) and grow on demand
     int64_t max_dets = p->max_dets > 0 ? p->max_dets : (int64_t)std::min(target, 16777216.0);
     max_dets = std::max<int64_t>(max_dets, 1024);
-    // about 1024 determinants of the capacity hint per bucket (the store holds
-    // R = 1024 per bucket; buckets double when one overflows)
+    // kBucketOccupancy determinants of the capacity hint per bucket (the store
+    // holds R = 1024 per bucket; buckets double when one overflows)
     int B = p->buckets_log2 > 0 ? (1 << std::min(p->buckets_log2, 22))
-                                : (int)next_pow2((uint64_t)((max_dets + 1023) / 1024));
+                                : (int)next_pow2((uint64_t)((max_dets + kBucketOccupancy - 1) / kBucketOccupancy));
     long long spawn_cap = p->max_spawns > 0 ? p->max_spawns
                                             : (long long)std::min(std::max(65536.0, 1.0 * target), 33554432.0);
     if (W == 1 && p->mode == FCIQMC_MODE_INTEGER) r->eng.reset(new Engine<1, int32_t>(sys, r->stream, rs));

@@ -24,11 +24,15 @@ namespace fq {
 
 constexpr int kThreads = 256;
 constexpr int kChunk = kThreads;     // spawn attempts per workgroup
+constexpr int kPostThreads = 512;   // the post kernel's single workgroup
 // Each bucket's record slab is split into kSub sub-slabs, each with its own
 // counter; workgroup g appends to sub-slab g mod kSub, which divides the
 // contention on any one counter by kSub.
 constexpr int kSub = 8;
-constexpr int kSlots = 2048;        // LDS hash slots per bucket
+#ifndef FQ_SLOTS
+#define FQ_SLOTS 1024
+#endif
+constexpr int kSlots = FQ_SLOTS;    // LDS hash slots per bucket (table size adapts below this)
 constexpr int kSlotsPerThread = kSlots / kThreads;
 constexpr int kFresh = 512;         // new determinants per bucket whose diagonal is spread over the workgroup
 
@@ -303,8 +307,9 @@ template <int W> __device__ __forceinline__ uint64_t lds_load(const uint64_t* p)
 // Returns the slot, -1 if absent (not inserted), -2 if the table is full,
 // -3 if a claimed slot never became readable.
 template <int W, class V>
-__device__ __forceinline__ int lds_find(Lds<W, V>& L, const Key<W>& key, uint64_t h, bool insert) {
-    int s = (int)(h & (uint64_t)(kSlots - 1));
+__device__ __forceinline__ int lds_find(Lds<W, V>& L, const Key<W>& key, uint64_t h, uint64_t mask,
+                                        bool insert) {
+    int s = (int)(h & mask);
     int probes = 0;
     int spins = 0;
     while (true) {
@@ -340,8 +345,8 @@ __device__ __forceinline__ int lds_find(Lds<W, V>& L, const Key<W>& key, uint64_
         } else {
             if (w0 == key.w[0]) return s;
         }
-        s = (s + 1) & (kSlots - 1);
-        if (++probes >= kSlots) return -2;
+        s = (s + 1) & (int)mask;
+        if (++probes > (int)mask) return -2;
     }
 }
 
@@ -350,14 +355,83 @@ template <class V> __device__ __forceinline__ void lds_add(V* p, V v) {
 }
 
 // ---------------------------------------------------------------------------
+// Global sums and next-step offsets (attempt prefix over buckets, record
+// sub-slab offsets), executed by one workgroup of NT threads.
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, const int32_t* __restrict__ count,
+                                          const double* __restrict__ nw_b, const double* __restrict__ en_b,
+                                          const int64_t* __restrict__ rel, const int64_t* __restrict__ need_b,
+                                          const int64_t* __restrict__ recs_b, int B,
+                                          int64_t* __restrict__ aoff, int64_t* __restrict__ soff, Ctl* ctl,
+                                          int64_t* sh, double* shd, int64_t* shm) {
+    // one pass of loads (all per-bucket values of this thread's run of
+    // buckets), the scans, then one pass of writes
+    const int per = (B + NT - 1) / NT;
+    const int b0 = threadIdx.x * per, b1 = min(B, b0 + per);
+    int64_t la = 0, ln = 0, cnt = 0, rc = 0, mx = 0;
+    double nw = 0.0, en = 0.0;
+    for (int b = b0; b < b1; ++b) {
+        la += batt[b];
+        ln += need_b[b];
+        const int64_t c = count[b];
+        cnt += c;
+        rc += recs_b[b];
+        mx = max(mx, c);
+        nw = nw + nw_b[b];
+        en = en + en_b[b];
+    }
+    int64_t atot, ntot, crtot;
+    const int64_t abase = block_excl_scan<NT, int64_t>(la, atot, sh);
+    const int64_t nbase = block_excl_scan<NT, int64_t>(ln, ntot, sh);
+    // determinants (< 2^32) and records (< 2^31 per step) packed in one scan
+    (void)block_excl_scan<NT, int64_t>((cnt << 32) | rc, crtot, sh);
+    int64_t run = abase, base = nbase;
+    for (int b = b0; b < b1; ++b) {
+        aoff[b] = run;
+        run += batt[b];
+        for (int j = 0; j < kSub; ++j) soff[(int64_t)b * kSub + j] = base + rel[(int64_t)b * kSub + j];
+        base += need_b[b];
+    }
+    // N_w and the E_proj numerator in a fixed order: per-thread runs, wave
+    // butterflies, waves in order
+    nw = wave_sum(nw);
+    en = wave_sum(en);
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, (int64_t)__shfl_xor(mx, o));
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) { shd[w] = nw; shd[NT / 64 + w] = en; shm[w] = mx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, c = 0.0;
+        int64_t m = 0;
+        for (int i = 0; i < NT / 64; ++i) { a = a + shd[i]; c = c + shd[NT / 64 + i]; m = max(m, shm[i]); }
+        aoff[B] = atot;
+        soff[(int64_t)B * kSub] = ntot;
+        ctl->nw = a;
+        ctl->enum_ = c;
+        ctl->ndets = crtot >> 32;
+        ctl->attempts = atot;
+        ctl->nrec_out = crtot & 0xFFFFFFFFLL;
+        ctl->max_count = m;
+        ctl->nref_out = ctl->nref;
+        ctl->rec_need = ntot;
+        ctl->nrec = 0;
+        ctl->nref = 0.0;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // Death, annihilation with the initiator rule, compaction and estimators,
 // one workgroup per bucket (Sec. I steps (b) and (c); Sec. IV Eq. (proje)).
 // ---------------------------------------------------------------------------
+constexpr int64_t kM40 = (1LL << 40) - 1;
+
 template <int W, class V>
 __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> in, Store<V> out,
                                                          StepScalars sc,
                                                          const Rec<W, V>* __restrict__ rec2,
-                                                         const int64_t* __restrict__ soff,
+                                                         int64_t* __restrict__ soff,
                                                          int32_t* __restrict__ scount,
                                                          int64_t* __restrict__ rel,
                                                          int64_t* __restrict__ need_b,
@@ -369,7 +443,25 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
     const Key<W> ref = make_key<W>(sc.ref_a, sc.ref_b);
     constexpr bool kInt = sizeof(V) == 4;
     for (int b = blockIdx.x; b < sc.B; b += gridDim.x) {
-        for (int i = threadIdx.x; i < kSlots; i += kThreads) {
+        const int64_t eb = (int64_t)b * sc.R;
+        const int cnt = sc.import_mode ? 0 : in.count[b];
+        // the bucket's records: its kSub sub-slabs, walked as one sequence
+        // (cumulative counts and starts held in registers, selected unrolled)
+        int64_t cum[kSub + 1], lo[kSub];
+        int32_t cj[kSub];
+        cum[0] = 0;
+#pragma unroll
+        for (int j = 0; j < kSub; ++j) {
+            lo[j] = soff[(int64_t)b * kSub + j];
+            cj[j] = scount[(int64_t)b * kSub + j];
+            cum[j + 1] = cum[j] + cj[j];
+        }
+        // LDS table sized to the bucket: keys <= determinants + records, load <= 3/4
+        const int64_t want = ((int64_t)cnt + cum[kSub]) * 4 / 3 + 1;
+        int nslots = kThreads;
+        while (nslots < want && nslots < kSlots) nslots <<= 1;
+        const uint64_t mask = (uint64_t)(nslots - 1);
+        for (int i = threadIdx.x; i < nslots; i += kThreads) {
             L.key0[i] = kEmpty;
             if constexpr (W == 2) L.key1[i] = kEmpty;
             L.val[i] = (V)0;
@@ -377,57 +469,42 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
         }
         if (threadIdx.x == 0) L.nfresh = 0;
         __syncthreads();
-        const int64_t eb = (int64_t)b * sc.R;
         // (b) death of the walkers occupied at tau: x = (1 - dtau (d_i - S)) C_i,
         // stochastically rounded; the slot is marked as occupied at tau.
-        if (!sc.import_mode) {
-            const int cnt = in.count[b];
-            for (int e = threadIdx.x; e < cnt; e += kThreads) {
-                const Key<W> key = load_key<W>(in.keys + (eb + e) * W);
-                const V C = in.vals[eb + e];
-                const double d = in.diag[eb + e];
-                const double t1 = d - sc.S;
-                const double t2 = sc.tau * t1;
-                const double f = 1.0 - t2;
-                const double xv = f * (double)C;
-                const double u = unif(draw<W>(key, sc.t, 0, kDeath, sc.seed, sc.replica).x[0]);
-                V post;
-                if constexpr (kInt) {
-                    const double ax = fabs(xv);
-                    const double fl = floor(ax);
-                    const double fr = ax - fl;
-                    const double nn = fl + (u < fr ? 1.0 : 0.0);
-                    if (nn > 2147483000.0) atomicOr(&ctl->flags, kFlagPop);
-                    post = (V)(xv < 0.0 ? -nn : nn);
-                } else {
-                    const double ax = fabs(xv);
-                    double y = xv;
-                    if (ax < sc.c_min && xv != 0.0) {
-                        const double pr = ax / sc.c_min;
-                        y = (u < pr) ? (xv < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
-                    }
-                    post = (V)y;
+        for (int e = threadIdx.x; e < cnt; e += kThreads) {
+            const Key<W> key = load_key<W>(in.keys + (eb + e) * W);
+            const V C = in.vals[eb + e];
+            const double d = in.diag[eb + e];
+            const double t1 = d - sc.S;
+            const double t2 = sc.tau * t1;
+            const double f = 1.0 - t2;
+            const double xv = f * (double)C;
+            const double u = unif(draw<W>(key, sc.t, 0, kDeath, sc.seed, sc.replica).x[0]);
+            V post;
+            if constexpr (kInt) {
+                const double ax = fabs(xv);
+                const double fl = floor(ax);
+                const double fr = ax - fl;
+                const double nn = fl + (u < fr ? 1.0 : 0.0);
+                if (nn > 2147483000.0) atomicOr(&ctl->flags, kFlagPop);
+                post = (V)(xv < 0.0 ? -nn : nn);
+            } else {
+                const double ax = fabs(xv);
+                double y = xv;
+                if (ax < sc.c_min && xv != 0.0) {
+                    const double pr = ax / sc.c_min;
+                    y = (u < pr) ? (xv < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
                 }
-                const int s = lds_find<W, V>(L, key, key_hash<W>(key), true);
-                if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); continue; }
-                L.val[s] = post;
-                L.idx[s] = e;
+                post = (V)y;
             }
+            const int s = lds_find<W, V>(L, key, key_hash<W>(key), mask, true);
+            if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); continue; }
+            L.val[s] = post;
+            L.idx[s] = e;
         }
         __syncthreads();
         // (c) annihilation: a target occupied at tau takes every contribution;
         // an unoccupied one only those of initiator parents (Sec. I).
-        // the bucket's records: its kSub sub-slabs, walked as one sequence
-        // (cumulative counts and starts held in registers, selected unrolled)
-        int64_t cum[kSub + 1], lo[kSub];
-        int32_t cnt[kSub];
-        cum[0] = 0;
-#pragma unroll
-        for (int j = 0; j < kSub; ++j) {
-            lo[j] = soff[(int64_t)b * kSub + j];
-            cnt[j] = scount[(int64_t)b * kSub + j];
-            cum[j + 1] = cum[j] + cnt[j];
-        }
         for (int64_t q = threadIdx.x; q < cum[kSub]; q += kThreads) {
             int64_t src = 0;
 #pragma unroll
@@ -438,97 +515,93 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
 #pragma unroll
             for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
             const bool init = (x.flag & 1u) != 0;
-            const int s = lds_find<W, V>(L, key, key_hash<W>(key), init);
+            const int s = lds_find<W, V>(L, key, key_hash<W>(key), mask, init);
             if (s == -1) continue;
             if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); continue; }
             if (init || L.idx[s] >= 0) lds_add<V>(&L.val[s], x.v);
         }
         __syncthreads();
-        // slabs of the next step: this step's counts plus headroom, relative
-        // to the bucket's base (set by k_post); the counters restart at zero
-        if (!sc.import_mode && threadIdx.x == 0) {
-            int64_t acc = 0;
+        if (threadIdx.x == 0) {
+            // slabs of the next step: this step's counts plus headroom, relative
+            // to the bucket's base (set by the post work); counters restart at 0
+            if (!sc.import_mode) {
+                int64_t acc = 0;
 #pragma unroll
-            for (int j = 0; j < kSub; ++j) {
-                rel[(int64_t)b * kSub + j] = acc;
-                acc += slab_size(cnt[j]);
-                scount[(int64_t)b * kSub + j] = 0;
+                for (int j = 0; j < kSub; ++j) {
+                    rel[(int64_t)b * kSub + j] = acc;
+                    acc += slab_size(cj[j]);
+                    scount[(int64_t)b * kSub + j] = 0;
+                }
+                need_b[b] = acc;
             }
-            need_b[b] = acc;
+            recs_b[b] = cum[kSub];
         }
-        if (threadIdx.x == 0) recs_b[b] = cum[kSub];
-        // compaction, stochastic rounding of small real amplitudes, estimators
-        int nkeep = 0;
-        int64_t mloc = 0;
-        const int s0 = threadIdx.x * kSlotsPerThread;
-#pragma unroll
-        for (int j = 0; j < kSlotsPerThread; ++j) {
-            const int s = s0 + j;
-            if (L.key0[s] == kEmpty) continue;
-            V v = L.val[s];
-            if constexpr (!kInt) {
-                if (!sc.import_mode) {
+        // compaction in passes of kThreads consecutive slots: rounding of small
+        // real amplitudes, output positions and attempt prefixes by a block
+        // scan of (kept, attempts) packed as kept << 40 | attempts
+        int64_t obase = 0, mbase = 0;
+        double nw = 0.0, en = 0.0;
+        bool over = false;
+        for (int p0 = 0; p0 < nslots; p0 += kThreads) {
+            const int s = p0 + threadIdx.x;
+            const uint64_t k0 = L.key0[s];
+            V v = (V)0;
+            Key<W> key;
+            key.w[0] = k0;
+            if constexpr (W == 2) key.w[1] = L.key1[s];
+            if (k0 != kEmpty) {
+                v = L.val[s];
+                if constexpr (!kInt) {
                     const double av = fabs((double)v);
-                    if (v != 0.0 && av < sc.c_min) {
-                        Key<W> key;
-                        key.w[0] = L.key0[s];
-                        if constexpr (W == 2) key.w[1] = L.key1[s];
+                    if (!sc.import_mode && v != 0.0 && av < sc.c_min) {
                         const double u = unif(draw<W>(key, sc.t, 0, kAnn, sc.seed, sc.replica).x[0]);
                         const double pr = av / sc.c_min;
                         v = (u < pr) ? (v < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
-                        L.val[s] = v;
                     }
                 }
             }
-            if (v != (V)0) { ++nkeep; mloc += n_attempts(v); }
+            const bool keep = v != (V)0;
+            const int64_t m = keep ? n_attempts(v) : 0;
+            int64_t tot;
+            const int64_t ex = block_excl_scan<kThreads, int64_t>(keep ? ((1LL << 40) | m) : 0, tot, L.sh64);
+            const int64_t pos = obase + (ex >> 40);
+            const int64_t mp = mbase + (ex & kM40);
+            obase += tot >> 40;
+            mbase += tot & kM40;
+            if (obase > sc.R || mbase >= (int64_t)0x7FFFFFFF) { over = true; break; }
+            if (keep) {
+                const int64_t o = eb + pos;
+                store_key<W>(out.keys + o * W, key);
+                out.vals[o] = v;
+                out.mpre[o] = (int32_t)mp;
+                const int oi = L.idx[s];
+                const uint64_t ka = key_alpha<W>(key), kb = key_beta<W>(key);
+                if (oi >= 0) {
+                    out.diag[o] = in.diag[eb + oi];
+                } else {
+                    // new determinant: its diagonal is computed below, one per lane
+                    const int f = atomicAdd(&L.nfresh, 1);
+                    if (f < kFresh) L.fresh[f] = s | ((int)pos << 11);
+                    else { const double hd = h_diag(sys, ka, kb); out.diag[o] = hd - sc.h00; }
+                }
+                const double av = vabs(v);
+                nw = nw + av;
+                if (key_eq<W>(key, ref)) {
+                    ctl->nref = (double)v;
+                } else {
+                    const int lvl = popc64(ka ^ sc.ref_a) + popc64(kb ^ sc.ref_b);
+                    if (lvl == 2 || lvl == 4) {
+                        const double h = h_offdiag(sys, sc.ref_a, sc.ref_b, ka, kb);
+                        const double c = h * (double)v;
+                        en = en + c;
+                    }
+                }
+            }
         }
-        int nkeep_tot;
-        int pos = block_excl_scan<kThreads, int>(nkeep, nkeep_tot, (int*)L.sh64);
-        int64_t m_tot;
-        int64_t mpos = block_excl_scan<kThreads, int64_t>(mloc, m_tot, L.sh64);
-        if (nkeep_tot > sc.R || m_tot >= (int64_t)0x7FFFFFFF) {
+        if (over) {
             if (threadIdx.x == 0) atomicOr(&ctl->flags, kFlagStore);
             __syncthreads();
             continue;
-        }
-        double nw = 0.0, en = 0.0;
-#pragma unroll
-        for (int j = 0; j < kSlotsPerThread; ++j) {
-            const int s = s0 + j;
-            if (L.key0[s] == kEmpty) continue;
-            const V v = L.val[s];
-            if (v == (V)0) continue;
-            Key<W> key;
-            key.w[0] = L.key0[s];
-            if constexpr (W == 2) key.w[1] = L.key1[s];
-            const int64_t o = eb + pos;
-            store_key<W>(out.keys + o * W, key);
-            out.vals[o] = v;
-            const int oi = L.idx[s];
-            const uint64_t ka = key_alpha<W>(key), kb = key_beta<W>(key);
-            if (oi >= 0) {
-                out.diag[o] = in.diag[eb + oi];
-            } else {
-                // new determinant: its diagonal is computed below, one per lane
-                const int f = atomicAdd(&L.nfresh, 1);
-                if (f < kFresh) L.fresh[f] = s | (pos << 11);
-                else { const double hd = h_diag(sys, ka, kb); out.diag[o] = hd - sc.h00; }
-            }
-            out.mpre[o] = (int32_t)mpos;
-            ++pos;
-            mpos += n_attempts(v);
-            const double av = vabs(v);
-            nw = nw + av;
-            if (key_eq<W>(key, ref)) {
-                ctl->nref = (double)v;
-            } else {
-                const int lvl = popc64(ka ^ sc.ref_a) + popc64(kb ^ sc.ref_b);
-                if (lvl == 2 || lvl == 4) {
-                    const double h = h_offdiag(sys, sc.ref_a, sc.ref_b, ka, kb);
-                    const double c = h * (double)v;
-                    en = en + c;
-                }
-            }
         }
         nw = wave_sum(nw);
         en = wave_sum(en);
@@ -548,12 +621,13 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
         if (threadIdx.x == 0) {
             nw_b[b] = ((L.shd[0] + L.shd[1]) + L.shd[2]) + L.shd[3];
             en_b[b] = ((L.shd[4] + L.shd[5]) + L.shd[6]) + L.shd[7];
-            out.count[b] = nkeep_tot;
-            out.batt[b] = m_tot;
+            out.count[b] = (int32_t)obase;
+            out.batt[b] = mbase;
         }
         __syncthreads();
     }
 }
+
 
 // After an import the per-bucket kernel leaves the counters alone; size the
 // next step's slabs from the imported counts and restart the counters.
@@ -570,8 +644,8 @@ __global__ void k_import_slabs(int32_t* __restrict__ scount, int B, int64_t* __r
     need_b[b] = acc;
 }
 
-// Attempt offsets for the next step and global sums (one workgroup).
-__global__ __launch_bounds__(1024) void k_post(const int64_t* __restrict__ batt,
+// Post work as its own launch (one workgroup).
+__global__ __launch_bounds__(kPostThreads) void k_post(const int64_t* __restrict__ batt,
                                                const int32_t* __restrict__ count,
                                                const double* __restrict__ nw_b,
                                                const double* __restrict__ en_b, int B,
@@ -581,69 +655,9 @@ __global__ __launch_bounds__(1024) void k_post(const int64_t* __restrict__ batt,
                                                const int64_t* __restrict__ recs_b,
                                                int64_t* __restrict__ soff, Ctl* ctl) {
     if (ctl->flags) return;
-    __shared__ int64_t sh[16];
-    __shared__ long long rec_need, nrs;
-    {
-        // sub-slab offsets of the next step: bucket base + relative offset
-        const int per = (B + 1023) / 1024;
-        const int b0 = threadIdx.x * per, b1 = min(B, b0 + per);
-        int64_t loc = 0;
-        for (int b = b0; b < b1; ++b) loc += need_b[b];
-        int64_t tot;
-        int64_t base = block_excl_scan<1024, int64_t>(loc, tot, sh);
-        for (int b = b0; b < b1; ++b) {
-            for (int j = 0; j < kSub; ++j) soff[(int64_t)b * kSub + j] = base + rel[(int64_t)b * kSub + j];
-            base += need_b[b];
-        }
-        if (threadIdx.x == 0) { soff[(int64_t)B * kSub] = tot; rec_need = tot; }
-        int64_t rl = 0;
-        for (int b = b0; b < b1; ++b) rl += recs_b[b];
-        int64_t rtot;
-        (void)block_excl_scan<1024, int64_t>(rl, rtot, sh);
-        if (threadIdx.x == 0) nrs = rtot;
-    }
-    __shared__ double shd[32];
-    const int T = 1024;
-    const int per = (B + T - 1) / T;
-    const int s0 = threadIdx.x * per;
-    const int s1 = min(B, s0 + per);
-    int64_t loc = 0, cnt = 0, mx = 0;
-    double nw = 0.0, en = 0.0;
-    for (int i = s0; i < s1; ++i) {
-        loc += batt[i];
-        cnt += count[i];
-        mx = max(mx, (int64_t)count[i]);
-        nw = nw + nw_b[i];
-        en = en + en_b[i];
-    }
-    int64_t tot;
-    int64_t run = block_excl_scan<1024, int64_t>(loc, tot, sh);
-    for (int i = s0; i < s1; ++i) { aoff[i] = run; run += batt[i]; }
-    int64_t ctot;
-    (void)block_excl_scan<1024, int64_t>(cnt, ctot, sh);
-    // fixed-order reductions: wave tree, then the 16 wave sums in order
-    nw = wave_sum(nw);
-    en = wave_sum(en);
-    for (int o = 32; o > 0; o >>= 1) mx = max(mx, (int64_t)__shfl_xor(mx, o));
-    __shared__ int64_t shm[16];
-    if (lane_id() == 0) { shd[threadIdx.x >> 6] = nw; shd[16 + (threadIdx.x >> 6)] = en; shm[threadIdx.x >> 6] = mx; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double a = 0.0, c = 0.0;
-        int64_t m = 0;
-        for (int i = 0; i < 16; ++i) { a = a + shd[i]; c = c + shd[16 + i]; m = max(m, shm[i]); }
-        aoff[B] = tot;
-        ctl->nw = a;
-        ctl->enum_ = c;
-        ctl->ndets = ctot;
-        ctl->attempts = tot;
-        ctl->nrec_out = nrs;
-        ctl->max_count = m;
-        ctl->nref_out = ctl->nref;
-        ctl->rec_need = rec_need;
-        ctl->nrec = 0;
-        ctl->nref = 0.0;
-    }
+    __shared__ int64_t sh[kPostThreads / 64], shm[kPostThreads / 64];
+    __shared__ double shd[2 * kPostThreads / 64];
+    post_work<kPostThreads>(batt, count, nw_b, en_b, rel, need_b, recs_b, B, aoff, soff, ctl, sh, shd, shm);
 }
 
 // Copy the store to flat arrays (offsets from a count scan).
