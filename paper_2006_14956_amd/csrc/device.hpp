@@ -155,6 +155,7 @@ struct SysView {
     const double* J;      // J[p*N+q] = (pp|qq)
     const double* K;      // K[p*N+q] = (pq|qp)
     const double* X;      // X[p*N+q] = (pp|qq) - (pq|qp), the same-spin pair term
+    const double* Hd;     // Hd[p] = h_pp
     const double* U;      // U[p] = (pp|pp)
     const int* deg;       // lattice degree
     const int* nbr;       // N*N ascending neighbour lists
@@ -219,30 +220,39 @@ __device__ __forceinline__ double h_double(const SysView& s, uint64_t a, uint64_
     return (par & 1) ? -v : v;
 }
 
-// H_ii: sum_p h_pp + sum_{p<q} [(pp|qq) - delta(spin)(pq|qp)], canonical order.
-__device__ __forceinline__ double h_diag(const SysView& s, uint64_t a, uint64_t b) {
-    const int N = s.N;
+// H_ii: sum_p h_pp + sum_{p<q} [(pp|qq) - delta(spin)(pq|qp)], canonical order,
+// from tables hd[p] = h_pp, X[p*N+q] = (pp|qq) - (pq|qp), J[p*N+q] = (pp|qq)
+// (global or LDS copies; the additions are the same either way).
+__device__ __forceinline__ double h_diag_tab(const double* hd, const double* X, const double* J, int N,
+                                             uint64_t a, uint64_t b) {
     double acc = 0.0;
-    for (uint64_t x = a; x; x &= x - 1) { const int p = ctz64(x); acc = acc + s.h1[p * N + p]; }
-    for (uint64_t x = b; x; x &= x - 1) { const int p = ctz64(x); acc = acc + s.h1[p * N + p]; }
-    if (s.onsite) {
-        // only opposite-spin pairs on one site contribute; they occur in
-        // ascending site order in the canonical pair loop
-        for (uint64_t x = a & b; x; x &= x - 1) { const int p = ctz64(x); acc = acc + s.U[p]; }
-        return acc;
-    }
+    for (uint64_t x = a; x; x &= x - 1) acc = acc + hd[ctz64(x)];
+    for (uint64_t x = b; x; x &= x - 1) acc = acc + hd[ctz64(x)];
     for (uint64_t x = a; x; x &= x - 1) {
         const int p = ctz64(x);
-        const double* xr = s.X + p * N;
-        const double* jr = s.J + p * N;
+        const double* xr = X + p * N;
+        const double* jr = J + p * N;
         for (uint64_t y = x & (x - 1); y; y &= y - 1) acc = acc + xr[ctz64(y)];
         for (uint64_t y = b; y; y &= y - 1) acc = acc + jr[ctz64(y)];
     }
     for (uint64_t x = b; x; x &= x - 1) {
-        const double* xr = s.X + ctz64(x) * N;
+        const double* xr = X + ctz64(x) * N;
         for (uint64_t y = x & (x - 1); y; y &= y - 1) acc = acc + xr[ctz64(y)];
     }
     return acc;
+}
+
+__device__ __forceinline__ double h_diag(const SysView& s, uint64_t a, uint64_t b) {
+    if (s.onsite) {
+        // only opposite-spin pairs on one site contribute; they occur in
+        // ascending site order in the canonical pair loop
+        double acc = 0.0;
+        for (uint64_t x = a; x; x &= x - 1) acc = acc + s.Hd[ctz64(x)];
+        for (uint64_t x = b; x; x &= x - 1) acc = acc + s.Hd[ctz64(x)];
+        for (uint64_t x = a & b; x; x &= x - 1) acc = acc + s.U[ctz64(x)];
+        return acc;
+    }
+    return h_diag_tab(s.Hd, s.X, s.J, s.N, a, b);
 }
 
 // <D2|H|D1> for D1 != D2 by excitation level (zero beyond doubles).

@@ -106,7 +106,7 @@ struct fciqmc_system {
     double e_core = 0.0;
     bool onsite = false;
     Arena arena;
-    double *h1 = nullptr, *eri = nullptr, *J = nullptr, *K = nullptr, *X = nullptr, *U = nullptr;
+    double *h1 = nullptr, *eri = nullptr, *J = nullptr, *K = nullptr, *X = nullptr, *U = nullptr, *Hd = nullptr;
     int *deg = nullptr, *nbr = nullptr, *pair_of = nullptr;
     bool pchb = false;
     double *hb_w_opp = nullptr, *hb_p_opp = nullptr, *hb_s_opp = nullptr;
@@ -119,7 +119,7 @@ struct fciqmc_system {
         SysView v{};
         v.N = N; v.na = na; v.nb = nb; v.n = na + nb;
         v.onsite = onsite ? 1 : 0;
-        v.h1 = h1; v.eri = eri; v.J = J; v.K = K; v.X = X; v.U = U;
+        v.h1 = h1; v.eri = eri; v.J = J; v.K = K; v.X = X; v.U = U; v.Hd = Hd;
         v.deg = deg; v.nbr = nbr;
         v.hb_w_opp = hb_w_opp; v.hb_p_opp = hb_p_opp; v.hb_a_opp = hb_a_opp; v.hb_s_opp = hb_s_opp;
         v.hb_w_same = hb_w_same; v.hb_p_same = hb_p_same; v.hb_a_same = hb_a_same; v.hb_s_same = hb_s_same;
@@ -640,6 +640,7 @@ int fciqmc_load_integrals(int n_orb, int n_alpha, int n_beta, double e_core, con
     CHECK(dalloc(s->arena, &s->J, (size_t)N * N));
     CHECK(dalloc(s->arena, &s->K, (size_t)N * N));
     CHECK(dalloc(s->arena, &s->X, (size_t)N * N));
+    CHECK(dalloc(s->arena, &s->Hd, (size_t)N));
     CHECK(dalloc(s->arena, &s->U, (size_t)N));
     CHECK(dalloc(s->arena, &s->deg, (size_t)N));
     CHECK(dalloc(s->arena, &s->nbr, (size_t)N * N));
@@ -659,7 +660,7 @@ int fciqmc_load_integrals(int n_orb, int n_alpha, int n_beta, double e_core, con
         for (int B = A + 1; B < N; ++B, ++c) po[c] = A * 64 + B;
     HIP_OK(hipMemcpy(s->pair_of, po.data(), sizeof(int) * po.size(), hipMemcpyHostToDevice));
     SysView v = s->view();
-    hipLaunchKernelGGL(k_build_jk, dim3((N * N + 255) / 256), dim3(256), 0, 0, v, s->J, s->K, s->X, s->U);
+    hipLaunchKernelGGL(k_build_jk, dim3((N * N + 255) / 256), dim3(256), 0, 0, v, s->J, s->K, s->X, s->U, s->Hd);
     HIP_OK(hipGetLastError());
     HIP_OK(hipDeviceSynchronize());
     *out = s.release();

@@ -288,11 +288,20 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const Rec<W, V>* __restric
 // ---------------------------------------------------------------------------
 // LDS hash table of one bucket.
 // ---------------------------------------------------------------------------
-template <int W, class V> struct Lds {
+template <int W, class V> struct LdsTable {
     uint64_t key0[kSlots];
     uint64_t key1[W == 2 ? kSlots : 1];
     V val[kSlots];
     int32_t idx[kSlots];   // entry index in the input store, -1 for a new determinant
+};
+
+template <int W, class V> struct Lds {
+    union {
+        LdsTable<W, V> t;
+        // after compaction: h_pp, the same-spin pair term X and J staged for
+        // the diagonals of new determinants
+        double diag_tabs[sizeof(LdsTable<W, V>) / sizeof(double)];
+    };
     int32_t fresh[kFresh]; // new survivors awaiting their diagonal: slot | out position << 11
     int nfresh;
     int64_t sh64[8];
@@ -313,19 +322,19 @@ __device__ __forceinline__ int lds_find(Lds<W, V>& L, const Key<W>& key, uint64_
     int probes = 0;
     int spins = 0;
     while (true) {
-        uint64_t w0 = lds_load<W>(&L.key0[s]);
+        uint64_t w0 = lds_load<W>(&L.t.key0[s]);
         if (w0 == kEmpty) {
             if (!insert) return -1;
             if constexpr (W == 1) {
-                const uint64_t old = atomicCAS((unsigned long long*)&L.key0[s], kEmpty, key.w[0]);
+                const uint64_t old = atomicCAS((unsigned long long*)&L.t.key0[s], kEmpty, key.w[0]);
                 if (old == kEmpty || old == key.w[0]) return s;
                 w0 = old;
             } else {
-                const uint64_t old = atomicCAS((unsigned long long*)&L.key0[s], kEmpty, kLocked);
+                const uint64_t old = atomicCAS((unsigned long long*)&L.t.key0[s], kEmpty, kLocked);
                 if (old == kEmpty) {
-                    __hip_atomic_store(&L.key1[s], key.w[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_store(&L.t.key1[s], key.w[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                    __hip_atomic_store(&L.key0[s], key.w[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_store(&L.t.key0[s], key.w[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     return s;
                 }
                 w0 = old;
@@ -340,7 +349,7 @@ __device__ __forceinline__ int lds_find(Lds<W, V>& L, const Key<W>& key, uint64_
             }
             if (w0 == key.w[0]) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                if (lds_load<W>(&L.key1[s]) == key.w[1]) return s;
+                if (lds_load<W>(&L.t.key1[s]) == key.w[1]) return s;
             }
         } else {
             if (w0 == key.w[0]) return s;
@@ -462,10 +471,10 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
         while (nslots < want && nslots < kSlots) nslots <<= 1;
         const uint64_t mask = (uint64_t)(nslots - 1);
         for (int i = threadIdx.x; i < nslots; i += kThreads) {
-            L.key0[i] = kEmpty;
-            if constexpr (W == 2) L.key1[i] = kEmpty;
-            L.val[i] = (V)0;
-            L.idx[i] = -1;
+            L.t.key0[i] = kEmpty;
+            if constexpr (W == 2) L.t.key1[i] = kEmpty;
+            L.t.val[i] = (V)0;
+            L.t.idx[i] = -1;
         }
         if (threadIdx.x == 0) L.nfresh = 0;
         __syncthreads();
@@ -499,8 +508,8 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
             }
             const int s = lds_find<W, V>(L, key, key_hash<W>(key), mask, true);
             if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); continue; }
-            L.val[s] = post;
-            L.idx[s] = e;
+            L.t.val[s] = post;
+            L.t.idx[s] = e;
         }
         __syncthreads();
         // (c) annihilation: a target occupied at tau takes every contribution;
@@ -518,7 +527,7 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
             const int s = lds_find<W, V>(L, key, key_hash<W>(key), mask, init);
             if (s == -1) continue;
             if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); continue; }
-            if (init || L.idx[s] >= 0) lds_add<V>(&L.val[s], x.v);
+            if (init || L.t.idx[s] >= 0) lds_add<V>(&L.t.val[s], x.v);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -544,13 +553,13 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
         bool over = false;
         for (int p0 = 0; p0 < nslots; p0 += kThreads) {
             const int s = p0 + threadIdx.x;
-            const uint64_t k0 = L.key0[s];
+            const uint64_t k0 = L.t.key0[s];
             V v = (V)0;
             Key<W> key;
             key.w[0] = k0;
-            if constexpr (W == 2) key.w[1] = L.key1[s];
+            if constexpr (W == 2) key.w[1] = L.t.key1[s];
             if (k0 != kEmpty) {
-                v = L.val[s];
+                v = L.t.val[s];
                 if constexpr (!kInt) {
                     const double av = fabs((double)v);
                     if (!sc.import_mode && v != 0.0 && av < sc.c_min) {
@@ -574,7 +583,7 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
                 store_key<W>(out.keys + o * W, key);
                 out.vals[o] = v;
                 out.mpre[o] = (int32_t)mp;
-                const int oi = L.idx[s];
+                const int oi = L.t.idx[s];
                 const uint64_t ka = key_alpha<W>(key), kb = key_beta<W>(key);
                 if (oi >= 0) {
                     out.diag[o] = in.diag[eb + oi];
@@ -607,16 +616,42 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
         en = wave_sum(en);
         if (lane_id() == 0) { L.shd[threadIdx.x >> 6] = nw; L.shd[4 + (threadIdx.x >> 6)] = en; }
         __syncthreads();
-        // diagonals of the new determinants, spread over the workgroup
+        // diagonals of the new determinants, spread over the workgroup; the
+        // keys go to registers, then the dead hash table holds h_pp, X and J
         const int nf = min(L.nfresh, kFresh);
-        for (int f = threadIdx.x; f < nf; f += kThreads) {
-            const int s = L.fresh[f] & 2047;
-            const int64_t o = eb + (L.fresh[f] >> 11);
-            Key<W> key;
-            key.w[0] = L.key0[s];
-            if constexpr (W == 2) key.w[1] = L.key1[s];
-            const double hd = h_diag(sys, key_alpha<W>(key), key_beta<W>(key));
-            out.diag[o] = hd - sc.h00;
+        Key<W> fk[kFresh / kThreads];
+        int64_t fo[kFresh / kThreads];
+#pragma unroll
+        for (int i = 0; i < kFresh / kThreads; ++i) {
+            const int f = threadIdx.x + i * kThreads;
+            fo[i] = -1;
+            if (f < nf) {
+                const int s = L.fresh[f] & 2047;
+                fo[i] = eb + (L.fresh[f] >> 11);
+                fk[i].w[0] = L.t.key0[s];
+                if constexpr (W == 2) fk[i].w[1] = L.t.key1[s];
+            }
+        }
+        const int N = sys.N;
+        const bool stage = nf > 0 && !sys.onsite &&
+                           (int64_t)N + 2 * (int64_t)N * N <= (int64_t)(sizeof(L.diag_tabs) / sizeof(double));
+        if (stage) {
+            __syncthreads();
+            double* hd = L.diag_tabs;
+            double* xt = hd + N;
+            double* jt = xt + N * N;
+            for (int i = threadIdx.x; i < N * N; i += kThreads) { xt[i] = sys.X[i]; jt[i] = sys.J[i]; }
+            for (int i = threadIdx.x; i < N; i += kThreads) hd[i] = sys.Hd[i];
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < kFresh / kThreads; ++i) {
+            if (fo[i] < 0) continue;
+            const uint64_t ka = key_alpha<W>(fk[i]), kb = key_beta<W>(fk[i]);
+            double h;
+            if (stage) h = h_diag_tab(L.diag_tabs, L.diag_tabs + N, L.diag_tabs + N + N * N, N, ka, kb);
+            else h = h_diag(sys, ka, kb);
+            out.diag[fo[i]] = h - sc.h00;
         }
         if (threadIdx.x == 0) {
             nw_b[b] = ((L.shd[0] + L.shd[1]) + L.shd[2]) + L.shd[3];
@@ -689,7 +724,7 @@ __global__ void k_hij(SysView sys, const uint64_t* __restrict__ di, const uint64
 
 // J/K/U tables copied out of the packed integrals, and the same-spin pair
 // term X = J - K of the diagonal (one rounding, as in the diagonal's sum).
-__global__ void k_build_jk(SysView sys, double* J, double* K, double* X, double* U) {
+__global__ void k_build_jk(SysView sys, double* J, double* K, double* X, double* U, double* Hd) {
     const int N = sys.N;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N * N; i += gridDim.x * blockDim.x) {
         const int p = i / N, q = i % N;
@@ -698,7 +733,7 @@ __global__ void k_build_jk(SysView sys, double* J, double* K, double* X, double*
         J[i] = j;
         K[i] = k;
         X[i] = j - k;
-        if (p == q) U[p] = eri(sys, p, p, p, p);
+        if (p == q) { U[p] = eri(sys, p, p, p, p); Hd[p] = sys.h1[i]; }
     }
 }
 
