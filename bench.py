@@ -41,6 +41,14 @@ def workload(name):
                 "excitation_generator": "lattice", "walkers": "integer", "det_bits": 64,
                 "shift_damping": 0.3}
         return s, p, desc
+    if name == "mol40":
+        s = inputs.molecule_40o26e()
+        p = dict(tau=0.0012, walker_target=1e8, initiator_na=3.0, mode=F.MODE_REAL, c_min=1.0,
+                 excitgen=F.GEN_PCHB, seed=1, shift_damping=0.3, n_initial=1000.0)
+        desc = {"workload": "synthetic_molecule_26e40o_damped_rank40", "walkers_target": 1e8,
+                "initiator_na": 3, "tau": 0.0012, "excitation_generator": "pchb",
+                "walkers": "real", "c_min": 1.0, "det_bits": 128, "shift_damping": 0.3}
+        return s, p, desc
     if name == "mol8":
         s = inputs.molecule_8o8e()
         p = dict(tau=0.01, walker_target=1e4, seed=1)
@@ -62,6 +70,66 @@ def algorithmic_bytes(kernel, d_in, d_out, recs, words, vbytes):
     return 0
 
 
+def measure(F, np, torch, stream, name, steps, warmup):
+    """Grow, settle and time one workload; returns the run and its figures."""
+    s, pd, desc = workload(name)
+    sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
+    run = F.fciqmc_init(sysd, F.fciqmc_params_default(**pd), stream=stream)
+    # initialisation: grow until the shift varies (not timed)
+    t0 = time.perf_counter()
+    grown = 0
+    while grown < 5000:
+        st = F.fciqmc_step(run, 10)
+        grown += 10
+        if st[-1]["vary_shift"]:
+            break
+    log(f"[{name}] grown {grown} steps in {time.perf_counter() - t0:.2f}s: N_w={st[-1]['nw']:.4g} "
+        f"dets={st[-1]['ndets']} S={st[-1]['shift']:.4f}")
+    if warmup:
+        st = F.fciqmc_step(run, warmup)
+        log(f"[{name}] warmup {warmup}: N_w={st[-1]['nw']:.4g} dets={st[-1]['ndets']} "
+            f"S={st[-1]['shift']:.4f} E_proj={st[-1]['e_proj']:.5f}")
+    F.fciqmc_profile(run, True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = F.fciqmc_step(run, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    ms, nsteps, layout = F.fciqmc_profile(run, False)
+    attempts = sum(x["attempts"] for x in st)
+    spawns = sum(x["spawns"] for x in st)
+    log(f"[{name}] timed {steps} steps in {wall:.4f}s: {attempts / wall:.4e} attempts/s, "
+        f"{1e3 * wall / steps:.4f} ms/step; kernels (ms total): "
+        + ", ".join(f"{k}={v:.2f}" for k, v in ms.items()))
+    # roofline of the dominant kernel from the live event timings
+    words = 1 if s.n_orb <= 32 else 2
+    vbytes = 4 if pd.get("mode", F.MODE_INTEGER) == F.MODE_INTEGER else 8
+    dets = [x["ndets"] for x in st]
+    d_in = float(np.mean([st[0]["ndets"]] + dets[:-1]))
+    d_out = float(np.mean(dets))
+    recs = spawns / len(st)
+    kern = {k: {"ms_per_launch": v / nsteps,
+                "algorithmic_bytes": algorithmic_bytes(k, d_in, d_out, recs, words, vbytes)}
+            for k, v in ms.items()}
+    for k in kern:
+        a = kern[k]["algorithmic_bytes"]
+        kern[k]["achieved_GBps"] = a / (kern[k]["ms_per_launch"] * 1e-3) / 1e9 if a else None
+    dom = max(("spawn", "annihilate"), key=lambda k: ms[k])
+    roof = roofline(kern, dom)
+    desc = dict(desc, dets_mean=d_out, spawns_per_step=recs, attempts_per_step=attempts / len(st),
+                buckets=layout["buckets"], ms_per_step=1e3 * wall / steps,
+                attempts_per_s=attempts / wall)
+    return s, pd, desc, run, sysd, st, wall, ms, nsteps, layout, kern, roof
+
+
+def roofline(kern, k):
+    ab = kern[k]["algorithmic_bytes"]
+    achieved = ab / (kern[k]["ms_per_launch"] * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": k, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "algorithmic_bytes_per_launch": ab, "ms_per_launch": kern[k]["ms_per_launch"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +138,10 @@ def main():
     ap.add_argument("--workload", default="hubbard4x4")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--second", default="mol40",
+                    help="second workload measured after the first ('' to skip)")
+    ap.add_argument("--second-steps", type=int, default=60)
+    ap.add_argument("--second-warmup", type=int, default=400)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -82,57 +154,14 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    s, pd, desc = workload(args.workload)
-    sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
-    run = F.fciqmc_init(sysd, F.fciqmc_params_default(**pd), stream=stream)
-
-    # initialisation: grow until the shift varies (not timed)
-    t0 = time.perf_counter()
-    grown = 0
-    while grown < 5000:
-        st = F.fciqmc_step(run, 10)
-        grown += 10
-        if st[-1]["vary_shift"]:
-            break
-    log(f"grown {grown} steps in {time.perf_counter() - t0:.2f}s: N_w={st[-1]['nw']:.0f} "
-        f"dets={st[-1]['ndets']} S={st[-1]['shift']:.4f}")
-    if args.warmup:
-        st = F.fciqmc_step(run, args.warmup)
-        log(f"warmup {args.warmup}: N_w={st[-1]['nw']:.0f} dets={st[-1]['ndets']} "
-            f"S={st[-1]['shift']:.4f} E_proj={st[-1]['e_proj']:.5f}")
-
-    F.fciqmc_profile(run, True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st = F.fciqmc_step(run, args.steps)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    wall = t2 - t1
-    ms, nsteps, layout = F.fciqmc_profile(run, False)
+    s, pd, desc, run, sysd, st, wall, ms, nsteps, layout, kern, roof = measure(
+        F, np, torch, stream, args.workload, args.steps, args.warmup)
     attempts = sum(x["attempts"] for x in st)
     spawns = sum(x["spawns"] for x in st)
-    dets = [x["ndets"] for x in st]
     value = attempts / wall
-    log(f"timed {args.steps} steps in {wall:.4f}s: {value:.4e} attempts/s, "
-        f"{1e3 * wall / args.steps:.4f} ms/step; kernels (ms total): "
-        + ", ".join(f"{k}={v:.2f}" for k, v in ms.items()))
-
-    # roofline of the dominant kernel from the live event timings
     words = 1 if s.n_orb <= 32 else 2
-    vbytes = 4
-    d_in = float(np.mean([st[0]["ndets"]] + dets[:-1]))
-    d_out = float(np.mean(dets))
+    d_out = float(np.mean([x["ndets"] for x in st]))
     recs = spawns / len(st)
-    dom = max(("spawn", "annihilate"), key=lambda k: ms[k])
-    per_launch_ms = ms[dom] / nsteps
-    ab = algorithmic_bytes(dom, d_in, d_out, recs, words, vbytes)
-    achieved = ab / (per_launch_ms * 1e-3) / 1e9
-    kern = {k: {"ms_per_launch": v / nsteps,
-                "algorithmic_bytes": algorithmic_bytes(k, d_in, d_out, recs, words, vbytes)}
-            for k, v in ms.items()}
-    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "algorithmic_bytes_per_launch": ab, "ms_per_launch": per_launch_ms}
 
     cpu = None
     if not args.no_cpu:
@@ -161,6 +190,19 @@ def main():
                          f"({len(v)} determinants), {cwall:.1f}s on one host core"}
         log(f"cpu oracle: {osteps} steps, {oatt / cwall:.4e} attempts/s")
 
+    second = None
+    if args.second:
+        F.fciqmc_free_run(run)
+        F.fciqmc_free_system(sysd)
+        run = sysd = None
+        _, _, desc2, run2, sys2, _, wall2, _, _, _, kern2, _ = measure(
+            F, np, torch, stream, args.second, args.second_steps, args.second_warmup)
+        second = {"config": desc2, "value": desc2["attempts_per_s"], "unit": "attempts/s",
+                  "ms_per_step": desc2["ms_per_step"], "kernels": kern2,
+                  "roofline_annihilate": roofline(kern2, "annihilate")}
+        F.fciqmc_free_run(run2)
+        F.fciqmc_free_system(sys2)
+
     out = {
         "metric": "spawn attempts/s (spawn+annihilate+death)",
         "value": value,
@@ -174,15 +216,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": dict(desc, dets_mean=d_out, spawns_per_step=recs,
-                       attempts_per_step=attempts / len(st), buckets=layout["buckets"]),
+        "config": desc,
         "kernels": kern,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "second_workload": second,
     }
     print(json.dumps(out), flush=True)
-    F.fciqmc_free_run(run)
-    F.fciqmc_free_system(sysd)
+    if run is not None:
+        F.fciqmc_free_run(run)
+        F.fciqmc_free_system(sysd)
 
 
 if __name__ == "__main__":

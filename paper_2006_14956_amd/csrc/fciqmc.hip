@@ -213,6 +213,7 @@ template <int W, class V> struct Engine : EngineBase {
     int64_t* rel = nullptr;     // next step's sub-slab offsets within their bucket, B*kSub
     int64_t* need_b = nullptr;  // next step's slab size per bucket, B
     int64_t* recs_b = nullptr;  // records per bucket this step, B
+    PostPart* part = nullptr;   // partial totals of the multi-workgroup post work
     double *nw_b = nullptr, *en_b = nullptr;
     Ctl* ctl = nullptr;
     Ctl* hctl = nullptr;  // pinned
@@ -288,6 +289,7 @@ template <int W, class V> struct Engine : EngineBase {
         CHECK(dalloc(arena, &rel, (size_t)B * kSub));
         CHECK(dalloc(arena, &need_b, (size_t)B));
         CHECK(dalloc(arena, &recs_b, (size_t)B));
+        CHECK(dalloc(arena, &part, (size_t)(B + kPostSpan - 1) / kPostSpan));
         CHECK(dalloc(arena, &soff, (size_t)B * kSub + 1));
         HIP_OK(hipMemsetAsync(scount, 0, sizeof(int32_t) * B * kSub, stream));
         HIP_OK(hipMemsetAsync(soff, 0, sizeof(int64_t) * (B * kSub + 1), stream));
@@ -299,8 +301,8 @@ template <int W, class V> struct Engine : EngineBase {
         free_store(st[0]);
         free_store(st[1]);
         arena.release(scount); arena.release(soff);
-        arena.release(rel); arena.release(need_b); arena.release(recs_b);
-        rel = nullptr; need_b = nullptr; recs_b = nullptr;
+        arena.release(rel); arena.release(need_b); arena.release(recs_b); arena.release(part);
+        rel = nullptr; need_b = nullptr; recs_b = nullptr; part = nullptr;
         arena.release(nw_b); arena.release(en_b);
         scount = nullptr; soff = nullptr; nw_b = en_b = nullptr;
     }
@@ -357,8 +359,17 @@ template <int W, class V> struct Engine : EngineBase {
             hipLaunchKernelGGL(k_import_slabs, dim3((B + 255) / 256), dim3(256), 0, stream, scount, B, rel,
                                need_b);
         }
-        hipLaunchKernelGGL(k_post, dim3(1), dim3(kPostThreads), 0, stream, out.batt, out.count, nw_b, en_b,
-                           B, out.aoff, rel, need_b, recs_b, soff, ctl);
+        if (B <= 4 * kPostSpan) {
+            hipLaunchKernelGGL(k_post, dim3(1), dim3(kPostThreads), 0, stream, out.batt, out.count, nw_b, en_b,
+                               B, out.aoff, rel, need_b, recs_b, soff, ctl);
+        } else {
+            const int G = (B + kPostSpan - 1) / kPostSpan;
+            hipLaunchKernelGGL(k_post_a, dim3(G), dim3(256), 0, stream, out.batt, out.count, nw_b, en_b, need_b,
+                               recs_b, B, part, ctl);
+            hipLaunchKernelGGL(k_post_b, dim3(1), dim3(256), 0, stream, part, G, B, out.aoff, soff, ctl);
+            hipLaunchKernelGGL(k_post_c, dim3(G), dim3(256), 0, stream, out.batt, rel, need_b, B, part, out.aoff,
+                               soff, ctl);
+        }
         mark(3);
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));

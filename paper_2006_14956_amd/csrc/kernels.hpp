@@ -664,6 +664,136 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
 }
 
 
+// Post work for many buckets, in three launches.  Phase a: workgroup g
+// reduces buckets [g*kPostSpan, (g+1)*kPostSpan) to partial totals.  Phase b
+// (one workgroup): prefix of the partials and the global sums.  Phase c:
+// workgroup g writes the attempt and sub-slab offsets of its buckets.
+constexpr int kPostSpan = 1024;
+
+struct PostPart {
+    int64_t att, need, cnt, rec, mx;
+    double nw, en;
+};
+
+__global__ __launch_bounds__(256) void k_post_a(const int64_t* __restrict__ batt,
+                                                const int32_t* __restrict__ count,
+                                                const double* __restrict__ nw_b,
+                                                const double* __restrict__ en_b,
+                                                const int64_t* __restrict__ need_b,
+                                                const int64_t* __restrict__ recs_b, int B,
+                                                PostPart* __restrict__ part, const Ctl* ctl) {
+    if (ctl->flags) return;
+    __shared__ int64_t sh[4];
+    __shared__ double shd[8];
+    __shared__ int64_t shm[4];
+    const int g0 = blockIdx.x * kPostSpan;
+    const int per = kPostSpan / 256;
+    const int b0 = g0 + threadIdx.x * per, b1 = min(B, b0 + per);
+    int64_t la = 0, ln = 0, c = 0, r = 0, mx = 0;
+    double nw = 0.0, en = 0.0;
+    for (int b = b0; b < b1; ++b) {
+        la += batt[b];
+        ln += need_b[b];
+        const int64_t cb = count[b];
+        c += cb;
+        r += recs_b[b];
+        mx = max(mx, cb);
+        nw = nw + nw_b[b];
+        en = en + en_b[b];
+    }
+    int64_t ta, tn, tcr;
+    (void)block_excl_scan<256, int64_t>(la, ta, sh);
+    (void)block_excl_scan<256, int64_t>(ln, tn, sh);
+    (void)block_excl_scan<256, int64_t>((c << 32) | r, tcr, sh);
+    nw = wave_sum(nw);
+    en = wave_sum(en);
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, (int64_t)__shfl_xor(mx, o));
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) { shd[w] = nw; shd[4 + w] = en; shm[w] = mx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        PostPart p;
+        p.att = ta;
+        p.need = tn;
+        p.cnt = tcr >> 32;
+        p.rec = tcr & 0xFFFFFFFFLL;
+        p.mx = max(max(shm[0], shm[1]), max(shm[2], shm[3]));
+        p.nw = ((shd[0] + shd[1]) + shd[2]) + shd[3];
+        p.en = ((shd[4] + shd[5]) + shd[6]) + shd[7];
+        part[blockIdx.x] = p;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_post_b(PostPart* __restrict__ part, int G, int B,
+                                                int64_t* __restrict__ aoff, int64_t* __restrict__ soff,
+                                                Ctl* ctl) {
+    if (ctl->flags) return;
+    __shared__ int64_t sh[4];
+    // exclusive prefix of the partials (attempts, slab sizes), in place
+    const int per = (G + 255) / 256;
+    const int g0 = threadIdx.x * per, g1 = min(G, g0 + per);
+    int64_t la = 0, ln = 0;
+    for (int g = g0; g < g1; ++g) { la += part[g].att; ln += part[g].need; }
+    int64_t ta, tn;
+    int64_t ra = block_excl_scan<256, int64_t>(la, ta, sh);
+    int64_t rn = block_excl_scan<256, int64_t>(ln, tn, sh);
+    for (int g = g0; g < g1; ++g) {
+        const int64_t a = part[g].att, n = part[g].need;
+        part[g].att = ra;
+        part[g].need = rn;
+        ra += a;
+        rn += n;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double nw = 0.0, en = 0.0;
+        int64_t c = 0, r = 0, m = 0;
+        for (int g = 0; g < G; ++g) {
+            nw = nw + part[g].nw;
+            en = en + part[g].en;
+            c += part[g].cnt;
+            r += part[g].rec;
+            m = max(m, part[g].mx);
+        }
+        aoff[B] = ta;
+        soff[(int64_t)B * kSub] = tn;
+        ctl->nw = nw;
+        ctl->enum_ = en;
+        ctl->ndets = c;
+        ctl->attempts = ta;
+        ctl->nrec_out = r;
+        ctl->max_count = m;
+        ctl->nref_out = ctl->nref;
+        ctl->rec_need = tn;
+        ctl->nrec = 0;
+        ctl->nref = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_post_c(const int64_t* __restrict__ batt,
+                                                const int64_t* __restrict__ rel,
+                                                const int64_t* __restrict__ need_b, int B,
+                                                const PostPart* __restrict__ part,
+                                                int64_t* __restrict__ aoff, int64_t* __restrict__ soff,
+                                                const Ctl* ctl) {
+    if (ctl->flags) return;
+    __shared__ int64_t sh[4];
+    const int g0 = blockIdx.x * kPostSpan;
+    const int per = kPostSpan / 256;
+    const int b0 = g0 + threadIdx.x * per, b1 = min(B, b0 + per);
+    int64_t la = 0, ln = 0;
+    for (int b = b0; b < b1; ++b) { la += batt[b]; ln += need_b[b]; }
+    int64_t ta, tn;
+    int64_t ra = part[blockIdx.x].att + block_excl_scan<256, int64_t>(la, ta, sh);
+    int64_t rn = part[blockIdx.x].need + block_excl_scan<256, int64_t>(ln, tn, sh);
+    for (int b = b0; b < b1; ++b) {
+        aoff[b] = ra;
+        ra += batt[b];
+        for (int j = 0; j < kSub; ++j) soff[(int64_t)b * kSub + j] = rn + rel[(int64_t)b * kSub + j];
+        rn += need_b[b];
+    }
+}
+
 // After an import the per-bucket kernel leaves the counters alone; size the
 // next step's slabs from the imported counts and restart the counters.
 __global__ void k_import_slabs(int32_t* __restrict__ scount, int B, int64_t* __restrict__ rel,

@@ -216,3 +216,18 @@ def test_hubbard_full_size_one_step():
     assert_same_walkers(run, orun)
     F.fciqmc_free_run(run)
     F.fciqmc_free_system(sysd)
+
+
+@pytest.mark.parametrize("buckets_log2", [3, 13])
+def test_trajectory_independent_of_bucket_count(buckets_log2):
+    """The walker store's partition (8 buckets, or 8192 buckets which also
+    takes the multi-workgroup post path) does not change the trajectory."""
+    s = inputs.molecule_8o8e()
+    sysd, run, orun = make_pair(s, tau=0.01, target=1e4, seed=7, buckets_log2=buckets_log2)
+    g = F.fciqmc_step(run, 300)
+    o = orun.step(300)
+    for gg, oo in zip(g, o):
+        assert_same_stats(gg, oo)
+    assert_same_walkers(run, orun)
+    F.fciqmc_free_run(run)
+    F.fciqmc_free_system(sysd)
