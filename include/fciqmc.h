@@ -50,6 +50,7 @@ extern "C" {
 
 typedef struct fciqmc_system fciqmc_system;
 typedef struct fciqmc_run fciqmc_run;
+typedef struct fciqmc_batch fciqmc_batch;
 
 /* Parameters of one walker population.  fciqmc_params_default() fills every
  * field; callers then override what they need. */
@@ -166,6 +167,58 @@ int64_t fciqmc_run_device_bytes(const fciqmc_run *run);
  * layout: host, 2 entries receive the bucket count of the walker store and
  * the spawn-record capacity (either output may be NULL). */
 int fciqmc_profile(fciqmc_run *run, int enable, double *ms, int64_t *steps, int64_t *layout);
+
+/* ---- Batches: many populations advanced by shared launches ------------
+ *
+ * A batch steps its member runs together: per step it issues one spawn
+ * launch per excitation generator, one annihilation launch and one post
+ * launch for all members of the same determinant width and value type, and
+ * a single read-back and synchronisation for the whole batch.  The members
+ * may hold different systems (orbital counts, integrals), parameters and
+ * population sizes.  Each member's arithmetic is exactly that of stepping
+ * it alone (Eq. fciqmc_dyn applied per population; the populations never
+ * interact), so in integer mode every member's trajectory is bit-identical
+ * to its solo trajectory; a member whose step overflows a capacity replays
+ * that step alone before the batch step returns.
+ *
+ * While a run is a member, its own stream is not used (the batch's is),
+ * fciqmc_step on it returns ESTATE, and fciqmc_free_run removes it first.
+ * fciqmc_energy, get/set_walkers and the checkpoint calls stay valid. */
+
+/* stream: as for fciqmc_init (NULL = library-owned stream). */
+int fciqmc_batch_create(void *stream, fciqmc_batch **out);
+/* Add a run (EINVAL if it already belongs to a batch); remove it again
+ * (EINVAL if it is not a member).  Members keep their order of addition. */
+int fciqmc_batch_add(fciqmc_batch *batch, fciqmc_run *run);
+int fciqmc_batch_remove(fciqmc_batch *batch, fciqmc_run *run);
+int fciqmc_batch_size(const fciqmc_batch *batch);
+/* Advance every member n_steps.  stats: host array of n_steps * size
+ * entries or NULL; entry [s * size + m] is member m after step s.  On an
+ * error the failing member has not recorded that step; the others have. */
+int fciqmc_batch_step(fciqmc_batch *batch, int n_steps, fciqmc_step_stats *stats);
+
+/* Autotuner report (see fciqmc_batch_tune). */
+typedef struct fciqmc_tune_report {
+    int dets_per_bucket;   /* chosen walker-store occupancy; 0 = partition left as found    */
+    int grid_spawn;        /* chosen spawn workgroups per launch; 0 = one per 256 attempts */
+    int grid_annihilate;   /* chosen annihilation workgroups; 0 = one per bucket            */
+    int trials;            /* configurations timed                                          */
+    int64_t steps;         /* steps the tuning advanced every member                        */
+    double rate_initial;   /* spawn attempts/s of the configuration found                   */
+    double rate_best;      /* spawn attempts/s of the configuration chosen                  */
+} fciqmc_tune_report;
+
+/* Time trial_steps real steps under each candidate launch shape -- walker
+ * store occupancy (determinants per bucket, which sets each member's bucket
+ * count), spawn grid and annihilation grid, one coordinate at a time -- and
+ * keep the fastest.  None of these changes any trajectory; the tuning steps
+ * are ordinary steps of every member.  out: host, may be NULL. */
+int fciqmc_batch_tune(fciqmc_batch *batch, int trial_steps, fciqmc_tune_report *out);
+/* Per-kernel timing of the batch's launches, as fciqmc_profile (ms: spawn,
+ * annihilation, post launches of all members; *steps: batch steps timed). */
+int fciqmc_batch_profile(fciqmc_batch *batch, int enable, double *ms, int64_t *steps);
+/* Remove every member (they keep their state) and release the batch. */
+void fciqmc_batch_free(fciqmc_batch *batch);
 
 void fciqmc_free_run(fciqmc_run *run);
 void fciqmc_free_system(fciqmc_system *sys);

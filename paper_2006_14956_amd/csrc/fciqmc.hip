@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -179,7 +180,16 @@ struct EngineBase {
     virtual void kernel_times(double* ms, int64_t* launches) const = 0;
     virtual int64_t buckets() const = 0;
     virtual int64_t spawn_capacity() const = 0;
+    virtual void set_stream(hipStream_t s) = 0;
+    virtual hipStream_t get_stream() const = 0;
+    virtual int kind() const = 0;        // determinant width and value type, see kind_of
+    virtual int64_t ndets() const = 0;   // occupied determinants after the last step
+    virtual int rebucket(int buckets) = 0;
 };
+
+// Engines of one kind share batched launches: 0 = (1 word, int32),
+// 1 = (1 word, FP64), 2 = (2 words, int32), 3 = (2 words, FP64).
+template <int W, class V> constexpr int kind_of() { return (W - 1) * 2 + (sizeof(V) == 8 ? 1 : 0); }
 
 // kernels of one step, in launch order: spawn, annihilation, post
 constexpr int kKernels = 3;
@@ -512,45 +522,36 @@ template <int W, class V> struct Engine : EngineBase {
         return 0;
     }
 
-    int step_once(int64_t t, double S, Ctl& out, int& retries, int64_t& attempts) override {
-        retries = 0;
-        attempts = att_next;
-        if (dirty) {
+    // Outcome of a launched step whose scalars are in hctl: done, or the
+    // capacities fixed for a replay of the same step, or an error.
+    int settle(int64_t t, int& retries, bool& done) {
+        const unsigned flags = hctl->flags;
+        done = flags == 0;
+        if (done) return 0;
+        dirty = true;
+        if (flags & kFlagBloom)
+            return fail(FCIQMC_EOVERFLOW, "a spawn exceeded 2^30 walkers at step %lld (time step too large)",
+                        (long long)t);
+        if (flags & kFlagPop)
+            return fail(FCIQMC_EOVERFLOW, "a walker number exceeded the int32 range at step %lld", (long long)t);
+        if (flags & kFlagSpin) return fail(FCIQMC_EDEVICE, "LDS hash claim did not complete");
+        ++retries;
+        if (retries > 24) return fail(FCIQMC_EOVERFLOW, "step %lld did not fit after 24 capacity growths", (long long)t);
+        if (flags & (kFlagTable | kFlagStore)) {
+            CHECK(grow_buckets());
+            dirty = false;
+            return 0;
+        }
+        if (flags & kFlagSpawnCap) {
             CHECK(recover());
             dirty = false;
+            return 0;
         }
-        for (;;) {
-            const StepScalars sc = scalars(t, S, 0);
-            mark(0);
-            CHECK(launch_spawn(sc));
-            mark(1);
-            CHECK(merge_and_post(sc));
-            const unsigned flags = hctl->flags;
-            if (flags == 0) {
-                CHECK(collect());
-                break;
-            }
-            dirty = true;
-            if (flags & kFlagBloom)
-                return fail(FCIQMC_EOVERFLOW, "a spawn exceeded 2^30 walkers at step %lld (time step too large)",
-                            (long long)t);
-            if (flags & kFlagPop)
-                return fail(FCIQMC_EOVERFLOW, "a walker number exceeded the int32 range at step %lld", (long long)t);
-            if (flags & kFlagSpin) return fail(FCIQMC_EDEVICE, "LDS hash claim did not complete");
-            ++retries;
-            if (retries > 24) return fail(FCIQMC_EOVERFLOW, "step %lld did not fit after 24 capacity growths", (long long)t);
-            if (flags & (kFlagTable | kFlagStore)) {
-                CHECK(grow_buckets());
-                dirty = false;
-                continue;
-            }
-            if (flags & kFlagSpawnCap) {
-                CHECK(recover());
-                dirty = false;
-                continue;
-            }
-            return fail(FCIQMC_EDEVICE, "device flags 0x%x", flags);
-        }
+        return fail(FCIQMC_EDEVICE, "device flags 0x%x", flags);
+    }
+
+    // Accept the step: swap the stores, take the next step's sizes.
+    int complete(Ctl& out) {
         cur = 1 - cur;
         att_next = hctl->attempts;
         rec_need = hctl->rec_need;
@@ -558,6 +559,73 @@ template <int W, class V> struct Engine : EngineBase {
         out = *hctl;
         out.nref = hctl->nref_out;
         return 0;
+    }
+
+    // Launch the step alone until it fits.
+    int run_alone(int64_t t, double S, int& retries) {
+        for (;;) {
+            const StepScalars sc = scalars(t, S, 0);
+            mark(0);
+            CHECK(launch_spawn(sc));
+            mark(1);
+            CHECK(merge_and_post(sc));
+            bool done = false;
+            CHECK(settle(t, retries, done));
+            if (done) return collect();
+        }
+    }
+
+    int step_once(int64_t t, double S, Ctl& out, int& retries, int64_t& attempts) override {
+        retries = 0;
+        attempts = att_next;
+        if (dirty) {
+            CHECK(recover());
+            dirty = false;
+        }
+        CHECK(run_alone(t, S, retries));
+        return complete(out);
+    }
+
+    // Batched stepping: the instance descriptor of step t and its spawn chunks.
+    int batch_prepare(int64_t t, double S, Inst<W, V>& d, int64_t& chunks) {
+        if (dirty) {
+            CHECK(recover());
+            dirty = false;
+        }
+        d.sys = sys->view();
+        d.in = st[cur];
+        d.out = st[1 - cur];
+        d.sc = scalars(t, S, 0);
+        d.rec2 = rec2; d.soff = soff; d.rel = rel; d.need_b = need_b; d.recs_b = recs_b;
+        d.scount = scount; d.nw_b = nw_b; d.en_b = en_b; d.ctl = ctl;
+        chunks = (att_next + kChunk - 1) / kChunk;
+        return 0;
+    }
+    // The batch's read-back of this instance; a flagged step is replayed alone.
+    int batch_finish(int64_t t, double S, const Ctl& c, Ctl& out, int& retries, int64_t& attempts) {
+        retries = 0;
+        attempts = att_next;
+        *hctl = c;
+        bool done = false;
+        CHECK(settle(t, retries, done));
+        if (!done) CHECK(run_alone(t, S, retries));
+        return complete(out);
+    }
+    void set_stream(hipStream_t s) override { stream = s; }
+    hipStream_t get_stream() const override { return stream; }
+    int kind() const override { return kind_of<W, V>(); }
+    int64_t ndets() const override { return hctl ? hctl->ndets : 0; }
+    int rebucket(int buckets) override {
+        if (buckets == B) return 0;
+        std::vector<uint64_t> ab;
+        std::vector<double> vals;
+        CHECK(get_walkers(ab, vals));
+        free_buckets();
+        B = buckets;
+        CHECK(alloc_buckets());
+        cur = 0;
+        dirty = false;
+        return import(ab.data(), vals.data(), (int64_t)vals.size());
     }
 };
 
@@ -579,11 +647,295 @@ struct fciqmc_run {
     double xi = 0.0;                // restoring strength of the shift update
     std::vector<double> nw_ring;    // N_w(t) of the last A+1 steps, indexed t mod (A+1)
     std::vector<fciqmc_step_stats> hist;
+    fciqmc_batch* batch = nullptr;  // set while the run steps inside a batch
+    int batch_slot = -1;            // its position among the batch's members
     ~fciqmc_run() {
         eng.reset();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
 };
+
+// Population control (Sec. I leaves the update open).  Reading: S stays 0
+// (relative to H_00) until N_w first reaches the target N_t.  At that step T
+// the shift is set from the measured growth rate,
+// S = -ln(N_w(T)/N_w(T-L))/(L dtau), L = min(A, steps since the population was
+// set).  From then on, every A steps,
+//   S <- S - zeta/(A dtau) ln(N_w(t)/N_w(t-A)) - xi/(A dtau) ln(N_w(t)/N_t),
+// the damped control of the original method plus the restoring term of
+// Yang, Pahl and Brand (J. Chem. Phys. 153, 174103 (2020)); xi = zeta^2/4 by
+// default.  An extinct population (N_w = 0) leaves S unchanged.
+static void shift_update(fciqmc_run* r, double nw) {
+    const int64_t T = r->t;
+    const int64_t A = (int64_t)r->p.shift_interval;
+    if (!r->vary) {
+        if (nw >= r->p.walker_target) {
+            r->vary = 1;
+            int64_t L = std::min<int64_t>(T - r->t_set, A);
+            if (L > 0) {
+                const double nw_prev = r->nw_ring[(size_t)((T - L) % (A + 1))];
+                const double c = 1.0 / ((double)L * r->p.tau);
+                const double ratio = nw / nw_prev;
+                const double l = std::log(ratio);
+                const double dS = c * l;
+                r->S = 0.0 - dS;
+            }
+            r->t_last = T;
+            r->nw_last = nw;
+            r->t_vary = T;
+        }
+    } else if (T - r->t_last == A && nw > 0.0) {
+        const double at = (double)r->p.shift_interval * r->p.tau;
+        const double c1 = r->p.shift_damping / at;
+        const double c2 = r->xi / at;
+        const double l1 = std::log(nw / r->nw_last);
+        const double l2 = std::log(nw / r->p.walker_target);
+        const double d1 = c1 * l1;
+        const double d2 = c2 * l2;
+        const double s1 = r->S - d1;
+        r->S = s1 - d2;
+        r->t_last = T;
+        r->nw_last = nw;
+    }
+    r->nw_ring[(size_t)(T % (A + 1))] = nw;
+}
+
+
+// Advance the run's clock by the completed step: shift update and the
+// recorded per-step estimators.
+static void record_step(fciqmc_run* run, const Ctl& c, int retries, int64_t attempts, fciqmc_step_stats* out) {
+    run->t += 1;
+    shift_update(run, c.nw);
+    fciqmc_step_stats s{};
+    s.iter = run->t;
+    s.nw = c.nw;
+    s.nref = c.nref;
+    s.enum_ = c.enum_;
+    s.shift = run->S;
+    const double eref = run->h00 + run->sys->e_core;
+    const double q = c.enum_ / c.nref;
+    s.e_proj = eref + q;
+    s.ndets = c.ndets;
+    s.attempts = attempts;
+    s.spawns = c.nrec_out;
+    s.vary_shift = run->vary;
+    s.retries = retries;
+    run->hist.push_back(s);
+    if (out) *out = s;
+}
+
+// ---------------------------------------------------------------------------
+// Batches: runs that advance together, one set of launches per step for all
+// of them.  Runs are grouped by engine kind (determinant width and value
+// type); each group launches one spawn kernel per excitation generator, one
+// annihilation kernel and one post kernel, and all groups share one
+// read-back and one synchronisation per step.
+// ---------------------------------------------------------------------------
+struct BatchGroupBase {
+    std::vector<fciqmc_run*> runs;  // ordered by excitation generator
+    virtual ~BatchGroupBase() {}
+    virtual int prepare(hipStream_t s) = 0;
+    virtual int launch_spawn(hipStream_t s, int grid) = 0;
+    virtual int launch_annihilate(hipStream_t s, int grid) = 0;
+    virtual int launch_post(hipStream_t s) = 0;
+    // after the stream synchronised: accept or replay each run's step
+    virtual int finish(fciqmc_step_stats* row) = 0;
+};
+
+template <int W, class V> struct BatchGroup : BatchGroupBase {
+    using E = Engine<W, V>;
+    Arena arena;
+    size_t cap = 0;             // instances the buffers hold
+    char* hbuf = nullptr;       // pinned: Inst[cap], bucket prefix [cap+1], chunk prefixes [cap+3]
+    char* dbuf = nullptr;       // device copy of hbuf
+    Ctl* hctl = nullptr;        // pinned read-back, one per instance
+    Ctl* dctl = nullptr;
+    int g0[4] = {0, 0, 0, 0};   // first instance of each generator, g0[3] = n
+    int64_t ctot[3] = {0, 0, 0};
+    int64_t btot = 0;
+
+    ~BatchGroup() override {
+        if (hbuf) (void)hipHostFree(hbuf);
+        if (hctl) (void)hipHostFree(hctl);
+        arena.clear();
+    }
+    E* eng(size_t i) const { return static_cast<E*>(runs[i]->eng.get()); }
+    static size_t bytes_for(size_t n) { return sizeof(Inst<W, V>) * n + sizeof(int64_t) * (2 * n + 4); }
+    int64_t* bfirst(char* base) const { return reinterpret_cast<int64_t*>(base + sizeof(Inst<W, V>) * cap); }
+    int64_t* cfirst(char* base) const { return bfirst(base) + cap + 1; }
+
+    int reserve(size_t n) {
+        if (n <= cap) return 0;
+        const size_t c = std::max<size_t>({n, 2 * cap, 8});
+        if (hbuf) (void)hipHostFree(hbuf);
+        if (hctl) (void)hipHostFree(hctl);
+        hbuf = nullptr;
+        hctl = nullptr;
+        arena.clear();
+        cap = 0;
+        HIP_OK(hipHostMalloc((void**)&hbuf, bytes_for(c), hipHostMallocDefault));
+        HIP_OK(hipHostMalloc((void**)&hctl, sizeof(Ctl) * c, hipHostMallocDefault));
+        CHECK(dalloc(arena, &dbuf, bytes_for(c)));
+        CHECK(dalloc(arena, &dctl, c));
+        cap = c;
+        return 0;
+    }
+
+    int prepare(hipStream_t s) override {
+        const size_t n = runs.size();
+        if (n == 0) return 0;
+        CHECK(reserve(n));
+        Inst<W, V>* hi = reinterpret_cast<Inst<W, V>*>(hbuf);
+        int64_t* bf = bfirst(hbuf);
+        int64_t* cf = cfirst(hbuf);
+        std::vector<int64_t> chunks(n);
+        btot = 0;
+        for (size_t i = 0; i < n; ++i) {
+            CHECK(eng(i)->batch_prepare(runs[i]->t, runs[i]->S, hi[i], chunks[i]));
+            bf[i] = btot;
+            btot += eng(i)->B;
+        }
+        bf[n] = btot;
+        // generator ranges; range g keeps its chunk prefix in cf[g0[g] + g .. g0[g+1] + g]
+        int k = 0;
+        for (int g = 0; g < 3; ++g) {
+            g0[g] = k;
+            while (k < (int)n && runs[k]->p.excitgen == g) ++k;
+        }
+        g0[3] = (int)n;
+        for (int g = 0; g < 3; ++g) {
+            int64_t c = 0;
+            for (int i = g0[g]; i < g0[g + 1]; ++i) {
+                cf[i + g] = c;
+                c += chunks[i];
+            }
+            cf[g0[g + 1] + g] = c;
+            ctot[g] = c;
+        }
+        HIP_OK(hipMemcpyAsync(dbuf, hbuf, bytes_for(cap), hipMemcpyHostToDevice, s));
+        return 0;
+    }
+    int launch_spawn(hipStream_t s, int grid) override {
+        if (runs.empty()) return 0;
+        const Inst<W, V>* di = reinterpret_cast<const Inst<W, V>*>(dbuf);
+        const int64_t* cf = cfirst(dbuf);
+        for (int g = 0; g < 3; ++g) {
+            if (ctot[g] == 0) continue;
+            const unsigned gs = (unsigned)(grid > 0 ? std::min<int64_t>(ctot[g], grid) : ctot[g]);
+            const int k = g0[g + 1] - g0[g];
+            if (g == FCIQMC_GEN_UNIFORM)
+                hipLaunchKernelGGL((k_spawn_batch<W, V, 0>), dim3(gs), dim3(kThreads), 0, s, di + g0[g], cf + g0[g] + g, k);
+            else if (g == FCIQMC_GEN_LATTICE)
+                hipLaunchKernelGGL((k_spawn_batch<W, V, 1>), dim3(gs), dim3(kThreads), 0, s, di + g0[g], cf + g0[g] + g, k);
+            else
+                hipLaunchKernelGGL((k_spawn_batch<W, V, 2>), dim3(gs), dim3(kThreads), 0, s, di + g0[g], cf + g0[g] + g, k);
+        }
+        HIP_OK(hipGetLastError());
+        return 0;
+    }
+    int launch_annihilate(hipStream_t s, int grid) override {
+        if (runs.empty()) return 0;
+        const unsigned gs = (unsigned)(grid > 0 ? std::min<int64_t>(btot, grid) : btot);
+        hipLaunchKernelGGL((k_annihilate_batch<W, V>), dim3(gs), dim3(kThreads), 0, s,
+                           reinterpret_cast<const Inst<W, V>*>(dbuf), (const int64_t*)bfirst(dbuf), (int)runs.size());
+        HIP_OK(hipGetLastError());
+        return 0;
+    }
+    int launch_post(hipStream_t s) override {
+        if (runs.empty()) return 0;
+        hipLaunchKernelGGL((k_post_batch<W, V>), dim3((unsigned)runs.size()), dim3(kPostThreads), 0, s,
+                           reinterpret_cast<const Inst<W, V>*>(dbuf), dctl);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(hctl, dctl, sizeof(Ctl) * runs.size(), hipMemcpyDeviceToHost, s));
+        return 0;
+    }
+    int finish(fciqmc_step_stats* row) override {
+        int rc = 0;
+        for (size_t i = 0; i < runs.size(); ++i) {
+            fciqmc_run* r = runs[i];
+            Ctl out{};
+            int retries = 0;
+            int64_t attempts = 0;
+            const int e = eng(i)->batch_finish(r->t, r->S, hctl[i], out, retries, attempts);
+            if (e) {
+                if (!rc) rc = e;
+                continue;
+            }
+            record_step(r, out, retries, attempts, row ? row + r->batch_slot : nullptr);
+        }
+        return rc;
+    }
+};
+
+static std::unique_ptr<BatchGroupBase> make_group(int kind) {
+    switch (kind) {
+        case kind_of<1, int32_t>(): return std::unique_ptr<BatchGroupBase>(new BatchGroup<1, int32_t>());
+        case kind_of<1, double>(): return std::unique_ptr<BatchGroupBase>(new BatchGroup<1, double>());
+        case kind_of<2, int32_t>(): return std::unique_ptr<BatchGroupBase>(new BatchGroup<2, int32_t>());
+        default: return std::unique_ptr<BatchGroupBase>(new BatchGroup<2, double>());
+    }
+}
+
+struct fciqmc_batch {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<fciqmc_run*> members;          // in order of addition
+    std::unique_ptr<BatchGroupBase> group[4];  // by engine kind
+    int grid_spawn = 0, grid_ann = 0;          // workgroups per launch, 0 = one per work item
+    bool profile = false;
+    hipEvent_t ev[kKernels + 1]{};
+    double kms[kKernels]{};
+    int64_t ksteps = 0;
+    ~fciqmc_batch() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (profile)
+            for (auto& e : ev) (void)hipEventDestroy(e);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+static void batch_detach(fciqmc_batch* b, fciqmc_run* r) {
+    (void)hipStreamSynchronize(b->stream);
+    auto& g = b->group[r->eng->kind()]->runs;
+    g.erase(std::find(g.begin(), g.end(), r));
+    b->members.erase(std::find(b->members.begin(), b->members.end(), r));
+    for (size_t i = 0; i < b->members.size(); ++i) b->members[i]->batch_slot = (int)i;
+    r->eng->set_stream(r->stream);
+    r->batch = nullptr;
+    r->batch_slot = -1;
+}
+
+// One step of every member: all launches queued, one synchronisation, then
+// each run accepts its step (or replays it alone after a capacity flag).
+static int batch_step_once(fciqmc_batch* b, fciqmc_step_stats* row) {
+    for (auto& g : b->group)
+        if (g) CHECK(g->prepare(b->stream));
+    if (b->profile) HIP_OK(hipEventRecord(b->ev[0], b->stream));
+    for (auto& g : b->group)
+        if (g) CHECK(g->launch_spawn(b->stream, b->grid_spawn));
+    if (b->profile) HIP_OK(hipEventRecord(b->ev[1], b->stream));
+    for (auto& g : b->group)
+        if (g) CHECK(g->launch_annihilate(b->stream, b->grid_ann));
+    if (b->profile) HIP_OK(hipEventRecord(b->ev[2], b->stream));
+    for (auto& g : b->group)
+        if (g) CHECK(g->launch_post(b->stream));
+    if (b->profile) HIP_OK(hipEventRecord(b->ev[3], b->stream));
+    HIP_OK(hipStreamSynchronize(b->stream));
+    if (b->profile) {
+        for (int i = 0; i < kKernels; ++i) {
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, b->ev[i], b->ev[i + 1]));
+            b->kms[i] += ms;
+        }
+        ++b->ksteps;
+    }
+    int rc = 0;
+    for (auto& g : b->group)
+        if (g) {
+            const int e = g->finish(row);
+            if (e && !rc) rc = e;
+        }
+    return rc;
+}
 
 extern "C" {
 
@@ -793,7 +1145,165 @@ int fciqmc_init(const fciqmc_system* csys, const fciqmc_params* p, void* stream,
     return 0;
 }
 
-void fciqmc_free_run(fciqmc_run* run) { delete run; }
+void fciqmc_free_run(fciqmc_run* run) {
+    if (!run) return;
+    if (run->batch) batch_detach(run->batch, run);
+    delete run;
+}
+
+int fciqmc_batch_create(void* stream, fciqmc_batch** out) {
+    if (!out) return fail(FCIQMC_EINVAL, "null argument");
+    *out = nullptr;
+    std::unique_ptr<fciqmc_batch> b(new fciqmc_batch());
+    if (stream) b->stream = (hipStream_t)stream;
+    else { HIP_OK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking)); b->own_stream = true; }
+    *out = b.release();
+    return 0;
+}
+
+int fciqmc_batch_add(fciqmc_batch* b, fciqmc_run* run) {
+    if (!b || !run || !run->eng) return fail(FCIQMC_EINVAL, "null argument");
+    if (run->batch) return fail(FCIQMC_EINVAL, "the run already belongs to a batch");
+    HIP_OK(hipStreamSynchronize(run->stream));
+    const int k = run->eng->kind();
+    if (!b->group[k]) b->group[k] = make_group(k);
+    auto& g = b->group[k]->runs;
+    // keep each group ordered by generator (stable within a generator)
+    auto pos = std::upper_bound(g.begin(), g.end(), run, [](const fciqmc_run* a, const fciqmc_run* c) {
+        return a->p.excitgen < c->p.excitgen;
+    });
+    g.insert(pos, run);
+    run->batch = b;
+    run->batch_slot = (int)b->members.size();
+    b->members.push_back(run);
+    run->eng->set_stream(b->stream);
+    return 0;
+}
+
+int fciqmc_batch_remove(fciqmc_batch* b, fciqmc_run* run) {
+    if (!b || !run) return fail(FCIQMC_EINVAL, "null argument");
+    if (run->batch != b) return fail(FCIQMC_EINVAL, "the run is not a member of this batch");
+    batch_detach(b, run);
+    return 0;
+}
+
+int fciqmc_batch_size(const fciqmc_batch* b) { return b ? (int)b->members.size() : 0; }
+
+int fciqmc_batch_step(fciqmc_batch* b, int n_steps, fciqmc_step_stats* stats) {
+    if (!b) return fail(FCIQMC_EINVAL, "null argument");
+    if (n_steps < 0) return fail(FCIQMC_EINVAL, "n_steps must be >= 0");
+    const size_t m = b->members.size();
+    if (m == 0) return 0;
+    for (int i = 0; i < n_steps; ++i) CHECK(batch_step_once(b, stats ? stats + (size_t)i * m : nullptr));
+    return 0;
+}
+
+int fciqmc_batch_profile(fciqmc_batch* b, int enable, double* ms, int64_t* steps) {
+    if (!b) return fail(FCIQMC_EINVAL, "null argument");
+    if (enable && !b->profile) {
+        for (auto& e : b->ev) HIP_OK(hipEventCreate(&e));
+        b->profile = true;
+    }
+    if (ms && steps) {
+        for (int i = 0; i < kKernels; ++i) ms[i] = b->kms[i];
+        *steps = b->ksteps;
+    }
+    return 0;
+}
+
+// Attempts per second of `steps` batch steps under the current launch shape.
+static int batch_rate(fciqmc_batch* b, int steps, double& rate) {
+    const size_t m = b->members.size();
+    std::vector<fciqmc_step_stats> st((size_t)steps * m);
+    HIP_OK(hipStreamSynchronize(b->stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < steps; ++i) CHECK(batch_step_once(b, st.data() + (size_t)i * m));
+    const auto t1 = std::chrono::steady_clock::now();
+    double att = 0.0;
+    for (const auto& x : st) att += (double)x.attempts;
+    const double sec = std::chrono::duration<double>(t1 - t0).count();
+    rate = sec > 0.0 ? att / sec : 0.0;
+    return 0;
+}
+
+// Bucket count giving about `occ` occupied determinants per bucket.
+static int buckets_for(int64_t ndets, int occ) {
+    const int64_t b = (ndets + occ - 1) / occ;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, 1 << 22));
+}
+
+int fciqmc_batch_tune(fciqmc_batch* b, int trial_steps, fciqmc_tune_report* out) {
+    if (!b) return fail(FCIQMC_EINVAL, "null argument");
+    if (trial_steps < 1) return fail(FCIQMC_EINVAL, "trial_steps must be >= 1");
+    fciqmc_tune_report rep{};
+    if (b->members.empty()) {
+        if (out) *out = rep;
+        return 0;
+    }
+    int trials = 0;
+    double best = 0.0;
+    CHECK(batch_rate(b, trial_steps, best));
+    ++trials;
+    rep.rate_initial = best;
+    // walker-store occupancy: rebucket every member, time, keep the best
+    const std::vector<int64_t> start_b = [&] {
+        std::vector<int64_t> v;
+        for (auto* r : b->members) v.push_back(r->eng->buckets());
+        return v;
+    }();
+    std::vector<int64_t> best_b = start_b;
+    int best_occ = 0;
+    for (int occ : {128, 256, 384}) {
+        for (auto* r : b->members) CHECK(r->eng->rebucket(buckets_for(r->eng->ndets(), occ)));
+        double rate = 0.0;
+        CHECK(batch_rate(b, trial_steps, rate));
+        ++trials;
+        if (rate > best) {
+            best = rate;
+            best_occ = occ;
+            best_b.clear();
+            for (auto* r : b->members) best_b.push_back(r->eng->buckets());
+        }
+    }
+    if (best_occ == 0)
+        for (size_t i = 0; i < b->members.size(); ++i) CHECK(b->members[i]->eng->rebucket((int)start_b[i]));
+    else
+        for (auto* r : b->members) CHECK(r->eng->rebucket(buckets_for(r->eng->ndets(), best_occ)));
+    // persistent grids of the two large launches
+    int best_gs = b->grid_spawn, best_ga = b->grid_ann;
+    for (int gs : {0, 2048, 8192}) {
+        if (gs == best_gs) continue;
+        b->grid_spawn = gs;
+        double rate = 0.0;
+        CHECK(batch_rate(b, trial_steps, rate));
+        ++trials;
+        if (rate > best) { best = rate; best_gs = gs; }
+    }
+    b->grid_spawn = best_gs;
+    for (int ga : {0, 1024, 4096}) {
+        if (ga == best_ga) continue;
+        b->grid_ann = ga;
+        double rate = 0.0;
+        CHECK(batch_rate(b, trial_steps, rate));
+        ++trials;
+        if (rate > best) { best = rate; best_ga = ga; }
+    }
+    b->grid_ann = best_ga;
+    rep.dets_per_bucket = best_occ;
+    rep.grid_spawn = best_gs;
+    rep.grid_annihilate = best_ga;
+    rep.trials = trials;
+    rep.steps = (int64_t)trials * trial_steps;
+    rep.rate_best = best;
+    if (out) *out = rep;
+    return 0;
+}
+
+void fciqmc_batch_free(fciqmc_batch* b) {
+    if (!b) return;
+    while (!b->members.empty()) batch_detach(b, b->members.back());
+    delete b;
+}
 
 int64_t fciqmc_run_device_bytes(const fciqmc_run* run) { return run && run->eng ? run->eng->bytes() : 0; }
 
@@ -808,76 +1318,16 @@ int fciqmc_profile(fciqmc_run* run, int enable, double* ms, int64_t* steps, int6
     return 0;
 }
 
-// Population control (Sec. I leaves the update open).  Reading: S stays 0
-// (relative to H_00) until N_w first reaches the target N_t.  At that step T
-// the shift is set from the measured growth rate,
-// S = -ln(N_w(T)/N_w(T-L))/(L dtau), L = min(A, steps since the population was
-// set).  From then on, every A steps,
-//   S <- S - zeta/(A dtau) ln(N_w(t)/N_w(t-A)) - xi/(A dtau) ln(N_w(t)/N_t),
-// the damped control of the original method plus the restoring term of
-// Yang, Pahl and Brand (J. Chem. Phys. 153, 174103 (2020)); xi = zeta^2/4 by
-// default.  An extinct population (N_w = 0) leaves S unchanged.
-static void shift_update(fciqmc_run* r, double nw) {
-    const int64_t T = r->t;
-    const int64_t A = (int64_t)r->p.shift_interval;
-    if (!r->vary) {
-        if (nw >= r->p.walker_target) {
-            r->vary = 1;
-            int64_t L = std::min<int64_t>(T - r->t_set, A);
-            if (L > 0) {
-                const double nw_prev = r->nw_ring[(size_t)((T - L) % (A + 1))];
-                const double c = 1.0 / ((double)L * r->p.tau);
-                const double ratio = nw / nw_prev;
-                const double l = std::log(ratio);
-                const double dS = c * l;
-                r->S = 0.0 - dS;
-            }
-            r->t_last = T;
-            r->nw_last = nw;
-            r->t_vary = T;
-        }
-    } else if (T - r->t_last == A && nw > 0.0) {
-        const double at = (double)r->p.shift_interval * r->p.tau;
-        const double c1 = r->p.shift_damping / at;
-        const double c2 = r->xi / at;
-        const double l1 = std::log(nw / r->nw_last);
-        const double l2 = std::log(nw / r->p.walker_target);
-        const double d1 = c1 * l1;
-        const double d2 = c2 * l2;
-        const double s1 = r->S - d1;
-        r->S = s1 - d2;
-        r->t_last = T;
-        r->nw_last = nw;
-    }
-    r->nw_ring[(size_t)(T % (A + 1))] = nw;
-}
-
 int fciqmc_step(fciqmc_run* run, int n_steps, fciqmc_step_stats* stats) {
     if (!run || !run->eng) return fail(FCIQMC_ESTATE, "run not initialised");
+    if (run->batch) return fail(FCIQMC_ESTATE, "the run belongs to a batch: step the batch");
     if (n_steps < 0) return fail(FCIQMC_EINVAL, "n_steps must be >= 0");
     for (int i = 0; i < n_steps; ++i) {
         Ctl c{};
         int retries = 0;
         int64_t attempts = 0;
         CHECK(run->eng->step_once(run->t, run->S, c, retries, attempts));
-        run->t += 1;
-        shift_update(run, c.nw);
-        fciqmc_step_stats s{};
-        s.iter = run->t;
-        s.nw = c.nw;
-        s.nref = c.nref;
-        s.enum_ = c.enum_;
-        s.shift = run->S;
-        const double eref = run->h00 + run->sys->e_core;
-        const double q = c.enum_ / c.nref;
-        s.e_proj = eref + q;
-        s.ndets = c.ndets;
-        s.attempts = attempts;
-        s.spawns = c.nrec_out;
-        s.vary_shift = run->vary;
-        s.retries = retries;
-        run->hist.push_back(s);
-        if (stats) stats[i] = s;
+        record_step(run, c, retries, attempts, stats ? stats + i : nullptr);
     }
     return 0;
 }

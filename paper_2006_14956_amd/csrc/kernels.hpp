@@ -101,18 +101,16 @@ struct StepScalars {
 // attempt counts; each lane finds its (bucket, entry, k) by binary search.
 // ---------------------------------------------------------------------------
 template <int W, class V, int GEN>
-__global__ __launch_bounds__(kThreads) void k_spawn(SysView sys, Store<V> st, StepScalars sc,
-                                                    Rec<W, V>* __restrict__ rec2,
-                                                    const int64_t* __restrict__ soff,
-                                                    int32_t* __restrict__ scount, Ctl* ctl) {
-    // Workgroup g owns attempts [g*kChunk, (g+1)*kChunk).  Two lanes find the
-    // buckets of its first and last attempt; the others search between them.
-    // A record takes the next place of sub-slab j = b*kSub + g mod kSub of its
-    // target bucket b, rec2[soff[j] .. soff[j+1]).
-    __shared__ int bspan[2];
+__device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& st, const StepScalars& sc,
+                                            Rec<W, V>* __restrict__ rec2, const int64_t* __restrict__ soff,
+                                            int32_t* __restrict__ scount, Ctl* ctl, int64_t g, int* bspan) {
+    // Workgroup chunk g owns attempts [g*kChunk, (g+1)*kChunk).  Two lanes find
+    // the buckets of its first and last attempt; the others search between
+    // them.  A record takes the next place of sub-slab j = b*kSub + g mod kSub
+    // of its target bucket b, rec2[soff[j] .. soff[j+1]).
     const int64_t total = st.aoff[sc.B];
     const Key<W> ref = make_key<W>(sc.ref_a, sc.ref_b);
-    const int64_t g0 = (int64_t)blockIdx.x * kChunk;
+    const int64_t g0 = g * kChunk;
     if (threadIdx.x < 2) {
         const int64_t a0 = threadIdx.x == 0 ? g0 : min(g0 + kChunk, total) - 1;
         int lo = 0, hi = sc.B;
@@ -194,12 +192,22 @@ __global__ __launch_bounds__(kThreads) void k_spawn(SysView sys, Store<V> st, St
             }
         }
         if (emit) {
-            const uint32_t j = (out.flag >> 1) * kSub + (blockIdx.x & (kSub - 1));
+            const uint32_t j = (out.flag >> 1) * kSub + (uint32_t)(g & (kSub - 1));
             const int64_t pos = (int64_t)atomicAdd(&scount[j], 1);
             if (soff[j] + pos < soff[j + 1]) rec2[soff[j] + pos] = out;
             else atomicOr(&ctl->flags, kFlagSpawnCap);
         }
     }
+    __syncthreads();  // bspan is reused by the workgroup's next chunk
+}
+
+template <int W, class V, int GEN>
+__global__ __launch_bounds__(kThreads) void k_spawn(SysView sys, Store<V> st, StepScalars sc,
+                                                    Rec<W, V>* __restrict__ rec2,
+                                                    const int64_t* __restrict__ soff,
+                                                    int32_t* __restrict__ scount, Ctl* ctl) {
+    __shared__ int bspan[2];
+    spawn_chunk<W, V, GEN>(sys, st, sc, rec2, soff, scount, ctl, (int64_t)blockIdx.x, bspan);
 }
 
 // Records uploaded from the host (population import): assign buckets.
@@ -436,6 +444,235 @@ __device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, cons
 // ---------------------------------------------------------------------------
 constexpr int64_t kM40 = (1LL << 40) - 1;
 
+// The step's flag word, read once for the whole workgroup so that every wave
+// takes the same branch (another workgroup may set a flag meanwhile).
+__device__ __forceinline__ unsigned wg_flags(const Ctl* ctl, unsigned* sh) {
+    if (threadIdx.x == 0) *sh = __hip_atomic_load(&ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const unsigned f = *sh;
+    __syncthreads();
+    return f;
+}
+
+template <int W, class V>
+__device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Store<V>& in, const Store<V>& out,
+                                                  const StepScalars& sc, const Rec<W, V>* __restrict__ rec2,
+                                                  int64_t* __restrict__ soff, int32_t* __restrict__ scount,
+                                                  int64_t* __restrict__ rel, int64_t* __restrict__ need_b,
+                                                  int64_t* __restrict__ recs_b, double* __restrict__ nw_b,
+                                                  double* __restrict__ en_b, Ctl* ctl, int b, Lds<W, V>& L) {
+    const Key<W> ref = make_key<W>(sc.ref_a, sc.ref_b);
+    constexpr bool kInt = sizeof(V) == 4;
+    const int64_t eb = (int64_t)b * sc.R;
+    const int cnt = sc.import_mode ? 0 : in.count[b];
+    // the bucket's records: its kSub sub-slabs, walked as one sequence
+    // (cumulative counts and starts held in registers, selected unrolled)
+    int64_t cum[kSub + 1], lo[kSub];
+    int32_t cj[kSub];
+    cum[0] = 0;
+#pragma unroll
+    for (int j = 0; j < kSub; ++j) {
+        lo[j] = soff[(int64_t)b * kSub + j];
+        cj[j] = scount[(int64_t)b * kSub + j];
+        cum[j + 1] = cum[j] + cj[j];
+    }
+    // LDS table sized to the bucket: keys <= determinants + records, load <= 3/4
+    const int64_t want = ((int64_t)cnt + cum[kSub]) * 4 / 3 + 1;
+    int nslots = kThreads;
+    while (nslots < want && nslots < kSlots) nslots <<= 1;
+    const uint64_t mask = (uint64_t)(nslots - 1);
+    for (int i = threadIdx.x; i < nslots; i += kThreads) {
+        L.t.key0[i] = kEmpty;
+        if constexpr (W == 2) L.t.key1[i] = kEmpty;
+        L.t.val[i] = (V)0;
+        L.t.idx[i] = -1;
+    }
+    if (threadIdx.x == 0) L.nfresh = 0;
+    __syncthreads();
+    // (b) death of the walkers occupied at tau: x = (1 - dtau (d_i - S)) C_i,
+    // stochastically rounded; the slot is marked as occupied at tau.
+    for (int e = threadIdx.x; e < cnt; e += kThreads) {
+        const Key<W> key = load_key<W>(in.keys + (eb + e) * W);
+        const V C = in.vals[eb + e];
+        const double d = in.diag[eb + e];
+        const double t1 = d - sc.S;
+        const double t2 = sc.tau * t1;
+        const double f = 1.0 - t2;
+        const double xv = f * (double)C;
+        const double u = unif(draw<W>(key, sc.t, 0, kDeath, sc.seed, sc.replica).x[0]);
+        V post;
+        if constexpr (kInt) {
+            const double ax = fabs(xv);
+            const double fl = floor(ax);
+            const double fr = ax - fl;
+            const double nn = fl + (u < fr ? 1.0 : 0.0);
+            if (nn > 2147483000.0) atomicOr(&ctl->flags, kFlagPop);
+            post = (V)(xv < 0.0 ? -nn : nn);
+        } else {
+            const double ax = fabs(xv);
+            double y = xv;
+            if (ax < sc.c_min && xv != 0.0) {
+                const double pr = ax / sc.c_min;
+                y = (u < pr) ? (xv < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
+            }
+            post = (V)y;
+        }
+        const int s = lds_find<W, V>(L, key, key_hash<W>(key), mask, true);
+        if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); continue; }
+        L.t.val[s] = post;
+        L.t.idx[s] = e;
+    }
+    __syncthreads();
+    // (c) annihilation: a target occupied at tau takes every contribution;
+    // an unoccupied one only those of initiator parents (Sec. I).
+    for (int64_t q = threadIdx.x; q < cum[kSub]; q += kThreads) {
+        int64_t src = 0;
+#pragma unroll
+        for (int j = 0; j < kSub; ++j)
+            if (q >= cum[j] && q < cum[j + 1]) src = lo[j] + (q - cum[j]);
+        const Rec<W, V> x = rec2[src];
+        Key<W> key;
+#pragma unroll
+        for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
+        const bool init = (x.flag & 1u) != 0;
+        const int s = lds_find<W, V>(L, key, key_hash<W>(key), mask, init);
+        if (s == -1) continue;
+        if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); continue; }
+        if (init || L.t.idx[s] >= 0) lds_add<V>(&L.t.val[s], x.v);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // slabs of the next step: this step's counts plus headroom, relative
+        // to the bucket's base (set by the post work); counters restart at 0
+        if (!sc.import_mode) {
+            int64_t acc = 0;
+#pragma unroll
+            for (int j = 0; j < kSub; ++j) {
+                rel[(int64_t)b * kSub + j] = acc;
+                acc += slab_size(cj[j]);
+                scount[(int64_t)b * kSub + j] = 0;
+            }
+            need_b[b] = acc;
+        }
+        recs_b[b] = cum[kSub];
+    }
+    // compaction in passes of kThreads consecutive slots: rounding of small
+    // real amplitudes, output positions and attempt prefixes by a block
+    // scan of (kept, attempts) packed as kept << 40 | attempts
+    int64_t obase = 0, mbase = 0;
+    double nw = 0.0, en = 0.0;
+    bool over = false;
+    for (int p0 = 0; p0 < nslots; p0 += kThreads) {
+        const int s = p0 + threadIdx.x;
+        const uint64_t k0 = L.t.key0[s];
+        V v = (V)0;
+        Key<W> key;
+        key.w[0] = k0;
+        if constexpr (W == 2) key.w[1] = L.t.key1[s];
+        if (k0 != kEmpty) {
+            v = L.t.val[s];
+            if constexpr (!kInt) {
+                const double av = fabs((double)v);
+                if (!sc.import_mode && v != 0.0 && av < sc.c_min) {
+                    const double u = unif(draw<W>(key, sc.t, 0, kAnn, sc.seed, sc.replica).x[0]);
+                    const double pr = av / sc.c_min;
+                    v = (u < pr) ? (v < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
+                }
+            }
+        }
+        const bool keep = v != (V)0;
+        const int64_t m = keep ? n_attempts(v) : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan<kThreads, int64_t>(keep ? ((1LL << 40) | m) : 0, tot, L.sh64);
+        const int64_t pos = obase + (ex >> 40);
+        const int64_t mp = mbase + (ex & kM40);
+        obase += tot >> 40;
+        mbase += tot & kM40;
+        if (obase > sc.R || mbase >= (int64_t)0x7FFFFFFF) { over = true; break; }
+        if (keep) {
+            const int64_t o = eb + pos;
+            store_key<W>(out.keys + o * W, key);
+            out.vals[o] = v;
+            out.mpre[o] = (int32_t)mp;
+            const int oi = L.t.idx[s];
+            const uint64_t ka = key_alpha<W>(key), kb = key_beta<W>(key);
+            if (oi >= 0) {
+                out.diag[o] = in.diag[eb + oi];
+            } else {
+                // new determinant: its diagonal is computed below, one per lane
+                const int f = atomicAdd(&L.nfresh, 1);
+                if (f < kFresh) L.fresh[f] = s | ((int)pos << 11);
+                else { const double hd = h_diag(sys, ka, kb); out.diag[o] = hd - sc.h00; }
+            }
+            const double av = vabs(v);
+            nw = nw + av;
+            if (key_eq<W>(key, ref)) {
+                ctl->nref = (double)v;
+            } else {
+                const int lvl = popc64(ka ^ sc.ref_a) + popc64(kb ^ sc.ref_b);
+                if (lvl == 2 || lvl == 4) {
+                    const double h = h_offdiag(sys, sc.ref_a, sc.ref_b, ka, kb);
+                    const double c = h * (double)v;
+                    en = en + c;
+                }
+            }
+        }
+    }
+    if (over) {
+        if (threadIdx.x == 0) atomicOr(&ctl->flags, kFlagStore);
+        __syncthreads();
+        return;
+    }
+    nw = wave_sum(nw);
+    en = wave_sum(en);
+    if (lane_id() == 0) { L.shd[threadIdx.x >> 6] = nw; L.shd[4 + (threadIdx.x >> 6)] = en; }
+    __syncthreads();
+    // diagonals of the new determinants, spread over the workgroup; the
+    // keys go to registers, then the dead hash table holds h_pp, X and J
+    const int nf = min(L.nfresh, kFresh);
+    Key<W> fk[kFresh / kThreads];
+    int64_t fo[kFresh / kThreads];
+#pragma unroll
+    for (int i = 0; i < kFresh / kThreads; ++i) {
+        const int f = threadIdx.x + i * kThreads;
+        fo[i] = -1;
+        if (f < nf) {
+            const int s = L.fresh[f] & 2047;
+            fo[i] = eb + (L.fresh[f] >> 11);
+            fk[i].w[0] = L.t.key0[s];
+            if constexpr (W == 2) fk[i].w[1] = L.t.key1[s];
+        }
+    }
+    const int N = sys.N;
+    const bool stage = nf > 0 && !sys.onsite &&
+                       (int64_t)N + 2 * (int64_t)N * N <= (int64_t)(sizeof(L.diag_tabs) / sizeof(double));
+    if (stage) {
+        __syncthreads();
+        double* hd = L.diag_tabs;
+        double* xt = hd + N;
+        double* jt = xt + N * N;
+        for (int i = threadIdx.x; i < N * N; i += kThreads) { xt[i] = sys.X[i]; jt[i] = sys.J[i]; }
+        for (int i = threadIdx.x; i < N; i += kThreads) hd[i] = sys.Hd[i];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < kFresh / kThreads; ++i) {
+        if (fo[i] < 0) continue;
+        const uint64_t ka = key_alpha<W>(fk[i]), kb = key_beta<W>(fk[i]);
+        double h;
+        if (stage) h = h_diag_tab(L.diag_tabs, L.diag_tabs + N, L.diag_tabs + N + N * N, N, ka, kb);
+        else h = h_diag(sys, ka, kb);
+        out.diag[fo[i]] = h - sc.h00;
+    }
+    if (threadIdx.x == 0) {
+        nw_b[b] = ((L.shd[0] + L.shd[1]) + L.shd[2]) + L.shd[3];
+        en_b[b] = ((L.shd[4] + L.shd[5]) + L.shd[6]) + L.shd[7];
+        out.count[b] = (int32_t)obase;
+        out.batt[b] = mbase;
+    }
+    __syncthreads();
+}
+
 template <int W, class V>
 __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> in, Store<V> out,
                                                          StepScalars sc,
@@ -447,221 +684,13 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
                                                          int64_t* __restrict__ recs_b,
                                                          double* __restrict__ nw_b,
                                                          double* __restrict__ en_b, Ctl* ctl) {
-    if (ctl->flags) return;
     __shared__ Lds<W, V> L;
-    const Key<W> ref = make_key<W>(sc.ref_a, sc.ref_b);
-    constexpr bool kInt = sizeof(V) == 4;
-    for (int b = blockIdx.x; b < sc.B; b += gridDim.x) {
-        const int64_t eb = (int64_t)b * sc.R;
-        const int cnt = sc.import_mode ? 0 : in.count[b];
-        // the bucket's records: its kSub sub-slabs, walked as one sequence
-        // (cumulative counts and starts held in registers, selected unrolled)
-        int64_t cum[kSub + 1], lo[kSub];
-        int32_t cj[kSub];
-        cum[0] = 0;
-#pragma unroll
-        for (int j = 0; j < kSub; ++j) {
-            lo[j] = soff[(int64_t)b * kSub + j];
-            cj[j] = scount[(int64_t)b * kSub + j];
-            cum[j + 1] = cum[j] + cj[j];
-        }
-        // LDS table sized to the bucket: keys <= determinants + records, load <= 3/4
-        const int64_t want = ((int64_t)cnt + cum[kSub]) * 4 / 3 + 1;
-        int nslots = kThreads;
-        while (nslots < want && nslots < kSlots) nslots <<= 1;
-        const uint64_t mask = (uint64_t)(nslots - 1);
-        for (int i = threadIdx.x; i < nslots; i += kThreads) {
-            L.t.key0[i] = kEmpty;
-            if constexpr (W == 2) L.t.key1[i] = kEmpty;
-            L.t.val[i] = (V)0;
-            L.t.idx[i] = -1;
-        }
-        if (threadIdx.x == 0) L.nfresh = 0;
-        __syncthreads();
-        // (b) death of the walkers occupied at tau: x = (1 - dtau (d_i - S)) C_i,
-        // stochastically rounded; the slot is marked as occupied at tau.
-        for (int e = threadIdx.x; e < cnt; e += kThreads) {
-            const Key<W> key = load_key<W>(in.keys + (eb + e) * W);
-            const V C = in.vals[eb + e];
-            const double d = in.diag[eb + e];
-            const double t1 = d - sc.S;
-            const double t2 = sc.tau * t1;
-            const double f = 1.0 - t2;
-            const double xv = f * (double)C;
-            const double u = unif(draw<W>(key, sc.t, 0, kDeath, sc.seed, sc.replica).x[0]);
-            V post;
-            if constexpr (kInt) {
-                const double ax = fabs(xv);
-                const double fl = floor(ax);
-                const double fr = ax - fl;
-                const double nn = fl + (u < fr ? 1.0 : 0.0);
-                if (nn > 2147483000.0) atomicOr(&ctl->flags, kFlagPop);
-                post = (V)(xv < 0.0 ? -nn : nn);
-            } else {
-                const double ax = fabs(xv);
-                double y = xv;
-                if (ax < sc.c_min && xv != 0.0) {
-                    const double pr = ax / sc.c_min;
-                    y = (u < pr) ? (xv < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
-                }
-                post = (V)y;
-            }
-            const int s = lds_find<W, V>(L, key, key_hash<W>(key), mask, true);
-            if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); continue; }
-            L.t.val[s] = post;
-            L.t.idx[s] = e;
-        }
-        __syncthreads();
-        // (c) annihilation: a target occupied at tau takes every contribution;
-        // an unoccupied one only those of initiator parents (Sec. I).
-        for (int64_t q = threadIdx.x; q < cum[kSub]; q += kThreads) {
-            int64_t src = 0;
-#pragma unroll
-            for (int j = 0; j < kSub; ++j)
-                if (q >= cum[j] && q < cum[j + 1]) src = lo[j] + (q - cum[j]);
-            const Rec<W, V> x = rec2[src];
-            Key<W> key;
-#pragma unroll
-            for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
-            const bool init = (x.flag & 1u) != 0;
-            const int s = lds_find<W, V>(L, key, key_hash<W>(key), mask, init);
-            if (s == -1) continue;
-            if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); continue; }
-            if (init || L.t.idx[s] >= 0) lds_add<V>(&L.t.val[s], x.v);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            // slabs of the next step: this step's counts plus headroom, relative
-            // to the bucket's base (set by the post work); counters restart at 0
-            if (!sc.import_mode) {
-                int64_t acc = 0;
-#pragma unroll
-                for (int j = 0; j < kSub; ++j) {
-                    rel[(int64_t)b * kSub + j] = acc;
-                    acc += slab_size(cj[j]);
-                    scount[(int64_t)b * kSub + j] = 0;
-                }
-                need_b[b] = acc;
-            }
-            recs_b[b] = cum[kSub];
-        }
-        // compaction in passes of kThreads consecutive slots: rounding of small
-        // real amplitudes, output positions and attempt prefixes by a block
-        // scan of (kept, attempts) packed as kept << 40 | attempts
-        int64_t obase = 0, mbase = 0;
-        double nw = 0.0, en = 0.0;
-        bool over = false;
-        for (int p0 = 0; p0 < nslots; p0 += kThreads) {
-            const int s = p0 + threadIdx.x;
-            const uint64_t k0 = L.t.key0[s];
-            V v = (V)0;
-            Key<W> key;
-            key.w[0] = k0;
-            if constexpr (W == 2) key.w[1] = L.t.key1[s];
-            if (k0 != kEmpty) {
-                v = L.t.val[s];
-                if constexpr (!kInt) {
-                    const double av = fabs((double)v);
-                    if (!sc.import_mode && v != 0.0 && av < sc.c_min) {
-                        const double u = unif(draw<W>(key, sc.t, 0, kAnn, sc.seed, sc.replica).x[0]);
-                        const double pr = av / sc.c_min;
-                        v = (u < pr) ? (v < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
-                    }
-                }
-            }
-            const bool keep = v != (V)0;
-            const int64_t m = keep ? n_attempts(v) : 0;
-            int64_t tot;
-            const int64_t ex = block_excl_scan<kThreads, int64_t>(keep ? ((1LL << 40) | m) : 0, tot, L.sh64);
-            const int64_t pos = obase + (ex >> 40);
-            const int64_t mp = mbase + (ex & kM40);
-            obase += tot >> 40;
-            mbase += tot & kM40;
-            if (obase > sc.R || mbase >= (int64_t)0x7FFFFFFF) { over = true; break; }
-            if (keep) {
-                const int64_t o = eb + pos;
-                store_key<W>(out.keys + o * W, key);
-                out.vals[o] = v;
-                out.mpre[o] = (int32_t)mp;
-                const int oi = L.t.idx[s];
-                const uint64_t ka = key_alpha<W>(key), kb = key_beta<W>(key);
-                if (oi >= 0) {
-                    out.diag[o] = in.diag[eb + oi];
-                } else {
-                    // new determinant: its diagonal is computed below, one per lane
-                    const int f = atomicAdd(&L.nfresh, 1);
-                    if (f < kFresh) L.fresh[f] = s | ((int)pos << 11);
-                    else { const double hd = h_diag(sys, ka, kb); out.diag[o] = hd - sc.h00; }
-                }
-                const double av = vabs(v);
-                nw = nw + av;
-                if (key_eq<W>(key, ref)) {
-                    ctl->nref = (double)v;
-                } else {
-                    const int lvl = popc64(ka ^ sc.ref_a) + popc64(kb ^ sc.ref_b);
-                    if (lvl == 2 || lvl == 4) {
-                        const double h = h_offdiag(sys, sc.ref_a, sc.ref_b, ka, kb);
-                        const double c = h * (double)v;
-                        en = en + c;
-                    }
-                }
-            }
-        }
-        if (over) {
-            if (threadIdx.x == 0) atomicOr(&ctl->flags, kFlagStore);
-            __syncthreads();
-            continue;
-        }
-        nw = wave_sum(nw);
-        en = wave_sum(en);
-        if (lane_id() == 0) { L.shd[threadIdx.x >> 6] = nw; L.shd[4 + (threadIdx.x >> 6)] = en; }
-        __syncthreads();
-        // diagonals of the new determinants, spread over the workgroup; the
-        // keys go to registers, then the dead hash table holds h_pp, X and J
-        const int nf = min(L.nfresh, kFresh);
-        Key<W> fk[kFresh / kThreads];
-        int64_t fo[kFresh / kThreads];
-#pragma unroll
-        for (int i = 0; i < kFresh / kThreads; ++i) {
-            const int f = threadIdx.x + i * kThreads;
-            fo[i] = -1;
-            if (f < nf) {
-                const int s = L.fresh[f] & 2047;
-                fo[i] = eb + (L.fresh[f] >> 11);
-                fk[i].w[0] = L.t.key0[s];
-                if constexpr (W == 2) fk[i].w[1] = L.t.key1[s];
-            }
-        }
-        const int N = sys.N;
-        const bool stage = nf > 0 && !sys.onsite &&
-                           (int64_t)N + 2 * (int64_t)N * N <= (int64_t)(sizeof(L.diag_tabs) / sizeof(double));
-        if (stage) {
-            __syncthreads();
-            double* hd = L.diag_tabs;
-            double* xt = hd + N;
-            double* jt = xt + N * N;
-            for (int i = threadIdx.x; i < N * N; i += kThreads) { xt[i] = sys.X[i]; jt[i] = sys.J[i]; }
-            for (int i = threadIdx.x; i < N; i += kThreads) hd[i] = sys.Hd[i];
-            __syncthreads();
-        }
-#pragma unroll
-        for (int i = 0; i < kFresh / kThreads; ++i) {
-            if (fo[i] < 0) continue;
-            const uint64_t ka = key_alpha<W>(fk[i]), kb = key_beta<W>(fk[i]);
-            double h;
-            if (stage) h = h_diag_tab(L.diag_tabs, L.diag_tabs + N, L.diag_tabs + N + N * N, N, ka, kb);
-            else h = h_diag(sys, ka, kb);
-            out.diag[fo[i]] = h - sc.h00;
-        }
-        if (threadIdx.x == 0) {
-            nw_b[b] = ((L.shd[0] + L.shd[1]) + L.shd[2]) + L.shd[3];
-            en_b[b] = ((L.shd[4] + L.shd[5]) + L.shd[6]) + L.shd[7];
-            out.count[b] = (int32_t)obase;
-            out.batt[b] = mbase;
-        }
-        __syncthreads();
-    }
+    __shared__ unsigned fl;
+    if (wg_flags(ctl, &fl)) return;
+    for (int b = blockIdx.x; b < sc.B; b += gridDim.x)
+        annihilate_bucket<W, V>(sys, in, out, sc, rec2, soff, scount, rel, need_b, recs_b, nw_b, en_b, ctl, b, L);
 }
+
 
 
 // Post work for many buckets, in three launches.  Phase a: workgroup g
@@ -823,6 +852,77 @@ __global__ __launch_bounds__(kPostThreads) void k_post(const int64_t* __restrict
     __shared__ int64_t sh[kPostThreads / 64], shm[kPostThreads / 64];
     __shared__ double shd[2 * kPostThreads / 64];
     post_work<kPostThreads>(batt, count, nw_b, en_b, rel, need_b, recs_b, B, aoff, soff, ctl, sh, shd, shm);
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches: many independent walker populations (instances, each with
+// its own integrals, parameters and store) advance one step in shared
+// launches.  Instance i owns the work items [first[i], first[i+1]) of a
+// launch (spawn chunks, or buckets); a workgroup takes items blockIdx.x,
+// blockIdx.x + gridDim.x, ... and finds each item's instance by binary search
+// over the prefix.  Every instance's arithmetic is that of its own launch, so
+// its trajectory does not depend on the company it keeps.
+// ---------------------------------------------------------------------------
+template <int W, class V> struct Inst {
+    SysView sys;
+    Store<V> in, out;
+    StepScalars sc;
+    Rec<W, V>* rec2;
+    int64_t *soff, *rel, *need_b, *recs_b;
+    int32_t* scount;
+    double *nw_b, *en_b;
+    Ctl* ctl;
+};
+
+__device__ __forceinline__ int owner_of(const int64_t* __restrict__ first, int k, int64_t g) {
+    int lo = 0, hi = k;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (first[mid] <= g) lo = mid; else hi = mid;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+template <int W, class V, int GEN>
+__global__ __launch_bounds__(kThreads) void k_spawn_batch(const Inst<W, V>* __restrict__ inst,
+                                                          const int64_t* __restrict__ first, int k) {
+    __shared__ int bspan[2];
+    const int64_t total = first[k];
+    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+        const int i = owner_of(first, k, g);
+        const Inst<W, V>& I = inst[i];
+        spawn_chunk<W, V, GEN>(I.sys, I.in, I.sc, I.rec2, I.soff, I.scount, I.ctl, g - first[i], bspan);
+    }
+}
+
+template <int W, class V>
+__global__ __launch_bounds__(kThreads) void k_annihilate_batch(const Inst<W, V>* __restrict__ inst,
+                                                               const int64_t* __restrict__ first, int k) {
+    __shared__ Lds<W, V> L;
+    __shared__ unsigned fl;
+    const int64_t total = first[k];
+    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+        const int i = owner_of(first, k, g);
+        const Inst<W, V>& I = inst[i];
+        if (wg_flags(I.ctl, &fl)) continue;  // this instance replays its step alone
+        annihilate_bucket<W, V>(I.sys, I.in, I.out, I.sc, I.rec2, I.soff, I.scount, I.rel, I.need_b, I.recs_b,
+                                I.nw_b, I.en_b, I.ctl, (int)(g - first[i]), L);
+    }
+}
+
+// Post work of instance blockIdx.x, then a copy of its step scalars into
+// ctl_out[blockIdx.x] (one read-back for the whole batch).
+template <int W, class V>
+__global__ __launch_bounds__(kPostThreads) void k_post_batch(const Inst<W, V>* __restrict__ inst,
+                                                             Ctl* __restrict__ ctl_out) {
+    __shared__ int64_t sh[kPostThreads / 64], shm[kPostThreads / 64];
+    __shared__ double shd[2 * kPostThreads / 64];
+    __shared__ unsigned fl;
+    const Inst<W, V>& I = inst[blockIdx.x];
+    if (!wg_flags(I.ctl, &fl))
+        post_work<kPostThreads>(I.out.batt, I.out.count, I.nw_b, I.en_b, I.rel, I.need_b, I.recs_b, I.sc.B,
+                                I.out.aoff, I.soff, I.ctl, sh, shd, shm);
+    if (threadIdx.x == 0) ctl_out[blockIdx.x] = *I.ctl;
 }
 
 // Copy the store to flat arrays (offsets from a count scan).

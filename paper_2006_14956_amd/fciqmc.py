@@ -56,10 +56,18 @@ class Checkpoint(C.Structure):
                 ("last_update_iter", C.c_int64), ("last_update_nw", C.c_double)]
 
 
+class TuneReport(C.Structure):
+    _fields_ = [("dets_per_bucket", C.c_int), ("grid_spawn", C.c_int), ("grid_annihilate", C.c_int),
+                ("trials", C.c_int), ("steps", C.c_int64), ("rate_initial", C.c_double),
+                ("rate_best", C.c_double)]
+
+
 EXPORTS = ["fciqmc_params_default", "fciqmc_load_integrals", "fciqmc_init", "fciqmc_step",
            "fciqmc_energy", "fciqmc_get_walkers", "fciqmc_set_walkers", "fciqmc_get_checkpoint",
            "fciqmc_set_checkpoint", "fciqmc_matrix_elements", "fciqmc_run_device_bytes",
-           "fciqmc_profile",
+           "fciqmc_profile", "fciqmc_batch_create", "fciqmc_batch_add", "fciqmc_batch_remove",
+           "fciqmc_batch_size", "fciqmc_batch_step", "fciqmc_batch_tune", "fciqmc_batch_profile",
+           "fciqmc_batch_free",
            "fciqmc_free_run", "fciqmc_free_system", "fciqmc_last_error"]
 
 _lib = None
@@ -97,6 +105,15 @@ def lib():
         L.fciqmc_run_device_bytes.argtypes = [vp]
         L.fciqmc_run_device_bytes.restype = i64
         L.fciqmc_profile.argtypes = [vp, C.c_int, pdbl, C.POINTER(i64), C.POINTER(i64)]
+        L.fciqmc_batch_create.argtypes = [vp, C.POINTER(vp)]
+        L.fciqmc_batch_add.argtypes = [vp, vp]
+        L.fciqmc_batch_remove.argtypes = [vp, vp]
+        L.fciqmc_batch_size.argtypes = [vp]
+        L.fciqmc_batch_step.argtypes = [vp, C.c_int, C.POINTER(StepStats)]
+        L.fciqmc_batch_tune.argtypes = [vp, C.c_int, C.POINTER(TuneReport)]
+        L.fciqmc_batch_profile.argtypes = [vp, C.c_int, pdbl, C.POINTER(i64)]
+        L.fciqmc_batch_free.argtypes = [vp]
+        L.fciqmc_batch_free.restype = None
         L.fciqmc_free_run.argtypes = [vp]
         L.fciqmc_free_run.restype = None
         L.fciqmc_free_system.argtypes = [vp]
@@ -144,10 +161,28 @@ class Run:
     def __init__(self, handle, system):
         self.handle = handle
         self.system = system  # keep the system alive
+        self.batch = None
 
     def free(self):
         if self.handle:
             lib().fciqmc_free_run(self.handle)
+            if self.batch is not None:
+                self.batch.members.remove(self)
+                self.batch = None
+            self.handle = None
+
+
+class Batch:
+    def __init__(self, handle):
+        self.handle = handle
+        self.members = []  # Run objects, in order of addition
+
+    def free(self):
+        if self.handle:
+            lib().fciqmc_batch_free(self.handle)
+            for r in self.members:
+                r.batch = None
+            self.members = []
             self.handle = None
 
 
@@ -262,3 +297,52 @@ def fciqmc_free_run(run: Run):
 
 def fciqmc_free_system(system: System):
     system.free()
+
+
+def fciqmc_batch_create(stream=None) -> Batch:
+    out = C.c_void_p()
+    _check(lib().fciqmc_batch_create(_stream_ptr(stream), C.byref(out)))
+    return Batch(out.value)
+
+
+def fciqmc_batch_add(batch: Batch, run: Run):
+    _check(lib().fciqmc_batch_add(batch.handle, run.handle))
+    batch.members.append(run)
+    run.batch = batch
+
+
+def fciqmc_batch_remove(batch: Batch, run: Run):
+    _check(lib().fciqmc_batch_remove(batch.handle, run.handle))
+    batch.members.remove(run)
+    run.batch = None
+
+
+def fciqmc_batch_size(batch: Batch) -> int:
+    return int(lib().fciqmc_batch_size(batch.handle))
+
+
+def fciqmc_batch_step(batch: Batch, n_steps: int = 1):
+    """Advance every member n_steps; returns [step][member] stats dicts."""
+    m = len(batch.members)
+    arr = (StepStats * max(1, n_steps * m))()
+    _check(lib().fciqmc_batch_step(batch.handle, int(n_steps), arr))
+    return [[{k: getattr(arr[s * m + i], k) for k, _ in StepStats._fields_} for i in range(m)]
+            for s in range(n_steps)]
+
+
+def fciqmc_batch_tune(batch: Batch, trial_steps: int = 20) -> dict:
+    r = TuneReport()
+    _check(lib().fciqmc_batch_tune(batch.handle, int(trial_steps), C.byref(r)))
+    return {k: getattr(r, k) for k, _ in TuneReport._fields_}
+
+
+def fciqmc_batch_profile(batch: Batch, enable: bool = True):
+    """Enable batch kernel timing; returns (ms per kernel dict, batch steps timed)."""
+    ms = np.zeros(len(KERNELS))
+    steps = C.c_int64()
+    _check(lib().fciqmc_batch_profile(batch.handle, int(enable), _p(ms, C.c_double), C.byref(steps)))
+    return dict(zip(KERNELS, ms.tolist())), steps.value
+
+
+def fciqmc_batch_free(batch: Batch):
+    batch.free()

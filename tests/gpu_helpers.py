@@ -16,13 +16,14 @@ def ref_of(s):
     return (1 << s.n_alpha) - 1, (1 << s.n_beta) - 1
 
 
-def make_pair(s, tau, target, gen="uniform", n_a=-1.0, mode="integer", seed=1, zeta=0.05,
-              interval=10, c_min=1.0, det_words=0, n_initial=10.0, p_single=-1.0, p_opp=-1.0,
-              buckets_log2=0, max_spawns=0, stream=None, replica=0):
-    """(gpu_run, oracle_run) started from n_initial walkers on the reference."""
-    g, o = GEN[gen]
+def make_gpu_run(s, tau, target, gen="uniform", n_a=-1.0, mode="integer", seed=1, zeta=0.05,
+                 interval=10, c_min=1.0, det_words=0, n_initial=10.0, p_single=-1.0, p_opp=-1.0,
+                 buckets_log2=0, max_spawns=0, stream=None, replica=0, sysd=None):
+    """(system handle, gpu_run) started from n_initial walkers on the reference."""
+    g, _ = GEN[gen]
     m = F.MODE_INTEGER if mode == "integer" else F.MODE_REAL
-    sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
+    if sysd is None:
+        sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
     ra, rb = ref_of(s)
     p = F.fciqmc_params_default(tau=tau, walker_target=target, initiator_na=n_a, mode=m,
                                 excitgen=g, seed=seed, shift_damping=zeta, shift_interval=interval,
@@ -30,7 +31,20 @@ def make_pair(s, tau, target, gen="uniform", n_a=-1.0, mode="integer", seed=1, z
                                 ref_alpha=ra, ref_beta=rb, p_single=p_single, p_opp=p_opp,
                                 buckets_log2=buckets_log2, max_spawns=max_spawns,
                                 replica_id=replica)
-    run = F.fciqmc_init(sysd, p, stream=stream)
+    return sysd, F.fciqmc_init(sysd, p, stream=stream)
+
+
+def make_pair(s, tau, target, gen="uniform", n_a=-1.0, mode="integer", seed=1, zeta=0.05,
+              interval=10, c_min=1.0, det_words=0, n_initial=10.0, p_single=-1.0, p_opp=-1.0,
+              buckets_log2=0, max_spawns=0, stream=None, replica=0):
+    """(gpu_run, oracle_run) started from n_initial walkers on the reference."""
+    _, o = GEN[gen]
+    sysd, run = make_gpu_run(s, tau, target, gen=gen, n_a=n_a, mode=mode, seed=seed, zeta=zeta,
+                             interval=interval, c_min=c_min, det_words=det_words,
+                             n_initial=n_initial, p_single=p_single, p_opp=p_opp,
+                             buckets_log2=buckets_log2, max_spawns=max_spawns, stream=stream,
+                             replica=replica)
+    ra, rb = ref_of(s)
     words = det_words if det_words else (1 if s.n_orb <= 32 else 2)
     osys = oracle.System.from_inputs(s, words=words)
     orun = oracle.Run(osys, ref=(ra, rb), tau=tau, target=target, n_a=n_a, c_min=c_min,
@@ -78,3 +92,23 @@ def assert_same_stats(g, o, exact_shift=True):
     if exact_shift:
         assert g["shift"] == o["shift"], (g["shift"], o["shift"])
     assert abs(g["enum_"] - o["enum_"]) <= enum_tol(o["enum_"]), (g["enum_"], o["enum_"])
+
+
+def assert_same_gpu_stats(a, b):
+    """Two GPU runs of the same population: every count and the shift agree
+    exactly; the E_proj numerator to the reordered-sum bound (the LDS hash
+    order of a bucket may differ between launches)."""
+    for k in ("nw", "nref", "ndets", "attempts", "spawns", "vary_shift", "shift", "iter"):
+        assert a[k] == b[k], (k, a[k], b[k])
+    assert abs(a["enum_"] - b["enum_"]) <= enum_tol(b["enum_"]), (a["enum_"], b["enum_"])
+
+
+def assert_same_gpu_walkers(r1, r2, exact=True, rtol=0.0):
+    a1, b1, v1 = gpu_walkers(r1)
+    a2, b2, v2 = gpu_walkers(r2)
+    assert len(a1) == len(a2), (len(a1), len(a2))
+    assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+    if exact:
+        assert np.array_equal(v1, v2)
+    else:
+        assert np.allclose(v1, v2, rtol=rtol, atol=0.0)
