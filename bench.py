@@ -122,6 +122,125 @@ def measure(F, np, torch, stream, name, steps, warmup):
     return s, pd, desc, run, sysd, st, wall, ms, nsteps, layout, kern, roof
 
 
+BATCH_DESC = {"workload": "batched_64_synthetic_molecules_8to24_orbitals",
+              "instances": 64, "integral_seeds": "0..63", "philox_seeds": "0..63",
+              "orbitals": "uniform 8..24", "electrons": "2*floor(N/2), Sz=0",
+              "walkers_target": "log-uniform 1e4..1e6 per instance",
+              "tau": "min(0.005, 0.3 / sum_j |H_0j|) per instance",
+              "excitation_generator": "uniform", "walkers": "integer", "initiator": "off",
+              "shift_damping": 0.3, "det_bits": 64}
+
+
+def ref_row_norm(F, np, sysd, s):
+    """sum_j |H_0j| over the single and double excitations of the aufbau
+    reference, with the library's matrix elements."""
+    from itertools import combinations
+    na, nb, N = s.n_alpha, s.n_beta, s.n_orb
+    ra, rb = (1 << na) - 1, (1 << nb) - 1
+    occ_a, vir_a = list(range(na)), list(range(na, N))
+    occ_b, vir_b = list(range(nb)), list(range(nb, N))
+    tgt = []
+    for i in occ_a:
+        for a in vir_a:
+            tgt.append((ra ^ (1 << i) ^ (1 << a), rb))
+    for i in occ_b:
+        for a in vir_b:
+            tgt.append((ra, rb ^ (1 << i) ^ (1 << a)))
+    for (i, j) in combinations(occ_a, 2):
+        for (a, b) in combinations(vir_a, 2):
+            tgt.append((ra ^ (1 << i) ^ (1 << j) ^ (1 << a) ^ (1 << b), rb))
+    for (i, j) in combinations(occ_b, 2):
+        for (a, b) in combinations(vir_b, 2):
+            tgt.append((ra, rb ^ (1 << i) ^ (1 << j) ^ (1 << a) ^ (1 << b)))
+    for i in occ_a:
+        for a in vir_a:
+            for j in occ_b:
+                for b in vir_b:
+                    tgt.append((ra ^ (1 << i) ^ (1 << a), rb ^ (1 << j) ^ (1 << b)))
+    dj = np.array(tgt, dtype=np.uint64)
+    di = np.tile(np.array([[ra, rb]], dtype=np.uint64), (len(dj), 1))
+    return float(np.abs(F.fciqmc_matrix_elements(sysd, di, dj)).sum())
+
+
+def measure_batched(F, np, steps, warmup, grow_max, tune_steps, plain=True):
+    """64 independent molecules advanced as one batch (tuned), then the same
+    populations from the same state advanced one run after another."""
+    from paper_2006_14956_amd import inputs
+    mols = inputs.batched_molecules()
+    systems, runs, params = [], [], []
+    batch = F.fciqmc_batch_create()
+    for i, (s, target) in enumerate(mols):
+        sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
+        # dtau = 0.005, lowered where the reference row would spawn more than
+        # 0.3 walkers per walker and step
+        tau = min(0.005, 0.3 / ref_row_norm(F, np, sysd, s))
+        p = dict(tau=tau, walker_target=target, seed=i, shift_damping=0.3)
+        run = F.fciqmc_init(sysd, F.fciqmc_params_default(**p))
+        F.fciqmc_batch_add(batch, run)
+        systems.append(sysd)
+        runs.append(run)
+        params.append(p)
+    t0 = time.perf_counter()
+    grown = 0
+    while grown < grow_max:
+        st = F.fciqmc_batch_step(batch, 100)
+        grown += 100
+        if all(x["vary_shift"] for x in st[-1]):
+            break
+    last = st[-1]
+    taus = [p["tau"] for p in params]
+    log(f"[batched] dtau per instance: min {min(taus):.4g} max {max(taus):.4g}")
+    log(f"[batched] grown {grown} steps in {time.perf_counter() - t0:.1f}s: "
+        f"{sum(x['vary_shift'] for x in last)}/64 varying, N_w total {sum(x['nw'] for x in last):.4g}")
+    if warmup:
+        F.fciqmc_batch_step(batch, warmup)
+    tune = F.fciqmc_batch_tune(batch, tune_steps)
+    log(f"[batched] tuned: {tune}")
+    # the state both timings start from
+    snap = [(F.fciqmc_get_walkers(r), F.fciqmc_get_checkpoint(r)) for r in runs]
+    F.fciqmc_batch_profile(batch, True)
+    t1 = time.perf_counter()
+    st = F.fciqmc_batch_step(batch, steps)
+    wall = time.perf_counter() - t1
+    ms, nsteps = F.fciqmc_batch_profile(batch, False)
+    att = sum(x["attempts"] for row in st for x in row)
+    final_b = [x["nw"] for x in st[-1]]
+    rate_b = att / wall
+    log(f"[batched] timed {steps} steps in {wall:.3f}s: {rate_b:.4e} attempts/s, "
+        f"{1e3 * wall / steps:.4f} ms/step; kernels (ms total): "
+        + ", ".join(f"{k}={v:.2f}" for k, v in ms.items()))
+    ndets = sum(x["ndets"] for x in st[-1])
+    F.fciqmc_batch_free(batch)
+    for r in runs:
+        F.fciqmc_free_run(r)
+    out = {"config": dict(BATCH_DESC, steps=steps, grown_steps=grown,
+                          walkers_total=float(sum(final_b)), dets_total=int(ndets)),
+           "value": rate_b, "unit": "attempts/s", "ms_per_step": 1e3 * wall / steps,
+           "kernels_ms_per_step": {k: v / max(1, nsteps) for k, v in ms.items()},
+           "tune": tune}
+    if plain:
+        solo = []
+        for i, ((a, b, v), ck) in enumerate(snap):
+            r = F.fciqmc_init(systems[i], F.fciqmc_params_default(**params[i]))
+            F.fciqmc_set_walkers(r, a, b, v)
+            F.fciqmc_set_checkpoint(r, **ck)
+            solo.append(r)
+        t2 = time.perf_counter()
+        sst = [F.fciqmc_step(r, steps) for r in solo]
+        wall_p = time.perf_counter() - t2
+        att_p = sum(x["attempts"] for rs in sst for x in rs)
+        same = all(rs[-1]["nw"] == nb for rs, nb in zip(sst, final_b))
+        log(f"[plain] {steps} steps of each run in turn: {wall_p:.3f}s, {att_p / wall_p:.4e} attempts/s; "
+            f"final populations equal to the batch's: {same}")
+        for r in solo:
+            F.fciqmc_free_run(r)
+        out.update(plain_value=att_p / wall_p, plain_wall_s=wall_p, batched_wall_s=wall,
+                   speedup_vs_plain=wall_p / wall, same_trajectories=same)
+    for sysd in systems:
+        F.fciqmc_free_system(sysd)
+    return out
+
+
 def roofline(kern, k):
     ab = kern[k]["algorithmic_bytes"]
     achieved = ab / (kern[k]["ms_per_launch"] * 1e-3) / 1e9
@@ -142,6 +261,11 @@ def main():
                     help="second workload measured after the first ('' to skip)")
     ap.add_argument("--second-steps", type=int, default=60)
     ap.add_argument("--second-warmup", type=int, default=400)
+    ap.add_argument("--batched-steps", type=int, default=1000,
+                    help="timed steps of the 64-molecule batch (0 to skip)")
+    ap.add_argument("--batched-warmup", type=int, default=200)
+    ap.add_argument("--batched-grow", type=int, default=20000)
+    ap.add_argument("--batched-tune", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -203,6 +327,11 @@ def main():
         F.fciqmc_free_run(run2)
         F.fciqmc_free_system(sys2)
 
+    batched = None
+    if args.batched_steps:
+        batched = measure_batched(F, np, args.batched_steps, args.batched_warmup, args.batched_grow,
+                                  args.batched_tune)
+
     out = {
         "metric": "spawn attempts/s (spawn+annihilate+death)",
         "value": value,
@@ -221,6 +350,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "second_workload": second,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
     if run is not None:

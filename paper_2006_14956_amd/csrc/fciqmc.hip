@@ -61,7 +61,10 @@ struct Arena {
             return fail(FCIQMC_ENOMEM, "device memory budget exceeded (%lld + %zu > %lld bytes)",
                         (long long)bytes, n, (long long)budget);
         hipError_t e = hipMalloc(p, n);
-        if (e != hipSuccess) return fail(FCIQMC_ENOMEM, "hipMalloc(%zu) failed: %s", n, hipGetErrorString(e));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();  // the failure is reported here, not by a later launch check
+            return fail(FCIQMC_ENOMEM, "hipMalloc(%zu) failed: %s", n, hipGetErrorString(e));
+        }
         bytes += (int64_t)n;
         live.push_back(*p);
         sizes.push_back((int64_t)n);
@@ -850,6 +853,7 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
     }
     int finish(fciqmc_step_stats* row) override {
         int rc = 0;
+        std::string msg;
         for (size_t i = 0; i < runs.size(); ++i) {
             fciqmc_run* r = runs[i];
             Ctl out{};
@@ -857,11 +861,15 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
             int64_t attempts = 0;
             const int e = eng(i)->batch_finish(r->t, r->S, hctl[i], out, retries, attempts);
             if (e) {
-                if (!rc) rc = e;
+                if (!rc) {
+                    rc = e;
+                    msg = "batch member " + std::to_string(r->batch_slot) + ": " + g_err;
+                }
                 continue;
             }
             record_step(r, out, retries, attempts, row ? row + r->batch_slot : nullptr);
         }
+        if (rc) g_err = msg;
         return rc;
     }
 };
@@ -929,11 +937,16 @@ static int batch_step_once(fciqmc_batch* b, fciqmc_step_stats* row) {
         ++b->ksteps;
     }
     int rc = 0;
+    std::string msg;
     for (auto& g : b->group)
         if (g) {
             const int e = g->finish(row);
-            if (e && !rc) rc = e;
+            if (e && !rc) {
+                rc = e;
+                msg = g_err;
+            }
         }
+    if (rc) g_err = msg;
     return rc;
 }
 
