@@ -51,6 +51,7 @@ extern "C" {
 typedef struct fciqmc_system fciqmc_system;
 typedef struct fciqmc_run fciqmc_run;
 typedef struct fciqmc_batch fciqmc_batch;
+typedef struct fciqmc_server fciqmc_server;
 
 /* Parameters of one walker population.  fciqmc_params_default() fills every
  * field; callers then override what they need. */
@@ -219,6 +220,61 @@ int fciqmc_batch_tune(fciqmc_batch *batch, int trial_steps, fciqmc_tune_report *
 int fciqmc_batch_profile(fciqmc_batch *batch, int enable, double *ms, int64_t *steps);
 /* Remove every member (they keep their state) and release the batch. */
 void fciqmc_batch_free(fciqmc_batch *batch);
+
+/* ---- Request server: continuous batching of solves --------------------
+ *
+ * A solve is a run from n_initial walkers until its energy report (the
+ * blocking analysis of fciqmc_energy, with the run's conv_tol and
+ * equil_steps) says converged, checked every check_interval of its own
+ * steps, or until max_steps.  Requests wait in arrival order; each poll
+ * step admits the head of the queue while its device-memory reservation
+ * (fciqmc_estimate_bytes) fits the server's budget and fewer than
+ * max_running solves run, then advances every running solve by one step in
+ * one batch (see the batch calls) and retires those that finished, which
+ * frees their memory and slot for the next admission.  A solve's
+ * trajectory, step count and energy report are those of the same run
+ * stepped alone.  Each admitted run is limited to its reservation
+ * (hbm_budget_bytes): outgrowing it fails that request with ENOMEM. */
+
+#define FCIQMC_REQ_QUEUED 0
+#define FCIQMC_REQ_RUNNING 1
+#define FCIQMC_REQ_DONE 2
+#define FCIQMC_REQ_FAILED 3
+
+typedef struct fciqmc_request_info {
+    int state;                  /* FCIQMC_REQ_*                                            */
+    int error;                  /* FAILED: the FCIQMC_E* code of the failure               */
+    int converged;              /* DONE: 1 if the energy criterion ended it, 0 if max_steps */
+    int64_t steps;              /* steps taken                                             */
+    int64_t attempts;           /* spawn attempts made                                     */
+    int64_t reserved_bytes;     /* device memory reserved for it                           */
+    double t_arrival;           /* server clock (seconds since creation)                   */
+    double t_admit, t_done;     /* server clock; -1 until reached                          */
+    fciqmc_energy_report energy; /* at the last check (fields -1 before the first)         */
+} fciqmc_request_info;
+
+/* Device bytes a run with these parameters reserves: its walker store after
+ * one doubling of the bucket count and spawn slabs for twice its walker
+ * target.  Negative FCIQMC_E* on bad arguments. */
+int64_t fciqmc_estimate_bytes(const fciqmc_system *sys, const fciqmc_params *p);
+/* hbm_budget_bytes: device memory the running solves may reserve together;
+ * max_running: largest batch; stream as for fciqmc_init. */
+int fciqmc_server_create(int64_t hbm_budget_bytes, int max_running, void *stream,
+                         fciqmc_server **out);
+/* Queue a solve.  sys is borrowed and must outlive the request; p is copied.
+ * t_arrival: the request's arrival on the server clock (< 0: now), from
+ * which its latency t_done - t_arrival counts.  *ticket identifies it. */
+int fciqmc_server_submit(fciqmc_server *srv, const fciqmc_system *sys, const fciqmc_params *p,
+                         int check_interval, int64_t max_steps, double t_arrival,
+                         int64_t *ticket);
+/* Admit what fits and advance the running solves by up to n_steps batch
+ * steps (fewer when none runs); n_running, n_queued (may be NULL) receive
+ * the counts afterwards. */
+int fciqmc_server_poll(fciqmc_server *srv, int n_steps, int *n_running, int *n_queued);
+int fciqmc_server_info(const fciqmc_server *srv, int64_t ticket, fciqmc_request_info *out);
+double fciqmc_server_clock(const fciqmc_server *srv);
+/* Release every running solve and the server (systems stay the caller's). */
+void fciqmc_server_free(fciqmc_server *srv);
 
 void fciqmc_free_run(fciqmc_run *run);
 void fciqmc_free_system(fciqmc_system *sys);

@@ -22,8 +22,8 @@ HIPCC_FLAGS = [
 
 def build(verbose: bool = False) -> str:
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
-    src = os.path.join(CSRC, "fciqmc.hip")
-    cmd = ["/opt/rocm/bin/hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-o", OUT + ".tmp", src]
+    srcs = [os.path.join(CSRC, "fciqmc.hip"), os.path.join(CSRC, "server.cpp")]
+    cmd = ["/opt/rocm/bin/hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-o", OUT + ".tmp", *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "../../include/fciqmc.h"
+#include "errors.hpp"
 #include "kernels.hpp"
 
 using namespace fq;
@@ -35,6 +36,20 @@ int fail(int code, const char* fmt, ...) {
     g_err = buf;
     return code;
 }
+
+}  // namespace
+
+int fq_set_error(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+namespace {
 
 #define HIP_OK(expr)                                                                           \
     do {                                                                                       \
@@ -1067,6 +1082,37 @@ static bool valid_det(const fciqmc_system* s, uint64_t a, uint64_t b) {
            __builtin_popcountll(b) == s->nb;
 }
 
+// Initial walker-store buckets and spawn-record capacity of a run: from the
+// hints, else from the walker target (both grow on demand).
+static void initial_capacity(const fciqmc_params* p, int& B, long long& spawn_cap) {
+    const double target = std::max(1.0, p->walker_target);
+    int64_t max_dets = p->max_dets > 0 ? p->max_dets : (int64_t)std::min(target, 16777216.0);
+    max_dets = std::max<int64_t>(max_dets, 1024);
+    // kBucketOccupancy determinants of the capacity hint per bucket (the store
+    // holds R = 1024 per bucket; buckets double when one overflows)
+    B = p->buckets_log2 > 0 ? (1 << std::min(p->buckets_log2, 22))
+                            : (int)next_pow2((uint64_t)((max_dets + kBucketOccupancy - 1) / kBucketOccupancy));
+    spawn_cap = p->max_spawns > 0 ? p->max_spawns : (long long)std::min(std::max(65536.0, 1.0 * target), 33554432.0);
+}
+
+// Device bytes a run reserves: its walker store after one doubling of the
+// bucket count and spawn slabs for twice the walker target.
+static int64_t reserve_bytes(const fciqmc_system* sys, const fciqmc_params* p) {
+    int B = 1;
+    long long cap = 0;
+    initial_capacity(p, B, cap);
+    const int W = p->det_words ? p->det_words : (sys->N <= 32 ? 1 : 2);
+    const int64_t vb = p->mode == FCIQMC_MODE_INTEGER ? 4 : 8;
+    const int64_t rb = ((8 * W + vb + 4) + 7) / 8 * 8;          // one spawn record
+    const int64_t B2 = 2 * (int64_t)B;
+    const int64_t entry = 8 * W + vb + 8 + 4;                     // key, value, diagonal, attempt prefix
+    const int64_t store = B2 * 1024 * entry + B2 * (4 + 8 + 8);
+    const int64_t per_bucket = B2 * (kSub * (4 + 8 + 8) + 8 * 4);
+    const double target = std::max(1.0, p->walker_target);
+    const int64_t slabs = (int64_t)(1.25 * std::max<double>((double)cap, 2.0 * target)) * rb;
+    return 2 * store + per_bucket + slabs + (1 << 20);
+}
+
 int fciqmc_init(const fciqmc_system* csys, const fciqmc_params* p, void* stream, fciqmc_run** out) {
     if (!csys || !p || !out) return fail(FCIQMC_EINVAL, "null argument");
     *out = nullptr;
@@ -1123,16 +1169,9 @@ int fciqmc_init(const fciqmc_system* csys, const fciqmc_params* p, void* stream,
     rs.seed = p->seed; rs.replica = p->replica_id;
     rs.ref_a = ra; rs.ref_b = rb;
     rs.gen = p->excitgen;
-    const double target = std::max(1.0, p->walker_target);
-    // capacities start from the hints (or the target) and grow on demand
-    int64_t max_dets = p->max_dets > 0 ? p->max_dets : (int64_t)std::min(target, 16777216.0);
-    max_dets = std::max<int64_t>(max_dets, 1024);
-    // kBucketOccupancy determinants of the capacity hint per bucket (the store
-    // holds R = 1024 per bucket; buckets double when one overflows)
-    int B = p->buckets_log2 > 0 ? (1 << std::min(p->buckets_log2, 22))
-                                : (int)next_pow2((uint64_t)((max_dets + kBucketOccupancy - 1) / kBucketOccupancy));
-    long long spawn_cap = p->max_spawns > 0 ? p->max_spawns
-                                            : (long long)std::min(std::max(65536.0, 1.0 * target), 33554432.0);
+    int B = 1;
+    long long spawn_cap = 0;
+    initial_capacity(p, B, spawn_cap);
     if (W == 1 && p->mode == FCIQMC_MODE_INTEGER) r->eng.reset(new Engine<1, int32_t>(sys, r->stream, rs));
     else if (W == 1) r->eng.reset(new Engine<1, double>(sys, r->stream, rs));
     else if (p->mode == FCIQMC_MODE_INTEGER) r->eng.reset(new Engine<2, int32_t>(sys, r->stream, rs));
@@ -1316,6 +1355,11 @@ void fciqmc_batch_free(fciqmc_batch* b) {
     if (!b) return;
     while (!b->members.empty()) batch_detach(b, b->members.back());
     delete b;
+}
+
+int64_t fciqmc_estimate_bytes(const fciqmc_system* sys, const fciqmc_params* p) {
+    if (!sys || !p) return fail(FCIQMC_EINVAL, "null argument");
+    return reserve_bytes(sys, p);
 }
 
 int64_t fciqmc_run_device_bytes(const fciqmc_run* run) { return run && run->eng ? run->eng->bytes() : 0; }

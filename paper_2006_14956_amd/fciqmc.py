@@ -56,6 +56,16 @@ class Checkpoint(C.Structure):
                 ("last_update_iter", C.c_int64), ("last_update_nw", C.c_double)]
 
 
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int), ("error", C.c_int), ("converged", C.c_int),
+                ("steps", C.c_int64), ("attempts", C.c_int64), ("reserved_bytes", C.c_int64),
+                ("t_arrival", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("energy", EnergyReport)]
+
+
 class TuneReport(C.Structure):
     _fields_ = [("dets_per_bucket", C.c_int), ("grid_spawn", C.c_int), ("grid_annihilate", C.c_int),
                 ("trials", C.c_int), ("steps", C.c_int64), ("rate_initial", C.c_double),
@@ -67,7 +77,9 @@ EXPORTS = ["fciqmc_params_default", "fciqmc_load_integrals", "fciqmc_init", "fci
            "fciqmc_set_checkpoint", "fciqmc_matrix_elements", "fciqmc_run_device_bytes",
            "fciqmc_profile", "fciqmc_batch_create", "fciqmc_batch_add", "fciqmc_batch_remove",
            "fciqmc_batch_size", "fciqmc_batch_step", "fciqmc_batch_tune", "fciqmc_batch_profile",
-           "fciqmc_batch_free",
+           "fciqmc_batch_free", "fciqmc_estimate_bytes", "fciqmc_server_create",
+           "fciqmc_server_submit", "fciqmc_server_poll", "fciqmc_server_info",
+           "fciqmc_server_clock", "fciqmc_server_free",
            "fciqmc_free_run", "fciqmc_free_system", "fciqmc_last_error"]
 
 _lib = None
@@ -114,6 +126,17 @@ def lib():
         L.fciqmc_batch_profile.argtypes = [vp, C.c_int, pdbl, C.POINTER(i64)]
         L.fciqmc_batch_free.argtypes = [vp]
         L.fciqmc_batch_free.restype = None
+        L.fciqmc_estimate_bytes.argtypes = [vp, C.POINTER(Params)]
+        L.fciqmc_estimate_bytes.restype = i64
+        L.fciqmc_server_create.argtypes = [i64, C.c_int, vp, C.POINTER(vp)]
+        L.fciqmc_server_submit.argtypes = [vp, vp, C.POINTER(Params), C.c_int, i64, dbl,
+                                           C.POINTER(i64)]
+        L.fciqmc_server_poll.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.fciqmc_server_info.argtypes = [vp, i64, C.POINTER(RequestInfo)]
+        L.fciqmc_server_clock.argtypes = [vp]
+        L.fciqmc_server_clock.restype = dbl
+        L.fciqmc_server_free.argtypes = [vp]
+        L.fciqmc_server_free.restype = None
         L.fciqmc_free_run.argtypes = [vp]
         L.fciqmc_free_run.restype = None
         L.fciqmc_free_system.argtypes = [vp]
@@ -346,3 +369,61 @@ def fciqmc_batch_profile(batch: Batch, enable: bool = True):
 
 def fciqmc_batch_free(batch: Batch):
     batch.free()
+
+
+def fciqmc_estimate_bytes(system: System, params: Params) -> int:
+    n = int(lib().fciqmc_estimate_bytes(system.handle, C.byref(params)))
+    if n < 0:
+        _check(n)
+    return n
+
+
+class Server:
+    def __init__(self, handle):
+        self.handle = handle
+        self.systems = []  # systems of submitted requests stay alive with the server
+
+    def free(self):
+        if self.handle:
+            lib().fciqmc_server_free(self.handle)
+            self.handle = None
+
+
+def fciqmc_server_create(hbm_budget_bytes: int, max_running: int = 256, stream=None) -> Server:
+    out = C.c_void_p()
+    _check(lib().fciqmc_server_create(int(hbm_budget_bytes), int(max_running), _stream_ptr(stream),
+                                      C.byref(out)))
+    return Server(out.value)
+
+
+def fciqmc_server_submit(server: Server, system: System, params: Params, check_interval: int = 100,
+                         max_steps: int = 100000, t_arrival: float = -1.0) -> int:
+    t = C.c_int64()
+    _check(lib().fciqmc_server_submit(server.handle, system.handle, C.byref(params),
+                                      int(check_interval), int(max_steps), float(t_arrival),
+                                      C.byref(t)))
+    server.systems.append(system)
+    return t.value
+
+
+def fciqmc_server_poll(server: Server, n_steps: int = 1):
+    """Admit and advance; returns (running, queued)."""
+    r, q = C.c_int(), C.c_int()
+    _check(lib().fciqmc_server_poll(server.handle, int(n_steps), C.byref(r), C.byref(q)))
+    return r.value, q.value
+
+
+def fciqmc_server_info(server: Server, ticket: int) -> dict:
+    i = RequestInfo()
+    _check(lib().fciqmc_server_info(server.handle, int(ticket), C.byref(i)))
+    d = {k: getattr(i, k) for k, _ in RequestInfo._fields_ if k != "energy"}
+    d["energy"] = {k: getattr(i.energy, k) for k, _ in EnergyReport._fields_}
+    return d
+
+
+def fciqmc_server_clock(server: Server) -> float:
+    return float(lib().fciqmc_server_clock(server.handle))
+
+
+def fciqmc_server_free(server: Server):
+    server.free()

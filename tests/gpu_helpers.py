@@ -112,3 +112,30 @@ def assert_same_gpu_walkers(r1, r2, exact=True, rtol=0.0):
         assert np.array_equal(v1, v2)
     else:
         assert np.allclose(v1, v2, rtol=rtol, atol=0.0)
+
+
+def solve_alone(sysd, params, interval, max_steps):
+    """The plain path of one solve: step the run alone, check its energy
+    report every `interval` steps, stop when converged or at max_steps.
+    Returns (steps, attempts, energy report)."""
+    run = F.fciqmc_init(sysd, params)
+    steps, att = 0, 0
+    while True:
+        n = min(interval - steps % interval, max_steps - steps)
+        st = F.fciqmc_step(run, n)
+        steps += n
+        att += sum(x["attempts"] for x in st)
+        e = F.fciqmc_energy(run)
+        if e["converged"] or steps >= max_steps:
+            break
+    F.fciqmc_free_run(run)
+    return steps, att, e
+
+
+def assert_same_report(a, b):
+    """Energy reports of the same trajectory: shift statistics exact, the
+    projected energy to the reordered-sum bound of its numerator."""
+    for k in ("shift", "shift_err", "e_ref", "n_samples", "first_step", "steps_done", "converged"):
+        assert a[k] == b[k] or (a[k] != a[k] and b[k] != b[k]), (k, a[k], b[k])
+    for k in ("e_proj", "e_proj_err"):
+        assert abs(a[k] - b[k]) <= 1e-8 * max(1.0, abs(b[k])) or (a[k] != a[k] and b[k] != b[k]), (k, a[k], b[k])
