@@ -241,6 +241,165 @@ def measure_batched(F, np, steps, warmup, grow_max, tune_steps, plain=True):
     return out
 
 
+SERVED_CLASSES = {
+    # class: (shape, walker target, check interval, step cap)
+    "A": ("8 electrons in 8 orbitals, uniform generator, integer, tau 0.01", 1e4, 100, 20000),
+    "B": ("4x4 Hubbard U=4, lattice generator, initiator 3, integer, tau 0.005", 1e5, 100, 5000),
+    "C": ("26 electrons in 40 orbitals, PCHB, initiator 3, real, tau 0.0012", 1e5, 100, 2000),
+}
+
+
+def served_stream(n, rate, seed):
+    """Poisson arrivals and a 70/25/5 class mix from one seeded stream."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    for i in range(n):
+        t += rng.exponential(1.0 / rate)
+        u = rng.random()
+        out.append((t, "A" if u < 0.70 else ("B" if u < 0.95 else "C"), i))
+    return out
+
+
+def served_inputs(F, cls, i, tol):
+    """Host integrals and run parameters of request i of class cls."""
+    from paper_2006_14956_amd import inputs
+    shape, target, interval, cap = SERVED_CLASSES[cls]
+    if cls == "A":
+        s = inputs.synthetic_molecule(8, 4, 4, seed=i, rank=16)
+        p = dict(tau=0.01, walker_target=target, seed=i, conv_tol=tol)
+    elif cls == "B":
+        s = inputs.hubbard_4x4()
+        p = dict(tau=0.005, walker_target=target, initiator_na=3.0, excitgen=F.GEN_LATTICE, seed=i,
+                 shift_damping=0.3, ref_alpha=s.ref_alpha, ref_beta=s.ref_beta, conv_tol=tol)
+    else:
+        s = inputs.synthetic_molecule(40, 13, 13, seed=i, rank=40, damping=8.0)
+        p = dict(tau=0.0012, walker_target=target, initiator_na=3.0, mode=F.MODE_REAL, c_min=1.0,
+                 excitgen=F.GEN_PCHB, seed=i, shift_damping=0.3, n_initial=100.0, conv_tol=tol)
+    return s, p, interval, cap
+
+
+def solve_alone(F, sysd, params, interval, max_steps):
+    run = F.fciqmc_init(sysd, params)
+    steps, att = 0, 0
+    while True:
+        n = min(interval - steps % interval, max_steps - steps)
+        st = F.fciqmc_step(run, n)
+        steps += n
+        att += sum(x["attempts"] for x in st)
+        e = F.fciqmc_energy(run)
+        if e["converged"] or steps >= max_steps:
+            break
+    F.fciqmc_free_run(run)
+    return steps, att, e
+
+
+def pct(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+def measure_served(F, np, n_req, rate, tol, budget, plain=True):
+    """Requests arriving as a Poisson stream, served by continuous batching,
+    then the same requests run alone one after another (first come, first
+    served) for the plain latencies."""
+    reqs = served_stream(n_req, rate, 0)
+    data = {i: served_inputs(F, cls, i, tol) for _, cls, i in reqs}  # client-side inputs
+    srv = F.fciqmc_server_create(budget, max_running=512)
+    t0 = F.fciqmc_server_clock(srv)
+    tickets, systems = {}, []
+    k = 0
+    peak = 0
+    polls = 0
+    while True:
+        now = F.fciqmc_server_clock(srv) - t0
+        while k < n_req and reqs[k][0] <= now:
+            t_arr, cls, i = reqs[k]
+            s, p, interval, cap = data[i]
+            sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
+            systems.append(sysd)
+            tickets[i] = F.fciqmc_server_submit(srv, sysd, F.fciqmc_params_default(**p), interval, cap,
+                                                t_arrival=t0 + t_arr)
+            k += 1
+        running, queued = F.fciqmc_server_poll(srv, 10)
+        polls += 1
+        peak = max(peak, running)
+        if running == 0 and queued == 0:
+            if k == n_req:
+                break
+            time.sleep(max(0.0, reqs[k][0] - (F.fciqmc_server_clock(srv) - t0)))
+    infos = {i: F.fciqmc_server_info(srv, t) for i, t in tickets.items()}
+    F.fciqmc_server_free(srv)
+    for sysd in systems:
+        F.fciqmc_free_system(sysd)
+    lat = {i: x["t_done"] - x["t_arrival"] for i, x in infos.items()}
+    first = min(x["t_arrival"] for x in infos.values())
+    last = max(x["t_done"] for x in infos.values())
+    att = sum(x["attempts"] for x in infos.values())
+    failed = [i for i, x in infos.items() if x["state"] != F.REQ_DONE]
+    out = {"config": {"workload": "served_poisson_stream", "requests": n_req, "rate_per_s": rate,
+                      "stream_seed": 0, "mix": "70/25/5", "conv_tol_hartree": tol,
+                      "hbm_budget_bytes": budget,
+                      "classes": {c: {"shape": v[0], "walkers_target": v[1], "check_interval": v[2],
+                                      "max_steps": v[3]} for c, v in SERVED_CLASSES.items()},
+                      "integral_and_philox_seed": "request index"},
+           "value": att / (last - first), "unit": "attempts/s",
+           "latency_p50_s": pct(list(lat.values()), 50), "latency_p99_s": pct(list(lat.values()), 99),
+           "makespan_s": last - first, "peak_running": peak, "failed": len(failed),
+           "failed_errors": sorted({infos[i]["error"] for i in failed})}
+    per = {}
+    for c in SERVED_CLASSES:
+        ids = [i for _, cc, i in reqs if cc == c]
+        per[c] = {"requests": len(ids), "converged": sum(infos[i]["converged"] for i in ids),
+                  "latency_p50_s": pct([lat[i] for i in ids], 50),
+                  "latency_p99_s": pct([lat[i] for i in ids], 99),
+                  "steps_mean": float(np.mean([infos[i]["steps"] for i in ids])) if ids else None}
+    out["classes"] = per
+    log(f"[served] {n_req} requests, makespan {last - first:.2f}s, {out['value']:.4e} attempts/s, "
+        f"latency p50 {out['latency_p50_s']:.3f}s p99 {out['latency_p99_s']:.3f}s, peak running {peak}, "
+        f"failed {len(failed)}; per class {per}")
+    if plain:
+        # integer classes: identical steps, attempts and shift; real-coefficient
+        # class: sums rounded in another order may flip a stochastic rounding,
+        # so the shifts must agree within their combined error bar
+        service, same, max_de, max_z = [], 0, 0.0, 0.0
+        for t_arr, cls, i in reqs:
+            s, p, interval, cap = data[i]
+            c0 = time.perf_counter()
+            sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
+            steps, a, e = solve_alone(F, sysd, F.fciqmc_params_default(**p), interval, cap)
+            F.fciqmc_free_system(sysd)
+            service.append((time.perf_counter() - c0, a))
+            x = infos[i]
+            if p.get("mode", F.MODE_INTEGER) == F.MODE_INTEGER:
+                ok = (x["steps"] == steps and x["attempts"] == a and x["converged"] == e["converged"]
+                      and x["energy"]["shift"] == e["shift"])
+                if e["shift"] == e["shift"]:
+                    max_de = max(max_de, abs(x["energy"]["shift"] - e["shift"]))
+            else:
+                d = abs(x["energy"]["shift"] - e["shift"])
+                err = (x["energy"]["shift_err"] ** 2 + e["shift_err"] ** 2) ** 0.5
+                z = d / err if err > 0 else (0.0 if d == 0 else float("inf"))
+                max_z = max(max_z, z)
+                ok = x["steps"] == steps and x["state"] == F.REQ_DONE and z < 3.0
+            same += int(ok)
+        done, lat_p = 0.0, []
+        for (t_arr, _, _), (sv, _) in zip(reqs, service):
+            done = max(done, t_arr) + sv
+            lat_p.append(done - t_arr)
+        busy = sum(sv for sv, _ in service)
+        out.update(plain_value=sum(a for _, a in service) / busy,
+                   plain_latency_p50_s=pct(lat_p, 50), plain_latency_p99_s=pct(lat_p, 99),
+                   plain_busy_s=busy, plain_makespan_s=done,
+                   same_result_alone_and_in_mix=same, max_shift_difference_integer=max_de,
+                   max_shift_z_real=max_z)
+        log(f"[plain] busy {busy:.2f}s, {out['plain_value']:.4e} attempts/s, FIFO latency p50 "
+            f"{out['plain_latency_p50_s']:.3f}s p99 {out['plain_latency_p99_s']:.3f}s; same result alone "
+            f"and in the mix: {same}/{n_req}, max |shift difference| (integer) {max_de:.3g}, "
+            f"max shift z (real) {max_z:.3g}")
+    return out
+
+
 def roofline(kern, k):
     ab = kern[k]["algorithmic_bytes"]
     achieved = ab / (kern[k]["ms_per_launch"] * 1e-3) / 1e9
@@ -266,6 +425,11 @@ def main():
     ap.add_argument("--batched-warmup", type=int, default=200)
     ap.add_argument("--batched-grow", type=int, default=20000)
     ap.add_argument("--batched-tune", type=int, default=10)
+    ap.add_argument("--served-requests", type=int, default=100,
+                    help="requests of the served stream (0 to skip)")
+    ap.add_argument("--served-rate", type=float, default=20.0)
+    ap.add_argument("--served-tol", type=float, default=0.01)
+    ap.add_argument("--served-budget", type=float, default=200e9)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -332,6 +496,11 @@ def main():
         batched = measure_batched(F, np, args.batched_steps, args.batched_warmup, args.batched_grow,
                                   args.batched_tune)
 
+    served = None
+    if args.served_requests:
+        served = measure_served(F, np, args.served_requests, args.served_rate, args.served_tol,
+                                int(args.served_budget))
+
     out = {
         "metric": "spawn attempts/s (spawn+annihilate+death)",
         "value": value,
@@ -351,6 +520,7 @@ def main():
         "cpu_baseline": cpu,
         "second_workload": second,
         "batched": batched,
+        "served": served,
     }
     print(json.dumps(out), flush=True)
     if run is not None:

@@ -253,9 +253,11 @@ typedef struct fciqmc_request_info {
     fciqmc_energy_report energy; /* at the last check (fields -1 before the first)         */
 } fciqmc_request_info;
 
-/* Device bytes a run with these parameters reserves: its walker store after
- * one doubling of the bucket count and spawn slabs for twice its walker
- * target.  Negative FCIQMC_E* on bad arguments. */
+/* Device bytes a run with these parameters reserves: a walker store of one
+ * bucket (1024 entries) per 256 target walkers and at least twice the
+ * initial buckets, spawn slabs for three records per target walker, and the
+ * staging buffer of a population import.  Negative FCIQMC_E* on bad
+ * arguments. */
 int64_t fciqmc_estimate_bytes(const fciqmc_system *sys, const fciqmc_params *p);
 /* hbm_budget_bytes: device memory the running solves may reserve together;
  * max_running: largest batch; stream as for fciqmc_init. */

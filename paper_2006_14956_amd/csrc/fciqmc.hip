@@ -1095,8 +1095,11 @@ static void initial_capacity(const fciqmc_params* p, int& B, long long& spawn_ca
     spawn_cap = p->max_spawns > 0 ? p->max_spawns : (long long)std::min(std::max(65536.0, 1.0 * target), 33554432.0);
 }
 
-// Device bytes a run reserves: its walker store after one doubling of the
-// bucket count and spawn slabs for twice the walker target.
+// Device bytes a run reserves: a walker store of one bucket per 256 walkers
+// of the target (a bucket's LDS table holds about that many determinants
+// next to their spawn targets), at least one doubling of the initial store;
+// spawn slabs for three records per target walker plus the per-sub-slab
+// floor; the import staging buffer.
 static int64_t reserve_bytes(const fciqmc_system* sys, const fciqmc_params* p) {
     int B = 1;
     long long cap = 0;
@@ -1104,13 +1107,15 @@ static int64_t reserve_bytes(const fciqmc_system* sys, const fciqmc_params* p) {
     const int W = p->det_words ? p->det_words : (sys->N <= 32 ? 1 : 2);
     const int64_t vb = p->mode == FCIQMC_MODE_INTEGER ? 4 : 8;
     const int64_t rb = ((8 * W + vb + 4) + 7) / 8 * 8;          // one spawn record
-    const int64_t B2 = 2 * (int64_t)B;
-    const int64_t entry = 8 * W + vb + 8 + 4;                     // key, value, diagonal, attempt prefix
-    const int64_t store = B2 * 1024 * entry + B2 * (4 + 8 + 8);
-    const int64_t per_bucket = B2 * (kSub * (4 + 8 + 8) + 8 * 4);
     const double target = std::max(1.0, p->walker_target);
-    const int64_t slabs = (int64_t)(1.25 * std::max<double>((double)cap, 2.0 * target)) * rb;
-    return 2 * store + per_bucket + slabs + (1 << 20);
+    const int64_t Br = std::max<int64_t>(2 * (int64_t)B, (int64_t)next_pow2((uint64_t)std::ceil(target / 256.0)));
+    const int64_t entry = 8 * W + vb + 8 + 4;                     // key, value, diagonal, attempt prefix
+    const int64_t store = Br * 1024 * entry + Br * (4 + 8 + 8);
+    const int64_t per_bucket = Br * (kSub * (4 + 8 + 8) + 8 * 4);
+    const double recs = std::max<double>((double)cap, 3.0 * target) + 256.0 * (double)Br;
+    const int64_t slabs = (int64_t)(1.25 * recs) * rb;
+    const int64_t stage = (int64_t)target * rb;
+    return 2 * store + per_bucket + slabs + stage + (1 << 20);
 }
 
 int fciqmc_init(const fciqmc_system* csys, const fciqmc_params* p, void* stream, fciqmc_run** out) {
