@@ -75,7 +75,10 @@ typedef struct fciqmc_params {
     int64_t max_dets;       /* capacity hint for occupied determinants (0 = from target)  */
     int64_t max_spawns;     /* capacity hint for spawn records per step (0 = from target) */
     int64_t hbm_budget_bytes; /* device memory this run may hold (0 = no limit)           */
-    int buckets_log2;       /* hash-partition count 2^k of the walker store (0 = auto)    */
+    int buckets_log2;       /* hash-partition count 2^k of the walker store (0 = auto: from
+                               the target, doubled whenever a step leaves more than 600
+                               occupied determinants per bucket on average; k > 0 fixes it
+                               except where a bucket overflows)                             */
     int det_words;          /* 1 (N <= 32) or 2 (N <= 63) uint64 per determinant; 0 auto  */
     double conv_tol;        /* energy agreement tolerance for the report (Hartree)        */
     int equil_steps;        /* steps after the shift starts varying that the report drops */

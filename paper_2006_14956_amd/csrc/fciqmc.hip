@@ -187,6 +187,7 @@ static int build_pchb(fciqmc_system* s, hipStream_t stream) {
 // width W and value type V (int32 walker numbers or FP64 coefficients).
 // ---------------------------------------------------------------------------
 struct EngineBase {
+    bool fixed_b = false;  // the caller fixed the bucket count: no growth by occupancy
     virtual ~EngineBase() {}
     virtual int step_once(int64_t t, double S, Ctl& out, int& retries, int64_t& attempts) = 0;
     virtual int set_walkers(const uint64_t* dets, const double* vals, int64_t n) = 0;
@@ -216,6 +217,9 @@ constexpr int kKernels = 3;
 #endif
 // determinants of the capacity hint per bucket of the walker store
 constexpr int kBucketOccupancy = FQ_OCCUPANCY;
+// mean occupied determinants per bucket above which the store doubles its
+// bucket count after a step (the per-bucket hash tables stay below ~3/4 load)
+constexpr int64_t kMaxMeanOccupancy = 600;
 
 struct RunScalars {
     double tau, p_single, p_double, p_opp, n_a, c_min, h00;
@@ -243,6 +247,8 @@ template <int W, class V> struct Engine : EngineBase {
     int64_t* recs_b = nullptr;  // records per bucket this step, B
     PostPart* part = nullptr;   // partial totals of the multi-workgroup post work
     double *nw_b = nullptr, *en_b = nullptr;
+    uint16_t* fpos = nullptr;   // per bucket: output positions of new determinants (molecular systems)
+    int32_t* fcnt = nullptr;    // per bucket: their number
     Ctl* ctl = nullptr;
     Ctl* hctl = nullptr;  // pinned
     int64_t att_next = 0;
@@ -323,6 +329,10 @@ template <int W, class V> struct Engine : EngineBase {
         HIP_OK(hipMemsetAsync(soff, 0, sizeof(int64_t) * (B * kSub + 1), stream));
         CHECK(dalloc(arena, &nw_b, (size_t)B));
         CHECK(dalloc(arena, &en_b, (size_t)B));
+        if (!sys->onsite) {
+            CHECK(dalloc(arena, &fpos, (size_t)B * R));
+            CHECK(dalloc(arena, &fcnt, (size_t)B));
+        }
         return 0;
     }
     void free_buckets() {
@@ -332,7 +342,9 @@ template <int W, class V> struct Engine : EngineBase {
         arena.release(rel); arena.release(need_b); arena.release(recs_b); arena.release(part);
         rel = nullptr; need_b = nullptr; recs_b = nullptr; part = nullptr;
         arena.release(nw_b); arena.release(en_b);
+        arena.release(fpos); arena.release(fcnt);
         scount = nullptr; soff = nullptr; nw_b = en_b = nullptr;
+        fpos = nullptr; fcnt = nullptr;
     }
     // Grow the slab buffer to hold c records (contents are not kept).
     int ensure_slabs(long long c) {
@@ -380,7 +392,12 @@ template <int W, class V> struct Engine : EngineBase {
         Store<V> in = st[cur], out = st[1 - cur];
         const int gb = std::min(B, 32768);
         hipLaunchKernelGGL((k_annihilate<W, V>), dim3(gb), dim3(kThreads), 0, stream, v, in, out, sc,
-                           rec2, soff, scount, rel, need_b, recs_b, nw_b, en_b, ctl);
+                           rec2, soff, scount, rel, need_b, recs_b, nw_b, en_b, fpos, fcnt, ctl);
+        if (!sys->onsite) {
+            const int64_t items = (B + kFreshSpan - 1) / kFreshSpan;
+            hipLaunchKernelGGL((k_fresh<W, V>), dim3((unsigned)std::min<int64_t>(items, 4096)), dim3(kThreads),
+                               fresh_lds_bytes(sys->N), stream, v, out, sc, fpos, fcnt, ctl);
+        }
         mark(2);
         if (sc.import_mode) {
             // slabs of the first step after an import: from the imported counts
@@ -568,15 +585,19 @@ template <int W, class V> struct Engine : EngineBase {
         return fail(FCIQMC_EDEVICE, "device flags 0x%x", flags);
     }
 
-    // Accept the step: swap the stores, take the next step's sizes.
+    // Accept the step: swap the stores, take the next step's sizes; double
+    // the bucket count when the mean occupancy has grown past the bound.
     int complete(Ctl& out) {
         cur = 1 - cur;
         att_next = hctl->attempts;
         rec_need = hctl->rec_need;
-        CHECK(ensure_slabs(rec_need));
         out = *hctl;
         out.nref = hctl->nref_out;
-        return 0;
+        if (hctl->ndets > kMaxMeanOccupancy * (int64_t)B && (int64_t)B * 2 <= max_b && !fixed_b) {
+            CHECK(grow_buckets());
+            return 0;
+        }
+        return ensure_slabs(rec_need);
     }
 
     // Launch the step alone until it fits.
@@ -615,7 +636,7 @@ template <int W, class V> struct Engine : EngineBase {
         d.out = st[1 - cur];
         d.sc = scalars(t, S, 0);
         d.rec2 = rec2; d.soff = soff; d.rel = rel; d.need_b = need_b; d.recs_b = recs_b;
-        d.scount = scount; d.nw_b = nw_b; d.en_b = en_b; d.ctl = ctl;
+        d.scount = scount; d.nw_b = nw_b; d.en_b = en_b; d.fpos = fpos; d.fcnt = fcnt; d.ctl = ctl;
         chunks = (att_next + kChunk - 1) / kChunk;
         return 0;
     }
@@ -763,13 +784,16 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
     using E = Engine<W, V>;
     Arena arena;
     size_t cap = 0;             // instances the buffers hold
-    char* hbuf = nullptr;       // pinned: Inst[cap], bucket prefix [cap+1], chunk prefixes [cap+3]
+    char* hbuf = nullptr;       // pinned: Inst[cap], bucket prefix [cap+1], chunk prefixes [cap+3],
+                                // diagonal work-item prefix [cap+1]
     char* dbuf = nullptr;       // device copy of hbuf
     Ctl* hctl = nullptr;        // pinned read-back, one per instance
     Ctl* dctl = nullptr;
     int g0[4] = {0, 0, 0, 0};   // first instance of each generator, g0[3] = n
     int64_t ctot[3] = {0, 0, 0};
     int64_t btot = 0;
+    int64_t ftot = 0;           // work items of the new-diagonal kernel
+    size_t flds = 0;            // its LDS bytes (largest molecular member)
 
     ~BatchGroup() override {
         if (hbuf) (void)hipHostFree(hbuf);
@@ -777,9 +801,10 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
         arena.clear();
     }
     E* eng(size_t i) const { return static_cast<E*>(runs[i]->eng.get()); }
-    static size_t bytes_for(size_t n) { return sizeof(Inst<W, V>) * n + sizeof(int64_t) * (2 * n + 4); }
+    static size_t bytes_for(size_t n) { return sizeof(Inst<W, V>) * n + sizeof(int64_t) * (3 * n + 5); }
     int64_t* bfirst(char* base) const { return reinterpret_cast<int64_t*>(base + sizeof(Inst<W, V>) * cap); }
     int64_t* cfirst(char* base) const { return bfirst(base) + cap + 1; }
+    int64_t* ffirst(char* base) const { return cfirst(base) + cap + 3; }
 
     int reserve(size_t n) {
         if (n <= cap) return 0;
@@ -805,14 +830,23 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
         Inst<W, V>* hi = reinterpret_cast<Inst<W, V>*>(hbuf);
         int64_t* bf = bfirst(hbuf);
         int64_t* cf = cfirst(hbuf);
+        int64_t* ff = ffirst(hbuf);
         std::vector<int64_t> chunks(n);
         btot = 0;
+        ftot = 0;
+        flds = 0;
         for (size_t i = 0; i < n; ++i) {
             CHECK(eng(i)->batch_prepare(runs[i]->t, runs[i]->S, hi[i], chunks[i]));
             bf[i] = btot;
             btot += eng(i)->B;
+            ff[i] = ftot;
+            if (!hi[i].sys.onsite) {
+                ftot += (eng(i)->B + kFreshSpan - 1) / kFreshSpan;
+                flds = std::max(flds, fresh_lds_bytes(hi[i].sys.N));
+            }
         }
         bf[n] = btot;
+        ff[n] = ftot;
         // generator ranges; range g keeps its chunk prefix in cf[g0[g] + g .. g0[g+1] + g]
         int k = 0;
         for (int g = 0; g < 3; ++g) {
@@ -855,6 +889,10 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
         const unsigned gs = (unsigned)(grid > 0 ? std::min<int64_t>(btot, grid) : btot);
         hipLaunchKernelGGL((k_annihilate_batch<W, V>), dim3(gs), dim3(kThreads), 0, s,
                            reinterpret_cast<const Inst<W, V>*>(dbuf), (const int64_t*)bfirst(dbuf), (int)runs.size());
+        if (ftot > 0)
+            hipLaunchKernelGGL((k_fresh_batch<W, V>), dim3((unsigned)std::min<int64_t>(ftot, 4096)), dim3(kThreads),
+                               flds, s, reinterpret_cast<const Inst<W, V>*>(dbuf), (const int64_t*)ffirst(dbuf),
+                               (int)runs.size());
         HIP_OK(hipGetLastError());
         return 0;
     }
@@ -1187,6 +1225,7 @@ int fciqmc_init(const fciqmc_system* csys, const fciqmc_params* p, void* stream,
     else if (p->mode == FCIQMC_MODE_INTEGER) rc = static_cast<Engine<2, int32_t>*>(r->eng.get())->init(B, spawn_cap, p->hbm_budget_bytes);
     else rc = static_cast<Engine<2, double>*>(r->eng.get())->init(B, spawn_cap, p->hbm_budget_bytes);
     if (rc) return rc;
+    r->eng->fixed_b = p->buckets_log2 > 0;
     uint64_t ab[2] = {ra, rb};
     double v0 = p->n_initial;
     CHECK(r->eng->set_walkers(ab, &v0, 1));

@@ -304,13 +304,8 @@ template <int W, class V> struct LdsTable {
 };
 
 template <int W, class V> struct Lds {
-    union {
-        LdsTable<W, V> t;
-        // after compaction: h_pp, the same-spin pair term X and J staged for
-        // the diagonals of new determinants
-        double diag_tabs[sizeof(LdsTable<W, V>) / sizeof(double)];
-    };
-    int32_t fresh[kFresh]; // new survivors awaiting their diagonal: slot | out position << 11
+    LdsTable<W, V> t;
+    int32_t fresh[kFresh]; // lattice systems: new survivors awaiting their diagonal, slot | out position << 11
     int nfresh;
     int64_t sh64[8];
     double shd[8];
@@ -460,7 +455,8 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
                                                   int64_t* __restrict__ soff, int32_t* __restrict__ scount,
                                                   int64_t* __restrict__ rel, int64_t* __restrict__ need_b,
                                                   int64_t* __restrict__ recs_b, double* __restrict__ nw_b,
-                                                  double* __restrict__ en_b, Ctl* ctl, int b, Lds<W, V>& L) {
+                                                  double* __restrict__ en_b, uint16_t* __restrict__ fpos,
+                                                  int32_t* __restrict__ fcnt, Ctl* ctl, int b, Lds<W, V>& L) {
     const Key<W> ref = make_key<W>(sc.ref_a, sc.ref_b);
     constexpr bool kInt = sizeof(V) == 4;
     const int64_t eb = (int64_t)b * sc.R;
@@ -598,11 +594,16 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
             const uint64_t ka = key_alpha<W>(key), kb = key_beta<W>(key);
             if (oi >= 0) {
                 out.diag[o] = in.diag[eb + oi];
-            } else {
-                // new determinant: its diagonal is computed below, one per lane
+            } else if (sys.onsite) {
+                // new determinant of a lattice system: its (short) diagonal is
+                // computed below, spread over the workgroup
                 const int f = atomicAdd(&L.nfresh, 1);
                 if (f < kFresh) L.fresh[f] = s | ((int)pos << 11);
                 else { const double hd = h_diag(sys, ka, kb); out.diag[o] = hd - sc.h00; }
+            } else {
+                // new determinant: listed for the diagonal kernel (k_fresh)
+                const int f = atomicAdd(&L.nfresh, 1);
+                fpos[eb + f] = (uint16_t)pos;
             }
             const double av = vabs(v);
             nw = nw + av;
@@ -627,42 +628,22 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
     en = wave_sum(en);
     if (lane_id() == 0) { L.shd[threadIdx.x >> 6] = nw; L.shd[4 + (threadIdx.x >> 6)] = en; }
     __syncthreads();
-    // diagonals of the new determinants, spread over the workgroup; the
-    // keys go to registers, then the dead hash table holds h_pp, X and J
-    const int nf = min(L.nfresh, kFresh);
-    Key<W> fk[kFresh / kThreads];
-    int64_t fo[kFresh / kThreads];
+    if (sys.onsite) {
+        // diagonals of new lattice determinants, spread over the workgroup
+        const int nf = min(L.nfresh, kFresh);
 #pragma unroll
-    for (int i = 0; i < kFresh / kThreads; ++i) {
-        const int f = threadIdx.x + i * kThreads;
-        fo[i] = -1;
-        if (f < nf) {
+        for (int i = 0; i < kFresh / kThreads; ++i) {
+            const int f = threadIdx.x + i * kThreads;
+            if (f >= nf) continue;
             const int s = L.fresh[f] & 2047;
-            fo[i] = eb + (L.fresh[f] >> 11);
-            fk[i].w[0] = L.t.key0[s];
-            if constexpr (W == 2) fk[i].w[1] = L.t.key1[s];
+            Key<W> fk;
+            fk.w[0] = L.t.key0[s];
+            if constexpr (W == 2) fk.w[1] = L.t.key1[s];
+            const double h = h_diag(sys, key_alpha<W>(fk), key_beta<W>(fk));
+            out.diag[eb + (L.fresh[f] >> 11)] = h - sc.h00;
         }
-    }
-    const int N = sys.N;
-    const bool stage = nf > 0 && !sys.onsite &&
-                       (int64_t)N + 2 * (int64_t)N * N <= (int64_t)(sizeof(L.diag_tabs) / sizeof(double));
-    if (stage) {
-        __syncthreads();
-        double* hd = L.diag_tabs;
-        double* xt = hd + N;
-        double* jt = xt + N * N;
-        for (int i = threadIdx.x; i < N * N; i += kThreads) { xt[i] = sys.X[i]; jt[i] = sys.J[i]; }
-        for (int i = threadIdx.x; i < N; i += kThreads) hd[i] = sys.Hd[i];
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < kFresh / kThreads; ++i) {
-        if (fo[i] < 0) continue;
-        const uint64_t ka = key_alpha<W>(fk[i]), kb = key_beta<W>(fk[i]);
-        double h;
-        if (stage) h = h_diag_tab(L.diag_tabs, L.diag_tabs + N, L.diag_tabs + N + N * N, N, ka, kb);
-        else h = h_diag(sys, ka, kb);
-        out.diag[fo[i]] = h - sc.h00;
+    } else if (threadIdx.x == 0) {
+        fcnt[b] = L.nfresh;
     }
     if (threadIdx.x == 0) {
         nw_b[b] = ((L.shd[0] + L.shd[1]) + L.shd[2]) + L.shd[3];
@@ -683,12 +664,76 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
                                                          int64_t* __restrict__ need_b,
                                                          int64_t* __restrict__ recs_b,
                                                          double* __restrict__ nw_b,
-                                                         double* __restrict__ en_b, Ctl* ctl) {
+                                                         double* __restrict__ en_b,
+                                                         uint16_t* __restrict__ fpos,
+                                                         int32_t* __restrict__ fcnt, Ctl* ctl) {
     __shared__ Lds<W, V> L;
     __shared__ unsigned fl;
     if (wg_flags(ctl, &fl)) return;
     for (int b = blockIdx.x; b < sc.B; b += gridDim.x)
-        annihilate_bucket<W, V>(sys, in, out, sc, rec2, soff, scount, rel, need_b, recs_b, nw_b, en_b, ctl, b, L);
+        annihilate_bucket<W, V>(sys, in, out, sc, rec2, soff, scount, rel, need_b, recs_b, nw_b, en_b, fpos, fcnt,
+                                ctl, b, L);
+}
+
+// ---------------------------------------------------------------------------
+// Diagonals H_jj - H_00 of the determinants that entered the store this step
+// (molecular systems; lattice systems compute theirs in the per-bucket
+// kernel).  Work item g covers buckets [g*kFreshSpan, (g+1)*kFreshSpan): h_pp,
+// X and J are staged in LDS, then one lane per listed determinant sums its
+// diagonal in the canonical order.  Done here rather than in the per-bucket
+// kernel because each diagonal is a long serial chain that would hold that
+// kernel's LDS hash table while one wave works.
+// ---------------------------------------------------------------------------
+constexpr int kFreshSpan = 32;
+
+__host__ __device__ inline size_t fresh_lds_bytes(int N) { return sizeof(double) * ((size_t)N + 2 * (size_t)N * N); }
+
+template <int W, class V>
+__device__ __forceinline__ void fresh_item(const SysView& sys, const Store<V>& out, double h00, int R, int B,
+                                           const uint16_t* __restrict__ fpos, const int32_t* __restrict__ fcnt,
+                                           int64_t g, double* tabs, int* pre) {
+    const int b0 = (int)(g * kFreshSpan);
+    const int nb = min(kFreshSpan, B - b0);
+    const int N = sys.N;
+    double* hd = tabs;
+    double* xt = tabs + N;
+    double* jt = xt + N * N;
+    for (int i = threadIdx.x; i < N * N; i += kThreads) { xt[i] = sys.X[i]; jt[i] = sys.J[i]; }
+    for (int i = threadIdx.x; i < N; i += kThreads) hd[i] = sys.Hd[i];
+    if (threadIdx.x < nb) pre[threadIdx.x + 1] = fcnt[b0 + threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        pre[0] = 0;
+        for (int k = 1; k <= nb; ++k) pre[k] += pre[k - 1];
+    }
+    __syncthreads();
+    const int total = pre[nb];
+    for (int t = threadIdx.x; t < total; t += kThreads) {
+        int lo = 0, hi = nb;  // bucket k with pre[k] <= t < pre[k+1]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= t) lo = mid; else hi = mid;
+        }
+        const int64_t base = (int64_t)(b0 + lo) * R;
+        const int64_t e = base + fpos[base + (t - pre[lo])];
+        const Key<W> key = load_key<W>(out.keys + e * W);
+        const double h = h_diag_tab(hd, xt, jt, N, key_alpha<W>(key), key_beta<W>(key));
+        out.diag[e] = h - h00;
+    }
+    __syncthreads();
+}
+
+template <int W, class V>
+__global__ __launch_bounds__(kThreads) void k_fresh(SysView sys, Store<V> out, StepScalars sc,
+                                                    const uint16_t* __restrict__ fpos,
+                                                    const int32_t* __restrict__ fcnt, const Ctl* ctl) {
+    extern __shared__ double tabs[];
+    __shared__ int pre[kFreshSpan + 1];
+    __shared__ unsigned fl;
+    if (wg_flags(ctl, &fl)) return;
+    const int64_t items = (sc.B + kFreshSpan - 1) / kFreshSpan;
+    for (int64_t g = blockIdx.x; g < items; g += gridDim.x)
+        fresh_item<W, V>(sys, out, sc.h00, sc.R, sc.B, fpos, fcnt, g, tabs, pre);
 }
 
 
@@ -871,6 +916,8 @@ template <int W, class V> struct Inst {
     int64_t *soff, *rel, *need_b, *recs_b;
     int32_t* scount;
     double *nw_b, *en_b;
+    uint16_t* fpos;
+    int32_t* fcnt;
     Ctl* ctl;
 };
 
@@ -906,7 +953,24 @@ __global__ __launch_bounds__(kThreads) void k_annihilate_batch(const Inst<W, V>*
         const Inst<W, V>& I = inst[i];
         if (wg_flags(I.ctl, &fl)) continue;  // this instance replays its step alone
         annihilate_bucket<W, V>(I.sys, I.in, I.out, I.sc, I.rec2, I.soff, I.scount, I.rel, I.need_b, I.recs_b,
-                                I.nw_b, I.en_b, I.ctl, (int)(g - first[i]), L);
+                                I.nw_b, I.en_b, I.fpos, I.fcnt, I.ctl, (int)(g - first[i]), L);
+    }
+}
+
+// New diagonals of the molecular members (work items as in k_fresh).
+template <int W, class V>
+__global__ __launch_bounds__(kThreads) void k_fresh_batch(const Inst<W, V>* __restrict__ inst,
+                                                          const int64_t* __restrict__ first, int k) {
+    extern __shared__ double tabs[];
+    __shared__ int pre[kFreshSpan + 1];
+    __shared__ unsigned fl;
+    const int64_t total = first[k];
+    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+        const int i = owner_of(first, k, g);
+        const Inst<W, V>& I = inst[i];
+        if (I.sys.onsite) continue;
+        if (wg_flags(I.ctl, &fl)) continue;
+        fresh_item<W, V>(I.sys, I.out, I.sc.h00, I.sc.R, I.sc.B, I.fpos, I.fcnt, g - first[i], tabs, pre);
     }
 }
 

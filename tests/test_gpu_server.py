@@ -70,8 +70,11 @@ def test_server_results_equal_solo_runs():
 
 
 def test_admission_respects_budget_in_arrival_order():
-    loaded = _load(_requests()[:4])
-    need = max(F.fciqmc_estimate_bytes(sysd, F.fciqmc_params_default(**p)) for sysd, p in loaded)
+    # four molecules of one size: equal reservations, two fit the budget
+    loaded = _load([(s, dict(p, walker_target=4e3)) for s, p in _requests()[:4]])
+    needs = [F.fciqmc_estimate_bytes(sysd, F.fciqmc_params_default(**p)) for sysd, p in loaded]
+    assert len(set(needs)) == 1
+    need = needs[0]
     srv = F.fciqmc_server_create(int(2.5 * need), max_running=64)
     tickets = [F.fciqmc_server_submit(srv, sysd, F.fciqmc_params_default(**p), INTERVAL, MAX_STEPS)
                for sysd, p in loaded]
