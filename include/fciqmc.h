@@ -165,9 +165,10 @@ int fciqmc_matrix_elements(const fciqmc_system *sys, const uint64_t *dets_i,
 int64_t fciqmc_run_device_bytes(const fciqmc_run *run);
 
 /* Per-kernel timing.  enable != 0 starts recording HIP events around each
- * kernel of every later step (on the run's stream).  ms: host, 3 entries
- * receive the accumulated milliseconds of the spawn, annihilation and post
- * kernels; *steps the number of steps timed.
+ * kernel of every 16th later step (steps whose number is a multiple of 16;
+ * on the run's stream).  ms: host, 3 entries receive the accumulated
+ * milliseconds of the spawn, annihilation and post kernels over the timed
+ * steps; *steps the number of steps timed.
  * layout: host, 2 entries receive the bucket count of the walker store and
  * the spawn-record capacity (either output may be NULL). */
 int fciqmc_profile(fciqmc_run *run, int enable, double *ms, int64_t *steps, int64_t *layout);

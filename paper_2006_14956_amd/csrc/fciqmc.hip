@@ -212,6 +212,7 @@ template <int W, class V> constexpr int kind_of() { return (W - 1) * 2 + (sizeof
 
 // kernels of one step, in launch order: spawn, annihilation, post
 constexpr int kKernels = 3;
+constexpr int64_t kProfileEvery = 16;
 #ifndef FQ_OCCUPANCY
 #define FQ_OCCUPANCY 1024
 #endif
@@ -252,11 +253,22 @@ template <int W, class V> struct Engine : EngineBase {
     Ctl* ctl = nullptr;
     Ctl* hctl = nullptr;  // pinned
     int64_t att_next = 0;
+    int64_t chunk_next = 0;     // spawn chunks of the next step
+    int64_t* cmap = nullptr;    // chunk -> bucket << 32 | local chunk, for the next step
+    int64_t cap_cmap = 0;
     int64_t max_b = 1 << 22;
     bool dirty = false;  // a step stopped on a flag; counters need rebuilding
-    // optional per-kernel timing (HIP events around each launch of a step)
+    // The spawn launch of step t+1 is queued right after step t's post work,
+    // before the host reads step t's scalars (spawning does not use the
+    // shift).  It is discarded and launched again if step t fails or a buffer
+    // it used has to grow.
+    bool pending = false;
+    int64_t pending_t = -1;
+    hipEvent_t ev_copy = nullptr;  // the step scalars have reached the host
+    // optional per-kernel timing (HIP events around each launch of a step),
+    // one set per step parity since the next spawn is queued early
     bool profile = false;
-    hipEvent_t ev[kKernels + 1]{};
+    hipEvent_t ev[2][kKernels + 1]{};
     double kms[kKernels]{};
     int64_t klaunch = 0;
 
@@ -265,26 +277,43 @@ template <int W, class V> struct Engine : EngineBase {
         (void)hipStreamSynchronize(stream);
         arena.clear();
         if (hctl) (void)hipHostFree(hctl);
+        if (ev_copy) (void)hipEventDestroy(ev_copy);
         if (profile)
-            for (auto& e : ev) (void)hipEventDestroy(e);
+            for (auto& set : ev)
+                for (auto& e : set) (void)hipEventDestroy(e);
     }
     int enable_profile() override {
         if (profile) return 0;
-        for (auto& e : ev) HIP_OK(hipEventCreate(&e));
+        CHECK(discard_pending());  // the next spawn launch then carries its events
+        for (auto& set : ev)
+            for (auto& e : set) HIP_OK(hipEventCreate(&e));
         profile = true;
         return 0;
     }
-    void mark(int i) {
-        if (profile) (void)hipEventRecord(ev[i], stream);
+    // Steps timed by events: one in kProfileEvery (event markers cost a few
+    // microseconds each, comparable to a kernel at cache-resident sizes).
+    static bool sampled(int64_t t) { return t % kProfileEvery == 0; }
+    void mark(int set, int i) {
+        if (profile && set >= 0) (void)hipEventRecord(ev[set][i], stream);
     }
-    int collect() {
-        if (!profile) return 0;
+    int collect(int set) {
+        if (!profile || set < 0) return 0;
         for (int i = 0; i < kKernels; ++i) {
             float ms = 0.f;
-            HIP_OK(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            HIP_OK(hipEventElapsedTime(&ms, ev[set][i], ev[set][i + 1]));
             kms[i] += ms;
         }
         ++klaunch;
+        return 0;
+    }
+    // Drop a queued spawn launch: wait for it, clear the record counters and
+    // the step accumulators it touched (the slab offsets stay valid).
+    int discard_pending() {
+        if (!pending) return 0;
+        HIP_OK(hipStreamSynchronize(stream));
+        HIP_OK(hipMemsetAsync(scount, 0, sizeof(int32_t) * B * kSub, stream));
+        HIP_OK(hipMemsetAsync(ctl, 0, offsetof(Ctl, nw), stream));
+        pending = false;
         return 0;
     }
     int64_t bytes() const override { return arena.bytes; }
@@ -367,11 +396,28 @@ template <int W, class V> struct Engine : EngineBase {
     int init(int buckets, long long spawn_cap, int64_t budget) {
         arena.budget = budget;
         B = buckets;
-        HIP_OK(hipHostMalloc((void**)&hctl, sizeof(Ctl), hipHostMallocDefault));
+        HIP_OK(hipHostMalloc((void**)&hctl, sizeof(Ctl), hipHostMallocCoherent));  // written by kernels
+        HIP_OK(hipEventCreateWithFlags(&ev_copy, hipEventDisableTiming));
         CHECK(dalloc(arena, &ctl, 1));
         HIP_OK(hipMemsetAsync(ctl, 0, sizeof(Ctl), stream));
         CHECK(alloc_buckets());
         CHECK(ensure_slabs(spawn_cap));
+        cap_cmap = std::max<int64_t>(1 << 16, spawn_cap / kChunk + 4 * (int64_t)B);
+        CHECK(dalloc(arena, &cmap, (size_t)cap_cmap));
+        return 0;
+    }
+    // Room in the chunk map for the next step; after growth the map is
+    // rebuilt from the chunk prefix the post work left in st[cur].
+    int ensure_cmap() {
+        chunk_next = hctl->chunks;
+        if (chunk_next <= cap_cmap) return 0;
+        arena.release(cmap);
+        cmap = nullptr;
+        cap_cmap = chunk_next + chunk_next / 2 + 1024;
+        CHECK(dalloc(arena, &cmap, (size_t)cap_cmap));
+        hipLaunchKernelGGL(k_chunk_map, dim3((unsigned)std::min<int64_t>((B + 255) / 256, 4096)), dim3(256), 0, stream,
+                           st[cur].aoff, B, cmap);
+        HIP_OK(hipGetLastError());
         return 0;
     }
 
@@ -388,6 +434,14 @@ template <int W, class V> struct Engine : EngineBase {
     // Run the per-bucket kernel from st[cur] into st[1-cur] on the records in
     // the slabs, then the global sums; read the step's scalars back.
     int merge_and_post(const StepScalars& sc) {
+        CHECK(launch_merge_post(sc, -1));
+        HIP_OK(hipStreamSynchronize(stream));
+        return 0;
+    }
+
+    // Queue annihilation, new diagonals and the post work of a step, which
+    // writes the step scalars to the host (ev_copy marks its completion).
+    int launch_merge_post(const StepScalars& sc, int set) {
         const SysView v = sys->view();
         Store<V> in = st[cur], out = st[1 - cur];
         const int gb = std::min(B, 32768);
@@ -398,7 +452,7 @@ template <int W, class V> struct Engine : EngineBase {
             hipLaunchKernelGGL((k_fresh<W, V>), dim3((unsigned)std::min<int64_t>(items, 4096)), dim3(kThreads),
                                fresh_lds_bytes(sys->N), stream, v, out, sc, fpos, fcnt, ctl);
         }
-        mark(2);
+        mark(set, 2);
         if (sc.import_mode) {
             // slabs of the first step after an import: from the imported counts
             hipLaunchKernelGGL(k_import_slabs, dim3((B + 255) / 256), dim3(256), 0, stream, scount, B, rel,
@@ -406,19 +460,19 @@ template <int W, class V> struct Engine : EngineBase {
         }
         if (B <= 4 * kPostSpan) {
             hipLaunchKernelGGL(k_post, dim3(1), dim3(kPostThreads), 0, stream, out.batt, out.count, nw_b, en_b,
-                               B, out.aoff, rel, need_b, recs_b, soff, ctl);
+                               B, out.aoff, rel, need_b, recs_b, soff, cmap, cap_cmap, ctl, hctl);
         } else {
             const int G = (B + kPostSpan - 1) / kPostSpan;
             hipLaunchKernelGGL(k_post_a, dim3(G), dim3(256), 0, stream, out.batt, out.count, nw_b, en_b, need_b,
                                recs_b, B, part, ctl);
-            hipLaunchKernelGGL(k_post_b, dim3(1), dim3(256), 0, stream, part, G, B, out.aoff, soff, ctl);
+            hipLaunchKernelGGL(k_post_b, dim3(1), dim3(256), 0, stream, part, G, B, out.aoff, soff, ctl, hctl);
             hipLaunchKernelGGL(k_post_c, dim3(G), dim3(256), 0, stream, out.batt, rel, need_b, B, part, out.aoff,
-                               soff, ctl);
+                               soff, cmap, cap_cmap, ctl);
         }
-        mark(3);
+        mark(set, 3);
         HIP_OK(hipGetLastError());
-        HIP_OK(hipMemcpyAsync(hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
-        HIP_OK(hipStreamSynchronize(stream));
+        // the post kernel has written the step scalars to hctl (pinned host memory)
+        HIP_OK(hipEventRecord(ev_copy, stream));
         return 0;
     }
 
@@ -449,6 +503,7 @@ template <int W, class V> struct Engine : EngineBase {
 
     // Load a population through the per-bucket merge with death and rounding off.
     int import(const uint64_t* ab, const double* vals, int64_t n) {
+        CHECK(discard_pending());
         for (int attempt = 0; attempt < 24; ++attempt) {
             CHECK(ensure_stage(std::max<int64_t>(n, 1)));
             CHECK(ensure_slabs(std::max<int64_t>(n, 1)));
@@ -482,6 +537,7 @@ template <int W, class V> struct Engine : EngineBase {
                 cur = 1 - cur;
                 att_next = hctl->attempts;
                 rec_need = hctl->rec_need;
+                CHECK(ensure_cmap());
                 return ensure_slabs(rec_need);
             }
             if (flags & (kFlagTable | kFlagStore)) {
@@ -535,22 +591,23 @@ template <int W, class V> struct Engine : EngineBase {
         return 0;
     }
 
-    int launch_spawn(const StepScalars& sc) {
+    // Spawn from store `in` with `grid` workgroups (the kernel reads the
+    // chunk count from the device and strides over it).
+    int launch_spawn(const Store<V>& in, const StepScalars& sc, int64_t grid) {
         const SysView v = sys->view();
-        const int64_t blocks = std::max<int64_t>(1, (att_next + kChunk - 1) / kChunk);
-        const Store<V> in = st[cur];
+        const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(grid, 1 << 30));
         switch (rs.gen) {
             case FCIQMC_GEN_UNIFORM:
                 hipLaunchKernelGGL((k_spawn<W, V, 0>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
-                                   soff, scount, ctl);
+                                   soff, scount, ctl, cmap, cap_cmap);
                 break;
             case FCIQMC_GEN_LATTICE:
                 hipLaunchKernelGGL((k_spawn<W, V, 1>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
-                                   soff, scount, ctl);
+                                   soff, scount, ctl, cmap, cap_cmap);
                 break;
             default:
                 hipLaunchKernelGGL((k_spawn<W, V, 2>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
-                                   soff, scount, ctl);
+                                   soff, scount, ctl, cmap, cap_cmap);
                 break;
         }
         HIP_OK(hipGetLastError());
@@ -593,40 +650,68 @@ template <int W, class V> struct Engine : EngineBase {
         rec_need = hctl->rec_need;
         out = *hctl;
         out.nref = hctl->nref_out;
-        if (hctl->ndets > kMaxMeanOccupancy * (int64_t)B && (int64_t)B * 2 <= max_b && !fixed_b) {
-            CHECK(grow_buckets());
+        const bool grow = hctl->ndets > kMaxMeanOccupancy * (int64_t)B && (int64_t)B * 2 <= max_b && !fixed_b;
+        if (!grow && hctl->chunks <= cap_cmap && rec_need <= cap) {
+            chunk_next = hctl->chunks;
             return 0;
         }
+        CHECK(discard_pending());  // a queued spawn used buffers that change now
+        if (grow) return grow_buckets();
+        CHECK(ensure_cmap());
         return ensure_slabs(rec_need);
     }
 
-    // Launch the step alone until it fits.
-    int run_alone(int64_t t, double S, int& retries) {
+    // Launch the step alone until it fits.  With `ahead`, the next step's
+    // spawn is queued behind this step's post work while the host waits for
+    // the scalars.
+    int run_alone(int64_t t, double S, int& retries, bool ahead) {
         for (;;) {
             const StepScalars sc = scalars(t, S, 0);
-            mark(0);
-            CHECK(launch_spawn(sc));
-            mark(1);
-            CHECK(merge_and_post(sc));
+            const int set = sampled(t) ? (int)(t & 1) : -1;
+            if (!pending) {
+                mark(set, 0);
+                CHECK(launch_spawn(st[cur], sc, chunk_next));
+                mark(set, 1);
+            }
+            pending = false;
+            CHECK(launch_merge_post(sc, set));
+            if (ahead) {
+                const int nset = sampled(t + 1) ? (int)((t + 1) & 1) : -1;
+                mark(nset, 0);
+                CHECK(launch_spawn(st[1 - cur], scalars(t + 1, S, 0), chunk_next + chunk_next / 8 + 64));
+                mark(nset, 1);
+                HIP_OK(hipGetLastError());
+                pending = true;
+                pending_t = t + 1;
+            }
+            HIP_OK(hipEventSynchronize(ev_copy));
+            if (hctl->flags && pending) {
+                // the queued spawn ran on a failed step's output: let it end;
+                // its record counts only enlarge the recovered slabs
+                HIP_OK(hipStreamSynchronize(stream));
+                pending = false;
+            }
             bool done = false;
             CHECK(settle(t, retries, done));
-            if (done) return collect();
+            if (done) return collect(set);
         }
     }
 
     int step_once(int64_t t, double S, Ctl& out, int& retries, int64_t& attempts) override {
         retries = 0;
         attempts = att_next;
+        if (pending && pending_t != t) CHECK(discard_pending());
         if (dirty) {
             CHECK(recover());
             dirty = false;
         }
-        CHECK(run_alone(t, S, retries));
+        CHECK(run_alone(t, S, retries, true));
         return complete(out);
     }
 
     // Batched stepping: the instance descriptor of step t and its spawn chunks.
     int batch_prepare(int64_t t, double S, Inst<W, V>& d, int64_t& chunks) {
+        CHECK(discard_pending());
         if (dirty) {
             CHECK(recover());
             dirty = false;
@@ -637,7 +722,8 @@ template <int W, class V> struct Engine : EngineBase {
         d.sc = scalars(t, S, 0);
         d.rec2 = rec2; d.soff = soff; d.rel = rel; d.need_b = need_b; d.recs_b = recs_b;
         d.scount = scount; d.nw_b = nw_b; d.en_b = en_b; d.fpos = fpos; d.fcnt = fcnt; d.ctl = ctl;
-        chunks = (att_next + kChunk - 1) / kChunk;
+        d.cmap = cmap; d.cmap_cap = cap_cmap;
+        chunks = chunk_next;
         return 0;
     }
     // The batch's read-back of this instance; a flagged step is replayed alone.
@@ -647,7 +733,7 @@ template <int W, class V> struct Engine : EngineBase {
         *hctl = c;
         bool done = false;
         CHECK(settle(t, retries, done));
-        if (!done) CHECK(run_alone(t, S, retries));
+        if (!done) CHECK(run_alone(t, S, retries, false));
         return complete(out);
     }
     void set_stream(hipStream_t s) override { stream = s; }
@@ -787,8 +873,7 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
     char* hbuf = nullptr;       // pinned: Inst[cap], bucket prefix [cap+1], chunk prefixes [cap+3],
                                 // diagonal work-item prefix [cap+1]
     char* dbuf = nullptr;       // device copy of hbuf
-    Ctl* hctl = nullptr;        // pinned read-back, one per instance
-    Ctl* dctl = nullptr;
+    Ctl* hctl = nullptr;        // pinned, written by the post kernel, one per instance
     int g0[4] = {0, 0, 0, 0};   // first instance of each generator, g0[3] = n
     int64_t ctot[3] = {0, 0, 0};
     int64_t btot = 0;
@@ -816,9 +901,8 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
         arena.clear();
         cap = 0;
         HIP_OK(hipHostMalloc((void**)&hbuf, bytes_for(c), hipHostMallocDefault));
-        HIP_OK(hipHostMalloc((void**)&hctl, sizeof(Ctl) * c, hipHostMallocDefault));
+        HIP_OK(hipHostMalloc((void**)&hctl, sizeof(Ctl) * c, hipHostMallocCoherent));  // written by kernels
         CHECK(dalloc(arena, &dbuf, bytes_for(c)));
-        CHECK(dalloc(arena, &dctl, c));
         cap = c;
         return 0;
     }
@@ -899,9 +983,8 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
     int launch_post(hipStream_t s) override {
         if (runs.empty()) return 0;
         hipLaunchKernelGGL((k_post_batch<W, V>), dim3((unsigned)runs.size()), dim3(kPostThreads), 0, s,
-                           reinterpret_cast<const Inst<W, V>*>(dbuf), dctl);
+                           reinterpret_cast<const Inst<W, V>*>(dbuf), hctl);
         HIP_OK(hipGetLastError());
-        HIP_OK(hipMemcpyAsync(hctl, dctl, sizeof(Ctl) * runs.size(), hipMemcpyDeviceToHost, s));
         return 0;
     }
     int finish(fciqmc_step_stats* row) override {

@@ -35,6 +35,11 @@ constexpr int kSub = 8;
 constexpr int kSlots = FQ_SLOTS;    // LDS hash slots per bucket (table size adapts below this)
 constexpr int kSlotsPerThread = kSlots / kThreads;
 constexpr int kFresh = 512;         // new determinants per bucket whose diagonal is spread over the workgroup
+constexpr int kMaxR = 1024;         // entries per bucket of the walker store
+
+// Spawn chunks of a bucket: its attempts in runs of kChunk (chunks never
+// cross buckets, so a chunk's attempts index one bucket's entries).
+__host__ __device__ inline int64_t chunks_of(int64_t attempts) { return (attempts + kChunk - 1) / kChunk; }
 
 template <int W, class V> struct Rec {
     uint64_t k[W];
@@ -49,7 +54,7 @@ template <class V> struct Store {
     int32_t* mpre;    // B*R: exclusive prefix of attempts within the bucket
     int32_t* count;   // B
     int64_t* batt;    // B: attempts of the bucket
-    int64_t* aoff;    // B+1: exclusive prefix of batt
+    int64_t* aoff;    // B+1: exclusive prefix of the spawn chunks of the buckets, ceil(batt / kChunk)
 };
 
 struct Ctl {
@@ -67,6 +72,7 @@ struct Ctl {
     long long max_count;       // fullest bucket
     double nref_out;
     long long rec_need;        // record slab capacity the next step reserves
+    long long chunks;          // spawn chunks (workgroups) of the next step
 };
 
 // Record sub-slab for the next step: this step's count plus headroom for
@@ -103,44 +109,33 @@ struct StepScalars {
 template <int W, class V, int GEN>
 __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& st, const StepScalars& sc,
                                             Rec<W, V>* __restrict__ rec2, const int64_t* __restrict__ soff,
-                                            int32_t* __restrict__ scount, Ctl* ctl, int64_t g, int* bspan) {
-    // Workgroup chunk g owns attempts [g*kChunk, (g+1)*kChunk).  Two lanes find
-    // the buckets of its first and last attempt; the others search between
-    // them.  A record takes the next place of sub-slab j = b*kSub + g mod kSub
-    // of its target bucket b, rec2[soff[j] .. soff[j+1]).
-    const int64_t total = st.aoff[sc.B];
+                                            int32_t* __restrict__ scount, Ctl* ctl,
+                                            const int64_t* __restrict__ cmap, int64_t g, int32_t* smpre) {
+    // Chunk g is local chunk c of bucket b (cmap[g] = b << 32 | c): the
+    // bucket's attempts [c*kChunk, (c+1)*kChunk), one per lane.  The
+    // bucket's attempt prefixes are read once into LDS; each lane finds its
+    // determinant there.  A record takes the next place of sub-slab
+    // j = b'*kSub + g mod kSub of its target bucket b', rec2[soff[j] .. soff[j+1]).
     const Key<W> ref = make_key<W>(sc.ref_a, sc.ref_b);
-    const int64_t g0 = g * kChunk;
-    if (threadIdx.x < 2) {
-        const int64_t a0 = threadIdx.x == 0 ? g0 : min(g0 + kChunk, total) - 1;
-        int lo = 0, hi = sc.B;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (st.aoff[mid] <= a0) lo = mid; else hi = mid;
-        }
-        bspan[threadIdx.x] = lo;
-    }
+    const int64_t m = cmap[g];
+    const int b = (int)(m >> 32);
+    const int64_t eb = (int64_t)b * sc.R;
+    const int cnt = st.count[b];
+    const int64_t natt = st.batt[b];
+    for (int i = threadIdx.x; i < cnt; i += kThreads) smpre[i] = st.mpre[eb + i];
     __syncthreads();
     {
-        const int64_t at = g0 + threadIdx.x;
+        const int64_t local = (m & 0xFFFFFFFFLL) * kChunk + threadIdx.x;
         bool emit = false;
         Rec<W, V> out;
-        if (at < total) {
-            int lo = bspan[0], hi = bspan[1] + 1;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (st.aoff[mid] <= at) lo = mid; else hi = mid;
-            }
-            const int b = lo;
-            const int64_t local = at - st.aoff[b];
-            const int64_t eb = (int64_t)b * sc.R;
-            int elo = 0, ehi = st.count[b];
+        if (local < natt) {
+            int elo = 0, ehi = cnt;
             while (ehi - elo > 1) {
                 const int mid = (elo + ehi) >> 1;
-                if ((int64_t)st.mpre[eb + mid] <= local) elo = mid; else ehi = mid;
+                if ((int64_t)smpre[mid] <= local) elo = mid; else ehi = mid;
             }
             const int64_t e = eb + elo;
-            const uint64_t k = (uint64_t)(local - st.mpre[e]);
+            const uint64_t k = (uint64_t)(local - smpre[elo]);
             const Key<W> key = load_key<W>(st.keys + e * W);
             const V C = st.vals[e];
             const double aC = vabs(C);
@@ -194,20 +189,29 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
         if (emit) {
             const uint32_t j = (out.flag >> 1) * kSub + (uint32_t)(g & (kSub - 1));
             const int64_t pos = (int64_t)atomicAdd(&scount[j], 1);
-            if (soff[j] + pos < soff[j + 1]) rec2[soff[j] + pos] = out;
+            if (soff[j] + pos < soff[j + 1] && soff[j] + pos < sc.spawn_cap) rec2[soff[j] + pos] = out;
             else atomicOr(&ctl->flags, kFlagSpawnCap);
         }
     }
-    __syncthreads();  // bspan is reused by the workgroup's next chunk
+    __syncthreads();  // smpre is reused by the workgroup's next chunk
 }
 
 template <int W, class V, int GEN>
 __global__ __launch_bounds__(kThreads) void k_spawn(SysView sys, Store<V> st, StepScalars sc,
                                                     Rec<W, V>* __restrict__ rec2,
                                                     const int64_t* __restrict__ soff,
-                                                    int32_t* __restrict__ scount, Ctl* ctl) {
-    __shared__ int bspan[2];
-    spawn_chunk<W, V, GEN>(sys, st, sc, rec2, soff, scount, ctl, (int64_t)blockIdx.x, bspan);
+                                                    int32_t* __restrict__ scount, Ctl* ctl,
+                                                    const int64_t* __restrict__ cmap, int64_t cmap_cap) {
+    // the chunk count of this step comes from the post work of the previous
+    // one, so a launch may be queued before the host has read it
+    __shared__ int32_t smpre[kMaxR];
+    const int64_t n = ctl->chunks;
+    if (n > cmap_cap) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctl->flags, kFlagSpawnCap);
+        return;
+    }
+    for (int64_t g = blockIdx.x; g < n; g += gridDim.x)
+        spawn_chunk<W, V, GEN>(sys, st, sc, rec2, soff, scount, ctl, cmap, g, smpre);
 }
 
 // Records uploaded from the host (population import): assign buckets.
@@ -375,16 +379,18 @@ __device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, cons
                                           const double* __restrict__ nw_b, const double* __restrict__ en_b,
                                           const int64_t* __restrict__ rel, const int64_t* __restrict__ need_b,
                                           const int64_t* __restrict__ recs_b, int B,
-                                          int64_t* __restrict__ aoff, int64_t* __restrict__ soff, Ctl* ctl,
+                                          int64_t* __restrict__ aoff, int64_t* __restrict__ soff,
+                                          int64_t* __restrict__ cmap, int64_t cmap_cap, Ctl* ctl,
                                           int64_t* sh, double* shd, int64_t* shm) {
     // one pass of loads (all per-bucket values of this thread's run of
     // buckets), the scans, then one pass of writes
     const int per = (B + NT - 1) / NT;
     const int b0 = threadIdx.x * per, b1 = min(B, b0 + per);
-    int64_t la = 0, ln = 0, cnt = 0, rc = 0, mx = 0;
+    int64_t la = 0, lk = 0, ln = 0, cnt = 0, rc = 0, mx = 0;
     double nw = 0.0, en = 0.0;
     for (int b = b0; b < b1; ++b) {
         la += batt[b];
+        lk += chunks_of(batt[b]);
         ln += need_b[b];
         const int64_t c = count[b];
         cnt += c;
@@ -393,15 +399,18 @@ __device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, cons
         nw = nw + nw_b[b];
         en = en + en_b[b];
     }
-    int64_t atot, ntot, crtot;
-    const int64_t abase = block_excl_scan<NT, int64_t>(la, atot, sh);
+    int64_t atot, ktot, ntot, crtot;
+    (void)block_excl_scan<NT, int64_t>(la, atot, sh);
+    const int64_t kbase = block_excl_scan<NT, int64_t>(lk, ktot, sh);
     const int64_t nbase = block_excl_scan<NT, int64_t>(ln, ntot, sh);
     // determinants (< 2^32) and records (< 2^31 per step) packed in one scan
     (void)block_excl_scan<NT, int64_t>((cnt << 32) | rc, crtot, sh);
-    int64_t run = abase, base = nbase;
+    int64_t run = kbase, base = nbase;
     for (int b = b0; b < b1; ++b) {
         aoff[b] = run;
-        run += batt[b];
+        const int64_t nk = chunks_of(batt[b]);
+        for (int64_t c = 0; c < nk && run + c < cmap_cap; ++c) cmap[run + c] = ((int64_t)b << 32) | c;
+        run += nk;
         for (int j = 0; j < kSub; ++j) soff[(int64_t)b * kSub + j] = base + rel[(int64_t)b * kSub + j];
         base += need_b[b];
     }
@@ -417,12 +426,13 @@ __device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, cons
         double a = 0.0, c = 0.0;
         int64_t m = 0;
         for (int i = 0; i < NT / 64; ++i) { a = a + shd[i]; c = c + shd[NT / 64 + i]; m = max(m, shm[i]); }
-        aoff[B] = atot;
+        aoff[B] = ktot;
         soff[(int64_t)B * kSub] = ntot;
         ctl->nw = a;
         ctl->enum_ = c;
         ctl->ndets = crtot >> 32;
         ctl->attempts = atot;
+        ctl->chunks = ktot;
         ctl->nrec_out = crtot & 0xFFFFFFFFLL;
         ctl->max_count = m;
         ctl->nref_out = ctl->nref;
@@ -745,7 +755,7 @@ __global__ __launch_bounds__(kThreads) void k_fresh(SysView sys, Store<V> out, S
 constexpr int kPostSpan = 1024;
 
 struct PostPart {
-    int64_t att, need, cnt, rec, mx;
+    int64_t att, chk, need, cnt, rec, mx;
     double nw, en;
 };
 
@@ -763,10 +773,11 @@ __global__ __launch_bounds__(256) void k_post_a(const int64_t* __restrict__ batt
     const int g0 = blockIdx.x * kPostSpan;
     const int per = kPostSpan / 256;
     const int b0 = g0 + threadIdx.x * per, b1 = min(B, b0 + per);
-    int64_t la = 0, ln = 0, c = 0, r = 0, mx = 0;
+    int64_t la = 0, lk = 0, ln = 0, c = 0, r = 0, mx = 0;
     double nw = 0.0, en = 0.0;
     for (int b = b0; b < b1; ++b) {
         la += batt[b];
+        lk += chunks_of(batt[b]);
         ln += need_b[b];
         const int64_t cb = count[b];
         c += cb;
@@ -775,8 +786,9 @@ __global__ __launch_bounds__(256) void k_post_a(const int64_t* __restrict__ batt
         nw = nw + nw_b[b];
         en = en + en_b[b];
     }
-    int64_t ta, tn, tcr;
+    int64_t ta, tk, tn, tcr;
     (void)block_excl_scan<256, int64_t>(la, ta, sh);
+    (void)block_excl_scan<256, int64_t>(lk, tk, sh);
     (void)block_excl_scan<256, int64_t>(ln, tn, sh);
     (void)block_excl_scan<256, int64_t>((c << 32) | r, tcr, sh);
     nw = wave_sum(nw);
@@ -788,6 +800,7 @@ __global__ __launch_bounds__(256) void k_post_a(const int64_t* __restrict__ batt
     if (threadIdx.x == 0) {
         PostPart p;
         p.att = ta;
+        p.chk = tk;
         p.need = tn;
         p.cnt = tcr >> 32;
         p.rec = tcr & 0xFFFFFFFFLL;
@@ -800,22 +813,28 @@ __global__ __launch_bounds__(256) void k_post_a(const int64_t* __restrict__ batt
 
 __global__ __launch_bounds__(256) void k_post_b(PostPart* __restrict__ part, int G, int B,
                                                 int64_t* __restrict__ aoff, int64_t* __restrict__ soff,
-                                                Ctl* ctl) {
-    if (ctl->flags) return;
+                                                Ctl* ctl,
+                                                Ctl* __restrict__ host) {
+    if (ctl->flags) {
+        if (threadIdx.x == 0) *host = *ctl;
+        return;
+    }
     __shared__ int64_t sh[4];
-    // exclusive prefix of the partials (attempts, slab sizes), in place
+    // exclusive prefix of the partials (chunks, slab sizes), in place;
+    // the attempt total
     const int per = (G + 255) / 256;
     const int g0 = threadIdx.x * per, g1 = min(G, g0 + per);
-    int64_t la = 0, ln = 0;
-    for (int g = g0; g < g1; ++g) { la += part[g].att; ln += part[g].need; }
-    int64_t ta, tn;
-    int64_t ra = block_excl_scan<256, int64_t>(la, ta, sh);
+    int64_t la = 0, lk = 0, ln = 0;
+    for (int g = g0; g < g1; ++g) { la += part[g].att; lk += part[g].chk; ln += part[g].need; }
+    int64_t ta, tk, tn;
+    (void)block_excl_scan<256, int64_t>(la, ta, sh);
+    int64_t rk = block_excl_scan<256, int64_t>(lk, tk, sh);
     int64_t rn = block_excl_scan<256, int64_t>(ln, tn, sh);
     for (int g = g0; g < g1; ++g) {
-        const int64_t a = part[g].att, n = part[g].need;
-        part[g].att = ra;
+        const int64_t k = part[g].chk, n = part[g].need;
+        part[g].chk = rk;
         part[g].need = rn;
-        ra += a;
+        rk += k;
         rn += n;
     }
     __syncthreads();
@@ -829,18 +848,20 @@ __global__ __launch_bounds__(256) void k_post_b(PostPart* __restrict__ part, int
             r += part[g].rec;
             m = max(m, part[g].mx);
         }
-        aoff[B] = ta;
+        aoff[B] = tk;
         soff[(int64_t)B * kSub] = tn;
         ctl->nw = nw;
         ctl->enum_ = en;
         ctl->ndets = c;
         ctl->attempts = ta;
+        ctl->chunks = tk;
         ctl->nrec_out = r;
         ctl->max_count = m;
         ctl->nref_out = ctl->nref;
         ctl->rec_need = tn;
         ctl->nrec = 0;
         ctl->nref = 0.0;
+        *host = *ctl;
     }
 }
 
@@ -849,20 +870,22 @@ __global__ __launch_bounds__(256) void k_post_c(const int64_t* __restrict__ batt
                                                 const int64_t* __restrict__ need_b, int B,
                                                 const PostPart* __restrict__ part,
                                                 int64_t* __restrict__ aoff, int64_t* __restrict__ soff,
-                                                const Ctl* ctl) {
+                                                int64_t* __restrict__ cmap, int64_t cmap_cap, const Ctl* ctl) {
     if (ctl->flags) return;
     __shared__ int64_t sh[4];
     const int g0 = blockIdx.x * kPostSpan;
     const int per = kPostSpan / 256;
     const int b0 = g0 + threadIdx.x * per, b1 = min(B, b0 + per);
-    int64_t la = 0, ln = 0;
-    for (int b = b0; b < b1; ++b) { la += batt[b]; ln += need_b[b]; }
-    int64_t ta, tn;
-    int64_t ra = part[blockIdx.x].att + block_excl_scan<256, int64_t>(la, ta, sh);
+    int64_t lk = 0, ln = 0;
+    for (int b = b0; b < b1; ++b) { lk += chunks_of(batt[b]); ln += need_b[b]; }
+    int64_t tk, tn;
+    int64_t rk = part[blockIdx.x].chk + block_excl_scan<256, int64_t>(lk, tk, sh);
     int64_t rn = part[blockIdx.x].need + block_excl_scan<256, int64_t>(ln, tn, sh);
     for (int b = b0; b < b1; ++b) {
-        aoff[b] = ra;
-        ra += batt[b];
+        aoff[b] = rk;
+        const int64_t nk = chunks_of(batt[b]);
+        for (int64_t c = 0; c < nk && rk + c < cmap_cap; ++c) cmap[rk + c] = ((int64_t)b << 32) | c;
+        rk += nk;
         for (int j = 0; j < kSub; ++j) soff[(int64_t)b * kSub + j] = rn + rel[(int64_t)b * kSub + j];
         rn += need_b[b];
     }
@@ -892,11 +915,21 @@ __global__ __launch_bounds__(kPostThreads) void k_post(const int64_t* __restrict
                                                const int64_t* __restrict__ rel,
                                                const int64_t* __restrict__ need_b,
                                                const int64_t* __restrict__ recs_b,
-                                               int64_t* __restrict__ soff, Ctl* ctl) {
-    if (ctl->flags) return;
+                                               int64_t* __restrict__ soff, int64_t* __restrict__ cmap,
+                                               int64_t cmap_cap, Ctl* ctl, Ctl* __restrict__ host) {
     __shared__ int64_t sh[kPostThreads / 64], shm[kPostThreads / 64];
     __shared__ double shd[2 * kPostThreads / 64];
-    post_work<kPostThreads>(batt, count, nw_b, en_b, rel, need_b, recs_b, B, aoff, soff, ctl, sh, shd, shm);
+    if (!ctl->flags)
+        post_work<kPostThreads>(batt, count, nw_b, en_b, rel, need_b, recs_b, B, aoff, soff, cmap, cmap_cap, ctl,
+                                sh, shd, shm);
+    if (threadIdx.x == 0) *host = *ctl;
+}
+
+// The chunk map from the chunk prefix (when the map had to grow after the
+// post work): cmap[aoff[b] + c] = b << 32 | c.
+__global__ void k_chunk_map(const int64_t* __restrict__ aoff, int B, int64_t* __restrict__ cmap) {
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x)
+        for (int64_t c = aoff[b]; c < aoff[b + 1]; ++c) cmap[c] = ((int64_t)b << 32) | (c - aoff[b]);
 }
 
 // ---------------------------------------------------------------------------
@@ -918,6 +951,8 @@ template <int W, class V> struct Inst {
     double *nw_b, *en_b;
     uint16_t* fpos;
     int32_t* fcnt;
+    int64_t* cmap;
+    int64_t cmap_cap;
     Ctl* ctl;
 };
 
@@ -933,12 +968,12 @@ __device__ __forceinline__ int owner_of(const int64_t* __restrict__ first, int k
 template <int W, class V, int GEN>
 __global__ __launch_bounds__(kThreads) void k_spawn_batch(const Inst<W, V>* __restrict__ inst,
                                                           const int64_t* __restrict__ first, int k) {
-    __shared__ int bspan[2];
+    __shared__ int32_t smpre[kMaxR];
     const int64_t total = first[k];
     for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
         const int i = owner_of(first, k, g);
         const Inst<W, V>& I = inst[i];
-        spawn_chunk<W, V, GEN>(I.sys, I.in, I.sc, I.rec2, I.soff, I.scount, I.ctl, g - first[i], bspan);
+        spawn_chunk<W, V, GEN>(I.sys, I.in, I.sc, I.rec2, I.soff, I.scount, I.ctl, I.cmap, g - first[i], smpre);
     }
 }
 
@@ -974,8 +1009,8 @@ __global__ __launch_bounds__(kThreads) void k_fresh_batch(const Inst<W, V>* __re
     }
 }
 
-// Post work of instance blockIdx.x, then a copy of its step scalars into
-// ctl_out[blockIdx.x] (one read-back for the whole batch).
+// Post work of instance blockIdx.x, then its step scalars written to
+// ctl_out[blockIdx.x] in pinned host memory (no copy operation per step).
 template <int W, class V>
 __global__ __launch_bounds__(kPostThreads) void k_post_batch(const Inst<W, V>* __restrict__ inst,
                                                              Ctl* __restrict__ ctl_out) {
@@ -985,7 +1020,7 @@ __global__ __launch_bounds__(kPostThreads) void k_post_batch(const Inst<W, V>* _
     const Inst<W, V>& I = inst[blockIdx.x];
     if (!wg_flags(I.ctl, &fl))
         post_work<kPostThreads>(I.out.batt, I.out.count, I.nw_b, I.en_b, I.rel, I.need_b, I.recs_b, I.sc.B,
-                                I.out.aoff, I.soff, I.ctl, sh, shd, shm);
+                                I.out.aoff, I.soff, I.cmap, I.cmap_cap, I.ctl, sh, shd, shm);
     if (threadIdx.x == 0) ctl_out[blockIdx.x] = *I.ctl;
 }
 
