@@ -430,7 +430,20 @@ def main():
     ap.add_argument("--served-rate", type=float, default=20.0)
     ap.add_argument("--served-tol", type=float, default=0.01)
     ap.add_argument("--served-budget", type=float, default=200e9)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run 5 device-to-device copies of BYTES (the known-size copy "
+                         "that scales rocprofv3 FETCH_SIZE/WRITE_SIZE readings)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n, "copies": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "path is a design, not built", file=sys.stderr)

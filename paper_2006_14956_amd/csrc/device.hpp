@@ -147,6 +147,17 @@ __device__ __forceinline__ void pair_decode(uint64_t q, int n, int& x, int& y) {
 // --------------------------------------------------------------------------
 // Integrals.
 // --------------------------------------------------------------------------
+// One column of a heat-bath alias table, packed so that a draw reads a
+// single aligned 32-byte entry: the alias threshold and column, and the
+// normalised weight w/sum of both outcomes (this column and its alias).
+struct alignas(32) HbEntry {
+    double prob;
+    double q_self;
+    double q_alias;
+    int32_t alias;
+    int32_t pad;
+};
+
 struct SysView {
     int N, na, nb, n;
     int onsite;           // two-electron integrals vanish except (pp|pp)
@@ -160,8 +171,8 @@ struct SysView {
     const int* deg;       // lattice degree
     const int* nbr;       // N*N ascending neighbour lists
     // pre-computed heat-bath tables (see the PCHB generator)
-    const double* hb_w_opp; const double* hb_p_opp; const int* hb_a_opp; const double* hb_s_opp;
-    const double* hb_w_same; const double* hb_p_same; const int* hb_a_same; const double* hb_s_same;
+    const HbEntry* hb_opp;   // rows (I alpha, J beta), N^2 columns each
+    const HbEntry* hb_same;  // rows I < J, N(N-1)/2 columns each
     const int* pair_of;   // same-spin column index -> A*64+B
 };
 
@@ -377,19 +388,19 @@ __device__ __forceinline__ bool gen_pchb(const SysView& s, uint64_t a, uint64_t 
         const int I = select64(a, (int)(q / (uint64_t)nb));
         const int J = select64(b, (int)(q % (uint64_t)nb));
         const int row = I * N + J;
-        const double sum = s.hb_s_opp[row];
-        if (sum == 0.0) return false;
         const int K = N * N;
         const size_t base = (size_t)row * (size_t)K;
         const int c0 = (int)pick(r.x[2], (uint64_t)K);
-        const int c = coin < s.hb_p_opp[base + c0] ? c0 : s.hb_a_opp[base + c0];
-        const double wc = s.hb_w_opp[base + c];
-        if (wc == 0.0) return false;
+        // p(ab|ij) = w_ab / sum_row; zero for a zero row or a zero weight (null)
+        const HbEntry en = s.hb_opp[base + c0];
+        const bool self = coin < en.prob;
+        const int c = self ? c0 : en.alias;
+        const double pab = self ? en.q_self : en.q_alias;
+        if (pab == 0.0) return false;
         const int A = c / N, Bo = c % N;
         if (((a >> A) & 1ULL) || ((b >> Bo) & 1ULL)) return false;
         const double p1 = p_double * p_opp;
         const double p2 = p1 / (double)n_opp;
-        const double pab = wc / sum;
         out.pgen = p2 * pab;
         out.H = h_double(s, a, b, 0, I, 1, J, 0, A, 1, Bo);
         out.ta = (a & ~(1ULL << I)) | (1ULL << A);
@@ -405,20 +416,19 @@ __device__ __forceinline__ bool gen_pchb(const SysView& s, uint64_t a, uint64_t 
     pair_decode(q, sg ? nb : na, e1, e2);
     const int I = select64(occ, e1), J = select64(occ, e2);
     const int row = I * (2 * N - I - 1) / 2 + (J - I - 1);
-    const double sum = s.hb_s_same[row];
-    if (sum == 0.0) return false;
     const int K = N * (N - 1) / 2;
     const size_t base = (size_t)row * (size_t)K;
     const int c0 = (int)pick(r.x[2], (uint64_t)K);
-    const int c = coin < s.hb_p_same[base + c0] ? c0 : s.hb_a_same[base + c0];
-    const double wc = s.hb_w_same[base + c];
-    if (wc == 0.0) return false;
+    const HbEntry en = s.hb_same[base + c0];
+    const bool self = coin < en.prob;
+    const int c = self ? c0 : en.alias;
+    const double pab = self ? en.q_self : en.q_alias;
+    if (pab == 0.0) return false;
     const int ab = s.pair_of[c];
     const int A = ab >> 6, Bo = ab & 63;
     if (((occ >> A) & 1ULL) || ((occ >> Bo) & 1ULL)) return false;
     const double p1 = p_double * (1.0 - p_opp);
     const double p2 = p1 / (double)n_same;
-    const double pab = wc / sum;
     out.pgen = p2 * pab;
     out.H = h_double(s, a, b, sg, I, sg, J, sg, A, sg, Bo);
     const uint64_t m = (occ & ~(1ULL << I) & ~(1ULL << J)) | (1ULL << A) | (1ULL << Bo);

@@ -128,10 +128,7 @@ struct fciqmc_system {
     double *h1 = nullptr, *eri = nullptr, *J = nullptr, *K = nullptr, *X = nullptr, *U = nullptr, *Hd = nullptr;
     int *deg = nullptr, *nbr = nullptr, *pair_of = nullptr;
     bool pchb = false;
-    double *hb_w_opp = nullptr, *hb_p_opp = nullptr, *hb_s_opp = nullptr;
-    int* hb_a_opp = nullptr;
-    double *hb_w_same = nullptr, *hb_p_same = nullptr, *hb_s_same = nullptr;
-    int* hb_a_same = nullptr;
+    HbEntry *hb_opp = nullptr, *hb_same = nullptr;  // packed alias tables
     int device = 0;
 
     SysView view() const {
@@ -140,8 +137,8 @@ struct fciqmc_system {
         v.onsite = onsite ? 1 : 0;
         v.h1 = h1; v.eri = eri; v.J = J; v.K = K; v.X = X; v.U = U; v.Hd = Hd;
         v.deg = deg; v.nbr = nbr;
-        v.hb_w_opp = hb_w_opp; v.hb_p_opp = hb_p_opp; v.hb_a_opp = hb_a_opp; v.hb_s_opp = hb_s_opp;
-        v.hb_w_same = hb_w_same; v.hb_p_same = hb_p_same; v.hb_a_same = hb_a_same; v.hb_s_same = hb_s_same;
+        v.hb_opp = hb_opp;
+        v.hb_same = hb_same;
         v.pair_of = pair_of;
         return v;
     }
@@ -152,16 +149,22 @@ static int build_pchb(fciqmc_system* s, hipStream_t stream) {
     if (s->pchb) return 0;
     const int N = s->N, NN = N * N, np = N * (N - 1) / 2;
     const size_t ko = (size_t)NN * NN, ks = (size_t)np * np;
-    CHECK(dalloc(s->arena, &s->hb_w_opp, ko));
-    CHECK(dalloc(s->arena, &s->hb_p_opp, ko));
-    CHECK(dalloc(s->arena, &s->hb_a_opp, ko));
-    CHECK(dalloc(s->arena, &s->hb_s_opp, NN));
-    CHECK(dalloc(s->arena, &s->hb_w_same, ks + 1));
-    CHECK(dalloc(s->arena, &s->hb_p_same, ks + 1));
-    CHECK(dalloc(s->arena, &s->hb_a_same, ks + 1));
-    CHECK(dalloc(s->arena, &s->hb_s_same, np + 1));
-    // scratch of the alias construction (released afterwards)
+    // weights, alias thresholds, alias columns and row sums (scratch), then
+    // the packed tables the generator reads
     Arena tmp;
+    double *w_opp = nullptr, *p_opp = nullptr, *s_opp = nullptr, *w_same = nullptr, *p_same = nullptr,
+           *s_same = nullptr;
+    int *a_opp = nullptr, *a_same = nullptr;
+    CHECK(dalloc(tmp, &w_opp, ko));
+    CHECK(dalloc(tmp, &p_opp, ko));
+    CHECK(dalloc(tmp, &a_opp, ko));
+    CHECK(dalloc(tmp, &s_opp, NN));
+    CHECK(dalloc(tmp, &w_same, ks + 1));
+    CHECK(dalloc(tmp, &p_same, ks + 1));
+    CHECK(dalloc(tmp, &a_same, ks + 1));
+    CHECK(dalloc(tmp, &s_same, np + 1));
+    CHECK(dalloc(s->arena, &s->hb_opp, ko));
+    CHECK(dalloc(s->arena, &s->hb_same, ks + 1));
     double* scaled = nullptr;
     int *small = nullptr, *large = nullptr;
     const size_t kw = ko + ks + 1;
@@ -172,9 +175,12 @@ static int build_pchb(fciqmc_system* s, hipStream_t stream) {
     // row r of K columns uses [r*K, (r+1)*K) of a region sized for its class
     SysView v = s->view();
     const int rows = NN + np;
-    hipLaunchKernelGGL(k_pchb_build, dim3((rows + 63) / 64), dim3(64), 0, stream, v, s->hb_w_opp,
-                       s->hb_p_opp, s->hb_a_opp, s->hb_s_opp, s->hb_w_same, s->hb_p_same,
-                       s->hb_a_same, s->hb_s_same, scaled, small, large);
+    hipLaunchKernelGGL(k_pchb_build, dim3((rows + 63) / 64), dim3(64), 0, stream, v, w_opp, p_opp, a_opp, s_opp,
+                       w_same, p_same, a_same, s_same, scaled, small, large);
+    hipLaunchKernelGGL(k_pchb_pack, dim3(4096), dim3(256), 0, stream, w_opp, p_opp, a_opp, s_opp, NN, NN, s->hb_opp);
+    if (np > 0)
+        hipLaunchKernelGGL(k_pchb_pack, dim3(4096), dim3(256), 0, stream, w_same, p_same, a_same, s_same, np, np,
+                           s->hb_same);
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(stream));
     tmp.clear();

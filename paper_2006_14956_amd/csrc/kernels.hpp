@@ -932,6 +932,26 @@ __global__ void k_chunk_map(const int64_t* __restrict__ aoff, int B, int64_t* __
         for (int64_t c = aoff[b]; c < aoff[b + 1]; ++c) cmap[c] = ((int64_t)b << 32) | (c - aoff[b]);
 }
 
+// Pack a heat-bath class (rows x K columns of weights w, alias thresholds p,
+// alias columns a, row sums) into 32-byte entries; q = w / sum, the same
+// division a draw would make, and 0 for a zero row.
+__global__ void k_pchb_pack(const double* __restrict__ w, const double* __restrict__ p,
+                            const int* __restrict__ a, const double* __restrict__ sum, int rows, int K,
+                            HbEntry* __restrict__ out) {
+    const size_t n = (size_t)rows * (size_t)K;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t row = i / (size_t)K;
+        const double sm = sum[row];
+        HbEntry e;
+        e.prob = p[i];
+        e.alias = a[i];
+        e.pad = 0;
+        e.q_self = sm != 0.0 ? w[i] / sm : 0.0;
+        e.q_alias = sm != 0.0 ? w[row * (size_t)K + (size_t)a[i]] / sm : 0.0;
+        out[i] = e;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Batched launches: many independent walker populations (instances, each with
 // its own integrals, parameters and store) advance one step in shared
