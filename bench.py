@@ -115,7 +115,7 @@ def measure(F, np, torch, stream, name, steps, warmup):
         a = kern[k]["algorithmic_bytes"]
         kern[k]["achieved_GBps"] = a / (kern[k]["ms_per_launch"] * 1e-3) / 1e9 if a else None
     dom = max(("spawn", "annihilate"), key=lambda k: ms[k])
-    roof = roofline(kern, dom)
+    roof = roofline(kern, dom, name)
     desc = dict(desc, dets_mean=d_out, spawns_per_step=recs, attempts_per_step=attempts / len(st),
                 buckets=layout["buckets"], ms_per_step=1e3 * wall / steps,
                 attempts_per_s=attempts / wall)
@@ -400,11 +400,44 @@ def measure_served(F, np, n_req, rate, tol, budget, plain=True):
     return out
 
 
-def roofline(kern, k):
+KERNEL_SOURCES = ("paper_2006_14956_amd/csrc/kernels.hpp", "paper_2006_14956_amd/csrc/device.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_hubbard4x4_mol40.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when it is missing or the kernels changed since."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    if f"kernel sources sha256: {kernel_source_hash()}" not in text:
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 7 and cells[0] == workload and cells[1] == kernel:
+            try:
+                return float(cells[6])
+            except ValueError:
+                return None
+    return None
+
+
+def roofline(kern, k, workload=None):
     ab = kern[k]["algorithmic_bytes"]
     achieved = ab / (kern[k]["ms_per_launch"] * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": k, "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(workload, k) if workload else None,
             "algorithmic_bytes_per_launch": ab, "ms_per_launch": kern[k]["ms_per_launch"]}
 
 
@@ -500,7 +533,7 @@ def main():
             F, np, torch, stream, args.second, args.second_steps, args.second_warmup)
         second = {"config": desc2, "value": desc2["attempts_per_s"], "unit": "attempts/s",
                   "ms_per_step": desc2["ms_per_step"], "kernels": kern2,
-                  "roofline_annihilate": roofline(kern2, "annihilate")}
+                  "roofline_annihilate": roofline(kern2, "annihilate", args.second)}
         F.fciqmc_free_run(run2)
         F.fciqmc_free_system(sys2)
 
