@@ -148,12 +148,15 @@ __device__ __forceinline__ void pair_decode(uint64_t q, int n, int& x, int& y) {
 // Integrals.
 // --------------------------------------------------------------------------
 // One column of a heat-bath alias table, packed so that a draw reads a
-// single aligned 32-byte entry: the alias threshold and column, and the
-// normalised weight w/sum of both outcomes (this column and its alias).
+// single aligned 32-byte entry: the alias threshold and column, and for
+// both outcomes (this column and its alias) the signed two-electron value v
+// whose magnitude is the column's weight: (AI|BJ) for opposite spins,
+// (AI|BJ) - (AJ|BI) for equal spins, 0 where the weight is zeroed.  |v|
+// gives p(ab|ij) with the row sum, and v gives H_ij up to the fermion sign.
 struct alignas(32) HbEntry {
     double prob;
-    double q_self;
-    double q_alias;
+    double v_self;
+    double v_alias;
     int32_t alias;
     int32_t pad;
 };
@@ -173,6 +176,8 @@ struct SysView {
     // pre-computed heat-bath tables (see the PCHB generator)
     const HbEntry* hb_opp;   // rows (I alpha, J beta), N^2 columns each
     const HbEntry* hb_same;  // rows I < J, N(N-1)/2 columns each
+    const double* hb_sum_opp;   // row sums of the weights
+    const double* hb_sum_same;
     const int* pair_of;   // same-spin column index -> A*64+B
 };
 
@@ -213,13 +218,9 @@ __device__ __forceinline__ double h_single(const SysView& s, uint64_t a, uint64_
 
 // <D_j|H|D_i>, D_j = sgn a+_a a+_b a_j a_i D_i with i<j and a<b canonical;
 // the operator's coefficient is <ab||ij> = (ai|bj) - (aj|bi) on matching spins.
-__device__ __forceinline__ double h_double(const SysView& s, uint64_t a, uint64_t b, int si, int pi,
-                                           int sj, int pj, int sa, int pa, int sb, int pb) {
-    const double direct = (sa == si && sb == sj) ? eri(s, pa, pi, pb, pj) : 0.0;
-    const double exch = (sa == sj && sb == si) ? eri(s, pa, pj, pb, pi) : 0.0;
-    double v;
-    if (si == sj) v = direct - exch;
-    else v = (sa == si) ? direct : -exch;
+// Fermion sign of a+_a a+_b a_j a_i applied to (a, b): 1 if odd.
+__device__ __forceinline__ int double_parity(uint64_t a, uint64_t b, int si, int pi, int sj, int pj, int sa,
+                                             int pa, int sb, int pb) {
     uint64_t A = a, B = b;
     int par = below(A, B, si, pi);
     clear_so(A, B, si, pi);
@@ -228,7 +229,17 @@ __device__ __forceinline__ double h_double(const SysView& s, uint64_t a, uint64_
     par += below(A, B, sb, pb);
     set_so(A, B, sb, pb);
     par += below(A, B, sa, pa);
-    return (par & 1) ? -v : v;
+    return par & 1;
+}
+
+__device__ __forceinline__ double h_double(const SysView& s, uint64_t a, uint64_t b, int si, int pi,
+                                           int sj, int pj, int sa, int pa, int sb, int pb) {
+    const double direct = (sa == si && sb == sj) ? eri(s, pa, pi, pb, pj) : 0.0;
+    const double exch = (sa == sj && sb == si) ? eri(s, pa, pj, pb, pi) : 0.0;
+    double v;
+    if (si == sj) v = direct - exch;
+    else v = (sa == si) ? direct : -exch;
+    return double_parity(a, b, si, pi, sj, pj, sa, pa, sb, pb) ? -v : v;
 }
 
 // H_ii: sum_p h_pp + sum_{p<q} [(pp|qq) - delta(spin)(pq|qp)], canonical order,
@@ -391,18 +402,22 @@ __device__ __forceinline__ bool gen_pchb(const SysView& s, uint64_t a, uint64_t 
         const int K = N * N;
         const size_t base = (size_t)row * (size_t)K;
         const int c0 = (int)pick(r.x[2], (uint64_t)K);
-        // p(ab|ij) = w_ab / sum_row; zero for a zero row or a zero weight (null)
+        // p(ab|ij) = w_ab / sum_row with w_ab = |v|; a zero weight (or a
+        // zero row) is a null draw
         const HbEntry en = s.hb_opp[base + c0];
         const bool self = coin < en.prob;
         const int c = self ? c0 : en.alias;
-        const double pab = self ? en.q_self : en.q_alias;
-        if (pab == 0.0) return false;
+        const double v = self ? en.v_self : en.v_alias;
+        const double wc = fabs(v);
+        if (wc == 0.0) return false;
         const int A = c / N, Bo = c % N;
         if (((a >> A) & 1ULL) || ((b >> Bo) & 1ULL)) return false;
+        const double sum = s.hb_sum_opp[row];
         const double p1 = p_double * p_opp;
         const double p2 = p1 / (double)n_opp;
+        const double pab = wc / sum;
         out.pgen = p2 * pab;
-        out.H = h_double(s, a, b, 0, I, 1, J, 0, A, 1, Bo);
+        out.H = double_parity(a, b, 0, I, 1, J, 0, A, 1, Bo) ? -v : v;
         out.ta = (a & ~(1ULL << I)) | (1ULL << A);
         out.tb = (b & ~(1ULL << J)) | (1ULL << Bo);
         return true;
@@ -422,15 +437,18 @@ __device__ __forceinline__ bool gen_pchb(const SysView& s, uint64_t a, uint64_t 
     const HbEntry en = s.hb_same[base + c0];
     const bool self = coin < en.prob;
     const int c = self ? c0 : en.alias;
-    const double pab = self ? en.q_self : en.q_alias;
-    if (pab == 0.0) return false;
+    const double v = self ? en.v_self : en.v_alias;
+    const double wc = fabs(v);
+    if (wc == 0.0) return false;
     const int ab = s.pair_of[c];
     const int A = ab >> 6, Bo = ab & 63;
     if (((occ >> A) & 1ULL) || ((occ >> Bo) & 1ULL)) return false;
+    const double sum = s.hb_sum_same[row];
     const double p1 = p_double * (1.0 - p_opp);
     const double p2 = p1 / (double)n_same;
+    const double pab = wc / sum;
     out.pgen = p2 * pab;
-    out.H = h_double(s, a, b, sg, I, sg, J, sg, A, sg, Bo);
+    out.H = double_parity(a, b, sg, I, sg, J, sg, A, sg, Bo) ? -v : v;
     const uint64_t m = (occ & ~(1ULL << I) & ~(1ULL << J)) | (1ULL << A) | (1ULL << Bo);
     out.ta = sg ? a : m;
     out.tb = sg ? m : b;

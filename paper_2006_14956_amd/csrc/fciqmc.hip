@@ -129,6 +129,7 @@ struct fciqmc_system {
     int *deg = nullptr, *nbr = nullptr, *pair_of = nullptr;
     bool pchb = false;
     HbEntry *hb_opp = nullptr, *hb_same = nullptr;  // packed alias tables
+    double *hb_sum_opp = nullptr, *hb_sum_same = nullptr;  // their row sums
     int device = 0;
 
     SysView view() const {
@@ -139,6 +140,8 @@ struct fciqmc_system {
         v.deg = deg; v.nbr = nbr;
         v.hb_opp = hb_opp;
         v.hb_same = hb_same;
+        v.hb_sum_opp = hb_sum_opp;
+        v.hb_sum_same = hb_sum_same;
         v.pair_of = pair_of;
         return v;
     }
@@ -152,17 +155,16 @@ static int build_pchb(fciqmc_system* s, hipStream_t stream) {
     // weights, alias thresholds, alias columns and row sums (scratch), then
     // the packed tables the generator reads
     Arena tmp;
-    double *w_opp = nullptr, *p_opp = nullptr, *s_opp = nullptr, *w_same = nullptr, *p_same = nullptr,
-           *s_same = nullptr;
+    double *w_opp = nullptr, *p_opp = nullptr, *w_same = nullptr, *p_same = nullptr;
     int *a_opp = nullptr, *a_same = nullptr;
     CHECK(dalloc(tmp, &w_opp, ko));
     CHECK(dalloc(tmp, &p_opp, ko));
     CHECK(dalloc(tmp, &a_opp, ko));
-    CHECK(dalloc(tmp, &s_opp, NN));
     CHECK(dalloc(tmp, &w_same, ks + 1));
     CHECK(dalloc(tmp, &p_same, ks + 1));
     CHECK(dalloc(tmp, &a_same, ks + 1));
-    CHECK(dalloc(tmp, &s_same, np + 1));
+    CHECK(dalloc(s->arena, &s->hb_sum_opp, NN));
+    CHECK(dalloc(s->arena, &s->hb_sum_same, np + 1));
     CHECK(dalloc(s->arena, &s->hb_opp, ko));
     CHECK(dalloc(s->arena, &s->hb_same, ks + 1));
     double* scaled = nullptr;
@@ -175,11 +177,11 @@ static int build_pchb(fciqmc_system* s, hipStream_t stream) {
     // row r of K columns uses [r*K, (r+1)*K) of a region sized for its class
     SysView v = s->view();
     const int rows = NN + np;
-    hipLaunchKernelGGL(k_pchb_build, dim3((rows + 63) / 64), dim3(64), 0, stream, v, w_opp, p_opp, a_opp, s_opp,
-                       w_same, p_same, a_same, s_same, scaled, small, large);
-    hipLaunchKernelGGL(k_pchb_pack, dim3(4096), dim3(256), 0, stream, w_opp, p_opp, a_opp, s_opp, NN, NN, s->hb_opp);
+    hipLaunchKernelGGL(k_pchb_build, dim3((rows + 63) / 64), dim3(64), 0, stream, v, w_opp, p_opp, a_opp,
+                       s->hb_sum_opp, w_same, p_same, a_same, s->hb_sum_same, scaled, small, large);
+    hipLaunchKernelGGL(k_pchb_pack, dim3(4096), dim3(256), 0, stream, v, true, p_opp, a_opp, NN, NN, s->hb_opp);
     if (np > 0)
-        hipLaunchKernelGGL(k_pchb_pack, dim3(4096), dim3(256), 0, stream, w_same, p_same, a_same, s_same, np, np,
+        hipLaunchKernelGGL(k_pchb_pack, dim3(4096), dim3(256), 0, stream, v, false, p_same, a_same, np, np,
                            s->hb_same);
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(stream));
@@ -1548,12 +1550,17 @@ void blocking(std::vector<double> x, std::vector<double> y, double& mx, double& 
     ratio = my != 0.0 ? mx / my : NAN;
     std::vector<Level> lx, lr;
     while (x.size() >= 2) {
+        // (co)variances about this level's own means (a level drops the odd
+        // last element); the ratio's derivatives at the overall means
         const size_t n = x.size();
+        double ax = 0.0, ay = 0.0;
+        for (size_t i = 0; i < n; ++i) { ax += x[i]; ay += y[i]; }
+        ax /= (double)n; ay /= (double)n;
         double vx = 0.0, vy = 0.0, cxy = 0.0;
         for (size_t i = 0; i < n; ++i) {
-            vx += (x[i] - mx) * (x[i] - mx);
-            vy += (y[i] - my) * (y[i] - my);
-            cxy += (x[i] - mx) * (y[i] - my);
+            vx += (x[i] - ax) * (x[i] - ax);
+            vy += (y[i] - ay) * (y[i] - ay);
+            cxy += (x[i] - ax) * (y[i] - ay);
         }
         vx /= (double)n; vy /= (double)n; cxy /= (double)n;
         const double e = std::sqrt(vx / (double)(n - 1));
