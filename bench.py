@@ -92,20 +92,20 @@ def measure(F, np, torch, stream, name, steps, warmup):
     F.fciqmc_profile(run, True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    st = F.fciqmc_step(run, steps)
+    st = F.fciqmc_step(run, steps, as_array=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t1
     ms, nsteps, layout = F.fciqmc_profile(run, False)
-    attempts = sum(x["attempts"] for x in st)
-    spawns = sum(x["spawns"] for x in st)
+    attempts = int(st["attempts"].sum())
+    spawns = int(st["spawns"].sum())
     log(f"[{name}] timed {steps} steps in {wall:.4f}s: {attempts / wall:.4e} attempts/s, "
         f"{1e3 * wall / steps:.4f} ms/step; kernels (ms total): "
         + ", ".join(f"{k}={v:.2f}" for k, v in ms.items()))
     # roofline of the dominant kernel from the live event timings
     words = 1 if s.n_orb <= 32 else 2
     vbytes = 4 if pd.get("mode", F.MODE_INTEGER) == F.MODE_INTEGER else 8
-    dets = [x["ndets"] for x in st]
-    d_in = float(np.mean([st[0]["ndets"]] + dets[:-1]))
+    dets = [int(x) for x in st["ndets"]]
+    d_in = float(np.mean([dets[0]] + dets[:-1]))
     d_out = float(np.mean(dets))
     recs = spawns / len(st)
     kern = {k: {"ms_per_launch": v / nsteps,
@@ -200,16 +200,16 @@ def measure_batched(F, np, steps, warmup, grow_max, tune_steps, plain=True):
     snap = [(F.fciqmc_get_walkers(r), F.fciqmc_get_checkpoint(r)) for r in runs]
     F.fciqmc_batch_profile(batch, True)
     t1 = time.perf_counter()
-    st = F.fciqmc_batch_step(batch, steps)
+    st = F.fciqmc_batch_step(batch, steps, as_array=True)
     wall = time.perf_counter() - t1
     ms, nsteps = F.fciqmc_batch_profile(batch, False)
-    att = sum(x["attempts"] for row in st for x in row)
-    final_b = [x["nw"] for x in st[-1]]
+    att = int(st["attempts"].sum())
+    final_b = [float(x) for x in st[-1]["nw"]]
     rate_b = att / wall
     log(f"[batched] timed {steps} steps in {wall:.3f}s: {rate_b:.4e} attempts/s, "
         f"{1e3 * wall / steps:.4f} ms/step; kernels (ms total): "
         + ", ".join(f"{k}={v:.2f}" for k, v in ms.items()))
-    ndets = sum(x["ndets"] for x in st[-1])
+    ndets = int(st[-1]["ndets"].sum())
     F.fciqmc_batch_free(batch)
     for r in runs:
         F.fciqmc_free_run(r)
@@ -226,10 +226,10 @@ def measure_batched(F, np, steps, warmup, grow_max, tune_steps, plain=True):
             F.fciqmc_set_checkpoint(r, **ck)
             solo.append(r)
         t2 = time.perf_counter()
-        sst = [F.fciqmc_step(r, steps) for r in solo]
+        sst = [F.fciqmc_step(r, steps, as_array=True) for r in solo]
         wall_p = time.perf_counter() - t2
-        att_p = sum(x["attempts"] for rs in sst for x in rs)
-        same = all(rs[-1]["nw"] == nb for rs, nb in zip(sst, final_b))
+        att_p = int(sum(rs["attempts"].sum() for rs in sst))
+        same = all(float(rs[-1]["nw"]) == nb for rs, nb in zip(sst, final_b))
         log(f"[plain] {steps} steps of each run in turn: {wall_p:.3f}s, {att_p / wall_p:.4e} attempts/s; "
             f"final populations equal to the batch's: {same}")
         for r in solo:
@@ -490,12 +490,9 @@ def main():
     stream = torch.cuda.current_stream()
     s, pd, desc, run, sysd, st, wall, ms, nsteps, layout, kern, roof = measure(
         F, np, torch, stream, args.workload, args.steps, args.warmup)
-    attempts = sum(x["attempts"] for x in st)
-    spawns = sum(x["spawns"] for x in st)
+    attempts = int(st["attempts"].sum())
     value = attempts / wall
     words = 1 if s.n_orb <= 32 else 2
-    d_out = float(np.mean([x["ndets"] for x in st]))
-    recs = spawns / len(st)
 
     cpu = None
     if not args.no_cpu:

@@ -259,9 +259,9 @@ typedef struct fciqmc_request_info {
 
 /* Device bytes a run with these parameters reserves: a walker store of one
  * bucket (1024 entries) per 256 target walkers and at least twice the
- * initial buckets, spawn slabs for three records per target walker, and the
- * staging buffer of a population import.  Negative FCIQMC_E* on bad
- * arguments. */
+ * initial buckets, spawn slabs for six records per target walker (a growing
+ * population overshoots its target), and an import staging buffer for three
+ * times the target.  Negative FCIQMC_E* on bad arguments. */
 int64_t fciqmc_estimate_bytes(const fciqmc_system *sys, const fciqmc_params *p);
 /* hbm_budget_bytes: device memory the running solves may reserve together;
  * max_running: largest batch; stream as for fciqmc_init. */

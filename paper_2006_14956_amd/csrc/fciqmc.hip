@@ -1227,8 +1227,8 @@ static void initial_capacity(const fciqmc_params* p, int& B, long long& spawn_ca
 // Device bytes a run reserves: a walker store of one bucket per 256 walkers
 // of the target (a bucket's LDS table holds about that many determinants
 // next to their spawn targets), at least one doubling of the initial store;
-// spawn slabs for three records per target walker plus the per-sub-slab
-// floor; the import staging buffer.
+// spawn slabs for six records per target walker plus the per-sub-slab
+// floor; an import staging buffer for three times the target.
 static int64_t reserve_bytes(const fciqmc_system* sys, const fciqmc_params* p) {
     int B = 1;
     long long cap = 0;
@@ -1241,9 +1241,10 @@ static int64_t reserve_bytes(const fciqmc_system* sys, const fciqmc_params* p) {
     const int64_t entry = 8 * W + vb + 8 + 4;                     // key, value, diagonal, attempt prefix
     const int64_t store = Br * 1024 * entry + Br * (4 + 8 + 8);
     const int64_t per_bucket = Br * (kSub * (4 + 8 + 8) + 8 * 4);
-    const double recs = std::max<double>((double)cap, 3.0 * target) + 256.0 * (double)Br;
+    // a growing population overshoots the target before the shift holds it
+    const double recs = std::max<double>((double)cap, 6.0 * target) + 256.0 * (double)Br;
     const int64_t slabs = (int64_t)(1.25 * recs) * rb;
-    const int64_t stage = (int64_t)target * rb;
+    const int64_t stage = (int64_t)(3.0 * target) * rb;
     return 2 * store + per_bucket + slabs + stage + (1 << 20);
 }
 

@@ -237,10 +237,17 @@ STATS_DTYPE = np.dtype([(n, np.int64 if t in (C.c_int64,) else (np.int32 if t is
                         for n, t in StepStats._fields_])
 
 
-def fciqmc_step(run: Run, n_steps: int = 1):
-    """Advance n_steps; returns a list of per-step stats dicts."""
+assert STATS_DTYPE.itemsize == C.sizeof(StepStats)
+
+
+def fciqmc_step(run: Run, n_steps: int = 1, as_array: bool = False):
+    """Advance n_steps; returns a list of per-step stats dicts, or with
+    as_array a numpy structured array over the same memory (no per-step
+    Python work)."""
     arr = (StepStats * max(1, n_steps))()
     _check(lib().fciqmc_step(run.handle, int(n_steps), arr))
+    if as_array:
+        return np.frombuffer(arr, dtype=STATS_DTYPE, count=n_steps)
     return [{k: getattr(arr[i], k) for k, _ in StepStats._fields_} for i in range(n_steps)]
 
 
@@ -344,11 +351,14 @@ def fciqmc_batch_size(batch: Batch) -> int:
     return int(lib().fciqmc_batch_size(batch.handle))
 
 
-def fciqmc_batch_step(batch: Batch, n_steps: int = 1):
-    """Advance every member n_steps; returns [step][member] stats dicts."""
+def fciqmc_batch_step(batch: Batch, n_steps: int = 1, as_array: bool = False):
+    """Advance every member n_steps; returns [step][member] stats dicts, or
+    with as_array a (n_steps, members) numpy structured array."""
     m = len(batch.members)
     arr = (StepStats * max(1, n_steps * m))()
     _check(lib().fciqmc_batch_step(batch.handle, int(n_steps), arr))
+    if as_array:
+        return np.frombuffer(arr, dtype=STATS_DTYPE, count=n_steps * m).reshape(n_steps, m)
     return [[{k: getattr(arr[s * m + i], k) for k, _ in StepStats._fields_} for i in range(m)]
             for s in range(n_steps)]
 
