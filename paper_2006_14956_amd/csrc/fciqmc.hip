@@ -456,7 +456,7 @@ template <int W, class V> struct Engine : EngineBase {
         hipLaunchKernelGGL((k_annihilate<W, V>), dim3(gb), dim3(kThreads), 0, stream, v, in, out, sc,
                            rec2, soff, scount, rel, need_b, recs_b, nw_b, en_b, fpos, fcnt, ctl);
         if (!sys->onsite) {
-            const int64_t items = (B + kFreshSpan - 1) / kFreshSpan;
+            const int64_t items = fresh_items(B);
             hipLaunchKernelGGL((k_fresh<W, V>), dim3((unsigned)std::min<int64_t>(items, 4096)), dim3(kThreads),
                                fresh_lds_bytes(sys->N), stream, v, out, sc, fpos, fcnt, ctl);
         }
@@ -933,7 +933,7 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
             btot += eng(i)->B;
             ff[i] = ftot;
             if (!hi[i].sys.onsite) {
-                ftot += (eng(i)->B + kFreshSpan - 1) / kFreshSpan;
+                ftot += fresh_items(eng(i)->B);
                 flds = std::max(flds, fresh_lds_bytes(hi[i].sys.N));
             }
         }

@@ -688,13 +688,24 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
 // ---------------------------------------------------------------------------
 // Diagonals H_jj - H_00 of the determinants that entered the store this step
 // (molecular systems; lattice systems compute theirs in the per-bucket
-// kernel).  Work item g covers buckets [g*kFreshSpan, (g+1)*kFreshSpan): h_pp,
-// X and J are staged in LDS, then one lane per listed determinant sums its
-// diagonal in the canonical order.  Done here rather than in the per-bucket
-// kernel because each diagonal is a long serial chain that would hold that
-// kernel's LDS hash table while one wave works.
+// kernel).  Work item g covers buckets [g*span, (g+1)*span): h_pp, X and J
+// are staged in LDS, then one lane per listed determinant sums its diagonal
+// in the canonical order.  Done here rather than in the per-bucket kernel
+// because each diagonal is a long serial chain that would hold that
+// kernel's LDS hash table while one wave works.  The span grows with the
+// bucket count (about 2048 work items, at most 32 buckets each) so that
+// small stores still spread their diagonals over many workgroups.
 // ---------------------------------------------------------------------------
-constexpr int kFreshSpan = 32;
+constexpr int kFreshSpan = 32;  // largest span
+
+__host__ __device__ inline int fresh_span(int B) {
+    const int s = B / 2048;
+    return s < 1 ? 1 : (s > kFreshSpan ? kFreshSpan : s);
+}
+__host__ __device__ inline int64_t fresh_items(int B) {
+    const int s = fresh_span(B);
+    return (B + s - 1) / s;
+}
 
 __host__ __device__ inline size_t fresh_lds_bytes(int N) { return sizeof(double) * ((size_t)N + 2 * (size_t)N * N); }
 
@@ -702,8 +713,9 @@ template <int W, class V>
 __device__ __forceinline__ void fresh_item(const SysView& sys, const Store<V>& out, double h00, int R, int B,
                                            const uint16_t* __restrict__ fpos, const int32_t* __restrict__ fcnt,
                                            int64_t g, double* tabs, int* pre) {
-    const int b0 = (int)(g * kFreshSpan);
-    const int nb = min(kFreshSpan, B - b0);
+    const int span = fresh_span(B);
+    const int b0 = (int)(g * span);
+    const int nb = min(span, B - b0);
     const int N = sys.N;
     double* hd = tabs;
     double* xt = tabs + N;
@@ -741,7 +753,7 @@ __global__ __launch_bounds__(kThreads) void k_fresh(SysView sys, Store<V> out, S
     __shared__ int pre[kFreshSpan + 1];
     __shared__ unsigned fl;
     if (wg_flags(ctl, &fl)) return;
-    const int64_t items = (sc.B + kFreshSpan - 1) / kFreshSpan;
+    const int64_t items = fresh_items(sc.B);
     for (int64_t g = blockIdx.x; g < items; g += gridDim.x)
         fresh_item<W, V>(sys, out, sc.h00, sc.R, sc.B, fpos, fcnt, g, tabs, pre);
 }
