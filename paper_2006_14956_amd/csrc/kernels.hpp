@@ -304,12 +304,17 @@ template <int W, class V> struct LdsTable {
     uint64_t key0[kSlots];
     uint64_t key1[W == 2 ? kSlots : 1];
     V val[kSlots];
-    int32_t idx[kSlots];   // entry index in the input store, -1 for a new determinant
+    int16_t idx[kSlots];   // entry index in the input store (< R), -1 for a new determinant
 };
+
+// New survivors of lattice systems awaiting their diagonal (slot | out
+// position << 11); one-word layouts only, two-word lattice stores compute
+// theirs inline.
+template <int W> constexpr int fresh_cap() { return W == 1 ? kFresh : 0; }
 
 template <int W, class V> struct Lds {
     LdsTable<W, V> t;
-    int32_t fresh[kFresh]; // lattice systems: new survivors awaiting their diagonal, slot | out position << 11
+    int32_t fresh[W == 1 ? kFresh : 1];
     int nfresh;
     int64_t sh64[8];
     double shd[8];
@@ -608,7 +613,7 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
                 // new determinant of a lattice system: its (short) diagonal is
                 // computed below, spread over the workgroup
                 const int f = atomicAdd(&L.nfresh, 1);
-                if (f < kFresh) L.fresh[f] = s | ((int)pos << 11);
+                if (f < fresh_cap<W>()) L.fresh[f] = s | ((int)pos << 11);
                 else { const double hd = h_diag(sys, ka, kb); out.diag[o] = hd - sc.h00; }
             } else {
                 // new determinant: listed for the diagonal kernel (k_fresh)
@@ -640,9 +645,9 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
     __syncthreads();
     if (sys.onsite) {
         // diagonals of new lattice determinants, spread over the workgroup
-        const int nf = min(L.nfresh, kFresh);
+        const int nf = min(L.nfresh, fresh_cap<W>());
 #pragma unroll
-        for (int i = 0; i < kFresh / kThreads; ++i) {
+        for (int i = 0; i < fresh_cap<W>() / kThreads; ++i) {
             const int f = threadIdx.x + i * kThreads;
             if (f >= nf) continue;
             const int s = L.fresh[f] & 2047;
@@ -1027,7 +1032,7 @@ __global__ __launch_bounds__(kThreads) void k_spawn_batch(const Inst<W, V>* __re
 }
 
 template <int W, class V>
-__global__ __launch_bounds__(kThreads) void k_annihilate_batch(const Inst<W, V>* __restrict__ inst,
+__global__ __launch_bounds__(kThreads, 6) void k_annihilate_batch(const Inst<W, V>* __restrict__ inst,
                                                                const int64_t* __restrict__ first, int k) {
     __shared__ Lds<W, V> L;
     __shared__ unsigned fl;
