@@ -500,4 +500,34 @@ template <int NT, class T> __device__ __forceinline__ T block_excl_scan(T v, T& 
     return off + inc - v;
 }
 
+// Four exclusive prefix sums over the workgroup with one exchange (two
+// barriers): v[k] becomes the exclusive prefix of v[k], tot[k] the total.
+// sh holds 4 * NT/64 values.
+template <int NT>
+__device__ __forceinline__ void block_excl_scan4(int64_t (&v)[4], int64_t (&tot)[4], int64_t* sh) {
+    constexpr int NW = NT / 64;
+    const int w = (int)(threadIdx.x >> 6);
+    int64_t inc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) inc[k] = wave_incl_scan(v[k]);
+    if (lane_id() == 63) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sh[k * NW + w] = inc[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int64_t off = 0, t = 0;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            const int64_t x = sh[k * NW + i];
+            if (i < w) off += x;
+            t += x;
+        }
+        tot[k] = t;
+        v[k] = off + inc[k] - v[k];
+    }
+    __syncthreads();
+}
+
 }  // namespace fq

@@ -404,13 +404,13 @@ __device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, cons
         nw = nw + nw_b[b];
         en = en + en_b[b];
     }
-    int64_t atot, ktot, ntot, crtot;
-    (void)block_excl_scan<NT, int64_t>(la, atot, sh);
-    const int64_t kbase = block_excl_scan<NT, int64_t>(lk, ktot, sh);
-    const int64_t nbase = block_excl_scan<NT, int64_t>(ln, ntot, sh);
-    // determinants (< 2^32) and records (< 2^31 per step) packed in one scan
-    (void)block_excl_scan<NT, int64_t>((cnt << 32) | rc, crtot, sh);
-    int64_t run = kbase, base = nbase;
+    // attempts, chunks, slab sizes, and determinants (< 2^32) with records
+    // (< 2^31 per step) packed: four prefix sums in one exchange
+    int64_t v[4] = {la, lk, ln, (cnt << 32) | rc};
+    int64_t tot[4];
+    block_excl_scan4<NT>(v, tot, sh);
+    const int64_t atot = tot[0], ktot = tot[1], ntot = tot[2], crtot = tot[3];
+    int64_t run = v[1], base = v[2];
     for (int b = b0; b < b1; ++b) {
         aoff[b] = run;
         const int64_t nk = chunks_of(batt[b]);
@@ -934,7 +934,7 @@ __global__ __launch_bounds__(kPostThreads) void k_post(const int64_t* __restrict
                                                const int64_t* __restrict__ recs_b,
                                                int64_t* __restrict__ soff, int64_t* __restrict__ cmap,
                                                int64_t cmap_cap, Ctl* ctl, Ctl* __restrict__ host) {
-    __shared__ int64_t sh[kPostThreads / 64], shm[kPostThreads / 64];
+    __shared__ int64_t sh[4 * kPostThreads / 64], shm[kPostThreads / 64];
     __shared__ double shd[2 * kPostThreads / 64];
     if (!ctl->flags)
         post_work<kPostThreads>(batt, count, nw_b, en_b, rel, need_b, recs_b, B, aoff, soff, cmap, cmap_cap, ctl,
@@ -1068,7 +1068,7 @@ __global__ __launch_bounds__(kThreads) void k_fresh_batch(const Inst<W, V>* __re
 template <int W, class V>
 __global__ __launch_bounds__(kPostThreads) void k_post_batch(const Inst<W, V>* __restrict__ inst,
                                                              Ctl* __restrict__ ctl_out) {
-    __shared__ int64_t sh[kPostThreads / 64], shm[kPostThreads / 64];
+    __shared__ int64_t sh[4 * kPostThreads / 64], shm[kPostThreads / 64];
     __shared__ double shd[2 * kPostThreads / 64];
     __shared__ unsigned fl;
     const Inst<W, V>& I = inst[blockIdx.x];

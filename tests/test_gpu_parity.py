@@ -231,3 +231,47 @@ def test_trajectory_independent_of_bucket_count(buckets_log2):
     assert_same_walkers(run, orun)
     F.fciqmc_free_run(run)
     F.fciqmc_free_system(sysd)
+
+
+def test_bucket_growth_by_occupancy_keeps_trajectory():
+    """A 1024-determinant capacity hint starts the store at one bucket; the
+    population outgrows 600 determinants per bucket and the store doubles
+    several times between steps (discarding the queued spawn launch each
+    time); every step still equals the oracle's."""
+    s = inputs.molecule_8o8e()
+    sysd, run, orun = make_pair(s, tau=0.01, target=1e4, seed=5, max_dets=1024)
+    assert F.fciqmc_profile(run, False)[2]["buckets"] == 1
+    for block in range(4):
+        g = F.fciqmc_step(run, 100)
+        o = orun.step(100)
+        for gg, oo in zip(g, o):
+            assert_same_stats(gg, oo)
+        assert_same_walkers(run, orun)
+    assert F.fciqmc_profile(run, False)[2]["buckets"] >= 4
+    F.fciqmc_free_run(run)
+    F.fciqmc_free_system(sysd)
+
+
+def test_state_calls_between_steps_keep_trajectory():
+    """Reading walkers, re-importing them and resetting the checkpoint
+    between steps (each meets a queued spawn launch) leave the trajectory
+    that of the oracle."""
+    s = inputs.molecule_8o8e()
+    sysd, run, orun = make_pair(s, tau=0.01, target=1e4, seed=6)
+    F.fciqmc_step(run, 150)
+    orun.step(150)
+    a, b, v = F.fciqmc_get_walkers(run)       # read while a spawn is queued
+    g = F.fciqmc_step(run, 30)
+    o = orun.step(30)
+    for gg, oo in zip(g, o):
+        assert_same_stats(gg, oo)
+    F.fciqmc_set_walkers(run, *F.fciqmc_get_walkers(run))   # re-import mid-run
+    ck = F.fciqmc_get_checkpoint(run)
+    F.fciqmc_set_checkpoint(run, **ck)
+    g = F.fciqmc_step(run, 30)
+    o = orun.step(30)
+    for gg, oo in zip(g, o):
+        assert_same_stats(gg, oo)
+    assert_same_walkers(run, orun)
+    F.fciqmc_free_run(run)
+    F.fciqmc_free_system(sysd)
