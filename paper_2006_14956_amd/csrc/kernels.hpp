@@ -492,6 +492,25 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
     int nslots = kThreads;
     while (nslots < want && nslots < kSlots) nslots <<= 1;
     const uint64_t mask = (uint64_t)(nslots - 1);
+    // this thread's first determinant and first record are loaded now, so
+    // their latency overlaps the table reset (and the death pass)
+    const int e0 = (int)threadIdx.x;
+    Key<W> pk;
+    V pC = (V)0;
+    double pd = 0.0;
+    if (e0 < cnt) {
+        pk = load_key<W>(in.keys + (eb + e0) * W);
+        pC = in.vals[eb + e0];
+        pd = in.diag[eb + e0];
+    }
+    Rec<W, V> prec;
+    if ((int64_t)e0 < cum[kSub]) {
+        int64_t src = 0;
+#pragma unroll
+        for (int j = 0; j < kSub; ++j)
+            if (e0 >= cum[j] && e0 < cum[j + 1]) src = lo[j] + (e0 - cum[j]);
+        prec = rec2[src];
+    }
     for (int i = threadIdx.x; i < nslots; i += kThreads) {
         L.t.key0[i] = kEmpty;
         if constexpr (W == 2) L.t.key1[i] = kEmpty;
@@ -502,10 +521,19 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
     __syncthreads();
     // (b) death of the walkers occupied at tau: x = (1 - dtau (d_i - S)) C_i,
     // stochastically rounded; the slot is marked as occupied at tau.
-    for (int e = threadIdx.x; e < cnt; e += kThreads) {
-        const Key<W> key = load_key<W>(in.keys + (eb + e) * W);
-        const V C = in.vals[eb + e];
-        const double d = in.diag[eb + e];
+    for (int e = e0; e < cnt; e += kThreads) {
+        Key<W> key;
+        V C;
+        double d;
+        if (e == e0) {
+            key = pk;
+            C = pC;
+            d = pd;
+        } else {
+            key = load_key<W>(in.keys + (eb + e) * W);
+            C = in.vals[eb + e];
+            d = in.diag[eb + e];
+        }
         const double t1 = d - sc.S;
         const double t2 = sc.tau * t1;
         const double f = 1.0 - t2;
@@ -536,12 +564,12 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
     __syncthreads();
     // (c) annihilation: a target occupied at tau takes every contribution;
     // an unoccupied one only those of initiator parents (Sec. I).
-    for (int64_t q = threadIdx.x; q < cum[kSub]; q += kThreads) {
+    for (int64_t q = e0; q < cum[kSub]; q += kThreads) {
         int64_t src = 0;
 #pragma unroll
         for (int j = 0; j < kSub; ++j)
             if (q >= cum[j] && q < cum[j + 1]) src = lo[j] + (q - cum[j]);
-        const Rec<W, V> x = rec2[src];
+        const Rec<W, V> x = q == e0 ? prec : rec2[src];
         Key<W> key;
 #pragma unroll
         for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
