@@ -275,3 +275,26 @@ def test_state_calls_between_steps_keep_trajectory():
     assert_same_walkers(run, orun)
     F.fciqmc_free_run(run)
     F.fciqmc_free_system(sysd)
+
+
+def test_real_mode_statistics_match_oracle():
+    """Real coefficients, initiators, PCHB, two-word layout (the 40-orbital
+    workload's kind of run) on a 10-orbital molecule: the trajectories part
+    once a rounding decision sees a last-bit difference, so the comparison
+    is statistical -- the blocked mean shifts after equilibration agree
+    within four combined standard errors."""
+    s = inputs.synthetic_molecule(10, 4, 4, seed=2)
+    sysd, run, orun = make_pair(s, tau=0.01, target=2e3, mode="real", gen="pchb", det_words=2,
+                                n_a=3.0, zeta=0.3, seed=12)
+    g = F.fciqmc_step(run, 6000)
+    o = orun.step(6000)
+    gs = [x["shift"] for x in g[2000:]]
+    os_ = [x["shift"] for x in o[2000:]]
+    assert all(x["vary_shift"] for x in g[2000:]) and all(x["vary"] for x in o[2000:])
+    mg, eg = brute.blocked_error(gs)
+    mo, eo = brute.blocked_error(os_)
+    z = abs(mg - mo) / np.sqrt(eg ** 2 + eo ** 2)
+    assert z < 4.0, (mg, eg, mo, eo)
+    assert abs(np.mean([x["nw"] for x in g[2000:]]) / 2e3 - 1.0) < 0.2
+    F.fciqmc_free_run(run)
+    F.fciqmc_free_system(sysd)
