@@ -17,7 +17,7 @@ _SRC = os.path.join(_HERE, "fciqmc_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 MODE_INTEGER, MODE_REAL = 0, 1
-GEN_UNIFORM, GEN_LATTICE, GEN_PCHB = 0, 1, 2
+GEN_UNIFORM, GEN_LATTICE, GEN_PCHB, GEN_CS, GEN_PE = 0, 1, 2, 3, 4
 
 
 def build(force: bool = True) -> str:

@@ -490,7 +490,7 @@ int orc_lattice_degree(const orc_sys *s, int p) { return s->deg[p]; }
 /* Walker population and the step.                                            */
 /* ------------------------------------------------------------------------- */
 enum { MODE_INTEGER = 0, MODE_REAL = 1 };
-enum { GEN_UNIFORM = 0, GEN_LATTICE = 1, GEN_PCHB = 2 };
+enum { GEN_UNIFORM = 0, GEN_LATTICE = 1, GEN_PCHB = 2, GEN_CS = 3, GEN_PE = 4 };
 
 typedef struct {
     det_t d;
@@ -667,6 +667,8 @@ static double round_cmin(double x, double cmin, double u)
 
 int orc_pchb_gen(const orc_sys *s, det_t d, const uint64_t r1[4], const uint64_t r2[4],
                  double p_single, double p_opp, det_t *tgt, double *pgen);
+int orc_cs_gen(const orc_sys *s, det_t d, const uint64_t r1[4], const uint64_t r2[4],
+               double p_single, double p_opp, int exact, det_t *tgt, double *pgen);
 
 /* One imaginary-time step, Eq. (projector) split as Eq. (fciqmc_dyn):
  * (a) spawning from C(tau), (b) death in place, (c) annihilation with the
@@ -704,7 +706,10 @@ int orc_run_step(orc_run *r, orc_stats *st)
             else {
                 uint64_t r2[4];
                 draw(r, e->d, t, (uint64_t)k, PURPOSE_SPAWN2, r2);
-                ok = orc_pchb_gen(s, e->d, rr, r2, p->p_single, p->p_opp, &tgt, &pgen);
+                if (p->gen == GEN_PCHB)
+                    ok = orc_pchb_gen(s, e->d, rr, r2, p->p_single, p->p_opp, &tgt, &pgen);
+                else
+                    ok = orc_cs_gen(s, e->d, rr, r2, p->p_single, p->p_opp, p->gen == GEN_PE, &tgt, &pgen);
             }
             if (!ok) continue;
             double H = orc_hij_det(s, e->d, tgt);
@@ -1103,6 +1108,198 @@ void orc_pchb_row(const orc_sys *s, int opp, int row, double *w, double *prob, i
 }
 
 /* ------------------------------------------------------------------------- */
+/* On-the-fly Cauchy-Schwarz (CS) and Part-Exact (PE) generators              */
+/* (Appendix A.2).  No tables: every draw builds its cumulative probability  */
+/* functions (CPFs) from the integrals.                                        */
+/*                                                                             */
+/* Singles (weighted, Appendix A.2 "Single excitations"): electron i uniform  */
+/* among the n; hole a among the same-spin holes with weight |<D_i^a|H|D>|.   */
+/*   p_gen = (p_single / n) (w_a / sum_h w_h).                                 */
+/* Doubles, electron pair: i uniform among the n; j != i from the CPF with    */
+/* weights |<ik|ik>| = |(ii|kk)| times p_opp (opposite spins) or 1 - p_opp    */
+/* (equal spins).  p(ij) = (w_ij / S_i + w_ji / S_j) / n, where S_x is the    */
+/* sum of the CPF built from electron x.                                       */
+/*   Readings: the paper writes 1/N in p(ij), but i is drawn among the n      */
+/*   electrons, so the factor is 1/n; the two printed forms F_{j-i} and        */
+/*   F_{j-1} of the CPF increment are read as F_{j-1}, the weight of j.       */
+/* Opposite spins (i beta, j alpha by the paper's convention): hole a among   */
+/* the beta holes with weight sqrt(<aa|ii>) = sqrt((ia|ia)); hole b among the */
+/* alpha holes with weight sqrt(|<ij|ab>|) = sqrt(|(ia|jb)|) (PE) or          */
+/* sqrt(<bb|jj>) (CS).  p_gen = p_double p(ij) p(a|i) p(b|ija).               */
+/* Equal spins sigma: hole a among the sigma holes with weight                */
+/* sqrt(<aa|ii>) + sqrt(<aa|jj>); hole b among the other sigma holes with     */
+/* weight sqrt(|<ij|ab> - <ij|ba>|) = sqrt(|(ia|jb) - (ib|ja)|) (PE) or the    */
+/* first-hole weight (CS).  Either order of the holes gives the same target: */
+/*   p_gen = p_double p(ij) [p(a|ij) p(b|ija) + p(b|ij) p(a|ijb)].            */
+/* Readings: there are no point-group labels, so every orbital shares one     */
+/* irrep and the symmetry restriction of the paper is void; Coulomb integrals */
+/* and the arguments of the square roots enter as |x|: the same for physical */
+/* integrals, and a valid CPF for model integrals where (ii|kk) may be < 0.  */
+/*                                                                             */
+/* CPF inversion: xi = u * F_last with u uniform in [0, 1); the chosen index   */
+/* is the first k with F_k > xi, i.e. F_{k-1} <= xi < F_k (Reading: the       */
+/* half-open form never selects a zero weight).  If rounding leaves no such  */
+/* k, the last index of positive weight is taken.  A CPF whose last value is  */
+/* zero makes the draw null.  F is summed in the order of the candidates     */
+/* (ascending orbitals, alpha before beta).                                   */
+/* Random lanes: block SPAWN [0] single/double, [1] first electron, [2]       */
+/* second electron (doubles) or the hole (singles), [3] acceptance; block     */
+/* SPAWN2 [0] first hole, [1] second hole.                                    */
+/* ------------------------------------------------------------------------- */
+
+static double sqrt_abs(double x) { return sqrt(fabs(x)); }
+
+/* Index into w[0..m) by CPF inversion with uniform u; -1 if all weights are 0. */
+static int cpf_invert(const double *w, int m, double u, double *total)
+{
+    double sum = 0.0;
+    for (int k = 0; k < m; ++k) sum = sum + w[k];
+    *total = sum;
+    if (sum == 0.0) return -1;
+    double xi = u * sum;
+    double F = 0.0;
+    int last = -1;
+    for (int k = 0; k < m; ++k) {
+        F = F + w[k];
+        if (w[k] > 0.0) last = k;
+        if (F > xi) return k;
+    }
+    return last;
+}
+
+static double sum_of(const double *w, int m)
+{
+    double s = 0.0;
+    for (int k = 0; k < m; ++k) s = s + w[k];
+    return s;
+}
+
+/* Electron-pair CPF weights of electron x over the occupied list occ[0..n). */
+static void pair_weights(const orc_sys *s, const int *occ, int n, int x, double p_opp, double *w)
+{
+    double q_same = 1.0 - p_opp;
+    int px = so_orb(s, occ[x]);
+    for (int k = 0; k < n; ++k) {
+        if (k == x) { w[k] = 0.0; continue; }
+        int pk = so_orb(s, occ[k]);
+        double bias = so_spin(s, occ[k]) != so_spin(s, occ[x]) ? p_opp : q_same;
+        w[k] = fabs(eri(s, px, px, pk, pk)) * bias;
+    }
+}
+
+int orc_cs_gen(const orc_sys *s, det_t d, const uint64_t r1[4], const uint64_t r2[4],
+               double p_single, double p_opp, int exact, det_t *tgt, double *pgen)
+{
+    int occ[128], hol[64];
+    double w[128], w2[128], wr[128];
+    int n = det_occ_list(s, d, occ);
+    if (unif(r1[0]) < p_single) {
+        int e = (int)pick(r1[1], (uint64_t)n);
+        int i = occ[e];
+        int h = holes_of_spin(s, d, so_spin(s, i), hol);
+        for (int x = 0; x < h; ++x) w[x] = fabs(hsingle(s, d, i, hol[x]));
+        double tot;
+        int x = cpf_invert(w, h, unif(r1[2]), &tot);
+        if (x < 0) return 0;
+        det_t t = d; det_set(s, &t, i, 0); det_set(s, &t, hol[x], 1);
+        *tgt = t;
+        double pi = p_single / (double)n;
+        double pa = w[x] / tot;
+        *pgen = pi * pa;
+        return 1;
+    }
+    if (n < 2) return 0;
+    double pd = 1.0 - p_single;
+    /* electron pair */
+    int e1 = (int)pick(r1[1], (uint64_t)n);
+    pair_weights(s, occ, n, e1, p_opp, w);
+    double S1;
+    int e2 = cpf_invert(w, n, unif(r1[2]), &S1);
+    if (e2 < 0) return 0;
+    pair_weights(s, occ, n, e2, p_opp, w2);
+    double S2 = sum_of(w2, n);
+    double pij = (w[e2] / S1 + w2[e1] / S2) / (double)n;
+    int i = occ[e1], j = occ[e2];
+    if (i > j) { int tmp = i; i = j; j = tmp; }  /* canonical order */
+    int pi_ = so_orb(s, i), pj_ = so_orb(s, j);
+    det_t t = d;
+    if (so_spin(s, i) != so_spin(s, j)) {
+        /* i alpha (pi_), j beta (pj_): first hole beta, from electron j */
+        int hb[64], ha[64];
+        int nhb = holes_of_spin(s, d, 1, hb);
+        int nha = holes_of_spin(s, d, 0, ha);
+        for (int x = 0; x < nhb; ++x) w[x] = sqrt_abs(eri(s, pj_, so_orb(s, hb[x]), so_orb(s, hb[x]), pj_));
+        double SA;
+        int xa = cpf_invert(w, nhb, unif(r2[0]), &SA);
+        if (xa < 0) return 0;
+        int A = so_orb(s, hb[xa]);
+        for (int x = 0; x < nha; ++x) {
+            int B = so_orb(s, ha[x]);
+            if (exact) w2[x] = sqrt_abs(eri(s, pj_, A, pi_, B));
+            else w2[x] = sqrt_abs(eri(s, pi_, B, B, pi_));
+        }
+        double SB;
+        int xb = cpf_invert(w2, nha, unif(r2[1]), &SB);
+        if (xb < 0) return 0;
+        double p1 = pd * pij;
+        double p2 = p1 * (w[xa] / SA);
+        *pgen = p2 * (w2[xb] / SB);
+        det_set(s, &t, i, 0); det_set(s, &t, j, 0);
+        det_set(s, &t, ha[xb], 1); det_set(s, &t, hb[xa], 1);
+        *tgt = t;
+        return 1;
+    }
+    int sig = so_spin(s, i);
+    int h = holes_of_spin(s, d, sig, hol);
+    for (int x = 0; x < h; ++x) {
+        int P = so_orb(s, hol[x]);
+        double ci = sqrt_abs(eri(s, pi_, P, P, pi_));
+        double cj = sqrt_abs(eri(s, pj_, P, P, pj_));
+        w[x] = ci + cj;
+    }
+    double SA;
+    int xa = cpf_invert(w, h, unif(r2[0]), &SA);
+    if (xa < 0) return 0;
+    int A = so_orb(s, hol[xa]);
+    for (int x = 0; x < h; ++x) {
+        int P = so_orb(s, hol[x]);
+        if (x == xa) { w2[x] = 0.0; continue; }
+        if (exact) {
+            double dir = eri(s, pi_, A, pj_, P);
+            double exc = eri(s, pi_, P, pj_, A);
+            w2[x] = sqrt_abs(dir - exc);
+        } else {
+            w2[x] = w[x];
+        }
+    }
+    double SB;
+    int xb = cpf_invert(w2, h, unif(r2[1]), &SB);
+    if (xb < 0) return 0;
+    /* the reverse order: b first, then a */
+    int Bo = so_orb(s, hol[xb]);
+    for (int x = 0; x < h; ++x) {
+        int P = so_orb(s, hol[x]);
+        if (x == xb) { wr[x] = 0.0; continue; }
+        if (exact) {
+            double dir = eri(s, pi_, Bo, pj_, P);
+            double exc = eri(s, pi_, P, pj_, Bo);
+            wr[x] = sqrt_abs(dir - exc);
+        } else {
+            wr[x] = w[x];
+        }
+    }
+    double SR = sum_of(wr, h);
+    double pab = (w[xa] / SA) * (w2[xb] / SB);
+    double pba = (w[xb] / SA) * (wr[xa] / SR);
+    double p1 = pd * pij;
+    *pgen = p1 * (pab + pba);
+    det_set(s, &t, i, 0); det_set(s, &t, j, 0);
+    det_set(s, &t, hol[xa], 1); det_set(s, &t, hol[xb], 1);
+    *tgt = t;
+    return 1;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Flat entry points for the Python wrapper (dets as alpha/beta mask pairs).  */
 /* ------------------------------------------------------------------------- */
 double orc_hdiag(const orc_sys *s, uint64_t a, uint64_t b)
@@ -1131,7 +1328,10 @@ int orc_generate(const orc_run *r, uint64_t a, uint64_t b, int64_t t, uint64_t k
     else {
         uint64_t r2[4];
         draw(r, d, t, k, PURPOSE_SPAWN2, r2);
-        ok = orc_pchb_gen(r->s, d, rr, r2, r->p.p_single, r->p.p_opp, &tgt, pgen);
+        if (r->p.gen == GEN_PCHB)
+            ok = orc_pchb_gen(r->s, d, rr, r2, r->p.p_single, r->p.p_opp, &tgt, pgen);
+        else
+            ok = orc_cs_gen(r->s, d, rr, r2, r->p.p_single, r->p.p_opp, r->p.gen == GEN_PE, &tgt, pgen);
     }
     if (!ok) return 0;
     *ta = tgt.a; *tb = tgt.b;

@@ -199,15 +199,19 @@ def _chi2_pvalue(obs, exp):
     return chi2.sf(stat, len(obs) - 1)
 
 
-@pytest.mark.parametrize("gen", ["uniform", "lattice", "pchb"])
+def _gen_code(oracle_mod, gen):
+    return {"uniform": oracle_mod.GEN_UNIFORM, "lattice": oracle_mod.GEN_LATTICE,
+            "pchb": oracle_mod.GEN_PCHB, "cs": oracle_mod.GEN_CS, "pe": oracle_mod.GEN_PE}[gen]
+
+
+@pytest.mark.parametrize("gen", ["uniform", "lattice", "pchb", "cs", "pe"])
 def test_generator_frequencies(oracle_mod, gen):
     """Draw frequencies from the Philox stream match the reported p_gen (chi^2)."""
     if gen == "lattice":
         s = inputs.hubbard(3, 2, 1.0, 4.0, 3, 2)
-        g = oracle_mod.GEN_LATTICE
     else:
         s = inputs.synthetic_molecule(6, 3, 2, seed=8)
-        g = oracle_mod.GEN_UNIFORM if gen == "uniform" else oracle_mod.GEN_PCHB
+    g = _gen_code(oracle_mod, gen)
     osys = oracle_mod.System.from_inputs(s)
     run = oracle_mod.Run(osys, gen=g, seed=3)
     det = brute.basis(s.n_orb, s.n_alpha, s.n_beta)[5]
@@ -289,6 +293,109 @@ def test_pchb_pgen_exhaustive(oracle_mod):
         assert t in pg, "connected determinant never generated"
 
 
+def _draw_all(run, det, M, t=3):
+    """Distinct targets of M draws: {(a, b): (count, p_gen, H)} and the null count."""
+    out, null = {}, 0
+    for k in range(M):
+        r = run.generate(det[0], det[1], t, k)
+        if r is None:
+            null += 1
+            continue
+        c = out.get(r[:2])
+        if c is not None:
+            assert c[1] == r[2] and c[2] == r[3]
+        out[r[:2]] = ((c[0] if c else 0) + 1, r[2], r[3])
+    return out, null
+
+
+def _bits(x):
+    return [p for p in range(64) if (x >> p) & 1]
+
+
+@pytest.mark.parametrize("gen", ["cs", "pe"])
+def test_cs_pe_normalisation_and_coverage(oracle_mod, gen):
+    """Cauchy-Schwarz / Part-Exact generators (Appendix A.2): every single and
+    double of the determinant is reachable (p_gen > 0, so the spawn is
+    unbiased), no draw is null on a dense Hamiltonian, and the reported p_gen
+    of the distinct targets sum to one, which fails if a hole order of the
+    equal-spin doubles or an electron-pair term were dropped."""
+    s = inputs.synthetic_molecule(6, 3, 2, seed=12)
+    osys = oracle_mod.System.from_inputs(s)
+    run = oracle_mod.Run(osys, gen=_gen_code(oracle_mod, gen))
+    dets = brute.basis(6, 3, 2)
+    for idx in (17, 40):
+        det = dets[idx]
+        conn = _connected(osys, det, dets)
+        got, null = _draw_all(run, det, 120000)
+        assert null == 0
+        assert set(got) == set(conn)
+        total = sum(v[1] for v in got.values())
+        assert abs(total - 1.0) <= 1e-12
+
+
+@pytest.mark.parametrize("gen", ["cs", "pe"])
+def test_cs_pe_weights_follow_integrals(oracle_mod, gen):
+    """The conditional probabilities are the ones of Appendix A.2, checked
+    against integrals unpacked with numpy and H from the Slater-Condon rules:
+    singles p(a|i) proportional to |H|; opposite-spin doubles: the beta hole a
+    proportional to sqrt((ia|ia)) and, given a, the alpha hole b to
+    sqrt(|H|) (Part-Exact) or sqrt((jb|jb)) (Cauchy-Schwarz); for every
+    electron pair the targets sum to p_double p(ij) with
+    p(ij) = (w_ij/S_i + w_ji/S_j)/n, w = |(ii|jj)| x (p_opp or 1 - p_opp)."""
+    s = inputs.synthetic_molecule(6, 3, 3, seed=5)
+    N = 6
+    eri4 = inputs.unpack_eri(s.eri, N)
+    osys = oracle_mod.System.from_inputs(s)
+    run = oracle_mod.Run(osys, gen=_gen_code(oracle_mod, gen))
+    ps, po = run.p_single, run.params["p_opp"]
+    det = brute.basis(6, 3, 3)[33]
+    got, _ = _draw_all(run, det, 150000)
+    occ = [(0, p) for p in _bits(det[0])] + [(1, p) for p in _bits(det[1])]
+    n = len(occ)
+
+    def removed(t):
+        return ([(0, p) for p in _bits(det[0] & ~t[0])] + [(1, p) for p in _bits(det[1] & ~t[1])],
+                [(0, p) for p in _bits(t[0] & ~det[0])] + [(1, p) for p in _bits(t[1] & ~det[1])])
+
+    def same_ratio(vals):
+        vals = np.asarray(vals)
+        return np.max(np.abs(vals / vals[0] - 1.0)) <= 1e-12
+
+    singles, opp, pairs = {}, {}, {}
+    for t, (cnt, pg, H) in got.items():
+        el, ho = removed(t)
+        if len(el) == 1:
+            singles.setdefault(el[0], []).append(pg / abs(H))
+            continue
+        pairs.setdefault(tuple(el), []).append(pg)
+        if el[0][0] != el[1][0]:
+            (_, i_a), (_, j_b) = el          # alpha electron, beta electron
+            (_, b_a), (_, a_b) = ho          # alpha hole, beta hole
+            opp.setdefault((i_a, j_b), {}).setdefault(a_b, {})[b_a] = (pg, H)
+    for vals in singles.values():
+        assert same_ratio(vals)
+    # opposite spins: first hole from the beta electron j, second from alpha i
+    for (i_a, j_b), by_a in opp.items():
+        marg = []
+        for a_b, by_b in by_a.items():
+            if gen == "pe":
+                assert same_ratio([pg / np.sqrt(abs(H)) for pg, H in by_b.values()])
+            else:
+                assert same_ratio([pg / np.sqrt(eri4[i_a, b, b, i_a]) for b, (pg, _) in by_b.items()])
+            marg.append(sum(pg for pg, _ in by_b.values()) / np.sqrt(eri4[j_b, a_b, a_b, j_b]))
+        assert same_ratio(marg)
+
+    def weight(x, y):
+        bias = po if x[0] != y[0] else 1.0 - po
+        return abs(eri4[x[1], x[1], y[1], y[1]]) * bias
+
+    for (x, y), pgs in pairs.items():
+        sx = sum(weight(x, k) for k in occ if k != x)
+        sy = sum(weight(y, k) for k in occ if k != y)
+        pij = (weight(x, y) / sx + weight(y, x) / sy) / n
+        assert abs(sum(pgs) - (1.0 - ps) * pij) <= 1e-12 * pij
+
+
 # --- the whole step ------------------------------------------------------------------
 
 def _dense_projector(osys, dets, h00, tau, shift, masked_from=None):
@@ -300,8 +407,10 @@ def _dense_projector(osys, dets, h00, tau, shift, masked_from=None):
     return P
 
 
-@pytest.mark.parametrize("mode,na", [("integer", -1.0), ("real", -1.0), ("integer", 3.0)])
-def test_one_step_expectation(oracle_mod, mode, na):
+@pytest.mark.parametrize("mode,na,gen", [("integer", -1.0, "uniform"), ("real", -1.0, "uniform"),
+                                         ("integer", 3.0, "uniform"), ("integer", -1.0, "pe"),
+                                         ("real", -1.0, "cs")])
+def test_one_step_expectation(oracle_mod, mode, na, gen):
     """Averaged over independent streams, one step from a fixed population
     equals the dense projector (1 - dtau (H - S)) C of Eq. (projector), with
     the initiator-masked H when the approximation is on (Sec. II)."""
@@ -317,7 +426,7 @@ def test_one_step_expectation(oracle_mod, mode, na):
         C0[pick] = C0[pick] * 0.7
     tau, S = 0.05, -0.3
     params = dict(tau=tau, target=1e12, n_a=na, mode=oracle_mod.MODE_INTEGER if mode == "integer"
-                  else oracle_mod.MODE_REAL)
+                  else oracle_mod.MODE_REAL, gen=_gen_code(oracle_mod, gen))
     ref = dets[int(pick[0])]
     H = brute.oracle_dense_h(osys, dets)
     h00 = osys.hdiag(*ref)
