@@ -47,6 +47,14 @@ extern "C" {
 #define FCIQMC_GEN_UNIFORM 0  /* uniform singles and doubles (Appendix A.1)   */
 #define FCIQMC_GEN_LATTICE 1  /* real-space lattice hopping (Sec. II)         */
 #define FCIQMC_GEN_PCHB 2     /* pre-computed heat-bath doubles (App. A.3)    */
+/* On-the-fly generators of Appendix A.2 (no tables beyond N x N):
+ * weighted singles (hole drawn with weight |H|), electron pair from a uniform
+ * first electron and a CPF over |(ii|kk)| biased by p_opp, holes from CPFs
+ * over sqrt((ia|ia)) and, for the second hole, either the Cauchy-Schwarz
+ * bound (CS) or the exact sqrt(|<ij||ab>|) (Part-Exact).  O(nN) work per
+ * draw. */
+#define FCIQMC_GEN_CS 3       /* Cauchy-Schwarz (App. A.2)                    */
+#define FCIQMC_GEN_PE 4       /* Part-Exact refinement of CS (App. A.2)       */
 
 typedef struct fciqmc_system fciqmc_system;
 typedef struct fciqmc_run fciqmc_run;
@@ -64,7 +72,9 @@ typedef struct fciqmc_params {
     double c_min;           /* real mode: compression threshold C_min (Sec. I)           */
     int excitgen;           /* FCIQMC_GEN_*                                               */
     double p_single;        /* probability of a single excitation; < 0: nN/(nN + n^2N^2)  */
-    double p_opp;           /* PCHB: prob. of an opposite-spin pair; < 0: n_a n_b/C(n,2)  */
+    double p_opp;           /* PCHB: prob. of an opposite-spin pair; CS/PE: weight factor */
+                            /* of opposite-spin pairs (1 - p_opp for equal spins);       */
+                            /* < 0: n_a n_b/C(n,2)                                       */
     uint64_t seed;          /* Philox key word 0                                          */
     uint64_t replica_id;    /* Philox key word 1                                          */
     double shift_damping;   /* zeta of the shift update                                   */

@@ -174,6 +174,7 @@ struct SysView {
     const int* deg;       // lattice degree
     const int* nbr;       // N*N ascending neighbour lists
     // pre-computed heat-bath tables (see the PCHB generator)
+    const double* SK;     // SK[p*N+q] = sqrt(|(pq|qp)|), the Cauchy-Schwarz hole weights
     const HbEntry* hb_opp;   // rows (I alpha, J beta), N^2 columns each
     const HbEntry* hb_same;  // rows I < J, N(N-1)/2 columns each
     const double* hb_sum_opp;   // row sums of the weights
@@ -452,6 +453,162 @@ __device__ __forceinline__ bool gen_pchb(const SysView& s, uint64_t a, uint64_t 
     const uint64_t m = (occ & ~(1ULL << I) & ~(1ULL << J)) | (1ULL << A) | (1ULL << Bo);
     out.ta = sg ? a : m;
     out.tb = sg ? m : b;
+    return true;
+}
+
+// On-the-fly Cauchy-Schwarz (EXACT = false) and Part-Exact (EXACT = true)
+// generators (Appendix A.2).  Each draw builds its cumulative probability
+// functions (CPFs) from N x N tables and the packed integrals:
+//  * singles: electron uniform, hole of its spin with weight |H|;
+//  * electron pair: first uniform, second from the CPF of |(ii|kk)| times
+//    p_opp (opposite spins) or 1 - p_opp; p(ij) = (w_ij/S_i + w_ji/S_j)/n;
+//  * opposite spins: beta hole A with weight sqrt((jA|jA)) of the beta
+//    electron j, then alpha hole B with sqrt(|(jA|iB)|) (PE) or sqrt((iB|iB))
+//    (CS);
+//  * equal spins: hole A with sqrt((iA|iA)) + sqrt((jA|jA)), then hole B != A
+//    with sqrt(|(iA|jB) - (iB|jA)|) (PE) or the first weight (CS); p_gen sums
+//    the two hole orders.
+// A CPF is inverted at xi = u F_last: the first candidate with F > xi, or the
+// last positive weight when rounding leaves none; a zero total is a null
+// draw.  Candidates run in canonical order (alpha, then beta; ascending), and
+// both passes over a CPF repeat the same additions, so the result is the same
+// sequence of binary64 operations as a serial sum.
+// Random lanes: r 0 single/double, 1 first electron, 2 second electron (the
+// hole for singles), 3 acceptance; r2 0 first hole, 1 second hole.
+
+// Candidate sets m0 (alpha) and m1 (beta); wt(spin, orbital) >= 0.
+template <class Wt> __device__ __forceinline__ double cpf_total(uint64_t m0, uint64_t m1, Wt wt) {
+    double sum = 0.0;
+    for (uint64_t x = m0; x; x &= x - 1) sum = sum + wt(0, ctz64(x));
+    for (uint64_t x = m1; x; x &= x - 1) sum = sum + wt(1, ctz64(x));
+    return sum;
+}
+
+// Returns spin << 6 | orbital of the chosen candidate (-1 if the total is
+// zero), its weight in wsel and the total in total.
+template <class Wt>
+__device__ __forceinline__ int cpf_pick(uint64_t m0, uint64_t m1, Wt wt, double u, double& total,
+                                        double& wsel) {
+    const double sum = cpf_total(m0, m1, wt);
+    total = sum;
+    if (sum == 0.0) return -1;
+    const double xi = u * sum;
+    double acc = 0.0, wl = 0.0;
+    int last = -1;
+    for (int sp = 0; sp < 2; ++sp) {
+        for (uint64_t x = sp ? m1 : m0; x; x &= x - 1) {
+            const int p = ctz64(x);
+            const double w = wt(sp, p);
+            acc = acc + w;
+            if (w > 0.0) { last = (sp << 6) | p; wl = w; }
+            if (acc > xi) { wsel = w; return (sp << 6) | p; }
+        }
+    }
+    wsel = wl;
+    return last;
+}
+
+template <bool EXACT>
+__device__ __forceinline__ bool gen_cs(const SysView& s, uint64_t a, uint64_t b, const R4& r, const R4& r2,
+                                       double p_single, double p_double, double p_opp, Exc& out) {
+    const int N = s.N, na = s.na, n = s.n;
+    const uint64_t full = (N >= 64) ? ~0ULL : low_mask(N);
+    if (unif(r.x[0]) < p_single) {
+        const int e = (int)pick(r.x[1], (uint64_t)n);
+        const int sg = e < na ? 0 : 1;
+        const uint64_t occ = sg ? b : a;
+        const int pi = select64(occ, sg ? e - na : e);
+        double tot, wsel;
+        const int c = cpf_pick(~occ & full, 0ULL,
+                               [&](int, int h) { return fabs(h_single(s, a, b, sg, pi, h)); },
+                               unif(r.x[2]), tot, wsel);
+        if (c < 0) return false;
+        const int pa = c & 63;
+        const double p1 = p_single / (double)n;
+        out.pgen = p1 * (wsel / tot);
+        out.H = h_single(s, a, b, sg, pi, pa);
+        uint64_t A = a, B = b;
+        clear_so(A, B, sg, pi); set_so(A, B, sg, pa);
+        out.ta = A; out.tb = B;
+        return true;
+    }
+    if (n < 2) return false;
+    const double q_same = 1.0 - p_opp;
+    const double* J = s.J;
+    const double* SK = s.SK;
+    // electron pair
+    const int e1 = (int)pick(r.x[1], (uint64_t)n);
+    const int s1 = e1 < na ? 0 : 1;
+    const int p1 = select64(s1 ? b : a, s1 ? e1 - na : e1);
+    double S1, w12;
+    const int c2 = cpf_pick(s1 ? a : a & ~(1ULL << p1), s1 ? b & ~(1ULL << p1) : b,
+                            [&](int sk, int pk) { return fabs(J[p1 * N + pk]) * (sk != s1 ? p_opp : q_same); },
+                            unif(r.x[2]), S1, w12);
+    if (c2 < 0) return false;
+    const int s2 = c2 >> 6, p2 = c2 & 63;
+    const double S2 = cpf_total(s2 ? a : a & ~(1ULL << p2), s2 ? b & ~(1ULL << p2) : b,
+                                [&](int sk, int pk) { return fabs(J[p2 * N + pk]) * (sk != s2 ? p_opp : q_same); });
+    const double w21 = fabs(J[p2 * N + p1]) * (s1 != s2 ? p_opp : q_same);
+    const double pij = (w12 / S1 + w21 / S2) / (double)n;
+    const double pp = p_double * pij;
+    if (s1 != s2) {
+        const int pa_e = s1 ? p2 : p1;  // alpha electron
+        const int pb_e = s1 ? p1 : p2;  // beta electron
+        double SA, wA;
+        const int cA = cpf_pick(~b & full, 0ULL, [&](int, int h) { return SK[pb_e * N + h]; }, unif(r2.x[0]),
+                                SA, wA);
+        if (cA < 0) return false;
+        const int A = cA & 63;  // beta hole
+        double SB, wB;
+        const int cB = cpf_pick(~a & full, 0ULL,
+                                [&](int, int h) {
+                                    if constexpr (EXACT) return sqrt(fabs(eri(s, pb_e, A, pa_e, h)));
+                                    else return SK[pa_e * N + h];
+                                },
+                                unif(r2.x[1]), SB, wB);
+        if (cB < 0) return false;
+        const int B = cB & 63;  // alpha hole
+        const double q = pp * (wA / SA);
+        out.pgen = q * (wB / SB);
+        out.H = h_double(s, a, b, 0, pa_e, 1, pb_e, 0, B, 1, A);
+        out.ta = (a & ~(1ULL << pa_e)) | (1ULL << B);
+        out.tb = (b & ~(1ULL << pb_e)) | (1ULL << A);
+        return true;
+    }
+    const int pi = p1 < p2 ? p1 : p2, pj = p1 < p2 ? p2 : p1;
+    const uint64_t occ = s1 ? b : a;
+    const uint64_t hm = ~occ & full;
+    auto w_first = [&](int, int h) { return SK[pi * N + h] + SK[pj * N + h]; };
+    double SA, wA;
+    const int cA = cpf_pick(hm, 0ULL, w_first, unif(r2.x[0]), SA, wA);
+    if (cA < 0) return false;
+    const int A = cA & 63;
+    // second-hole weight given first hole f
+    auto w_second = [&](int f, int h) {
+        if constexpr (EXACT) {
+            const double dir = eri(s, pi, f, pj, h);
+            const double exc = eri(s, pi, h, pj, f);
+            return sqrt(fabs(dir - exc));
+        } else {
+            return SK[pi * N + h] + SK[pj * N + h];
+        }
+    };
+    double SB, wB;
+    const int cB = cpf_pick(hm & ~(1ULL << A), 0ULL, [&](int, int h) { return w_second(A, h); }, unif(r2.x[1]),
+                            SB, wB);
+    if (cB < 0) return false;
+    const int B = cB & 63;
+    const double SR = cpf_total(hm & ~(1ULL << B), 0ULL, [&](int, int h) { return w_second(B, h); });
+    const double wAr = w_second(B, A);
+    const double wBf = w_first(0, B);
+    const double pab = (wA / SA) * (wB / SB);
+    const double pba = (wBf / SA) * (wAr / SR);
+    out.pgen = pp * (pab + pba);
+    const int lo = A < B ? A : B, hi = A < B ? B : A;
+    out.H = h_double(s, a, b, s1, pi, s1, pj, s1, lo, s1, hi);
+    const uint64_t m = (occ & ~(1ULL << pi) & ~(1ULL << pj)) | (1ULL << A) | (1ULL << B);
+    out.ta = s1 ? a : m;
+    out.tb = s1 ? m : b;
     return true;
 }
 

@@ -109,6 +109,8 @@ template <class T> int dalloc(Arena& a, T** p, size_t count) {
     return a.alloc(reinterpret_cast<void**>(p), count * sizeof(T));
 }
 
+constexpr int kGens = 5;  // FCIQMC_GEN_UNIFORM .. FCIQMC_GEN_PE
+
 uint64_t next_pow2(uint64_t x) {
     uint64_t p = 1;
     while (p < x) p <<= 1;
@@ -125,7 +127,8 @@ struct fciqmc_system {
     double e_core = 0.0;
     bool onsite = false;
     Arena arena;
-    double *h1 = nullptr, *eri = nullptr, *J = nullptr, *K = nullptr, *X = nullptr, *U = nullptr, *Hd = nullptr;
+    double *h1 = nullptr, *eri = nullptr, *J = nullptr, *K = nullptr, *X = nullptr, *U = nullptr, *Hd = nullptr,
+           *SK = nullptr;
     int *deg = nullptr, *nbr = nullptr, *pair_of = nullptr;
     bool pchb = false;
     HbEntry *hb_opp = nullptr, *hb_same = nullptr;  // packed alias tables
@@ -136,7 +139,7 @@ struct fciqmc_system {
         SysView v{};
         v.N = N; v.na = na; v.nb = nb; v.n = na + nb;
         v.onsite = onsite ? 1 : 0;
-        v.h1 = h1; v.eri = eri; v.J = J; v.K = K; v.X = X; v.U = U; v.Hd = Hd;
+        v.h1 = h1; v.eri = eri; v.J = J; v.K = K; v.X = X; v.U = U; v.Hd = Hd; v.SK = SK;
         v.deg = deg; v.nbr = nbr;
         v.hb_opp = hb_opp;
         v.hb_same = hb_same;
@@ -613,8 +616,16 @@ template <int W, class V> struct Engine : EngineBase {
                 hipLaunchKernelGGL((k_spawn<W, V, 1>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
                                    soff, scount, ctl, cmap, cap_cmap);
                 break;
-            default:
+            case FCIQMC_GEN_PCHB:
                 hipLaunchKernelGGL((k_spawn<W, V, 2>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
+                                   soff, scount, ctl, cmap, cap_cmap);
+                break;
+            case FCIQMC_GEN_CS:
+                hipLaunchKernelGGL((k_spawn<W, V, 3>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
+                                   soff, scount, ctl, cmap, cap_cmap);
+                break;
+            default:
+                hipLaunchKernelGGL((k_spawn<W, V, 4>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
                                    soff, scount, ctl, cmap, cap_cmap);
                 break;
         }
@@ -878,12 +889,12 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
     using E = Engine<W, V>;
     Arena arena;
     size_t cap = 0;             // instances the buffers hold
-    char* hbuf = nullptr;       // pinned: Inst[cap], bucket prefix [cap+1], chunk prefixes [cap+3],
+    char* hbuf = nullptr;       // pinned: Inst[cap], bucket prefix [cap+1], chunk prefixes [cap+kGens],
                                 // diagonal work-item prefix [cap+1]
     char* dbuf = nullptr;       // device copy of hbuf
     Ctl* hctl = nullptr;        // pinned, written by the post kernel, one per instance
-    int g0[4] = {0, 0, 0, 0};   // first instance of each generator, g0[3] = n
-    int64_t ctot[3] = {0, 0, 0};
+    int g0[kGens + 1] = {};     // first instance of each generator, g0[kGens] = n
+    int64_t ctot[kGens] = {};
     int64_t btot = 0;
     int64_t ftot = 0;           // work items of the new-diagonal kernel
     size_t flds = 0;            // its LDS bytes (largest molecular member)
@@ -894,10 +905,10 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
         arena.clear();
     }
     E* eng(size_t i) const { return static_cast<E*>(runs[i]->eng.get()); }
-    static size_t bytes_for(size_t n) { return sizeof(Inst<W, V>) * n + sizeof(int64_t) * (3 * n + 5); }
+    static size_t bytes_for(size_t n) { return sizeof(Inst<W, V>) * n + sizeof(int64_t) * (3 * n + kGens + 2); }
     int64_t* bfirst(char* base) const { return reinterpret_cast<int64_t*>(base + sizeof(Inst<W, V>) * cap); }
     int64_t* cfirst(char* base) const { return bfirst(base) + cap + 1; }
-    int64_t* ffirst(char* base) const { return cfirst(base) + cap + 3; }
+    int64_t* ffirst(char* base) const { return cfirst(base) + cap + kGens; }
 
     int reserve(size_t n) {
         if (n <= cap) return 0;
@@ -941,12 +952,12 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
         ff[n] = ftot;
         // generator ranges; range g keeps its chunk prefix in cf[g0[g] + g .. g0[g+1] + g]
         int k = 0;
-        for (int g = 0; g < 3; ++g) {
+        for (int g = 0; g < kGens; ++g) {
             g0[g] = k;
             while (k < (int)n && runs[k]->p.excitgen == g) ++k;
         }
-        g0[3] = (int)n;
-        for (int g = 0; g < 3; ++g) {
+        g0[kGens] = (int)n;
+        for (int g = 0; g < kGens; ++g) {
             int64_t c = 0;
             for (int i = g0[g]; i < g0[g + 1]; ++i) {
                 cf[i + g] = c;
@@ -962,16 +973,22 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
         if (runs.empty()) return 0;
         const Inst<W, V>* di = reinterpret_cast<const Inst<W, V>*>(dbuf);
         const int64_t* cf = cfirst(dbuf);
-        for (int g = 0; g < 3; ++g) {
+        for (int g = 0; g < kGens; ++g) {
             if (ctot[g] == 0) continue;
             const unsigned gs = (unsigned)(grid > 0 ? std::min<int64_t>(ctot[g], grid) : ctot[g]);
             const int k = g0[g + 1] - g0[g];
+            const Inst<W, V>* ig = di + g0[g];
+            const int64_t* fg = cf + g0[g] + g;
             if (g == FCIQMC_GEN_UNIFORM)
-                hipLaunchKernelGGL((k_spawn_batch<W, V, 0>), dim3(gs), dim3(kThreads), 0, s, di + g0[g], cf + g0[g] + g, k);
+                hipLaunchKernelGGL((k_spawn_batch<W, V, 0>), dim3(gs), dim3(kThreads), 0, s, ig, fg, k);
             else if (g == FCIQMC_GEN_LATTICE)
-                hipLaunchKernelGGL((k_spawn_batch<W, V, 1>), dim3(gs), dim3(kThreads), 0, s, di + g0[g], cf + g0[g] + g, k);
+                hipLaunchKernelGGL((k_spawn_batch<W, V, 1>), dim3(gs), dim3(kThreads), 0, s, ig, fg, k);
+            else if (g == FCIQMC_GEN_PCHB)
+                hipLaunchKernelGGL((k_spawn_batch<W, V, 2>), dim3(gs), dim3(kThreads), 0, s, ig, fg, k);
+            else if (g == FCIQMC_GEN_CS)
+                hipLaunchKernelGGL((k_spawn_batch<W, V, 3>), dim3(gs), dim3(kThreads), 0, s, ig, fg, k);
             else
-                hipLaunchKernelGGL((k_spawn_batch<W, V, 2>), dim3(gs), dim3(kThreads), 0, s, di + g0[g], cf + g0[g] + g, k);
+                hipLaunchKernelGGL((k_spawn_batch<W, V, 4>), dim3(gs), dim3(kThreads), 0, s, ig, fg, k);
         }
         HIP_OK(hipGetLastError());
         return 0;
@@ -1160,6 +1177,7 @@ int fciqmc_load_integrals(int n_orb, int n_alpha, int n_beta, double e_core, con
     CHECK(dalloc(s->arena, &s->J, (size_t)N * N));
     CHECK(dalloc(s->arena, &s->K, (size_t)N * N));
     CHECK(dalloc(s->arena, &s->X, (size_t)N * N));
+    CHECK(dalloc(s->arena, &s->SK, (size_t)N * N));
     CHECK(dalloc(s->arena, &s->Hd, (size_t)N));
     CHECK(dalloc(s->arena, &s->U, (size_t)N));
     CHECK(dalloc(s->arena, &s->deg, (size_t)N));
@@ -1180,7 +1198,8 @@ int fciqmc_load_integrals(int n_orb, int n_alpha, int n_beta, double e_core, con
         for (int B = A + 1; B < N; ++B, ++c) po[c] = A * 64 + B;
     HIP_OK(hipMemcpy(s->pair_of, po.data(), sizeof(int) * po.size(), hipMemcpyHostToDevice));
     SysView v = s->view();
-    hipLaunchKernelGGL(k_build_jk, dim3((N * N + 255) / 256), dim3(256), 0, 0, v, s->J, s->K, s->X, s->U, s->Hd);
+    hipLaunchKernelGGL(k_build_jk, dim3((N * N + 255) / 256), dim3(256), 0, 0, v, s->J, s->K, s->X, s->U, s->Hd,
+                       s->SK);
     HIP_OK(hipGetLastError());
     HIP_OK(hipDeviceSynchronize());
     *out = s.release();
@@ -1254,7 +1273,7 @@ int fciqmc_init(const fciqmc_system* csys, const fciqmc_params* p, void* stream,
     fciqmc_system* sys = const_cast<fciqmc_system*>(csys);
     if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return fail(FCIQMC_EINVAL, "tau must be positive");
     if (p->mode != FCIQMC_MODE_INTEGER && p->mode != FCIQMC_MODE_REAL) return fail(FCIQMC_EINVAL, "unknown mode");
-    if (p->excitgen < 0 || p->excitgen > 2) return fail(FCIQMC_EINVAL, "unknown excitation generator");
+    if (p->excitgen < 0 || p->excitgen >= kGens) return fail(FCIQMC_EINVAL, "unknown excitation generator");
     if (p->excitgen == FCIQMC_GEN_LATTICE && !sys->onsite)
         return fail(FCIQMC_EINVAL, "the lattice generator needs on-site-only two-electron integrals");
     if (p->mode == FCIQMC_MODE_REAL && !(p->c_min > 0.0)) return fail(FCIQMC_EINVAL, "c_min must be positive");

@@ -146,9 +146,12 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
             bool ok;
             if constexpr (GEN == 0) ok = gen_uniform(sys, da, db, r, sc.p_single, sc.p_double, x);
             else if constexpr (GEN == 1) ok = gen_lattice(sys, da, db, r, x);
-            else {
+            else if constexpr (GEN == 2) {
                 const R4 r2 = draw<W>(key, sc.t, k, kSpawn2, sc.seed, sc.replica);
                 ok = gen_pchb(sys, da, db, r, r2, sc.p_single, sc.p_double, sc.p_opp, x);
+            } else {
+                const R4 r2 = draw<W>(key, sc.t, k, kSpawn2, sc.seed, sc.replica);
+                ok = gen_cs<GEN == 4>(sys, da, db, r, r2, sc.p_single, sc.p_double, sc.p_opp, x);
             }
             if (ok && x.H != 0.0) {
                 const double u = unif(r.x[3]);
@@ -1133,9 +1136,10 @@ __global__ void k_hij(SysView sys, const uint64_t* __restrict__ di, const uint64
     }
 }
 
-// J/K/U tables copied out of the packed integrals, and the same-spin pair
-// term X = J - K of the diagonal (one rounding, as in the diagonal's sum).
-__global__ void k_build_jk(SysView sys, double* J, double* K, double* X, double* U, double* Hd) {
+// J/K/U tables copied out of the packed integrals, the same-spin pair term
+// X = J - K of the diagonal (one rounding, as in the diagonal's sum) and the
+// Cauchy-Schwarz hole weights SK = sqrt(|K|) (correctly rounded square root).
+__global__ void k_build_jk(SysView sys, double* J, double* K, double* X, double* U, double* Hd, double* SK) {
     const int N = sys.N;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N * N; i += gridDim.x * blockDim.x) {
         const int p = i / N, q = i % N;
@@ -1144,6 +1148,7 @@ __global__ void k_build_jk(SysView sys, double* J, double* K, double* X, double*
         J[i] = j;
         K[i] = k;
         X[i] = j - k;
+        SK[i] = sqrt(fabs(k));
         if (p == q) { U[p] = eri(sys, p, p, p, p); Hd[p] = sys.h1[i]; }
     }
 }

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libfciqmc.so")
 
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
 MODE_INTEGER, MODE_REAL = 0, 1
-GEN_UNIFORM, GEN_LATTICE, GEN_PCHB = 0, 1, 2
+GEN_UNIFORM, GEN_LATTICE, GEN_PCHB, GEN_CS, GEN_PE = 0, 1, 2, 3, 4
 
 
 class FciqmcError(RuntimeError):

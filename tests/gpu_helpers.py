@@ -7,7 +7,9 @@ from paper_2006_14956_amd import fciqmc as F
 
 GEN = {"uniform": (F.GEN_UNIFORM, oracle.GEN_UNIFORM),
        "lattice": (F.GEN_LATTICE, oracle.GEN_LATTICE),
-       "pchb": (F.GEN_PCHB, oracle.GEN_PCHB)}
+       "pchb": (F.GEN_PCHB, oracle.GEN_PCHB),
+       "cs": (F.GEN_CS, oracle.GEN_CS),
+       "pe": (F.GEN_PE, oracle.GEN_PE)}
 
 
 def ref_of(s):
