@@ -49,6 +49,19 @@ def workload(name):
                 "initiator_na": 3, "tau": 0.0012, "excitation_generator": "pchb",
                 "walkers": "real", "c_min": 1.0, "det_bits": 128, "shift_damping": 0.3}
         return s, p, desc
+    if name.startswith("mol40-"):
+        # the 40-orbital molecule with another generator and walker target,
+        # e.g. mol40-pe-1e7 (generators: pchb, cs, pe)
+        _, gen, target = name.split("-")
+        s = inputs.molecule_40o26e()
+        g = {"pchb": F.GEN_PCHB, "cs": F.GEN_CS, "pe": F.GEN_PE}[gen]
+        p = dict(tau=0.0012, walker_target=float(target), initiator_na=3.0, mode=F.MODE_REAL,
+                 c_min=1.0, excitgen=g, seed=1, shift_damping=0.3, n_initial=1000.0)
+        desc = {"workload": "synthetic_molecule_26e40o_damped_rank40",
+                "walkers_target": float(target), "initiator_na": 3, "tau": 0.0012,
+                "excitation_generator": gen, "walkers": "real", "c_min": 1.0, "det_bits": 128,
+                "shift_damping": 0.3}
+        return s, p, desc
     if name == "mol8":
         s = inputs.molecule_8o8e()
         p = dict(tau=0.01, walker_target=1e4, seed=1)
@@ -404,6 +417,63 @@ KERNEL_SOURCES = ("paper_2006_14956_amd/csrc/kernels.hpp", "paper_2006_14956_amd
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_hubbard4x4_mol40.md")
 
 
+GEN_DESC = {"workload": "synthetic_molecule_26e40o_damped_rank40_fixed_random_population",
+            "state": "random determinants (seed 5) with real populations of up to 40 walkers, "
+                     "the reference included", "tau": 0.0012, "initiator_na": 3,
+            "walkers": "real", "c_min": 1.0, "det_bits": 128}
+
+
+def measure_generators(F, np, torch, n_dets, reps):
+    """Spawn kernel of the pre-computed heat-bath, Cauchy-Schwarz and
+    Part-Exact generators on one fixed population of the 40-orbital molecule:
+    the same walkers are set before each timed step, so every generator
+    draws from identical parents (event-timed, one sample per step).  The
+    wall time of such a step is not reported: after a population is set, the
+    first spawn of the step sizes its record slabs and is replayed once."""
+    from paper_2006_14956_amd import inputs
+    s = inputs.molecule_40o26e()
+    ra, rb = (1 << s.n_alpha) - 1, (1 << s.n_beta) - 1
+    a, b, v = inputs.random_walker_state(s.n_orb, s.n_alpha, s.n_beta, n_dets, seed=5, max_pop=40,
+                                         include=(ra, rb))
+    nw = float(np.abs(v).sum())
+    sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
+    N = s.n_orb
+    npair = N * (N - 1) // 2
+    table_bytes = {"pchb": 32 * (N ** 4 + npair * npair) + 8 * (N * N + npair),
+                   "cs": 8 * N * N, "pe": 8 * N * N}
+    out = {}
+    for name, g in (("pchb", F.GEN_PCHB), ("cs", F.GEN_CS), ("pe", F.GEN_PE)):
+        p = F.fciqmc_params_default(tau=0.0012, walker_target=1e12, initiator_na=3.0,
+                                    mode=F.MODE_REAL, c_min=1.0, excitgen=g, seed=1,
+                                    max_dets=20 * n_dets, buckets_log2=14)
+        run = F.fciqmc_init(sysd, p)
+        F.fciqmc_profile(run, True)
+        att = 0
+        for rep in range(reps + 1):
+            F.fciqmc_set_walkers(run, a, b, v)
+            F.fciqmc_set_checkpoint(run, 16 * (rep + 1), 0.0, 0, 0, nw)
+            st = F.fciqmc_step(run, 1)
+            att = int(st[0]["attempts"])
+            if rep == 0:  # first step on this run: allocation, left out
+                ms0, n0, _ = F.fciqmc_profile(run, False)
+        ms, nsteps, _ = F.fciqmc_profile(run, False)
+        nsteps -= n0
+        sp = (ms["spawn"] - ms0["spawn"]) / max(nsteps, 1)
+        other = {k: (v - ms0[k]) / max(nsteps, 1) for k, v in ms.items() if k != "spawn"}
+        out[name] = {"attempts_per_step": att, "spawns_per_step": int(st[0]["spawns"]),
+                     "dets_after_step": int(st[0]["ndets"]), "spawn_ms_per_launch": sp,
+                     "other_kernels_ms_per_launch": other,
+                     "spawn_attempts_per_s": att / (sp * 1e-3) if sp > 0 else None,
+                     "generator_table_bytes": table_bytes[name], "sampled_steps": nsteps}
+        log(f"[generators] {name}: {att} attempts, spawn {sp:.3f} ms/launch "
+            f"({out[name]['spawn_attempts_per_s']:.3e} attempts/s), "
+            f"{out[name]['spawns_per_step']} spawns, {out[name]['dets_after_step']} dets, other "
+            + ", ".join(f"{k}={v:.3f}" for k, v in other.items()))
+        F.fciqmc_free_run(run)
+    F.fciqmc_free_system(sysd)
+    return {"config": dict(GEN_DESC, dets=n_dets, walkers=nw), "generators": out}
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -465,6 +535,11 @@ def main():
     ap.add_argument("--served-rate", type=float, default=20.0)
     ap.add_argument("--served-tol", type=float, default=0.01)
     ap.add_argument("--served-budget", type=float, default=200e9)
+    ap.add_argument("--generators", type=int, default=400000, metavar="DETS",
+                    help="determinants of the fixed population on which the excitation "
+                         "generators are compared (0 to skip)")
+    ap.add_argument("--generators-only", action="store_true",
+                    help="only run the generator comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 5 device-to-device copies of BYTES (the known-size copy "
                          "that scales rocprofv3 FETCH_SIZE/WRITE_SIZE readings)")
@@ -490,6 +565,9 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.generators_only:
+        print(json.dumps(measure_generators(F, np, torch, args.generators or 400000, 3)), flush=True)
+        return
     s, pd, desc, run, sysd, st, wall, ms, nsteps, layout, kern, roof = measure(
         F, np, torch, stream, args.workload, args.steps, args.warmup)
     attempts = int(st["attempts"].sum())
@@ -536,6 +614,10 @@ def main():
         F.fciqmc_free_run(run2)
         F.fciqmc_free_system(sys2)
 
+    generators = None
+    if args.generators:
+        generators = measure_generators(F, np, torch, args.generators, 3)
+
     batched = None
     if args.batched_steps:
         batched = measure_batched(F, np, args.batched_steps, args.batched_warmup, args.batched_grow,
@@ -564,6 +646,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "second_workload": second,
+        "generators": generators,
         "batched": batched,
         "served": served,
     }

@@ -462,12 +462,12 @@ __device__ __forceinline__ bool gen_pchb(const SysView& s, uint64_t a, uint64_t 
 //  * singles: electron uniform, hole of its spin with weight |H|;
 //  * electron pair: first uniform, second from the CPF of |(ii|kk)| times
 //    p_opp (opposite spins) or 1 - p_opp; p(ij) = (w_ij/S_i + w_ji/S_j)/n;
-//  * opposite spins: beta hole A with weight sqrt((jA|jA)) of the beta
-//    electron j, then alpha hole B with sqrt(|(jA|iB)|) (PE) or sqrt((iB|iB))
-//    (CS);
-//  * equal spins: hole A with sqrt((iA|iA)) + sqrt((jA|jA)), then hole B != A
-//    with sqrt(|(iA|jB) - (iB|jA)|) (PE) or the first weight (CS); p_gen sums
-//    the two hole orders.
+//  * opposite spins: beta hole A with weight sqrt((xA|xA)) of the beta
+//    electron x, then alpha hole B with sqrt(|(xA|yB)|) (PE) or sqrt((yB|yB))
+//    (CS), y the alpha electron;
+//  * equal spins x < y: hole A with sqrt((xA|xA)) + sqrt((yA|yA)), then hole
+//    B != A with sqrt(|(xA|yB) - (xB|yA)|) (PE) or the first weight (CS);
+//    p_gen sums the two hole orders.
 // A CPF is inverted at xi = u F_last: the first candidate with F > xi, or the
 // last positive weight when rounding leaves none; a zero total is a null
 // draw.  Candidates run in canonical order (alpha, then beta; ascending), and
@@ -551,62 +551,61 @@ __device__ __forceinline__ bool gen_cs(const SysView& s, uint64_t a, uint64_t b,
     const double w21 = fabs(J[p2 * N + p1]) * (s1 != s2 ? p_opp : q_same);
     const double pij = (w12 / S1 + w21 / S2) / (double)n;
     const double pp = p_double * pij;
-    if (s1 != s2) {
-        const int pa_e = s1 ? p2 : p1;  // alpha electron
-        const int pb_e = s1 ? p1 : p2;  // beta electron
-        double SA, wA;
-        const int cA = cpf_pick(~b & full, 0ULL, [&](int, int h) { return SK[pb_e * N + h]; }, unif(r2.x[0]),
-                                SA, wA);
-        if (cA < 0) return false;
-        const int A = cA & 63;  // beta hole
-        double SB, wB;
-        const int cB = cpf_pick(~a & full, 0ULL,
-                                [&](int, int h) {
-                                    if constexpr (EXACT) return sqrt(fabs(eri(s, pb_e, A, pa_e, h)));
-                                    else return SK[pa_e * N + h];
-                                },
-                                unif(r2.x[1]), SB, wB);
-        if (cB < 0) return false;
-        const int B = cB & 63;  // alpha hole
-        const double q = pp * (wA / SA);
-        out.pgen = q * (wB / SB);
-        out.H = h_double(s, a, b, 0, pa_e, 1, pb_e, 0, B, 1, A);
-        out.ta = (a & ~(1ULL << pa_e)) | (1ULL << B);
-        out.tb = (b & ~(1ULL << pb_e)) | (1ULL << A);
-        return true;
-    }
-    const int pi = p1 < p2 ? p1 : p2, pj = p1 < p2 ? p2 : p1;
-    const uint64_t occ = s1 ? b : a;
-    const uint64_t hm = ~occ & full;
-    auto w_first = [&](int, int h) { return SK[pi * N + h] + SK[pj * N + h]; };
-    double SA, wA;
-    const int cA = cpf_pick(hm, 0ULL, w_first, unif(r2.x[0]), SA, wA);
-    if (cA < 0) return false;
-    const int A = cA & 63;
+    // Opposite spins: x the beta electron, y the alpha one, first hole beta;
+    // equal spins: x < y, both holes of their spin.  One code path for both,
+    // so that the lanes of a wave run the hole loops together.
+    const bool opp = s1 != s2;
+    const int x = opp ? (s1 ? p1 : p2) : (p1 < p2 ? p1 : p2);
+    const int y = opp ? (s1 ? p2 : p1) : (p1 < p2 ? p2 : p1);
+    const uint64_t holes_a = ~((opp || s1) ? b : a) & full;
+    auto w_first = [&](int, int h) {
+        const double u0 = SK[x * N + h];
+        if (opp) return u0;
+        const double u1 = SK[y * N + h];
+        return u0 + u1;
+    };
     // second-hole weight given first hole f
     auto w_second = [&](int f, int h) {
         if constexpr (EXACT) {
-            const double dir = eri(s, pi, f, pj, h);
-            const double exc = eri(s, pi, h, pj, f);
-            return sqrt(fabs(dir - exc));
+            const double d = eri(s, x, f, y, h);
+            if (opp) return sqrt(fabs(d));
+            const double e = eri(s, x, h, y, f);
+            return sqrt(fabs(d - e));
         } else {
-            return SK[pi * N + h] + SK[pj * N + h];
+            if (opp) return SK[y * N + h];
+            const double u0 = SK[x * N + h];
+            const double u1 = SK[y * N + h];
+            return u0 + u1;
         }
     };
+    double SA, wA;
+    const int cA = cpf_pick(holes_a, 0ULL, w_first, unif(r2.x[0]), SA, wA);
+    if (cA < 0) return false;
+    const int A = cA & 63;
+    const uint64_t holes_b = opp ? ~a & full : holes_a & ~(1ULL << A);
     double SB, wB;
-    const int cB = cpf_pick(hm & ~(1ULL << A), 0ULL, [&](int, int h) { return w_second(A, h); }, unif(r2.x[1]),
-                            SB, wB);
+    const int cB = cpf_pick(holes_b, 0ULL, [&](int, int h) { return w_second(A, h); }, unif(r2.x[1]), SB, wB);
     if (cB < 0) return false;
     const int B = cB & 63;
-    const double SR = cpf_total(hm & ~(1ULL << B), 0ULL, [&](int, int h) { return w_second(B, h); });
+    if (opp) {
+        const double q = pp * (wA / SA);
+        out.pgen = q * (wB / SB);
+        out.H = h_double(s, a, b, 0, y, 1, x, 0, B, 1, A);
+        out.ta = (a & ~(1ULL << y)) | (1ULL << B);
+        out.tb = (b & ~(1ULL << x)) | (1ULL << A);
+        return true;
+    }
+    // the other order of the holes: B first, then A
+    const double SR = cpf_total(holes_a & ~(1ULL << B), 0ULL, [&](int, int h) { return w_second(B, h); });
     const double wAr = w_second(B, A);
     const double wBf = w_first(0, B);
     const double pab = (wA / SA) * (wB / SB);
     const double pba = (wBf / SA) * (wAr / SR);
     out.pgen = pp * (pab + pba);
     const int lo = A < B ? A : B, hi = A < B ? B : A;
-    out.H = h_double(s, a, b, s1, pi, s1, pj, s1, lo, s1, hi);
-    const uint64_t m = (occ & ~(1ULL << pi) & ~(1ULL << pj)) | (1ULL << A) | (1ULL << B);
+    out.H = h_double(s, a, b, s1, x, s1, y, s1, lo, s1, hi);
+    const uint64_t occ = s1 ? b : a;
+    const uint64_t m = (occ & ~(1ULL << x) & ~(1ULL << y)) | (1ULL << A) | (1ULL << B);
     out.ta = s1 ? a : m;
     out.tb = s1 ? m : b;
     return true;
