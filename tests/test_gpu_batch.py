@@ -11,7 +11,7 @@ from tests.gpu_helpers import (assert_same_gpu_stats, assert_same_gpu_walkers, a
 pytestmark = pytest.mark.gpu
 
 # (system, run options): uneven orbital counts, both determinant widths, all
-# three generators, initiator on and off
+# five generators, initiator on and off
 MEMBERS = [
     (lambda: inputs.molecule_8o8e(), dict(tau=0.01, target=1e4, seed=1)),
     (lambda: inputs.synthetic_molecule(10, 5, 5, seed=3), dict(tau=0.01, target=3e4, n_a=3.0, seed=2)),
@@ -21,6 +21,9 @@ MEMBERS = [
                                                                det_words=2, seed=4)),
     (lambda: inputs.synthetic_molecule(9, 4, 4, seed=11), dict(tau=0.01, target=2e4, gen="pchb",
                                                                n_a=3.0, seed=5)),
+    (lambda: inputs.synthetic_molecule(10, 4, 4, seed=13), dict(tau=0.01, target=1e4, gen="cs", seed=6)),
+    (lambda: inputs.synthetic_molecule(11, 5, 4, seed=17), dict(tau=0.005, target=2e4, gen="pe",
+                                                                n_a=3.0, det_words=2, seed=7)),
 ]
 
 
