@@ -75,6 +75,11 @@ def lib():
         L.orc_run_step.argtypes = [vp, C.POINTER(OrcStats)]
         L.orc_run_estimate.argtypes = [vp, pdbl, pdbl, pdbl]
         L.orc_generate.argtypes = [vp, u64, u64, i64, u64, pu64, pu64, pdbl, pdbl]
+        L.orc_run_set_core.restype = i64
+        L.orc_run_set_core.argtypes = [vp, i64]
+        L.orc_run_core_size.restype = i64
+        L.orc_run_core_size.argtypes = [vp]
+        L.orc_run_get_core.argtypes = [vp, pu64, pu64]
         _lib = L
     return _lib
 
@@ -263,6 +268,18 @@ class Run:
         nw, nr, en = C.c_double(), C.c_double(), C.c_double()
         lib().orc_run_estimate(self.ptr, C.byref(nw), C.byref(nr), C.byref(en))
         return dict(nw=nw.value, nref=nr.value, enum_=en.value)
+
+    def set_core(self, n_core):
+        """Deterministic space of the n_core most populated determinants
+        (semi-stochastic projection); returns its size (-1 in integer mode)."""
+        return lib().orc_run_set_core(self.ptr, int(n_core))
+
+    def core(self):
+        n = lib().orc_run_core_size(self.ptr)
+        a = np.zeros(n, dtype=np.uint64)
+        b = np.zeros(n, dtype=np.uint64)
+        lib().orc_run_get_core(self.ptr, _p(a, C.c_uint64), _p(b, C.c_uint64))
+        return a, b
 
     def generate(self, a, b, t, k):
         ta, tb, pg, H = C.c_uint64(), C.c_uint64(), C.c_double(), C.c_double()

@@ -531,6 +531,11 @@ typedef struct {
     int64_t t_set;     /* step at which the population was last set */
     ent_t *list;
     int64_t n, cap;
+    /* semi-stochastic deterministic space (Sec. "Semi-stochastic FCIQMC") */
+    det_t *core;        /* nc determinants, ascending */
+    int64_t nc;
+    double *hcore;      /* nc x nc: H_kj for k != j (dense; the diagonal is unused) */
+    double *core_diag;  /* H_kk - H_00 */
 } orc_run;
 
 static int ent_cmp(const void *x, const void *y)
@@ -585,9 +590,17 @@ orc_run *orc_run_create(const orc_sys *s, const orc_params *p, uint64_t ref_a, u
     return r;
 }
 
+static void core_clear(orc_run *r)
+{
+    free(r->core); free(r->hcore); free(r->core_diag);
+    r->core = NULL; r->hcore = NULL; r->core_diag = NULL;
+    r->nc = 0;
+}
+
 void orc_run_free(orc_run *r)
 {
     if (!r) return;
+    core_clear(r);
     free(r->list);
     free(r->nw_ring);
     free(r);
@@ -596,9 +609,11 @@ void orc_run_free(orc_run *r)
 double orc_run_h00(const orc_run *r) { return r->h00; }
 double orc_run_p_single(const orc_run *r) { return r->p.p_single; }
 
-/* Replace the population; values are stored as given, zero entries dropped. */
+/* Replace the population; values are stored as given, zero entries dropped.
+ * A deterministic space, if any, is dropped too. */
 void orc_run_set_walkers(orc_run *r, const uint64_t *a, const uint64_t *b, const double *v, int64_t n)
 {
+    core_clear(r);
     free(r->list);
     r->cap = n > 16 ? n : 16;
     r->list = (ent_t *)malloc(sizeof(ent_t) * r->cap);
@@ -654,6 +669,73 @@ static int64_t find(const ent_t *list, int64_t n, det_t d)
     return -1;
 }
 
+/* Index of d in the deterministic space, -1 if it is not there. */
+static int64_t core_find(const orc_run *r, det_t d)
+{
+    int64_t lo = 0, hi = r->nc;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        int c = det_cmp(r->core[mid], d);
+        if (c == 0) return mid;
+        if (c < 0) lo = mid + 1; else hi = mid;
+    }
+    return -1;
+}
+
+/* Order for choosing the deterministic space: larger |C| first, ties by
+ * ascending determinant. */
+static int weight_cmp(const void *x, const void *y)
+{
+    const ent_t *p = (const ent_t *)x, *q = (const ent_t *)y;
+    double a = fabs(p->v), b = fabs(q->v);
+    if (a != b) return a > b ? -1 : 1;
+    return det_cmp(p->d, q->d);
+}
+
+static int detv_cmp(const void *x, const void *y) { return det_cmp(*(const det_t *)x, *(const det_t *)y); }
+
+/* Semi-stochastic projection (Sec. "Semi-stochastic FCIQMC"): the projector
+ * splits into P^D, its elements between determinants of the deterministic
+ * space D, applied exactly every step as a matrix-vector product, and the
+ * rest, sampled by spawning as usual.  D is the n_core most populated
+ * determinants of the current population (the paper's usual choice); it is
+ * ordered by determinant and H^D is stored with it.  Readings (the paper
+ * leaves them open): P^D includes the diagonal, so the determinants of D
+ * have no stochastic death; their coefficients are never compressed to
+ * C_min and they stay in the population at any value, zero included; they
+ * count as initiators; spawns from D into D are dropped (their terms are in
+ * P^D).  Real coefficients only.  Returns the size of D, -1 in integer mode. */
+int64_t orc_run_set_core(orc_run *r, int64_t n_core)
+{
+    core_clear(r);
+    if (r->p.mode != MODE_REAL) return -1;
+    int64_t nc = n_core < r->n ? n_core : r->n;
+    if (nc <= 0) return 0;
+    ent_t *tmp = (ent_t *)malloc(sizeof(ent_t) * r->n);
+    memcpy(tmp, r->list, sizeof(ent_t) * r->n);
+    qsort(tmp, r->n, sizeof(ent_t), weight_cmp);
+    r->core = (det_t *)malloc(sizeof(det_t) * nc);
+    for (int64_t k = 0; k < nc; ++k) r->core[k] = tmp[k].d;
+    free(tmp);
+    qsort(r->core, nc, sizeof(det_t), detv_cmp);
+    r->nc = nc;
+    r->hcore = (double *)calloc((size_t)(nc * nc), sizeof(double));
+    r->core_diag = (double *)malloc(sizeof(double) * nc);
+    for (int64_t k = 0; k < nc; ++k) {
+        r->core_diag[k] = r->list[find(r->list, r->n, r->core[k])].diag;
+        for (int64_t j = 0; j < nc; ++j)
+            if (j != k) r->hcore[k * nc + j] = orc_hij_det(r->s, r->core[j], r->core[k]);
+    }
+    return nc;
+}
+
+int64_t orc_run_core_size(const orc_run *r) { return r->nc; }
+
+void orc_run_get_core(const orc_run *r, uint64_t *a, uint64_t *b)
+{
+    for (int64_t k = 0; k < r->nc; ++k) { a[k] = r->core[k].a; b[k] = r->core[k].b; }
+}
+
 /* Stochastic compression to C_min (Sec. I, the compressed storage rule):
  * keep |x| >= C_min, else sign(x) C_min with probability |x|/C_min, else 0. */
 static double round_cmin(double x, double cmin, double u)
@@ -694,6 +776,8 @@ int orc_run_step(orc_run *r, orc_stats *st)
         /* initiator: |C_i| above n_a (Sec. I); Reading: the reference always
          * counts as one; a negative n_a switches the approximation off. */
         int init = (p->n_a < 0.0) || (aC > p->n_a) || det_eq(e->d, r->ref);
+        int pcore = r->nc > 0 && core_find(r, e->d) >= 0;
+        if (pcore) init = 1;
         st->attempts += m;
         for (int64_t k = 0; k < m; ++k) {
             uint64_t rr[4];
@@ -712,6 +796,7 @@ int orc_run_step(orc_run *r, orc_stats *st)
                     ok = orc_cs_gen(s, e->d, rr, r2, p->p_single, p->p_opp, p->gen == GEN_PE, &tgt, &pgen);
             }
             if (!ok) continue;
+            if (pcore && core_find(r, tgt) >= 0) continue;  /* in P^D */
             double H = orc_hij_det(s, e->d, tgt);
             if (H == 0.0) continue;
             double amt;
@@ -756,6 +841,7 @@ int orc_run_step(orc_run *r, orc_stats *st)
     double *post = (double *)malloc(sizeof(double) * (r->n > 0 ? r->n : 1));
     for (int64_t x = 0; x < r->n; ++x) {
         const ent_t *e = &r->list[x];
+        if (r->nc > 0 && core_find(r, e->d) >= 0) continue;  /* set below */
         double t1 = e->diag - r->S;
         double t2 = p->tau * t1;
         double f = 1.0 - t2;
@@ -772,6 +858,27 @@ int orc_run_step(orc_run *r, orc_stats *st)
         } else {
             post[x] = round_cmin(xv, p->c_min, u);
         }
+    }
+
+    /* Deterministic space: (P^D C)_k = (1 - dtau (H_kk - S)) C_k
+     * - dtau sum_{j != k} H_kj C_j, exactly, over j in ascending order. */
+    if (r->nc > 0) {
+        int64_t *at = (int64_t *)malloc(sizeof(int64_t) * r->nc);
+        for (int64_t k = 0; k < r->nc; ++k) at[k] = find(r->list, r->n, r->core[k]);
+        for (int64_t k = 0; k < r->nc; ++k) {
+            double t1 = r->core_diag[k] - r->S;
+            double t2 = p->tau * t1;
+            double f = 1.0 - t2;
+            double acc = f * r->list[at[k]].v;
+            for (int64_t j = 0; j < r->nc; ++j) {
+                if (j == k) continue;
+                double x1 = p->tau * r->hcore[k * r->nc + j];
+                double x2 = x1 * r->list[at[j]].v;
+                acc = acc - x2;
+            }
+            post[at[k]] = acc;
+        }
+        free(at);
     }
 
     /* (c) annihilation.  Sum all contributions per target.  Initiator rule
@@ -811,7 +918,7 @@ int orc_run_step(orc_run *r, orc_stats *st)
     if (!integer) {
         for (int64_t x = 0; x < nn; ++x) {
             double v = next[x].v;
-            if (v != 0.0 && fabs(v) < p->c_min) {
+            if (v != 0.0 && fabs(v) < p->c_min && !(r->nc > 0 && core_find(r, next[x].d) >= 0)) {
                 uint64_t rr[4];
                 draw(r, next[x].d, t, 0, PURPOSE_ANN, rr);
                 next[x].v = round_cmin(v, p->c_min, unif(rr[0]));
@@ -820,7 +927,7 @@ int orc_run_step(orc_run *r, orc_stats *st)
     }
     int64_t m = 0;
     for (int64_t x = 0; x < nn; ++x)
-        if (next[x].v != 0.0) next[m++] = next[x];
+        if (next[x].v != 0.0 || (r->nc > 0 && core_find(r, next[x].d) >= 0)) next[m++] = next[x];
     qsort(next, m, sizeof(ent_t), ent_cmp);
     free(r->list);
     free(post);

@@ -475,6 +475,114 @@ def test_one_step_expectation(oracle_mod, mode, na, gen):
         assert np.max(zf) > 5.0
 
 
+def _walker_map(run, index, D):
+    ra, rb, rv, _ = run.get_walkers()
+    out = np.zeros(D)
+    for x, y, z in zip(ra, rb, rv):
+        out[index[(int(x), int(y))]] = z
+    return out, len(rv)
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_semistochastic_full_space_is_the_projector(oracle_mod, seed):
+    """Sec. "Semi-stochastic FCIQMC": with every determinant in the
+    deterministic space, one step is exactly (1 - dtau (H - S)) C, whatever
+    the random stream, and values below C_min stay unrounded."""
+    s = inputs.synthetic_molecule(5, 2, 2, seed=21, rank=8)
+    osys = oracle_mod.System.from_inputs(s)
+    dets = brute.basis(5, 2, 2)
+    index = {d: i for i, d in enumerate(dets)}
+    D = len(dets)
+    rng = np.random.default_rng(2)
+    C0 = rng.normal(0.0, 3.0, size=D)
+    tau, S = 0.05, -0.3
+    ref = dets[0]
+    run = oracle_mod.Run(osys, ref=ref, tau=tau, target=1e12, mode=oracle_mod.MODE_REAL,
+                         seed=seed, n_a=3.0)
+    run.set_walkers([d[0] for d in dets], [d[1] for d in dets], C0)
+    run.set_state(0, S, 1, 0, 1.0)
+    assert run.set_core(D) == D
+    run.step()
+    H = brute.oracle_dense_h(osys, dets)
+    h00 = osys.hdiag(*ref)
+    P = -tau * H
+    for i in range(D):
+        P[i, i] = 1.0 - tau * (H[i, i] - h00 - S)
+    got, n = _walker_map(run, index, D)
+    assert n == D
+    want = P @ C0
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    assert np.sum(np.abs(got) < 1.0) > 0   # fractional values survive uncompressed
+
+
+@pytest.mark.parametrize("na", [-1.0, 3.0])
+def test_semistochastic_one_step_expectation(oracle_mod, na):
+    """Part of the population in the deterministic space: averaged over
+    independent streams, one step still equals the projector (masked by the
+    initiator rule, with the deterministic determinants counted as
+    initiators), and the deterministic coefficients that receive no spawns
+    from outside the space come out with zero variance."""
+    s = inputs.synthetic_molecule(5, 2, 2, seed=21, rank=8)
+    osys = oracle_mod.System.from_inputs(s)
+    dets = brute.basis(5, 2, 2)
+    index = {d: i for i, d in enumerate(dets)}
+    D = len(dets)
+    rng = np.random.default_rng(1)
+    pick = rng.choice(D, size=12, replace=False)
+    C0 = np.zeros(D)
+    C0[pick] = rng.integers(1, 9, size=12) * rng.choice([-1, 1], size=12) * 0.7
+    tau, S = 0.05, -0.3
+    ref = dets[int(pick[0])]
+    a = np.array([dets[i][0] for i in pick], dtype=np.uint64)
+    b = np.array([dets[i][1] for i in pick], dtype=np.uint64)
+    H = brute.oracle_dense_h(osys, dets)
+    h00 = osys.hdiag(*ref)
+    probe = oracle_mod.Run(osys, ref=ref, tau=tau, target=1e12, n_a=na, mode=oracle_mod.MODE_REAL)
+    probe.set_walkers(a, b, C0[pick])
+    assert probe.set_core(5) == 5
+    ca, cb = probe.core()
+    core = {index[(int(x), int(y))] for x, y in zip(ca, cb)}
+    # the five largest |C| (ties by determinant order)
+    order = sorted(pick, key=lambda i: (-abs(C0[i]), dets[i]))
+    assert core == set(int(i) for i in order[:5])
+    P = -tau * H
+    for i in range(D):
+        P[i, i] = 1.0 - tau * (H[i, i] - h00 - S)
+    if na >= 0:
+        for i in range(D):
+            if abs(C0[i]) > na or dets[i] == ref or i in core:
+                continue
+            for j in range(D):
+                if j != i and C0[j] == 0.0:
+                    P[j, i] = 0.0
+    expect = P @ C0
+    nrep = 6000
+    acc = np.zeros(D)
+    acc2 = np.zeros(D)
+    for rep in range(nrep):
+        run = oracle_mod.Run(osys, ref=ref, tau=tau, target=1e12, n_a=na, mode=oracle_mod.MODE_REAL,
+                             seed=5000 + rep)
+        run.set_walkers(a, b, C0[pick])
+        run.set_state(0, S, 1, 0, 1.0)
+        run.set_core(5)
+        run.step()
+        out, _ = _walker_map(run, index, D)
+        acc += out
+        acc2 += out * out
+    mean = acc / nrep
+    var = np.maximum(acc2 / nrep - mean * mean, 0.0)
+    se = np.sqrt(var / nrep)
+    z = np.abs(mean - expect) / np.maximum(se, 1e-9)
+    assert np.max(z) < 5.0, (np.max(z), np.argmax(z))
+    # a deterministic determinant that no determinant outside the space can
+    # reach has an exact, noise-free coefficient
+    outside = [i for i in pick if i not in core]
+    quiet = [k for k in core if all(H[k, j] == 0.0 for j in outside)]
+    for k in quiet:
+        assert var[k] <= 1e-20 * max(1.0, expect[k] ** 2)
+        assert abs(mean[k] - expect[k]) <= 1e-12 * max(1.0, abs(expect[k]))
+
+
 def test_projected_energy_of_eigenvector(oracle_mod):
     """E_Ref is exact for an eigenstate (Eq. proje)."""
     s = inputs.synthetic_molecule(6, 3, 3, seed=5)
