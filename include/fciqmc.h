@@ -161,8 +161,30 @@ int fciqmc_energy(const fciqmc_run *run, fciqmc_energy_report *out);
  * (ENOMEM-free: returns EOVERFLOW with *n set when cap is too small). */
 int fciqmc_get_walkers(const fciqmc_run *run, uint64_t *dets, double *vals, int64_t cap,
                        int64_t *n);
-/* Replace the population (values must be non-zero; integer mode: integers). */
+/* Replace the population (values must be non-zero; integer mode: integers).
+ * Drops the deterministic space, if any. */
 int fciqmc_set_walkers(fciqmc_run *run, const uint64_t *dets, const double *vals, int64_t n);
+
+/* Semi-stochastic projection (Sec. "Semi-stochastic FCIQMC"): make the
+ * n_core determinants of largest |C| in the current population (ties:
+ * ascending alpha, then beta mask) the deterministic space D.  From the
+ * next step on, the projector's elements between determinants of D are
+ * applied exactly (a sparse product with H^D, built here on the device by
+ * testing all pairs) and only the rest is sampled: spawns from D into D are
+ * dropped, the determinants of D have no stochastic death, are never
+ * compressed to C_min, stay in the population at any value (zero included)
+ * and count as initiators.  Calling it again re-selects D from the current
+ * population; n_core = 0 removes it.  Real mode only (EINVAL otherwise);
+ * 0 <= n_core <= 131072 (EINVAL); a run in a batch: ESTATE, and a run with
+ * a deterministic space cannot join a batch.  *n_out (may be NULL)
+ * receives |D| = min(n_core, determinants). */
+int fciqmc_set_core(fciqmc_run *run, int64_t n_core, int64_t *n_out);
+
+/* The deterministic space: *n_out = |D|, *nnz_out = off-diagonal nonzeros
+ * of H^D (either may be NULL); dets (host, may be NULL) receives up to
+ * capacity determinants as (alpha, beta) mask pairs, ascending. */
+int fciqmc_get_core(const fciqmc_run *run, uint64_t *dets, int64_t capacity, int64_t *n_out,
+                    int64_t *nnz_out);
 int fciqmc_get_checkpoint(const fciqmc_run *run, fciqmc_checkpoint *out);
 int fciqmc_set_checkpoint(fciqmc_run *run, const fciqmc_checkpoint *in);
 

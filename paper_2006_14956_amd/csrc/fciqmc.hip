@@ -215,7 +215,15 @@ struct EngineBase {
     virtual int kind() const = 0;        // determinant width and value type, see kind_of
     virtual int64_t ndets() const = 0;   // occupied determinants after the last step
     virtual int rebucket(int buckets) = 0;
+    // semi-stochastic deterministic space
+    virtual int set_core(int64_t n_core) = 0;
+    virtual int64_t core_size() const = 0;
+    virtual int64_t core_nnz() const = 0;
+    virtual const std::vector<uint64_t>& core_dets() const = 0;
 };
+
+// Largest deterministic space: H^D is built by testing all N_D^2 pairs.
+constexpr int64_t kMaxCore = 1 << 17;
 
 // Engines of one kind share batched launches: 0 = (1 word, int32),
 // 1 = (1 word, FP64), 2 = (2 words, int32), 3 = (2 words, FP64).
@@ -279,6 +287,22 @@ template <int W, class V> struct Engine : EngineBase {
     // optional per-kernel timing (HIP events around each launch of a step),
     // one set per step parity since the next spawn is queued early
     bool profile = false;
+    // semi-stochastic deterministic space (Sec. "Semi-stochastic FCIQMC"):
+    // its determinants ascending, H^D in CSR without the diagonal, the
+    // diagonal H_kk - H_00, C_D for each store, and P^D C_D of the step
+    int64_t ncore = 0, nnz = 0;
+    std::vector<uint64_t> core_host;  // alpha, beta masks of each determinant
+    uint64_t* core_keys = nullptr;
+    uint64_t* core_hkeys = nullptr;
+    int32_t* core_hidx = nullptr;
+    uint64_t core_hmask = 0;
+    double* core_cdiag = nullptr;
+    double* core_cv[2] = {nullptr, nullptr};
+    double* core_dv = nullptr;
+    int64_t* core_rowp = nullptr;
+    int32_t* core_col = nullptr;
+    double* core_val = nullptr;
+    unsigned long long* core_missing = nullptr;
     hipEvent_t ev[2][kKernels + 1]{};
     double kms[kKernels]{};
     int64_t klaunch = 0;
@@ -439,6 +463,14 @@ template <int W, class V> struct Engine : EngineBase {
         sc.n_a = rs.n_a; sc.c_min = rs.c_min; sc.S = S; sc.h00 = rs.h00;
         sc.ref_a = rs.ref_a; sc.ref_b = rs.ref_b;
         sc.B = B; sc.R = R; sc.spawn_cap = cap; sc.import_mode = import_mode;
+        sc.ncore = ncore;
+        if (ncore > 0) {
+            sc.core_d = core_dv;
+            sc.core_c = core_cv[1 - cur];
+            sc.core_hkeys = core_hkeys;
+            sc.core_hidx = core_hidx;
+            sc.core_hmask = core_hmask;
+        }
         return sc;
     }
 
@@ -456,6 +488,9 @@ template <int W, class V> struct Engine : EngineBase {
         const SysView v = sys->view();
         Store<V> in = st[cur], out = st[1 - cur];
         const int gb = std::min(B, 32768);
+        if (ncore > 0 && !sc.import_mode)
+            hipLaunchKernelGGL(k_core_spmv, dim3((unsigned)((ncore + 3) / 4)), dim3(kThreads), 0, stream, core_rowp,
+                               core_col, core_val, core_cdiag, core_cv[cur], core_dv, ncore, rs.tau, sc.S);
         hipLaunchKernelGGL((k_annihilate<W, V>), dim3(gb), dim3(kThreads), 0, stream, v, in, out, sc,
                            rec2, soff, scount, rel, need_b, recs_b, nw_b, en_b, fpos, fcnt, ctl);
         if (!sys->onsite) {
@@ -549,7 +584,8 @@ template <int W, class V> struct Engine : EngineBase {
                 att_next = hctl->attempts;
                 rec_need = hctl->rec_need;
                 CHECK(ensure_cmap());
-                return ensure_slabs(rec_need);
+                CHECK(ensure_slabs(rec_need));
+                return tag_core();
             }
             if (flags & (kFlagTable | kFlagStore)) {
                 if ((int64_t)B * 2 > max_b) return fail(FCIQMC_EOVERFLOW, "population does not fit the walker store");
@@ -565,10 +601,118 @@ template <int W, class V> struct Engine : EngineBase {
     }
 
     int set_walkers(const uint64_t* ab, const double* vals, int64_t n) override {
+        clear_core();  // a new population has no deterministic space
         cur = 0;
         dirty = false;
         return import(ab, vals, n);
     }
+
+    // ---- deterministic space ----
+    void clear_core() {
+        for (void* p : {(void*)core_keys, (void*)core_hkeys, (void*)core_hidx, (void*)core_cdiag, (void*)core_cv[0],
+                        (void*)core_cv[1], (void*)core_dv, (void*)core_rowp, (void*)core_col, (void*)core_val,
+                        (void*)core_missing})
+            arena.release(p);
+        core_keys = core_hkeys = nullptr;
+        core_hidx = core_col = nullptr;
+        core_cdiag = core_cv[0] = core_cv[1] = core_dv = core_val = nullptr;
+        core_rowp = nullptr;
+        core_missing = nullptr;
+        core_host.clear();
+        ncore = nnz = 0;
+    }
+    // Tag the space's determinants in the current store and read C_D.
+    int tag_core() {
+        if (ncore == 0) return 0;
+        HIP_OK(hipMemsetAsync(core_missing, 0, sizeof(unsigned long long), stream));
+        const unsigned g = (unsigned)std::min<int64_t>((ncore + 255) / 256, 4096);
+        hipLaunchKernelGGL((k_core_tag<W, V>), dim3(g), dim3(256), 0, stream, st[cur], R, B, core_keys, ncore,
+                           core_cv[cur], core_missing);
+        HIP_OK(hipGetLastError());
+        unsigned long long miss = 0;
+        HIP_OK(hipMemcpyAsync(&miss, core_missing, sizeof(miss), hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipStreamSynchronize(stream));
+        if (miss)
+            return fail(FCIQMC_EDEVICE, "%llu determinants of the deterministic space are not in the population", miss);
+        return 0;
+    }
+    // The n_core determinants of largest |C| (ties: ascending determinant),
+    // H^D between them, and the tags in the store.
+    int set_core(int64_t n_core) override {
+        CHECK(discard_pending());  // a queued spawn ignores the new space
+        clear_core();
+        if (n_core == 0) return 0;
+        std::vector<uint64_t> ab;
+        std::vector<double> vals;
+        CHECK(get_walkers(ab, vals));
+        const int64_t n = (int64_t)vals.size();
+        const int64_t nc = std::min(n_core, n);
+        if (nc == 0) return 0;
+        std::vector<int64_t> ord((size_t)n);
+        for (int64_t i = 0; i < n; ++i) ord[(size_t)i] = i;
+        std::partial_sort(ord.begin(), ord.begin() + nc, ord.end(), [&](int64_t x, int64_t y) {
+            const double ax = std::fabs(vals[(size_t)x]), ay = std::fabs(vals[(size_t)y]);
+            if (ax != ay) return ax > ay;
+            if (ab[2 * x] != ab[2 * y]) return ab[2 * x] < ab[2 * y];
+            return ab[2 * x + 1] < ab[2 * y + 1];
+        });
+        std::vector<std::pair<uint64_t, uint64_t>> dets((size_t)nc);
+        for (int64_t k = 0; k < nc; ++k) dets[(size_t)k] = {ab[2 * ord[(size_t)k]], ab[2 * ord[(size_t)k] + 1]};
+        std::sort(dets.begin(), dets.end());
+        core_host.resize((size_t)nc * 2);
+        std::vector<uint64_t> keys((size_t)nc * W);
+        for (int64_t k = 0; k < nc; ++k) {
+            const uint64_t a = dets[(size_t)k].first, b = dets[(size_t)k].second;
+            core_host[(size_t)(2 * k)] = a;
+            core_host[(size_t)(2 * k + 1)] = b;
+            if constexpr (W == 1) keys[(size_t)k] = a | (b << 32);
+            else { keys[(size_t)(2 * k)] = a; keys[(size_t)(2 * k + 1)] = b; }
+        }
+        const int64_t slots = (int64_t)next_pow2((uint64_t)std::max<int64_t>(64, 2 * nc));
+        CHECK(dalloc(arena, &core_keys, (size_t)nc * W));
+        CHECK(dalloc(arena, &core_hkeys, (size_t)slots * W));
+        CHECK(dalloc(arena, &core_hidx, (size_t)slots));
+        CHECK(dalloc(arena, &core_cdiag, (size_t)nc));
+        CHECK(dalloc(arena, &core_cv[0], (size_t)nc));
+        CHECK(dalloc(arena, &core_cv[1], (size_t)nc));
+        CHECK(dalloc(arena, &core_dv, (size_t)nc));
+        CHECK(dalloc(arena, &core_rowp, (size_t)nc + 1));
+        CHECK(dalloc(arena, &core_missing, 1));
+        core_hmask = (uint64_t)slots - 1;
+        HIP_OK(hipMemcpyAsync(core_keys, keys.data(), sizeof(uint64_t) * keys.size(), hipMemcpyHostToDevice, stream));
+        HIP_OK(hipMemsetAsync(core_hidx, 0xFF, sizeof(int32_t) * slots, stream));
+        const SysView v = sys->view();
+        const unsigned g = (unsigned)std::min<int64_t>((nc + 255) / 256, 4096);
+        hipLaunchKernelGGL((k_core_hash<W>), dim3(g), dim3(256), 0, stream, core_keys, nc, core_hkeys, core_hidx,
+                           core_hmask);
+        hipLaunchKernelGGL((k_core_diag<W>), dim3(g), dim3(256), 0, stream, v, core_keys, nc, rs.h00, core_cdiag);
+        // H^D: row counts, their prefix on the host, then the rows
+        int64_t* cnt = nullptr;
+        Arena tmp;
+        CHECK(dalloc(tmp, &cnt, (size_t)nc));
+        const unsigned gr = (unsigned)std::min<int64_t>(nc, 65536);
+        hipLaunchKernelGGL((k_core_rows<W>), dim3(gr), dim3(kThreads), 0, stream, v, core_keys, nc,
+                           (const int64_t*)nullptr, (int32_t*)nullptr, (double*)nullptr, cnt);
+        HIP_OK(hipGetLastError());
+        std::vector<int64_t> hc((size_t)nc), rp((size_t)nc + 1, 0);
+        HIP_OK(hipMemcpyAsync(hc.data(), cnt, sizeof(int64_t) * nc, hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipStreamSynchronize(stream));
+        for (int64_t k = 0; k < nc; ++k) rp[(size_t)k + 1] = rp[(size_t)k] + hc[(size_t)k];
+        nnz = rp[(size_t)nc];
+        CHECK(dalloc(arena, &core_col, (size_t)std::max<int64_t>(nnz, 1)));
+        CHECK(dalloc(arena, &core_val, (size_t)std::max<int64_t>(nnz, 1)));
+        HIP_OK(hipMemcpyAsync(core_rowp, rp.data(), sizeof(int64_t) * (nc + 1), hipMemcpyHostToDevice, stream));
+        hipLaunchKernelGGL((k_core_rows<W>), dim3(gr), dim3(kThreads), 0, stream, v, core_keys, nc,
+                           (const int64_t*)core_rowp, core_col, core_val, (int64_t*)nullptr);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipStreamSynchronize(stream));
+        tmp.clear();
+        ncore = nc;
+        return tag_core();
+    }
+    int64_t core_size() const override { return ncore; }
+    int64_t core_nnz() const override { return nnz; }
+    const std::vector<uint64_t>& core_dets() const override { return core_host; }
 
     int get_walkers(std::vector<uint64_t>& ab, std::vector<double>& vals) override {
         const Store<V>& s = st[cur];
@@ -1371,6 +1515,8 @@ int fciqmc_batch_create(void* stream, fciqmc_batch** out) {
 int fciqmc_batch_add(fciqmc_batch* b, fciqmc_run* run) {
     if (!b || !run || !run->eng) return fail(FCIQMC_EINVAL, "null argument");
     if (run->batch) return fail(FCIQMC_EINVAL, "the run already belongs to a batch");
+    if (run->eng->core_size() > 0)
+        return fail(FCIQMC_EINVAL, "a run with a deterministic space is stepped alone");
     HIP_OK(hipStreamSynchronize(run->stream));
     const int k = run->eng->kind();
     if (!b->group[k]) b->group[k] = make_group(k);
@@ -1668,6 +1814,31 @@ int fciqmc_set_walkers(fciqmc_run* run, const uint64_t* dets, const double* vals
     const int64_t A = run->p.shift_interval;
     run->t_set = run->t;
     run->nw_ring[(size_t)(run->t % (A + 1))] = run->eng->last_nw();
+    return 0;
+}
+
+int fciqmc_set_core(fciqmc_run* run, int64_t n_core, int64_t* n_out) {
+    if (!run || !run->eng) return fail(FCIQMC_ESTATE, "run not initialised");
+    if (run->batch) return fail(FCIQMC_ESTATE, "the run belongs to a batch");
+    if (run->p.mode != FCIQMC_MODE_REAL)
+        return fail(FCIQMC_EINVAL, "the semi-stochastic projection needs real coefficients");
+    if (n_core < 0 || n_core > kMaxCore)
+        return fail(FCIQMC_EINVAL, "n_core must be in [0, %lld]", (long long)kMaxCore);
+    CHECK(run->eng->set_core(n_core));
+    if (n_out) *n_out = run->eng->core_size();
+    return 0;
+}
+
+int fciqmc_get_core(const fciqmc_run* run, uint64_t* dets, int64_t capacity, int64_t* n_out, int64_t* nnz_out) {
+    if (!run || !run->eng) return fail(FCIQMC_ESTATE, "run not initialised");
+    const int64_t n = run->eng->core_size();
+    if (n_out) *n_out = n;
+    if (nnz_out) *nnz_out = run->eng->core_nnz();
+    if (dets && capacity > 0) {
+        const auto& c = run->eng->core_dets();
+        const int64_t m = std::min(n, capacity);
+        std::copy(c.begin(), c.begin() + 2 * m, dets);
+    }
     return 0;
 }
 

@@ -98,7 +98,42 @@ struct StepScalars {
     int B, R;
     long long spawn_cap;
     int import_mode;
+    // semi-stochastic deterministic space (ncore = 0: none)
+    int64_t ncore;
+    const double* core_d;        // (P^D C)_k of this step
+    double* core_c;              // C_k after this step, written by the merge
+    const uint64_t* core_hkeys;  // open-addressing table of the space: keys (W words a slot)
+    const int32_t* core_hidx;    // and indices in the space, -1 for an empty slot
+    uint64_t core_hmask;
 };
+
+// ---------------------------------------------------------------------------
+// Semi-stochastic projection (Sec. "Semi-stochastic FCIQMC").  A determinant
+// of the deterministic space keeps, in its cached-diagonal slot of the
+// walker store, the bits kCoreTag | k: a NaN that no finite diagonal takes,
+// carrying its index k in the space.  Entries are copied verbatim, so the
+// tag follows the determinant through every step.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kCoreTag = 0x7FFC000000000000ULL;
+__device__ __forceinline__ bool is_core(double d) {
+    return ((uint64_t)__double_as_longlong(d) >> 48) == (kCoreTag >> 48);
+}
+__device__ __forceinline__ int64_t core_index(double d) {
+    return (int64_t)((uint64_t)__double_as_longlong(d) & 0xFFFFFFFFFFFFULL);
+}
+__device__ __forceinline__ double core_tag(int64_t k) { return __longlong_as_double((long long)(kCoreTag | (uint64_t)k)); }
+
+// Index of `key` in the deterministic space, -1 if it is not there (the
+// table is at most half full, so the probe meets an empty slot).
+template <int W> __device__ __forceinline__ int64_t core_find(const StepScalars& sc, const Key<W>& key) {
+    uint64_t s = key_hash<W>(key) & sc.core_hmask;
+    for (;;) {
+        const int32_t x = sc.core_hidx[s];
+        if (x < 0) return -1;
+        if (key_eq<W>(load_key<W>(sc.core_hkeys + s * W), key)) return x;
+        s = (s + 1) & sc.core_hmask;
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Spawn (Sec. I, step (a)): attempt k of determinant D_i draws an excitation
@@ -139,7 +174,9 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
             const Key<W> key = load_key<W>(st.keys + e * W);
             const V C = st.vals[e];
             const double aC = vabs(C);
-            const bool init = (sc.n_a < 0.0) || (aC > sc.n_a) || key_eq<W>(key, ref);
+            // determinants of the deterministic space count as initiators
+            const bool pcore = sc.ncore > 0 && is_core(st.diag[e]);
+            const bool init = pcore || (sc.n_a < 0.0) || (aC > sc.n_a) || key_eq<W>(key, ref);
             const uint64_t da = key_alpha<W>(key), db = key_beta<W>(key);
             const R4 r = draw<W>(key, sc.t, k, kSpawn, sc.seed, sc.replica);
             Exc x;
@@ -153,6 +190,8 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
                 const R4 r2 = draw<W>(key, sc.t, k, kSpawn2, sc.seed, sc.replica);
                 ok = gen_cs<GEN == 4>(sys, da, db, r, r2, sc.p_single, sc.p_double, sc.p_opp, x);
             }
+            // spawns from the deterministic space into it are part of P^D
+            if (ok && pcore && core_find<W>(sc, make_key<W>(x.ta, x.tb)) >= 0) ok = false;
             if (ok && x.H != 0.0) {
                 const double u = unif(r.x[3]);
                 if constexpr (sizeof(V) == 4) {
@@ -537,27 +576,32 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
             C = in.vals[eb + e];
             d = in.diag[eb + e];
         }
-        const double t1 = d - sc.S;
-        const double t2 = sc.tau * t1;
-        const double f = 1.0 - t2;
-        const double xv = f * (double)C;
-        const double u = unif(draw<W>(key, sc.t, 0, kDeath, sc.seed, sc.replica).x[0]);
         V post;
-        if constexpr (kInt) {
-            const double ax = fabs(xv);
-            const double fl = floor(ax);
-            const double fr = ax - fl;
-            const double nn = fl + (u < fr ? 1.0 : 0.0);
-            if (nn > 2147483000.0) atomicOr(&ctl->flags, kFlagPop);
-            post = (V)(xv < 0.0 ? -nn : nn);
+        if (sc.ncore > 0 && is_core(d)) {
+            // deterministic space: P^D C, diagonal included, unrounded
+            post = (V)sc.core_d[core_index(d)];
         } else {
-            const double ax = fabs(xv);
-            double y = xv;
-            if (ax < sc.c_min && xv != 0.0) {
-                const double pr = ax / sc.c_min;
-                y = (u < pr) ? (xv < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
+            const double t1 = d - sc.S;
+            const double t2 = sc.tau * t1;
+            const double f = 1.0 - t2;
+            const double xv = f * (double)C;
+            const double u = unif(draw<W>(key, sc.t, 0, kDeath, sc.seed, sc.replica).x[0]);
+            if constexpr (kInt) {
+                const double ax = fabs(xv);
+                const double fl = floor(ax);
+                const double fr = ax - fl;
+                const double nn = fl + (u < fr ? 1.0 : 0.0);
+                if (nn > 2147483000.0) atomicOr(&ctl->flags, kFlagPop);
+                post = (V)(xv < 0.0 ? -nn : nn);
+            } else {
+                const double ax = fabs(xv);
+                double y = xv;
+                if (ax < sc.c_min && xv != 0.0) {
+                    const double pr = ax / sc.c_min;
+                    y = (u < pr) ? (xv < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
+                }
+                post = (V)y;
             }
-            post = (V)y;
         }
         const int s = lds_find<W, V>(L, key, key_hash<W>(key), mask, true);
         if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); continue; }
@@ -611,18 +655,26 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
         Key<W> key;
         key.w[0] = k0;
         if constexpr (W == 2) key.w[1] = L.t.key1[s];
+        bool core = false;
+        int64_t ck = 0;
         if (k0 != kEmpty) {
             v = L.t.val[s];
+            if (sc.ncore > 0 && L.t.idx[s] >= 0) {
+                const double dd = in.diag[eb + L.t.idx[s]];
+                if (is_core(dd)) { core = true; ck = core_index(dd); }
+            }
             if constexpr (!kInt) {
                 const double av = fabs((double)v);
-                if (!sc.import_mode && v != 0.0 && av < sc.c_min) {
+                if (!core && !sc.import_mode && v != 0.0 && av < sc.c_min) {
                     const double u = unif(draw<W>(key, sc.t, 0, kAnn, sc.seed, sc.replica).x[0]);
                     const double pr = av / sc.c_min;
                     v = (u < pr) ? (v < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
                 }
             }
         }
-        const bool keep = v != (V)0;
+        // the deterministic space stays at any value; an import keeps every
+        // entry it was given
+        const bool keep = v != (V)0 || core || (sc.import_mode && k0 != kEmpty);
         const int64_t m = keep ? n_attempts(v) : 0;
         int64_t tot;
         const int64_t ex = block_excl_scan<kThreads, int64_t>(keep ? ((1LL << 40) | m) : 0, tot, L.sh64);
@@ -636,6 +688,7 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
             store_key<W>(out.keys + o * W, key);
             out.vals[o] = v;
             out.mpre[o] = (int32_t)mp;
+            if (core) sc.core_c[ck] = (double)v;
             const int oi = L.t.idx[s];
             const uint64_t ka = key_alpha<W>(key), kb = key_beta<W>(key);
             if (oi >= 0) {
@@ -1150,6 +1203,114 @@ __global__ void k_build_jk(SysView sys, double* J, double* K, double* X, double*
         X[i] = j - k;
         SK[i] = sqrt(fabs(k));
         if (p == q) { U[p] = eri(sys, p, p, p, p); Hd[p] = sys.h1[i]; }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic space set-up and its per-step product.
+// ---------------------------------------------------------------------------
+// Open-addressing table of the space's determinants (hidx preset to -1).
+template <int W>
+__global__ void k_core_hash(const uint64_t* __restrict__ keys, int64_t n, uint64_t* __restrict__ hkeys,
+                            int32_t* __restrict__ hidx, uint64_t mask) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const Key<W> key = load_key<W>(keys + k * W);
+        uint64_t s = key_hash<W>(key) & mask;
+        while (atomicCAS(&hidx[s], -1, (int32_t)k) != -1) s = (s + 1) & mask;
+        store_key<W>(hkeys + s * W, key);
+    }
+}
+
+// Row k of H^D: the nonzero H_kj = <D_k|H|D_j>, j != k, in ascending j (one
+// workgroup per row, positions by block scans).  With col == nullptr only
+// the counts are written.
+template <int W>
+__global__ __launch_bounds__(kThreads) void k_core_rows(SysView sys, const uint64_t* __restrict__ keys, int64_t n,
+                                                        const int64_t* __restrict__ rowp, int32_t* __restrict__ col,
+                                                        double* __restrict__ val, int64_t* __restrict__ cnt) {
+    __shared__ int64_t sh[kThreads / 64];
+    for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+        const Key<W> kk = load_key<W>(keys + k * W);
+        const uint64_t ak = key_alpha<W>(kk), bk = key_beta<W>(kk);
+        int64_t base = 0;
+        for (int64_t j0 = 0; j0 < n; j0 += kThreads) {
+            const int64_t j = j0 + threadIdx.x;
+            double h = 0.0;
+            if (j < n && j != k) {
+                const Key<W> kj = load_key<W>(keys + j * W);
+                const uint64_t aj = key_alpha<W>(kj), bj = key_beta<W>(kj);
+                if (popc64(ak ^ aj) + popc64(bk ^ bj) <= 4) h = h_offdiag(sys, aj, bj, ak, bk);
+            }
+            const bool nz = h != 0.0;
+            int64_t tot;
+            const int64_t ex = block_excl_scan<kThreads, int64_t>(nz ? 1 : 0, tot, sh);
+            if (nz && col) {
+                col[rowp[k] + base + ex] = (int32_t)j;
+                val[rowp[k] + base + ex] = h;
+            }
+            base += tot;
+        }
+        if (!col && threadIdx.x == 0) cnt[k] = base;
+    }
+}
+
+// H_kk - H_00 of the space's determinants (the same sum as the store's).
+template <int W>
+__global__ void k_core_diag(SysView sys, const uint64_t* __restrict__ keys, int64_t n, double h00,
+                            double* __restrict__ cdiag) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const Key<W> key = load_key<W>(keys + k * W);
+        const double h = h_diag(sys, key_alpha<W>(key), key_beta<W>(key));
+        cdiag[k] = h - h00;
+    }
+}
+
+// Mark the space's determinants in the store (tag the diagonal slot) and
+// read their coefficients into c; a determinant not found is counted.
+template <int W, class V>
+__global__ void k_core_tag(Store<V> st, int R, int B, const uint64_t* __restrict__ keys, int64_t n,
+                           double* __restrict__ c, unsigned long long* __restrict__ missing) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const Key<W> key = load_key<W>(keys + k * W);
+        const int b = (int)bucket_of(key_hash<W>(key), (uint32_t)B);
+        const int cnt = st.count[b];
+        bool found = false;
+        for (int e = 0; e < cnt; ++e) {
+            const int64_t x = (int64_t)b * R + e;
+            if (key_eq<W>(load_key<W>(st.keys + x * W), key)) {
+                st.diag[x] = core_tag(k);
+                c[k] = (double)st.vals[x];
+                found = true;
+                break;
+            }
+        }
+        if (!found) atomicAdd(missing, 1ULL);
+    }
+}
+
+// (P^D C)_k = (1 - dtau (H_kk - S)) C_k - dtau sum_{j != k} H_kj C_j, one
+// wave per row (CSR), the row sum reduced across the wave in a fixed order.
+__global__ __launch_bounds__(kThreads) void k_core_spmv(const int64_t* __restrict__ rowp,
+                                                        const int32_t* __restrict__ col,
+                                                        const double* __restrict__ val,
+                                                        const double* __restrict__ cdiag,
+                                                        const double* __restrict__ c, double* __restrict__ d,
+                                                        int64_t n, double tau, double S) {
+    const int64_t row = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+    if (row >= n) return;  // whole waves
+    double acc = 0.0;
+    for (int64_t q = rowp[row] + lane_id(); q < rowp[row + 1]; q += 64) {
+        const double x = val[q] * c[col[q]];
+        acc = acc + x;
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0) {
+        const double t1 = cdiag[row] - S;
+        const double t2 = tau * t1;
+        const double f = 1.0 - t2;
+        const double xv = f * c[row];
+        const double y = tau * acc;
+        d[row] = xv - y;
     }
 }
 

@@ -79,7 +79,7 @@ EXPORTS = ["fciqmc_params_default", "fciqmc_load_integrals", "fciqmc_init", "fci
            "fciqmc_batch_size", "fciqmc_batch_step", "fciqmc_batch_tune", "fciqmc_batch_profile",
            "fciqmc_batch_free", "fciqmc_estimate_bytes", "fciqmc_server_create",
            "fciqmc_server_submit", "fciqmc_server_poll", "fciqmc_server_info",
-           "fciqmc_server_clock", "fciqmc_server_free",
+           "fciqmc_server_clock", "fciqmc_server_free", "fciqmc_set_core", "fciqmc_get_core",
            "fciqmc_free_run", "fciqmc_free_system", "fciqmc_last_error"]
 
 _lib = None
@@ -111,6 +111,8 @@ def lib():
         L.fciqmc_energy.argtypes = [vp, C.POINTER(EnergyReport)]
         L.fciqmc_get_walkers.argtypes = [vp, pu64, pdbl, i64, C.POINTER(i64)]
         L.fciqmc_set_walkers.argtypes = [vp, pu64, pdbl, i64]
+        L.fciqmc_set_core.argtypes = [vp, i64, C.POINTER(i64)]
+        L.fciqmc_get_core.argtypes = [vp, pu64, i64, C.POINTER(i64), C.POINTER(i64)]
         L.fciqmc_get_checkpoint.argtypes = [vp, C.POINTER(Checkpoint)]
         L.fciqmc_set_checkpoint.argtypes = [vp, C.POINTER(Checkpoint)]
         L.fciqmc_matrix_elements.argtypes = [vp, pu64, pu64, i64, pdbl]
@@ -278,6 +280,24 @@ def fciqmc_set_walkers(run: Run, alpha, beta, vals):
     d = np.ascontiguousarray(np.stack([a, b], axis=1).reshape(-1))
     v = np.ascontiguousarray(vals, dtype=np.float64)
     _check(lib().fciqmc_set_walkers(run.handle, _p(d, C.c_uint64), _p(v, C.c_double), len(v)))
+
+
+def fciqmc_set_core(run: Run, n_core: int) -> int:
+    """Semi-stochastic projection: the n_core most populated determinants
+    become the deterministic space; returns its size."""
+    n = C.c_int64(0)
+    _check(lib().fciqmc_set_core(run.handle, int(n_core), C.byref(n)))
+    return n.value
+
+
+def fciqmc_get_core(run: Run):
+    """(alpha masks, beta masks, nonzeros of H^D) of the deterministic space."""
+    n, nnz = C.c_int64(0), C.c_int64(0)
+    _check(lib().fciqmc_get_core(run.handle, None, 0, C.byref(n), C.byref(nnz)))
+    d = np.zeros(2 * max(n.value, 1), dtype=np.uint64)
+    _check(lib().fciqmc_get_core(run.handle, _p(d, C.c_uint64), n.value, None, None))
+    d = d[:2 * n.value].reshape(-1, 2)
+    return d[:, 0].copy(), d[:, 1].copy(), nnz.value
 
 
 def fciqmc_get_checkpoint(run: Run) -> dict:
