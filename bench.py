@@ -474,6 +474,55 @@ def measure_generators(F, np, torch, n_dets, reps):
     return {"config": dict(GEN_DESC, dets=n_dets, walkers=nw), "generators": out}
 
 
+SEMI_DESC = {"workload": "synthetic_molecule_8e8o_4900dets_real_walkers",
+             "walkers_target": 2e4, "tau": 0.01, "initiator": "off", "walkers": "real",
+             "c_min": 1.0, "shift_damping": 0.05, "det_bits": 64}
+
+
+def measure_semistoch(F, np, torch, steps, n_core):
+    """Statistical efficiency of the semi-stochastic projection: one
+    equilibrated population of the 8-orbital molecule (real walkers, 2e4),
+    continued for the same number of steps fully stochastically and with its
+    n_core most populated determinants deterministic; the blocked errors and
+    the time per step give the efficiency ratio (err^2 x time)."""
+    from paper_2006_14956_amd import inputs
+    s = inputs.molecule_8o8e()
+    sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
+    pd = dict(tau=0.01, walker_target=2e4, mode=F.MODE_REAL, c_min=1.0, seed=1, shift_damping=0.05,
+              n_initial=100.0)
+    base = F.fciqmc_init(sysd, F.fciqmc_params_default(**pd))
+    F.fciqmc_step(base, 3000)
+    a, b, v = F.fciqmc_get_walkers(base)
+    ck = F.fciqmc_get_checkpoint(base)
+    F.fciqmc_free_run(base)
+    out = {"config": dict(SEMI_DESC, steps=steps, n_core=n_core, equilibration_steps=3000)}
+    for name, nc in (("stochastic", 0), ("semi_stochastic", n_core)):
+        run = F.fciqmc_init(sysd, F.fciqmc_params_default(**dict(pd, seed=2)))
+        F.fciqmc_set_walkers(run, a, b, v)
+        F.fciqmc_set_checkpoint(run, ck["iter"], ck["shift"], ck["vary_shift"], ck["last_update_iter"],
+                                ck["last_update_nw"])
+        got = F.fciqmc_set_core(run, nc) if nc else 0
+        nnz = F.fciqmc_get_core(run)[2] if nc else 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F.fciqmc_step(run, steps, as_array=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        e = F.fciqmc_energy(run)
+        out[name] = {"n_core": got, "h_core_nonzeros": nnz, "ms_per_step": 1e3 * wall / steps,
+                     "e_proj": e["e_proj"], "e_proj_err": e["e_proj_err"], "shift": e["shift"],
+                     "shift_err": e["shift_err"], "n_samples": e["n_samples"]}
+        log(f"[semistoch] {name}: core {got} ({nnz} nonzeros), {1e3 * wall / steps:.4f} ms/step, "
+            f"E_proj {e['e_proj']:.6f} +- {e['e_proj_err']:.2e}, shift {e['shift']:.6f} +- {e['shift_err']:.2e}")
+        F.fciqmc_free_run(run)
+    F.fciqmc_free_system(sysd)
+    A, B = out["stochastic"], out["semi_stochastic"]
+    for k in ("e_proj", "shift"):
+        if B[k + "_err"] > 0:
+            out[k + "_efficiency_gain"] = (A[k + "_err"] ** 2 * A["ms_per_step"]) / (B[k + "_err"] ** 2 * B["ms_per_step"])
+    return out
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -538,6 +587,11 @@ def main():
     ap.add_argument("--generators", type=int, default=400000, metavar="DETS",
                     help="determinants of the fixed population on which the excitation "
                          "generators are compared (0 to skip)")
+    ap.add_argument("--semistoch", type=int, default=20000, metavar="STEPS",
+                    help="steps of the semi-stochastic comparison (0 to skip)")
+    ap.add_argument("--semistoch-core", type=int, default=500)
+    ap.add_argument("--semistoch-only", action="store_true",
+                    help="only run the semi-stochastic comparison")
     ap.add_argument("--generators-only", action="store_true",
                     help="only run the generator comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -565,6 +619,10 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.semistoch_only:
+        print(json.dumps(measure_semistoch(F, np, torch, args.semistoch or 20000, args.semistoch_core)),
+              flush=True)
+        return
     if args.generators_only:
         print(json.dumps(measure_generators(F, np, torch, args.generators or 400000, 3)), flush=True)
         return
@@ -618,6 +676,10 @@ def main():
     if args.generators:
         generators = measure_generators(F, np, torch, args.generators, 3)
 
+    semistoch = None
+    if args.semistoch:
+        semistoch = measure_semistoch(F, np, torch, args.semistoch, args.semistoch_core)
+
     batched = None
     if args.batched_steps:
         batched = measure_batched(F, np, args.batched_steps, args.batched_warmup, args.batched_grow,
@@ -647,6 +709,7 @@ def main():
         "cpu_baseline": cpu,
         "second_workload": second,
         "generators": generators,
+        "semistoch": semistoch,
         "batched": batched,
         "served": served,
     }
