@@ -80,6 +80,12 @@ def lib():
         L.orc_run_core_size.restype = i64
         L.orc_run_core_size.argtypes = [vp]
         L.orc_run_get_core.argtypes = [vp, pu64, pu64]
+        L.orc_run_collect_rejected.argtypes = [vp, C.c_int]
+        L.orc_pair_pt2.restype = dbl
+        L.orc_pair_pt2.argtypes = [vp, vp]
+        L.orc_run_rejected_size.restype = i64
+        L.orc_run_rejected_size.argtypes = [vp]
+        L.orc_run_get_rejected.argtypes = [vp, pu64, pu64, pdbl]
         _lib = L
     return _lib
 
@@ -281,8 +287,30 @@ class Run:
         lib().orc_run_get_core(self.ptr, _p(a, C.c_uint64), _p(b, C.c_uint64))
         return a, b
 
+    def collect_rejected(self, on=True):
+        """Record the discarded spawns of each step (for the PT2 correction)."""
+        lib().orc_run_collect_rejected(self.ptr, int(bool(on)))
+
+    def rejected_size(self):
+        return lib().orc_run_rejected_size(self.ptr)
+
+    def rejected(self):
+        """(alpha, beta, weight) of the last step's discarded targets."""
+        n = lib().orc_run_rejected_size(self.ptr)
+        a = np.zeros(n, dtype=np.uint64)
+        b = np.zeros(n, dtype=np.uint64)
+        w = np.zeros(n)
+        lib().orc_run_get_rejected(self.ptr, _p(a, C.c_uint64), _p(b, C.c_uint64), _p(w, C.c_double))
+        return a, b, w
+
     def generate(self, a, b, t, k):
         ta, tb, pg, H = C.c_uint64(), C.c_uint64(), C.c_double(), C.c_double()
         ok = lib().orc_generate(self.ptr, int(a), int(b), int(t), int(k), C.byref(ta),
                                 C.byref(tb), C.byref(pg), C.byref(H))
         return (ta.value, tb.value, pg.value, H.value) if ok else None
+
+
+def pair_pt2(r1: Run, r2: Run) -> float:
+    """Epstein-Nesbet correction from the spawns both replicas discarded in
+    their last step (each must collect its rejected spawns)."""
+    return lib().orc_pair_pt2(r1.ptr, r2.ptr)

@@ -536,6 +536,14 @@ typedef struct {
     int64_t nc;
     double *hcore;      /* nc x nc: H_kj for k != j (dense; the diagonal is unused) */
     double *core_diag;  /* H_kk - H_00 */
+    /* discarded spawns of the last step (Sec. "Perturbative correction"):
+     * targets unoccupied at tau that no initiator spawn reached, with the
+     * summed weight spawned onto them; ascending */
+    int collect_rej;
+    det_t *rej;
+    double *rej_w;
+    int64_t nrej;
+    double S_step;      /* shift used in the last step */
 } orc_run;
 
 static int ent_cmp(const void *x, const void *y)
@@ -601,6 +609,7 @@ void orc_run_free(orc_run *r)
 {
     if (!r) return;
     core_clear(r);
+    free(r->rej); free(r->rej_w);
     free(r->list);
     free(r->nw_ring);
     free(r);
@@ -734,6 +743,42 @@ int64_t orc_run_core_size(const orc_run *r) { return r->nc; }
 void orc_run_get_core(const orc_run *r, uint64_t *a, uint64_t *b)
 {
     for (int64_t k = 0; k < r->nc; ++k) { a[k] = r->core[k].a; b[k] = r->core[k].b; }
+}
+
+void orc_run_collect_rejected(orc_run *r, int on) { r->collect_rej = on; }
+
+/* Epstein-Nesbet second-order correction from the spawns discarded on both
+ * replicas in their last step (Sec. "Perturbative correction", Eq.
+ * (pt2_correction)):
+ *   dE2 = 1/dtau^2 sum_j S_j^1 S_j^2 / (E_0 - H_jj)
+ * over the determinants j rejected by both, S_j^r the weight spawned onto j
+ * in replica r.  Reading: E_0 is the mean of the two replicas' shifts in
+ * that step; energies relative to H_00 (E_0 - H_jj = S - (H_jj - H_00)). */
+double orc_pair_pt2(const orc_run *r1, const orc_run *r2)
+{
+    double e0 = (r1->S_step + r2->S_step) / 2.0;
+    double tau2 = r1->p.tau * r1->p.tau;
+    double acc = 0.0;
+    int64_t x = 0, y = 0;
+    while (x < r1->nrej && y < r2->nrej) {
+        int c = det_cmp(r1->rej[x], r2->rej[y]);
+        if (c < 0) { ++x; continue; }
+        if (c > 0) { ++y; continue; }
+        double dj = orc_hdiag_det(r1->s, r1->rej[x]) - r1->h00;
+        double num = r1->rej_w[x] * r2->rej_w[y];
+        double den = e0 - dj;
+        double q = num / den;
+        acc = acc + q;
+        ++x; ++y;
+    }
+    return acc / tau2;
+}
+
+int64_t orc_run_rejected_size(const orc_run *r) { return r->nrej; }
+
+void orc_run_get_rejected(const orc_run *r, uint64_t *a, uint64_t *b, double *w)
+{
+    for (int64_t x = 0; x < r->nrej; ++x) { a[x] = r->rej[x].a; b[x] = r->rej[x].b; w[x] = r->rej_w[x]; }
 }
 
 /* Stochastic compression to C_min (Sec. I, the compressed storage rule):
@@ -881,6 +926,14 @@ int orc_run_step(orc_run *r, orc_stats *st)
         free(at);
     }
 
+    if (r->collect_rej) {
+        free(r->rej); free(r->rej_w);
+        r->rej = (det_t *)malloc(sizeof(det_t) * (nrec > 0 ? nrec : 1));
+        r->rej_w = (double *)malloc(sizeof(double) * (nrec > 0 ? nrec : 1));
+        r->nrej = 0;
+    }
+    r->S_step = r->S;
+
     /* (c) annihilation.  Sum all contributions per target.  Initiator rule
      * (Sec. I): matrix elements between non-initiators and determinants with
      * C(tau) = 0 are zeroed, i.e. a target unoccupied at tau only receives the
@@ -898,12 +951,18 @@ int orc_run_step(orc_run *r, orc_stats *st)
     for (int64_t x = 0; x < nrec;) {
         int64_t y = x;
         double sum_all = 0.0, sum_init = 0.0;
+        int any_init = 0;
         while (y < nrec && det_eq(recs[y].r.d, recs[x].r.d)) {
             sum_all = sum_all + recs[y].r.v;
-            if (recs[y].r.init) sum_init = sum_init + recs[y].r.v;
+            if (recs[y].r.init) { sum_init = sum_init + recs[y].r.v; any_init = 1; }
             y++;
         }
         int64_t at = find(r->list, r->n, recs[x].r.d);
+        if (r->collect_rej && at < 0 && !any_init) {
+            r->rej[r->nrej] = recs[x].r.d;
+            r->rej_w[r->nrej] = sum_all;
+            r->nrej++;
+        }
         if (at >= 0) {
             next[at].v = next[at].v + sum_all;
         } else if (sum_init != 0.0) {

@@ -583,6 +583,63 @@ def test_semistochastic_one_step_expectation(oracle_mod, na):
         assert abs(mean[k] - expect[k]) <= 1e-12 * max(1.0, abs(expect[k]))
 
 
+def _pt2_setup(oracle_mod, na):
+    s = inputs.synthetic_molecule(5, 2, 2, seed=21, rank=8)
+    osys = oracle_mod.System.from_inputs(s)
+    dets = brute.basis(5, 2, 2)
+    rng = np.random.default_rng(4)
+    pick = rng.choice(np.arange(1, len(dets)), size=12, replace=False)
+    C = np.zeros(len(dets))
+    C[pick] = rng.integers(1, 9, size=12) * rng.choice([-1, 1], size=12)
+    return osys, dets, pick, C
+
+
+def _pt2_pair(oracle_mod, osys, dets, pick, C, na, seed, tau, S):
+    ref = dets[0]   # unoccupied: no determinant counts as an initiator by being the reference
+    runs = []
+    for rep in (0, 1):
+        r = oracle_mod.Run(osys, ref=ref, tau=tau, target=1e12, n_a=na, seed=seed, replica=rep)
+        r.set_walkers([dets[i][0] for i in pick], [dets[i][1] for i in pick], C[pick])
+        r.set_state(0, S, 1, 0, 1.0)
+        r.collect_rejected(True)
+        r.step()
+        runs.append(r)
+    return oracle_mod.pair_pt2(runs[0], runs[1]), runs
+
+
+def test_pt2_expectation_is_epstein_nesbet(oracle_mod):
+    """Sec. "Perturbative correction", Eq. (pt2_correction): with no parent an
+    initiator, every spawn onto an unoccupied determinant is discarded on
+    both replicas, independent replicas give E[S^1 S^2] = dtau^2
+    <j|H|C>^2, so the mean of dE2 over streams is the Epstein-Nesbet sum
+    sum_{j unoccupied} <j|H|C>^2 / (E_0 - H_jj) (energies relative to H_00,
+    E_0 the shift)."""
+    osys, dets, pick, C = _pt2_setup(oracle_mod, 1e9)
+    tau, S = 0.05, -1.5
+    H = brute.oracle_dense_h(osys, dets)
+    h00 = osys.hdiag(*dets[0])
+    occ = set(int(i) for i in pick)
+    HC = H @ C
+    want = sum(HC[j] ** 2 / (S - (H[j, j] - h00)) for j in range(len(dets)) if j not in occ)
+    # the discarded targets are exactly the unoccupied determinants that
+    # received spawns, with their summed weight
+    _, runs = _pt2_pair(oracle_mod, osys, dets, pick, C, 1e9, 699, tau, S)
+    ra, rb, rw = runs[0].rejected()
+    assert len(ra) > 0 and not ({(int(x), int(y)) for x, y in zip(ra, rb)} & {dets[i] for i in occ})
+    xs = np.array([_pt2_pair(oracle_mod, osys, dets, pick, C, 1e9, 700 + k, tau, S)[0]
+                   for k in range(8000)])
+    se = xs.std() / np.sqrt(len(xs))
+    assert abs(xs.mean() - want) < 5 * se, (xs.mean(), want, se)
+    assert abs(want) > 10 * se   # the test resolves the correction
+
+
+def test_pt2_vanishes_without_initiator_rule(oracle_mod):
+    """With the initiator rule off no spawn is discarded, so dE2 = 0."""
+    osys, dets, pick, C = _pt2_setup(oracle_mod, -1.0)
+    e2, runs = _pt2_pair(oracle_mod, osys, dets, pick, C, -1.0, 11, 0.05, -1.5)
+    assert e2 == 0.0 and runs[0].rejected_size() == 0
+
+
 def test_projected_energy_of_eigenvector(oracle_mod):
     """E_Ref is exact for an eigenstate (Eq. proje)."""
     s = inputs.synthetic_molecule(6, 3, 3, seed=5)
