@@ -60,6 +60,7 @@ typedef struct fciqmc_system fciqmc_system;
 typedef struct fciqmc_run fciqmc_run;
 typedef struct fciqmc_batch fciqmc_batch;
 typedef struct fciqmc_server fciqmc_server;
+typedef struct fciqmc_pair fciqmc_pair;
 
 /* Parameters of one walker population.  fciqmc_params_default() fills every
  * field; callers then override what they need. */
@@ -313,6 +314,33 @@ int fciqmc_server_info(const fciqmc_server *srv, int64_t ticket, fciqmc_request_
 double fciqmc_server_clock(const fciqmc_server *srv);
 /* Release every running solve and the server (systems stay the caller's). */
 void fciqmc_server_free(fciqmc_server *srv);
+
+/* ---- Replica pairs and the PT2 correction (Sec. "Perturbative correction",
+ * Eq. (pt2_correction)) ----
+ * Two runs of one system with independent random streams (different
+ * replica_id or seed), the same time step, determinant layout and reference,
+ * stepped in lockstep.  In each step a run records its discarded spawns: the
+ * non-initiator spawns onto determinants unoccupied at tau that no initiator
+ * spawn reached.  Over the determinants both replicas discarded,
+ *   dE2 = 1/dtau^2 sum_j S_j^1 S_j^2 / (E_0 - H_jj),
+ * S_j^r the weight replica r spawned onto j, E_0 the mean of the two shifts
+ * used in that step.  The correction applies to a variational energy of the
+ * initiator approximation (not computed here).  Creating a pair gives both
+ * runs the same bucket count and fixes it (a store that still outgrows it
+ * skips that step's dE2 and both are re-bucketed); a run in a pair cannot
+ * join a batch or another pair, is stepped through fciqmc_pair_step only,
+ * and freeing it detaches it (the pair then returns ESTATE).
+ * fciqmc_pair_step: n_steps lockstep steps; stats1/stats2 (host, n_steps
+ * entries) and de2 (host, n_steps doubles, NaN for a skipped step) may be
+ * NULL.  EOVERFLOW if one bucket holds more than 1536 distinct discarded
+ * targets (use more buckets).
+ * fciqmc_pair_pt2: mean and blocked error of dE2 over the pair's steps from
+ * number `skip` on (NaN steps left out); *n receives the steps used. */
+int fciqmc_pair_create(fciqmc_run *r1, fciqmc_run *r2, fciqmc_pair **out);
+int fciqmc_pair_step(fciqmc_pair *pair, int n_steps, fciqmc_step_stats *stats1,
+                     fciqmc_step_stats *stats2, double *de2);
+int fciqmc_pair_pt2(const fciqmc_pair *pair, int64_t skip, double *mean, double *err, int64_t *n);
+void fciqmc_pair_free(fciqmc_pair *pair);
 
 void fciqmc_free_run(fciqmc_run *run);
 void fciqmc_free_system(fciqmc_system *sys);

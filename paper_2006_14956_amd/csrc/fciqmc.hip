@@ -220,6 +220,11 @@ struct EngineBase {
     virtual int64_t core_size() const = 0;
     virtual int64_t core_nnz() const = 0;
     virtual const std::vector<uint64_t>& core_dets() const = 0;
+    // discarded spawns of each step, kept for a replica pair's PT2 correction
+    virtual int set_collect(bool on) = 0;
+    virtual void* rej_records() const = 0;
+    virtual int64_t* rej_offsets() const = 0;
+    virtual int32_t* rej_counts() const = 0;
 };
 
 // Largest deterministic space: H^D is built by testing all N_D^2 pairs.
@@ -303,6 +308,12 @@ template <int W, class V> struct Engine : EngineBase {
     int32_t* core_col = nullptr;
     double* core_val = nullptr;
     unsigned long long* core_missing = nullptr;
+    // discarded spawns of the last step (replica-pair PT2): records laid out
+    // like the slabs, per-bucket start and count
+    bool keep_rej = false;
+    Rec<W, V>* rej = nullptr;
+    int64_t* rej_off = nullptr;
+    int32_t* rej_cnt = nullptr;
     hipEvent_t ev[2][kKernels + 1]{};
     double kms[kKernels]{};
     int64_t klaunch = 0;
@@ -397,6 +408,14 @@ template <int W, class V> struct Engine : EngineBase {
             CHECK(dalloc(arena, &fpos, (size_t)B * R));
             CHECK(dalloc(arena, &fcnt, (size_t)B));
         }
+        if (keep_rej) CHECK(alloc_rej_index());
+        return 0;
+    }
+    int alloc_rej_index() {
+        CHECK(dalloc(arena, &rej_off, (size_t)B));
+        CHECK(dalloc(arena, &rej_cnt, (size_t)B));
+        HIP_OK(hipMemsetAsync(rej_off, 0, sizeof(int64_t) * B, stream));
+        HIP_OK(hipMemsetAsync(rej_cnt, 0, sizeof(int32_t) * B, stream));
         return 0;
     }
     void free_buckets() {
@@ -405,6 +424,8 @@ template <int W, class V> struct Engine : EngineBase {
         arena.release(scount); arena.release(soff);
         arena.release(rel); arena.release(need_b); arena.release(recs_b); arena.release(part);
         rel = nullptr; need_b = nullptr; recs_b = nullptr; part = nullptr;
+        arena.release(rej_off); arena.release(rej_cnt);
+        rej_off = nullptr; rej_cnt = nullptr;
         arena.release(nw_b); arena.release(en_b);
         arena.release(fpos); arena.release(fcnt);
         scount = nullptr; soff = nullptr; nw_b = en_b = nullptr;
@@ -417,6 +438,11 @@ template <int W, class V> struct Engine : EngineBase {
         rec2 = nullptr;
         cap = c + c / 4;
         CHECK(dalloc(arena, &rec2, (size_t)cap));
+        if (keep_rej) {
+            arena.release(rej);
+            rej = nullptr;
+            CHECK(dalloc(arena, &rej, (size_t)cap));
+        }
         return 0;
     }
     int ensure_stage(long long c) {
@@ -470,6 +496,11 @@ template <int W, class V> struct Engine : EngineBase {
             sc.core_hkeys = core_hkeys;
             sc.core_hidx = core_hidx;
             sc.core_hmask = core_hmask;
+        }
+        if (keep_rej) {
+            sc.rej = rej;
+            sc.rej_off = rej_off;
+            sc.rej_cnt = rej_cnt;
         }
         return sc;
     }
@@ -710,6 +741,22 @@ template <int W, class V> struct Engine : EngineBase {
         ncore = nc;
         return tag_core();
     }
+    int set_collect(bool on) override {
+        if (on == keep_rej) return 0;
+        CHECK(discard_pending());
+        if (!on) {
+            arena.release(rej); arena.release(rej_off); arena.release(rej_cnt);
+            rej = nullptr; rej_off = nullptr; rej_cnt = nullptr;
+            keep_rej = false;
+            return 0;
+        }
+        keep_rej = true;
+        CHECK(dalloc(arena, &rej, (size_t)std::max<long long>(cap, 1)));
+        return alloc_rej_index();
+    }
+    void* rej_records() const override { return rej; }
+    int64_t* rej_offsets() const override { return rej_off; }
+    int32_t* rej_counts() const override { return rej_cnt; }
     int64_t core_size() const override { return ncore; }
     int64_t core_nnz() const override { return nnz; }
     const std::vector<uint64_t>& core_dets() const override { return core_host; }
@@ -937,6 +984,7 @@ struct fciqmc_run {
     std::vector<fciqmc_step_stats> hist;
     fciqmc_batch* batch = nullptr;  // set while the run steps inside a batch
     int batch_slot = -1;            // its position among the batch's members
+    fciqmc_pair* pair = nullptr;    // set while the run is one replica of a pair
     ~fciqmc_run() {
         eng.reset();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -1496,9 +1544,12 @@ int fciqmc_init(const fciqmc_system* csys, const fciqmc_params* p, void* stream,
     return 0;
 }
 
+void pair_detach(fciqmc_run* run);
+
 void fciqmc_free_run(fciqmc_run* run) {
     if (!run) return;
     if (run->batch) batch_detach(run->batch, run);
+    if (run->pair) pair_detach(run);
     delete run;
 }
 
@@ -1517,6 +1568,7 @@ int fciqmc_batch_add(fciqmc_batch* b, fciqmc_run* run) {
     if (run->batch) return fail(FCIQMC_EINVAL, "the run already belongs to a batch");
     if (run->eng->core_size() > 0)
         return fail(FCIQMC_EINVAL, "a run with a deterministic space is stepped alone");
+    if (run->pair) return fail(FCIQMC_EINVAL, "a replica of a pair is stepped by its pair");
     HIP_OK(hipStreamSynchronize(run->stream));
     const int k = run->eng->kind();
     if (!b->group[k]) b->group[k] = make_group(k);
@@ -1890,6 +1942,160 @@ int fciqmc_matrix_elements(const fciqmc_system* sys, const uint64_t* di, const u
     HIP_OK(hipMemcpy(out, o, sizeof(double) * n, hipMemcpyDeviceToHost));
     tmp.clear();
     return 0;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Replica pairs and the second-order correction from discarded spawns
+// (Sec. "Perturbative correction", Eq. (pt2_correction)).
+// ---------------------------------------------------------------------------
+struct fciqmc_pair {
+    fciqmc_run* r[2] = {nullptr, nullptr};
+    bool fixed[2] = {false, false};  // the runs' own bucket-growth setting, restored on free
+    Arena arena;
+    double* part = nullptr;  // per-bucket partial sums
+    int64_t part_n = 0;
+    double* sum = nullptr;
+    unsigned* err = nullptr;
+    std::vector<double> de2;  // one value per paired step (NaN: not evaluated)
+    ~fciqmc_pair() { arena.clear(); }
+};
+
+void pair_detach(fciqmc_run* run) {
+    fciqmc_pair* p = run->pair;
+    for (auto& x : p->r)
+        if (x == run) x = nullptr;
+    run->pair = nullptr;
+}
+
+namespace {
+template <int W, class V> void launch_pt2(fciqmc_pair* p, int B, double e0, hipStream_t s) {
+    const EngineBase* a = p->r[0]->eng.get();
+    const EngineBase* b = p->r[1]->eng.get();
+    hipLaunchKernelGGL((k_pt2<W, V>), dim3((unsigned)std::min(B, 4096)), dim3(kThreads), 0, s,
+                       p->r[0]->sys->view(), (const Rec<W, V>*)a->rej_records(), a->rej_offsets(),
+                       a->rej_counts(), (const Rec<W, V>*)b->rej_records(), b->rej_offsets(), b->rej_counts(), B,
+                       e0, p->r[0]->h00, p->part, p->err);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, s, p->part, B, p->sum);
+}
+}  // namespace
+
+extern "C" {
+
+int fciqmc_pair_create(fciqmc_run* r1, fciqmc_run* r2, fciqmc_pair** out) {
+    if (!r1 || !r2 || !out || !r1->eng || !r2->eng) return fail(FCIQMC_EINVAL, "null argument");
+    *out = nullptr;
+    if (r1 == r2) return fail(FCIQMC_EINVAL, "a pair needs two runs");
+    for (fciqmc_run* r : {r1, r2}) {
+        if (r->batch) return fail(FCIQMC_ESTATE, "a run in a batch cannot join a pair");
+        if (r->pair) return fail(FCIQMC_ESTATE, "the run already belongs to a pair");
+    }
+    if (r1->sys != r2->sys || r1->eng->kind() != r2->eng->kind() || r1->p.tau != r2->p.tau ||
+        r1->ref_a != r2->ref_a || r1->ref_b != r2->ref_b)
+        return fail(FCIQMC_EINVAL, "replicas need the same system, layout, time step and reference");
+    if (r1->p.seed == r2->p.seed && r1->p.replica_id == r2->p.replica_id)
+        return fail(FCIQMC_EINVAL, "replicas need different random streams (replica_id or seed)");
+    std::unique_ptr<fciqmc_pair> p(new fciqmc_pair());
+    CHECK(dalloc(p->arena, &p->sum, 1));
+    CHECK(dalloc(p->arena, &p->err, 1));
+    const int64_t B = std::max(r1->eng->buckets(), r2->eng->buckets());
+    fciqmc_run* rr[2] = {r1, r2};
+    for (int i = 0; i < 2; ++i) {
+        p->fixed[i] = rr[i]->eng->fixed_b;
+        CHECK(rr[i]->eng->rebucket((int)B));
+        rr[i]->eng->fixed_b = true;
+        CHECK(rr[i]->eng->set_collect(true));
+        p->r[i] = rr[i];
+        rr[i]->pair = p.get();
+    }
+    *out = p.release();
+    return 0;
+}
+
+int fciqmc_pair_step(fciqmc_pair* p, int n_steps, fciqmc_step_stats* stats1, fciqmc_step_stats* stats2,
+                     double* de2) {
+    if (!p) return fail(FCIQMC_EINVAL, "null argument");
+    if (!p->r[0] || !p->r[1]) return fail(FCIQMC_ESTATE, "a replica of the pair was freed");
+    if (n_steps < 0) return fail(FCIQMC_EINVAL, "n_steps must be >= 0");
+    fciqmc_run* a = p->r[0];
+    fciqmc_run* b = p->r[1];
+    for (int i = 0; i < n_steps; ++i) {
+        const double e0 = (a->S + b->S) / 2.0;  // the shifts this step uses
+        CHECK(fciqmc_step(a, 1, stats1 ? stats1 + i : nullptr));
+        CHECK(fciqmc_step(b, 1, stats2 ? stats2 + i : nullptr));
+        double v = NAN;
+        const int64_t Ba = a->eng->buckets(), Bb = b->eng->buckets();
+        if (Ba == Bb) {
+            const int B = (int)Ba;
+            if (p->part_n < B) {
+                p->arena.release(p->part);
+                p->part = nullptr;
+                CHECK(dalloc(p->arena, &p->part, (size_t)B));
+                p->part_n = B;
+            }
+            HIP_OK(hipStreamSynchronize(b->stream));
+            HIP_OK(hipMemsetAsync(p->err, 0, sizeof(unsigned), a->stream));
+            switch (a->eng->kind()) {
+                case 0: launch_pt2<1, int32_t>(p, B, e0, a->stream); break;
+                case 1: launch_pt2<1, double>(p, B, e0, a->stream); break;
+                case 2: launch_pt2<2, int32_t>(p, B, e0, a->stream); break;
+                default: launch_pt2<2, double>(p, B, e0, a->stream); break;
+            }
+            HIP_OK(hipGetLastError());
+            double sum = 0.0;
+            unsigned e = 0;
+            HIP_OK(hipMemcpyAsync(&sum, p->sum, sizeof(double), hipMemcpyDeviceToHost, a->stream));
+            HIP_OK(hipMemcpyAsync(&e, p->err, sizeof(unsigned), hipMemcpyDeviceToHost, a->stream));
+            HIP_OK(hipStreamSynchronize(a->stream));
+            if (e) return fail(FCIQMC_EOVERFLOW, "a bucket holds more discarded targets than its table (%d slots)", kPtSlots);
+            v = sum / (a->p.tau * a->p.tau);
+        } else {
+            // a store outgrew its buckets during the step: this step is not
+            // evaluated, and both use the larger count from the next one
+            const int64_t B = std::max(Ba, Bb);
+            CHECK(a->eng->rebucket((int)B));
+            CHECK(b->eng->rebucket((int)B));
+        }
+        p->de2.push_back(v);
+        if (de2) de2[i] = v;
+    }
+    return 0;
+}
+
+int fciqmc_pair_pt2(const fciqmc_pair* p, int64_t skip, double* mean, double* err, int64_t* n) {
+    if (!p || !mean || !err || !n) return fail(FCIQMC_EINVAL, "null argument");
+    std::vector<double> x;
+    for (size_t i = (size_t)std::max<int64_t>(skip, 0); i < p->de2.size(); ++i)
+        if (!std::isnan(p->de2[i])) x.push_back(p->de2[i]);
+    *n = (int64_t)x.size();
+    *mean = NAN;
+    *err = NAN;
+    if (x.empty()) return 0;
+    if (x.size() < 16) {
+        double m = 0.0;
+        for (double y : x) m += y;
+        *mean = m / (double)x.size();
+        return 0;
+    }
+    double mx, ex, my, r, er;
+    std::vector<double> ones(x.size(), 1.0);
+    blocking(x, ones, mx, ex, my, r, er);
+    *mean = mx;
+    *err = ex;
+    return 0;
+}
+
+void fciqmc_pair_free(fciqmc_pair* p) {
+    if (!p) return;
+    for (int i = 0; i < 2; ++i) {
+        fciqmc_run* r = p->r[i];
+        if (!r) continue;
+        (void)r->eng->set_collect(false);
+        r->eng->fixed_b = p->fixed[i];
+        r->pair = nullptr;
+    }
+    delete p;
 }
 
 }  // extern "C"

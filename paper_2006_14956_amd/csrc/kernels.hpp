@@ -105,6 +105,11 @@ struct StepScalars {
     const uint64_t* core_hkeys;  // open-addressing table of the space: keys (W words a slot)
     const int32_t* core_hidx;    // and indices in the space, -1 for an empty slot
     uint64_t core_hmask;
+    // discarded spawns (replica-pair PT2; rej = nullptr: not collected):
+    // records of bucket b go to rej[rej_off[b] ...], rej_cnt[b] of them
+    void* rej;
+    int64_t* rej_off;
+    int32_t* rej_cnt;
 };
 
 // ---------------------------------------------------------------------------
@@ -366,29 +371,29 @@ template <int W> __device__ __forceinline__ uint64_t lds_load(const uint64_t* p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Find the slot of `key`; insert it if absent and `insert` is set.
-// Returns the slot, -1 if absent (not inserted), -2 if the table is full,
-// -3 if a claimed slot never became readable.
-template <int W, class V>
-__device__ __forceinline__ int lds_find(Lds<W, V>& L, const Key<W>& key, uint64_t h, uint64_t mask,
-                                        bool insert) {
+// Find the slot of `key` in an LDS table T (arrays key0, and key1 for
+// two-word keys); insert it if absent and `insert` is set.  Returns the
+// slot, -1 if absent (not inserted), -2 if the table is full, -3 if a
+// claimed slot never became readable.
+template <int W, class T>
+__device__ __forceinline__ int lds_find(T& tab, const Key<W>& key, uint64_t h, uint64_t mask, bool insert) {
     int s = (int)(h & mask);
     int probes = 0;
     int spins = 0;
     while (true) {
-        uint64_t w0 = lds_load<W>(&L.t.key0[s]);
+        uint64_t w0 = lds_load<W>(&tab.key0[s]);
         if (w0 == kEmpty) {
             if (!insert) return -1;
             if constexpr (W == 1) {
-                const uint64_t old = atomicCAS((unsigned long long*)&L.t.key0[s], kEmpty, key.w[0]);
+                const uint64_t old = atomicCAS((unsigned long long*)&tab.key0[s], kEmpty, key.w[0]);
                 if (old == kEmpty || old == key.w[0]) return s;
                 w0 = old;
             } else {
-                const uint64_t old = atomicCAS((unsigned long long*)&L.t.key0[s], kEmpty, kLocked);
+                const uint64_t old = atomicCAS((unsigned long long*)&tab.key0[s], kEmpty, kLocked);
                 if (old == kEmpty) {
-                    __hip_atomic_store(&L.t.key1[s], key.w[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_store(&tab.key1[s], key.w[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                    __hip_atomic_store(&L.t.key0[s], key.w[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_store(&tab.key0[s], key.w[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     return s;
                 }
                 w0 = old;
@@ -403,7 +408,7 @@ __device__ __forceinline__ int lds_find(Lds<W, V>& L, const Key<W>& key, uint64_
             }
             if (w0 == key.w[0]) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                if (lds_load<W>(&L.t.key1[s]) == key.w[1]) return s;
+                if (lds_load<W>(&tab.key1[s]) == key.w[1]) return s;
             }
         } else {
             if (w0 == key.w[0]) return s;
@@ -603,7 +608,7 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
                 post = (V)y;
             }
         }
-        const int s = lds_find<W, V>(L, key, key_hash<W>(key), mask, true);
+        const int s = lds_find<W>(L.t, key, key_hash<W>(key), mask, true);
         if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); continue; }
         L.t.val[s] = post;
         L.t.idx[s] = e;
@@ -621,12 +626,45 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
 #pragma unroll
         for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
         const bool init = (x.flag & 1u) != 0;
-        const int s = lds_find<W, V>(L, key, key_hash<W>(key), mask, init);
+        const int s = lds_find<W>(L.t, key, key_hash<W>(key), mask, init);
         if (s == -1) continue;
         if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); continue; }
         if (init || L.t.idx[s] >= 0) lds_add<V>(&L.t.val[s], x.v);
     }
     __syncthreads();
+    if (sc.rej != nullptr && !sc.import_mode) {
+        // discarded spawns: non-initiator records whose target is in neither
+        // the population at tau nor the new one (no initiator spawn reached
+        // it), kept in record order in the bucket's region of the buffer
+        Rec<W, V>* rej = static_cast<Rec<W, V>*>(sc.rej);
+        int64_t nb = 0;
+        for (int64_t q0 = 0; q0 < cum[kSub]; q0 += kThreads) {
+            const int64_t q = q0 + threadIdx.x;
+            bool dropped = false;
+            Rec<W, V> x;
+            if (q < cum[kSub]) {
+                int64_t src = 0;
+#pragma unroll
+                for (int j = 0; j < kSub; ++j)
+                    if (q >= cum[j] && q < cum[j + 1]) src = lo[j] + (q - cum[j]);
+                x = rec2[src];
+                if (!(x.flag & 1u)) {
+                    Key<W> key;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
+                    dropped = lds_find<W>(L.t, key, key_hash<W>(key), mask, false) == -1;
+                }
+            }
+            int64_t tot;
+            const int64_t ex = block_excl_scan<kThreads, int64_t>(dropped ? 1 : 0, tot, L.sh64);
+            if (dropped) rej[lo[0] + nb + ex] = x;
+            nb += tot;
+        }
+        if (threadIdx.x == 0) {
+            sc.rej_off[b] = lo[0];
+            sc.rej_cnt[b] = (int32_t)nb;
+        }
+    }
     if (threadIdx.x == 0) {
         // slabs of the next step: this step's counts plus headroom, relative
         // to the bucket's base (set by the post work); counters restart at 0
@@ -1204,6 +1242,96 @@ __global__ void k_build_jk(SysView sys, double* J, double* K, double* X, double*
         SK[i] = sqrt(fabs(k));
         if (p == q) { U[p] = eri(sys, p, p, p, p); Hd[p] = sys.h1[i]; }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Replica-pair PT2 correction (Sec. "Perturbative correction", Eq.
+// (pt2_correction)).  Both replicas use the same bucket count, so a target
+// discarded by both sits in the same bucket of each: one workgroup per
+// bucket sums each replica's discarded weight per target in LDS and adds
+// S^1 S^2 / (E_0 - (H_jj - H_00)) over the targets both discarded.
+// ---------------------------------------------------------------------------
+constexpr int kPtSlots = 2048;
+template <int W> struct PtTable {
+    uint64_t key0[kPtSlots];
+    uint64_t key1[W == 2 ? kPtSlots : 1];
+    double w1[kPtSlots];
+    double w2[kPtSlots];
+    int64_t sh[kThreads / 64];
+    double shd[kThreads / 64];
+};
+
+template <int W, class V>
+__global__ __launch_bounds__(kThreads) void k_pt2(SysView sys, const Rec<W, V>* __restrict__ rej1,
+                                                  const int64_t* __restrict__ off1, const int32_t* __restrict__ cnt1,
+                                                  const Rec<W, V>* __restrict__ rej2,
+                                                  const int64_t* __restrict__ off2, const int32_t* __restrict__ cnt2,
+                                                  int B, double e0, double h00, double* __restrict__ part,
+                                                  unsigned* __restrict__ err) {
+    __shared__ PtTable<W> T;
+    for (int b = blockIdx.x; b < B; b += gridDim.x) {
+        const int n1 = cnt1[b], n2 = cnt2[b];
+        int nslots = kThreads;
+        while (nslots < (n1 * 4) / 3 + 1 && nslots < kPtSlots) nslots <<= 1;
+        const uint64_t mask = (uint64_t)(nslots - 1);
+        for (int i = threadIdx.x; i < nslots; i += kThreads) {
+            T.key0[i] = kEmpty;
+            if constexpr (W == 2) T.key1[i] = kEmpty;
+            T.w1[i] = 0.0;
+            T.w2[i] = 0.0;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < n1; q += kThreads) {
+            const Rec<W, V> x = rej1[off1[b] + q];
+            Key<W> key;
+#pragma unroll
+            for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
+            const int s = lds_find<W>(T, key, key_hash<W>(key), mask, true);
+            if (s < 0) { atomicOr(err, 1u); continue; }
+            lds_add<double>(&T.w1[s], (double)x.v);
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < n2; q += kThreads) {
+            const Rec<W, V> x = rej2[off2[b] + q];
+            Key<W> key;
+#pragma unroll
+            for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
+            const int s = lds_find<W>(T, key, key_hash<W>(key), mask, false);
+            if (s >= 0) lds_add<double>(&T.w2[s], (double)x.v);
+        }
+        __syncthreads();
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < nslots; i += kThreads) {
+            const double a = T.w1[i], c = T.w2[i];
+            if (T.key0[i] == kEmpty || a == 0.0 || c == 0.0) continue;
+            Key<W> key;
+            key.w[0] = T.key0[i];
+            if constexpr (W == 2) key.w[1] = T.key1[i];
+            const double hd = h_diag(sys, key_alpha<W>(key), key_beta<W>(key));
+            const double dj = hd - h00;
+            const double num = a * c;
+            const double den = e0 - dj;
+            const double x = num / den;
+            acc = acc + x;
+        }
+        acc = wave_sum(acc);
+        if (lane_id() == 0) T.shd[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) part[b] = ((T.shd[0] + T.shd[1]) + T.shd[2]) + T.shd[3];
+        __syncthreads();
+    }
+}
+
+// Sum of the per-bucket partials in a fixed order (one workgroup).
+__global__ __launch_bounds__(kThreads) void k_sum(const double* __restrict__ part, int n, double* __restrict__ out) {
+    __shared__ double shd[kThreads / 64];
+    double acc = 0.0;
+    const int per = (n + kThreads - 1) / kThreads;
+    for (int i = threadIdx.x * per; i < min(n, (int)(threadIdx.x + 1) * per); ++i) acc = acc + part[i];
+    acc = wave_sum(acc);
+    if (lane_id() == 0) shd[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = ((shd[0] + shd[1]) + shd[2]) + shd[3];
 }
 
 // ---------------------------------------------------------------------------

@@ -80,6 +80,7 @@ EXPORTS = ["fciqmc_params_default", "fciqmc_load_integrals", "fciqmc_init", "fci
            "fciqmc_batch_free", "fciqmc_estimate_bytes", "fciqmc_server_create",
            "fciqmc_server_submit", "fciqmc_server_poll", "fciqmc_server_info",
            "fciqmc_server_clock", "fciqmc_server_free", "fciqmc_set_core", "fciqmc_get_core",
+           "fciqmc_pair_create", "fciqmc_pair_step", "fciqmc_pair_pt2", "fciqmc_pair_free",
            "fciqmc_free_run", "fciqmc_free_system", "fciqmc_last_error"]
 
 _lib = None
@@ -138,6 +139,11 @@ def lib():
         L.fciqmc_server_clock.argtypes = [vp]
         L.fciqmc_server_clock.restype = dbl
         L.fciqmc_server_free.argtypes = [vp]
+        L.fciqmc_pair_create.argtypes = [vp, vp, C.POINTER(vp)]
+        L.fciqmc_pair_step.argtypes = [vp, C.c_int, C.POINTER(StepStats), C.POINTER(StepStats), pdbl]
+        L.fciqmc_pair_pt2.argtypes = [vp, i64, pdbl, pdbl, C.POINTER(i64)]
+        L.fciqmc_pair_free.argtypes = [vp]
+        L.fciqmc_pair_free.restype = None
         L.fciqmc_server_free.restype = None
         L.fciqmc_free_run.argtypes = [vp]
         L.fciqmc_free_run.restype = None
@@ -251,6 +257,46 @@ def fciqmc_step(run: Run, n_steps: int = 1, as_array: bool = False):
     if as_array:
         return np.frombuffer(arr, dtype=STATS_DTYPE, count=n_steps)
     return [{k: getattr(arr[i], k) for k, _ in StepStats._fields_} for i in range(n_steps)]
+
+
+class Pair:
+    """Two replicas stepped in lockstep (replica-pair PT2 correction)."""
+
+    def __init__(self, handle, runs):
+        self.handle = handle
+        self.runs = runs  # keep both runs alive
+
+    def free(self):
+        if self.handle:
+            lib().fciqmc_pair_free(self.handle)
+            self.handle = None
+
+
+def fciqmc_pair_create(run1: Run, run2: Run) -> Pair:
+    h = C.c_void_p()
+    _check(lib().fciqmc_pair_create(run1.handle, run2.handle, C.byref(h)))
+    return Pair(h, (run1, run2))
+
+
+def fciqmc_pair_step(pair: Pair, n_steps: int = 1):
+    """n_steps lockstep steps: (stats of replica 1, stats of replica 2, dE2
+    per step as a numpy array, NaN where a step was not evaluated)."""
+    a1 = (StepStats * max(1, n_steps))()
+    a2 = (StepStats * max(1, n_steps))()
+    d = np.zeros(max(1, n_steps))
+    _check(lib().fciqmc_pair_step(pair.handle, int(n_steps), a1, a2, _p(d, C.c_double)))
+    conv = lambda arr: [{k: getattr(arr[i], k) for k, _ in StepStats._fields_} for i in range(n_steps)]
+    return conv(a1), conv(a2), d[:n_steps]
+
+
+def fciqmc_pair_pt2(pair: Pair, skip: int = 0) -> dict:
+    m, e, n = C.c_double(), C.c_double(), C.c_int64()
+    _check(lib().fciqmc_pair_pt2(pair.handle, int(skip), C.byref(m), C.byref(e), C.byref(n)))
+    return {"mean": m.value, "err": e.value, "n": n.value}
+
+
+def fciqmc_pair_free(pair: Pair):
+    pair.free()
 
 
 def fciqmc_energy(run: Run) -> dict:
