@@ -83,6 +83,8 @@ def lib():
         L.orc_run_collect_rejected.argtypes = [vp, C.c_int]
         L.orc_pair_pt2.restype = dbl
         L.orc_pair_pt2.argtypes = [vp, vp]
+        L.orc_pair_overlap.restype = dbl
+        L.orc_pair_overlap.argtypes = [vp, vp]
         L.orc_run_rejected_size.restype = i64
         L.orc_run_rejected_size.argtypes = [vp]
         L.orc_run_get_rejected.argtypes = [vp, pu64, pu64, pdbl]
@@ -312,5 +314,11 @@ class Run:
 
 def pair_pt2(r1: Run, r2: Run) -> float:
     """Epstein-Nesbet correction from the spawns both replicas discarded in
-    their last step (each must collect its rejected spawns)."""
+    their last step (each must collect its rejected spawns), before the
+    division by the replica overlap of the populations the step began from."""
     return lib().orc_pair_pt2(r1.ptr, r2.ptr)
+
+
+def pair_overlap(r1: Run, r2: Run) -> float:
+    """sum_i C_i^1 C_i^2 of the two replicas' current populations."""
+    return lib().orc_pair_overlap(r1.ptr, r2.ptr)

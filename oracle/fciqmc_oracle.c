@@ -749,7 +749,8 @@ void orc_run_collect_rejected(orc_run *r, int on) { r->collect_rej = on; }
 
 /* Epstein-Nesbet second-order correction from the spawns discarded on both
  * replicas in their last step (Sec. "Perturbative correction", Eq.
- * (pt2_correction)):
+ * (pt2_correction)), before the normalisation by the replica overlap
+ * (orc_pair_overlap):
  *   dE2 = 1/dtau^2 sum_j S_j^1 S_j^2 / (E_0 - H_jj)
  * over the determinants j rejected by both, S_j^r the weight spawned onto j
  * in replica r.  Reading: E_0 is the mean of the two replicas' shifts in
@@ -772,6 +773,26 @@ double orc_pair_pt2(const orc_run *r1, const orc_run *r2)
         ++x; ++y;
     }
     return acc / tau2;
+}
+
+/* Overlap of two replicas' populations, sum_i C_i^1 C_i^2: the norm of the
+ * replica estimate of the wave function.  Reading: Eq. (pt2_correction)
+ * holds for a normalised wave function, so dE2 is divided by this overlap of
+ * the populations the step started from (averaged as a ratio of means over
+ * steps), as the variational energy it corrects is. */
+double orc_pair_overlap(const orc_run *r1, const orc_run *r2)
+{
+    double acc = 0.0;
+    int64_t x = 0, y = 0;
+    while (x < r1->n && y < r2->n) {
+        int c = det_cmp(r1->list[x].d, r2->list[y].d);
+        if (c < 0) { ++x; continue; }
+        if (c > 0) { ++y; continue; }
+        double q = r1->list[x].v * r2->list[y].v;
+        acc = acc + q;
+        ++x; ++y;
+    }
+    return acc;
 }
 
 int64_t orc_run_rejected_size(const orc_run *r) { return r->nrej; }

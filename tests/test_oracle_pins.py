@@ -611,9 +611,9 @@ def test_pt2_expectation_is_epstein_nesbet(oracle_mod):
     """Sec. "Perturbative correction", Eq. (pt2_correction): with no parent an
     initiator, every spawn onto an unoccupied determinant is discarded on
     both replicas, independent replicas give E[S^1 S^2] = dtau^2
-    <j|H|C>^2, so the mean of dE2 over streams is the Epstein-Nesbet sum
-    sum_{j unoccupied} <j|H|C>^2 / (E_0 - H_jj) (energies relative to H_00,
-    E_0 the shift)."""
+    <j|H|C>^2, so the mean over streams of dE2 before its division by the
+    replica overlap is the Epstein-Nesbet sum over unoccupied j of
+    <j|H|C>^2 / (E_0 - H_jj) (energies relative to H_00, E_0 the shift)."""
     osys, dets, pick, C = _pt2_setup(oracle_mod, 1e9)
     tau, S = 0.05, -1.5
     H = brute.oracle_dense_h(osys, dets)
@@ -631,6 +631,21 @@ def test_pt2_expectation_is_epstein_nesbet(oracle_mod):
     se = xs.std() / np.sqrt(len(xs))
     assert abs(xs.mean() - want) < 5 * se, (xs.mean(), want, se)
     assert abs(want) > 10 * se   # the test resolves the correction
+
+
+def test_pair_overlap(oracle_mod):
+    """The replica overlap is sum_i C_i^1 C_i^2 over the common determinants."""
+    osys, dets, pick, C = _pt2_setup(oracle_mod, 1e9)
+    rng = np.random.default_rng(9)
+    pick2 = rng.choice(np.arange(1, len(dets)), size=15, replace=False)
+    C2 = np.zeros(len(dets))
+    C2[pick2] = rng.normal(0.0, 2.0, size=15)
+    r1 = oracle_mod.Run(osys, ref=dets[0])
+    r2 = oracle_mod.Run(osys, ref=dets[0], replica=1)
+    r1.set_walkers([dets[i][0] for i in pick], [dets[i][1] for i in pick], C[pick])
+    r2.set_walkers([dets[i][0] for i in pick2], [dets[i][1] for i in pick2], C2[pick2])
+    assert abs(oracle_mod.pair_overlap(r1, r2) - float(C @ C2)) <= 1e-12 * max(1.0, abs(float(C @ C2)))
+    assert oracle_mod.pair_overlap(r1, r1) == float(np.sum(C[pick] ** 2))
 
 
 def test_pt2_vanishes_without_initiator_rule(oracle_mod):
