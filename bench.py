@@ -523,6 +523,54 @@ def measure_semistoch(F, np, torch, steps, n_core):
     return out
 
 
+PT2_DESC = {"workload": "synthetic_molecule_8e8o_4900dets_two_replicas",
+            "walkers_target": 2e4, "tau": 0.01, "initiator_na": 3, "walkers": "real", "c_min": 1.0,
+            "shift_damping": 0.05, "det_bits": 64}
+
+
+def measure_pt2(F, np, torch, steps):
+    """Replica pair with the PT2 correction on the 8-orbital molecule in the
+    initiator approximation (n_a = 3, real walkers, 2e4): both replicas
+    grown apart, then `steps` lockstep steps; the
+    mean dE2, each replica's E_proj and the time per paired step against
+    the same runs stepped alone."""
+    from paper_2006_14956_amd import inputs
+    s = inputs.molecule_8o8e()
+    sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
+    pd = dict(tau=0.01, walker_target=2e4, initiator_na=3.0, seed=1, shift_damping=0.05,
+              n_initial=10.0, mode=F.MODE_REAL, c_min=1.0)
+    runs = [F.fciqmc_init(sysd, F.fciqmc_params_default(**dict(pd, replica_id=r))) for r in (0, 1)]
+    for r in runs:
+        F.fciqmc_step(r, 3000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in runs:
+        F.fciqmc_step(r, 1000, as_array=True)
+    torch.cuda.synchronize()
+    alone = (time.perf_counter() - t0) / 1000
+    pair = F.fciqmc_pair_create(runs[0], runs[1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, d = F.fciqmc_pair_step(pair, steps)
+    torch.cuda.synchronize()
+    paired = (time.perf_counter() - t0) / steps
+    rep = F.fciqmc_pair_pt2(pair)
+    es = [F.fciqmc_energy(r) for r in runs]
+    F.fciqmc_pair_free(pair)
+    out = {"config": dict(PT2_DESC, growth_steps=3000, paired_steps=steps),
+           "de2": rep["mean"], "de2_err": rep["err"], "de2_steps": rep["n"],
+           "ms_per_paired_step": 1e3 * paired, "ms_per_two_solo_steps": 1e3 * alone,
+           "replicas": [{"e_proj": e["e_proj"], "e_proj_err": e["e_proj_err"], "shift": e["shift"],
+                         "shift_err": e["shift_err"]} for e in es]}
+    log(f"[pt2] dE2 {rep['mean']:.6f} +- {rep['err']:.2e} over {rep['n']} steps; "
+        f"{1e3 * paired:.4f} ms per paired step vs {1e3 * alone:.4f} for the two alone; E_proj "
+        + ", ".join(f"{e['e_proj']:.6f} +- {e['e_proj_err']:.1e}" for e in es))
+    for r in runs:
+        F.fciqmc_free_run(r)
+    F.fciqmc_free_system(sysd)
+    return out
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -590,6 +638,9 @@ def main():
     ap.add_argument("--semistoch", type=int, default=20000, metavar="STEPS",
                     help="steps of the semi-stochastic comparison (0 to skip)")
     ap.add_argument("--semistoch-core", type=int, default=500)
+    ap.add_argument("--pt2", type=int, default=20000, metavar="STEPS",
+                    help="lockstep steps of the replica-pair PT2 leg (0 to skip)")
+    ap.add_argument("--pt2-only", action="store_true", help="only run the PT2 leg")
     ap.add_argument("--semistoch-only", action="store_true",
                     help="only run the semi-stochastic comparison")
     ap.add_argument("--generators-only", action="store_true",
@@ -619,6 +670,9 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.pt2_only:
+        print(json.dumps(measure_pt2(F, np, torch, args.pt2 or 20000)), flush=True)
+        return
     if args.semistoch_only:
         print(json.dumps(measure_semistoch(F, np, torch, args.semistoch or 20000, args.semistoch_core)),
               flush=True)
@@ -680,6 +734,10 @@ def main():
     if args.semistoch:
         semistoch = measure_semistoch(F, np, torch, args.semistoch, args.semistoch_core)
 
+    pt2 = None
+    if args.pt2:
+        pt2 = measure_pt2(F, np, torch, args.pt2)
+
     batched = None
     if args.batched_steps:
         batched = measure_batched(F, np, args.batched_steps, args.batched_warmup, args.batched_grow,
@@ -710,6 +768,7 @@ def main():
         "second_workload": second,
         "generators": generators,
         "semistoch": semistoch,
+        "pt2": pt2,
         "batched": batched,
         "served": served,
     }

@@ -324,8 +324,11 @@ void fciqmc_server_free(fciqmc_server *srv);
  * spawn reached.  Over the determinants both replicas discarded,
  *   dE2 = 1/dtau^2 sum_j S_j^1 S_j^2 / (E_0 - H_jj),
  * S_j^r the weight replica r spawned onto j, E_0 the mean of the two shifts
- * used in that step.  The correction applies to a variational energy of the
- * initiator approximation (not computed here).  Creating a pair gives both
+ * used in that step, divided by the replica overlap sum_i C_i^1 C_i^2 of
+ * the populations the step began from (the printed equation holds for a
+ * normalised wave function; averaged over steps as a ratio of means).  The
+ * correction applies to a variational energy of the initiator
+ * approximation (not computed here).  Creating a pair gives both
  * runs the same bucket count and fixes it (a store that still outgrows it
  * skips that step's dE2 and both are re-bucketed); a run in a pair cannot
  * join a batch or another pair, is stepped through fciqmc_pair_step only,
@@ -333,9 +336,10 @@ void fciqmc_server_free(fciqmc_server *srv);
  * fciqmc_pair_step: n_steps lockstep steps; stats1/stats2 (host, n_steps
  * entries) and de2 (host, n_steps doubles, NaN for a skipped step) may be
  * NULL.  EOVERFLOW if one bucket holds more than 1536 distinct discarded
- * targets (use more buckets).
- * fciqmc_pair_pt2: mean and blocked error of dE2 over the pair's steps from
- * number `skip` on (NaN steps left out); *n receives the steps used. */
+ * targets or occupied determinants (use more buckets).
+ * fciqmc_pair_pt2: dE2 over the pair's steps from number `skip` on (NaN
+ * steps left out) as the ratio of the mean numerator to the mean overlap,
+ * with its blocked error; *n receives the steps used. */
 int fciqmc_pair_create(fciqmc_run *r1, fciqmc_run *r2, fciqmc_pair **out);
 int fciqmc_pair_step(fciqmc_pair *pair, int n_steps, fciqmc_step_stats *stats1,
                      fciqmc_step_stats *stats2, double *de2);

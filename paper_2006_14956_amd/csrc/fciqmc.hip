@@ -225,6 +225,8 @@ struct EngineBase {
     virtual void* rej_records() const = 0;
     virtual int64_t* rej_offsets() const = 0;
     virtual int32_t* rej_counts() const = 0;
+    virtual const void* current_store() const = 0;  // Store<V> of the population
+    virtual int bucket_entries() const = 0;         // R
 };
 
 // Largest deterministic space: H^D is built by testing all N_D^2 pairs.
@@ -757,6 +759,8 @@ template <int W, class V> struct Engine : EngineBase {
     void* rej_records() const override { return rej; }
     int64_t* rej_offsets() const override { return rej_off; }
     int32_t* rej_counts() const override { return rej_cnt; }
+    const void* current_store() const override { return &st[cur]; }
+    int bucket_entries() const override { return R; }
     int64_t core_size() const override { return ncore; }
     int64_t core_nnz() const override { return nnz; }
     const std::vector<uint64_t>& core_dets() const override { return core_host; }
@@ -1958,7 +1962,8 @@ struct fciqmc_pair {
     int64_t part_n = 0;
     double* sum = nullptr;
     unsigned* err = nullptr;
-    std::vector<double> de2;  // one value per paired step (NaN: not evaluated)
+    std::vector<double> num;  // per paired step: 1/dtau^2 sum S^1 S^2 / (E_0 - H_jj) (NaN: not evaluated)
+    std::vector<double> ovl;  // and the replica overlap of the populations it began from
     ~fciqmc_pair() { arena.clear(); }
 };
 
@@ -1978,6 +1983,47 @@ template <int W, class V> void launch_pt2(fciqmc_pair* p, int B, double e0, hipS
                        a->rej_counts(), (const Rec<W, V>*)b->rej_records(), b->rej_offsets(), b->rej_counts(), B,
                        e0, p->r[0]->h00, p->part, p->err);
     hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, s, p->part, B, p->sum);
+}
+template <int W, class V> void launch_overlap(fciqmc_pair* p, int B, hipStream_t s) {
+    const Store<V> s1 = *static_cast<const Store<V>*>(p->r[0]->eng->current_store());
+    const Store<V> s2 = *static_cast<const Store<V>*>(p->r[1]->eng->current_store());
+    hipLaunchKernelGGL((k_overlap<W, V>), dim3((unsigned)std::min(B, 4096)), dim3(kThreads), 0, s, s1, s2,
+                       p->r[0]->eng->bucket_entries(), B, p->part, p->err);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, s, p->part, B, p->sum);
+}
+// Run the pair kernel `which` (0: PT2 sum, 1: overlap) over both replicas
+// (equal bucket counts) and return its value.
+int pair_kernel(fciqmc_pair* p, int which, double e0, double& out) {
+    fciqmc_run* a = p->r[0];
+    fciqmc_run* b = p->r[1];
+    const int B = (int)a->eng->buckets();
+    if (p->part_n < B) {
+        p->arena.release(p->part);
+        p->part = nullptr;
+        CHECK(dalloc(p->arena, &p->part, (size_t)B));
+        p->part_n = B;
+    }
+    HIP_OK(hipStreamSynchronize(b->stream));
+    HIP_OK(hipMemsetAsync(p->err, 0, sizeof(unsigned), a->stream));
+    const int k = a->eng->kind();
+    if (which == 0) {
+        if (k == 0) launch_pt2<1, int32_t>(p, B, e0, a->stream);
+        else if (k == 1) launch_pt2<1, double>(p, B, e0, a->stream);
+        else if (k == 2) launch_pt2<2, int32_t>(p, B, e0, a->stream);
+        else launch_pt2<2, double>(p, B, e0, a->stream);
+    } else {
+        if (k == 0) launch_overlap<1, int32_t>(p, B, a->stream);
+        else if (k == 1) launch_overlap<1, double>(p, B, a->stream);
+        else if (k == 2) launch_overlap<2, int32_t>(p, B, a->stream);
+        else launch_overlap<2, double>(p, B, a->stream);
+    }
+    HIP_OK(hipGetLastError());
+    unsigned e = 0;
+    HIP_OK(hipMemcpyAsync(&out, p->sum, sizeof(double), hipMemcpyDeviceToHost, a->stream));
+    HIP_OK(hipMemcpyAsync(&e, p->err, sizeof(unsigned), hipMemcpyDeviceToHost, a->stream));
+    HIP_OK(hipStreamSynchronize(a->stream));
+    if (e) return fail(FCIQMC_EOVERFLOW, "a bucket holds more entries than the pair table (%d slots)", kPtSlots);
+    return 0;
 }
 }  // namespace
 
@@ -2022,67 +2068,49 @@ int fciqmc_pair_step(fciqmc_pair* p, int n_steps, fciqmc_step_stats* stats1, fci
     fciqmc_run* b = p->r[1];
     for (int i = 0; i < n_steps; ++i) {
         const double e0 = (a->S + b->S) / 2.0;  // the shifts this step uses
+        double ovl = NAN;
+        if (a->eng->buckets() == b->eng->buckets()) CHECK(pair_kernel(p, 1, 0.0, ovl));
         CHECK(fciqmc_step(a, 1, stats1 ? stats1 + i : nullptr));
         CHECK(fciqmc_step(b, 1, stats2 ? stats2 + i : nullptr));
-        double v = NAN;
+        double num = NAN;
         const int64_t Ba = a->eng->buckets(), Bb = b->eng->buckets();
-        if (Ba == Bb) {
-            const int B = (int)Ba;
-            if (p->part_n < B) {
-                p->arena.release(p->part);
-                p->part = nullptr;
-                CHECK(dalloc(p->arena, &p->part, (size_t)B));
-                p->part_n = B;
-            }
-            HIP_OK(hipStreamSynchronize(b->stream));
-            HIP_OK(hipMemsetAsync(p->err, 0, sizeof(unsigned), a->stream));
-            switch (a->eng->kind()) {
-                case 0: launch_pt2<1, int32_t>(p, B, e0, a->stream); break;
-                case 1: launch_pt2<1, double>(p, B, e0, a->stream); break;
-                case 2: launch_pt2<2, int32_t>(p, B, e0, a->stream); break;
-                default: launch_pt2<2, double>(p, B, e0, a->stream); break;
-            }
-            HIP_OK(hipGetLastError());
+        if (Ba == Bb && !std::isnan(ovl)) {
             double sum = 0.0;
-            unsigned e = 0;
-            HIP_OK(hipMemcpyAsync(&sum, p->sum, sizeof(double), hipMemcpyDeviceToHost, a->stream));
-            HIP_OK(hipMemcpyAsync(&e, p->err, sizeof(unsigned), hipMemcpyDeviceToHost, a->stream));
-            HIP_OK(hipStreamSynchronize(a->stream));
-            if (e) return fail(FCIQMC_EOVERFLOW, "a bucket holds more discarded targets than its table (%d slots)", kPtSlots);
-            v = sum / (a->p.tau * a->p.tau);
-        } else {
+            CHECK(pair_kernel(p, 0, e0, sum));
+            num = sum / (a->p.tau * a->p.tau);
+        } else if (Ba != Bb) {
             // a store outgrew its buckets during the step: this step is not
             // evaluated, and both use the larger count from the next one
             const int64_t B = std::max(Ba, Bb);
             CHECK(a->eng->rebucket((int)B));
             CHECK(b->eng->rebucket((int)B));
         }
-        p->de2.push_back(v);
-        if (de2) de2[i] = v;
+        p->num.push_back(num);
+        p->ovl.push_back(ovl);
+        if (de2) de2[i] = num / ovl;
     }
     return 0;
 }
 
 int fciqmc_pair_pt2(const fciqmc_pair* p, int64_t skip, double* mean, double* err, int64_t* n) {
     if (!p || !mean || !err || !n) return fail(FCIQMC_EINVAL, "null argument");
-    std::vector<double> x;
-    for (size_t i = (size_t)std::max<int64_t>(skip, 0); i < p->de2.size(); ++i)
-        if (!std::isnan(p->de2[i])) x.push_back(p->de2[i]);
+    std::vector<double> x, y;
+    for (size_t i = (size_t)std::max<int64_t>(skip, 0); i < p->num.size(); ++i)
+        if (!std::isnan(p->num[i]) && !std::isnan(p->ovl[i])) { x.push_back(p->num[i]); y.push_back(p->ovl[i]); }
     *n = (int64_t)x.size();
     *mean = NAN;
     *err = NAN;
     if (x.empty()) return 0;
+    double mx, ex, my, r, er;
     if (x.size() < 16) {
-        double m = 0.0;
-        for (double y : x) m += y;
-        *mean = m / (double)x.size();
+        mx = 0.0; my = 0.0;
+        for (size_t i = 0; i < x.size(); ++i) { mx += x[i]; my += y[i]; }
+        *mean = my != 0.0 ? mx / my : NAN;
         return 0;
     }
-    double mx, ex, my, r, er;
-    std::vector<double> ones(x.size(), 1.0);
-    blocking(x, ones, mx, ex, my, r, er);
-    *mean = mx;
-    *err = ex;
+    blocking(x, y, mx, ex, my, r, er);
+    *mean = r;
+    *err = er;
     return 0;
 }
 

@@ -1322,6 +1322,47 @@ __global__ __launch_bounds__(kThreads) void k_pt2(SysView sys, const Rec<W, V>* 
     }
 }
 
+// Replica overlap sum_i C_i^1 C_i^2 per bucket: the first store's entries
+// in an LDS table, probed with the second's.
+template <int W, class V>
+__global__ __launch_bounds__(kThreads) void k_overlap(Store<V> s1, Store<V> s2, int R, int B,
+                                                      double* __restrict__ part, unsigned* __restrict__ err) {
+    __shared__ PtTable<W> T;
+    for (int b = blockIdx.x; b < B; b += gridDim.x) {
+        const int n1 = s1.count[b], n2 = s2.count[b];
+        int nslots = kThreads;
+        while (nslots < (n1 * 4) / 3 + 1 && nslots < kPtSlots) nslots <<= 1;
+        const uint64_t mask = (uint64_t)(nslots - 1);
+        const int64_t eb = (int64_t)b * R;
+        for (int i = threadIdx.x; i < nslots; i += kThreads) {
+            T.key0[i] = kEmpty;
+            if constexpr (W == 2) T.key1[i] = kEmpty;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < n1; e += kThreads) {
+            const Key<W> key = load_key<W>(s1.keys + (eb + e) * W);
+            const int s = lds_find<W>(T, key, key_hash<W>(key), mask, true);
+            if (s < 0) { atomicOr(err, 1u); continue; }
+            T.w1[s] = (double)s1.vals[eb + e];
+        }
+        __syncthreads();
+        double acc = 0.0;
+        for (int e = threadIdx.x; e < n2; e += kThreads) {
+            const Key<W> key = load_key<W>(s2.keys + (eb + e) * W);
+            const int s = lds_find<W>(T, key, key_hash<W>(key), mask, false);
+            if (s >= 0) {
+                const double q = T.w1[s] * (double)s2.vals[eb + e];
+                acc = acc + q;
+            }
+        }
+        acc = wave_sum(acc);
+        if (lane_id() == 0) T.shd[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) part[b] = ((T.shd[0] + T.shd[1]) + T.shd[2]) + T.shd[3];
+        __syncthreads();
+    }
+}
+
 // Sum of the per-bucket partials in a fixed order (one workgroup).
 __global__ __launch_bounds__(kThreads) void k_sum(const double* __restrict__ part, int n, double* __restrict__ out) {
     __shared__ double shd[kThreads / 64];

@@ -280,7 +280,8 @@ def fciqmc_pair_create(run1: Run, run2: Run) -> Pair:
 
 def fciqmc_pair_step(pair: Pair, n_steps: int = 1):
     """n_steps lockstep steps: (stats of replica 1, stats of replica 2, dE2
-    per step as a numpy array, NaN where a step was not evaluated)."""
+    of each step, normalised by that step's replica overlap, as a numpy
+    array; NaN where a step was not evaluated)."""
     a1 = (StepStats * max(1, n_steps))()
     a2 = (StepStats * max(1, n_steps))()
     d = np.zeros(max(1, n_steps))

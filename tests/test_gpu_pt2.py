@@ -1,7 +1,8 @@
 """GPU parity of the replica-pair PT2 correction (Sec. "Perturbative
-correction", Eq. (pt2_correction)) against the oracle.  Integer walkers:
-both replicas follow the oracle bit for bit, the discarded weights are sums
-of integers, and dE2 differs only by the order of its final sum."""
+correction", Eq. (pt2_correction), normalised by the replica overlap)
+against the oracle.  Integer walkers: both replicas follow the oracle bit
+for bit, the discarded weights and the overlap are sums of integers, and
+dE2 differs only by the order of its final sums."""
 import math
 
 import numpy as np
@@ -54,11 +55,12 @@ def test_pair_correction_matches_oracle(words):
     nonzero = 0
     for step in range(12):
         g1, g2, d = F.fciqmc_pair_step(pair, 1)
+        ovl = oracle.pair_overlap(orc[0], orc[1])
         o1 = orc[0].step(1)
         o2 = orc[1].step(1)
         assert_same_stats(g1[0], o1[0])
         assert_same_stats(g2[0], o2[0])
-        want = oracle.pair_pt2(orc[0], orc[1])
+        want = oracle.pair_pt2(orc[0], orc[1]) / ovl
         assert not math.isnan(d[0])
         assert abs(d[0] - want) <= 1e-10 * max(1e-12, abs(want)), (step, d[0], want)
         nonzero += want != 0.0
