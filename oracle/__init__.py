@@ -88,6 +88,8 @@ def lib():
         L.orc_run_rejected_size.restype = i64
         L.orc_run_rejected_size.argtypes = [vp]
         L.orc_run_get_rejected.argtypes = [vp, pu64, pu64, pdbl]
+        L.orc_run_adaptive_f.restype = dbl
+        L.orc_run_adaptive_f.argtypes = [vp, u64, u64]
         _lib = L
     return _lib
 
@@ -97,7 +99,7 @@ class OrcParams(C.Structure):
                 ("c_min", C.c_double), ("zeta", C.c_double), ("p_single", C.c_double),
                 ("p_opp", C.c_double), ("interval", C.c_int), ("mode", C.c_int),
                 ("gen", C.c_int), ("seed", C.c_uint64), ("replica", C.c_uint64),
-                ("xi", C.c_double)]
+                ("xi", C.c_double), ("adaptive", C.c_int)]
 
 
 class OrcStats(C.Structure):
@@ -199,7 +201,7 @@ class System:
 
 DEFAULTS = dict(tau=0.01, target=1e4, n_a=-1.0, c_min=1.0, zeta=0.05, p_single=-1.0,
                 p_opp=-1.0, interval=10, mode=MODE_INTEGER, gen=GEN_UNIFORM, seed=1, replica=0,
-                xi=-1.0)
+                xi=-1.0, adaptive=0)
 
 
 class Run:
@@ -295,6 +297,10 @@ class Run:
 
     def rejected_size(self):
         return lib().orc_run_rejected_size(self.ptr)
+
+    def adaptive_f(self, a, b):
+        """Adaptive-shift fraction f of (a, b) in the last step (-1: not occupied)."""
+        return lib().orc_run_adaptive_f(self.ptr, int(a), int(b))
 
     def rejected(self):
         """(alpha, beta, weight) of the last step's discarded targets."""

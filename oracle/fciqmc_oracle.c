@@ -502,6 +502,8 @@ typedef struct {
     det_t d;
     double v;
     int init;
+    int64_t par;   /* adaptive shift: the non-initiator parent's list index, else -1 */
+    double habs;   /* |H_ji| of the spawn */
 } rec_t;
 
 typedef struct {
@@ -509,6 +511,7 @@ typedef struct {
     int interval, mode, gen;
     uint64_t seed, replica;
     double xi; /* restoring strength of the shift update; < 0: zeta^2/4 */
+    int adaptive; /* adaptive shift for non-initiators (Sec. "Adaptive Shift") */
 } orc_params;
 
 typedef struct {
@@ -544,6 +547,10 @@ typedef struct {
     double *rej_w;
     int64_t nrej;
     double S_step;      /* shift used in the last step */
+    /* adaptive shift of the last step: f of each determinant occupied at tau */
+    det_t *f_det;
+    double *f_val;
+    int64_t nf;
 } orc_run;
 
 static int ent_cmp(const void *x, const void *y)
@@ -610,6 +617,7 @@ void orc_run_free(orc_run *r)
     if (!r) return;
     core_clear(r);
     free(r->rej); free(r->rej_w);
+    free(r->f_det); free(r->f_val);
     free(r->list);
     free(r->nw_ring);
     free(r);
@@ -797,6 +805,16 @@ double orc_pair_overlap(const orc_run *r1, const orc_run *r2)
 
 int64_t orc_run_rejected_size(const orc_run *r) { return r->nrej; }
 
+/* f of determinant (a, b) in the last adaptive-shift step (1 for an
+ * initiator or a determinant without spawn weight); -1 if it was not
+ * occupied at the start of that step. */
+double orc_run_adaptive_f(const orc_run *r, uint64_t a, uint64_t b)
+{
+    for (int64_t x = 0; x < r->nf; ++x)
+        if (r->f_det[x].a == a && r->f_det[x].b == b) return r->f_val[x];
+    return -1.0;
+}
+
 void orc_run_get_rejected(const orc_run *r, uint64_t *a, uint64_t *b, double *w)
 {
     for (int64_t x = 0; x < r->nrej; ++x) { a[x] = r->rej[x].a; b[x] = r->rej[x].b; w[x] = r->rej_w[x]; }
@@ -896,11 +914,43 @@ int orc_run_step(orc_run *r, orc_stats *st)
             recs[nrec].r.d = tgt;
             recs[nrec].r.v = amt;
             recs[nrec].r.init = init;
+            recs[nrec].r.par = (p->adaptive && !init) ? x : -1;
+            recs[nrec].r.habs = fabs(H);
             recs[nrec].seq = nrec;
             nrec++;
         }
     }
     st->spawns = nrec;
+
+    /* Adaptive shift (Sec. "Adaptive Shift", Eq. (as_fval)): a non-initiator
+     * D_i dies with the local shift S_i = f_i S, f_i the share of the weights
+     * w_ij = |H_ij| / (H_jj - E_0) of its spawns this step that the
+     * initiator rule accepted (target occupied at tau).  Readings: E_0 is the
+     * current shift, the denominator is taken as |H_jj - E_0| (weight 0 if
+     * it vanishes) and w is capped at 1e6; every spawn record counts once;
+     * f_i = 1 when no weight was spawned; the weights are summed in fixed
+     * point with 2^-40 resolution, so the sums do not depend on their order. */
+    int64_t *acc_w = NULL, *all_w = NULL;
+    if (p->adaptive) {
+        free(r->f_det); free(r->f_val);
+        r->f_det = (det_t *)malloc(sizeof(det_t) * (r->n > 0 ? r->n : 1));
+        r->f_val = (double *)malloc(sizeof(double) * (r->n > 0 ? r->n : 1));
+        r->nf = r->n;
+        acc_w = (int64_t *)calloc((size_t)(r->n > 0 ? r->n : 1), sizeof(int64_t));
+        all_w = (int64_t *)calloc((size_t)(r->n > 0 ? r->n : 1), sizeof(int64_t));
+        for (int64_t q = 0; q < nrec; ++q) {
+            const rec_t *x = &recs[q].r;
+            if (x->par < 0) continue;
+            int64_t at = find(r->list, r->n, x->d);
+            double dj = at >= 0 ? r->list[at].diag : orc_hdiag_det(s, x->d) - r->h00;
+            double den = fabs(dj - r->S);
+            double w = den > 0.0 ? x->habs / den : 0.0;
+            if (w > 1e6) w = 1e6;
+            int64_t qw = (int64_t)floor(w * 1099511627776.0 + 0.5);
+            all_w[x->par] += qw;
+            if (at >= 0) acc_w[x->par] += qw;
+        }
+    }
 
     /* (b) death: C_i <- (1 - dtau (H_ii - S)) C_i, then stochastic rounding
      * (integer mode: to the neighbouring integers; real mode: the C_min rule). */
@@ -908,7 +958,19 @@ int orc_run_step(orc_run *r, orc_stats *st)
     for (int64_t x = 0; x < r->n; ++x) {
         const ent_t *e = &r->list[x];
         if (r->nc > 0 && core_find(r, e->d) >= 0) continue;  /* set below */
-        double t1 = e->diag - r->S;
+        double Sx = r->S;
+        if (p->adaptive) {
+            double ax = fabs(e->v);
+            int ini = (p->n_a < 0.0) || (ax > p->n_a) || det_eq(e->d, r->ref);
+            double f = 1.0;
+            if (!ini && all_w[x] > 0) {
+                f = (double)acc_w[x] / (double)all_w[x];
+                Sx = f * r->S;
+            }
+            r->f_det[x] = e->d;
+            r->f_val[x] = f;
+        }
+        double t1 = e->diag - Sx;
         double t2 = p->tau * t1;
         double f = 1.0 - t2;
         double xv = f * e->v;
@@ -1012,6 +1074,8 @@ int orc_run_step(orc_run *r, orc_stats *st)
     free(r->list);
     free(post);
     free(recs);
+    free(acc_w);
+    free(all_w);
     r->list = next;
     r->n = m;
     r->cap = ncap;

@@ -655,6 +655,76 @@ def test_pt2_vanishes_without_initiator_rule(oracle_mod):
     assert e2 == 0.0 and runs[0].rejected_size() == 0
 
 
+def test_adaptive_shift_without_initiator_rule_is_plain(oracle_mod):
+    """Sec. "Adaptive Shift": initiators keep the full shift, so with the
+    initiator rule off the adaptive run is the plain one, bit for bit."""
+    s = inputs.synthetic_molecule(6, 3, 2, seed=3)
+    osys = oracle_mod.System.from_inputs(s)
+    runs = [oracle_mod.Run(osys, tau=0.02, target=300.0, seed=5, adaptive=a) for a in (0, 1)]
+    for r in runs:
+        r.set_walkers([7], [3], [10.0])
+    o0, o1 = runs[0].step(150), runs[1].step(150)
+    assert o0 == o1
+    a0, a1 = runs[0].get_walkers(), runs[1].get_walkers()
+    assert all(np.array_equal(x, y) for x, y in zip(a0, a1))
+
+
+def test_adaptive_fraction_is_accepted_weight_share(oracle_mod):
+    """Eq. (as_fval): a non-initiator with two walkers whose strongest
+    neighbour is occupied and the others empty; whatever its two attempts
+    produce, f is 1 (no spawn or only accepted ones), 0 (only rejected
+    ones) or w_occ / (w_occ + w_k) for an empty neighbour k, with
+    w_j = |H_ij| / |H_jj - E_0| from the Slater-Condon elements and E_0 the
+    shift; several mixed values occur."""
+    s = inputs.synthetic_molecule(3, 1, 1, seed=4, h_offdiag_sd=0.3)
+    osys = oracle_mod.System.from_inputs(s)
+    dets = brute.basis(3, 1, 1)
+    par = (1, 1)
+    nb = [d for d in dets if d != par and osys.hij(par[0], par[1], d[0], d[1]) != 0.0]
+    occ = max(nb, key=lambda d: abs(osys.hij(par[0], par[1], d[0], d[1])))
+    S = -0.4
+    h00 = osys.hdiag(*occ)
+
+    def w(j):
+        return abs(osys.hij(par[0], par[1], j[0], j[1])) / abs(osys.hdiag(*j) - h00 - S)
+
+    allowed = [0.0, 1.0] + [w(occ) / (w(occ) + w(k)) for k in nb if k != occ]
+    seen = set()
+    for seed in range(400):
+        r = oracle_mod.Run(osys, ref=occ, tau=0.3, target=1e12, n_a=3.0, seed=seed, adaptive=1,
+                           p_single=0.5)
+        r.set_walkers([par[0], occ[0]], [par[1], occ[1]], [2.0, 5.0])
+        r.set_state(0, S, 1, 0, 7.0)
+        r.step()
+        f = r.adaptive_f(*par)
+        k = int(np.argmin([abs(f - x) for x in allowed]))
+        assert abs(f - allowed[k]) <= 1e-9, (seed, f, allowed)
+        seen.add(k)
+        assert r.adaptive_f(*occ) == 1.0   # the reference is an initiator
+    assert {0, 1} <= seen and len(seen - {0, 1}) >= 2, seen
+    # the local shift f S replaces S in the parent's death: with the same
+    # random stream (spawning does not depend on S) and no rounding, the
+    # parent's coefficient moves by dtau S (f - 1) C relative to the plain run
+    tau = 0.3
+    moved = 0
+    for seed in range(60):
+        out = []
+        for ada in (0, 1):
+            r = oracle_mod.Run(osys, ref=occ, tau=tau, target=1e12, n_a=3.0, seed=seed, adaptive=ada,
+                               p_single=0.5, mode=oracle_mod.MODE_REAL, c_min=1e-9)
+            r.set_walkers([par[0], occ[0]], [par[1], occ[1]], [2.0, 5.0])
+            r.set_state(0, S, 1, 0, 7.0)
+            r.step()
+            a, b, v, _ = r.get_walkers()
+            out.append((dict(zip(zip(a.tolist(), b.tolist()), v.tolist())), r))
+        f = out[1][1].adaptive_f(*par)
+        want = tau * S * (f - 1.0) * 2.0
+        got = out[1][0][par] - out[0][0][par]
+        assert abs(got - want) <= 1e-12, (seed, got, want)
+        moved += f != 1.0
+    assert moved > 0
+
+
 def test_projected_energy_of_eigenvector(oracle_mod):
     """E_Ref is exact for an eigenstate (Eq. proje)."""
     s = inputs.synthetic_molecule(6, 3, 3, seed=5)
