@@ -93,6 +93,11 @@ typedef struct fciqmc_params {
     int det_words;          /* 1 (N <= 32) or 2 (N <= 63) uint64 per determinant; 0 auto  */
     double conv_tol;        /* energy agreement tolerance for the report (Hartree)        */
     int equil_steps;        /* steps after the shift starts varying that the report drops */
+    int adaptive_shift;     /* 1: non-initiators die with the local shift f_i S of
+                               Sec. "Adaptive Shift" (f_i: accepted share of the weights
+                               |H_ij|/|H_jj - E_0| of their spawns this step, E_0 the shift;
+                               f_i = 1 without spawns); runs with it step alone (no
+                               batch) and take no deterministic space                      */
 } fciqmc_params;
 
 /* Per-step diagnostics (after the step). */

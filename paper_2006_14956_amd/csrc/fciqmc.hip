@@ -252,6 +252,7 @@ struct RunScalars {
     double tau, p_single, p_double, p_opp, n_a, c_min, h00;
     uint64_t seed, replica, ref_a, ref_b;
     int gen;
+    int adaptive;  // adaptive shift for non-initiators
 };
 
 template <int W, class V> struct Engine : EngineBase {
@@ -312,6 +313,12 @@ template <int W, class V> struct Engine : EngineBase {
     unsigned long long* core_missing = nullptr;
     // discarded spawns of the last step (replica-pair PT2): records laid out
     // like the slabs, per-bucket start and count
+    // adaptive shift: per record the non-initiator parent and |H| (laid out
+    // like the slabs), per store entry the weight sums
+    int64_t* rec_par = nullptr;
+    double* rec_h = nullptr;
+    int64_t* ada_acc = nullptr;
+    int64_t* ada_all = nullptr;
     bool keep_rej = false;
     Rec<W, V>* rej = nullptr;
     int64_t* rej_off = nullptr;
@@ -411,6 +418,10 @@ template <int W, class V> struct Engine : EngineBase {
             CHECK(dalloc(arena, &fcnt, (size_t)B));
         }
         if (keep_rej) CHECK(alloc_rej_index());
+        if (rs.adaptive) {
+            CHECK(dalloc(arena, &ada_acc, (size_t)B * R));
+            CHECK(dalloc(arena, &ada_all, (size_t)B * R));
+        }
         return 0;
     }
     int alloc_rej_index() {
@@ -428,6 +439,8 @@ template <int W, class V> struct Engine : EngineBase {
         rel = nullptr; need_b = nullptr; recs_b = nullptr; part = nullptr;
         arena.release(rej_off); arena.release(rej_cnt);
         rej_off = nullptr; rej_cnt = nullptr;
+        arena.release(ada_acc); arena.release(ada_all);
+        ada_acc = nullptr; ada_all = nullptr;
         arena.release(nw_b); arena.release(en_b);
         arena.release(fpos); arena.release(fcnt);
         scount = nullptr; soff = nullptr; nw_b = en_b = nullptr;
@@ -444,6 +457,14 @@ template <int W, class V> struct Engine : EngineBase {
             arena.release(rej);
             rej = nullptr;
             CHECK(dalloc(arena, &rej, (size_t)cap));
+        }
+        if (rs.adaptive) {
+            arena.release(rec_par);
+            arena.release(rec_h);
+            rec_par = nullptr;
+            rec_h = nullptr;
+            CHECK(dalloc(arena, &rec_par, (size_t)cap));
+            CHECK(dalloc(arena, &rec_h, (size_t)cap));
         }
         return 0;
     }
@@ -504,6 +525,12 @@ template <int W, class V> struct Engine : EngineBase {
             sc.rej_off = rej_off;
             sc.rej_cnt = rej_cnt;
         }
+        if (rs.adaptive) {
+            sc.rec_par = rec_par;
+            sc.rec_h = rec_h;
+            sc.ada_acc = ada_acc;
+            sc.ada_all = ada_all;
+        }
         return sc;
     }
 
@@ -521,6 +548,12 @@ template <int W, class V> struct Engine : EngineBase {
         const SysView v = sys->view();
         Store<V> in = st[cur], out = st[1 - cur];
         const int gb = std::min(B, 32768);
+        if (rs.adaptive && !sc.import_mode) {
+            const unsigned ga = (unsigned)std::min(B, 8192);
+            hipLaunchKernelGGL((k_ada_zero<V>), dim3(ga), dim3(kThreads), 0, stream, in, R, B, ada_acc, ada_all);
+            hipLaunchKernelGGL((k_ada_weights<W, V>), dim3(ga), dim3(kThreads), 0, stream, v, in, sc, rec2, soff,
+                               scount, ctl);
+        }
         if (ncore > 0 && !sc.import_mode)
             hipLaunchKernelGGL(k_core_spmv, dim3((unsigned)((ncore + 3) / 4)), dim3(kThreads), 0, stream, core_rowp,
                                core_col, core_val, core_cdiag, core_cv[cur], core_dv, ncore, rs.tau, sc.S);
@@ -1519,6 +1552,7 @@ int fciqmc_init(const fciqmc_system* csys, const fciqmc_params* p, void* stream,
     rs.seed = p->seed; rs.replica = p->replica_id;
     rs.ref_a = ra; rs.ref_b = rb;
     rs.gen = p->excitgen;
+    rs.adaptive = p->adaptive_shift ? 1 : 0;
     int B = 1;
     long long spawn_cap = 0;
     initial_capacity(p, B, spawn_cap);
@@ -1573,6 +1607,7 @@ int fciqmc_batch_add(fciqmc_batch* b, fciqmc_run* run) {
     if (run->eng->core_size() > 0)
         return fail(FCIQMC_EINVAL, "a run with a deterministic space is stepped alone");
     if (run->pair) return fail(FCIQMC_EINVAL, "a replica of a pair is stepped by its pair");
+    if (run->p.adaptive_shift) return fail(FCIQMC_EINVAL, "a run with the adaptive shift is stepped alone");
     HIP_OK(hipStreamSynchronize(run->stream));
     const int k = run->eng->kind();
     if (!b->group[k]) b->group[k] = make_group(k);
@@ -1878,6 +1913,8 @@ int fciqmc_set_core(fciqmc_run* run, int64_t n_core, int64_t* n_out) {
     if (run->batch) return fail(FCIQMC_ESTATE, "the run belongs to a batch");
     if (run->p.mode != FCIQMC_MODE_REAL)
         return fail(FCIQMC_EINVAL, "the semi-stochastic projection needs real coefficients");
+    if (run->p.adaptive_shift)
+        return fail(FCIQMC_EINVAL, "the adaptive shift and a deterministic space are not combined");
     if (n_core < 0 || n_core > kMaxCore)
         return fail(FCIQMC_EINVAL, "n_core must be in [0, %lld]", (long long)kMaxCore);
     CHECK(run->eng->set_core(n_core));

@@ -110,7 +110,18 @@ struct StepScalars {
     void* rej;
     int64_t* rej_off;
     int32_t* rej_cnt;
+    // adaptive shift (ada_all = nullptr: off): per record the non-initiator
+    // parent's store index (-1 otherwise) and |H|; per input entry the fixed-
+    // point sums of accepted and of all spawn weights
+    int64_t* rec_par;
+    double* rec_h;
+    int64_t* ada_acc;
+    int64_t* ada_all;
 };
+
+// Fixed point of the adaptive-shift weights: 2^-40 resolution, so integer
+// sums of them do not depend on their order.
+constexpr double kAdaScale = 1099511627776.0;
 
 // ---------------------------------------------------------------------------
 // Semi-stochastic projection (Sec. "Semi-stochastic FCIQMC").  A determinant
@@ -168,6 +179,8 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
         const int64_t local = (m & 0xFFFFFFFFLL) * kChunk + threadIdx.x;
         bool emit = false;
         Rec<W, V> out;
+        int64_t out_parent = -1;  // adaptive shift: non-initiator parent's store index
+        double out_h = 0.0;
         if (local < natt) {
             int elo = 0, ehi = cnt;
             while (ehi - elo > 1) {
@@ -225,6 +238,8 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
                     if (amp != 0.0) { out.v = (V)amp; emit = true; }
                 }
                 if (emit) {
+                    if (!init) out_parent = e;
+                    out_h = fabs(x.H);
                     const Key<W> tk = make_key<W>(x.ta, x.tb);
 #pragma unroll
                     for (int w = 0; w < W; ++w) out.k[w] = tk.w[w];
@@ -236,8 +251,15 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
         if (emit) {
             const uint32_t j = (out.flag >> 1) * kSub + (uint32_t)(g & (kSub - 1));
             const int64_t pos = (int64_t)atomicAdd(&scount[j], 1);
-            if (soff[j] + pos < soff[j + 1] && soff[j] + pos < sc.spawn_cap) rec2[soff[j] + pos] = out;
-            else atomicOr(&ctl->flags, kFlagSpawnCap);
+            if (soff[j] + pos < soff[j + 1] && soff[j] + pos < sc.spawn_cap) {
+                rec2[soff[j] + pos] = out;
+                if (sc.rec_par) {
+                    sc.rec_par[soff[j] + pos] = (out_parent < 0) ? -1 : out_parent;
+                    sc.rec_h[soff[j] + pos] = out_h;
+                }
+            } else {
+                atomicOr(&ctl->flags, kFlagSpawnCap);
+            }
         }
     }
     __syncthreads();  // smpre is reused by the workgroup's next chunk
@@ -586,7 +608,17 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
             // deterministic space: P^D C, diagonal included, unrounded
             post = (V)sc.core_d[core_index(d)];
         } else {
-            const double t1 = d - sc.S;
+            double Sx = sc.S;
+            if (sc.ada_all) {
+                // adaptive shift: a non-initiator's local shift f S
+                const bool ini = (sc.n_a < 0.0) || (vabs(C) > sc.n_a) || key_eq<W>(key, ref);
+                const int64_t T = sc.ada_all[eb + e];
+                if (!ini && T > 0) {
+                    const double f = (double)sc.ada_acc[eb + e] / (double)T;
+                    Sx = f * sc.S;
+                }
+            }
+            const double t1 = d - Sx;
             const double t2 = sc.tau * t1;
             const double f = 1.0 - t2;
             const double xv = f * (double)C;
@@ -1241,6 +1273,93 @@ __global__ void k_build_jk(SysView sys, double* J, double* K, double* X, double*
         X[i] = j - k;
         SK[i] = sqrt(fabs(k));
         if (p == q) { U[p] = eri(sys, p, p, p, p); Hd[p] = sys.h1[i]; }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adaptive shift (Sec. "Adaptive Shift", Eq. (as_fval)).  Between the spawn
+// and the merge of a step: clear the per-entry sums, then per bucket look up
+// each record's target among the bucket's entries at tau (an LDS table) and
+// add its weight w = |H| / |H_jj - E_0| (E_0 the shift; capped at 1e6) to
+// its non-initiator parent's sum of all weights, and, when the target is
+// occupied (the spawn is accepted), to its sum of accepted weights.
+// ---------------------------------------------------------------------------
+template <class V>
+__global__ __launch_bounds__(kThreads) void k_ada_zero(Store<V> in, int R, int B, int64_t* __restrict__ acc,
+                                                       int64_t* __restrict__ all) {
+    for (int b = blockIdx.x; b < B; b += gridDim.x) {
+        const int cnt = in.count[b];
+        for (int e = threadIdx.x; e < cnt; e += kThreads) {
+            acc[(int64_t)b * R + e] = 0;
+            all[(int64_t)b * R + e] = 0;
+        }
+    }
+}
+
+template <int W> struct AdaTable {
+    uint64_t key0[2 * kMaxR];
+    uint64_t key1[W == 2 ? 2 * kMaxR : 1];
+    int32_t idx[2 * kMaxR];
+};
+
+template <int W, class V>
+__global__ __launch_bounds__(kThreads) void k_ada_weights(SysView sys, Store<V> in, StepScalars sc,
+                                                          const Rec<W, V>* __restrict__ rec2,
+                                                          const int64_t* __restrict__ soff,
+                                                          const int32_t* __restrict__ scount, Ctl* ctl) {
+    __shared__ AdaTable<W> T;
+    for (int b = blockIdx.x; b < sc.B; b += gridDim.x) {
+        const int64_t eb = (int64_t)b * sc.R;
+        const int cnt = in.count[b];
+        int nslots = kThreads;
+        while (nslots < (cnt * 4) / 3 + 1 && nslots < 2 * kMaxR) nslots <<= 1;
+        const uint64_t mask = (uint64_t)(nslots - 1);
+        for (int i = threadIdx.x; i < nslots; i += kThreads) {
+            T.key0[i] = kEmpty;
+            if constexpr (W == 2) T.key1[i] = kEmpty;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < cnt; e += kThreads) {
+            const Key<W> key = load_key<W>(in.keys + (eb + e) * W);
+            const int s = lds_find<W>(T, key, key_hash<W>(key), mask, true);
+            if (s < 0) { atomicOr(&ctl->flags, kFlagTable); continue; }
+            T.idx[s] = e;
+        }
+        __syncthreads();
+        int64_t cum[kSub + 1], lo[kSub];
+        cum[0] = 0;
+#pragma unroll
+        for (int j = 0; j < kSub; ++j) {
+            lo[j] = soff[(int64_t)b * kSub + j];
+            cum[j + 1] = cum[j] + scount[(int64_t)b * kSub + j];
+        }
+        for (int64_t q = threadIdx.x; q < cum[kSub]; q += kThreads) {
+            int64_t src = 0;
+#pragma unroll
+            for (int j = 0; j < kSub; ++j)
+                if (q >= cum[j] && q < cum[j + 1]) src = lo[j] + (q - cum[j]);
+            const int64_t par = sc.rec_par[src];
+            if (par < 0) continue;
+            const Rec<W, V> x = rec2[src];
+            Key<W> key;
+#pragma unroll
+            for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
+            const int s = lds_find<W>(T, key, key_hash<W>(key), mask, false);
+            double dj;
+            if (s >= 0) {
+                dj = in.diag[eb + T.idx[s]];
+            } else {
+                const double hd = h_diag(sys, key_alpha<W>(key), key_beta<W>(key));
+                dj = hd - sc.h00;
+            }
+            const double den = fabs(dj - sc.S);
+            double w = den > 0.0 ? sc.rec_h[src] / den : 0.0;
+            if (w > 1e6) w = 1e6;
+            const long long qw = (long long)floor(w * kAdaScale + 0.5);
+            atomicAdd((unsigned long long*)&sc.ada_all[par], (unsigned long long)qw);
+            if (s >= 0) atomicAdd((unsigned long long*)&sc.ada_acc[par], (unsigned long long)qw);
+        }
+        __syncthreads();
     }
 }
 

@@ -35,7 +35,7 @@ class Params(C.Structure):
                 ("shift_interval", C.c_int), ("ref_alpha", C.c_uint64), ("ref_beta", C.c_uint64),
                 ("max_dets", C.c_int64), ("max_spawns", C.c_int64),
                 ("hbm_budget_bytes", C.c_int64), ("buckets_log2", C.c_int), ("det_words", C.c_int),
-                ("conv_tol", C.c_double), ("equil_steps", C.c_int)]
+                ("conv_tol", C.c_double), ("equil_steps", C.c_int), ("adaptive_shift", C.c_int)]
 
 
 class StepStats(C.Structure):

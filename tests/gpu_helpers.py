@@ -20,7 +20,8 @@ def ref_of(s):
 
 def make_gpu_run(s, tau, target, gen="uniform", n_a=-1.0, mode="integer", seed=1, zeta=0.05,
                  interval=10, c_min=1.0, det_words=0, n_initial=10.0, p_single=-1.0, p_opp=-1.0,
-                 buckets_log2=0, max_spawns=0, stream=None, replica=0, sysd=None, max_dets=0):
+                 buckets_log2=0, max_spawns=0, stream=None, replica=0, sysd=None, max_dets=0,
+                 adaptive=0):
     """(system handle, gpu_run) started from n_initial walkers on the reference."""
     g, _ = GEN[gen]
     m = F.MODE_INTEGER if mode == "integer" else F.MODE_REAL
@@ -32,27 +33,27 @@ def make_gpu_run(s, tau, target, gen="uniform", n_a=-1.0, mode="integer", seed=1
                                 c_min=c_min, det_words=det_words, n_initial=n_initial,
                                 ref_alpha=ra, ref_beta=rb, p_single=p_single, p_opp=p_opp,
                                 buckets_log2=buckets_log2, max_spawns=max_spawns,
-                                replica_id=replica, max_dets=max_dets)
+                                replica_id=replica, max_dets=max_dets, adaptive_shift=adaptive)
     return sysd, F.fciqmc_init(sysd, p, stream=stream)
 
 
 def make_pair(s, tau, target, gen="uniform", n_a=-1.0, mode="integer", seed=1, zeta=0.05,
               interval=10, c_min=1.0, det_words=0, n_initial=10.0, p_single=-1.0, p_opp=-1.0,
-              buckets_log2=0, max_spawns=0, stream=None, replica=0, max_dets=0):
+              buckets_log2=0, max_spawns=0, stream=None, replica=0, max_dets=0, adaptive=0):
     """(gpu_run, oracle_run) started from n_initial walkers on the reference."""
     _, o = GEN[gen]
     sysd, run = make_gpu_run(s, tau, target, gen=gen, n_a=n_a, mode=mode, seed=seed, zeta=zeta,
                              interval=interval, c_min=c_min, det_words=det_words,
                              n_initial=n_initial, p_single=p_single, p_opp=p_opp,
                              buckets_log2=buckets_log2, max_spawns=max_spawns, stream=stream,
-                             replica=replica, max_dets=max_dets)
+                             replica=replica, max_dets=max_dets, adaptive=adaptive)
     ra, rb = ref_of(s)
     words = det_words if det_words else (1 if s.n_orb <= 32 else 2)
     osys = oracle.System.from_inputs(s, words=words)
     orun = oracle.Run(osys, ref=(ra, rb), tau=tau, target=target, n_a=n_a, c_min=c_min,
                       zeta=zeta, p_single=p_single, p_opp=p_opp, interval=interval,
                       mode=oracle.MODE_INTEGER if mode == "integer" else oracle.MODE_REAL,
-                      gen=o, seed=seed, replica=replica)
+                      gen=o, seed=seed, replica=replica, adaptive=adaptive)
     orun.set_walkers([ra], [rb], [n_initial])
     return sysd, run, orun
 
