@@ -571,6 +571,39 @@ def measure_pt2(F, np, torch, steps):
     return out
 
 
+ADA_DESC = {"workload": "synthetic_molecule_8e8o_4900dets_initiator", "walkers_target": 500,
+            "tau": 0.01, "initiator_na": 3, "walkers": "integer", "shift_damping": 0.05,
+            "det_bits": 64}
+
+
+def measure_adaptive(F, np, torch, steps):
+    """Initiator bias with and without the adaptive shift: the 8-orbital
+    molecule at a small walker number (500, n_a = 3), each run grown from
+    the reference and stepped `steps` times; blocked energies and time per
+    step (the exact ground state of this system is in the docs)."""
+    from paper_2006_14956_amd import inputs
+    s = inputs.molecule_8o8e()
+    sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
+    out = {"config": dict(ADA_DESC, steps=steps)}
+    for name, ada in (("initiator", 0), ("adaptive_shift", 1)):
+        p = F.fciqmc_params_default(tau=0.01, walker_target=500.0, initiator_na=3.0, seed=1,
+                                    shift_damping=0.05, n_initial=10.0, adaptive_shift=ada)
+        run = F.fciqmc_init(sysd, p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F.fciqmc_step(run, steps, as_array=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        e = F.fciqmc_energy(run)
+        out[name] = {"ms_per_step": 1e3 * wall / steps, "e_proj": e["e_proj"], "e_proj_err": e["e_proj_err"],
+                     "shift": e["shift"], "shift_err": e["shift_err"], "n_samples": e["n_samples"]}
+        log(f"[adaptive] {name}: {1e3 * wall / steps:.4f} ms/step, E_proj {e['e_proj']:.6f} +- "
+            f"{e['e_proj_err']:.1e}, shift {e['shift']:.6f} +- {e['shift_err']:.1e}")
+        F.fciqmc_free_run(run)
+    F.fciqmc_free_system(sysd)
+    return out
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -641,6 +674,9 @@ def main():
     ap.add_argument("--pt2", type=int, default=20000, metavar="STEPS",
                     help="lockstep steps of the replica-pair PT2 leg (0 to skip)")
     ap.add_argument("--pt2-only", action="store_true", help="only run the PT2 leg")
+    ap.add_argument("--adaptive", type=int, default=100000, metavar="STEPS",
+                    help="steps of each run of the adaptive-shift leg (0 to skip)")
+    ap.add_argument("--adaptive-only", action="store_true", help="only run the adaptive-shift leg")
     ap.add_argument("--semistoch-only", action="store_true",
                     help="only run the semi-stochastic comparison")
     ap.add_argument("--generators-only", action="store_true",
@@ -670,6 +706,9 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.adaptive_only:
+        print(json.dumps(measure_adaptive(F, np, torch, args.adaptive or 100000)), flush=True)
+        return
     if args.pt2_only:
         print(json.dumps(measure_pt2(F, np, torch, args.pt2 or 20000)), flush=True)
         return
@@ -734,6 +773,10 @@ def main():
     if args.semistoch:
         semistoch = measure_semistoch(F, np, torch, args.semistoch, args.semistoch_core)
 
+    adaptive = None
+    if args.adaptive:
+        adaptive = measure_adaptive(F, np, torch, args.adaptive)
+
     pt2 = None
     if args.pt2:
         pt2 = measure_pt2(F, np, torch, args.pt2)
@@ -769,6 +812,7 @@ def main():
         "generators": generators,
         "semistoch": semistoch,
         "pt2": pt2,
+        "adaptive_shift": adaptive,
         "batched": batched,
         "served": served,
     }
