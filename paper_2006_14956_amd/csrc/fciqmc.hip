@@ -557,8 +557,12 @@ template <int W, class V> struct Engine : EngineBase {
         if (ncore > 0 && !sc.import_mode)
             hipLaunchKernelGGL(k_core_spmv, dim3((unsigned)((ncore + 3) / 4)), dim3(kThreads), 0, stream, core_rowp,
                                core_col, core_val, core_cdiag, core_cv[cur], core_dv, ncore, rs.tau, sc.S);
-        hipLaunchKernelGGL((k_annihilate<W, V>), dim3(gb), dim3(kThreads), 0, stream, v, in, out, sc,
-                           rec2, soff, scount, rel, need_b, recs_b, nw_b, en_b, fpos, fcnt, ctl);
+        if (ext())
+            hipLaunchKernelGGL((k_annihilate<W, V, true>), dim3(gb), dim3(kThreads), 0, stream, v, in, out, sc,
+                               rec2, soff, scount, rel, need_b, recs_b, nw_b, en_b, fpos, fcnt, ctl);
+        else
+            hipLaunchKernelGGL((k_annihilate<W, V, false>), dim3(gb), dim3(kThreads), 0, stream, v, in, out, sc,
+                               rec2, soff, scount, rel, need_b, recs_b, nw_b, en_b, fpos, fcnt, ctl);
         if (!sys->onsite) {
             const int64_t items = fresh_items(B);
             hipLaunchKernelGGL((k_fresh<W, V>), dim3((unsigned)std::min<int64_t>(items, 4096)), dim3(kThreads),
@@ -830,32 +834,29 @@ template <int W, class V> struct Engine : EngineBase {
         return 0;
     }
 
+    // The step's extensions (deterministic space, discarded-spawn records,
+    // adaptive shift) run in their own kernel instantiations, so the plain
+    // step keeps the code it had without them.
+    bool ext() const { return ncore > 0 || keep_rej || rs.adaptive; }
+    template <int GEN> void launch_spawn_g(const Store<V>& in, const StepScalars& sc, unsigned blocks) {
+        const SysView v = sys->view();
+        if (ext())
+            hipLaunchKernelGGL((k_spawn<W, V, GEN, true>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
+                               soff, scount, ctl, cmap, cap_cmap);
+        else
+            hipLaunchKernelGGL((k_spawn<W, V, GEN, false>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
+                               soff, scount, ctl, cmap, cap_cmap);
+    }
     // Spawn from store `in` with `grid` workgroups (the kernel reads the
     // chunk count from the device and strides over it).
     int launch_spawn(const Store<V>& in, const StepScalars& sc, int64_t grid) {
-        const SysView v = sys->view();
         const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(grid, 1 << 30));
         switch (rs.gen) {
-            case FCIQMC_GEN_UNIFORM:
-                hipLaunchKernelGGL((k_spawn<W, V, 0>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
-                                   soff, scount, ctl, cmap, cap_cmap);
-                break;
-            case FCIQMC_GEN_LATTICE:
-                hipLaunchKernelGGL((k_spawn<W, V, 1>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
-                                   soff, scount, ctl, cmap, cap_cmap);
-                break;
-            case FCIQMC_GEN_PCHB:
-                hipLaunchKernelGGL((k_spawn<W, V, 2>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
-                                   soff, scount, ctl, cmap, cap_cmap);
-                break;
-            case FCIQMC_GEN_CS:
-                hipLaunchKernelGGL((k_spawn<W, V, 3>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
-                                   soff, scount, ctl, cmap, cap_cmap);
-                break;
-            default:
-                hipLaunchKernelGGL((k_spawn<W, V, 4>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
-                                   soff, scount, ctl, cmap, cap_cmap);
-                break;
+            case FCIQMC_GEN_UNIFORM: launch_spawn_g<0>(in, sc, blocks); break;
+            case FCIQMC_GEN_LATTICE: launch_spawn_g<1>(in, sc, blocks); break;
+            case FCIQMC_GEN_PCHB: launch_spawn_g<2>(in, sc, blocks); break;
+            case FCIQMC_GEN_CS: launch_spawn_g<3>(in, sc, blocks); break;
+            default: launch_spawn_g<4>(in, sc, blocks); break;
         }
         HIP_OK(hipGetLastError());
         return 0;

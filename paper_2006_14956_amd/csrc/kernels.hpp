@@ -157,7 +157,7 @@ template <int W> __device__ __forceinline__ int64_t core_find(const StepScalars&
 // (Sec. II).  Attempts are numbered globally by the prefix sums of the
 // attempt counts; each lane finds its (bucket, entry, k) by binary search.
 // ---------------------------------------------------------------------------
-template <int W, class V, int GEN>
+template <int W, class V, int GEN, bool EXT>
 __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& st, const StepScalars& sc,
                                             Rec<W, V>* __restrict__ rec2, const int64_t* __restrict__ soff,
                                             int32_t* __restrict__ scount, Ctl* ctl,
@@ -193,7 +193,8 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
             const V C = st.vals[e];
             const double aC = vabs(C);
             // determinants of the deterministic space count as initiators
-            const bool pcore = sc.ncore > 0 && is_core(st.diag[e]);
+            bool pcore = false;
+            if constexpr (EXT) pcore = sc.ncore > 0 && is_core(st.diag[e]);
             const bool init = pcore || (sc.n_a < 0.0) || (aC > sc.n_a) || key_eq<W>(key, ref);
             const uint64_t da = key_alpha<W>(key), db = key_beta<W>(key);
             const R4 r = draw<W>(key, sc.t, k, kSpawn, sc.seed, sc.replica);
@@ -209,7 +210,8 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
                 ok = gen_cs<GEN == 4>(sys, da, db, r, r2, sc.p_single, sc.p_double, sc.p_opp, x);
             }
             // spawns from the deterministic space into it are part of P^D
-            if (ok && pcore && core_find<W>(sc, make_key<W>(x.ta, x.tb)) >= 0) ok = false;
+            if constexpr (EXT)
+                if (ok && pcore && core_find<W>(sc, make_key<W>(x.ta, x.tb)) >= 0) ok = false;
             if (ok && x.H != 0.0) {
                 const double u = unif(r.x[3]);
                 if constexpr (sizeof(V) == 4) {
@@ -238,8 +240,10 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
                     if (amp != 0.0) { out.v = (V)amp; emit = true; }
                 }
                 if (emit) {
-                    if (!init) out_parent = e;
-                    out_h = fabs(x.H);
+                    if constexpr (EXT) {
+                        if (!init) out_parent = e;
+                        out_h = fabs(x.H);
+                    }
                     const Key<W> tk = make_key<W>(x.ta, x.tb);
 #pragma unroll
                     for (int w = 0; w < W; ++w) out.k[w] = tk.w[w];
@@ -253,7 +257,7 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
             const int64_t pos = (int64_t)atomicAdd(&scount[j], 1);
             if (soff[j] + pos < soff[j + 1] && soff[j] + pos < sc.spawn_cap) {
                 rec2[soff[j] + pos] = out;
-                if (sc.rec_par) {
+                if (EXT && sc.rec_par) {
                     sc.rec_par[soff[j] + pos] = (out_parent < 0) ? -1 : out_parent;
                     sc.rec_h[soff[j] + pos] = out_h;
                 }
@@ -265,7 +269,7 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
     __syncthreads();  // smpre is reused by the workgroup's next chunk
 }
 
-template <int W, class V, int GEN>
+template <int W, class V, int GEN, bool EXT>
 __global__ __launch_bounds__(kThreads) void k_spawn(SysView sys, Store<V> st, StepScalars sc,
                                                     Rec<W, V>* __restrict__ rec2,
                                                     const int64_t* __restrict__ soff,
@@ -280,7 +284,7 @@ __global__ __launch_bounds__(kThreads) void k_spawn(SysView sys, Store<V> st, St
         return;
     }
     for (int64_t g = blockIdx.x; g < n; g += gridDim.x)
-        spawn_chunk<W, V, GEN>(sys, st, sc, rec2, soff, scount, ctl, cmap, g, smpre);
+        spawn_chunk<W, V, GEN, EXT>(sys, st, sc, rec2, soff, scount, ctl, cmap, g, smpre);
 }
 
 // Records uploaded from the host (population import): assign buckets.
@@ -533,7 +537,7 @@ __device__ __forceinline__ unsigned wg_flags(const Ctl* ctl, unsigned* sh) {
     return f;
 }
 
-template <int W, class V>
+template <int W, class V, bool EXT>
 __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Store<V>& in, const Store<V>& out,
                                                   const StepScalars& sc, const Rec<W, V>* __restrict__ rec2,
                                                   int64_t* __restrict__ soff, int32_t* __restrict__ scount,
@@ -604,12 +608,12 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
             d = in.diag[eb + e];
         }
         V post;
-        if (sc.ncore > 0 && is_core(d)) {
+        if (EXT && sc.ncore > 0 && is_core(d)) {
             // deterministic space: P^D C, diagonal included, unrounded
             post = (V)sc.core_d[core_index(d)];
         } else {
             double Sx = sc.S;
-            if (sc.ada_all) {
+            if (EXT && sc.ada_all) {
                 // adaptive shift: a non-initiator's local shift f S
                 const bool ini = (sc.n_a < 0.0) || (vabs(C) > sc.n_a) || key_eq<W>(key, ref);
                 const int64_t T = sc.ada_all[eb + e];
@@ -664,7 +668,7 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
         if (init || L.t.idx[s] >= 0) lds_add<V>(&L.t.val[s], x.v);
     }
     __syncthreads();
-    if (sc.rej != nullptr && !sc.import_mode) {
+    if (EXT && sc.rej != nullptr && !sc.import_mode) {
         // discarded spawns: non-initiator records whose target is in neither
         // the population at tau nor the new one (no initiator spawn reached
         // it), kept in record order in the bucket's region of the buffer
@@ -729,7 +733,7 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
         int64_t ck = 0;
         if (k0 != kEmpty) {
             v = L.t.val[s];
-            if (sc.ncore > 0 && L.t.idx[s] >= 0) {
+            if (EXT && sc.ncore > 0 && L.t.idx[s] >= 0) {
                 const double dd = in.diag[eb + L.t.idx[s]];
                 if (is_core(dd)) { core = true; ck = core_index(dd); }
             }
@@ -758,7 +762,7 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
             store_key<W>(out.keys + o * W, key);
             out.vals[o] = v;
             out.mpre[o] = (int32_t)mp;
-            if (core) sc.core_c[ck] = (double)v;
+            if (EXT && core) sc.core_c[ck] = (double)v;
             const int oi = L.t.idx[s];
             const uint64_t ka = key_alpha<W>(key), kb = key_beta<W>(key);
             if (oi >= 0) {
@@ -823,7 +827,7 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
     __syncthreads();
 }
 
-template <int W, class V>
+template <int W, class V, bool EXT>
 __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> in, Store<V> out,
                                                          StepScalars sc,
                                                          const Rec<W, V>* __restrict__ rec2,
@@ -840,7 +844,7 @@ __global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> i
     __shared__ unsigned fl;
     if (wg_flags(ctl, &fl)) return;
     for (int b = blockIdx.x; b < sc.B; b += gridDim.x)
-        annihilate_bucket<W, V>(sys, in, out, sc, rec2, soff, scount, rel, need_b, recs_b, nw_b, en_b, fpos, fcnt,
+        annihilate_bucket<W, V, EXT>(sys, in, out, sc, rec2, soff, scount, rel, need_b, recs_b, nw_b, en_b, fpos, fcnt,
                                 ctl, b, L);
 }
 
@@ -1181,7 +1185,7 @@ __global__ __launch_bounds__(kThreads) void k_spawn_batch(const Inst<W, V>* __re
     for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
         const int i = owner_of(first, k, g);
         const Inst<W, V>& I = inst[i];
-        spawn_chunk<W, V, GEN>(I.sys, I.in, I.sc, I.rec2, I.soff, I.scount, I.ctl, I.cmap, g - first[i], smpre);
+        spawn_chunk<W, V, GEN, false>(I.sys, I.in, I.sc, I.rec2, I.soff, I.scount, I.ctl, I.cmap, g - first[i], smpre);
     }
 }
 
@@ -1195,7 +1199,7 @@ __global__ __launch_bounds__(kThreads, 6) void k_annihilate_batch(const Inst<W, 
         const int i = owner_of(first, k, g);
         const Inst<W, V>& I = inst[i];
         if (wg_flags(I.ctl, &fl)) continue;  // this instance replays its step alone
-        annihilate_bucket<W, V>(I.sys, I.in, I.out, I.sc, I.rec2, I.soff, I.scount, I.rel, I.need_b, I.recs_b,
+        annihilate_bucket<W, V, false>(I.sys, I.in, I.out, I.sc, I.rec2, I.soff, I.scount, I.rel, I.need_b, I.recs_b,
                                 I.nw_b, I.en_b, I.fpos, I.fcnt, I.ctl, (int)(g - first[i]), L);
     }
 }
