@@ -75,6 +75,48 @@ def test_pair_correction_matches_oracle(words):
     F.fciqmc_free_system(sysd)
 
 
+def test_pair_through_store_growth():
+    """Both replicas start on two buckets and grow from 1000 walkers on the
+    reference to most of the 4900 determinants, so a store outgrows the
+    common bucket count: that step's dE2 is NaN, both
+    stores are re-bucketed, and every other step equals the oracle."""
+    s = inputs.molecule_8o8e()
+    sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
+    ra, rb = ref_of(s)
+    osys = oracle.System.from_inputs(s)
+    gpu, orc = [], []
+    for rep in (0, 1):
+        _, run = make_gpu_run(s, tau=0.02, target=1e9, n_a=3.0, seed=4, replica=rep, sysd=sysd,
+                              buckets_log2=1, n_initial=1000.0)
+        o = oracle.Run(osys, ref=(ra, rb), tau=0.02, target=1e9, n_a=3.0, seed=4, replica=rep)
+        o.set_walkers([ra], [rb], [1000.0])
+        o.collect_rejected(True)
+        gpu.append(run)
+        orc.append(o)
+    pair = F.fciqmc_pair_create(gpu[0], gpu[1])
+    skipped = 0
+    for step in range(120):
+        g1, g2, d = F.fciqmc_pair_step(pair, 1)
+        ovl = oracle.pair_overlap(orc[0], orc[1])
+        o1 = orc[0].step(1)
+        o2 = orc[1].step(1)
+        assert_same_stats(g1[0], o1[0])
+        assert_same_stats(g2[0], o2[0])
+        want = oracle.pair_pt2(orc[0], orc[1]) / ovl
+        if math.isnan(d[0]):
+            skipped += 1
+            continue
+        assert abs(d[0] - want) <= 1e-10 * max(1e-12, abs(want)), (step, d[0], want)
+    assert skipped >= 1
+    assert F.fciqmc_profile(gpu[0], False)[2]["buckets"] > 2
+    rep = F.fciqmc_pair_pt2(pair)
+    assert rep["n"] == 120 - skipped
+    F.fciqmc_pair_free(pair)
+    for g in gpu:
+        F.fciqmc_free_run(g)
+    F.fciqmc_free_system(sysd)
+
+
 def test_pair_without_initiator_rule_is_zero():
     """No initiator rule: nothing is discarded and dE2 is 0 every step."""
     s = inputs.synthetic_molecule(10, 4, 3, seed=7)
