@@ -321,6 +321,7 @@ template <int W, class V> struct Engine : EngineBase {
     int64_t* ada_all = nullptr;
     bool keep_rej = false;
     Rec<W, V>* rej = nullptr;
+    long long cap_rej = 0;
     int64_t* rej_off = nullptr;
     int32_t* rej_cnt = nullptr;
     hipEvent_t ev[2][kKernels + 1]{};
@@ -453,11 +454,6 @@ template <int W, class V> struct Engine : EngineBase {
         rec2 = nullptr;
         cap = c + c / 4;
         CHECK(dalloc(arena, &rec2, (size_t)cap));
-        if (keep_rej) {
-            arena.release(rej);
-            rej = nullptr;
-            CHECK(dalloc(arena, &rej, (size_t)cap));
-        }
         if (rs.adaptive) {
             arena.release(rec_par);
             arena.release(rec_h);
@@ -466,6 +462,17 @@ template <int W, class V> struct Engine : EngineBase {
             CHECK(dalloc(arena, &rec_par, (size_t)cap));
             CHECK(dalloc(arena, &rec_h, (size_t)cap));
         }
+        return 0;
+    }
+    // The discarded-spawn buffer follows the slab capacity, but is replaced
+    // only right before a merge: the records of the last accepted step stay
+    // readable after it (a replica pair sums them then).
+    int ensure_rej() {
+        if (!keep_rej || cap_rej >= cap) return 0;
+        arena.release(rej);
+        rej = nullptr;
+        CHECK(dalloc(arena, &rej, (size_t)cap));
+        cap_rej = cap;
         return 0;
     }
     int ensure_stage(long long c) {
@@ -787,10 +794,12 @@ template <int W, class V> struct Engine : EngineBase {
             arena.release(rej); arena.release(rej_off); arena.release(rej_cnt);
             rej = nullptr; rej_off = nullptr; rej_cnt = nullptr;
             keep_rej = false;
+            cap_rej = 0;
             return 0;
         }
         keep_rej = true;
-        CHECK(dalloc(arena, &rej, (size_t)std::max<long long>(cap, 1)));
+        cap_rej = std::max<long long>(cap, 1);
+        CHECK(dalloc(arena, &rej, (size_t)cap_rej));
         return alloc_rej_index();
     }
     void* rej_records() const override { return rej; }
@@ -914,6 +923,7 @@ template <int W, class V> struct Engine : EngineBase {
     // the scalars.
     int run_alone(int64_t t, double S, int& retries, bool ahead) {
         for (;;) {
+            CHECK(ensure_rej());
             const StepScalars sc = scalars(t, S, 0);
             const int set = sampled(t) ? (int)(t & 1) : -1;
             if (!pending) {

@@ -440,7 +440,10 @@ __device__ __forceinline__ int lds_find(T& tab, const Key<W>& key, uint64_t h, u
             if (w0 == key.w[0]) return s;
         }
         s = (s + 1) & (int)mask;
-        if (++probes > (int)mask) return -2;
+        // every slot visited: a full table cannot take the key, and a lookup
+        // has seen every key there is (one that runs while other lanes still
+        // insert may find the table full only because of them)
+        if (++probes > (int)mask) return insert ? -2 : -1;
     }
 }
 
