@@ -719,54 +719,65 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
         }
         recs_b[b] = cum[kSub];
     }
-    // compaction in passes of kThreads consecutive slots: rounding of small
-    // real amplitudes, output positions and attempt prefixes by a block
-    // scan of (kept, attempts) packed as kept << 40 | attempts
-    int64_t obase = 0, mbase = 0;
-    double nw = 0.0, en = 0.0;
-    bool over = false;
-    for (int p0 = 0; p0 < nslots; p0 += kThreads) {
-        const int s = p0 + threadIdx.x;
+    // compaction: (1) each thread rounds its run of nslots / kThreads
+    // consecutive slots in place (small real amplitudes) and drops what it
+    // does not keep; (2) one block scan of (kept << 40 | attempts) over the
+    // runs gives each run's output position and attempt prefix, so the
+    // output stays in slot order; (3) the runs are written out.
+    const int run_len = nslots / kThreads;
+    const int s0 = (int)threadIdx.x * run_len;
+    int64_t mine = 0;
+    for (int j = 0; j < run_len; ++j) {
+        const int s = s0 + j;
         const uint64_t k0 = L.t.key0[s];
-        V v = (V)0;
-        Key<W> key;
-        key.w[0] = k0;
-        if constexpr (W == 2) key.w[1] = L.t.key1[s];
+        if (k0 == kEmpty) continue;
+        V v = L.t.val[s];
         bool core = false;
-        int64_t ck = 0;
-        if (k0 != kEmpty) {
-            v = L.t.val[s];
-            if (EXT && sc.ncore > 0 && L.t.idx[s] >= 0) {
-                const double dd = in.diag[eb + L.t.idx[s]];
-                if (is_core(dd)) { core = true; ck = core_index(dd); }
-            }
-            if constexpr (!kInt) {
-                const double av = fabs((double)v);
-                if (!core && !sc.import_mode && v != 0.0 && av < sc.c_min) {
-                    const double u = unif(draw<W>(key, sc.t, 0, kAnn, sc.seed, sc.replica).x[0]);
-                    const double pr = av / sc.c_min;
-                    v = (u < pr) ? (v < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
-                }
+        if (EXT && sc.ncore > 0 && L.t.idx[s] >= 0) core = is_core(in.diag[eb + L.t.idx[s]]);
+        if constexpr (!kInt) {
+            const double av = fabs((double)v);
+            if (!core && !sc.import_mode && v != 0.0 && av < sc.c_min) {
+                Key<W> key;
+                key.w[0] = k0;
+                if constexpr (W == 2) key.w[1] = L.t.key1[s];
+                const double u = unif(draw<W>(key, sc.t, 0, kAnn, sc.seed, sc.replica).x[0]);
+                const double pr = av / sc.c_min;
+                v = (u < pr) ? (v < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
+                L.t.val[s] = v;
             }
         }
         // the deterministic space stays at any value; an import keeps every
         // entry it was given
-        const bool keep = v != (V)0 || core || (sc.import_mode && k0 != kEmpty);
-        const int64_t m = keep ? n_attempts(v) : 0;
-        int64_t tot;
-        const int64_t ex = block_excl_scan<kThreads, int64_t>(keep ? ((1LL << 40) | m) : 0, tot, L.sh64);
-        const int64_t pos = obase + (ex >> 40);
-        const int64_t mp = mbase + (ex & kM40);
-        obase += tot >> 40;
-        mbase += tot & kM40;
-        if (obase > sc.R || mbase >= (int64_t)0x7FFFFFFF) { over = true; break; }
-        if (keep) {
+        const bool keep = v != (V)0 || core || sc.import_mode;
+        if (keep) mine += (1LL << 40) | n_attempts(v);
+        else L.t.key0[s] = kEmpty;
+    }
+    int64_t tot;
+    const int64_t ex = block_excl_scan<kThreads, int64_t>(mine, tot, L.sh64);
+    const int64_t obase = tot >> 40, mbase = tot & kM40;
+    const bool over = obase > sc.R || mbase >= (int64_t)0x7FFFFFFF;
+    double nw = 0.0, en = 0.0;
+    if (!over) {
+        int64_t pos = ex >> 40, mp = ex & kM40;
+        for (int j = 0; j < run_len; ++j) {
+            const int s = s0 + j;
+            const uint64_t k0 = L.t.key0[s];
+            if (k0 == kEmpty) continue;
+            Key<W> key;
+            key.w[0] = k0;
+            if constexpr (W == 2) key.w[1] = L.t.key1[s];
+            const V v = L.t.val[s];
             const int64_t o = eb + pos;
             store_key<W>(out.keys + o * W, key);
             out.vals[o] = v;
             out.mpre[o] = (int32_t)mp;
-            if (EXT && core) sc.core_c[ck] = (double)v;
             const int oi = L.t.idx[s];
+            if constexpr (EXT) {
+                if (sc.ncore > 0 && oi >= 0) {
+                    const double dd = in.diag[eb + oi];
+                    if (is_core(dd)) sc.core_c[core_index(dd)] = (double)v;
+                }
+            }
             const uint64_t ka = key_alpha<W>(key), kb = key_beta<W>(key);
             if (oi >= 0) {
                 out.diag[o] = in.diag[eb + oi];
@@ -793,6 +804,8 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
                     en = en + c;
                 }
             }
+            pos += 1;
+            mp += n_attempts(v);
         }
     }
     if (over) {
@@ -831,7 +844,7 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
 }
 
 template <int W, class V, bool EXT>
-__global__ __launch_bounds__(kThreads) void k_annihilate(SysView sys, Store<V> in, Store<V> out,
+__global__ __launch_bounds__(kThreads, 6) void k_annihilate(SysView sys, Store<V> in, Store<V> out,
                                                          StepScalars sc,
                                                          const Rec<W, V>* __restrict__ rec2,
                                                          int64_t* __restrict__ soff,

@@ -84,7 +84,8 @@ def assert_same_walkers(run, orun, exact=True, rtol=0.0):
 
 
 def enum_tol(x):
-    # estimator sums run in different orders; see the design doc (tolerances)
+    # estimator sums run in different orders on the two sides: their fp64
+    # rounding stays many orders of magnitude below 1e-10 relative
     return 1e-10 * max(1.0, abs(x))
 
 
