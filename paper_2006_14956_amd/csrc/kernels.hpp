@@ -453,7 +453,12 @@ template <class V> __device__ __forceinline__ void lds_add(V* p, V v) {
 
 // ---------------------------------------------------------------------------
 // Global sums and next-step offsets (attempt prefix over buckets, record
-// sub-slab offsets), executed by one workgroup of NT threads.
+// sub-slab offsets), executed by one workgroup of NT threads, then the step
+// scalars written to `host` (pinned host memory).  The flag word, the
+// reference amplitude and the per-bucket values are loaded together, and the
+// host copy is composed from registers, so the kernel waits on memory twice
+// (loads, then the final stores) instead of once per stage.  A flagged step
+// writes no offsets; its host copy is the control block as the step left it.
 // ---------------------------------------------------------------------------
 template <int NT>
 __device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, const int32_t* __restrict__ count,
@@ -462,7 +467,13 @@ __device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, cons
                                           const int64_t* __restrict__ recs_b, int B,
                                           int64_t* __restrict__ aoff, int64_t* __restrict__ soff,
                                           int64_t* __restrict__ cmap, int64_t cmap_cap, Ctl* ctl,
-                                          int64_t* sh, double* shd, int64_t* shm) {
+                                          Ctl* __restrict__ host, int64_t* sh, double* shd, int64_t* shm,
+                                          unsigned* shf) {
+    double nref = 0.0;
+    if (threadIdx.x == 0) {
+        *shf = __hip_atomic_load(&ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        nref = ctl->nref;
+    }
     // one pass of loads (all per-bucket values of this thread's run of
     // buckets), the scans, then one pass of writes
     const int per = (B + NT - 1) / NT;
@@ -481,19 +492,23 @@ __device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, cons
         en = en + en_b[b];
     }
     // attempts, chunks, slab sizes, and determinants (< 2^32) with records
-    // (< 2^31 per step) packed: four prefix sums in one exchange
+    // (< 2^31 per step) packed: four prefix sums in one exchange (whose
+    // barrier also publishes the flag word)
     int64_t v[4] = {la, lk, ln, (cnt << 32) | rc};
     int64_t tot[4];
     block_excl_scan4<NT>(v, tot, sh);
+    const unsigned flags = *shf;
     const int64_t atot = tot[0], ktot = tot[1], ntot = tot[2], crtot = tot[3];
-    int64_t run = v[1], base = v[2];
-    for (int b = b0; b < b1; ++b) {
-        aoff[b] = run;
-        const int64_t nk = chunks_of(batt[b]);
-        for (int64_t c = 0; c < nk && run + c < cmap_cap; ++c) cmap[run + c] = ((int64_t)b << 32) | c;
-        run += nk;
-        for (int j = 0; j < kSub; ++j) soff[(int64_t)b * kSub + j] = base + rel[(int64_t)b * kSub + j];
-        base += need_b[b];
+    if (flags == 0) {
+        int64_t run = v[1], base = v[2];
+        for (int b = b0; b < b1; ++b) {
+            aoff[b] = run;
+            const int64_t nk = chunks_of(batt[b]);
+            for (int64_t c = 0; c < nk && run + c < cmap_cap; ++c) cmap[run + c] = ((int64_t)b << 32) | c;
+            run += nk;
+            for (int j = 0; j < kSub; ++j) soff[(int64_t)b * kSub + j] = base + rel[(int64_t)b * kSub + j];
+            base += need_b[b];
+        }
     }
     // N_w and the E_proj numerator in a fixed order: per-thread runs, wave
     // butterflies, waves in order
@@ -504,22 +519,31 @@ __device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, cons
     if (lane_id() == 0) { shd[w] = nw; shd[NT / 64 + w] = en; shm[w] = mx; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double a = 0.0, c = 0.0;
-        int64_t m = 0;
-        for (int i = 0; i < NT / 64; ++i) { a = a + shd[i]; c = c + shd[NT / 64 + i]; m = max(m, shm[i]); }
-        aoff[B] = ktot;
-        soff[(int64_t)B * kSub] = ntot;
-        ctl->nw = a;
-        ctl->enum_ = c;
-        ctl->ndets = crtot >> 32;
-        ctl->attempts = atot;
-        ctl->chunks = ktot;
-        ctl->nrec_out = crtot & 0xFFFFFFFFLL;
-        ctl->max_count = m;
-        ctl->nref_out = ctl->nref;
-        ctl->rec_need = ntot;
-        ctl->nrec = 0;
-        ctl->nref = 0.0;
+        if (flags != 0) {
+            *host = *ctl;
+        } else {
+            double a = 0.0, c = 0.0;
+            int64_t m = 0;
+            for (int i = 0; i < NT / 64; ++i) { a = a + shd[i]; c = c + shd[NT / 64 + i]; m = max(m, shm[i]); }
+            aoff[B] = ktot;
+            soff[(int64_t)B * kSub] = ntot;
+            Ctl h;
+            h.nrec = 0;
+            h.flags = 0;
+            h.pad0 = 0;
+            h.nref = 0.0;
+            h.nw = a;
+            h.enum_ = c;
+            h.ndets = crtot >> 32;
+            h.attempts = atot;
+            h.nrec_out = crtot & 0xFFFFFFFFLL;
+            h.max_count = m;
+            h.nref_out = nref;
+            h.rec_need = ntot;
+            h.chunks = ktot;
+            *ctl = h;
+            *host = h;
+        }
     }
     __syncthreads();
 }
@@ -1110,10 +1134,9 @@ __global__ __launch_bounds__(kPostThreads) void k_post(const int64_t* __restrict
                                                int64_t cmap_cap, Ctl* ctl, Ctl* __restrict__ host) {
     __shared__ int64_t sh[4 * kPostThreads / 64], shm[kPostThreads / 64];
     __shared__ double shd[2 * kPostThreads / 64];
-    if (!ctl->flags)
-        post_work<kPostThreads>(batt, count, nw_b, en_b, rel, need_b, recs_b, B, aoff, soff, cmap, cmap_cap, ctl,
-                                sh, shd, shm);
-    if (threadIdx.x == 0) *host = *ctl;
+    __shared__ unsigned shf;
+    post_work<kPostThreads>(batt, count, nw_b, en_b, rel, need_b, recs_b, B, aoff, soff, cmap, cmap_cap, ctl, host,
+                            sh, shd, shm, &shf);
 }
 
 // The chunk map from the chunk prefix (when the map had to grow after the
@@ -1246,10 +1269,8 @@ __global__ __launch_bounds__(kPostThreads) void k_post_batch(const Inst<W, V>* _
     __shared__ double shd[2 * kPostThreads / 64];
     __shared__ unsigned fl;
     const Inst<W, V>& I = inst[blockIdx.x];
-    if (!wg_flags(I.ctl, &fl))
-        post_work<kPostThreads>(I.out.batt, I.out.count, I.nw_b, I.en_b, I.rel, I.need_b, I.recs_b, I.sc.B,
-                                I.out.aoff, I.soff, I.cmap, I.cmap_cap, I.ctl, sh, shd, shm);
-    if (threadIdx.x == 0) ctl_out[blockIdx.x] = *I.ctl;
+    post_work<kPostThreads>(I.out.batt, I.out.count, I.nw_b, I.en_b, I.rel, I.need_b, I.recs_b, I.sc.B,
+                            I.out.aoff, I.soff, I.cmap, I.cmap_cap, I.ctl, ctl_out + blockIdx.x, sh, shd, shm, &fl);
 }
 
 // Copy the store to flat arrays (offsets from a count scan).
