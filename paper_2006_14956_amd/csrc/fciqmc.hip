@@ -469,6 +469,7 @@ template <int W, class V> struct Engine : EngineBase {
     // readable after it (a replica pair sums them then).
     int ensure_rej() {
         if (!keep_rej || cap_rej >= cap) return 0;
+        HIP_OK(hipStreamSynchronize(stream));  // a queued pair sum may still read the records
         arena.release(rej);
         rej = nullptr;
         CHECK(dalloc(arena, &rej, (size_t)cap));
@@ -2008,11 +2009,16 @@ struct fciqmc_pair {
     Arena arena;
     double* part = nullptr;  // per-bucket partial sums
     int64_t part_n = 0;
-    double* sum = nullptr;
+    double* res = nullptr;   // per paired step of a call: PT2 sum, overlap
+    int64_t res_n = 0;
     unsigned* err = nullptr;
+    hipEvent_t ev = nullptr;  // the pair kernels queued so far on the first replica's stream are done
     std::vector<double> num;  // per paired step: 1/dtau^2 sum S^1 S^2 / (E_0 - H_jj) (NaN: not evaluated)
     std::vector<double> ovl;  // and the replica overlap of the populations it began from
-    ~fciqmc_pair() { arena.clear(); }
+    ~fciqmc_pair() {
+        if (ev) (void)hipEventDestroy(ev);
+        arena.clear();
+    }
 };
 
 void pair_detach(fciqmc_run* run) {
@@ -2023,56 +2029,58 @@ void pair_detach(fciqmc_run* run) {
 }
 
 namespace {
-template <int W, class V> void launch_pt2(fciqmc_pair* p, int B, double e0, hipStream_t s) {
+template <int W, class V> void launch_pt2(fciqmc_pair* p, int B, double e0, double* out, hipStream_t s) {
     const EngineBase* a = p->r[0]->eng.get();
     const EngineBase* b = p->r[1]->eng.get();
     hipLaunchKernelGGL((k_pt2<W, V>), dim3((unsigned)std::min(B, 4096)), dim3(kThreads), 0, s,
                        p->r[0]->sys->view(), (const Rec<W, V>*)a->rej_records(), a->rej_offsets(),
                        a->rej_counts(), (const Rec<W, V>*)b->rej_records(), b->rej_offsets(), b->rej_counts(), B,
                        e0, p->r[0]->h00, p->part, p->err);
-    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, s, p->part, B, p->sum);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, s, p->part, B, out);
 }
-template <int W, class V> void launch_overlap(fciqmc_pair* p, int B, hipStream_t s) {
+template <int W, class V> void launch_overlap(fciqmc_pair* p, int B, double* out, hipStream_t s) {
     const Store<V> s1 = *static_cast<const Store<V>*>(p->r[0]->eng->current_store());
     const Store<V> s2 = *static_cast<const Store<V>*>(p->r[1]->eng->current_store());
     hipLaunchKernelGGL((k_overlap<W, V>), dim3((unsigned)std::min(B, 4096)), dim3(kThreads), 0, s, s1, s2,
                        p->r[0]->eng->bucket_entries(), B, p->part, p->err);
-    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, s, p->part, B, p->sum);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, s, p->part, B, out);
 }
-// Run the pair kernel `which` (0: PT2 sum, 1: overlap) over both replicas
-// (equal bucket counts) and return its value.
-int pair_kernel(fciqmc_pair* p, int which, double e0, double& out) {
+// Queue the pair kernel `which` (0: PT2 sum, 1: overlap) over both replicas
+// (equal bucket counts) on the first replica's stream; its value lands in
+// `out` (device memory).  No host wait here: the kernels read the second
+// replica's buffers, so the caller lets that replica step (or re-bucket)
+// only after the pair's event has completed.
+int pair_launch(fciqmc_pair* p, int which, double e0, double* out) {
     fciqmc_run* a = p->r[0];
-    fciqmc_run* b = p->r[1];
     const int B = (int)a->eng->buckets();
     if (p->part_n < B) {
+        HIP_OK(hipStreamSynchronize(a->stream));  // queued pair kernels still use the old buffer
         p->arena.release(p->part);
         p->part = nullptr;
         CHECK(dalloc(p->arena, &p->part, (size_t)B));
         p->part_n = B;
     }
-    HIP_OK(hipStreamSynchronize(b->stream));
-    HIP_OK(hipMemsetAsync(p->err, 0, sizeof(unsigned), a->stream));
     const int k = a->eng->kind();
     if (which == 0) {
-        if (k == 0) launch_pt2<1, int32_t>(p, B, e0, a->stream);
-        else if (k == 1) launch_pt2<1, double>(p, B, e0, a->stream);
-        else if (k == 2) launch_pt2<2, int32_t>(p, B, e0, a->stream);
-        else launch_pt2<2, double>(p, B, e0, a->stream);
+        if (k == 0) launch_pt2<1, int32_t>(p, B, e0, out, a->stream);
+        else if (k == 1) launch_pt2<1, double>(p, B, e0, out, a->stream);
+        else if (k == 2) launch_pt2<2, int32_t>(p, B, e0, out, a->stream);
+        else launch_pt2<2, double>(p, B, e0, out, a->stream);
     } else {
-        if (k == 0) launch_overlap<1, int32_t>(p, B, a->stream);
-        else if (k == 1) launch_overlap<1, double>(p, B, a->stream);
-        else if (k == 2) launch_overlap<2, int32_t>(p, B, a->stream);
-        else launch_overlap<2, double>(p, B, a->stream);
+        if (k == 0) launch_overlap<1, int32_t>(p, B, out, a->stream);
+        else if (k == 1) launch_overlap<1, double>(p, B, out, a->stream);
+        else if (k == 2) launch_overlap<2, int32_t>(p, B, out, a->stream);
+        else launch_overlap<2, double>(p, B, out, a->stream);
     }
     HIP_OK(hipGetLastError());
-    unsigned e = 0;
-    HIP_OK(hipMemcpyAsync(&out, p->sum, sizeof(double), hipMemcpyDeviceToHost, a->stream));
-    HIP_OK(hipMemcpyAsync(&e, p->err, sizeof(unsigned), hipMemcpyDeviceToHost, a->stream));
-    HIP_OK(hipStreamSynchronize(a->stream));
-    if (e) return fail(FCIQMC_EOVERFLOW, "a bucket holds more entries than the pair table (%d slots)", kPtSlots);
     return 0;
 }
+// Waits for a stream when it goes out of scope (also on an error return), so
+// that no queued pair kernel outlives the call that queued it.
+struct StreamWait {
+    hipStream_t s;
+    ~StreamWait() { (void)hipStreamSynchronize(s); }
+};
 }  // namespace
 
 extern "C" {
@@ -2091,8 +2099,8 @@ int fciqmc_pair_create(fciqmc_run* r1, fciqmc_run* r2, fciqmc_pair** out) {
     if (r1->p.seed == r2->p.seed && r1->p.replica_id == r2->p.replica_id)
         return fail(FCIQMC_EINVAL, "replicas need different random streams (replica_id or seed)");
     std::unique_ptr<fciqmc_pair> p(new fciqmc_pair());
-    CHECK(dalloc(p->arena, &p->sum, 1));
     CHECK(dalloc(p->arena, &p->err, 1));
+    HIP_OK(hipEventCreateWithFlags(&p->ev, hipEventDisableTiming));
     const int64_t B = std::max(r1->eng->buckets(), r2->eng->buckets());
     fciqmc_run* rr[2] = {r1, r2};
     for (int i = 0; i < 2; ++i) {
@@ -2114,25 +2122,54 @@ int fciqmc_pair_step(fciqmc_pair* p, int n_steps, fciqmc_step_stats* stats1, fci
     if (n_steps < 0) return fail(FCIQMC_EINVAL, "n_steps must be >= 0");
     fciqmc_run* a = p->r[0];
     fciqmc_run* b = p->r[1];
-    for (int i = 0; i < n_steps; ++i) {
-        const double e0 = (a->S + b->S) / 2.0;  // the shifts this step uses
-        double ovl = NAN;
-        if (a->eng->buckets() == b->eng->buckets()) CHECK(pair_kernel(p, 1, 0.0, ovl));
-        CHECK(fciqmc_step(a, 1, stats1 ? stats1 + i : nullptr));
-        CHECK(fciqmc_step(b, 1, stats2 ? stats2 + i : nullptr));
-        double num = NAN;
-        const int64_t Ba = a->eng->buckets(), Bb = b->eng->buckets();
-        if (Ba == Bb && !std::isnan(ovl)) {
-            double sum = 0.0;
-            CHECK(pair_kernel(p, 0, e0, sum));
-            num = sum / (a->p.tau * a->p.tau);
-        } else if (Ba != Bb) {
-            // a store outgrew its buckets during the step: this step is not
-            // evaluated, and both use the larger count from the next one
-            const int64_t B = std::max(Ba, Bb);
-            CHECK(a->eng->rebucket((int)B));
-            CHECK(b->eng->rebucket((int)B));
+    if (n_steps == 0) return 0;
+    if (p->res_n < 2 * (int64_t)n_steps) {
+        HIP_OK(hipStreamSynchronize(a->stream));
+        p->arena.release(p->res);
+        p->res = nullptr;
+        CHECK(dalloc(p->arena, &p->res, (size_t)2 * n_steps));
+        p->res_n = 2 * (int64_t)n_steps;
+    }
+    std::vector<char> has_ovl((size_t)n_steps, 0), has_num((size_t)n_steps, 0);
+    std::vector<double> e0s((size_t)n_steps, 0.0);
+    {
+        StreamWait wait{a->stream};
+        HIP_OK(hipMemsetAsync(p->err, 0, sizeof(unsigned), a->stream));
+        for (int i = 0; i < n_steps; ++i) {
+            e0s[i] = (a->S + b->S) / 2.0;  // the shifts this step uses
+            if (a->eng->buckets() == b->eng->buckets()) {
+                CHECK(pair_launch(p, 1, 0.0, p->res + 2 * i + 1));
+                has_ovl[i] = 1;
+            }
+            HIP_OK(hipEventRecord(p->ev, a->stream));
+            CHECK(fciqmc_step(a, 1, stats1 ? stats1 + i : nullptr));
+            // the pair kernels queued before this step (overlap, last PT2
+            // sum) read the second replica's store and records: done before
+            // it steps (normally already, since the host waited for the
+            // first replica's step behind them)
+            HIP_OK(hipEventSynchronize(p->ev));
+            CHECK(fciqmc_step(b, 1, stats2 ? stats2 + i : nullptr));
+            const int64_t Ba = a->eng->buckets(), Bb = b->eng->buckets();
+            if (Ba == Bb && has_ovl[i]) {
+                CHECK(pair_launch(p, 0, e0s[i], p->res + 2 * i));
+                has_num[i] = 1;
+            } else if (Ba != Bb) {
+                // a store outgrew its buckets during the step: this step is not
+                // evaluated, and both use the larger count from the next one
+                const int64_t B = std::max(Ba, Bb);
+                CHECK(a->eng->rebucket((int)B));
+                CHECK(b->eng->rebucket((int)B));
+            }
         }
+    }
+    std::vector<double> h((size_t)2 * n_steps, 0.0);
+    unsigned e = 0;
+    HIP_OK(hipMemcpy(h.data(), p->res, sizeof(double) * 2 * n_steps, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(&e, p->err, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (e) return fail(FCIQMC_EOVERFLOW, "a bucket holds more entries than the pair table (%d slots)", kPtSlots);
+    for (int i = 0; i < n_steps; ++i) {
+        const double num = has_num[i] ? h[2 * i] / (a->p.tau * a->p.tau) : NAN;
+        const double ovl = has_ovl[i] ? h[2 * i + 1] : NAN;
         p->num.push_back(num);
         p->ovl.push_back(ovl);
         if (de2) de2[i] = num / ovl;
