@@ -117,6 +117,51 @@ def test_pair_through_store_growth():
     F.fciqmc_free_system(sysd)
 
 
+def test_pair_multi_step_calls_through_growth():
+    """The growth scenario again, in calls of 7 paired steps: the values a
+    call gathers from the device at its end are, step by step, the oracle's
+    (NaN where a store outgrew the common bucket count), and the per-step
+    statistics of both replicas agree with it."""
+    s = inputs.molecule_8o8e()
+    sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
+    ra, rb = ref_of(s)
+    osys = oracle.System.from_inputs(s)
+    gpu, orc = [], []
+    for rep in (0, 1):
+        _, run = make_gpu_run(s, tau=0.02, target=1e9, n_a=3.0, seed=4, replica=rep, sysd=sysd,
+                              buckets_log2=1, n_initial=1000.0)
+        o = oracle.Run(osys, ref=(ra, rb), tau=0.02, target=1e9, n_a=3.0, seed=4, replica=rep)
+        o.set_walkers([ra], [rb], [1000.0])
+        o.collect_rejected(True)
+        gpu.append(run)
+        orc.append(o)
+    pair = F.fciqmc_pair_create(gpu[0], gpu[1])
+    skipped = evaluated = 0
+    for call in range(9):
+        g1, g2, d = F.fciqmc_pair_step(pair, 7)
+        assert len(d) == 7 and len(g1) == 7 and len(g2) == 7
+        for i in range(7):
+            ovl = oracle.pair_overlap(orc[0], orc[1])
+            o1 = orc[0].step(1)
+            o2 = orc[1].step(1)
+            assert_same_stats(g1[i], o1[0])
+            assert_same_stats(g2[i], o2[0])
+            if math.isnan(d[i]):
+                skipped += 1
+                continue
+            want = oracle.pair_pt2(orc[0], orc[1]) / ovl
+            assert abs(d[i] - want) <= 1e-10 * max(1e-12, abs(want)), (call, i, d[i], want)
+            evaluated += 1
+    assert skipped >= 1 and evaluated >= 50
+    for g, o in zip(gpu, orc):
+        assert_same_walkers(g, o)
+    assert F.fciqmc_pair_pt2(pair)["n"] == evaluated
+    F.fciqmc_pair_free(pair)
+    for g in gpu:
+        F.fciqmc_free_run(g)
+    F.fciqmc_free_system(sysd)
+
+
 def test_pair_without_initiator_rule_is_zero():
     """No initiator rule: nothing is discarded and dE2 is 0 every step."""
     s = inputs.synthetic_molecule(10, 4, 3, seed=7)
