@@ -508,9 +508,11 @@ __device__ __forceinline__ int cpf_pick(uint64_t m0, uint64_t m1, Wt wt, double 
     return last;
 }
 
+// J and SK are the system's tables of that name, or a copy of them (in LDS).
 template <bool EXACT>
-__device__ __forceinline__ bool gen_cs(const SysView& s, uint64_t a, uint64_t b, const R4& r, const R4& r2,
-                                       double p_single, double p_double, double p_opp, Exc& out) {
+__device__ __forceinline__ bool gen_cs(const SysView& s, const double* __restrict__ J,
+                                       const double* __restrict__ SK, uint64_t a, uint64_t b, const R4& r,
+                                       const R4& r2, double p_single, double p_double, double p_opp, Exc& out) {
     const int N = s.N, na = s.na, n = s.n;
     const uint64_t full = (N >= 64) ? ~0ULL : low_mask(N);
     if (unif(r.x[0]) < p_single) {
@@ -534,8 +536,6 @@ __device__ __forceinline__ bool gen_cs(const SysView& s, uint64_t a, uint64_t b,
     }
     if (n < 2) return false;
     const double q_same = 1.0 - p_opp;
-    const double* J = s.J;
-    const double* SK = s.SK;
     // electron pair
     const int e1 = (int)pick(r.x[1], (uint64_t)n);
     const int s1 = e1 < na ? 0 : 1;

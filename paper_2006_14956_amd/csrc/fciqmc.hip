@@ -850,12 +850,14 @@ template <int W, class V> struct Engine : EngineBase {
     bool ext() const { return ncore > 0 || keep_rej || rs.adaptive; }
     template <int GEN> void launch_spawn_g(const Store<V>& in, const StepScalars& sc, unsigned blocks) {
         const SysView v = sys->view();
+        // the Cauchy-Schwarz generators keep J and SK in LDS
+        const size_t lds = (GEN >= 3 && v.N <= kCsLdsMaxN) ? 2 * sizeof(double) * (size_t)v.N * (size_t)v.N : 0;
         if (ext())
-            hipLaunchKernelGGL((k_spawn<W, V, GEN, true>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
-                               soff, scount, ctl, cmap, cap_cmap);
+            hipLaunchKernelGGL((k_spawn<W, V, GEN, true>), dim3(blocks), dim3(kThreads), lds, stream, v, in, sc,
+                               rec2, soff, scount, ctl, cmap, cap_cmap);
         else
-            hipLaunchKernelGGL((k_spawn<W, V, GEN, false>), dim3(blocks), dim3(kThreads), 0, stream, v, in, sc, rec2,
-                               soff, scount, ctl, cmap, cap_cmap);
+            hipLaunchKernelGGL((k_spawn<W, V, GEN, false>), dim3(blocks), dim3(kThreads), lds, stream, v, in, sc,
+                               rec2, soff, scount, ctl, cmap, cap_cmap);
     }
     // Spawn from store `in` with `grid` workgroups (the kernel reads the
     // chunk count from the device and strides over it).

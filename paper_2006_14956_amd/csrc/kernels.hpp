@@ -161,7 +161,8 @@ template <int W, class V, int GEN, bool EXT>
 __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& st, const StepScalars& sc,
                                             Rec<W, V>* __restrict__ rec2, const int64_t* __restrict__ soff,
                                             int32_t* __restrict__ scount, Ctl* ctl,
-                                            const int64_t* __restrict__ cmap, int64_t g, int32_t* smpre) {
+                                            const int64_t* __restrict__ cmap, int64_t g, int32_t* smpre,
+                                            const double* __restrict__ tJ, const double* __restrict__ tSK) {
     // Chunk g is local chunk c of bucket b (cmap[g] = b << 32 | c): the
     // bucket's attempts [c*kChunk, (c+1)*kChunk), one per lane.  The
     // bucket's attempt prefixes are read once into LDS; each lane finds its
@@ -207,7 +208,7 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
                 ok = gen_pchb(sys, da, db, r, r2, sc.p_single, sc.p_double, sc.p_opp, x);
             } else {
                 const R4 r2 = draw<W>(key, sc.t, k, kSpawn2, sc.seed, sc.replica);
-                ok = gen_cs<GEN == 4>(sys, da, db, r, r2, sc.p_single, sc.p_double, sc.p_opp, x);
+                ok = gen_cs<GEN == 4>(sys, tJ, tSK, da, db, r, r2, sc.p_single, sc.p_double, sc.p_opp, x);
             }
             // spawns from the deterministic space into it are part of P^D
             if constexpr (EXT)
@@ -269,6 +270,11 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
     __syncthreads();  // smpre is reused by the workgroup's next chunk
 }
 
+// Largest orbital count whose J and SK tables the spawn kernel copies to
+// LDS (2 N^2 doubles, 32.4 KB at N = 45); larger systems read them from
+// global memory.
+constexpr int kCsLdsMaxN = 45;
+
 template <int W, class V, int GEN, bool EXT>
 __global__ __launch_bounds__(kThreads) void k_spawn(SysView sys, Store<V> st, StepScalars sc,
                                                     Rec<W, V>* __restrict__ rec2,
@@ -283,8 +289,24 @@ __global__ __launch_bounds__(kThreads) void k_spawn(SysView sys, Store<V> st, St
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctl->flags, kFlagSpawnCap);
         return;
     }
+    if (GEN >= 3 && sys.N <= kCsLdsMaxN) {
+        // the Cauchy-Schwarz generators read J and SK for every candidate
+        // electron and hole: both N x N tables are copied to LDS (dynamic
+        // shared memory of 2 N^2 doubles) once per workgroup; the loop is
+        // its own copy so that its table reads compile to LDS loads
+        extern __shared__ double cs_tab[];
+        const int nn = sys.N * sys.N;
+        for (int i = threadIdx.x; i < nn; i += kThreads) {
+            cs_tab[i] = sys.J[i];
+            cs_tab[nn + i] = sys.SK[i];
+        }
+        __syncthreads();
+        for (int64_t g = blockIdx.x; g < n; g += gridDim.x)
+            spawn_chunk<W, V, GEN, EXT>(sys, st, sc, rec2, soff, scount, ctl, cmap, g, smpre, cs_tab, cs_tab + nn);
+        return;
+    }
     for (int64_t g = blockIdx.x; g < n; g += gridDim.x)
-        spawn_chunk<W, V, GEN, EXT>(sys, st, sc, rec2, soff, scount, ctl, cmap, g, smpre);
+        spawn_chunk<W, V, GEN, EXT>(sys, st, sc, rec2, soff, scount, ctl, cmap, g, smpre, sys.J, sys.SK);
 }
 
 // Records uploaded from the host (population import): assign buckets.
@@ -1224,7 +1246,8 @@ __global__ __launch_bounds__(kThreads) void k_spawn_batch(const Inst<W, V>* __re
     for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
         const int i = owner_of(first, k, g);
         const Inst<W, V>& I = inst[i];
-        spawn_chunk<W, V, GEN, false>(I.sys, I.in, I.sc, I.rec2, I.soff, I.scount, I.ctl, I.cmap, g - first[i], smpre);
+        spawn_chunk<W, V, GEN, false>(I.sys, I.in, I.sc, I.rec2, I.soff, I.scount, I.ctl, I.cmap, g - first[i], smpre,
+                                      I.sys.J, I.sys.SK);
     }
 }
 
