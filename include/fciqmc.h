@@ -341,7 +341,10 @@ void fciqmc_server_free(fciqmc_server *srv);
  * fciqmc_pair_step: n_steps lockstep steps; stats1/stats2 (host, n_steps
  * entries) and de2 (host, n_steps doubles, NaN for a skipped step) may be
  * NULL.  EOVERFLOW if one bucket holds more than 1536 distinct discarded
- * targets or occupied determinants (use more buckets).
+ * targets or occupied determinants (use more buckets).  If a step fails,
+ * the steps before it keep their values (de2, and the pair's record used by
+ * fciqmc_pair_pt2), de2 is NaN from the failed step on, and the replicas may
+ * stand a step apart: free the pair.
  * fciqmc_pair_pt2: dE2 over the pair's steps from number `skip` on (NaN
  * steps left out) as the ratio of the mean numerator to the mean overlap,
  * with its blocked error; *n receives the steps used. */

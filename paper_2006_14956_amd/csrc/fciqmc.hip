@@ -2133,12 +2133,12 @@ int fciqmc_pair_step(fciqmc_pair* p, int n_steps, fciqmc_step_stats* stats1, fci
         p->res_n = 2 * (int64_t)n_steps;
     }
     std::vector<char> has_ovl((size_t)n_steps, 0), has_num((size_t)n_steps, 0);
-    std::vector<double> e0s((size_t)n_steps, 0.0);
-    {
+    int done = 0;  // steps whose values are queued (or skipped)
+    auto steps = [&]() -> int {
         StreamWait wait{a->stream};
         HIP_OK(hipMemsetAsync(p->err, 0, sizeof(unsigned), a->stream));
         for (int i = 0; i < n_steps; ++i) {
-            e0s[i] = (a->S + b->S) / 2.0;  // the shifts this step uses
+            const double e0 = (a->S + b->S) / 2.0;  // the shifts this step uses
             if (a->eng->buckets() == b->eng->buckets()) {
                 CHECK(pair_launch(p, 1, 0.0, p->res + 2 * i + 1));
                 has_ovl[i] = 1;
@@ -2153,29 +2153,42 @@ int fciqmc_pair_step(fciqmc_pair* p, int n_steps, fciqmc_step_stats* stats1, fci
             CHECK(fciqmc_step(b, 1, stats2 ? stats2 + i : nullptr));
             const int64_t Ba = a->eng->buckets(), Bb = b->eng->buckets();
             if (Ba == Bb && has_ovl[i]) {
-                CHECK(pair_launch(p, 0, e0s[i], p->res + 2 * i));
+                CHECK(pair_launch(p, 0, e0, p->res + 2 * i));
                 has_num[i] = 1;
             } else if (Ba != Bb) {
                 // a store outgrew its buckets during the step: this step is not
                 // evaluated, and both use the larger count from the next one
                 const int64_t B = std::max(Ba, Bb);
+                done = i + 1;
                 CHECK(a->eng->rebucket((int)B));
                 CHECK(b->eng->rebucket((int)B));
             }
+            done = i + 1;
         }
-    }
-    std::vector<double> h((size_t)2 * n_steps, 0.0);
+        return 0;
+    };
+    const int rc = steps();  // the queued pair kernels have finished when it returns
+    // the values of the steps done (all of them, or those before an error)
+    std::vector<double> h((size_t)2 * n_steps, NAN);
     unsigned e = 0;
-    HIP_OK(hipMemcpy(h.data(), p->res, sizeof(double) * 2 * n_steps, hipMemcpyDeviceToHost));
-    HIP_OK(hipMemcpy(&e, p->err, sizeof(unsigned), hipMemcpyDeviceToHost));
-    if (e) return fail(FCIQMC_EOVERFLOW, "a bucket holds more entries than the pair table (%d slots)", kPtSlots);
+    if (done > 0) {
+        HIP_OK(hipMemcpy(h.data(), p->res, sizeof(double) * 2 * done, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(&e, p->err, sizeof(unsigned), hipMemcpyDeviceToHost));
+    }
     for (int i = 0; i < n_steps; ++i) {
-        const double num = has_num[i] ? h[2 * i] / (a->p.tau * a->p.tau) : NAN;
-        const double ovl = has_ovl[i] ? h[2 * i + 1] : NAN;
-        p->num.push_back(num);
-        p->ovl.push_back(ovl);
+        double num = NAN, ovl = NAN;
+        if (i < done) {
+            num = has_num[i] ? h[2 * i] / (a->p.tau * a->p.tau) : NAN;
+            ovl = has_ovl[i] ? h[2 * i + 1] : NAN;
+            if (!e) {
+                p->num.push_back(num);
+                p->ovl.push_back(ovl);
+            }
+        }
         if (de2) de2[i] = num / ovl;
     }
+    if (rc) return rc;
+    if (e) return fail(FCIQMC_EOVERFLOW, "a bucket holds more entries than the pair table (%d slots)", kPtSlots);
     return 0;
 }
 
