@@ -319,6 +319,9 @@ template <int W, class V> struct Engine : EngineBase {
     double* rec_h = nullptr;
     int64_t* ada_acc = nullptr;
     int64_t* ada_all = nullptr;
+    // the accumulators of the population's entries are zero: the merge that
+    // produced it cleared them, and no weight pass has run on it since
+    bool ada_clean = false;
     bool keep_rej = false;
     Rec<W, V>* rej = nullptr;
     long long cap_rej = 0;
@@ -402,6 +405,7 @@ template <int W, class V> struct Engine : EngineBase {
         s = Store<V>{};
     }
     int alloc_buckets() {
+        ada_clean = false;  // fresh accumulators hold no known values
         CHECK(alloc_store(st[0]));
         CHECK(alloc_store(st[1]));
         CHECK(dalloc(arena, &scount, (size_t)B * kSub));
@@ -558,7 +562,9 @@ template <int W, class V> struct Engine : EngineBase {
         const int gb = std::min(B, 32768);
         if (rs.adaptive && !sc.import_mode) {
             const unsigned ga = (unsigned)std::min(B, 8192);
-            hipLaunchKernelGGL((k_ada_zero<V>), dim3(ga), dim3(kThreads), 0, stream, in, R, B, ada_acc, ada_all);
+            if (!ada_clean)
+                hipLaunchKernelGGL((k_ada_zero<V>), dim3(ga), dim3(kThreads), 0, stream, in, R, B, ada_acc, ada_all);
+            ada_clean = false;
             hipLaunchKernelGGL((k_ada_weights<W, V>), dim3(ga), dim3(kThreads), 0, stream, v, in, sc, rec2, soff,
                                scount, ctl);
         }
@@ -659,6 +665,7 @@ template <int W, class V> struct Engine : EngineBase {
             const unsigned flags = hctl->flags;
             if (flags == 0) {
                 cur = 1 - cur;
+                ada_clean = true;
                 att_next = hctl->attempts;
                 rec_need = hctl->rec_need;
                 CHECK(ensure_cmap());
@@ -906,6 +913,7 @@ template <int W, class V> struct Engine : EngineBase {
     // the bucket count when the mean occupancy has grown past the bound.
     int complete(Ctl& out) {
         cur = 1 - cur;
+        ada_clean = true;
         att_next = hctl->attempts;
         rec_need = hctl->rec_need;
         out = *hctl;

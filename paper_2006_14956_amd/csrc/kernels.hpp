@@ -819,6 +819,9 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
             out.mpre[o] = (int32_t)mp;
             const int oi = L.t.idx[s];
             if constexpr (EXT) {
+                // adaptive shift: the next step's accumulators start at zero
+                // (this bucket's death pass has read the old ones)
+                if (sc.ada_all) { sc.ada_acc[o] = 0; sc.ada_all[o] = 0; }
                 if (sc.ncore > 0 && oi >= 0) {
                     const double dd = in.diag[eb + oi];
                     if (is_core(dd)) sc.core_c[core_index(dd)] = (double)v;
