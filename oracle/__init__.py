@@ -41,7 +41,8 @@ def lib():
         L = C.CDLL(_LIB)
         u64, i64, dbl, vp = C.c_uint64, C.c_int64, C.c_double, C.c_void_p
         pu64, pdbl, pint = C.POINTER(u64), C.POINTER(dbl), C.POINTER(C.c_int)
-        L.orc_philox4x64_10.argtypes = [pu64, pu64, pu64]
+        pu32 = C.POINTER(C.c_uint32)
+        L.orc_philox4x32_10.argtypes = [pu32, pu32, pu32]
         L.orc_sys_create.restype = vp
         L.orc_sys_create.argtypes = [C.c_int, C.c_int, C.c_int, dbl, pdbl, pdbl]
         L.orc_sys_set_words.argtypes = [vp, C.c_int]
@@ -112,11 +113,11 @@ def _p(a, ct):
     return a.ctypes.data_as(C.POINTER(ct))
 
 
-def philox4x64_10(counter, key):
-    c = np.ascontiguousarray(counter, dtype=np.uint64)
-    k = np.ascontiguousarray(key, dtype=np.uint64)
-    out = np.zeros(4, dtype=np.uint64)
-    lib().orc_philox4x64_10(_p(c, C.c_uint64), _p(k, C.c_uint64), _p(out, C.c_uint64))
+def philox4x32_10(counter, key):
+    c = np.ascontiguousarray(counter, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_p(c, C.c_uint32), _p(k, C.c_uint32), _p(out, C.c_uint32))
     return out
 
 

@@ -30,36 +30,47 @@
 typedef unsigned __int128 u128;
 
 /* ------------------------------------------------------------------------- */
-/* Philox4x64-10 counter-based generator (Salmon, Moraes, Dror, Shaw,        */
-/* "Parallel random numbers: as easy as 1, 2, 3", SC'11).  The paper uses a   */
+/* Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw,        */
+/* "Parallel random numbers: as easy as 1, 2, 3", SC'11): ten rounds of two  */
+/* 32x32->64 multiplies with a Weyl-sequence key schedule.  The paper uses a */
 /* sequential Mersenne twister (dSFMT, Sec. I); Reading: a counter-based     */
 /* stream keyed by the walker's identity replaces it so that the result does */
 /* not depend on how walkers are distributed over threads.                   */
 /* ------------------------------------------------------------------------- */
-#define PHILOX_M0 0xD2E7470EE14C6C93ULL
-#define PHILOX_M1 0xCA5A826395121157ULL
-#define PHILOX_W0 0x9E3779B97F4A7C15ULL
-#define PHILOX_W1 0xBB67AE8584CAA73BULL
+#define PHILOX_M0 0xD2511F53U
+#define PHILOX_M1 0xCD9E8D57U
+#define PHILOX_W0 0x9E3779B9U
+#define PHILOX_W1 0xBB67AE85U
 
-void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
 {
-    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
-    uint64_t k0 = key[0], k1 = key[1];
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
     for (int round = 0; round < 10; ++round) {
         if (round > 0) {
             k0 += PHILOX_W0;
             k1 += PHILOX_W1;
         }
-        u128 p0 = (u128)PHILOX_M0 * c0;
-        u128 p1 = (u128)PHILOX_M1 * c2;
-        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
-        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        uint64_t p0 = (uint64_t)PHILOX_M0 * c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         c0 = hi1 ^ c1 ^ k0;
         c1 = lo1;
         c2 = hi0 ^ c3 ^ k1;
         c3 = lo0;
     }
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* splitmix64 finaliser (Steele, Lea, Flood, OOPSLA'14), a bijection of 64-bit */
+/* words; it hashes the stream identity into Philox keys and counters below.  */
+static uint64_t splitmix64_fin(uint64_t x)
+{
+    x ^= x >> 30; x *= 0xBF58476D1CE4E5B9ULL;
+    x ^= x >> 27; x *= 0x94D049BB133111EBULL;
+    x ^= x >> 31;
+    return x;
 }
 
 /* Discrete choice in [0, m): floor(x * m / 2^64). */
@@ -568,13 +579,31 @@ static int srec_cmp(const void *x, const void *y)
     return a->seq < b->seq ? -1 : (a->seq > b->seq);
 }
 
+/* Random words of (determinant D, iteration t, ordinal k, purpose), from a
+ * Philox4x32-10 block: counter (64-bit identity of D, t, k), key = a hash of
+ * (seed, replica, purpose).  The identity of a one-word determinant is the
+ * word itself; a two-word determinant (alpha, beta) is hashed to 64 bits,
+ * mix(alpha xor mix(beta + c)) with the splitmix finaliser.  t and k enter
+ * with their low 32 bits.  Two 64-bit words per block, word j = lanes 2j and
+ * 2j+1 (low half first); draw() takes words 0-1 from the block of the purpose
+ * and words 2-3 from the block of purpose + 128. */
+static void draw_block(const orc_run *r, det_t d, int64_t t, uint64_t k, uint64_t purpose, uint64_t out[2])
+{
+    uint64_t w0, w1;
+    layout_words(r->s, d, &w0, &w1);
+    uint64_t id = r->s->words == 1 ? w0 : splitmix64_fin(w0 ^ splitmix64_fin(w1 + 0x632BE59BD9B4E019ULL));
+    uint64_t sk = splitmix64_fin(splitmix64_fin(r->p.seed) ^ ((r->p.replica << 8) | purpose));
+    uint32_t ctr[4] = {(uint32_t)id, (uint32_t)(id >> 32), (uint32_t)t, (uint32_t)k};
+    uint32_t key[2] = {(uint32_t)sk, (uint32_t)(sk >> 32)}, o[4];
+    orc_philox4x32_10(ctr, key, o);
+    out[0] = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
+    out[1] = (uint64_t)o[2] | ((uint64_t)o[3] << 32);
+}
+
 static void draw(const orc_run *r, det_t d, int64_t t, uint64_t k, int purpose, uint64_t out[4])
 {
-    uint64_t ctr[4], key[2] = {r->p.seed, r->p.replica};
-    layout_words(r->s, d, &ctr[0], &ctr[1]);
-    ctr[2] = (uint64_t)t;
-    ctr[3] = (k << 8) | (uint64_t)purpose;
-    orc_philox4x64_10(ctr, key, out);
+    draw_block(r, d, t, k, (uint64_t)purpose, out);
+    draw_block(r, d, t, k, (uint64_t)purpose | 128, out + 2);
 }
 
 orc_run *orc_run_create(const orc_sys *s, const orc_params *p, uint64_t ref_a, uint64_t ref_b)
@@ -872,8 +901,8 @@ int orc_run_step(orc_run *r, orc_stats *st)
             if (p->gen == GEN_UNIFORM) ok = gen_uniform(s, e->d, rr, p->p_single, &tgt, &pgen);
             else if (p->gen == GEN_LATTICE) ok = gen_lattice(s, e->d, rr, &tgt, &pgen);
             else {
-                uint64_t r2[4];
-                draw(r, e->d, t, (uint64_t)k, PURPOSE_SPAWN2, r2);
+                uint64_t r2[4] = {0, 0, 0, 0};
+                draw_block(r, e->d, t, (uint64_t)k, PURPOSE_SPAWN2, r2);  /* words 0-1 */
                 if (p->gen == GEN_PCHB)
                     ok = orc_pchb_gen(s, e->d, rr, r2, p->p_single, p->p_opp, &tgt, &pgen);
                 else
@@ -975,7 +1004,7 @@ int orc_run_step(orc_run *r, orc_stats *st)
         double f = 1.0 - t2;
         double xv = f * e->v;
         uint64_t rr[4];
-        draw(r, e->d, t, 0, PURPOSE_DEATH, rr);
+        draw_block(r, e->d, t, 0, PURPOSE_DEATH, rr);
         double u = unif(rr[0]);
         if (integer) {
             double ax = fabs(xv);
@@ -1062,7 +1091,7 @@ int orc_run_step(orc_run *r, orc_stats *st)
             double v = next[x].v;
             if (v != 0.0 && fabs(v) < p->c_min && !(r->nc > 0 && core_find(r, next[x].d) >= 0)) {
                 uint64_t rr[4];
-                draw(r, next[x].d, t, 0, PURPOSE_ANN, rr);
+                draw_block(r, next[x].d, t, 0, PURPOSE_ANN, rr);
                 next[x].v = round_cmin(v, p->c_min, unif(rr[0]));
             }
         }
@@ -1577,8 +1606,8 @@ int orc_generate(const orc_run *r, uint64_t a, uint64_t b, int64_t t, uint64_t k
     if (r->p.gen == GEN_UNIFORM) ok = gen_uniform(r->s, d, rr, r->p.p_single, &tgt, pgen);
     else if (r->p.gen == GEN_LATTICE) ok = gen_lattice(r->s, d, rr, &tgt, pgen);
     else {
-        uint64_t r2[4];
-        draw(r, d, t, k, PURPOSE_SPAWN2, r2);
+        uint64_t r2[4] = {0, 0, 0, 0};
+        draw_block(r, d, t, k, PURPOSE_SPAWN2, r2);  /* words 0-1 */
         if (r->p.gen == GEN_PCHB)
             ok = orc_pchb_gen(r->s, d, rr, r2, r->p.p_single, r->p.p_opp, &tgt, pgen);
         else

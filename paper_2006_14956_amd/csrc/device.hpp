@@ -18,7 +18,8 @@ namespace fq {
 constexpr uint64_t kEmpty = ~0ULL;       // unused hash slot
 constexpr uint64_t kLocked = ~0ULL - 1;  // slot being claimed (2-word keys only)
 
-// Philox purposes (low byte of counter word 3).
+// Purposes of random blocks (part of the Philox key; the second block of a
+// four-word draw uses purpose + 128).
 enum : uint64_t { kSpawn = 0, kSpawn2 = 1, kDeath = 2, kAnn = 4 };
 
 // Error / overflow flags raised on the device, read back by the host.
@@ -26,26 +27,30 @@ enum : unsigned { kFlagSpawnCap = 1u, kFlagTable = 2u, kFlagStore = 4u, kFlagBlo
                   kFlagSpin = 16u, kFlagPop = 32u };
 
 // --------------------------------------------------------------------------
-// Philox4x64-10 (Salmon et al., SC'11): ten rounds of two 64x64->128
-// multiplies with a Weyl-sequence key schedule.
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
+// multiplies with a Weyl-sequence key schedule.  The 32-bit form suits this
+// target (a 32x32 product is one instruction pair; a 64x64 product is four
+// 64-bit multiply-adds).
 // --------------------------------------------------------------------------
 struct R4 { uint64_t x[4]; };
+struct R2 { uint64_t x[2]; };
 
-__device__ __forceinline__ R4 philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
-                                     uint64_t k0, uint64_t k1) {
-    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
-    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+__device__ __forceinline__ R2 philox4x32(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                         uint32_t k1) {
+    constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint64_t h0 = __umul64hi(M0, c0), l0 = M0 * c0;
-        const uint64_t h1 = __umul64hi(M1, c2), l1 = M1 * c2;
-        const uint64_t n0 = h1 ^ c1 ^ k0;
-        const uint64_t n2 = h0 ^ c3 ^ k1;
+        const uint32_t h0 = __umulhi(M0, c0), l0 = M0 * c0;
+        const uint32_t h1 = __umulhi(M1, c2), l1 = M1 * c2;
+        const uint32_t n0 = h1 ^ c1 ^ k0;
+        const uint32_t n2 = h0 ^ c3 ^ k1;
         c0 = n0; c1 = l1; c2 = n2; c3 = l0;
         k0 += W0; k1 += W1;
     }
-    R4 o;
-    o.x[0] = c0; o.x[1] = c1; o.x[2] = c2; o.x[3] = c3;
+    R2 o;
+    o.x[0] = (uint64_t)c0 | ((uint64_t)c1 << 32);
+    o.x[1] = (uint64_t)c2 | ((uint64_t)c3 << 32);
     return o;
 }
 
@@ -84,20 +89,38 @@ template <int W> __device__ __forceinline__ void store_key(uint64_t* p, const Ke
     else { ulonglong2 v; v.x = k.w[0]; v.y = k.w[1]; *reinterpret_cast<ulonglong2*>(p) = v; }
 }
 
-// Random block of (determinant, iteration, ordinal, purpose).
-template <int W> __device__ __forceinline__ R4 draw(const Key<W>& k, int64_t t, uint64_t ord,
-                                                    uint64_t purpose, uint64_t seed, uint64_t rep) {
-    return philox(k.w[0], W == 2 ? k.w[W - 1] : 0ULL, (uint64_t)t, (ord << 8) | purpose, seed, rep);
-}
-
-// splitmix64 finaliser; partitions determinants into buckets (high bits) and
-// places them in the per-bucket LDS table (low bits).
+// splitmix64 finaliser (a bijection of 64-bit words); partitions
+// determinants into buckets (high bits), places them in the per-bucket LDS
+// table (low bits) and hashes the identities of random streams.
 __device__ __forceinline__ uint64_t mix64(uint64_t x) {
     x ^= x >> 30; x *= 0xBF58476D1CE4E5B9ULL;
     x ^= x >> 27; x *= 0x94D049BB133111EBULL;
     x ^= x >> 31;
     return x;
 }
+
+// Random words of (determinant, iteration, ordinal, purpose): a Philox
+// block with counter (64-bit identity of the determinant, low 32 bits of t
+// and of the ordinal) and key = mix(mix(seed) ^ (replica << 8 | purpose)).
+// A one-word determinant is its own identity; a two-word one is hashed
+// (mix(w0 ^ mix(w1 + c))).  draw2 gives the block's two 64-bit words; draw
+// gives four, the second pair from the block of purpose + 128.
+template <int W> __device__ __forceinline__ R2 draw2(const Key<W>& k, int64_t t, uint64_t ord,
+                                                     uint64_t purpose, uint64_t seed, uint64_t rep) {
+    const uint64_t id = W == 1 ? k.w[0] : mix64(k.w[0] ^ mix64(k.w[W - 1] + 0x632BE59BD9B4E019ULL));
+    const uint64_t sk = mix64(mix64(seed) ^ ((rep << 8) | purpose));
+    return philox4x32((uint32_t)id, (uint32_t)(id >> 32), (uint32_t)t, (uint32_t)ord, (uint32_t)sk,
+                      (uint32_t)(sk >> 32));
+}
+template <int W> __device__ __forceinline__ R4 draw(const Key<W>& k, int64_t t, uint64_t ord,
+                                                    uint64_t purpose, uint64_t seed, uint64_t rep) {
+    const R2 a = draw2<W>(k, t, ord, purpose, seed, rep);
+    const R2 b = draw2<W>(k, t, ord, purpose | 128, seed, rep);
+    R4 o;
+    o.x[0] = a.x[0]; o.x[1] = a.x[1]; o.x[2] = b.x[0]; o.x[3] = b.x[1];
+    return o;
+}
+
 template <int W> __device__ __forceinline__ uint64_t key_hash(const Key<W>& k) {
     if constexpr (W == 1) return mix64(k.w[0] + 0x632BE59BD9B4E019ULL);
     else return mix64(k.w[0] ^ mix64(k.w[1] + 0x632BE59BD9B4E019ULL));
@@ -384,7 +407,7 @@ __device__ __forceinline__ bool gen_lattice(const SysView& s, uint64_t a, uint64
 // tables; uniform singles.  Block r: 0 single/double, 1 electrons, 2 alias
 // column, 3 acceptance; block r2: 0 alias coin, 1 pair class.
 __device__ __forceinline__ bool gen_pchb(const SysView& s, uint64_t a, uint64_t b, const R4& r,
-                                         const R4& r2, double p_single, double p_double,
+                                         const R2& r2, double p_single, double p_double,
                                          double p_opp, Exc& out) {
     const int N = s.N, na = s.na, nb = s.nb;
     if (unif(r.x[0]) < p_single) return gen_uniform(s, a, b, r, p_single, p_double, out);
@@ -512,7 +535,7 @@ __device__ __forceinline__ int cpf_pick(uint64_t m0, uint64_t m1, Wt wt, double 
 template <bool EXACT>
 __device__ __forceinline__ bool gen_cs(const SysView& s, const double* __restrict__ J,
                                        const double* __restrict__ SK, uint64_t a, uint64_t b, const R4& r,
-                                       const R4& r2, double p_single, double p_double, double p_opp, Exc& out) {
+                                       const R2& r2, double p_single, double p_double, double p_opp, Exc& out) {
     const int N = s.N, na = s.na, n = s.n;
     const uint64_t full = (N >= 64) ? ~0ULL : low_mask(N);
     if (unif(r.x[0]) < p_single) {

@@ -204,10 +204,10 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
             if constexpr (GEN == 0) ok = gen_uniform(sys, da, db, r, sc.p_single, sc.p_double, x);
             else if constexpr (GEN == 1) ok = gen_lattice(sys, da, db, r, x);
             else if constexpr (GEN == 2) {
-                const R4 r2 = draw<W>(key, sc.t, k, kSpawn2, sc.seed, sc.replica);
+                const R2 r2 = draw2<W>(key, sc.t, k, kSpawn2, sc.seed, sc.replica);
                 ok = gen_pchb(sys, da, db, r, r2, sc.p_single, sc.p_double, sc.p_opp, x);
             } else {
-                const R4 r2 = draw<W>(key, sc.t, k, kSpawn2, sc.seed, sc.replica);
+                const R2 r2 = draw2<W>(key, sc.t, k, kSpawn2, sc.seed, sc.replica);
                 ok = gen_cs<GEN == 4>(sys, tJ, tSK, da, db, r, r2, sc.p_single, sc.p_double, sc.p_opp, x);
             }
             // spawns from the deterministic space into it are part of P^D
@@ -675,7 +675,7 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
             const double t2 = sc.tau * t1;
             const double f = 1.0 - t2;
             const double xv = f * (double)C;
-            const double u = unif(draw<W>(key, sc.t, 0, kDeath, sc.seed, sc.replica).x[0]);
+            const double u = unif(draw2<W>(key, sc.t, 0, kDeath, sc.seed, sc.replica).x[0]);
             if constexpr (kInt) {
                 const double ax = fabs(xv);
                 const double fl = floor(ax);
@@ -786,7 +786,7 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
                 Key<W> key;
                 key.w[0] = k0;
                 if constexpr (W == 2) key.w[1] = L.t.key1[s];
-                const double u = unif(draw<W>(key, sc.t, 0, kAnn, sc.seed, sc.replica).x[0]);
+                const double u = unif(draw2<W>(key, sc.t, 0, kAnn, sc.seed, sc.replica).x[0]);
                 const double pr = av / sc.c_min;
                 v = (u < pr) ? (v < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
                 L.t.val[s] = v;

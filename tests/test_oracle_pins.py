@@ -1,7 +1,7 @@
 """Pins of the CPU oracle against facts fixed outside it.
 
 Each test checks the oracle against something it does not compute itself:
-numpy's Philox, a second-quantised Hamiltonian applied operator by operator,
+Random123's Philox known answers, a second-quantised Hamiltonian applied operator by operator,
 closed-form energies, exact diagonalisation, exhaustive enumeration of the
 generators and the exact expectation of one projector step.
 """
@@ -18,26 +18,17 @@ pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
 
 # --- random numbers -------------------------------------------------------------------
 
-def test_philox_matches_numpy(oracle_mod):
-    """numpy's Philox (4x64, 10 rounds) emits block(counter + 1) first."""
-    rng = np.random.default_rng(7)
-    for _ in range(50):
-        ctr = [int(x) for x in rng.integers(0, 2**63, size=4, dtype=np.uint64)]
-        key = [int(x) for x in rng.integers(0, 2**63, size=2, dtype=np.uint64)]
-        c = sum(v << (64 * i) for i, v in enumerate(ctr))
-        cm1 = (c - 1) % (1 << 256)
-        prev = [(cm1 >> (64 * i)) & ((1 << 64) - 1) for i in range(4)]
-        g = np.random.Philox(counter=prev, key=key)
-        ref = g.random_raw(4)
-        got = oracle_mod.philox4x64_10(ctr, key)
-        assert list(map(int, got)) == list(map(int, ref))
-
-
-def test_philox_known_answer_zero(oracle_mod):
-    """Random123 known-answer vector for philox4x64-10 at counter 0, key 0."""
-    got = oracle_mod.philox4x64_10([0, 0, 0, 0], [0, 0])
-    assert [int(x) for x in got] == [0x16554D9ECA36314C, 0xDB20FE9D672D0FDC,
-                                    0xD7E772CEE186176B, 0x7E68B68AEC7BA23B]
+@pytest.mark.parametrize("ctr,key,want", [
+    ([0, 0, 0, 0], [0, 0], [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]),
+    ([0xFFFFFFFF] * 4, [0xFFFFFFFF] * 2, [0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD]),
+    ([0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344], [0xA4093822, 0x299F31D0],
+     [0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1]),
+])
+def test_philox_known_answers(oracle_mod, ctr, key, want):
+    """Random123's published known-answer vectors for philox4x32-10 (zero,
+    all-ones, and the digits of pi as counter and key)."""
+    got = oracle_mod.philox4x32_10(ctr, key)
+    assert [int(x) for x in got] == want
 
 
 # --- Hamiltonian matrix elements ---------------------------------------------------------
