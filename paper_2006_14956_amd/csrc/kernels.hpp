@@ -26,14 +26,9 @@ constexpr int kThreads = 256;
 constexpr int kChunk = kThreads;     // spawn attempts per workgroup
 constexpr int kPostThreads = 512;   // the post kernel's single workgroup
 // Each bucket's record slab is split into kSub sub-slabs, each with its own
-// counter, which divides the contention on any one counter by kSub.  A
-// record goes to the sub-slab chosen by its parent determinant (the top
-// bits of a multiplicative hash of the parent's key), so that a heavily
-// populated parent fills the same sub-slab step after step and the slab
-// sizes taken from the previous step's counts hold.
+// counter; workgroup g appends to sub-slab g mod kSub, which divides the
+// contention on any one counter by kSub.
 constexpr int kSub = 8;
-constexpr int kSubBits = 3;
-static_assert((1 << kSubBits) == kSub, "kSub is a power of two");
 #ifndef FQ_SLOTS
 #define FQ_SLOTS 1024
 #endif
@@ -81,10 +76,14 @@ struct Ctl {
 };
 
 // Record sub-slab for the next step: this step's count plus headroom for
-// drift (c/8) and for Poisson fluctuations of the count (4 sqrt(c) + 32), so
-// that an overflow (and the replay it costs) stays rare across many slabs.
+// drift (c/8), for Poisson fluctuations of the count (4 sqrt(c)) and for a
+// lump of records that moves between sub-slabs (96): a heavily populated
+// parent whose attempts concentrate on a few targets (the heat-bath
+// generator does this) puts tens of records into one sub-slab of a bucket,
+// and which one follows its chunk index, which shifts from step to step.
+// An overflow costs a replay of the whole step.
 __device__ __forceinline__ int64_t slab_size(int32_t c) {
-    return (int64_t)c + (c >> 3) + (int64_t)(4.0 * sqrt((double)c)) + 32;
+    return (int64_t)c + (c >> 3) + (int64_t)(4.0 * sqrt((double)c)) + 96;
 }
 
 template <class V> __device__ __forceinline__ double vabs(V v) { return v < 0 ? -(double)v : (double)v; }
@@ -184,7 +183,6 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
     {
         const int64_t local = (m & 0xFFFFFFFFLL) * kChunk + threadIdx.x;
         bool emit = false;
-        uint32_t psub = 0;  // the record's sub-slab, from its parent
         Rec<W, V> out;
         int64_t out_parent = -1;  // adaptive shift: non-initiator parent's store index
         double out_h = 0.0;
@@ -204,7 +202,6 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
             if constexpr (EXT) pcore = sc.ncore > 0 && is_core(st.diag[e]);
             const bool init = pcore || (sc.n_a < 0.0) || (aC > sc.n_a) || key_eq<W>(key, ref);
             const uint64_t da = key_alpha<W>(key), db = key_beta<W>(key);
-            psub = (uint32_t)(((key.w[0] ^ key.w[W - 1]) * 0x9E3779B97F4A7C15ULL) >> (64 - kSubBits));
             const R4 r = draw<W>(key, sc.t, k, kSpawn, sc.seed, sc.replica);
             Exc x;
             bool ok;
@@ -261,7 +258,7 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
             }
         }
         if (emit) {
-            const uint32_t j = (out.flag >> 1) * kSub + psub;
+            const uint32_t j = (out.flag >> 1) * kSub + (uint32_t)(g & (kSub - 1));
             const int64_t pos = (int64_t)atomicAdd(&scount[j], 1);
             if (soff[j] + pos < soff[j + 1] && soff[j] + pos < sc.spawn_cap) {
                 rec2[soff[j] + pos] = out;
