@@ -484,15 +484,23 @@ int orc_lattice_apply(const orc_sys *s, det_t d, uint64_t idx1, uint64_t idx2,
     return 1;
 }
 
+/* Lattice draw: electron from the high and neighbour from the low 32-bit
+ * half of word 0 (Reading: one Philox block per attempt; both choices are
+ * floor(x m / 2^32), exact for the power-of-two counts of the 2D lattice). */
+static uint64_t pick32(uint32_t x, uint64_t m)
+{
+    return ((uint64_t)x * m) >> 32;
+}
+
 static int gen_lattice(const orc_sys *s, det_t d, const uint64_t r[4], det_t *tgt, double *pgen)
 {
     int occ[128];
     int n = det_occ_list(s, d, occ);
-    uint64_t idx1 = pick(r[1], (uint64_t)n);
+    uint64_t idx1 = pick32((uint32_t)(r[0] >> 32), (uint64_t)n);
     int p = so_orb(s, occ[idx1]);
     int z = s->deg[p];
     if (z == 0) return 0;
-    return orc_lattice_apply(s, d, idx1, pick(r[2], (uint64_t)z), tgt, pgen);
+    return orc_lattice_apply(s, d, idx1, pick32((uint32_t)r[0], (uint64_t)z), tgt, pgen);
 }
 
 int orc_lattice_degree(const orc_sys *s, int p) { return s->deg[p]; }
@@ -604,6 +612,21 @@ static void draw(const orc_run *r, det_t d, int64_t t, uint64_t k, int purpose, 
 {
     draw_block(r, d, t, k, (uint64_t)purpose, out);
     draw_block(r, d, t, k, (uint64_t)purpose | 128, out + 2);
+}
+
+/* The random words of spawn attempt k: four words (two blocks), word 3 the
+ * acceptance; the lattice generator uses one block, its electron and its
+ * neighbour from the two 32-bit halves of word 0 and the acceptance from
+ * word 1 (returned in word 3). */
+static void spawn_words(const orc_run *r, det_t d, int64_t t, uint64_t k, uint64_t out[4])
+{
+    if (r->p.gen == GEN_LATTICE) {
+        draw_block(r, d, t, k, PURPOSE_SPAWN, out);
+        out[3] = out[1];
+        out[1] = out[2] = 0;
+    } else {
+        draw(r, d, t, k, PURPOSE_SPAWN, out);
+    }
 }
 
 orc_run *orc_run_create(const orc_sys *s, const orc_params *p, uint64_t ref_a, uint64_t ref_b)
@@ -894,7 +917,7 @@ int orc_run_step(orc_run *r, orc_stats *st)
         st->attempts += m;
         for (int64_t k = 0; k < m; ++k) {
             uint64_t rr[4];
-            draw(r, e->d, t, (uint64_t)k, PURPOSE_SPAWN, rr);
+            spawn_words(r, e->d, t, (uint64_t)k, rr);
             det_t tgt;
             double pgen;
             int ok;
@@ -1601,7 +1624,7 @@ int orc_generate(const orc_run *r, uint64_t a, uint64_t b, int64_t t, uint64_t k
 {
     det_t d = {a, b}, tgt;
     uint64_t rr[4];
-    draw(r, d, t, k, PURPOSE_SPAWN, rr);
+    spawn_words(r, d, t, k, rr);
     int ok;
     if (r->p.gen == GEN_UNIFORM) ok = gen_uniform(r->s, d, rr, r->p.p_single, &tgt, pgen);
     else if (r->p.gen == GEN_LATTICE) ok = gen_lattice(r->s, d, rr, &tgt, pgen);

@@ -56,6 +56,8 @@ __device__ __forceinline__ R2 philox4x32(uint32_t c0, uint32_t c1, uint32_t c2, 
 
 // Choice in [0, m): floor(x m / 2^64).
 __device__ __forceinline__ uint64_t pick(uint64_t x, uint64_t m) { return __umul64hi(x, m); }
+// Choice in [0, m) from a 32-bit word: floor(x m / 2^32).
+__device__ __forceinline__ uint32_t pick32(uint32_t x, uint32_t m) { return __umulhi(x, m); }
 // Uniform in [0,1) from the top 53 bits.
 __device__ __forceinline__ double unif(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
 
@@ -384,16 +386,18 @@ __device__ __forceinline__ bool gen_uniform(const SysView& s, uint64_t a, uint64
 
 // Real-space lattice hopping: one of the n electrons, one of the z_p
 // neighbours of its site (same spin); null if occupied; p_gen = 1/(n z_p).
+// The electron comes from the high, the neighbour from the low 32-bit half
+// of word 0 (the attempt draws one block; its acceptance is word 1).
 __device__ __forceinline__ bool gen_lattice(const SysView& s, uint64_t a, uint64_t b, const R4& r,
                                             Exc& out) {
     const int N = s.N, na = s.na, n = s.n;
-    const int e = (int)pick(r.x[1], (uint64_t)n);
+    const int e = (int)pick32((uint32_t)(r.x[0] >> 32), (uint32_t)n);
     const int sg = e < na ? 0 : 1;
     const uint64_t occ = sg ? b : a;
     const int pi = select64(occ, sg ? e - na : e);
     const int z = s.deg[pi];
     if (z == 0) return false;
-    const int q = s.nbr[pi * N + (int)pick(r.x[2], (uint64_t)z)];
+    const int q = s.nbr[pi * N + (int)pick32((uint32_t)r.x[0], (uint32_t)z)];
     if ((occ >> q) & 1ULL) return false;
     out.pgen = 1.0 / (double)((uint64_t)n * (uint64_t)z);
     out.H = h_single(s, a, b, sg, pi, q);

@@ -202,7 +202,16 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
             if constexpr (EXT) pcore = sc.ncore > 0 && is_core(st.diag[e]);
             const bool init = pcore || (sc.n_a < 0.0) || (aC > sc.n_a) || key_eq<W>(key, ref);
             const uint64_t da = key_alpha<W>(key), db = key_beta<W>(key);
-            const R4 r = draw<W>(key, sc.t, k, kSpawn, sc.seed, sc.replica);
+            // the attempt's random words, word 3 the acceptance; the lattice
+            // generator needs one block (its choices share word 0, its
+            // acceptance is the block's word 1)
+            R4 r;
+            if constexpr (GEN == 1) {
+                const R2 q = draw2<W>(key, sc.t, k, kSpawn, sc.seed, sc.replica);
+                r.x[0] = q.x[0]; r.x[1] = 0; r.x[2] = 0; r.x[3] = q.x[1];
+            } else {
+                r = draw<W>(key, sc.t, k, kSpawn, sc.seed, sc.replica);
+            }
             Exc x;
             bool ok;
             if constexpr (GEN == 0) ok = gen_uniform(sys, da, db, r, sc.p_single, sc.p_double, x);
