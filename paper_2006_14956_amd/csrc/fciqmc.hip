@@ -226,6 +226,7 @@ struct EngineBase {
     virtual int64_t* rej_offsets() const = 0;
     virtual int32_t* rej_counts() const = 0;
     virtual const void* current_store() const = 0;  // Store<V> of the population
+    virtual const void* previous_store() const = 0; // Store<V> the last step read (intact until the next merge)
     virtual int bucket_entries() const = 0;         // R
 };
 
@@ -814,6 +815,7 @@ template <int W, class V> struct Engine : EngineBase {
     int64_t* rej_offsets() const override { return rej_off; }
     int32_t* rej_counts() const override { return rej_cnt; }
     const void* current_store() const override { return &st[cur]; }
+    const void* previous_store() const override { return &st[1 - cur]; }
     int bucket_entries() const override { return R; }
     int64_t core_size() const override { return ncore; }
     int64_t core_nnz() const override { return nnz; }
@@ -2039,49 +2041,40 @@ void pair_detach(fciqmc_run* run) {
 }
 
 namespace {
-template <int W, class V> void launch_pt2(fciqmc_pair* p, int B, double e0, double* out, hipStream_t s) {
+// Queue both sums of a paired step over the two replicas (equal bucket
+// counts) on the first replica's stream, after both have stepped: the
+// overlap of the populations the step started from and the discarded-spawn
+// sum; their values land in out[1] and out[0] (device memory).  No host
+// wait here: the kernel reads the second replica's records and previous
+// store, which its next merge overwrites, and that merge comes only after
+// the host has waited for the first replica's next step, queued behind
+// this kernel on the same stream.
+template <int W, class V> void launch_pair_sums(fciqmc_pair* p, int B, double e0, double* out, hipStream_t s) {
     const EngineBase* a = p->r[0]->eng.get();
     const EngineBase* b = p->r[1]->eng.get();
-    hipLaunchKernelGGL((k_pt2<W, V>), dim3((unsigned)std::min(B, 4096)), dim3(kThreads), 0, s,
-                       p->r[0]->sys->view(), (const Rec<W, V>*)a->rej_records(), a->rej_offsets(),
-                       a->rej_counts(), (const Rec<W, V>*)b->rej_records(), b->rej_offsets(), b->rej_counts(), B,
-                       e0, p->r[0]->h00, p->part, p->err);
-    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, s, p->part, B, out);
+    const Store<V> s1 = *static_cast<const Store<V>*>(a->previous_store());
+    const Store<V> s2 = *static_cast<const Store<V>*>(b->previous_store());
+    hipLaunchKernelGGL((k_pair_sums<W, V>), dim3((unsigned)std::min(B, 4096)), dim3(kThreads), 0, s,
+                       p->r[0]->sys->view(), s1, s2, a->bucket_entries(), (const Rec<W, V>*)a->rej_records(),
+                       a->rej_offsets(), a->rej_counts(), (const Rec<W, V>*)b->rej_records(), b->rej_offsets(),
+                       b->rej_counts(), B, e0, p->r[0]->h00, p->part, p->part + B, p->err);
+    hipLaunchKernelGGL(k_sum2, dim3(1), dim3(kThreads), 0, s, p->part, p->part + B, B, out);
 }
-template <int W, class V> void launch_overlap(fciqmc_pair* p, int B, double* out, hipStream_t s) {
-    const Store<V> s1 = *static_cast<const Store<V>*>(p->r[0]->eng->current_store());
-    const Store<V> s2 = *static_cast<const Store<V>*>(p->r[1]->eng->current_store());
-    hipLaunchKernelGGL((k_overlap<W, V>), dim3((unsigned)std::min(B, 4096)), dim3(kThreads), 0, s, s1, s2,
-                       p->r[0]->eng->bucket_entries(), B, p->part, p->err);
-    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, s, p->part, B, out);
-}
-// Queue the pair kernel `which` (0: PT2 sum, 1: overlap) over both replicas
-// (equal bucket counts) on the first replica's stream; its value lands in
-// `out` (device memory).  No host wait here: the kernels read the second
-// replica's buffers, so the caller lets that replica step (or re-bucket)
-// only after the pair's event has completed.
-int pair_launch(fciqmc_pair* p, int which, double e0, double* out) {
+int pair_sums(fciqmc_pair* p, double e0, double* out) {
     fciqmc_run* a = p->r[0];
     const int B = (int)a->eng->buckets();
-    if (p->part_n < B) {
+    if (p->part_n < 2 * (int64_t)B) {
         HIP_OK(hipStreamSynchronize(a->stream));  // queued pair kernels still use the old buffer
         p->arena.release(p->part);
         p->part = nullptr;
-        CHECK(dalloc(p->arena, &p->part, (size_t)B));
-        p->part_n = B;
+        CHECK(dalloc(p->arena, &p->part, (size_t)2 * B));
+        p->part_n = 2 * (int64_t)B;
     }
     const int k = a->eng->kind();
-    if (which == 0) {
-        if (k == 0) launch_pt2<1, int32_t>(p, B, e0, out, a->stream);
-        else if (k == 1) launch_pt2<1, double>(p, B, e0, out, a->stream);
-        else if (k == 2) launch_pt2<2, int32_t>(p, B, e0, out, a->stream);
-        else launch_pt2<2, double>(p, B, e0, out, a->stream);
-    } else {
-        if (k == 0) launch_overlap<1, int32_t>(p, B, out, a->stream);
-        else if (k == 1) launch_overlap<1, double>(p, B, out, a->stream);
-        else if (k == 2) launch_overlap<2, int32_t>(p, B, out, a->stream);
-        else launch_overlap<2, double>(p, B, out, a->stream);
-    }
+    if (k == 0) launch_pair_sums<1, int32_t>(p, B, e0, out, a->stream);
+    else if (k == 1) launch_pair_sums<1, double>(p, B, e0, out, a->stream);
+    else if (k == 2) launch_pair_sums<2, int32_t>(p, B, e0, out, a->stream);
+    else launch_pair_sums<2, double>(p, B, e0, out, a->stream);
     HIP_OK(hipGetLastError());
     return 0;
 }
@@ -2147,21 +2140,20 @@ int fciqmc_pair_step(fciqmc_pair* p, int n_steps, fciqmc_step_stats* stats1, fci
         HIP_OK(hipMemsetAsync(p->err, 0, sizeof(unsigned), a->stream));
         for (int i = 0; i < n_steps; ++i) {
             const double e0 = (a->S + b->S) / 2.0;  // the shifts this step uses
-            if (a->eng->buckets() == b->eng->buckets()) {
-                CHECK(pair_launch(p, 1, 0.0, p->res + 2 * i + 1));
-                has_ovl[i] = 1;
-            }
+            const int64_t B0 = a->eng->buckets();
+            const bool same = B0 == b->eng->buckets();
             HIP_OK(hipEventRecord(p->ev, a->stream));
             CHECK(fciqmc_step(a, 1, stats1 ? stats1 + i : nullptr));
-            // the pair kernels queued before this step (overlap, last PT2
-            // sum) read the second replica's store and records: done before
-            // it steps (normally already, since the host waited for the
-            // first replica's step behind them)
+            // the pair kernels of the last step read the second replica's
+            // records and previous store: done before it steps (normally
+            // already, since the host waited for the first replica's step
+            // behind them)
             HIP_OK(hipEventSynchronize(p->ev));
             CHECK(fciqmc_step(b, 1, stats2 ? stats2 + i : nullptr));
             const int64_t Ba = a->eng->buckets(), Bb = b->eng->buckets();
-            if (Ba == Bb && has_ovl[i]) {
-                CHECK(pair_launch(p, 0, e0, p->res + 2 * i));
+            if (same && Ba == B0 && Bb == B0) {
+                CHECK(pair_sums(p, e0, p->res + 2 * i));
+                has_ovl[i] = 1;
                 has_num[i] = 1;
             } else if (Ba != Bb) {
                 // a store outgrew its buckets during the step: this step is not

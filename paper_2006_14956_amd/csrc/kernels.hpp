@@ -1460,15 +1460,17 @@ template <int W> struct PtTable {
     double shd[kThreads / 64];
 };
 
+// Discarded-spawn sum of bucket b (Eq. (pt2_correction) before the 1/dtau^2):
+// replica 1's discarded weights per target in an LDS table, probed with
+// replica 2's; sum of S^1 S^2 / (E_0 - H_jj) over targets both discarded.
 template <int W, class V>
-__global__ __launch_bounds__(kThreads) void k_pt2(SysView sys, const Rec<W, V>* __restrict__ rej1,
-                                                  const int64_t* __restrict__ off1, const int32_t* __restrict__ cnt1,
-                                                  const Rec<W, V>* __restrict__ rej2,
-                                                  const int64_t* __restrict__ off2, const int32_t* __restrict__ cnt2,
-                                                  int B, double e0, double h00, double* __restrict__ part,
-                                                  unsigned* __restrict__ err) {
-    __shared__ PtTable<W> T;
-    for (int b = blockIdx.x; b < B; b += gridDim.x) {
+__device__ __forceinline__ void pt2_bucket(const SysView& sys, const Rec<W, V>* __restrict__ rej1,
+                                           const int64_t* __restrict__ off1, const int32_t* __restrict__ cnt1,
+                                           const Rec<W, V>* __restrict__ rej2,
+                                           const int64_t* __restrict__ off2, const int32_t* __restrict__ cnt2,
+                                           int b, double e0, double h00, double* __restrict__ part,
+                                           unsigned* __restrict__ err, PtTable<W>& T) {
+    {
         const int n1 = cnt1[b], n2 = cnt2[b];
         int nslots = kThreads;
         while (nslots < (n1 * 4) / 3 + 1 && nslots < kPtSlots) nslots <<= 1;
@@ -1521,13 +1523,13 @@ __global__ __launch_bounds__(kThreads) void k_pt2(SysView sys, const Rec<W, V>* 
     }
 }
 
-// Replica overlap sum_i C_i^1 C_i^2 per bucket: the first store's entries
+// Replica overlap sum_i C_i^1 C_i^2 of bucket b: the first store's entries
 // in an LDS table, probed with the second's.
 template <int W, class V>
-__global__ __launch_bounds__(kThreads) void k_overlap(Store<V> s1, Store<V> s2, int R, int B,
-                                                      double* __restrict__ part, unsigned* __restrict__ err) {
-    __shared__ PtTable<W> T;
-    for (int b = blockIdx.x; b < B; b += gridDim.x) {
+__device__ __forceinline__ void overlap_bucket(const Store<V>& s1, const Store<V>& s2, int R, int b,
+                                               double* __restrict__ part, unsigned* __restrict__ err,
+                                               PtTable<W>& T) {
+    {
         const int n1 = s1.count[b], n2 = s2.count[b];
         int nslots = kThreads;
         while (nslots < (n1 * 4) / 3 + 1 && nslots < kPtSlots) nslots <<= 1;
@@ -1562,16 +1564,47 @@ __global__ __launch_bounds__(kThreads) void k_overlap(Store<V> s1, Store<V> s2, 
     }
 }
 
-// Sum of the per-bucket partials in a fixed order (one workgroup).
-__global__ __launch_bounds__(kThreads) void k_sum(const double* __restrict__ part, int n, double* __restrict__ out) {
-    __shared__ double shd[kThreads / 64];
+// Both sums of a replica pair's step, one workgroup per bucket: the
+// overlap of the populations the step started from into part_ovl, the
+// discarded-spawn sum into part_pt2.
+template <int W, class V>
+__global__ __launch_bounds__(kThreads) void k_pair_sums(SysView sys, Store<V> s1, Store<V> s2, int R,
+                                                        const Rec<W, V>* __restrict__ rej1,
+                                                        const int64_t* __restrict__ off1,
+                                                        const int32_t* __restrict__ cnt1,
+                                                        const Rec<W, V>* __restrict__ rej2,
+                                                        const int64_t* __restrict__ off2,
+                                                        const int32_t* __restrict__ cnt2, int B, double e0,
+                                                        double h00, double* __restrict__ part_ovl,
+                                                        double* __restrict__ part_pt2, unsigned* __restrict__ err) {
+    __shared__ PtTable<W> T;
+    for (int b = blockIdx.x; b < B; b += gridDim.x) {
+        overlap_bucket<W, V>(s1, s2, R, b, part_ovl, err, T);
+        pt2_bucket<W, V>(sys, rej1, off1, cnt1, rej2, off2, cnt2, b, e0, h00, part_pt2, err, T);
+    }
+}
+
+// Sum of n per-bucket partials in a fixed order (one workgroup).
+__device__ __forceinline__ double sum_parts(const double* __restrict__ part, int n, double* shd) {
     double acc = 0.0;
     const int per = (n + kThreads - 1) / kThreads;
     for (int i = threadIdx.x * per; i < min(n, (int)(threadIdx.x + 1) * per); ++i) acc = acc + part[i];
     acc = wave_sum(acc);
     if (lane_id() == 0) shd[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) *out = ((shd[0] + shd[1]) + shd[2]) + shd[3];
+    const double t = ((shd[0] + shd[1]) + shd[2]) + shd[3];
+    __syncthreads();
+    return t;
+}
+
+// The two sums of a pair's partials (overlap into out[1], PT2 into out[0]).
+__global__ __launch_bounds__(kThreads) void k_sum2(const double* __restrict__ part_ovl,
+                                                   const double* __restrict__ part_pt2, int n,
+                                                   double* __restrict__ out) {
+    __shared__ double shd[kThreads / 64];
+    const double o = sum_parts(part_ovl, n, shd);
+    const double q = sum_parts(part_pt2, n, shd);
+    if (threadIdx.x == 0) { out[0] = q; out[1] = o; }
 }
 
 // ---------------------------------------------------------------------------
