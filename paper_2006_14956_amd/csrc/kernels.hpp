@@ -515,17 +515,33 @@ __device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, cons
     const int b0 = threadIdx.x * per, b1 = min(B, b0 + per);
     int64_t la = 0, lk = 0, ln = 0, cnt = 0, rc = 0, mx = 0;
     double nw = 0.0, en = 0.0;
-    for (int b = b0; b < b1; ++b) {
-        la += batt[b];
-        lk += chunks_of(batt[b]);
-        ln += need_b[b];
+    // the first kHeld buckets of the run keep what the offset pass needs in
+    // registers (no second round of loads after the scan)
+    constexpr int kHeld = 2;
+    int64_t hatt[kHeld] = {}, hneed[kHeld] = {}, hrel[kHeld][kSub] = {};
+    auto add = [&](int b, int64_t at, int64_t nd) {
+        la += at;
+        lk += chunks_of(at);
+        ln += nd;
         const int64_t c = count[b];
         cnt += c;
         rc += recs_b[b];
         mx = max(mx, c);
         nw = nw + nw_b[b];
         en = en + en_b[b];
+    };
+#pragma unroll
+    for (int i = 0; i < kHeld; ++i) {
+        const int b = b0 + i;
+        if (b < b1) {
+            hatt[i] = batt[b];
+            hneed[i] = need_b[b];
+#pragma unroll
+            for (int j = 0; j < kSub; ++j) hrel[i][j] = rel[(int64_t)b * kSub + j];
+            add(b, hatt[i], hneed[i]);
+        }
     }
+    for (int b = b0 + kHeld; b < b1; ++b) add(b, batt[b], need_b[b]);
     // attempts, chunks, slab sizes, and determinants (< 2^32) with records
     // (< 2^31 per step) packed: four prefix sums in one exchange (whose
     // barrier also publishes the flag word)
@@ -536,7 +552,20 @@ __device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, cons
     const int64_t atot = tot[0], ktot = tot[1], ntot = tot[2], crtot = tot[3];
     if (flags == 0) {
         int64_t run = v[1], base = v[2];
-        for (int b = b0; b < b1; ++b) {
+#pragma unroll
+        for (int i = 0; i < kHeld; ++i) {
+            const int b = b0 + i;
+            if (b < b1) {
+                aoff[b] = run;
+                const int64_t nk = chunks_of(hatt[i]);
+                for (int64_t c = 0; c < nk && run + c < cmap_cap; ++c) cmap[run + c] = ((int64_t)b << 32) | c;
+                run += nk;
+#pragma unroll
+                for (int j = 0; j < kSub; ++j) soff[(int64_t)b * kSub + j] = base + hrel[i][j];
+                base += hneed[i];
+            }
+        }
+        for (int b = b0 + kHeld; b < b1; ++b) {
             aoff[b] = run;
             const int64_t nk = chunks_of(batt[b]);
             for (int64_t c = 0; c < nk && run + c < cmap_cap; ++c) cmap[run + c] = ((int64_t)b << 32) | c;
