@@ -218,10 +218,12 @@ def test_hubbard_full_size_one_step():
     F.fciqmc_free_system(sysd)
 
 
-@pytest.mark.parametrize("buckets_log2", [3, 13])
+@pytest.mark.parametrize("buckets_log2", [3, 11, 12, 13])
 def test_trajectory_independent_of_bucket_count(buckets_log2):
-    """The walker store's partition (8 buckets, or 8192 buckets which also
-    takes the multi-workgroup post path) does not change the trajectory."""
+    """The walker store's partition does not change the trajectory: 8
+    buckets; 2048 and 4096, where each thread of the single-workgroup post
+    work owns a run of 4 or 8 buckets; 8192, which takes the
+    multi-workgroup post path."""
     s = inputs.molecule_8o8e()
     sysd, run, orun = make_pair(s, tau=0.01, target=1e4, seed=7, buckets_log2=buckets_log2)
     g = F.fciqmc_step(run, 300)
