@@ -460,12 +460,25 @@ static int gen_uniform(const orc_sys *s, det_t d, const uint64_t r[4], double p_
     return orc_uniform_apply(s, d, 0, idx1, pick(r[2], c2), p_single, tgt, pgen);
 }
 
+/* Probability that the 32-bit choice floor(x m / 2^32), x uniform over the
+ * 2^32 words, equals e: the words x >= e 2^32 / m and < (e+1) 2^32 / m,
+ * counted exactly and divided by 2^32 (both exact in binary64).  It is
+ * 1/m exactly when m is a power of two, and within 2^-32 of it otherwise. */
+static double pick32_prob(uint64_t e, uint64_t m)
+{
+    uint64_t lo = ((e << 32) + m - 1) / m;
+    uint64_t hi = (((e + 1) << 32) + m - 1) / m;
+    return (double)(hi - lo) * 0x1.0p-32;
+}
+
 /* Real-space lattice generator.  The paper names it (Sec. II) without an
- * algorithm.  Reading: pick one of the n electrons uniformly, then one of the
- * z_p lattice neighbours of its site (the distinct q with h_pq != 0,
- * ascending), same spin; null if that orbital is occupied.
- * p_gen = 1 / (n * z_p).  Exact for Hubbard-type Hamiltonians, whose only
- * off-diagonal elements are hoppings along bonds. */
+ * algorithm.  Reading: pick one of the n electrons, then one of the z_p
+ * lattice neighbours of its site (the distinct q with h_pq != 0,
+ * ascending), same spin; null if that orbital is occupied.  Both choices
+ * are made from 32-bit words (below), so p_gen is the product of their
+ * exact probabilities, p(e) p(q|e), which equals 1 / (n * z_p) whenever n
+ * and z_p are powers of two.  Exact for Hubbard-type Hamiltonians, whose
+ * only off-diagonal elements are hoppings along bonds. */
 int orc_lattice_apply(const orc_sys *s, det_t d, uint64_t idx1, uint64_t idx2,
                       det_t *tgt, double *pgen)
 {
@@ -480,13 +493,15 @@ int orc_lattice_apply(const orc_sys *s, det_t d, uint64_t idx1, uint64_t idx2,
     if (det_occ(s, d, a)) return 0;
     det_t t = d; det_set(s, &t, i, 0); det_set(s, &t, a, 1);
     *tgt = t;
-    *pgen = 1.0 / (double)((uint64_t)n * (uint64_t)z);
+    double pe = pick32_prob(idx1, (uint64_t)n);
+    double pq = pick32_prob(idx2, (uint64_t)z);
+    *pgen = pe * pq;
     return 1;
 }
 
 /* Lattice draw: electron from the high and neighbour from the low 32-bit
  * half of word 0 (Reading: one Philox block per attempt; both choices are
- * floor(x m / 2^32), exact for the power-of-two counts of the 2D lattice). */
+ * floor(x m / 2^32), whose exact probabilities enter p_gen above). */
 static uint64_t pick32(uint32_t x, uint64_t m)
 {
     return ((uint64_t)x * m) >> 32;

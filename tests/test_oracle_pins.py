@@ -160,26 +160,51 @@ def test_uniform_generator_exhaustive(oracle_mod, n_orb, na, nb):
             assert t in mass and mass[t] > 0.0
 
 
-def test_lattice_generator_exhaustive(oracle_mod):
-    s = inputs.hubbard(3, 2, 1.0, 4.0, 3, 2)
+def _word_mass(e, m):
+    """Exact probability that floor(x m / 2^32) = e for x uniform over the
+    2^32 32-bit words, found by bisection on that definition (the first word
+    reaching e and the first reaching e + 1)."""
+    def first(k):
+        lo, hi = 0, 1 << 32
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if (mid * m) >> 32 >= k:
+                hi = mid
+            else:
+                lo = mid + 1
+        return lo
+    from fractions import Fraction
+    return Fraction(first(e + 1) - first(e), 1 << 32)
+
+
+@pytest.mark.parametrize("lx,ly,na,nb", [(3, 2, 3, 2), (4, 2, 2, 2)])
+def test_lattice_generator_exhaustive(oracle_mod, lx, ly, na, nb):
+    """Every (electron, neighbour) choice carries the exact probability of
+    the 32-bit draws that make it; the reported p_gen is that product (to one
+    rounding), masses plus null mass are 1, and the reachable targets are
+    exactly the determinants connected by H.  The 3x2 lattice has five
+    electrons and three distinct neighbours per site (not powers of two)."""
+    from fractions import Fraction
+    s = inputs.hubbard(lx, ly, 1.0, 4.0, na, nb)
+    N = lx * ly
     osys = oracle_mod.System.from_inputs(s)
-    dets = brute.basis(6, 3, 2)
-    n = 5
+    dets = brute.basis(N, na, nb)
+    n = na + nb
     for det in dets[::7]:
         mass = {}
-        null = 0.0
-        occ = [p for p in range(6) if (det[0] >> p) & 1] + [p for p in range(6) if (det[1] >> p) & 1]
+        null = Fraction(0)
+        occ = [p for p in range(N) if (det[0] >> p) & 1] + [p for p in range(N) if (det[1] >> p) & 1]
         for idx1 in range(n):
             z = osys.lattice_degree(occ[idx1])
             for idx2 in range(z):
                 r = osys.lattice_apply(det[0], det[1], idx1, idx2)
-                m = 1.0 / n / z
+                m = _word_mass(idx1, n) * _word_mass(idx2, z)
                 if r is None:
                     null += m
                     continue
-                assert abs(r[2] - m) <= 1e-15
-                mass[r[:2]] = mass.get(r[:2], 0.0) + m
-        assert abs(sum(mass.values()) + null - 1.0) < 1e-12
+                assert r[2] == float(m) or abs(Fraction(r[2]) - m) <= m * Fraction(1, 1 << 52)
+                mass[r[:2]] = mass.get(r[:2], Fraction(0)) + m
+        assert sum(mass.values()) + null == 1
         conn = _connected(osys, det, dets)
         assert set(conn) == set(mass)
 
@@ -235,18 +260,32 @@ def test_pchb_alias_reconstruction(oracle_mod):
     osys.build_pchb()
     N = 7
     eri4 = inputs.unpack_eri(s.eri, N)
+    # same-spin rows and columns: orbital pairs I < J in lexicographic order
+    pairs = [(I, J) for I in range(N) for J in range(I + 1, N)]
     for opp in (True, False):
         K = N * N if opp else N * (N - 1) // 2
         rows = N * N if opp else N * (N - 1) // 2
         for row in range(0, rows, 3):
             w, pr, al, tot = osys.pchb_row(opp, row)
-            # weights are |<ab||ij>| from the integrals
+            # weights are |<ab||ij>| from the integrals (Eq. hbs): the direct
+            # term alone for opposite spins, direct minus exchange for equal
+            # spins, zero where a hole coincides with an electron's orbital
             if opp:
                 I, J = divmod(row, N)
                 for c in range(K):
                     A, B = divmod(c, N)
                     ref = 0.0 if (A == I or B == J) else abs(eri4[A, I, B, J])
                     assert w[c] == ref
+            else:
+                I, J = pairs[row]
+                for c in range(K):
+                    A, B = pairs[c]
+                    if {A, B} & {I, J}:
+                        ref = 0.0
+                    else:
+                        ref = abs(eri4[A, I, B, J] - eri4[A, J, B, I])
+                    assert w[c] == ref, (row, c)
+            assert tot == math.fsum(w) or abs(tot - math.fsum(w)) <= 1e-14 * math.fsum(w)
             if tot == 0.0:
                 continue
             got = pr.copy()
@@ -400,14 +439,22 @@ def _dense_projector(osys, dets, h00, tau, shift, masked_from=None):
 
 @pytest.mark.parametrize("mode,na,gen", [("integer", -1.0, "uniform"), ("real", -1.0, "uniform"),
                                          ("integer", 3.0, "uniform"), ("integer", -1.0, "pe"),
-                                         ("real", -1.0, "cs")])
+                                         ("real", -1.0, "cs"), ("integer", -1.0, "pchb"),
+                                         ("real", 3.0, "pchb"), ("integer", -1.0, "lattice"),
+                                         ("integer", 3.0, "lattice")])
 def test_one_step_expectation(oracle_mod, mode, na, gen):
     """Averaged over independent streams, one step from a fixed population
     equals the dense projector (1 - dtau (H - S)) C of Eq. (projector), with
-    the initiator-masked H when the approximation is on (Sec. II)."""
-    s = inputs.synthetic_molecule(5, 2, 2, seed=21, rank=8)
+    the initiator-masked H when the approximation is on (Sec. II).  The
+    lattice generator runs on a 3x2 periodic Hubbard lattice (3 + 2
+    electrons: five electrons and three distinct neighbours per site, so
+    neither count is a power of two), the others on a small molecule."""
+    if gen == "lattice":
+        s = inputs.hubbard(3, 2, 1.0, 4.0, 3, 2)
+    else:
+        s = inputs.synthetic_molecule(5, 2, 2, seed=21, rank=8)
     osys = oracle_mod.System.from_inputs(s)
-    dets = brute.basis(5, 2, 2)
+    dets = brute.basis(s.n_orb, s.n_alpha, s.n_beta)
     index = {d: i for i, d in enumerate(dets)}
     rng = np.random.default_rng(1)
     pick = rng.choice(len(dets), size=12, replace=False)
