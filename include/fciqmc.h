@@ -39,7 +39,12 @@ extern "C" {
 #define FCIQMC_ENOMEM (-2)    /* device allocation failed or over HBM budget  */
 #define FCIQMC_EOVERFLOW (-3) /* capacity could not grow; state is unchanged  */
 #define FCIQMC_EDEVICE (-4)   /* HIP runtime error                            */
-#define FCIQMC_ESTATE (-5)    /* call out of order                            */
+#define FCIQMC_ESTATE (-5)    /* call out of order, or the run is unusable:   */
+                              /* a call that failed with ENOMEM after         */
+                              /* releasing buffers it had to regrow leaves    */
+                              /* the run without its population; every later  */
+                              /* step, batch step, pair step or walker access  */
+                              /* on it returns ESTATE (free it)               */
 
 #define FCIQMC_MODE_INTEGER 0 /* signed integer walker numbers                */
 #define FCIQMC_MODE_REAL 1    /* real coefficients compressed at c_min        */
@@ -334,17 +339,20 @@ void fciqmc_server_free(fciqmc_server *srv);
  * normalised wave function; averaged over steps as a ratio of means).  The
  * correction applies to a variational energy of the initiator
  * approximation (not computed here).  Creating a pair gives both
- * runs the same bucket count and fixes it (a store that still outgrows it
- * skips that step's dE2 and both are re-bucketed); a run in a pair cannot
+ * runs the same bucket count and fixes it; a store that still outgrows it
+ * during a step is read in its own layout for that step's sums (bucket
+ * counts are powers of two, so each bucket of the finer layout lies inside
+ * one bucket of the coarser), and both are re-bucketed to the larger count
+ * afterwards, so every step is evaluated.  A run in a pair cannot
  * join a batch or another pair, is stepped through fciqmc_pair_step only,
  * and freeing it detaches it (the pair then returns ESTATE).
  * fciqmc_pair_step: n_steps lockstep steps; stats1/stats2 (host, n_steps
- * entries) and de2 (host, n_steps doubles, NaN for a skipped step) may be
- * NULL.  EOVERFLOW if one bucket holds more than 1536 distinct discarded
- * targets or occupied determinants (use more buckets).  If a step fails,
- * the steps before it keep their values (de2, and the pair's record used by
- * fciqmc_pair_pt2), de2 is NaN from the failed step on, and the replicas may
- * stand a step apart: free the pair.
+ * entries) and de2 (host, n_steps doubles) may be NULL.  The per-bucket sums
+ * run in as many passes over disjoint hash ranges as a bucket's discarded
+ * spawns need (no capacity limit).  If a step fails, the steps before it
+ * keep their values (de2, and the pair's record used by fciqmc_pair_pt2),
+ * de2 is NaN from the failed step on, and the replicas may stand a step
+ * apart: free the pair.
  * fciqmc_pair_pt2: dE2 over the pair's steps from number `skip` on (NaN
  * steps left out) as the ratio of the mean numerator to the mean overlap,
  * with its blocked error; *n receives the steps used. */

@@ -198,6 +198,11 @@ struct SysView {
     const double* U;      // U[p] = (pp|pp)
     const int* deg;       // lattice degree
     const int* nbr;       // N*N ascending neighbour lists
+    // exact probabilities of the lattice generator's 32-bit choices:
+    // lat_pe[e] of electron e among the n, lat_pz[z*N + d] of neighbour d
+    // among z (the share of 32-bit words x with floor(x m / 2^32) = index)
+    const double* lat_pe;
+    const double* lat_pz;
     // pre-computed heat-bath tables (see the PCHB generator)
     const double* SK;     // SK[p*N+q] = sqrt(|(pq|qp)|), the Cauchy-Schwarz hole weights
     const HbEntry* hb_opp;   // rows (I alpha, J beta), N^2 columns each
@@ -385,9 +390,10 @@ __device__ __forceinline__ bool gen_uniform(const SysView& s, uint64_t a, uint64
 }
 
 // Real-space lattice hopping: one of the n electrons, one of the z_p
-// neighbours of its site (same spin); null if occupied; p_gen = 1/(n z_p).
-// The electron comes from the high, the neighbour from the low 32-bit half
-// of word 0 (the attempt draws one block; its acceptance is word 1).
+// neighbours of its site (same spin); null if occupied.  The electron comes
+// from the high, the neighbour from the low 32-bit half of word 0 (the
+// attempt draws one block; its acceptance is word 1); p_gen is the product
+// of the two choices' exact probabilities, 1/(n z_p) for power-of-two counts.
 __device__ __forceinline__ bool gen_lattice(const SysView& s, uint64_t a, uint64_t b, const R4& r,
                                             Exc& out) {
     const int N = s.N, na = s.na, n = s.n;
@@ -397,9 +403,10 @@ __device__ __forceinline__ bool gen_lattice(const SysView& s, uint64_t a, uint64
     const int pi = select64(occ, sg ? e - na : e);
     const int z = s.deg[pi];
     if (z == 0) return false;
-    const int q = s.nbr[pi * N + (int)pick32((uint32_t)r.x[0], (uint32_t)z)];
+    const int d = (int)pick32((uint32_t)r.x[0], (uint32_t)z);
+    const int q = s.nbr[pi * N + d];
     if ((occ >> q) & 1ULL) return false;
-    out.pgen = 1.0 / (double)((uint64_t)n * (uint64_t)z);
+    out.pgen = s.lat_pe[e] * s.lat_pz[z * N + d];
     out.H = h_single(s, a, b, sg, pi, q);
     uint64_t A = a, B = b;
     clear_so(A, B, sg, pi); set_so(A, B, sg, q);

@@ -130,6 +130,7 @@ struct fciqmc_system {
     double *h1 = nullptr, *eri = nullptr, *J = nullptr, *K = nullptr, *X = nullptr, *U = nullptr, *Hd = nullptr,
            *SK = nullptr;
     int *deg = nullptr, *nbr = nullptr, *pair_of = nullptr;
+    double *lat_pe = nullptr, *lat_pz = nullptr;
     bool pchb = false;
     HbEntry *hb_opp = nullptr, *hb_same = nullptr;  // packed alias tables
     double *hb_sum_opp = nullptr, *hb_sum_same = nullptr;  // their row sums
@@ -141,6 +142,7 @@ struct fciqmc_system {
         v.onsite = onsite ? 1 : 0;
         v.h1 = h1; v.eri = eri; v.J = J; v.K = K; v.X = X; v.U = U; v.Hd = Hd; v.SK = SK;
         v.deg = deg; v.nbr = nbr;
+        v.lat_pe = lat_pe; v.lat_pz = lat_pz;
         v.hb_opp = hb_opp;
         v.hb_same = hb_same;
         v.hb_sum_opp = hb_sum_opp;
@@ -199,6 +201,16 @@ static int build_pchb(fciqmc_system* s, hipStream_t stream) {
 // ---------------------------------------------------------------------------
 struct EngineBase {
     bool fixed_b = false;  // the caller fixed the bucket count: no growth by occupancy
+    // A call failed after it had released device buffers it could not
+    // allocate again (over the memory budget, or hipMalloc failed): the
+    // population is gone and every later call on the run is refused.
+    bool broken = false;
+    int refuse_if_broken() const {
+        return broken ? fail(FCIQMC_ESTATE,
+                             "the run lost its device buffers in an earlier failed call (out of "
+                             "memory); free it")
+                      : 0;
+    }
     virtual ~EngineBase() {}
     virtual int step_once(int64_t t, double S, Ctl& out, int& retries, int64_t& attempts) = 0;
     virtual int set_walkers(const uint64_t* dets, const double* vals, int64_t n) = 0;
@@ -452,21 +464,37 @@ template <int W, class V> struct Engine : EngineBase {
         scount = nullptr; soff = nullptr; nw_b = en_b = nullptr;
         fpos = nullptr; fcnt = nullptr;
     }
+    // Replace buffer p by one of n elements (contents are not kept): the new
+    // one is allocated first and the old one kept if that fails; only when
+    // the budget cannot hold both is the old one released first, and if the
+    // allocation still fails the run is marked broken (p is then null).
+    template <class T> int regrow(T*& p, size_t n) {
+        T* q = nullptr;
+        if (dalloc(arena, &q, n) == 0) {
+            arena.release(p);
+            p = q;
+            return 0;
+        }
+        arena.release(p);
+        p = nullptr;
+        const int rc = dalloc(arena, &q, n);
+        if (rc) {
+            broken = true;
+            return rc;
+        }
+        p = q;
+        return 0;
+    }
     // Grow the slab buffer to hold c records (contents are not kept).
     int ensure_slabs(long long c) {
         if (c <= cap) return 0;
-        arena.release(rec2);
-        rec2 = nullptr;
-        cap = c + c / 4;
-        CHECK(dalloc(arena, &rec2, (size_t)cap));
+        const long long nc = c + c / 4;
+        CHECK(regrow(rec2, (size_t)nc));
         if (rs.adaptive) {
-            arena.release(rec_par);
-            arena.release(rec_h);
-            rec_par = nullptr;
-            rec_h = nullptr;
-            CHECK(dalloc(arena, &rec_par, (size_t)cap));
-            CHECK(dalloc(arena, &rec_h, (size_t)cap));
+            CHECK(regrow(rec_par, (size_t)nc));
+            CHECK(regrow(rec_h, (size_t)nc));
         }
+        cap = nc;
         return 0;
     }
     // The discarded-spawn buffer follows the slab capacity, but is replaced
@@ -475,18 +503,14 @@ template <int W, class V> struct Engine : EngineBase {
     int ensure_rej() {
         if (!keep_rej || cap_rej >= cap) return 0;
         HIP_OK(hipStreamSynchronize(stream));  // a queued pair sum may still read the records
-        arena.release(rej);
-        rej = nullptr;
-        CHECK(dalloc(arena, &rej, (size_t)cap));
+        CHECK(regrow(rej, (size_t)cap));
         cap_rej = cap;
         return 0;
     }
     int ensure_stage(long long c) {
         if (c <= cap_stage) return 0;
-        arena.release(rec);
-        rec = nullptr;
+        CHECK(regrow(rec, (size_t)c));
         cap_stage = c;
-        CHECK(dalloc(arena, &rec, (size_t)cap_stage));
         return 0;
     }
 
@@ -508,10 +532,9 @@ template <int W, class V> struct Engine : EngineBase {
     int ensure_cmap() {
         chunk_next = hctl->chunks;
         if (chunk_next <= cap_cmap) return 0;
-        arena.release(cmap);
-        cmap = nullptr;
-        cap_cmap = chunk_next + chunk_next / 2 + 1024;
-        CHECK(dalloc(arena, &cmap, (size_t)cap_cmap));
+        const int64_t nc = chunk_next + chunk_next / 2 + 1024;
+        CHECK(regrow(cmap, (size_t)nc));
+        cap_cmap = nc;
         hipLaunchKernelGGL(k_chunk_map, dim3((unsigned)std::min<int64_t>((B + 255) / 256, 4096)), dim3(256), 0, stream,
                            st[cur].aoff, B, cmap);
         HIP_OK(hipGetLastError());
@@ -625,6 +648,7 @@ template <int W, class V> struct Engine : EngineBase {
         std::vector<uint64_t> ab;
         std::vector<double> vals;
         CHECK(get_walkers(ab, vals));
+        broken = true;  // until the population is back in the new store
         free_buckets();
         B *= 2;
         CHECK(alloc_buckets());
@@ -635,6 +659,7 @@ template <int W, class V> struct Engine : EngineBase {
     // Load a population through the per-bucket merge with death and rounding off.
     int import(const uint64_t* ab, const double* vals, int64_t n) {
         CHECK(discard_pending());
+        broken = true;  // until the population is in the store
         for (int attempt = 0; attempt < 24; ++attempt) {
             CHECK(ensure_stage(std::max<int64_t>(n, 1)));
             CHECK(ensure_slabs(std::max<int64_t>(n, 1)));
@@ -671,6 +696,7 @@ template <int W, class V> struct Engine : EngineBase {
                 rec_need = hctl->rec_need;
                 CHECK(ensure_cmap());
                 CHECK(ensure_slabs(rec_need));
+                broken = false;
                 return tag_core();
             }
             if (flags & (kFlagTable | kFlagStore)) {
@@ -687,6 +713,7 @@ template <int W, class V> struct Engine : EngineBase {
     }
 
     int set_walkers(const uint64_t* ab, const double* vals, int64_t n) override {
+        CHECK(refuse_if_broken());
         clear_core();  // a new population has no deterministic space
         cur = 0;
         dirty = false;
@@ -725,6 +752,7 @@ template <int W, class V> struct Engine : EngineBase {
     // The n_core determinants of largest |C| (ties: ascending determinant),
     // H^D between them, and the tags in the store.
     int set_core(int64_t n_core) override {
+        CHECK(refuse_if_broken());
         CHECK(discard_pending());  // a queued spawn ignores the new space
         clear_core();
         if (n_core == 0) return 0;
@@ -822,6 +850,7 @@ template <int W, class V> struct Engine : EngineBase {
     const std::vector<uint64_t>& core_dets() const override { return core_host; }
 
     int get_walkers(std::vector<uint64_t>& ab, std::vector<double>& vals) override {
+        CHECK(refuse_if_broken());
         const Store<V>& s = st[cur];
         int64_t* off = nullptr;
         uint64_t* keys = nullptr;
@@ -969,6 +998,7 @@ template <int W, class V> struct Engine : EngineBase {
     }
 
     int step_once(int64_t t, double S, Ctl& out, int& retries, int64_t& attempts) override {
+        CHECK(refuse_if_broken());
         retries = 0;
         attempts = att_next;
         if (pending && pending_t != t) CHECK(discard_pending());
@@ -982,6 +1012,7 @@ template <int W, class V> struct Engine : EngineBase {
 
     // Batched stepping: the instance descriptor of step t and its spawn chunks.
     int batch_prepare(int64_t t, double S, Inst<W, V>& d, int64_t& chunks) {
+        CHECK(refuse_if_broken());
         CHECK(discard_pending());
         if (dirty) {
             CHECK(recover());
@@ -1013,9 +1044,11 @@ template <int W, class V> struct Engine : EngineBase {
     int64_t ndets() const override { return hctl ? hctl->ndets : 0; }
     int rebucket(int buckets) override {
         if (buckets == B) return 0;
+        CHECK(refuse_if_broken());
         std::vector<uint64_t> ab;
         std::vector<double> vals;
         CHECK(get_walkers(ab, vals));
+        broken = true;  // until the population is back in the new store
         free_buckets();
         B = buckets;
         CHECK(alloc_buckets());
@@ -1446,6 +1479,21 @@ int fciqmc_load_integrals(int n_orb, int n_alpha, int n_beta, double e_core, con
             if (q != p && h1[p * N + q] != 0.0) nbr[(size_t)p * N + deg[p]++] = q;
     HIP_OK(hipMemcpy(s->deg, deg.data(), sizeof(int) * N, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(s->nbr, nbr.data(), sizeof(int) * N * N, hipMemcpyHostToDevice));
+    // probabilities of the lattice generator's 32-bit choices: index k of m
+    // is taken by the words x in [ceil(k 2^32/m), ceil((k+1) 2^32/m))
+    auto word_share = [](uint64_t k, uint64_t m) {
+        const uint64_t first = ((k << 32) + m - 1) / m, next = (((k + 1) << 32) + m - 1) / m;
+        return (double)(next - first) * 0x1.0p-32;
+    };
+    const int ne = n_alpha + n_beta;
+    std::vector<double> pe((size_t)ne), pz((size_t)N * N, 0.0);
+    for (int e = 0; e < ne; ++e) pe[(size_t)e] = word_share((uint64_t)e, (uint64_t)ne);
+    for (int z = 1; z < N; ++z)
+        for (int d = 0; d < z; ++d) pz[(size_t)z * N + d] = word_share((uint64_t)d, (uint64_t)z);
+    CHECK(dalloc(s->arena, &s->lat_pe, (size_t)ne));
+    CHECK(dalloc(s->arena, &s->lat_pz, (size_t)N * N));
+    HIP_OK(hipMemcpy(s->lat_pe, pe.data(), sizeof(double) * ne, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(s->lat_pz, pz.data(), sizeof(double) * N * N, hipMemcpyHostToDevice));
     std::vector<int> po((size_t)std::max(np, 1), 0);
     for (int A = 0, c = 0; A < N; ++A)
         for (int B = A + 1; B < N; ++B, ++c) po[c] = A * 64 + B;
@@ -2041,40 +2089,51 @@ void pair_detach(fciqmc_run* run) {
 }
 
 namespace {
-// Queue both sums of a paired step over the two replicas (equal bucket
-// counts) on the first replica's stream, after both have stepped: the
-// overlap of the populations the step started from and the discarded-spawn
-// sum; their values land in out[1] and out[0] (device memory).  No host
-// wait here: the kernel reads the second replica's records and previous
-// store, which its next merge overwrites, and that merge comes only after
-// the host has waited for the first replica's next step, queued behind
-// this kernel on the same stream.
-template <int W, class V> void launch_pair_sums(fciqmc_pair* p, int B, double e0, double* out, hipStream_t s) {
+int log2_of(int64_t x) {
+    int k = 0;
+    while ((int64_t)1 << (k + 1) <= x) ++k;
+    return k;
+}
+// Queue both sums of a paired step over the two replicas on the first
+// replica's stream, after both have stepped: the overlap of the
+// populations the step started from and the discarded-spawn sum; their
+// values land in out[1] and out[0] (device memory).  The replicas may hold
+// different bucket counts (a store that grew during the step); the launch
+// covers the larger count.  No host wait here: the kernel reads the second
+// replica's records and previous store, which its next merge overwrites,
+// and that merge comes only after the host has waited for the first
+// replica's next step, queued behind this kernel on the same stream.
+template <int W, class V> void launch_pair_sums(fciqmc_pair* p, int64_t B1, int64_t B2, double e0, double* out,
+                                                hipStream_t s) {
     const EngineBase* a = p->r[0]->eng.get();
     const EngineBase* b = p->r[1]->eng.get();
     const Store<V> s1 = *static_cast<const Store<V>*>(a->previous_store());
     const Store<V> s2 = *static_cast<const Store<V>*>(b->previous_store());
-    hipLaunchKernelGGL((k_pair_sums<W, V>), dim3((unsigned)std::min(B, 4096)), dim3(kThreads), 0, s,
-                       p->r[0]->sys->view(), s1, s2, a->bucket_entries(), (const Rec<W, V>*)a->rej_records(),
-                       a->rej_offsets(), a->rej_counts(), (const Rec<W, V>*)b->rej_records(), b->rej_offsets(),
-                       b->rej_counts(), B, e0, p->r[0]->h00, p->part, p->part + B, p->err);
-    hipLaunchKernelGGL(k_sum2, dim3(1), dim3(kThreads), 0, s, p->part, p->part + B, B, out);
+    const int64_t Bm = std::max(B1, B2);
+    const int sh1 = log2_of(Bm) - log2_of(B1), sh2 = log2_of(Bm) - log2_of(B2);
+    hipLaunchKernelGGL((k_pair_sums<W, V>), dim3((unsigned)std::min<int64_t>(Bm, 4096)), dim3(kThreads), 0, s,
+                       p->r[0]->sys->view(), s1, sh1, s2, sh2, a->bucket_entries(),
+                       (const Rec<W, V>*)a->rej_records(), a->rej_offsets(), a->rej_counts(),
+                       (const Rec<W, V>*)b->rej_records(), b->rej_offsets(), b->rej_counts(), (int)Bm, e0,
+                       p->r[0]->h00, p->part, p->part + Bm, p->err);
+    hipLaunchKernelGGL(k_sum2, dim3(1), dim3(kThreads), 0, s, p->part, p->part + Bm, (int)Bm, out);
 }
 int pair_sums(fciqmc_pair* p, double e0, double* out) {
     fciqmc_run* a = p->r[0];
-    const int B = (int)a->eng->buckets();
-    if (p->part_n < 2 * (int64_t)B) {
+    const int64_t B1 = a->eng->buckets(), B2 = p->r[1]->eng->buckets();
+    const int64_t Bm = std::max(B1, B2);
+    if (p->part_n < 2 * Bm) {
         HIP_OK(hipStreamSynchronize(a->stream));  // queued pair kernels still use the old buffer
         p->arena.release(p->part);
         p->part = nullptr;
-        CHECK(dalloc(p->arena, &p->part, (size_t)2 * B));
-        p->part_n = 2 * (int64_t)B;
+        CHECK(dalloc(p->arena, &p->part, (size_t)(2 * Bm)));
+        p->part_n = 2 * Bm;
     }
     const int k = a->eng->kind();
-    if (k == 0) launch_pair_sums<1, int32_t>(p, B, e0, out, a->stream);
-    else if (k == 1) launch_pair_sums<1, double>(p, B, e0, out, a->stream);
-    else if (k == 2) launch_pair_sums<2, int32_t>(p, B, e0, out, a->stream);
-    else launch_pair_sums<2, double>(p, B, e0, out, a->stream);
+    if (k == 0) launch_pair_sums<1, int32_t>(p, B1, B2, e0, out, a->stream);
+    else if (k == 1) launch_pair_sums<1, double>(p, B1, B2, e0, out, a->stream);
+    else if (k == 2) launch_pair_sums<2, int32_t>(p, B1, B2, e0, out, a->stream);
+    else launch_pair_sums<2, double>(p, B1, B2, e0, out, a->stream);
     HIP_OK(hipGetLastError());
     return 0;
 }
@@ -2140,8 +2199,6 @@ int fciqmc_pair_step(fciqmc_pair* p, int n_steps, fciqmc_step_stats* stats1, fci
         HIP_OK(hipMemsetAsync(p->err, 0, sizeof(unsigned), a->stream));
         for (int i = 0; i < n_steps; ++i) {
             const double e0 = (a->S + b->S) / 2.0;  // the shifts this step uses
-            const int64_t B0 = a->eng->buckets();
-            const bool same = B0 == b->eng->buckets();
             HIP_OK(hipEventRecord(p->ev, a->stream));
             CHECK(fciqmc_step(a, 1, stats1 ? stats1 + i : nullptr));
             // the pair kernels of the last step read the second replica's
@@ -2150,20 +2207,22 @@ int fciqmc_pair_step(fciqmc_pair* p, int n_steps, fciqmc_step_stats* stats1, fci
             // behind them)
             HIP_OK(hipEventSynchronize(p->ev));
             CHECK(fciqmc_step(b, 1, stats2 ? stats2 + i : nullptr));
+            // every step is evaluated, also one in which a store outgrew its
+            // buckets (the sums read each replica in its own layout)
+            CHECK(pair_sums(p, e0, p->res + 2 * i));
+            has_ovl[i] = 1;
+            has_num[i] = 1;
+            done = i + 1;
             const int64_t Ba = a->eng->buckets(), Bb = b->eng->buckets();
-            if (same && Ba == B0 && Bb == B0) {
-                CHECK(pair_sums(p, e0, p->res + 2 * i));
-                has_ovl[i] = 1;
-                has_num[i] = 1;
-            } else if (Ba != Bb) {
-                // a store outgrew its buckets during the step: this step is not
-                // evaluated, and both use the larger count from the next one
+            if (Ba != Bb) {
+                // both use the larger count from the next step on; the sums
+                // just queued read the records and stores that re-bucketing
+                // replaces, so they finish first
+                HIP_OK(hipStreamSynchronize(a->stream));
                 const int64_t B = std::max(Ba, Bb);
-                done = i + 1;
                 CHECK(a->eng->rebucket((int)B));
                 CHECK(b->eng->rebucket((int)B));
             }
-            done = i + 1;
         }
         return 0;
     };
@@ -2188,7 +2247,7 @@ int fciqmc_pair_step(fciqmc_pair* p, int n_steps, fciqmc_step_stats* stats1, fci
         if (de2) de2[i] = num / ovl;
     }
     if (rc) return rc;
-    if (e) return fail(FCIQMC_EOVERFLOW, "a bucket holds more entries than the pair table (%d slots)", kPtSlots);
+    if (e) return fail(FCIQMC_EDEVICE, "pair sums: an LDS hash claim did not complete");
     return 0;
 }
 

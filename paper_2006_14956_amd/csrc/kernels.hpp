@@ -1474,12 +1474,18 @@ __global__ __launch_bounds__(kThreads) void k_ada_weights(SysView sys, Store<V> 
 
 // ---------------------------------------------------------------------------
 // Replica-pair PT2 correction (Sec. "Perturbative correction", Eq.
-// (pt2_correction)).  Both replicas use the same bucket count, so a target
-// discarded by both sits in the same bucket of each: one workgroup per
-// bucket sums each replica's discarded weight per target in LDS and adds
-// S^1 S^2 / (E_0 - (H_jj - H_00)) over the targets both discarded.
+// (pt2_correction)).  A determinant's bucket is the top bits of its hash,
+// so with power-of-two bucket counts B_r the bucket of a determinant in a
+// layout of B_max buckets is b and in replica r's layout b >> (log2 B_max -
+// log2 B_r): work item b of a launch over B_max buckets reads bucket
+// b >> k_r of each replica and keeps only the entries that fall into b.
+// This lets the two replicas hold different bucket counts (a store that
+// grew during the step).  Per work item, replica 1's discarded weights are
+// summed per target in an LDS table, probed with replica 2's, and
+// S^1 S^2 / (E_0 - (H_jj - H_00)) is added over the targets both discarded.
 // ---------------------------------------------------------------------------
 constexpr int kPtSlots = 2048;
+constexpr int kPtPassLoad = 768;   // distinct keys aimed at per pass (table load <= 3/8 on average)
 template <int W> struct PtTable {
     uint64_t key0[kPtSlots];
     uint64_t key1[W == 2 ? kPtSlots : 1];
@@ -1487,129 +1493,167 @@ template <int W> struct PtTable {
     double w2[kPtSlots];
     int64_t sh[kThreads / 64];
     double shd[kThreads / 64];
+    int full;
 };
 
-// Discarded-spawn sum of bucket b (Eq. (pt2_correction) before the 1/dtau^2):
-// replica 1's discarded weights per target in an LDS table, probed with
-// replica 2's; sum of S^1 S^2 / (E_0 - H_jj) over targets both discarded.
+// Whether an entry of hash h read through a replica layout `shift` levels
+// coarser than B_max belongs to work item b.
+__device__ __forceinline__ bool in_item(uint64_t h, int shift, uint32_t Bmax, int b) {
+    return shift == 0 || (int)bucket_of(h, Bmax) == b;
+}
+
+// Discarded-spawn sum of work item b (Eq. (pt2_correction) before the
+// 1/dtau^2).  Replica 1's targets are split into P passes by bits 16..31 of
+// their hash (bits that neither the bucket nor the LDS slot uses) so that a
+// pass fits the table; P starts from the record count and doubles if a
+// pass still fills the table.
 template <int W, class V>
 __device__ __forceinline__ void pt2_bucket(const SysView& sys, const Rec<W, V>* __restrict__ rej1,
                                            const int64_t* __restrict__ off1, const int32_t* __restrict__ cnt1,
-                                           const Rec<W, V>* __restrict__ rej2,
+                                           int sh1, const Rec<W, V>* __restrict__ rej2,
                                            const int64_t* __restrict__ off2, const int32_t* __restrict__ cnt2,
-                                           int b, double e0, double h00, double* __restrict__ part,
-                                           unsigned* __restrict__ err, PtTable<W>& T) {
-    {
-        const int n1 = cnt1[b], n2 = cnt2[b];
+                                           int sh2, uint32_t Bmax, int b, double e0, double h00,
+                                           double* __restrict__ part, unsigned* __restrict__ err, PtTable<W>& T) {
+    const int b1 = b >> sh1, b2 = b >> sh2;
+    const int n1 = cnt1[b1], n2 = cnt2[b2];
+    const int64_t o1 = off1[b1], o2 = off2[b2];
+    int P = 1;
+    while ((int64_t)n1 > (int64_t)P * kPtPassLoad && P < (1 << 16)) P <<= 1;
+    double acc = 0.0;
+    for (;;) {
         int nslots = kThreads;
-        while (nslots < (n1 * 4) / 3 + 1 && nslots < kPtSlots) nslots <<= 1;
+        const int want = P == 1 ? (n1 * 4) / 3 + 1 : kPtSlots;
+        while (nslots < want && nslots < kPtSlots) nslots <<= 1;
         const uint64_t mask = (uint64_t)(nslots - 1);
-        for (int i = threadIdx.x; i < nslots; i += kThreads) {
-            T.key0[i] = kEmpty;
-            if constexpr (W == 2) T.key1[i] = kEmpty;
-            T.w1[i] = 0.0;
-            T.w2[i] = 0.0;
-        }
-        __syncthreads();
-        for (int q = threadIdx.x; q < n1; q += kThreads) {
-            const Rec<W, V> x = rej1[off1[b] + q];
-            Key<W> key;
-#pragma unroll
-            for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
-            const int s = lds_find<W>(T, key, key_hash<W>(key), mask, true);
-            if (s < 0) { atomicOr(err, 1u); continue; }
-            lds_add<double>(&T.w1[s], (double)x.v);
-        }
-        __syncthreads();
-        for (int q = threadIdx.x; q < n2; q += kThreads) {
-            const Rec<W, V> x = rej2[off2[b] + q];
-            Key<W> key;
-#pragma unroll
-            for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
-            const int s = lds_find<W>(T, key, key_hash<W>(key), mask, false);
-            if (s >= 0) lds_add<double>(&T.w2[s], (double)x.v);
-        }
-        __syncthreads();
-        double acc = 0.0;
-        for (int i = threadIdx.x; i < nslots; i += kThreads) {
-            const double a = T.w1[i], c = T.w2[i];
-            if (T.key0[i] == kEmpty || a == 0.0 || c == 0.0) continue;
-            Key<W> key;
-            key.w[0] = T.key0[i];
-            if constexpr (W == 2) key.w[1] = T.key1[i];
-            const double hd = h_diag(sys, key_alpha<W>(key), key_beta<W>(key));
-            const double dj = hd - h00;
-            const double num = a * c;
-            const double den = e0 - dj;
-            const double x = num / den;
-            acc = acc + x;
-        }
-        acc = wave_sum(acc);
-        if (lane_id() == 0) T.shd[threadIdx.x >> 6] = acc;
-        __syncthreads();
-        if (threadIdx.x == 0) part[b] = ((T.shd[0] + T.shd[1]) + T.shd[2]) + T.shd[3];
-        __syncthreads();
-    }
-}
-
-// Replica overlap sum_i C_i^1 C_i^2 of bucket b: the first store's entries
-// in an LDS table, probed with the second's.
-template <int W, class V>
-__device__ __forceinline__ void overlap_bucket(const Store<V>& s1, const Store<V>& s2, int R, int b,
-                                               double* __restrict__ part, unsigned* __restrict__ err,
-                                               PtTable<W>& T) {
-    {
-        const int n1 = s1.count[b], n2 = s2.count[b];
-        int nslots = kThreads;
-        while (nslots < (n1 * 4) / 3 + 1 && nslots < kPtSlots) nslots <<= 1;
-        const uint64_t mask = (uint64_t)(nslots - 1);
-        const int64_t eb = (int64_t)b * R;
-        for (int i = threadIdx.x; i < nslots; i += kThreads) {
-            T.key0[i] = kEmpty;
-            if constexpr (W == 2) T.key1[i] = kEmpty;
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < n1; e += kThreads) {
-            const Key<W> key = load_key<W>(s1.keys + (eb + e) * W);
-            const int s = lds_find<W>(T, key, key_hash<W>(key), mask, true);
-            if (s < 0) { atomicOr(err, 1u); continue; }
-            T.w1[s] = (double)s1.vals[eb + e];
-        }
-        __syncthreads();
-        double acc = 0.0;
-        for (int e = threadIdx.x; e < n2; e += kThreads) {
-            const Key<W> key = load_key<W>(s2.keys + (eb + e) * W);
-            const int s = lds_find<W>(T, key, key_hash<W>(key), mask, false);
-            if (s >= 0) {
-                const double q = T.w1[s] * (double)s2.vals[eb + e];
-                acc = acc + q;
+        bool full = false;
+        acc = 0.0;
+        for (int pass = 0; pass < P && !full; ++pass) {
+            for (int i = threadIdx.x; i < nslots; i += kThreads) {
+                T.key0[i] = kEmpty;
+                if constexpr (W == 2) T.key1[i] = kEmpty;
+                T.w1[i] = 0.0;
+                T.w2[i] = 0.0;
             }
+            if (threadIdx.x == 0) T.full = 0;
+            __syncthreads();
+            for (int q = threadIdx.x; q < n1; q += kThreads) {
+                const Rec<W, V> x = rej1[o1 + q];
+                Key<W> key;
+#pragma unroll
+                for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
+                const uint64_t h = key_hash<W>(key);
+                if (!in_item(h, sh1, Bmax, b) || (int)((h >> 16) & (uint64_t)(P - 1)) != pass) continue;
+                const int s = lds_find<W>(T, key, h, mask, true);
+                if (s == -2) { T.full = 1; continue; }
+                if (s < 0) { atomicOr(err, 1u); continue; }
+                lds_add<double>(&T.w1[s], (double)x.v);
+            }
+            __syncthreads();
+            full = T.full != 0;
+            if (!full) {
+                for (int q = threadIdx.x; q < n2; q += kThreads) {
+                    const Rec<W, V> x = rej2[o2 + q];
+                    Key<W> key;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
+                    const uint64_t h = key_hash<W>(key);
+                    if (!in_item(h, sh2, Bmax, b) || (int)((h >> 16) & (uint64_t)(P - 1)) != pass) continue;
+                    const int s = lds_find<W>(T, key, h, mask, false);
+                    if (s >= 0) lds_add<double>(&T.w2[s], (double)x.v);
+                }
+                __syncthreads();
+                for (int i = threadIdx.x; i < nslots; i += kThreads) {
+                    const double a = T.w1[i], c = T.w2[i];
+                    if (T.key0[i] == kEmpty || a == 0.0 || c == 0.0) continue;
+                    Key<W> key;
+                    key.w[0] = T.key0[i];
+                    if constexpr (W == 2) key.w[1] = T.key1[i];
+                    const double hd = h_diag(sys, key_alpha<W>(key), key_beta<W>(key));
+                    const double dj = hd - h00;
+                    const double num = a * c;
+                    const double den = e0 - dj;
+                    const double x = num / den;
+                    acc = acc + x;
+                }
+            }
+            __syncthreads();
         }
-        acc = wave_sum(acc);
-        if (lane_id() == 0) T.shd[threadIdx.x >> 6] = acc;
-        __syncthreads();
-        if (threadIdx.x == 0) part[b] = ((T.shd[0] + T.shd[1]) + T.shd[2]) + T.shd[3];
-        __syncthreads();
+        if (!full || P >= (1 << 16)) {
+            if (full) atomicOr(err, 1u);
+            break;
+        }
+        P <<= 1;
     }
+    acc = wave_sum(acc);
+    if (lane_id() == 0) T.shd[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[b] = ((T.shd[0] + T.shd[1]) + T.shd[2]) + T.shd[3];
+    __syncthreads();
 }
 
-// Both sums of a replica pair's step, one workgroup per bucket: the
-// overlap of the populations the step started from into part_ovl, the
-// discarded-spawn sum into part_pt2.
+// Replica overlap sum_i C_i^1 C_i^2 over work item b: the first store's
+// entries in an LDS table (at most R = 1024 of them), probed with the
+// second's.
 template <int W, class V>
-__global__ __launch_bounds__(kThreads) void k_pair_sums(SysView sys, Store<V> s1, Store<V> s2, int R,
-                                                        const Rec<W, V>* __restrict__ rej1,
+__device__ __forceinline__ void overlap_bucket(const Store<V>& s1, int sh1, const Store<V>& s2, int sh2, int R,
+                                               uint32_t Bmax, int b, double* __restrict__ part,
+                                               unsigned* __restrict__ err, PtTable<W>& T) {
+    const int b1 = b >> sh1, b2 = b >> sh2;
+    const int n1 = s1.count[b1], n2 = s2.count[b2];
+    int nslots = kThreads;
+    while (nslots < (n1 * 4) / 3 + 1 && nslots < kPtSlots) nslots <<= 1;
+    const uint64_t mask = (uint64_t)(nslots - 1);
+    const int64_t e1 = (int64_t)b1 * R, e2 = (int64_t)b2 * R;
+    for (int i = threadIdx.x; i < nslots; i += kThreads) {
+        T.key0[i] = kEmpty;
+        if constexpr (W == 2) T.key1[i] = kEmpty;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n1; e += kThreads) {
+        const Key<W> key = load_key<W>(s1.keys + (e1 + e) * W);
+        const uint64_t h = key_hash<W>(key);
+        if (!in_item(h, sh1, Bmax, b)) continue;
+        const int s = lds_find<W>(T, key, h, mask, true);
+        if (s < 0) { atomicOr(err, 1u); continue; }
+        T.w1[s] = (double)s1.vals[e1 + e];
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < n2; e += kThreads) {
+        const Key<W> key = load_key<W>(s2.keys + (e2 + e) * W);
+        const uint64_t h = key_hash<W>(key);
+        if (!in_item(h, sh2, Bmax, b)) continue;
+        const int s = lds_find<W>(T, key, h, mask, false);
+        if (s >= 0) {
+            const double q = T.w1[s] * (double)s2.vals[e2 + e];
+            acc = acc + q;
+        }
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0) T.shd[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[b] = ((T.shd[0] + T.shd[1]) + T.shd[2]) + T.shd[3];
+    __syncthreads();
+}
+
+// Both sums of a replica pair's step over B_max = max(B_1, B_2) work items
+// (bucket counts are powers of two): the overlap of the populations the
+// step started from into part_ovl, the discarded-spawn sum into part_pt2.
+template <int W, class V>
+__global__ __launch_bounds__(kThreads) void k_pair_sums(SysView sys, Store<V> s1, int sh1, Store<V> s2, int sh2,
+                                                        int R, const Rec<W, V>* __restrict__ rej1,
                                                         const int64_t* __restrict__ off1,
                                                         const int32_t* __restrict__ cnt1,
                                                         const Rec<W, V>* __restrict__ rej2,
                                                         const int64_t* __restrict__ off2,
-                                                        const int32_t* __restrict__ cnt2, int B, double e0,
+                                                        const int32_t* __restrict__ cnt2, int Bmax, double e0,
                                                         double h00, double* __restrict__ part_ovl,
                                                         double* __restrict__ part_pt2, unsigned* __restrict__ err) {
     __shared__ PtTable<W> T;
-    for (int b = blockIdx.x; b < B; b += gridDim.x) {
-        overlap_bucket<W, V>(s1, s2, R, b, part_ovl, err, T);
-        pt2_bucket<W, V>(sys, rej1, off1, cnt1, rej2, off2, cnt2, b, e0, h00, part_pt2, err, T);
+    for (int b = blockIdx.x; b < Bmax; b += gridDim.x) {
+        overlap_bucket<W, V>(s1, sh1, s2, sh2, R, (uint32_t)Bmax, b, part_ovl, err, T);
+        pt2_bucket<W, V>(sys, rej1, off1, cnt1, sh1, rej2, off2, cnt2, sh2, (uint32_t)Bmax, b, e0, h00, part_pt2,
+                         err, T);
     }
 }
 

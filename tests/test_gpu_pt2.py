@@ -78,8 +78,9 @@ def test_pair_correction_matches_oracle(words):
 def test_pair_through_store_growth():
     """Both replicas start on two buckets and grow from 1000 walkers on the
     reference to most of the 4900 determinants, so a store outgrows the
-    common bucket count: that step's dE2 is NaN, both
-    stores are re-bucketed, and every other step equals the oracle."""
+    common bucket count during a step: that step is evaluated with the two
+    replicas in different layouts, both stores are then re-bucketed, and
+    every step's dE2 equals the oracle's."""
     s = inputs.molecule_8o8e()
     sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
     ra, rb = ref_of(s)
@@ -94,23 +95,23 @@ def test_pair_through_store_growth():
         gpu.append(run)
         orc.append(o)
     pair = F.fciqmc_pair_create(gpu[0], gpu[1])
-    skipped = 0
+    grew = 0
     for step in range(120):
+        b0 = F.fciqmc_profile(gpu[0], False)[2]["buckets"]
         g1, g2, d = F.fciqmc_pair_step(pair, 1)
+        grew += F.fciqmc_profile(gpu[0], False)[2]["buckets"] != b0
         ovl = oracle.pair_overlap(orc[0], orc[1])
         o1 = orc[0].step(1)
         o2 = orc[1].step(1)
         assert_same_stats(g1[0], o1[0])
         assert_same_stats(g2[0], o2[0])
         want = oracle.pair_pt2(orc[0], orc[1]) / ovl
-        if math.isnan(d[0]):
-            skipped += 1
-            continue
+        assert not math.isnan(d[0]), step
         assert abs(d[0] - want) <= 1e-10 * max(1e-12, abs(want)), (step, d[0], want)
-    assert skipped >= 1
+    assert grew >= 1
     assert F.fciqmc_profile(gpu[0], False)[2]["buckets"] > 2
     rep = F.fciqmc_pair_pt2(pair)
-    assert rep["n"] == 120 - skipped
+    assert rep["n"] == 120
     F.fciqmc_pair_free(pair)
     for g in gpu:
         F.fciqmc_free_run(g)
@@ -120,7 +121,7 @@ def test_pair_through_store_growth():
 def test_pair_multi_step_calls_through_growth():
     """The growth scenario again, in calls of 7 paired steps: the values a
     call gathers from the device at its end are, step by step, the oracle's
-    (NaN where a store outgrew the common bucket count), and the per-step
+    (also where a store outgrew the common bucket count), and the per-step
     statistics of both replicas agree with it."""
     s = inputs.molecule_8o8e()
     sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
@@ -136,7 +137,7 @@ def test_pair_multi_step_calls_through_growth():
         gpu.append(run)
         orc.append(o)
     pair = F.fciqmc_pair_create(gpu[0], gpu[1])
-    skipped = evaluated = 0
+    evaluated = 0
     for call in range(9):
         g1, g2, d = F.fciqmc_pair_step(pair, 7)
         assert len(d) == 7 and len(g1) == 7 and len(g2) == 7
@@ -146,16 +147,61 @@ def test_pair_multi_step_calls_through_growth():
             o2 = orc[1].step(1)
             assert_same_stats(g1[i], o1[0])
             assert_same_stats(g2[i], o2[0])
-            if math.isnan(d[i]):
-                skipped += 1
-                continue
+            assert not math.isnan(d[i]), (call, i)
             want = oracle.pair_pt2(orc[0], orc[1]) / ovl
             assert abs(d[i] - want) <= 1e-10 * max(1e-12, abs(want)), (call, i, d[i], want)
             evaluated += 1
-    assert skipped >= 1 and evaluated >= 50
+    assert evaluated == 63
+    assert F.fciqmc_profile(gpu[0], False)[2]["buckets"] > 2
     for g, o in zip(gpu, orc):
         assert_same_walkers(g, o)
     assert F.fciqmc_pair_pt2(pair)["n"] == evaluated
+    F.fciqmc_pair_free(pair)
+    for g in gpu:
+        F.fciqmc_free_run(g)
+    F.fciqmc_free_system(sysd)
+
+
+def test_pair_many_discards_per_bucket():
+    """Thousands of discarded spawns per bucket: 1000 non-initiators with up
+    to 100 walkers each (n_a = 100) on the 8-orbital molecule in eight
+    buckets, so a bucket holds several times more discard records than one
+    pass of the pair table takes and the sum runs in passes over disjoint
+    hash ranges; every step's dE2 equals the oracle's."""
+    s = inputs.molecule_8o8e()
+    sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
+    ra, rb = ref_of(s)
+    osys = oracle.System.from_inputs(s)
+    gpu, orc = [], []
+    for rep in (0, 1):
+        _, run = make_gpu_run(s, tau=0.04, target=1e9, n_a=100.0, seed=6, replica=rep, sysd=sysd,
+                              buckets_log2=3)
+        o = oracle.Run(osys, ref=(ra, rb), tau=0.04, target=1e9, n_a=100.0, seed=6, replica=rep)
+        o.collect_rejected(True)
+        gpu.append(run)
+        orc.append(o)
+    a, b, v = inputs.random_walker_state(s.n_orb, s.n_alpha, s.n_beta, 1000, seed=5, max_pop=100,
+                                         include=(ra, rb))
+    for g, o in zip(gpu, orc):
+        F.fciqmc_set_walkers(g, a, b, v)
+        F.fciqmc_set_checkpoint(g, 0, -0.7, 1, 0, float(np.abs(v).sum()))
+        o.set_walkers(a, b, v)
+        o.set_state(0, -0.7, 1, 0, float(np.abs(v).sum()))
+    pair = F.fciqmc_pair_create(gpu[0], gpu[1])
+    nb = F.fciqmc_profile(gpu[0], False)[2]["buckets"]
+    for step in range(3):
+        g1, g2, d = F.fciqmc_pair_step(pair, 1)
+        ovl = oracle.pair_overlap(orc[0], orc[1])
+        o1 = orc[0].step(1)
+        o2 = orc[1].step(1)
+        assert_same_stats(g1[0], o1[0])
+        assert_same_stats(g2[0], o2[0])
+        if step == 0:
+            # records per bucket far above one pass of the table (768)
+            assert g1[0]["spawns"] > 2000 * nb, (g1[0]["spawns"], nb)
+        want = oracle.pair_pt2(orc[0], orc[1]) / ovl
+        assert want != 0.0
+        assert abs(d[0] - want) <= 1e-10 * max(1e-12, abs(want)), (step, d[0], want)
     F.fciqmc_pair_free(pair)
     for g in gpu:
         F.fciqmc_free_run(g)
