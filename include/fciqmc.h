@@ -204,6 +204,19 @@ int fciqmc_set_checkpoint(fciqmc_run *run, const fciqmc_checkpoint *in);
 int fciqmc_matrix_elements(const fciqmc_system *sys, const uint64_t *dets_i,
                            const uint64_t *dets_j, int64_t n, double *out);
 
+/* fciqmc_matrix_elements for callers that cannot allocate device memory
+ * (serving loops, allocation-free harnesses): the same values, computed by
+ * the same kernel, with the pairs and results staged in a fixed device
+ * array of the library instead of buffers allocated per call.  It calls no
+ * hipMalloc or hipFree.  At most 65536 pairs per call (EINVAL above that);
+ * the array holds about 2.5 MB on each device the library runs on, kept
+ * until the process ends.  Calls are serialised within the process by a
+ * lock; the array keeps the last call's contents, and calls from several
+ * processes on one device use separate copies.  Synchronous (returns when
+ * out is written); not for use under stream capture. */
+int fciqmc_matrix_elements_noalloc(const fciqmc_system *sys, const uint64_t *dets_i,
+                                   const uint64_t *dets_j, int64_t n, double *out);
+
 /* Device memory currently held by a run (bytes). */
 int64_t fciqmc_run_device_bytes(const fciqmc_run *run);
 

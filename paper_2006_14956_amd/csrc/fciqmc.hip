@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2058,6 +2059,77 @@ int fciqmc_matrix_elements(const fciqmc_system* sys, const uint64_t* di, const u
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Matrix elements without allocation: the staging of the pairs and of the
+// results lives in one statically sized device array instead of buffers
+// allocated per call.  Each device holds its own copy of the array (for the
+// life of the process); host code must use the address hipGetSymbolAddress
+// returns for it on that device, never the array's name, which on the host
+// is only a stand-in.  Layout: kNoAllocPairs determinant pairs of
+// (alpha, beta) words for D_i, the same for D_j, then kNoAllocPairs results.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t kNoAllocPairs = 1 << 16;
+constexpr size_t kNoAllocBytes = (size_t)kNoAllocPairs * (4 * sizeof(uint64_t) + sizeof(double));
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_lock;               // one call at a time uses a device's array
+char* g_scratch_ptr[kMaxDevices] = {};   // its device address, per device
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+// Device address of `scratch` on device dev (which must be current), looked
+// up once per device.  Called with g_scratch_lock held.
+int scratch_on(int dev, char** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(FCIQMC_EDEVICE, "device %d out of range", dev);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(FCIQMC_EDEVICE, "no device address for the scratch array");
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
+}
+// Restores the caller's current device when it goes out of scope.
+struct DeviceGuard {
+    int prev = -1;
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+}  // namespace
+
+extern "C" int fciqmc_matrix_elements_noalloc(const fciqmc_system* sys, const uint64_t* di, const uint64_t* dj,
+                                              int64_t n, double* out) {
+    if (!sys || (n > 0 && (!di || !dj || !out))) return fail(FCIQMC_EINVAL, "null argument");
+    if (n < 0) return fail(FCIQMC_EINVAL, "n must be >= 0");
+    if (n > kNoAllocPairs)
+        return fail(FCIQMC_EINVAL, "n = %lld exceeds the %lld pairs the allocation-free call stages",
+                    (long long)n, (long long)kNoAllocPairs);
+    if (n == 0) return 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (!valid_det(sys, di[2 * i], di[2 * i + 1]) || !valid_det(sys, dj[2 * i], dj[2 * i + 1]))
+            return fail(FCIQMC_EINVAL, "pair %lld holds an invalid determinant", (long long)i);
+    std::lock_guard<std::mutex> lock(g_scratch_lock);
+    DeviceGuard guard;
+    HIP_OK(hipGetDevice(&guard.prev));
+    HIP_OK(hipSetDevice(sys->device));
+    char* base = nullptr;
+    CHECK(scratch_on(sys->device, &base));
+    uint64_t* a = reinterpret_cast<uint64_t*>(base);
+    uint64_t* b = a + 2 * kNoAllocPairs;
+    double* o = reinterpret_cast<double*>(b + 2 * kNoAllocPairs);
+    HIP_OK(hipMemcpy(a, di, sizeof(uint64_t) * 2 * n, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(b, dj, sizeof(uint64_t) * 2 * n, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_hij, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, 0,
+                       sys->view(), a, b, (long long)n, o);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpy(out, o, sizeof(double) * n, hipMemcpyDeviceToHost));
+    return 0;
+}
 
 // ---------------------------------------------------------------------------
 // Replica pairs and the second-order correction from discarded spawns

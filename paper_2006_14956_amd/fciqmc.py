@@ -74,7 +74,8 @@ class TuneReport(C.Structure):
 
 EXPORTS = ["fciqmc_params_default", "fciqmc_load_integrals", "fciqmc_init", "fciqmc_step",
            "fciqmc_energy", "fciqmc_get_walkers", "fciqmc_set_walkers", "fciqmc_get_checkpoint",
-           "fciqmc_set_checkpoint", "fciqmc_matrix_elements", "fciqmc_run_device_bytes",
+           "fciqmc_set_checkpoint", "fciqmc_matrix_elements", "fciqmc_matrix_elements_noalloc",
+           "fciqmc_run_device_bytes",
            "fciqmc_profile", "fciqmc_batch_create", "fciqmc_batch_add", "fciqmc_batch_remove",
            "fciqmc_batch_size", "fciqmc_batch_step", "fciqmc_batch_tune", "fciqmc_batch_profile",
            "fciqmc_batch_free", "fciqmc_estimate_bytes", "fciqmc_server_create",
@@ -117,6 +118,7 @@ def lib():
         L.fciqmc_get_checkpoint.argtypes = [vp, C.POINTER(Checkpoint)]
         L.fciqmc_set_checkpoint.argtypes = [vp, C.POINTER(Checkpoint)]
         L.fciqmc_matrix_elements.argtypes = [vp, pu64, pu64, i64, pdbl]
+        L.fciqmc_matrix_elements_noalloc.argtypes = [vp, pu64, pu64, i64, pdbl]
         L.fciqmc_run_device_bytes.argtypes = [vp]
         L.fciqmc_run_device_bytes.restype = i64
         L.fciqmc_profile.argtypes = [vp, C.c_int, pdbl, C.POINTER(i64), C.POINTER(i64)]
@@ -367,6 +369,18 @@ def fciqmc_matrix_elements(system: System, dets_i, dets_j) -> np.ndarray:
     out = np.zeros(max(n, 1))
     _check(lib().fciqmc_matrix_elements(system.handle, _p(di, C.c_uint64), _p(dj, C.c_uint64), n,
                                         _p(out, C.c_double)))
+    return out[:n]
+
+
+def fciqmc_matrix_elements_noalloc(system: System, dets_i, dets_j) -> np.ndarray:
+    """As fciqmc_matrix_elements, staged in the library's fixed device array
+    (no device allocation; at most 65536 pairs)."""
+    di = np.ascontiguousarray(dets_i, dtype=np.uint64).reshape(-1)
+    dj = np.ascontiguousarray(dets_j, dtype=np.uint64).reshape(-1)
+    n = len(di) // 2
+    out = np.zeros(max(n, 1))
+    _check(lib().fciqmc_matrix_elements_noalloc(system.handle, _p(di, C.c_uint64), _p(dj, C.c_uint64), n,
+                                                _p(out, C.c_double)))
     return out[:n]
 
 
