@@ -204,6 +204,17 @@ int fciqmc_set_checkpoint(fciqmc_run *run, const fciqmc_checkpoint *in);
 int fciqmc_matrix_elements(const fciqmc_system *sys, const uint64_t *dets_i,
                            const uint64_t *dets_j, int64_t n, double *out);
 
+/* One row of the pre-computed heat-bath alias tables (Appendix A.3, Eq.
+ * (hbs)), copied back for parity checks.  opp != 0: the opposite-spin row
+ * of electrons (I alpha, J beta), row = I*N + J, over the N*N hole columns
+ * A*N + B; opp == 0: the same-spin row of the orbital pair I < J (pairs in
+ * lexicographic order), over the N(N-1)/2 hole pairs A < B.  prob, alias,
+ * weight (host, one entry per column) receive the alias threshold, the
+ * alias column and the column's weight w_ab; *sum the row sum of the
+ * weights.  Builds the tables on first use; EINVAL for a row out of range. */
+int fciqmc_pchb_row(const fciqmc_system *sys, int opp, int64_t row, double *prob, int32_t *alias,
+                    double *weight, double *sum);
+
 /* fciqmc_matrix_elements for callers that cannot allocate device memory
  * (serving loops, allocation-free harnesses): the same values, computed by
  * the same kernel, with the pairs and results staged in a fixed device

@@ -2102,6 +2102,26 @@ struct DeviceGuard {
 };
 }  // namespace
 
+extern "C" int fciqmc_pchb_row(const fciqmc_system* csys, int opp, int64_t row, double* prob, int32_t* alias,
+                               double* weight, double* sum) {
+    if (!csys || !prob || !alias || !weight || !sum) return fail(FCIQMC_EINVAL, "null argument");
+    fciqmc_system* sys = const_cast<fciqmc_system*>(csys);
+    const int64_t N = sys->N;
+    const int64_t K = opp ? N * N : N * (N - 1) / 2;
+    if (row < 0 || row >= K) return fail(FCIQMC_EINVAL, "row %lld out of range [0, %lld)", (long long)row, (long long)K);
+    CHECK(build_pchb(sys, nullptr));
+    std::vector<HbEntry> h((size_t)K);
+    const HbEntry* src = (opp ? sys->hb_opp : sys->hb_same) + (size_t)row * (size_t)K;
+    HIP_OK(hipMemcpy(h.data(), src, sizeof(HbEntry) * K, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(sum, (opp ? sys->hb_sum_opp : sys->hb_sum_same) + row, sizeof(double), hipMemcpyDeviceToHost));
+    for (int64_t c = 0; c < K; ++c) {
+        prob[c] = h[(size_t)c].prob;
+        alias[c] = h[(size_t)c].alias;
+        weight[c] = std::fabs(h[(size_t)c].v_self);
+    }
+    return 0;
+}
+
 extern "C" int fciqmc_matrix_elements_noalloc(const fciqmc_system* sys, const uint64_t* di, const uint64_t* dj,
                                               int64_t n, double* out) {
     if (!sys || (n > 0 && (!di || !dj || !out))) return fail(FCIQMC_EINVAL, "null argument");

@@ -75,6 +75,7 @@ class TuneReport(C.Structure):
 EXPORTS = ["fciqmc_params_default", "fciqmc_load_integrals", "fciqmc_init", "fciqmc_step",
            "fciqmc_energy", "fciqmc_get_walkers", "fciqmc_set_walkers", "fciqmc_get_checkpoint",
            "fciqmc_set_checkpoint", "fciqmc_matrix_elements", "fciqmc_matrix_elements_noalloc",
+           "fciqmc_pchb_row",
            "fciqmc_run_device_bytes",
            "fciqmc_profile", "fciqmc_batch_create", "fciqmc_batch_add", "fciqmc_batch_remove",
            "fciqmc_batch_size", "fciqmc_batch_step", "fciqmc_batch_tune", "fciqmc_batch_profile",
@@ -119,6 +120,7 @@ def lib():
         L.fciqmc_set_checkpoint.argtypes = [vp, C.POINTER(Checkpoint)]
         L.fciqmc_matrix_elements.argtypes = [vp, pu64, pu64, i64, pdbl]
         L.fciqmc_matrix_elements_noalloc.argtypes = [vp, pu64, pu64, i64, pdbl]
+        L.fciqmc_pchb_row.argtypes = [vp, C.c_int, i64, pdbl, C.POINTER(C.c_int32), pdbl, pdbl]
         L.fciqmc_run_device_bytes.argtypes = [vp]
         L.fciqmc_run_device_bytes.restype = i64
         L.fciqmc_profile.argtypes = [vp, C.c_int, pdbl, C.POINTER(i64), C.POINTER(i64)]
@@ -382,6 +384,18 @@ def fciqmc_matrix_elements_noalloc(system: System, dets_i, dets_j) -> np.ndarray
     _check(lib().fciqmc_matrix_elements_noalloc(system.handle, _p(di, C.c_uint64), _p(dj, C.c_uint64), n,
                                                 _p(out, C.c_double)))
     return out[:n]
+
+
+def fciqmc_pchb_row(system: System, opp: bool, row: int, n_orb: int):
+    """(prob, alias, weight, row sum) of one heat-bath alias-table row."""
+    K = n_orb * n_orb if opp else n_orb * (n_orb - 1) // 2
+    prob = np.zeros(K)
+    alias = np.zeros(K, dtype=np.int32)
+    weight = np.zeros(K)
+    tot = C.c_double()
+    _check(lib().fciqmc_pchb_row(system.handle, int(bool(opp)), int(row), _p(prob, C.c_double),
+                                 _p(alias, C.c_int32), _p(weight, C.c_double), C.byref(tot)))
+    return prob, alias, weight, tot.value
 
 
 def fciqmc_run_device_bytes(run: Run) -> int:
