@@ -2,12 +2,15 @@
 
 A step is one full pass of the hot path (spawn, death, annihilation with the
 initiator rule, estimators, shift update) over the walker population.  The
-default workload is the 4x4 periodic Hubbard model (t=1, U=4, 8 up + 8 down,
-Neel reference), integer walkers with a 1e6 walker target, initiator n_a=3,
-dtau=0.005, lattice excitation generator, Philox seed 1.  The population is
-first grown until the shift varies (not timed: initialisation), then
-`--warmup` steps run untimed while the shift settles the population at the
-target, and `--steps` steps are timed.
+headline workload is the largest single-GPU configuration: 26 electrons in
+40 spatial orbitals (128-bit determinants), seeded synthetic integrals,
+real walkers with a 1e8 walker target, initiator n_a = 3, the pre-computed
+heat-bath generator, FP64.  The population is first grown from 1000 walkers
+on the reference until the shift varies (not timed: initialisation), then
+`--warmup` steps run untimed and `--steps` steps are timed.  The 4x4
+Hubbard workload (1e6 integer walkers) and the batched, served,
+semi-stochastic, adaptive-shift, replica-pair and generator legs follow as
+secondary figures.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -23,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "spawn attempts/s (spawn+annihilate+death); batched/served vs plain; p99 latency"
 
 
 def log(*a):
@@ -83,12 +87,18 @@ def algorithmic_bytes(kernel, d_in, d_out, recs, words, vbytes):
     return 0
 
 
+# Steps of initialisation after the shift starts varying, before the warm-up:
+# the shift's first value comes from the growth rate and overshoots, and the
+# population needs this long to come back to its target.
+SETTLE = {"mol40": 300, "hubbard4x4": 2000, "mol8": 500}
+
+
 def measure(F, np, torch, stream, name, steps, warmup):
     """Grow, settle and time one workload; returns the run and its figures."""
     s, pd, desc = workload(name)
     sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
     run = F.fciqmc_init(sysd, F.fciqmc_params_default(**pd), stream=stream)
-    # initialisation: grow until the shift varies (not timed)
+    # initialisation (not timed): grow until the shift varies, then settle
     t0 = time.perf_counter()
     grown = 0
     while grown < 5000:
@@ -96,8 +106,10 @@ def measure(F, np, torch, stream, name, steps, warmup):
         grown += 10
         if st[-1]["vary_shift"]:
             break
-    log(f"[{name}] grown {grown} steps in {time.perf_counter() - t0:.2f}s: N_w={st[-1]['nw']:.4g} "
-        f"dets={st[-1]['ndets']} S={st[-1]['shift']:.4f}")
+    settle = SETTLE.get(name.split("-")[0], 300)
+    st = F.fciqmc_step(run, settle)
+    log(f"[{name}] grown {grown} steps and settled {settle} in {time.perf_counter() - t0:.2f}s: "
+        f"N_w={st[-1]['nw']:.4g} dets={st[-1]['ndets']} S={st[-1]['shift']:.4f}")
     if warmup:
         st = F.fciqmc_step(run, warmup)
         log(f"[{name}] warmup {warmup}: N_w={st[-1]['nw']:.4g} dets={st[-1]['ndets']} "
@@ -604,6 +616,64 @@ def measure_adaptive(F, np, torch, steps):
     return out
 
 
+def F_ref(pd, s):
+    """Reference determinant of a workload: given, or aufbau."""
+    ra, rb = pd.get("ref_alpha", 0), pd.get("ref_beta", 0)
+    if not (ra or rb):
+        ra, rb = (1 << s.n_alpha) - 1, (1 << s.n_beta) - 1
+    return int(ra), int(rb)
+
+
+def oracle_baseline(s, pd, targets, seconds, attempts_per_step, ref):
+    """The oracle (single-threaded C, FP64, no FMA contraction) on the same
+    workload at reduced walker targets, each population grown by the oracle
+    itself from the reference (its own inputs: nothing comes from the GPU
+    run).  Every step's time is recorded; time per step is fitted linearly
+    in attempts per step over all of them (the cost of a step is linear in
+    the walker number) and evaluated at the GPU run's attempts per step,
+    which gives the extrapolated attempts/s of the oracle on the full
+    workload."""
+    import numpy as np
+    import oracle
+    words = 1 if s.n_orb <= 32 else 2
+    osys = oracle.System.from_inputs(s, words=words)
+    import paper_2006_14956_amd.fciqmc as F
+    gen = {F.GEN_UNIFORM: oracle.GEN_UNIFORM, F.GEN_LATTICE: oracle.GEN_LATTICE,
+           F.GEN_PCHB: oracle.GEN_PCHB}[pd.get("excitgen", F.GEN_UNIFORM)]
+    mode = oracle.MODE_REAL if pd.get("mode", F.MODE_INTEGER) == F.MODE_REAL else oracle.MODE_INTEGER
+    xs, ys, points = [], [], []
+    for target, budget in zip(targets, seconds):
+        orun = oracle.Run(osys, ref=ref, tau=pd["tau"], target=target, n_a=pd.get("initiator_na", -1.0),
+                          mode=mode, c_min=pd.get("c_min", 1.0), zeta=pd.get("shift_damping", 0.05),
+                          gen=gen, seed=pd["seed"])
+        orun.set_walkers([ref[0]], [ref[1]], [pd.get("n_initial", 10.0)])
+        t0 = time.perf_counter()
+        att = steps = 0
+        st = None
+        while steps == 0 or time.perf_counter() - t0 < budget:
+            c0 = time.perf_counter()
+            st = orun.step(1)[0]
+            xs.append(st["attempts"])
+            ys.append(time.perf_counter() - c0)
+            att += st["attempts"]
+            steps += 1
+        wall = time.perf_counter() - t0
+        points.append({"target": target, "steps": steps, "attempts": int(att), "seconds": wall,
+                       "attempts_per_s": att / wall, "walkers_last": st["nw"], "dets_last": st["ndets"]})
+        log(f"[oracle] target {target:.0e}: {steps} steps, {att / wall:.4e} attempts/s, "
+            f"N_w {st['nw']:.4g}, {st['ndets']} dets")
+    c1, c0 = np.polyfit(np.asarray(xs, dtype=float), np.asarray(ys), 1)
+    t_full = c0 + c1 * attempts_per_step
+    value = attempts_per_step / t_full
+    sample = ("oracle grown from the reference at walker targets "
+              + " and ".join(f"{p['target']:.0e}" for p in points)
+              + f" ({sum(p['steps'] for p in points)} steps, {sum(p['seconds'] for p in points):.1f} s "
+              f"on one host core); time per step fitted linearly in attempts per step and "
+              f"extrapolated to the GPU run's {attempts_per_step:.4g} attempts per step")
+    return {"value": value, "unit": "attempts/s", "cores": 1, "kind": "oracle", "extrapolated": True,
+            "sample": sample, "points": points, "fit_seconds_per_step": [c0, c1]}
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -646,15 +716,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     # 5000 timed steps as the 4x4 Hubbard configuration states; the warm-up
     # (~1.4 s) also brings the GPU to its clocks
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=20000)
-    ap.add_argument("--workload", default="hubbard4x4")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    # timed steps of the headline (40-orbital) workload; about 10 ms each
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="mol40")
+    ap.add_argument("--cpu-seconds", type=float, nargs=2, default=(5.0, 15.0),
+                    help="oracle seconds at the two reduced walker targets")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--second", default="mol40",
+    ap.add_argument("--second", default="hubbard4x4",
                     help="second workload measured after the first ('' to skip)")
-    ap.add_argument("--second-steps", type=int, default=60)
-    ap.add_argument("--second-warmup", type=int, default=400)
+    # 5000 timed steps as the 4x4 Hubbard configuration states; the warm-up
+    # (~1.4 s) lets the shift settle the population at its target
+    ap.add_argument("--second-steps", type=int, default=5000)
+    ap.add_argument("--second-warmup", type=int, default=18000)
     ap.add_argument("--batched-steps", type=int, default=1000,
                     help="timed steps of the 64-molecule batch (0 to skip)")
     ap.add_argument("--batched-warmup", type=int, default=200)
@@ -723,47 +797,31 @@ def main():
         F, np, torch, stream, args.workload, args.steps, args.warmup)
     attempts = int(st["attempts"].sum())
     value = attempts / wall
-    words = 1 if s.n_orb <= 32 else 2
+    roof_ann = roofline(kern, "annihilate", args.workload)
+    F.fciqmc_free_run(run)
+    F.fciqmc_free_system(sysd)
+    run = sysd = None
 
     cpu = None
     if not args.no_cpu:
-        import oracle
-        a, b, v = F.fciqmc_get_walkers(run)
-        ck = F.fciqmc_get_checkpoint(run)
-        osys = oracle.System.from_inputs(s, words=words)
-        orun = oracle.Run(osys, ref=(pd.get("ref_alpha", 0), pd.get("ref_beta", 0)),
-                          tau=pd["tau"], target=pd["walker_target"],
-                          n_a=pd.get("initiator_na", -1.0), zeta=pd.get("shift_damping", 0.05),
-                          gen={F.GEN_UNIFORM: oracle.GEN_UNIFORM, F.GEN_LATTICE: oracle.GEN_LATTICE,
-                               F.GEN_PCHB: oracle.GEN_PCHB}[pd.get("excitgen", F.GEN_UNIFORM)],
-                          seed=pd["seed"])
-        orun.set_walkers(a, b, v)
-        orun.set_state(ck["iter"], ck["shift"], ck["vary_shift"], ck["last_update_iter"],
-                       ck["last_update_nw"])
-        c0 = time.perf_counter()
-        oatt = 0
-        osteps = 0
-        while osteps == 0 or time.perf_counter() - c0 < args.cpu_seconds:
-            oatt += orun.step(1)[0]["attempts"]
-            osteps += 1
-        cwall = time.perf_counter() - c0
-        cpu = {"value": oatt / cwall, "unit": "attempts/s", "cores": 1, "kind": "oracle",
-               "sample": f"{osteps} oracle steps from the GPU's state after the timed region "
-                         f"({len(v)} determinants), {cwall:.1f}s on one host core"}
-        log(f"cpu oracle: {osteps} steps, {oatt / cwall:.4e} attempts/s")
+        # reduced walker targets of the same workload (a 1e8-walker oracle run
+        # would take days on one core), extrapolated linearly in walkers
+        targets = (1e5, 1e6) if s.n_orb > 32 else (1e4, 1e5)
+        cpu = oracle_baseline(s, pd, targets, args.cpu_seconds, attempts / len(st), F_ref(pd, s))
+        log(f"cpu oracle (extrapolated): {cpu['value']:.4e} attempts/s")
 
     second = None
     if args.second:
-        F.fciqmc_free_run(run)
-        F.fciqmc_free_system(sysd)
-        run = sysd = None
-        _, _, desc2, run2, sys2, _, wall2, _, _, _, kern2, _ = measure(
+        s2, pd2, desc2, run2, sys2, st2, wall2, _, _, _, kern2, roof2 = measure(
             F, np, torch, stream, args.second, args.second_steps, args.second_warmup)
         second = {"config": desc2, "value": desc2["attempts_per_s"], "unit": "attempts/s",
-                  "ms_per_step": desc2["ms_per_step"], "kernels": kern2,
+                  "ms_per_step": desc2["ms_per_step"], "kernels": kern2, "roofline": roof2,
                   "roofline_annihilate": roofline(kern2, "annihilate", args.second)}
         F.fciqmc_free_run(run2)
         F.fciqmc_free_system(sys2)
+        if not args.no_cpu:
+            second["cpu_baseline"] = oracle_baseline(
+                s2, pd2, (1e4, 1e5), (3.0, 8.0), int(st2["attempts"].sum()) / len(st2), F_ref(pd2, s2))
 
     generators = None
     if args.generators:
@@ -792,7 +850,7 @@ def main():
                                 int(args.served_budget))
 
     out = {
-        "metric": "spawn attempts/s (spawn+annihilate+death)",
+        "metric": METRIC,
         "value": value,
         "unit": "attempts/s",
         "n_gpus": 1,
@@ -807,6 +865,7 @@ def main():
         "config": desc,
         "kernels": kern,
         "roofline": roof,
+        "roofline_annihilate": roof_ann,
         "cpu_baseline": cpu,
         "second_workload": second,
         "generators": generators,
@@ -817,9 +876,6 @@ def main():
         "served": served,
     }
     print(json.dumps(out), flush=True)
-    if run is not None:
-        F.fciqmc_free_run(run)
-        F.fciqmc_free_system(sysd)
 
 
 if __name__ == "__main__":
