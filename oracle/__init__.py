@@ -91,6 +91,15 @@ def lib():
         L.orc_run_get_rejected.argtypes = [vp, pu64, pu64, pdbl]
         L.orc_run_adaptive_f.restype = dbl
         L.orc_run_adaptive_f.argtypes = [vp, u64, u64]
+        L.orc_rdm_dim.restype = i64
+        L.orc_rdm_dim.argtypes = [vp]
+        L.orc_rdm_exact.argtypes = [vp, pu64, pu64, pdbl, pdbl, i64, pdbl]
+        L.orc_rdm_energy.restype = dbl
+        L.orc_rdm_energy.argtypes = [vp, pdbl, pdbl]
+        L.orc_run_log_excitations.argtypes = [vp, C.c_int]
+        L.orc_run_excitations.restype = i64
+        L.orc_run_excitations.argtypes = [vp]
+        L.orc_pair_rdm_step.argtypes = [vp, vp, pdbl]
         _lib = L
     return _lib
 
@@ -169,6 +178,30 @@ class System:
         lib().orc_pchb_row(self.ptr, int(opp), int(row), _p(w, C.c_double), _p(pr, C.c_double),
                            _p(al, C.c_int), C.byref(s))
         return w, pr, al, s.value
+
+    def rdm_dim(self):
+        """M = C(2N, 2): the 2-RDM is an M x M matrix over spin-orbital pairs k < l."""
+        return int(lib().orc_rdm_dim(self.ptr))
+
+    def rdm_exact(self, a, b, ca, cb):
+        """Eq. (FCI2RDM) over one determinant list (ascending) with coefficient
+        vectors ca (bra) and cb (ket): an M x M array."""
+        a = np.ascontiguousarray(a, dtype=np.uint64)
+        b = np.ascontiguousarray(b, dtype=np.uint64)
+        ca = np.ascontiguousarray(ca, dtype=np.float64)
+        cb = np.ascontiguousarray(cb, dtype=np.float64)
+        M = self.rdm_dim()
+        G = np.zeros(M * M)
+        lib().orc_rdm_exact(self.ptr, _p(a, C.c_uint64), _p(b, C.c_uint64), _p(ca, C.c_double),
+                            _p(cb, C.c_double), len(a), _p(G, C.c_double))
+        return G.reshape(M, M)
+
+    def rdm_energy(self, G):
+        """(energy, norm) of a 2-RDM: <A|H|B>/<A|B> + E_core and <A|B>."""
+        G = np.ascontiguousarray(G, dtype=np.float64)
+        norm = C.c_double()
+        e = lib().orc_rdm_energy(self.ptr, _p(G, C.c_double), C.byref(norm))
+        return e, norm.value
 
     def uniform_count2(self, a, b, single, idx1):
         return int(lib().orc_uniform_count2_flat(self.ptr, int(a), int(b), int(single), int(idx1)))
@@ -312,6 +345,14 @@ class Run:
         lib().orc_run_get_rejected(self.ptr, _p(a, C.c_uint64), _p(b, C.c_uint64), _p(w, C.c_double))
         return a, b, w
 
+    def log_excitations(self, on=True):
+        """Keep the population each step starts from and every excitation it
+        generates (for the replica 2-RDM)."""
+        lib().orc_run_log_excitations(self.ptr, int(bool(on)))
+
+    def excitations(self):
+        return int(lib().orc_run_excitations(self.ptr))
+
     def generate(self, a, b, t, k):
         ta, tb, pg, H = C.c_uint64(), C.c_uint64(), C.c_double(), C.c_double()
         ok = lib().orc_generate(self.ptr, int(a), int(b), int(t), int(k), C.byref(ta),
@@ -329,3 +370,11 @@ def pair_pt2(r1: Run, r2: Run) -> float:
 def pair_overlap(r1: Run, r2: Run) -> float:
     """sum_i C_i^1 C_i^2 of the two replicas' current populations."""
     return lib().orc_pair_overlap(r1.ptr, r2.ptr)
+
+
+def pair_rdm_step(r1: Run, r2: Run, G):
+    """Add one paired step's sample of the replica 2-RDM to G (M x M, in
+    place); both runs must log their excitations."""
+    assert G.flags["C_CONTIGUOUS"] and G.dtype == np.float64
+    lib().orc_pair_rdm_step(r1.ptr, r2.ptr, _p(G, C.c_double))
+    return G

@@ -585,6 +585,15 @@ typedef struct {
     det_t *f_det;
     double *f_val;
     int64_t nf;
+    /* 2-RDM sampling (Sec. "Reduced density matrices"): the population the
+     * last step started from, and every non-null excitation it generated
+     * with the weight C_i / (m_i p_gen) */
+    int log_exc;
+    ent_t *prev;
+    int64_t nprev;
+    det_t *exc_par, *exc_chi;
+    double *exc_w;
+    int64_t nexc, cexc;
 } orc_run;
 
 static int ent_cmp(const void *x, const void *y)
@@ -684,6 +693,7 @@ void orc_run_free(orc_run *r)
     if (!r) return;
     core_clear(r);
     free(r->rej); free(r->rej_w);
+    free(r->prev); free(r->exc_par); free(r->exc_chi); free(r->exc_w);
     free(r->f_det); free(r->f_val);
     free(r->list);
     free(r->nw_ring);
@@ -870,6 +880,191 @@ double orc_pair_overlap(const orc_run *r1, const orc_run *r2)
     return acc;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Two-body reduced density matrix (Sec. "Reduced density matrices", Eq.      */
+/* (FCI2RDM)):                                                                 */
+/*   Gamma_{kl,mn} = sum_{i,j} C_i^A C_j^B <D_i| a+_k a+_l a_n a_m |D_j>      */
+/* over spin orbitals in canonical order.  It is antisymmetric in (k,l) and  */
+/* in (m,n), so only k < l, m < n are kept: pair index                        */
+/* P(k,l) = k(2K-k-1)/2 + l-k-1 over the M = K(K-1)/2 pairs of the K = 2N     */
+/* spin orbitals, stored row-major as G[P(k,l) M + P(m,n)].                   */
+/* ------------------------------------------------------------------------- */
+int64_t orc_rdm_dim(const orc_sys *s)
+{
+    int64_t K = 2 * (int64_t)s->N;
+    return K * (K - 1) / 2;
+}
+
+static int64_t rdm_pair(int64_t K, int k, int l)
+{
+    return (int64_t)k * (2 * K - k - 1) / 2 + (l - k - 1);
+}
+
+/* <D_i| a+_k a+_l a_n a_m |D_j>: the operators applied to D_j right to left
+ * (a_m first); 0 unless the result is D_i, else the fermion sign. */
+static int rdm_element(const orc_sys *s, det_t di, det_t dj, int k, int l, int m, int n)
+{
+    det_t t = dj;
+    if (!det_occ(s, t, m)) return 0;
+    int par = op_annihilate(s, &t, m);
+    if (!det_occ(s, t, n)) return 0;
+    par ^= op_annihilate(s, &t, n);
+    if (det_occ(s, t, l)) return 0;
+    par ^= op_create(s, &t, l);
+    if (det_occ(s, t, k)) return 0;
+    par ^= op_create(s, &t, k);
+    if (!det_eq(t, di)) return 0;
+    return par ? -1 : 1;
+}
+
+/* G += coef <D_i| a+_k a+_l a_n a_m |D_j> for every k<l, m<n (ascending m,
+ * n, then k, l), each addition one rounding. */
+static void rdm_add(const orc_sys *s, det_t di, det_t dj, double coef, double *G)
+{
+    int K = 2 * s->N;
+    int64_t M = (int64_t)K * (K - 1) / 2;
+    for (int m = 0; m < K; ++m)
+        for (int n = m + 1; n < K; ++n) {
+            if (!det_occ(s, dj, m) || !det_occ(s, dj, n)) continue;
+            for (int k = 0; k < K; ++k)
+                for (int l = k + 1; l < K; ++l) {
+                    int sg = rdm_element(s, di, dj, k, l, m, n);
+                    if (sg == 0) continue;
+                    double x = sg > 0 ? coef : -coef;
+                    int64_t at = rdm_pair(K, k, l) * M + rdm_pair(K, m, n);
+                    G[at] = G[at] + x;
+                }
+        }
+}
+
+/* The definition over a state pair on one determinant list: D_i, D_j run
+ * over the list (a, b masks; ascending), C^A = ca, C^B = cb.  G (M x M) is
+ * added to. */
+void orc_rdm_exact(const orc_sys *s, const uint64_t *a, const uint64_t *b, const double *ca,
+                   const double *cb, int64_t n, double *G)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        if (cb[j] == 0.0) continue;
+        det_t dj = {a[j], b[j]};
+        for (int64_t i = 0; i < n; ++i) {
+            if (ca[i] == 0.0) continue;
+            det_t di = {a[i], b[i]};
+            int x = __builtin_popcountll(di.a ^ dj.a) + __builtin_popcountll(di.b ^ dj.b);
+            if (x > 4) continue;  /* no two-body operator connects them */
+            double c = ca[i] * cb[j];
+            rdm_add(s, di, dj, c, G);
+        }
+    }
+}
+
+/* Energy of a 2-RDM, <A|H|B>/<A|B> + E_core, from the textbook contraction
+ *   E = sum_pq h_pq gamma_pq + sum_{k<l, m<n} Gamma_{kl,mn} <kl||mn>,
+ * <kl||mn> = <kl|mn> - <kl|nm>, <kl|mn> = (km|ln) d(s_k,s_m) d(s_l,s_n), and
+ * the one-body matrix gamma_pq = sum_r Gamma_{pr,qr} / (n-1) (n electrons).
+ * The norm <A|B> is the trace sum_{k<l} Gamma_{kl,kl} / (n(n-1)/2), returned
+ * in *norm.  Sums in ascending index order. */
+double orc_rdm_energy(const orc_sys *s, const double *G, double *norm)
+{
+    int K = 2 * s->N, N = s->N;
+    int ne = s->na + s->nb;
+    int64_t M = (int64_t)K * (K - 1) / 2;
+    double tr = 0.0;
+    for (int64_t P = 0; P < M; ++P) tr = tr + G[P * M + P];
+    double npair = (double)ne * (double)(ne - 1) / 2.0;
+    *norm = tr / npair;
+    /* one-body part */
+    double e1 = 0.0;
+    for (int p = 0; p < K; ++p)
+        for (int q = 0; q < K; ++q) {
+            if (so_spin(s, p) != so_spin(s, q)) continue;
+            double g = 0.0;
+            for (int r = 0; r < K; ++r) {
+                if (r == p || r == q) continue;
+                /* Gamma_{pr,qr} from the stored k<l, m<n entry */
+                int sg = 1;
+                int k = p, l = r, m = q, n = r;
+                if (k > l) { int t = k; k = l; l = t; sg = -sg; }
+                if (m > n) { int t = m; m = n; n = t; sg = -sg; }
+                double v = G[rdm_pair(K, k, l) * M + rdm_pair(K, m, n)];
+                g = g + (sg > 0 ? v : -v);
+            }
+            double gam = g / (double)(ne - 1);
+            double x = s->h[so_orb(s, p) * N + so_orb(s, q)] * gam;
+            e1 = e1 + x;
+        }
+    /* two-body part */
+    double e2 = 0.0;
+    for (int k = 0; k < K; ++k)
+        for (int l = k + 1; l < K; ++l)
+            for (int m = 0; m < K; ++m)
+                for (int n = m + 1; n < K; ++n) {
+                    double v = G[rdm_pair(K, k, l) * M + rdm_pair(K, m, n)];
+                    if (v == 0.0) continue;
+                    double d = (so_spin(s, k) == so_spin(s, m) && so_spin(s, l) == so_spin(s, n))
+                                   ? eri(s, so_orb(s, k), so_orb(s, m), so_orb(s, l), so_orb(s, n)) : 0.0;
+                    double x = (so_spin(s, k) == so_spin(s, n) && so_spin(s, l) == so_spin(s, m))
+                                   ? eri(s, so_orb(s, k), so_orb(s, n), so_orb(s, l), so_orb(s, m)) : 0.0;
+                    double a = d - x;
+                    double c = v * a;
+                    e2 = e2 + c;
+                }
+    double e = e1 + e2;
+    double q = e / *norm;
+    return q + s->e_core;
+}
+
+void orc_run_log_excitations(orc_run *r, int on) { r->log_exc = on; }
+int64_t orc_run_excitations(const orc_run *r) { return r->nexc; }
+
+static double prev_value(const orc_run *r, det_t d)
+{
+    int64_t at = find(r->prev, r->nprev, d);
+    return at >= 0 ? r->prev[at].v : 0.0;
+}
+
+/* One paired step's sample of the replica 2-RDM (Sec. "Reduced density
+ * matrices": the replica trick makes the estimate bilinear in two
+ * independent populations), added to G:
+ *  - the diagonal terms i = j exactly: C_i^1 C_i^2 over the determinants
+ *    occupied in both populations the step started from;
+ *  - the off-diagonal terms from the excitations the step generated: an
+ *    excitation D_i -> D_j drawn by replica r from the population at tau
+ *    (m_i attempts on D_i, each producing D_j with probability p_gen) adds
+ *    C_i^r C_j^r' / (m_i p_gen) times the operator elements
+ *    <D_i|a+_k a+_l a_n a_m|D_j> (r' the other replica; C_j^r' its
+ *    coefficient at tau), whose expectation is the sum over all j of
+ *    C_i^r C_j^r' <D_i|...|D_j>.  Each replica's parents estimate one
+ *    ordering of the replica product; both are added with weight 1/2.
+ *    Readings: every non-null draw counts, accepted or not, and the
+ *    unnormalised, not yet hermitian sum is returned (the paper makes the
+ *    accumulated matrix hermitian and fixes its trace at the end).
+ * Order: diagonal by ascending determinant, then replica 1's excitations in
+ * generation order, then replica 2's. */
+void orc_pair_rdm_step(const orc_run *r1, const orc_run *r2, double *G)
+{
+    const orc_sys *s = r1->s;
+    int64_t x = 0, y = 0;
+    while (x < r1->nprev && y < r2->nprev) {
+        int c = det_cmp(r1->prev[x].d, r2->prev[y].d);
+        if (c < 0) { ++x; continue; }
+        if (c > 0) { ++y; continue; }
+        double q = r1->prev[x].v * r2->prev[y].v;
+        if (q != 0.0) rdm_add(s, r1->prev[x].d, r1->prev[x].d, q, G);
+        ++x; ++y;
+    }
+    const orc_run *rr[2] = {r1, r2};
+    for (int side = 0; side < 2; ++side) {
+        const orc_run *r = rr[side], *o = rr[1 - side];
+        for (int64_t e = 0; e < r->nexc; ++e) {
+            double cj = prev_value(o, r->exc_chi[e]);
+            if (cj == 0.0) continue;
+            double w1 = r->exc_w[e] * cj;
+            double w2 = w1 * 0.5;
+            rdm_add(s, r->exc_par[e], r->exc_chi[e], w2, G);
+        }
+    }
+}
+
 int64_t orc_run_rejected_size(const orc_run *r) { return r->nrej; }
 
 /* f of determinant (a, b) in the last adaptive-shift step (1 for an
@@ -914,6 +1109,14 @@ int orc_run_step(orc_run *r, orc_stats *st)
     int integer = p->mode == MODE_INTEGER;
     memset(st, 0, sizeof(*st));
 
+    if (r->log_exc) {
+        free(r->prev);
+        r->prev = (ent_t *)malloc(sizeof(ent_t) * (r->n > 0 ? r->n : 1));
+        memcpy(r->prev, r->list, sizeof(ent_t) * (size_t)r->n);
+        r->nprev = r->n;
+        r->nexc = 0;
+    }
+
     /* (a) spawning.  Every walker of every occupied determinant makes one
      * attempt (integer mode: |C_i| attempts; real mode: ceil(|C_i|)).
      * Attempt k of determinant D_i draws Philox block (D_i, t, k, SPAWN). */
@@ -947,6 +1150,21 @@ int orc_run_step(orc_run *r, orc_stats *st)
                     ok = orc_cs_gen(s, e->d, rr, r2, p->p_single, p->p_opp, p->gen == GEN_PE, &tgt, &pgen);
             }
             if (!ok) continue;
+            if (r->log_exc) {
+                /* every generated excitation, accepted or not, with the
+                 * inverse of its expected number of draws in this step */
+                if (r->nexc == r->cexc) {
+                    r->cexc = r->cexc ? 2 * r->cexc : 1024;
+                    r->exc_par = (det_t *)realloc(r->exc_par, sizeof(det_t) * r->cexc);
+                    r->exc_chi = (det_t *)realloc(r->exc_chi, sizeof(det_t) * r->cexc);
+                    r->exc_w = (double *)realloc(r->exc_w, sizeof(double) * r->cexc);
+                }
+                double d1 = pgen * (double)m;
+                r->exc_par[r->nexc] = e->d;
+                r->exc_chi[r->nexc] = tgt;
+                r->exc_w[r->nexc] = C / d1;
+                r->nexc++;
+            }
             if (pcore && core_find(r, tgt) >= 0) continue;  /* in P^D */
             double H = orc_hij_det(s, e->d, tgt);
             if (H == 0.0) continue;

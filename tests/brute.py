@@ -137,3 +137,39 @@ def blocked_error(series):
         if all(abs(e - err) <= 2.0 * (derr + de) for _, e, de in rest[:3]):
             return mean, err
     return mean, max(e for _, e, _ in levels[: max(1, len(levels) - 3)])
+
+
+def rdm2(n_orb, dets, ca, cb):
+    """Gamma_{kl,mn} = sum_{i,j} ca_i cb_j <D_i| a+_k a+_l a_n a_m |D_j> for
+    spin orbitals k < l, m < n (alpha 0..N-1, then beta), by applying the
+    four operators to every ket, right to left.  Rows and columns run over
+    the pairs in lexicographic order."""
+    n2 = 2 * n_orb
+    pairs = [(k, l) for k in range(n2) for l in range(k + 1, n2)]
+    pidx = {p: i for i, p in enumerate(pairs)}
+    index = {d: i for i, d in enumerate(dets)}
+    M = len(pairs)
+    G = np.zeros((M, M))
+    for j, (am, bm) in enumerate(dets):
+        if cb[j] == 0.0:
+            continue
+        x = _to_so(am, bm, n_orb)
+        for (m, n) in pairs:
+            y1, s1 = _annihilate(x, m)
+            if y1 is None:
+                continue
+            y2, s2 = _annihilate(y1, n)
+            if y2 is None:
+                continue
+            for (k, l) in pairs:
+                y3, s3 = _create(y2, l)
+                if y3 is None:
+                    continue
+                y4, s4 = _create(y3, k)
+                if y4 is None:
+                    continue
+                i = index.get(_from_so(y4, n_orb))
+                if i is None or ca[i] == 0.0:
+                    continue
+                G[pidx[(k, l)], pidx[(m, n)]] += s1 * s2 * s3 * s4 * ca[i] * cb[j]
+    return G

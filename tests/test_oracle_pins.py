@@ -838,3 +838,145 @@ def test_long_run_matches_exact_diagonalisation(oracle_mod):
     # the population is held at the target
     nw = np.array([x["nw"] for x in keep])
     assert 0.5 * 3000 < nw.mean() < 2.0 * 3000
+
+
+# --- replica 2-RDM (Sec. "Reduced density matrices", Eq. (FCI2RDM)) -------------------
+
+def _sorted_basis(n_orb, na, nb):
+    dets = sorted(brute.basis(n_orb, na, nb))
+    a = np.array([d[0] for d in dets], dtype=np.uint64)
+    b = np.array([d[1] for d in dets], dtype=np.uint64)
+    return dets, a, b
+
+
+def test_rdm_definition_matches_operators(oracle_mod):
+    """The oracle's 2-RDM of two random states equals the operator string
+    a+_k a+_l a_n a_m applied bit by bit to every ket (tests/brute.py)."""
+    s = inputs.synthetic_molecule(4, 2, 1, seed=5, rank=4)
+    osys = oracle_mod.System.from_inputs(s)
+    dets, a, b = _sorted_basis(4, 2, 1)
+    rng = np.random.default_rng(2)
+    ca = rng.normal(size=len(dets))
+    cb = rng.normal(size=len(dets))
+    ca[rng.choice(len(dets), 5, replace=False)] = 0.0
+    G = osys.rdm_exact(a, b, ca, cb)
+    Gb = brute.rdm2(4, dets, ca, cb)
+    assert np.max(np.abs(G - Gb)) <= 1e-13 * max(1.0, np.max(np.abs(Gb)))
+    assert np.count_nonzero(np.abs(Gb) > 1e-12) > 100
+
+
+@pytest.mark.parametrize("system", ["mol", "ring"])
+def test_rdm_of_eigenvector(oracle_mod, system):
+    """The 2-RDM of a normalised exact eigenvector: its energy contraction
+    gives E0 to 1e-10, its trace is n(n-1)/2, it is symmetric, and its
+    one-body contraction has trace n and eigenvalues in [0, 1]."""
+    if system == "mol":
+        s = inputs.synthetic_molecule(6, 3, 2, seed=3, rank=6)
+    else:
+        s = inputs.hubbard_chain(6, 1.0, 4.0, 3, 3)
+    N, na, nb = s.n_orb, s.n_alpha, s.n_beta
+    n = na + nb
+    osys = oracle_mod.System.from_inputs(s)
+    dets, a, b = _sorted_basis(N, na, nb)
+    H = brute.hamiltonian(N, na, nb, s.h1, inputs.unpack_eri(s.eri, N))[1]
+    order = {d: i for i, d in enumerate(brute.basis(N, na, nb))}
+    perm = [order[d] for d in dets]
+    H = H[np.ix_(perm, perm)]
+    w, V = np.linalg.eigh(H)
+    v = V[:, 0]
+    G = osys.rdm_exact(a, b, v, v)
+    e, norm = osys.rdm_energy(G)
+    assert abs(e - (w[0] + s.e_core)) < 1e-10
+    assert abs(norm - 1.0) < 1e-12
+    assert abs(np.trace(G) - n * (n - 1) / 2) < 1e-10
+    assert np.max(np.abs(G - G.T)) < 1e-13
+    # one-body matrix gamma_pq = sum_r Gamma_{pr,qr} / (n-1), by explicit signs
+    K = 2 * N
+    pairs = {(k, l): i for i, (k, l) in enumerate((k, l) for k in range(K) for l in range(k + 1, K))}
+
+    def gam(p, r, q, t):
+        sg = 1
+        if p > r:
+            p, r, sg = r, p, -sg
+        if q > t:
+            q, t, sg = t, q, -sg
+        return sg * G[pairs[(p, r)], pairs[(q, t)]]
+    g1 = np.array([[sum(gam(p, r, q, r) for r in range(K) if r not in (p, q)) / (n - 1)
+                    for q in range(K)] for p in range(K)])
+    assert abs(np.trace(g1) - n) < 1e-10
+    ev = np.linalg.eigvalsh(g1)
+    assert ev.min() > -1e-10 and ev.max() < 1 + 1e-10
+
+
+def test_rdm_energy_is_the_expectation_value(oracle_mod):
+    """For two arbitrary states A, B the energy contraction of their
+    transition 2-RDM equals <A|H|B>/<A|B> + E_core with H built operator by
+    operator (not the oracle's Slater-Condon rules)."""
+    s = inputs.synthetic_molecule(5, 2, 2, seed=8, rank=6)
+    osys = oracle_mod.System.from_inputs(s)
+    dets, a, b = _sorted_basis(5, 2, 2)
+    H = brute.hamiltonian(5, 2, 2, s.h1, inputs.unpack_eri(s.eri, 5))[1]
+    order = {d: i for i, d in enumerate(brute.basis(5, 2, 2))}
+    perm = [order[d] for d in dets]
+    H = H[np.ix_(perm, perm)]
+    rng = np.random.default_rng(4)
+    ca = rng.normal(size=len(dets)) + 2.0
+    cb = rng.normal(size=len(dets)) + 2.0
+    G = osys.rdm_exact(a, b, ca, cb)
+    e, norm = osys.rdm_energy(G)
+    assert abs(norm - ca @ cb) < 1e-11 * abs(ca @ cb)
+    want = (ca @ H @ cb) / (ca @ cb) + s.e_core
+    assert abs(e - want) < 1e-10 * max(1.0, abs(want))
+
+
+@pytest.mark.parametrize("gen,mode", [("uniform", "integer"), ("pchb", "real")])
+def test_rdm_step_expectation(oracle_mod, gen, mode):
+    """Averaged over independent streams, one paired step's sampled 2-RDM
+    equals the symmetrised replica RDM 1/2 (Gamma(C1, C2) + Gamma(C2, C1))
+    of the two fixed populations the step starts from (z < 5 per entry); a
+    sampler without the 1/2 or without the 1/(m p_gen) weight is rejected."""
+    s = inputs.synthetic_molecule(5, 2, 2, seed=21, rank=8)
+    osys = oracle_mod.System.from_inputs(s)
+    dets, a_all, b_all = _sorted_basis(5, 2, 2)
+    rng = np.random.default_rng(7)
+    pick = np.sort(rng.choice(len(dets), size=14, replace=False))
+    C1 = np.zeros(len(dets))
+    C2 = np.zeros(len(dets))
+    C1[pick] = rng.integers(1, 6, size=14) * rng.choice([-1, 1], size=14)
+    C2[pick] = rng.integers(1, 6, size=14) * rng.choice([-1, 1], size=14)
+    C2[pick[:3]] = 0.0
+    if mode == "real":
+        C1 = C1 * 0.8
+        C2 = C2 * 0.9
+    want = 0.5 * (osys.rdm_exact(a_all, b_all, C1, C2) + osys.rdm_exact(a_all, b_all, C2, C1))
+    gcode = _gen_code(oracle_mod, gen)
+    m = oracle_mod.MODE_INTEGER if mode == "integer" else oracle_mod.MODE_REAL
+    M = osys.rdm_dim()
+    nrep = 3000
+    acc = np.zeros((M, M))
+    acc2 = np.zeros((M, M))
+    ref = dets[int(pick[0])]
+    for rep in range(nrep):
+        runs = []
+        for r, C in ((0, C1), (1, C2)):
+            run = oracle_mod.Run(osys, ref=ref, tau=0.05, target=1e12, mode=m, gen=gcode,
+                                 seed=5000 + rep, replica=r)
+            nz = C != 0.0
+            run.set_walkers(a_all[nz], b_all[nz], C[nz])
+            run.log_excitations(True)
+            run.step()
+            runs.append(run)
+        G = np.zeros((M, M))
+        oracle_mod.pair_rdm_step(runs[0], runs[1], G)
+        acc += G
+        acc2 += G * G
+    mean = acc / nrep
+    se = np.sqrt(np.maximum(acc2 / nrep - mean * mean, 0.0) / nrep)
+    hit = (np.abs(want) > 0) | (se > 0)
+    z = np.abs(mean - want)[hit] / np.maximum(se[hit], 1e-9)
+    assert np.max(z) < 5.0, np.max(z)
+    # the diagonal terms are exact, so the estimator is unbiased only with
+    # both factors in the off-diagonal weights
+    off = ~np.isclose(want, 0.0) & (se > 0)
+    z2 = np.abs(2.0 * mean - want)[off] / np.maximum(2.0 * se[off], 1e-9)
+    assert np.max(z2) > 5.0
