@@ -384,6 +384,36 @@ int fciqmc_pair_create(fciqmc_run *r1, fciqmc_run *r2, fciqmc_pair **out);
 int fciqmc_pair_step(fciqmc_pair *pair, int n_steps, fciqmc_step_stats *stats1,
                      fciqmc_step_stats *stats2, double *de2);
 int fciqmc_pair_pt2(const fciqmc_pair *pair, int64_t skip, double *mean, double *err, int64_t *n);
+
+/* ---- Replica 2-RDM and the variational energy (Sec. "Reduced density
+ * matrices", Eq. (FCI2RDM); Sec. "Perturbative correction": the energy the
+ * PT2 correction corrects) ----
+ * Gamma_{kl,mn} = sum_{i,j} C_i^1 C_j^2 <D_i| a+_k a+_l a_n a_m |D_j> over
+ * spin orbitals (canonical index: alpha orbital p -> p, beta p -> N + p),
+ * kept for k < l, m < n: pair index P(k,l) = k(2K-k-1)/2 + l-k-1 of the
+ * M = K(K-1)/2 pairs (K = 2N), matrix element [P(k,l) M + P(m,n)].
+ * fciqmc_pair_rdm_enable(pair, 1) clears the accumulator and samples every
+ * later paired step: the diagonal terms C_i^1 C_i^2 exactly over the
+ * determinants occupied in both populations a step starts from, and each
+ * excitation D_i -> D_j a replica draws in that step (accepted or not)
+ * with weight C_i / (m_i p_gen) times the other replica's C_j, halved
+ * between the replicas (an unbiased estimate of the replica product; the
+ * replica trick removes the bias of a squared amplitude).  Readings: every
+ * non-null draw counts; the sum is made hermitian and normalised only when
+ * reported.  Excitations the generator can never draw (zero weight) are
+ * absent; their Hamiltonian elements vanish.  enable(pair, 0) stops
+ * sampling and keeps the sum.  While sampling, a replica's next spawn is
+ * not queued ahead of its step.
+ * fciqmc_pair_rdm: the accumulated matrix made hermitian, (G + G^T)/2
+ * (gamma: host, capacity >= M*M entries, or NULL), *dim = M, the
+ * variational energy
+ *   E_var = [sum_pq h_pq gamma_pq + sum_{k<l,m<n} Gamma_{kl,mn} <kl||mn>] / norm + E_core,
+ *   gamma_pq = sum_r Gamma_{pr,qr} / (n-1),  norm = trace / (n(n-1)/2),
+ * the norm (the summed replica overlap) and the steps sampled (any output
+ * may be NULL).  ESTATE if sampling was never enabled. */
+int fciqmc_pair_rdm_enable(fciqmc_pair *pair, int on);
+int fciqmc_pair_rdm(const fciqmc_pair *pair, double *gamma, int64_t capacity, int64_t *dim, double *e_var,
+                    double *norm, int64_t *steps);
 void fciqmc_pair_free(fciqmc_pair *pair);
 
 void fciqmc_free_run(fciqmc_run *run);

@@ -928,6 +928,8 @@ static void rdm_add(const orc_sys *s, det_t di, det_t dj, double coef, double *G
             if (!det_occ(s, dj, m) || !det_occ(s, dj, n)) continue;
             for (int k = 0; k < K; ++k)
                 for (int l = k + 1; l < K; ++l) {
+                    /* the created orbitals are occupied in the result */
+                    if (!det_occ(s, di, k) || !det_occ(s, di, l)) continue;
                     int sg = rdm_element(s, di, dj, k, l, m, n);
                     if (sg == 0) continue;
                     double x = sg > 0 ? coef : -coef;

@@ -133,6 +133,7 @@ struct fciqmc_system {
     int *deg = nullptr, *nbr = nullptr, *pair_of = nullptr;
     double *lat_pe = nullptr, *lat_pz = nullptr;
     bool pchb = false;
+    std::vector<double> h1_host, eri_host;  // host copies (variational energy of an RDM)
     HbEntry *hb_opp = nullptr, *hb_same = nullptr;  // packed alias tables
     double *hb_sum_opp = nullptr, *hb_sum_same = nullptr;  // their row sums
     int device = 0;
@@ -241,6 +242,11 @@ struct EngineBase {
     virtual const void* current_store() const = 0;  // Store<V> of the population
     virtual const void* previous_store() const = 0; // Store<V> the last step read (intact until the next merge)
     virtual int bucket_entries() const = 0;         // R
+    // replica 2-RDM: every excitation of the last step (RdmRec<W>, rdm_count
+    // attempt slots)
+    virtual int set_rdm(bool on) = 0;
+    virtual const void* rdm_records() const = 0;
+    virtual int64_t rdm_count() const = 0;
 };
 
 // Largest deterministic space: H^D is built by testing all N_D^2 pairs.
@@ -339,6 +345,11 @@ template <int W, class V> struct Engine : EngineBase {
     bool keep_rej = false;
     Rec<W, V>* rej = nullptr;
     long long cap_rej = 0;
+    // replica 2-RDM sampling: one record per attempt slot of the last spawn
+    bool rdm_on = false;
+    RdmRec<W>* rdm = nullptr;
+    int64_t cap_rdm = 0;
+    int64_t rdm_n = 0;
     int64_t* rej_off = nullptr;
     int32_t* rej_cnt = nullptr;
     hipEvent_t ev[2][kKernels + 1]{};
@@ -567,6 +578,10 @@ template <int W, class V> struct Engine : EngineBase {
             sc.rec_h = rec_h;
             sc.ada_acc = ada_acc;
             sc.ada_all = ada_all;
+        }
+        if (rdm_on) {
+            sc.rdm_rec = rdm;
+            sc.rdm_cap = cap_rdm;
         }
         return sc;
     }
@@ -840,6 +855,30 @@ template <int W, class V> struct Engine : EngineBase {
         CHECK(dalloc(arena, &rej, (size_t)cap_rej));
         return alloc_rej_index();
     }
+    int set_rdm(bool on) override {
+        CHECK(discard_pending());  // a queued spawn would not log its draws
+        rdm_on = on;
+        rdm_n = 0;
+        if (!on) {
+            arena.release(rdm);
+            rdm = nullptr;
+            cap_rdm = 0;
+        }
+        return 0;
+    }
+    // Room for one RDM record per attempt slot of the next spawn launch.
+    int ensure_rdm() {
+        if (!rdm_on) return 0;
+        const int64_t need = std::max<int64_t>(chunk_next, 1) * kChunk;
+        if (need > cap_rdm) {
+            const int64_t c = need + need / 4;
+            CHECK(regrow(rdm, (size_t)c));
+            cap_rdm = c;
+        }
+        return 0;
+    }
+    const void* rdm_records() const override { return rdm; }
+    int64_t rdm_count() const override { return rdm_n; }
     void* rej_records() const override { return rej; }
     int64_t* rej_offsets() const override { return rej_off; }
     int32_t* rej_counts() const override { return rej_cnt; }
@@ -886,7 +925,7 @@ template <int W, class V> struct Engine : EngineBase {
     // The step's extensions (deterministic space, discarded-spawn records,
     // adaptive shift) run in their own kernel instantiations, so the plain
     // step keeps the code it had without them.
-    bool ext() const { return ncore > 0 || keep_rej || rs.adaptive; }
+    bool ext() const { return ncore > 0 || keep_rej || rs.adaptive || rdm_on; }
     template <int GEN> void launch_spawn_g(const Store<V>& in, const StepScalars& sc, unsigned blocks) {
         const SysView v = sys->view();
         // the Cauchy-Schwarz generators keep J and SK in LDS
@@ -967,10 +1006,12 @@ template <int W, class V> struct Engine : EngineBase {
     int run_alone(int64_t t, double S, int& retries, bool ahead) {
         for (;;) {
             CHECK(ensure_rej());
+            CHECK(ensure_rdm());
             const StepScalars sc = scalars(t, S, 0);
             const int set = sampled(t) ? (int)(t & 1) : -1;
             if (!pending) {
                 mark(set, 0);
+                rdm_n = rdm_on ? chunk_next * kChunk : 0;
                 CHECK(launch_spawn(st[cur], sc, chunk_next));
                 mark(set, 1);
             }
@@ -1007,7 +1048,9 @@ template <int W, class V> struct Engine : EngineBase {
             CHECK(recover());
             dirty = false;
         }
-        CHECK(run_alone(t, S, retries, true));
+        // with RDM logging the next spawn is not queued ahead: it would
+        // overwrite this step's records before the pair has read them
+        CHECK(run_alone(t, S, retries, !rdm_on));
         return complete(out);
     }
 
@@ -1473,6 +1516,8 @@ int fciqmc_load_integrals(int n_orb, int n_alpha, int n_beta, double e_core, con
     CHECK(dalloc(s->arena, &s->pair_of, (size_t)std::max(np, 1)));
     HIP_OK(hipMemcpy(s->h1, h1, sizeof(double) * N * N, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(s->eri, eri_packed, sizeof(double) * eri_len, hipMemcpyHostToDevice));
+    s->h1_host.assign(h1, h1 + (size_t)N * N);
+    s->eri_host.assign(eri_packed, eri_packed + eri_len);
     // lattice neighbour lists: the distinct q != p with h_pq != 0, ascending
     std::vector<int> deg(N, 0), nbr((size_t)N * N, 0);
     for (int p = 0; p < N; ++p)
@@ -2167,6 +2212,16 @@ struct fciqmc_pair {
     hipEvent_t ev = nullptr;  // the pair kernels queued so far on the first replica's stream are done
     std::vector<double> num;  // per paired step: 1/dtau^2 sum S^1 S^2 / (E_0 - H_jj) (NaN: not evaluated)
     std::vector<double> ovl;  // and the replica overlap of the populations it began from
+    // replica 2-RDM: the accumulated matrix (M x M over spin-orbital pairs)
+    // and each replica's population table of the step being sampled
+    bool rdm = false;
+    double* G = nullptr;
+    int64_t M = 0;
+    int64_t rdm_steps = 0;
+    uint64_t* tkeys[2] = {nullptr, nullptr};
+    double* tvals[2] = {nullptr, nullptr};
+    int32_t* tused[2] = {nullptr, nullptr};
+    int64_t tslots[2] = {0, 0};
     ~fciqmc_pair() {
         if (ev) (void)hipEventDestroy(ev);
         arena.clear();
@@ -2228,6 +2283,117 @@ int pair_sums(fciqmc_pair* p, double e0, double* out) {
     else launch_pair_sums<2, double>(p, B1, B2, e0, out, a->stream);
     HIP_OK(hipGetLastError());
     return 0;
+}
+// One paired step's sample of the replica 2-RDM, queued on the first
+// replica's stream after both have stepped (and before either steps
+// again): tables of both populations the step started from, the exact
+// diagonal terms, and each replica's generated excitations against the
+// other's table.  n_tau: each population's size at tau.
+template <int W, class V> int launch_pair_rdm(fciqmc_pair* p, const int64_t n_tau[2], hipStream_t s) {
+    const EngineBase* e[2] = {p->r[0]->eng.get(), p->r[1]->eng.get()};
+    for (int i = 0; i < 2; ++i) {
+        const int64_t want = (int64_t)next_pow2((uint64_t)std::max<int64_t>(256, 2 * n_tau[i]));
+        if (want > p->tslots[i]) {
+            HIP_OK(hipStreamSynchronize(s));  // queued samples still read the old tables
+            p->arena.release(p->tkeys[i]);
+            p->arena.release(p->tvals[i]);
+            p->arena.release(p->tused[i]);
+            p->tkeys[i] = nullptr;
+            p->tvals[i] = nullptr;
+            p->tused[i] = nullptr;
+            p->tslots[i] = 0;
+            CHECK(dalloc(p->arena, &p->tkeys[i], (size_t)want * W));
+            CHECK(dalloc(p->arena, &p->tvals[i], (size_t)want));
+            CHECK(dalloc(p->arena, &p->tused[i], (size_t)want));
+            p->tslots[i] = want;
+        }
+    }
+    PopTable<W> T[2];
+    for (int i = 0; i < 2; ++i) {
+        T[i].keys = p->tkeys[i];
+        T[i].vals = p->tvals[i];
+        T[i].used = p->tused[i];
+        T[i].mask = (uint64_t)p->tslots[i] - 1;
+        HIP_OK(hipMemsetAsync(p->tused[i], 0, sizeof(int32_t) * p->tslots[i], s));
+        const Store<V> st = *static_cast<const Store<V>*>(e[i]->previous_store());
+        const int B = (int)e[i]->buckets();
+        hipLaunchKernelGGL((k_pop_table<W, V>), dim3((unsigned)std::min(B, 4096)), dim3(kThreads), 0, s, st,
+                           e[i]->bucket_entries(), B, T[i]);
+    }
+    const int N = p->r[0]->sys->N;
+    {
+        const Store<V> s1 = *static_cast<const Store<V>*>(e[0]->previous_store());
+        const int B = (int)e[0]->buckets();
+        hipLaunchKernelGGL((k_rdm_diag<W, V>), dim3((unsigned)std::min(B, 1024)), dim3(kThreads),
+                           sizeof(double) * (size_t)p->M, s, s1, e[0]->bucket_entries(), B, T[1], N, p->G);
+    }
+    for (int i = 0; i < 2; ++i) {
+        const int64_t n = e[i]->rdm_count();
+        if (n == 0) continue;
+        hipLaunchKernelGGL((k_rdm_off<W>), dim3((unsigned)std::min<int64_t>((n + kThreads - 1) / kThreads, 8192)),
+                           dim3(kThreads), 0, s, static_cast<const RdmRec<W>*>(e[i]->rdm_records()), n, T[1 - i], N,
+                           p->G);
+    }
+    HIP_OK(hipGetLastError());
+    p->rdm_steps += 1;
+    return 0;
+}
+int pair_rdm(fciqmc_pair* p, const int64_t n_tau[2]) {
+    const int k = p->r[0]->eng->kind();
+    hipStream_t s = p->r[0]->stream;
+    if (k == 0) return launch_pair_rdm<1, int32_t>(p, n_tau, s);
+    if (k == 1) return launch_pair_rdm<1, double>(p, n_tau, s);
+    if (k == 2) return launch_pair_rdm<2, int32_t>(p, n_tau, s);
+    return launch_pair_rdm<2, double>(p, n_tau, s);
+}
+// Energy of a 2-RDM over spin-orbital pairs (the matrix made hermitian):
+// sum_pq h_pq gamma_pq + sum_{k<l,m<n} Gamma_{kl,mn} <kl||mn>, divided by
+// the norm trace / (n(n-1)/2), plus E_core; gamma_pq = sum_r Gamma_{pr,qr}/(n-1).
+double rdm_energy(const fciqmc_system* sys, const std::vector<double>& G, double& norm) {
+    const int N = sys->N, K = 2 * N, ne = sys->na + sys->nb;
+    const int64_t M = (int64_t)K * (K - 1) / 2;
+    auto P = [K](int k, int l) { return (int64_t)k * (2 * K - k - 1) / 2 + (l - k - 1); };
+    auto eri = [&](int a, int b, int c, int d) {
+        auto tri = [](int x, int y) { return x >= y ? x * (x + 1) / 2 + y : y * (y + 1) / 2 + x; };
+        const int64_t X = tri(a, b), Y = tri(c, d);
+        return sys->eri_host[(size_t)(X >= Y ? X * (X + 1) / 2 + Y : Y * (Y + 1) / 2 + X)];
+    };
+    double tr = 0.0;
+    for (int64_t i = 0; i < M; ++i) tr = tr + G[(size_t)(i * M + i)];
+    const double npair = (double)ne * (double)(ne - 1) / 2.0;
+    norm = tr / npair;
+    double e1 = 0.0;
+    for (int p = 0; p < K; ++p)
+        for (int q = 0; q < K; ++q) {
+            if (p / N != q / N) continue;
+            double g = 0.0;
+            for (int r = 0; r < K; ++r) {
+                if (r == p || r == q) continue;
+                int a = p, b = r, c = q, d = r, sg = 1;
+                if (a > b) { std::swap(a, b); sg = -sg; }
+                if (c > d) { std::swap(c, d); sg = -sg; }
+                const double v = G[(size_t)(P(a, b) * M + P(c, d))];
+                g = g + (sg > 0 ? v : -v);
+            }
+            const double gam = g / (double)(ne - 1);
+            const double x = sys->h1_host[(size_t)((p % N) * N + (q % N))] * gam;
+            e1 = e1 + x;
+        }
+    double e2 = 0.0;
+    for (int k = 0; k < K; ++k)
+        for (int l = k + 1; l < K; ++l)
+            for (int m = 0; m < K; ++m)
+                for (int n = m + 1; n < K; ++n) {
+                    const double v = G[(size_t)(P(k, l) * M + P(m, n))];
+                    if (v == 0.0) continue;
+                    const double d = (k / N == m / N && l / N == n / N) ? eri(k % N, m % N, l % N, n % N) : 0.0;
+                    const double x = (k / N == n / N && l / N == m / N) ? eri(k % N, n % N, l % N, m % N) : 0.0;
+                    const double a = d - x;
+                    const double c = v * a;
+                    e2 = e2 + c;
+                }
+    const double e = e1 + e2;
+    return e / norm + sys->e_core;
 }
 // Waits for a stream when it goes out of scope (also on an error return), so
 // that no queued pair kernel outlives the call that queued it.
@@ -2291,6 +2457,7 @@ int fciqmc_pair_step(fciqmc_pair* p, int n_steps, fciqmc_step_stats* stats1, fci
         HIP_OK(hipMemsetAsync(p->err, 0, sizeof(unsigned), a->stream));
         for (int i = 0; i < n_steps; ++i) {
             const double e0 = (a->S + b->S) / 2.0;  // the shifts this step uses
+            const int64_t n_tau[2] = {a->eng->ndets(), b->eng->ndets()};
             HIP_OK(hipEventRecord(p->ev, a->stream));
             CHECK(fciqmc_step(a, 1, stats1 ? stats1 + i : nullptr));
             // the pair kernels of the last step read the second replica's
@@ -2304,6 +2471,7 @@ int fciqmc_pair_step(fciqmc_pair* p, int n_steps, fciqmc_step_stats* stats1, fci
             CHECK(pair_sums(p, e0, p->res + 2 * i));
             has_ovl[i] = 1;
             has_num[i] = 1;
+            if (p->rdm) CHECK(pair_rdm(p, n_tau));
             done = i + 1;
             const int64_t Ba = a->eng->buckets(), Bb = b->eng->buckets();
             if (Ba != Bb) {
@@ -2340,6 +2508,65 @@ int fciqmc_pair_step(fciqmc_pair* p, int n_steps, fciqmc_step_stats* stats1, fci
     }
     if (rc) return rc;
     if (e) return fail(FCIQMC_EDEVICE, "pair sums: an LDS hash claim did not complete");
+    return 0;
+}
+
+int fciqmc_pair_rdm_enable(fciqmc_pair* p, int on) {
+    if (!p) return fail(FCIQMC_EINVAL, "null argument");
+    if (!p->r[0] || !p->r[1]) return fail(FCIQMC_ESTATE, "a replica of the pair was freed");
+    if (!on) {
+        p->rdm = false;
+        CHECK(p->r[0]->eng->set_rdm(false));
+        CHECK(p->r[1]->eng->set_rdm(false));
+        return 0;
+    }
+    const int64_t K = 2 * (int64_t)p->r[0]->sys->N;
+    const int64_t M = K * (K - 1) / 2;
+    hipStream_t s = p->r[0]->stream;
+    HIP_OK(hipStreamSynchronize(s));
+    if (!p->G || p->M != M) {
+        p->arena.release(p->G);
+        p->G = nullptr;
+        CHECK(dalloc(p->arena, &p->G, (size_t)(M * M)));
+        p->M = M;
+    }
+    HIP_OK(hipMemsetAsync(p->G, 0, sizeof(double) * M * M, s));
+    HIP_OK(hipStreamSynchronize(s));
+    p->rdm_steps = 0;
+    CHECK(p->r[0]->eng->set_rdm(true));
+    CHECK(p->r[1]->eng->set_rdm(true));
+    p->rdm = true;
+    return 0;
+}
+
+int fciqmc_pair_rdm(const fciqmc_pair* cp, double* gamma, int64_t capacity, int64_t* dim, double* e_var,
+                    double* norm, int64_t* steps) {
+    if (!cp) return fail(FCIQMC_EINVAL, "null argument");
+    fciqmc_pair* p = const_cast<fciqmc_pair*>(cp);
+    if (!p->r[0]) return fail(FCIQMC_ESTATE, "a replica of the pair was freed");
+    if (!p->G) return fail(FCIQMC_ESTATE, "the pair has not sampled a 2-RDM (fciqmc_pair_rdm_enable)");
+    const int64_t M = p->M;
+    if (dim) *dim = M;
+    if (steps) *steps = p->rdm_steps;
+    HIP_OK(hipStreamSynchronize(p->r[0]->stream));
+    std::vector<double> G((size_t)(M * M));
+    HIP_OK(hipMemcpy(G.data(), p->G, sizeof(double) * M * M, hipMemcpyDeviceToHost));
+    // hermitian part: the two orderings of a sampled pair carry independent noise
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t j = i + 1; j < M; ++j) {
+            const double x = G[(size_t)(i * M + j)] + G[(size_t)(j * M + i)];
+            const double h = x * 0.5;
+            G[(size_t)(i * M + j)] = h;
+            G[(size_t)(j * M + i)] = h;
+        }
+    double nm = 0.0;
+    const double e = p->rdm_steps > 0 ? rdm_energy(p->r[0]->sys, G, nm) : NAN;
+    if (e_var) *e_var = e;
+    if (norm) *norm = nm;
+    if (gamma) {
+        if (capacity < M * M) return fail(FCIQMC_EOVERFLOW, "gamma needs %lld entries", (long long)(M * M));
+        std::memcpy(gamma, G.data(), sizeof(double) * M * M);
+    }
     return 0;
 }
 

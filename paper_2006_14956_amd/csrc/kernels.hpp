@@ -121,6 +121,19 @@ struct StepScalars {
     double* rec_h;
     int64_t* ada_acc;
     int64_t* ada_all;
+    // replica 2-RDM sampling (rdm_rec = nullptr: off): one record per
+    // attempt slot, position chunk * kChunk + lane (RdmRec<W> below)
+    void* rdm_rec;
+    int64_t rdm_cap;
+};
+
+// A generated excitation for the replica 2-RDM: parent (bra) and child
+// (ket) determinants and the weight C_i / (m_i p_gen); w = 0 marks an
+// attempt slot without a non-null draw.
+template <int W> struct RdmRec {
+    uint64_t par[W];
+    uint64_t chi[W];
+    double w;
 };
 
 // Fixed point of the adaptive-shift weights: 2^-40 resolution, so integer
@@ -186,6 +199,8 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
         Rec<W, V> out;
         int64_t out_parent = -1;  // adaptive shift: non-initiator parent's store index
         double out_h = 0.0;
+        RdmRec<W> rdm;            // replica 2-RDM: this slot's draw (w = 0: none)
+        rdm.w = 0.0;
         if (local < natt) {
             int elo = 0, ehi = cnt;
             while (ehi - elo > 1) {
@@ -223,9 +238,18 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
                 const R2 r2 = draw2<W>(key, sc.t, k, kSpawn2, sc.seed, sc.replica);
                 ok = gen_cs<GEN == 4>(sys, tJ, tSK, da, db, r, r2, sc.p_single, sc.p_double, sc.p_opp, x);
             }
-            // spawns from the deterministic space into it are part of P^D
-            if constexpr (EXT)
+            if constexpr (EXT) {
+                // every non-null draw enters the RDM sample, whatever its fate
+                if (ok && sc.rdm_rec) {
+                    const double d1 = x.pgen * (double)n_attempts(C);
+                    rdm.w = (double)C / d1;
+                    const Key<W> tk = make_key<W>(x.ta, x.tb);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) { rdm.par[w] = key.w[w]; rdm.chi[w] = tk.w[w]; }
+                }
+                // spawns from the deterministic space into it are part of P^D
                 if (ok && pcore && core_find<W>(sc, make_key<W>(x.ta, x.tb)) >= 0) ok = false;
+            }
             if (ok && x.H != 0.0) {
                 const double u = unif(r.x[3]);
                 if constexpr (sizeof(V) == 4) {
@@ -264,6 +288,13 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
                     const uint32_t bk = bucket_of(key_hash<W>(tk), (uint32_t)sc.B);
                     out.flag = (init ? 1u : 0u) | (bk << 1);
                 }
+            }
+        }
+        if constexpr (EXT) {
+            if (sc.rdm_rec) {
+                const int64_t pos = g * kChunk + threadIdx.x;
+                if (pos < sc.rdm_cap) static_cast<RdmRec<W>*>(sc.rdm_rec)[pos] = rdm;
+                else atomicOr(&ctl->flags, kFlagSpawnCap);
             }
         }
         if (emit) {
@@ -1678,6 +1709,156 @@ __global__ __launch_bounds__(kThreads) void k_sum2(const double* __restrict__ pa
     const double o = sum_parts(part_ovl, n, shd);
     const double q = sum_parts(part_pt2, n, shd);
     if (threadIdx.x == 0) { out[0] = q; out[1] = o; }
+}
+
+// ---------------------------------------------------------------------------
+// Replica 2-RDM (Sec. "Reduced density matrices", Eq. (FCI2RDM)) over
+// spin-orbital pairs: canonical index so = spin * N + orbital, pair index
+// P(k,l) = k(2K-k-1)/2 + l-k-1 for k < l (K = 2N), matrix G[P(k,l) M +
+// P(m,n)] of M = K(K-1)/2 rows.  Per paired step: an open-addressing table
+// of each replica's population at tau, the exact diagonal terms
+// C_i^1 C_i^2 over determinants occupied in both, and for every excitation
+// D_i -> D_j a replica generated, (C_i / (m_i p_gen)) C_j^other / 2 times
+// <D_i|a+_k a+_l a_n a_m|D_j>.
+// ---------------------------------------------------------------------------
+template <int W> struct PopTable {
+    uint64_t* keys;   // slots * W
+    double* vals;
+    int32_t* used;    // 0 empty, 1 claimed
+    uint64_t mask;
+};
+
+// Insert every entry of a store (B buckets of R entries, count[b] used).
+template <int W, class V>
+__global__ __launch_bounds__(kThreads) void k_pop_table(Store<V> st, int R, int B, PopTable<W> T) {
+    for (int b = blockIdx.x; b < B; b += gridDim.x) {
+        const int cnt = st.count[b];
+        for (int e = threadIdx.x; e < cnt; e += kThreads) {
+            const int64_t x = (int64_t)b * R + e;
+            const Key<W> key = load_key<W>(st.keys + x * W);
+            uint64_t s = key_hash<W>(key) & T.mask;
+            while (atomicCAS(&T.used[s], 0, 1) != 0) s = (s + 1) & T.mask;
+            store_key<W>(T.keys + s * W, key);
+            T.vals[s] = (double)st.vals[x];
+        }
+    }
+}
+
+template <int W> __device__ __forceinline__ double pop_lookup(const PopTable<W>& T, const Key<W>& key) {
+    uint64_t s = key_hash<W>(key) & T.mask;
+    for (;;) {
+        if (T.used[s] == 0) return 0.0;
+        if (key_eq<W>(load_key<W>(T.keys + s * W), key)) return T.vals[s];
+        s = (s + 1) & T.mask;
+    }
+}
+
+__device__ __forceinline__ int64_t rdm_pair(int K, int k, int l) {
+    return (int64_t)k * (2 * K - k - 1) / 2 + (l - k - 1);
+}
+// canonical spin-orbital index of (spin, orbital)
+__device__ __forceinline__ int so_index(int N, int sg, int p) { return sg * N + p; }
+
+// Fermion sign of <D_i| a+_k a+_l a_n a_m |D_j> with D_i the result of the
+// operators on D_j (a, b its masks): each operator, applied right to left,
+// counts the occupied spin orbitals below it in the current string.
+__device__ __forceinline__ int rdm_parity(uint64_t a, uint64_t b, int N, int k, int l, int m, int n) {
+    uint64_t A = a, B = b;
+    int par = below(A, B, m / N, m % N);
+    clear_so(A, B, m / N, m % N);
+    par += below(A, B, n / N, n % N);
+    clear_so(A, B, n / N, n % N);
+    par += below(A, B, l / N, l % N);
+    set_so(A, B, l / N, l % N);
+    par += below(A, B, k / N, k % N);
+    return par & 1;
+}
+
+// Diagonal terms: for each determinant of the first population, C^1 C^2
+// (C^2 from the second population's table) on Gamma_{kl,kl} for every
+// occupied pair k < l; summed per workgroup in LDS (M doubles of dynamic
+// shared memory), then added to G.
+template <int W, class V>
+__global__ __launch_bounds__(kThreads) void k_rdm_diag(Store<V> s1, int R, int B, PopTable<W> T2, int N,
+                                                       double* __restrict__ G) {
+    extern __shared__ double dg[];
+    const int K = 2 * N;
+    const int64_t M = (int64_t)K * (K - 1) / 2;
+    for (int64_t i = threadIdx.x; i < M; i += kThreads) dg[i] = 0.0;
+    __syncthreads();
+    for (int bk = blockIdx.x; bk < B; bk += gridDim.x) {
+        const int cnt = s1.count[bk];
+        for (int e = threadIdx.x; e < cnt; e += kThreads) {
+            const int64_t x = (int64_t)bk * R + e;
+            const Key<W> key = load_key<W>(s1.keys + x * W);
+            const double c2 = pop_lookup<W>(T2, key);
+            const double q = (double)s1.vals[x] * c2;
+            if (q == 0.0) continue;
+            const uint64_t A = key_alpha<W>(key), Bm = key_beta<W>(key);
+            // occupied spin orbitals in canonical order: alpha, then beta
+            for (int sk = 0; sk < 2; ++sk)
+                for (uint64_t xk = sk ? Bm : A; xk; xk &= xk - 1) {
+                    const int k = so_index(N, sk, ctz64(xk));
+                    for (int sl = sk; sl < 2; ++sl)
+                        for (uint64_t xl = sl ? Bm : A; xl; xl &= xl - 1) {
+                            const int l = so_index(N, sl, ctz64(xl));
+                            if (l <= k) continue;
+                            const int64_t P = rdm_pair(K, k, l);
+                            lds_add<double>(&dg[P], q);
+                        }
+                }
+        }
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < M; i += kThreads)
+        if (dg[i] != 0.0) atomicAdd(&G[i * M + i], dg[i]);
+}
+
+// Off-diagonal terms from n generated excitations of one replica, the
+// child's coefficient from the other replica's table.
+template <int W>
+__global__ __launch_bounds__(kThreads) void k_rdm_off(const RdmRec<W>* __restrict__ rec, int64_t n,
+                                                      PopTable<W> To, int N, double* __restrict__ G) {
+    const int K = 2 * N;
+    const int64_t M = (int64_t)K * (K - 1) / 2;
+    for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < n; q += (int64_t)gridDim.x * kThreads) {
+        const RdmRec<W> r = rec[q];
+        if (r.w == 0.0) continue;
+        Key<W> pk, ck;
+#pragma unroll
+        for (int w = 0; w < W; ++w) { pk.w[w] = r.par[w]; ck.w[w] = r.chi[w]; }
+        const double cj = pop_lookup<W>(To, ck);
+        if (cj == 0.0) continue;
+        const double w1 = r.w * cj;
+        const double h = w1 * 0.5;
+        // bra D_i = parent, ket D_j = child: a_m a_n remove c\p, a+_l a+_k add p\c
+        const uint64_t pa = key_alpha<W>(pk), pb = key_beta<W>(pk);
+        const uint64_t ca = key_alpha<W>(ck), cb = key_beta<W>(ck);
+        const uint64_t ra = ca & ~pa, rb = cb & ~pb;   // in the ket only
+        const uint64_t xa = pa & ~ca, xb = pb & ~cb;   // in the bra only
+        const int nr = popc64(ra) + popc64(rb);
+        int rm[2], ad[2], c = 0, d = 0;
+        for (uint64_t t = ra; t; t &= t - 1) rm[c++] = so_index(N, 0, ctz64(t));
+        for (uint64_t t = rb; t; t &= t - 1) rm[c++] = so_index(N, 1, ctz64(t));
+        for (uint64_t t = xa; t; t &= t - 1) ad[d++] = so_index(N, 0, ctz64(t));
+        for (uint64_t t = xb; t; t &= t - 1) ad[d++] = so_index(N, 1, ctz64(t));
+        if (nr == 2) {
+            const int m = rm[0], nn = rm[1], k = ad[0], l = ad[1];
+            const int par = rdm_parity(ca, cb, N, k, l, m, nn);
+            atomicAdd(&G[rdm_pair(K, k, l) * M + rdm_pair(K, m, nn)], par ? -h : h);
+        } else if (nr == 1) {
+            // promotions over the orbitals q occupied in both
+            const uint64_t qa = pa & ca, qb = pb & cb;
+            for (int sq = 0; sq < 2; ++sq)
+                for (uint64_t t = sq ? qb : qa; t; t &= t - 1) {
+                    const int qq = so_index(N, sq, ctz64(t));
+                    const int m = rm[0] < qq ? rm[0] : qq, nn = rm[0] < qq ? qq : rm[0];
+                    const int k = ad[0] < qq ? ad[0] : qq, l = ad[0] < qq ? qq : ad[0];
+                    const int par = rdm_parity(ca, cb, N, k, l, m, nn);
+                    atomicAdd(&G[rdm_pair(K, k, l) * M + rdm_pair(K, m, nn)], par ? -h : h);
+                }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -83,6 +83,7 @@ EXPORTS = ["fciqmc_params_default", "fciqmc_load_integrals", "fciqmc_init", "fci
            "fciqmc_server_submit", "fciqmc_server_poll", "fciqmc_server_info",
            "fciqmc_server_clock", "fciqmc_server_free", "fciqmc_set_core", "fciqmc_get_core",
            "fciqmc_pair_create", "fciqmc_pair_step", "fciqmc_pair_pt2", "fciqmc_pair_free",
+           "fciqmc_pair_rdm_enable", "fciqmc_pair_rdm",
            "fciqmc_free_run", "fciqmc_free_system", "fciqmc_last_error"]
 
 _lib = None
@@ -147,6 +148,8 @@ def lib():
         L.fciqmc_pair_step.argtypes = [vp, C.c_int, C.POINTER(StepStats), C.POINTER(StepStats), pdbl]
         L.fciqmc_pair_pt2.argtypes = [vp, i64, pdbl, pdbl, C.POINTER(i64)]
         L.fciqmc_pair_free.argtypes = [vp]
+        L.fciqmc_pair_rdm_enable.argtypes = [vp, C.c_int]
+        L.fciqmc_pair_rdm.argtypes = [vp, pdbl, i64, C.POINTER(i64), pdbl, pdbl, C.POINTER(i64)]
         L.fciqmc_pair_free.restype = None
         L.fciqmc_server_free.restype = None
         L.fciqmc_free_run.argtypes = [vp]
@@ -298,6 +301,23 @@ def fciqmc_pair_pt2(pair: Pair, skip: int = 0) -> dict:
     m, e, n = C.c_double(), C.c_double(), C.c_int64()
     _check(lib().fciqmc_pair_pt2(pair.handle, int(skip), C.byref(m), C.byref(e), C.byref(n)))
     return {"mean": m.value, "err": e.value, "n": n.value}
+
+
+def fciqmc_pair_rdm_enable(pair: Pair, on: bool = True):
+    _check(lib().fciqmc_pair_rdm_enable(pair.handle, int(bool(on))))
+
+
+def fciqmc_pair_rdm(pair: Pair, matrix: bool = True) -> dict:
+    """The accumulated replica 2-RDM (hermitian, M x M, or None), the
+    variational energy, the norm and the steps sampled."""
+    dim, steps = C.c_int64(), C.c_int64()
+    e, nm = C.c_double(), C.c_double()
+    _check(lib().fciqmc_pair_rdm(pair.handle, None, 0, C.byref(dim), None, None, None))
+    M = dim.value
+    G = np.zeros((M, M)) if matrix else None
+    _check(lib().fciqmc_pair_rdm(pair.handle, _p(G, C.c_double) if matrix else None, M * M if matrix else 0,
+                                 C.byref(dim), C.byref(e), C.byref(nm), C.byref(steps)))
+    return {"gamma": G, "e_var": e.value, "norm": nm.value, "steps": steps.value, "dim": M}
 
 
 def fciqmc_pair_free(pair: Pair):

@@ -1,0 +1,121 @@
+"""GPU parity of the replica 2-RDM (Sec. "Reduced density matrices", Eq.
+(FCI2RDM)) and its variational energy against the oracle: both replicas
+follow the oracle bit for bit (integer walkers), so both sides sample the
+same excitations; the accumulated matrices differ only by the order of
+their sums (atomic additions on the device)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_14956_amd import fciqmc as F
+from paper_2006_14956_amd import inputs
+from tests.gpu_helpers import assert_same_stats, assert_same_walkers, make_gpu_run, ref_of
+
+pytestmark = pytest.mark.gpu
+
+
+def _hermitian(G):
+    return (G + G.T) * 0.5
+
+
+def _setup(s, n_a, words, mode, n_dets, seed):
+    sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
+    ra, rb = ref_of(s)
+    w = words if words else (1 if s.n_orb <= 32 else 2)
+    osys = oracle.System.from_inputs(s, words=w)
+    om = oracle.MODE_INTEGER if mode == "integer" else oracle.MODE_REAL
+    gpu, orc = [], []
+    for rep in (0, 1):
+        _, run = make_gpu_run(s, tau=0.02, target=1e9, n_a=n_a, seed=seed, replica=rep, sysd=sysd,
+                              det_words=words, mode=mode)
+        o = oracle.Run(osys, ref=(ra, rb), tau=0.02, target=1e9, n_a=n_a, seed=seed, replica=rep, mode=om)
+        o.collect_rejected(True)
+        o.log_excitations(True)
+        gpu.append(run)
+        orc.append(o)
+    a, b, v = inputs.random_walker_state(s.n_orb, s.n_alpha, s.n_beta, n_dets, seed=seed + 1, max_pop=20,
+                                         include=(ra, rb), integer=(mode == "integer"))
+    for g, o in zip(gpu, orc):
+        F.fciqmc_set_walkers(g, a, b, v)
+        F.fciqmc_set_checkpoint(g, 0, -0.5, 1, 0, float(np.abs(v).sum()))
+        o.set_walkers(a, b, v)
+        o.set_state(0, -0.5, 1, 0, float(np.abs(v).sum()))
+    return sysd, osys, gpu, orc
+
+
+@pytest.mark.parametrize("n_orb,na,nb,words", [(10, 4, 3, 1), (10, 4, 3, 2), (8, 4, 4, 1)])
+def test_rdm_matches_oracle(n_orb, na, nb, words):
+    s = inputs.synthetic_molecule(n_orb, na, nb, seed=7)
+    sysd, osys, gpu, orc = _setup(s, 3.0, words, "integer", 300, 11)
+    pair = F.fciqmc_pair_create(gpu[0], gpu[1])
+    F.fciqmc_pair_rdm_enable(pair, True)
+    M = osys.rdm_dim()
+    G = np.zeros((M, M))
+    for step in range(5):
+        g1, g2, _ = F.fciqmc_pair_step(pair, 1)
+        o1 = orc[0].step(1)
+        o2 = orc[1].step(1)
+        assert_same_stats(g1[0], o1[0])
+        assert_same_stats(g2[0], o2[0])
+        assert orc[0].excitations() > 1000
+        oracle.pair_rdm_step(orc[0], orc[1], G)
+    for g, o in zip(gpu, orc):
+        assert_same_walkers(g, o)
+    rep = F.fciqmc_pair_rdm(pair)
+    want = _hermitian(G)
+    assert rep["dim"] == M and rep["steps"] == 5
+    scale = np.max(np.abs(want))
+    assert np.max(np.abs(rep["gamma"] - want)) <= 1e-12 * scale, np.max(np.abs(rep["gamma"] - want)) / scale
+    assert np.count_nonzero(want) > M  # off-diagonal entries sampled
+    e, norm = osys.rdm_energy(want)
+    assert abs(rep["norm"] - norm) <= 1e-12 * abs(norm)
+    assert abs(rep["e_var"] - e) <= 1e-10 * abs(e), (rep["e_var"], e)
+    F.fciqmc_pair_free(pair)
+    for g in gpu:
+        F.fciqmc_free_run(g)
+    F.fciqmc_free_system(sysd)
+
+
+def test_rdm_real_walkers_one_step():
+    """Real coefficients: one paired step's sample equals the oracle's to
+    1e-12 (the populations agree to rounding, the excitations exactly)."""
+    s = inputs.synthetic_molecule(8, 4, 4, seed=2)
+    sysd, osys, gpu, orc = _setup(s, 3.0, 0, "real", 400, 5)
+    pair = F.fciqmc_pair_create(gpu[0], gpu[1])
+    F.fciqmc_pair_rdm_enable(pair, True)
+    F.fciqmc_pair_step(pair, 1)
+    for o in orc:
+        o.step(1)
+    M = osys.rdm_dim()
+    G = np.zeros((M, M))
+    oracle.pair_rdm_step(orc[0], orc[1], G)
+    want = _hermitian(G)
+    rep = F.fciqmc_pair_rdm(pair)
+    assert np.max(np.abs(rep["gamma"] - want)) <= 1e-12 * np.max(np.abs(want))
+    F.fciqmc_pair_free(pair)
+    for g in gpu:
+        F.fciqmc_free_run(g)
+    F.fciqmc_free_system(sysd)
+
+
+def test_rdm_enable_rules():
+    """No report before sampling was enabled; disabling keeps the sum and
+    stops adding to it."""
+    s = inputs.molecule_8o8e()
+    sysd, osys, gpu, orc = _setup(s, 3.0, 0, "integer", 100, 3)
+    pair = F.fciqmc_pair_create(gpu[0], gpu[1])
+    with pytest.raises(F.FciqmcError):
+        F.fciqmc_pair_rdm(pair)
+    F.fciqmc_pair_rdm_enable(pair, True)
+    F.fciqmc_pair_step(pair, 3)
+    r1 = F.fciqmc_pair_rdm(pair)
+    F.fciqmc_pair_rdm_enable(pair, False)
+    F.fciqmc_pair_step(pair, 2)
+    r2 = F.fciqmc_pair_rdm(pair)
+    assert r1["steps"] == r2["steps"] == 3
+    assert np.array_equal(r1["gamma"], r2["gamma"])
+    assert np.isfinite(r1["e_var"])
+    F.fciqmc_pair_free(pair)
+    for g in gpu:
+        F.fciqmc_free_run(g)
+    F.fciqmc_free_system(sysd)
