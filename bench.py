@@ -567,16 +567,30 @@ def measure_pt2(F, np, torch, steps):
     torch.cuda.synchronize()
     paired = (time.perf_counter() - t0) / steps
     rep = F.fciqmc_pair_pt2(pair)
+    # the variational energy the correction applies to: the replica 2-RDM
+    # sampled over as many further paired steps (Sec. "Reduced density matrices")
+    F.fciqmc_pair_rdm_enable(pair, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, d2 = F.fciqmc_pair_step(pair, steps)
+    torch.cuda.synchronize()
+    sampled = (time.perf_counter() - t0) / steps
+    rdm = F.fciqmc_pair_rdm(pair, matrix=False)
+    rep_all = F.fciqmc_pair_pt2(pair)
     es = [F.fciqmc_energy(r) for r in runs]
     F.fciqmc_pair_free(pair)
-    out = {"config": dict(PT2_DESC, growth_steps=3000, paired_steps=steps),
-           "de2": rep["mean"], "de2_err": rep["err"], "de2_steps": rep["n"],
-           "ms_per_paired_step": 1e3 * paired, "ms_per_two_solo_steps": 1e3 * alone,
+    out = {"config": dict(PT2_DESC, growth_steps=3000, paired_steps=steps, rdm_steps=steps),
+           "de2": rep_all["mean"], "de2_err": rep_all["err"], "de2_steps": rep_all["n"],
+           "e_var_rdm": rdm["e_var"], "e_var_plus_de2": rdm["e_var"] + rep_all["mean"],
+           "rdm_norm": rdm["norm"], "rdm_steps": rdm["steps"],
+           "ms_per_paired_step": 1e3 * paired, "ms_per_paired_step_with_rdm": 1e3 * sampled,
+           "ms_per_two_solo_steps": 1e3 * alone,
            "replicas": [{"e_proj": e["e_proj"], "e_proj_err": e["e_proj_err"], "shift": e["shift"],
                          "shift_err": e["shift_err"]} for e in es]}
-    log(f"[pt2] dE2 {rep['mean']:.6f} +- {rep['err']:.2e} over {rep['n']} steps; "
-        f"{1e3 * paired:.4f} ms per paired step vs {1e3 * alone:.4f} for the two alone; E_proj "
-        + ", ".join(f"{e['e_proj']:.6f} +- {e['e_proj_err']:.1e}" for e in es))
+    log(f"[pt2] dE2 {rep_all['mean']:.6f} +- {rep_all['err']:.2e} over {rep_all['n']} steps; E_var (2-RDM, "
+        f"{rdm['steps']} steps) {rdm['e_var']:.6f}, E_var + dE2 {rdm['e_var'] + rep_all['mean']:.6f}; "
+        f"{1e3 * paired:.4f} ms per paired step ({1e3 * sampled:.4f} with the RDM) vs {1e3 * alone:.4f} "
+        "for the two alone; E_proj " + ", ".join(f"{e['e_proj']:.6f} +- {e['e_proj_err']:.1e}" for e in es))
     for r in runs:
         F.fciqmc_free_run(r)
     F.fciqmc_free_system(sysd)
