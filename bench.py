@@ -221,6 +221,19 @@ def measure_batched(F, np, steps, warmup, grow_max, tune_steps, plain=True):
         F.fciqmc_batch_step(batch, warmup)
     tune = F.fciqmc_batch_tune(batch, tune_steps)
     log(f"[batched] tuned: {tune}")
+    # both launch forms at the tuned partition, persistent first
+    forms = {}
+    for form in (True, False):
+        F.fciqmc_batch_set_persistent(batch, form)
+        F.fciqmc_batch_step(batch, 20)
+        t1 = time.perf_counter()
+        sf = F.fciqmc_batch_step(batch, steps // 2, as_array=True)
+        wf = time.perf_counter() - t1
+        forms["persistent" if form else "per_phase"] = {"attempts_per_s": int(sf["attempts"].sum()) / wf,
+                                                        "ms_per_step": 1e3 * wf / (steps // 2)}
+    log(f"[batched] launch forms: " + ", ".join(f"{k} {v['attempts_per_s']:.4e} attempts/s "
+                                                 f"({v['ms_per_step']:.4f} ms/step)" for k, v in forms.items()))
+    F.fciqmc_batch_set_persistent(batch, bool(tune["persistent"]))
     # the state both timings start from
     snap = [(F.fciqmc_get_walkers(r), F.fciqmc_get_checkpoint(r)) for r in runs]
     F.fciqmc_batch_profile(batch, True)
@@ -242,7 +255,8 @@ def measure_batched(F, np, steps, warmup, grow_max, tune_steps, plain=True):
                           walkers_total=float(sum(final_b)), dets_total=int(ndets)),
            "value": rate_b, "unit": "attempts/s", "ms_per_step": 1e3 * wall / steps,
            "kernels_ms_per_step": {k: v / max(1, nsteps) for k, v in ms.items()},
-           "tune": tune}
+           "launch": "one cooperative launch per step" if tune["persistent"] else "one launch per phase",
+           "launch_forms": forms, "tune": tune}
     if plain:
         solo = []
         for i, ((a, b, v), ck) in enumerate(snap):
@@ -765,6 +779,7 @@ def main():
     ap.add_argument("--adaptive", type=int, default=100000, metavar="STEPS",
                     help="steps of each run of the adaptive-shift leg (0 to skip)")
     ap.add_argument("--adaptive-only", action="store_true", help="only run the adaptive-shift leg")
+    ap.add_argument("--batched-only", action="store_true", help="only run the batched leg")
     ap.add_argument("--semistoch-only", action="store_true",
                     help="only run the semi-stochastic comparison")
     ap.add_argument("--generators-only", action="store_true",
@@ -796,6 +811,10 @@ def main():
     stream = torch.cuda.current_stream()
     if args.adaptive_only:
         print(json.dumps(measure_adaptive(F, np, torch, args.adaptive or 100000)), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps(measure_batched(F, np, args.batched_steps or 1000, args.batched_warmup,
+                                         args.batched_grow, args.batched_tune)), flush=True)
         return
     if args.pt2_only:
         print(json.dumps(measure_pt2(F, np, torch, args.pt2 or 20000)), flush=True)

@@ -242,10 +242,11 @@ int fciqmc_profile(fciqmc_run *run, int enable, double *ms, int64_t *steps, int6
 
 /* ---- Batches: many populations advanced by shared launches ------------
  *
- * A batch steps its member runs together: per step it issues one spawn
- * launch per excitation generator, one annihilation launch and one post
- * launch for all members of the same determinant width and value type, and
- * a single read-back and synchronisation for the whole batch.  The members
+ * A batch steps its member runs together: per step one spawn launch per
+ * excitation generator, one annihilation launch and one post launch (or, in
+ * the persistent form, one cooperative launch) for all members of the same
+ * determinant width and value type, and a single read-back and
+ * synchronisation for the whole batch.  The members
  * may hold different systems (orbital counts, integrals), parameters and
  * population sizes.  Each member's arithmetic is exactly that of stepping
  * it alone (Eq. fciqmc_dyn applied per population; the populations never
@@ -271,6 +272,7 @@ int fciqmc_batch_step(fciqmc_batch *batch, int n_steps, fciqmc_step_stats *stats
 
 /* Autotuner report (see fciqmc_batch_tune). */
 typedef struct fciqmc_tune_report {
+    int persistent;        /* chosen launch form: 1 one cooperative launch per step          */
     int dets_per_bucket;   /* chosen walker-store occupancy; 0 = partition left as found    */
     int grid_spawn;        /* chosen spawn workgroups per launch; 0 = one per 256 attempts */
     int grid_annihilate;   /* chosen annihilation workgroups; 0 = one per bucket            */
@@ -280,12 +282,23 @@ typedef struct fciqmc_tune_report {
     double rate_best;      /* spawn attempts/s of the configuration chosen                  */
 } fciqmc_tune_report;
 
-/* Time trial_steps real steps under each candidate launch shape -- walker
- * store occupancy (determinants per bucket, which sets each member's bucket
- * count), spawn grid and annihilation grid, one coordinate at a time -- and
- * keep the fastest.  None of these changes any trajectory; the tuning steps
- * are ordinary steps of every member.  out: host, may be NULL. */
+/* Time trial_steps real steps under each candidate launch shape -- the
+ * launch form (persistent or per phase), walker-store occupancy
+ * (determinants per bucket, which sets each member's bucket count), spawn
+ * grid and annihilation grid, one coordinate at a time -- and keep the
+ * fastest.  None of these changes any trajectory; the tuning steps are
+ * ordinary steps of every member.  out: host, may be NULL. */
 int fciqmc_batch_tune(fciqmc_batch *batch, int trial_steps, fciqmc_tune_report *out);
+/* Launch form of a batch step (default off; fciqmc_batch_tune times both
+ * and keeps the faster): on, each group of members
+ * with the same determinant width and value type advances through spawn,
+ * annihilation, new diagonals and post work in ONE cooperative launch whose
+ * workgroups all stay resident, the phases separated by a grid-wide barrier
+ * (a bounded wait: a barrier that does not complete fails the step with
+ * EDEVICE instead of hanging); off, one launch per phase and generator.
+ * Work items and arithmetic are those of the per-phase launches, so every
+ * member's trajectory is the same either way. */
+int fciqmc_batch_set_persistent(fciqmc_batch *batch, int on);
 /* Per-kernel timing of the batch's launches, as fciqmc_profile (ms: spawn,
  * annihilation, post launches of all members; *steps: batch steps timed). */
 int fciqmc_batch_profile(fciqmc_batch *batch, int enable, double *ms, int64_t *steps);

@@ -1208,6 +1208,8 @@ struct BatchGroupBase {
     std::vector<fciqmc_run*> runs;  // ordered by excitation generator
     virtual ~BatchGroupBase() {}
     virtual int prepare(hipStream_t s) = 0;
+    // the whole step in one cooperative launch (after prepare)
+    virtual int launch_persistent(hipStream_t s) = 0;
     virtual int launch_spawn(hipStream_t s, int grid) = 0;
     virtual int launch_annihilate(hipStream_t s, int grid) = 0;
     virtual int launch_post(hipStream_t s) = 0;
@@ -1229,16 +1231,23 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
     int64_t ftot = 0;           // work items of the new-diagonal kernel
     size_t flds = 0;            // its LDS bytes (largest molecular member)
 
+    Arena arena_bar;            // holds bar (kept across reserve())
     ~BatchGroup() override {
         if (hbuf) (void)hipHostFree(hbuf);
         if (hctl) (void)hipHostFree(hctl);
         arena.clear();
+        arena_bar.clear();
     }
     E* eng(size_t i) const { return static_cast<E*>(runs[i]->eng.get()); }
-    static size_t bytes_for(size_t n) { return sizeof(Inst<W, V>) * n + sizeof(int64_t) * (3 * n + kGens + 2); }
+    GridBar* bar = nullptr;     // grid barrier of the persistent launch
+    bool bar_dirty = true;      // reset it before the next persistent launch
+    int max_blocks[kGens + 1] = {};  // co-resident workgroups per kernel variant (0 = not yet known)
+    size_t mb_lds[kGens + 1] = {};   // the dynamic LDS size they were found for
+    static size_t bytes_for(size_t n) { return sizeof(Inst<W, V>) * n + sizeof(int64_t) * (4 * n + kGens + 3); }
     int64_t* bfirst(char* base) const { return reinterpret_cast<int64_t*>(base + sizeof(Inst<W, V>) * cap); }
     int64_t* cfirst(char* base) const { return bfirst(base) + cap + 1; }
     int64_t* ffirst(char* base) const { return cfirst(base) + cap + kGens; }
+    int64_t* pfirst(char* base) const { return ffirst(base) + cap + 1; }  // chunks over all members
 
     int reserve(size_t n) {
         if (n <= cap) return 0;
@@ -1280,6 +1289,16 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
         }
         bf[n] = btot;
         ff[n] = ftot;
+        {
+            int64_t* pf = pfirst(hbuf);
+            int64_t c = 0;
+            for (size_t i = 0; i < n; ++i) {
+                pf[i] = c;
+                c += chunks[i];
+                hi[i].gen = runs[i]->p.excitgen;
+            }
+            pf[n] = c;
+        }
         // generator ranges; range g keeps its chunk prefix in cf[g0[g] + g .. g0[g+1] + g]
         int k = 0;
         for (int g = 0; g < kGens; ++g) {
@@ -1297,6 +1316,58 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
             ctot[g] = c;
         }
         HIP_OK(hipMemcpyAsync(dbuf, hbuf, bytes_for(cap), hipMemcpyHostToDevice, s));
+        return 0;
+    }
+    // One launch for the whole step of every member: a kernel variant with
+    // the generator fixed when all members share one of the table-free
+    // generators, else with the generator chosen per member; as many
+    // workgroups as can be resident together (at most the largest phase's
+    // work items); members' step scalars poisoned beforehand so that a
+    // launch whose barrier failed leaves them flagged.
+    int launch_persistent(hipStream_t s) override {
+        if (runs.empty()) return 0;
+        if (!bar) {
+            CHECK(dalloc(arena_bar, &bar, 1));
+            bar_dirty = true;
+        }
+        if (bar_dirty) {
+            HIP_OK(hipMemsetAsync(bar, 0, sizeof(GridBar), s));
+            bar_dirty = false;
+        }
+        int gen = runs[0]->p.excitgen;
+        for (auto* r : runs)
+            if (r->p.excitgen != gen) gen = -1;
+        if (gen > 2) gen = -1;
+        const void* fn;
+        switch (gen) {
+            case 0: fn = reinterpret_cast<const void*>(&k_batch_step<W, V, 0>); break;
+            case 1: fn = reinterpret_cast<const void*>(&k_batch_step<W, V, 1>); break;
+            case 2: fn = reinterpret_cast<const void*>(&k_batch_step<W, V, 2>); break;
+            default: fn = reinterpret_cast<const void*>(&k_batch_step<W, V, -1>); break;
+        }
+        // dynamic LDS: the new-diagonal tables of the largest molecular member
+        const size_t lds = std::max<size_t>(flds, sizeof(double));
+        int& mb = max_blocks[gen + 1];
+        if (mb == 0 || mb_lds[gen + 1] != lds) {
+            int per_cu = 0, cus = 0, dev = 0;
+            HIP_OK(hipGetDevice(&dev));
+            HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds));
+            mb = std::max(1, per_cu) * std::max(1, cus);
+            mb_lds[gen + 1] = lds;
+        }
+        const int64_t work = std::max<int64_t>({pfirst(hbuf)[runs.size()], btot, ftot, (int64_t)runs.size(), 1});
+        const unsigned grid = (unsigned)std::min<int64_t>(work, mb);
+        for (size_t i = 0; i < runs.size(); ++i) hctl[i].flags = kFlagSpin;
+        const Inst<W, V>* di = reinterpret_cast<const Inst<W, V>*>(dbuf);
+        const int64_t* cf = pfirst(dbuf);
+        const int64_t* bf = bfirst(dbuf);
+        const int64_t* ff = ffirst(dbuf);
+        int k = (int)runs.size();
+        GridBar* gb = bar;
+        Ctl* ho = hctl;
+        void* args[] = {&di, &cf, &bf, &ff, &k, &gb, &ho};
+        HIP_OK(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kThreads), args, lds, s));
         return 0;
     }
     int launch_spawn(hipStream_t s, int grid) override {
@@ -1345,6 +1416,8 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
     int finish(fciqmc_step_stats* row) override {
         int rc = 0;
         std::string msg;
+        for (size_t i = 0; i < runs.size(); ++i)
+            if (hctl[i].flags & kFlagSpin) bar_dirty = true;
         for (size_t i = 0; i < runs.size(); ++i) {
             fciqmc_run* r = runs[i];
             Ctl out{};
@@ -1380,6 +1453,7 @@ struct fciqmc_batch {
     std::vector<fciqmc_run*> members;          // in order of addition
     std::unique_ptr<BatchGroupBase> group[4];  // by engine kind
     int grid_spawn = 0, grid_ann = 0;          // workgroups per launch, 0 = one per work item
+    int persistent = 0;                        // 1: the step in one cooperative launch per group
     bool profile = false;
     hipEvent_t ev[kKernels + 1]{};
     double kms[kKernels]{};
@@ -1409,15 +1483,26 @@ static int batch_step_once(fciqmc_batch* b, fciqmc_step_stats* row) {
     for (auto& g : b->group)
         if (g) CHECK(g->prepare(b->stream));
     if (b->profile) HIP_OK(hipEventRecord(b->ev[0], b->stream));
-    for (auto& g : b->group)
-        if (g) CHECK(g->launch_spawn(b->stream, b->grid_spawn));
-    if (b->profile) HIP_OK(hipEventRecord(b->ev[1], b->stream));
-    for (auto& g : b->group)
-        if (g) CHECK(g->launch_annihilate(b->stream, b->grid_ann));
-    if (b->profile) HIP_OK(hipEventRecord(b->ev[2], b->stream));
-    for (auto& g : b->group)
-        if (g) CHECK(g->launch_post(b->stream));
-    if (b->profile) HIP_OK(hipEventRecord(b->ev[3], b->stream));
+    if (b->persistent) {
+        // the whole step in one launch per group: its time is counted as spawn
+        for (auto& g : b->group)
+            if (g) CHECK(g->launch_persistent(b->stream));
+        if (b->profile) {
+            HIP_OK(hipEventRecord(b->ev[1], b->stream));
+            HIP_OK(hipEventRecord(b->ev[2], b->stream));
+            HIP_OK(hipEventRecord(b->ev[3], b->stream));
+        }
+    } else {
+        for (auto& g : b->group)
+            if (g) CHECK(g->launch_spawn(b->stream, b->grid_spawn));
+        if (b->profile) HIP_OK(hipEventRecord(b->ev[1], b->stream));
+        for (auto& g : b->group)
+            if (g) CHECK(g->launch_annihilate(b->stream, b->grid_ann));
+        if (b->profile) HIP_OK(hipEventRecord(b->ev[2], b->stream));
+        for (auto& g : b->group)
+            if (g) CHECK(g->launch_post(b->stream));
+        if (b->profile) HIP_OK(hipEventRecord(b->ev[3], b->stream));
+    }
     HIP_OK(hipStreamSynchronize(b->stream));
     if (b->profile) {
         for (int i = 0; i < kKernels; ++i) {
@@ -1760,6 +1845,12 @@ int fciqmc_batch_step(fciqmc_batch* b, int n_steps, fciqmc_step_stats* stats) {
     return 0;
 }
 
+int fciqmc_batch_set_persistent(fciqmc_batch* b, int on) {
+    if (!b) return fail(FCIQMC_EINVAL, "null argument");
+    b->persistent = on ? 1 : 0;
+    return 0;
+}
+
 int fciqmc_batch_profile(fciqmc_batch* b, int enable, double* ms, int64_t* steps) {
     if (!b) return fail(FCIQMC_EINVAL, "null argument");
     if (enable && !b->profile) {
@@ -1807,6 +1898,16 @@ int fciqmc_batch_tune(fciqmc_batch* b, int trial_steps, fciqmc_tune_report* out)
     CHECK(batch_rate(b, trial_steps, best));
     ++trials;
     rep.rate_initial = best;
+    // one persistent launch per step, or separate launches per phase
+    {
+        const int found = b->persistent;
+        b->persistent = 1 - found;
+        double rate = 0.0;
+        CHECK(batch_rate(b, trial_steps, rate));
+        ++trials;
+        if (rate > best) best = rate;
+        else b->persistent = found;
+    }
     // walker-store occupancy: rebucket every member, time, keep the best
     const std::vector<int64_t> start_b = [&] {
         std::vector<int64_t> v;
@@ -1851,6 +1952,7 @@ int fciqmc_batch_tune(fciqmc_batch* b, int trial_steps, fciqmc_tune_report* out)
         if (rate > best) { best = rate; best_ga = ga; }
     }
     b->grid_ann = best_ga;
+    rep.persistent = b->persistent;
     rep.dets_per_bucket = best_occ;
     rep.grid_spawn = best_gs;
     rep.grid_annihilate = best_ga;

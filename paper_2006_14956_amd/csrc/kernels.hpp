@@ -526,7 +526,7 @@ template <class V> __device__ __forceinline__ void lds_add(V* p, V v) {
 // (loads, then the final stores) instead of once per stage.  A flagged step
 // writes no offsets; its host copy is the control block as the step left it.
 // ---------------------------------------------------------------------------
-template <int NT>
+template <int NT, int HELD = 2>
 __device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, const int32_t* __restrict__ count,
                                           const double* __restrict__ nw_b, const double* __restrict__ en_b,
                                           const int64_t* __restrict__ rel, const int64_t* __restrict__ need_b,
@@ -547,9 +547,11 @@ __device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, cons
     int64_t la = 0, lk = 0, ln = 0, cnt = 0, rc = 0, mx = 0;
     double nw = 0.0, en = 0.0;
     // the first kHeld buckets of the run keep what the offset pass needs in
-    // registers (no second round of loads after the scan)
-    constexpr int kHeld = 2;
-    int64_t hatt[kHeld] = {}, hneed[kHeld] = {}, hrel[kHeld][kSub] = {};
+    // registers (no second round of loads after the scan); kHeld = 0 keeps
+    // none, for kernels whose other work needs the registers
+    constexpr int kHeld = HELD;
+    int64_t hatt[kHeld > 0 ? kHeld : 1] = {}, hneed[kHeld > 0 ? kHeld : 1] = {},
+            hrel[kHeld > 0 ? kHeld : 1][kSub] = {};
     auto add = [&](int b, int64_t at, int64_t nd) {
         la += at;
         lk += chunks_of(at);
@@ -1303,6 +1305,7 @@ template <int W, class V> struct Inst {
     int64_t* cmap;
     int64_t cmap_cap;
     Ctl* ctl;
+    int gen;   // excitation generator (FCIQMC_GEN_*)
 };
 
 __device__ __forceinline__ int owner_of(const int64_t* __restrict__ first, int k, int64_t g) {
@@ -1370,6 +1373,150 @@ __global__ __launch_bounds__(kPostThreads) void k_post_batch(const Inst<W, V>* _
     const Inst<W, V>& I = inst[blockIdx.x];
     post_work<kPostThreads>(I.out.batt, I.out.count, I.nw_b, I.en_b, I.rel, I.need_b, I.recs_b, I.sc.B,
                             I.out.aoff, I.soff, I.cmap, I.cmap_cap, I.ctl, ctl_out + blockIdx.x, sh, shd, shm, &fl);
+}
+
+// ---------------------------------------------------------------------------
+// The whole batched step in one cooperative launch: spawn, annihilation, new
+// diagonals and post work of every member, with a grid-wide barrier between
+// the phases (every workgroup of a cooperative launch is resident, so all of
+// them reach each barrier).  Work items and their owners are those of the
+// separate launches above, so each member's arithmetic is unchanged.
+// ---------------------------------------------------------------------------
+struct GridBar {
+    unsigned count;  // workgroups arrived at the current barrier
+    unsigned gen;    // barriers completed
+    unsigned err;    // a wait ran out (the launch's results are void)
+    unsigned pad;
+};
+
+constexpr unsigned kBarrierSpins = 1u << 21;  // ~4 s of s_sleep 64: far beyond any phase
+
+// Grid barrier.  Every wave first waits until all its memory operations
+// have completed (its stores have reached this XCD's L2); after the
+// workgroup barrier the first thread alone releases at device scope (the
+// L2 write-back covers the whole workgroup's stores), reads the generation
+// (completed before the arrival is counted) and counts in; the last to
+// arrive resets the count and advances the generation, which the others
+// wait for with a bounded spin; the first thread then acquires at device
+// scope (invalidating the caches the whole workgroup reads through) before
+// the second workgroup barrier releases the other waves.  Returns false on
+// every workgroup once any wait has run out.
+__device__ __forceinline__ bool grid_barrier(GridBar* bar, unsigned* shok) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bool ok = true;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned g = __hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0);  // the generation is read before the arrival counts
+        const unsigned arrived = __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == gridDim.x - 1) {
+            __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0);  // the reset lands before the generation moves
+            __hip_atomic_fetch_add(&bar->gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            // the wait backs off (s_sleep 1, 2, 4 ... 64, about 1.7 us at
+            // most) so that the early workgroups' polls do not crowd the
+            // memory channel the late ones still use
+            unsigned spins = 0, nap = 1;
+            while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                switch (nap) {
+                    case 1: __builtin_amdgcn_s_sleep(1); break;
+                    case 2: __builtin_amdgcn_s_sleep(2); break;
+                    case 4: __builtin_amdgcn_s_sleep(4); break;
+                    case 8: __builtin_amdgcn_s_sleep(8); break;
+                    case 16: __builtin_amdgcn_s_sleep(16); break;
+                    case 32: __builtin_amdgcn_s_sleep(32); break;
+                    default: __builtin_amdgcn_s_sleep(64); break;
+                }
+                if (nap < 64) nap <<= 1;
+                if (++spins > kBarrierSpins) {
+                    __hip_atomic_fetch_or(&bar->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = false;
+                    break;
+                }
+            }
+        }
+        if (__hip_atomic_load(&bar->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = false;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *shok = ok ? 1u : 0u;
+    }
+    __syncthreads();
+    return *shok != 0;
+}
+
+// One spawn chunk of a member with the generator chosen at run time
+// (GEN < 0) or fixed (GEN >= 0).
+template <int W, class V, int GEN>
+__device__ __forceinline__ void spawn_member_chunk(const Inst<W, V>& I, int64_t g, int32_t* smpre) {
+    if constexpr (GEN >= 0) {
+        spawn_chunk<W, V, GEN, false>(I.sys, I.in, I.sc, I.rec2, I.soff, I.scount, I.ctl, I.cmap, g, smpre, I.sys.J,
+                                      I.sys.SK);
+    } else {
+        switch (I.gen) {
+            case 0: spawn_member_chunk<W, V, 0>(I, g, smpre); break;
+            case 1: spawn_member_chunk<W, V, 1>(I, g, smpre); break;
+            case 2: spawn_member_chunk<W, V, 2>(I, g, smpre); break;
+            case 3: spawn_member_chunk<W, V, 3>(I, g, smpre); break;
+            default: spawn_member_chunk<W, V, 4>(I, g, smpre); break;
+        }
+    }
+}
+
+template <int W, class V> union StepLds {
+    int32_t smpre[kMaxR];
+    Lds<W, V> L;
+    struct {
+        int64_t sh[4 * kThreads / 64];
+        int64_t shm[kThreads / 64];
+        double shd[2 * kThreads / 64];
+    } post;
+};
+
+// cfirst, bfirst, ffirst: prefixes of spawn chunks, buckets and new-diagonal
+// work items over the k members; ctl_out: the members' step scalars in
+// pinned host memory.
+template <int W, class V, int GEN>
+__global__ __launch_bounds__(kThreads, 6) void k_batch_step(const Inst<W, V>* __restrict__ inst,
+                                                         const int64_t* __restrict__ cfirst,
+                                                         const int64_t* __restrict__ bfirst,
+                                                         const int64_t* __restrict__ ffirst, int k, GridBar* bar,
+                                                         Ctl* __restrict__ ctl_out) {
+    __shared__ StepLds<W, V> U;
+    __shared__ int pre[kFreshSpan + 1];
+    __shared__ unsigned fl, ok;
+    extern __shared__ double tabs[];
+    // spawn
+    for (int64_t g = blockIdx.x; g < cfirst[k]; g += gridDim.x) {
+        const int i = owner_of(cfirst, k, g);
+        spawn_member_chunk<W, V, GEN>(inst[i], g - cfirst[i], U.smpre);
+    }
+    if (!grid_barrier(bar, &ok)) return;
+    // death, annihilation, compaction, estimator partials
+    for (int64_t g = blockIdx.x; g < bfirst[k]; g += gridDim.x) {
+        const int i = owner_of(bfirst, k, g);
+        const Inst<W, V>& I = inst[i];
+        if (wg_flags(I.ctl, &fl)) continue;  // this member replays its step alone
+        annihilate_bucket<W, V, false>(I.sys, I.in, I.out, I.sc, I.rec2, I.soff, I.scount, I.rel, I.need_b,
+                                       I.recs_b, I.nw_b, I.en_b, I.fpos, I.fcnt, I.ctl, (int)(g - bfirst[i]), U.L);
+    }
+    if (!grid_barrier(bar, &ok)) return;
+    // diagonals of the members' new determinants (molecular systems)
+    for (int64_t g = blockIdx.x; g < ffirst[k]; g += gridDim.x) {
+        const int i = owner_of(ffirst, k, g);
+        const Inst<W, V>& I = inst[i];
+        if (I.sys.onsite) continue;
+        if (wg_flags(I.ctl, &fl)) continue;
+        fresh_item<W, V>(I.sys, I.out, I.sc.h00, I.sc.R, I.sc.B, I.fpos, I.fcnt, g - ffirst[i], tabs, pre);
+    }
+    if (!grid_barrier(bar, &ok)) return;
+    // post work, one workgroup per member
+    for (int i = blockIdx.x; i < k; i += gridDim.x) {
+        const Inst<W, V>& I = inst[i];
+        post_work<kThreads, 0>(I.out.batt, I.out.count, I.nw_b, I.en_b, I.rel, I.need_b, I.recs_b, I.sc.B,
+                               I.out.aoff, I.soff, I.cmap, I.cmap_cap, I.ctl, ctl_out + i, U.post.sh, U.post.shd,
+                               U.post.shm, &fl);
+    }
 }
 
 // Copy the store to flat arrays (offsets from a count scan).

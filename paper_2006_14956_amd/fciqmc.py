@@ -67,7 +67,7 @@ class RequestInfo(C.Structure):
 
 
 class TuneReport(C.Structure):
-    _fields_ = [("dets_per_bucket", C.c_int), ("grid_spawn", C.c_int), ("grid_annihilate", C.c_int),
+    _fields_ = [("persistent", C.c_int), ("dets_per_bucket", C.c_int), ("grid_spawn", C.c_int), ("grid_annihilate", C.c_int),
                 ("trials", C.c_int), ("steps", C.c_int64), ("rate_initial", C.c_double),
                 ("rate_best", C.c_double)]
 
@@ -79,6 +79,7 @@ EXPORTS = ["fciqmc_params_default", "fciqmc_load_integrals", "fciqmc_init", "fci
            "fciqmc_run_device_bytes",
            "fciqmc_profile", "fciqmc_batch_create", "fciqmc_batch_add", "fciqmc_batch_remove",
            "fciqmc_batch_size", "fciqmc_batch_step", "fciqmc_batch_tune", "fciqmc_batch_profile",
+           "fciqmc_batch_set_persistent",
            "fciqmc_batch_free", "fciqmc_estimate_bytes", "fciqmc_server_create",
            "fciqmc_server_submit", "fciqmc_server_poll", "fciqmc_server_info",
            "fciqmc_server_clock", "fciqmc_server_free", "fciqmc_set_core", "fciqmc_get_core",
@@ -132,6 +133,7 @@ def lib():
         L.fciqmc_batch_step.argtypes = [vp, C.c_int, C.POINTER(StepStats)]
         L.fciqmc_batch_tune.argtypes = [vp, C.c_int, C.POINTER(TuneReport)]
         L.fciqmc_batch_profile.argtypes = [vp, C.c_int, pdbl, C.POINTER(i64)]
+        L.fciqmc_batch_set_persistent.argtypes = [vp, C.c_int]
         L.fciqmc_batch_free.argtypes = [vp]
         L.fciqmc_batch_free.restype = None
         L.fciqmc_estimate_bytes.argtypes = [vp, C.POINTER(Params)]
@@ -482,6 +484,10 @@ def fciqmc_batch_tune(batch: Batch, trial_steps: int = 20) -> dict:
     r = TuneReport()
     _check(lib().fciqmc_batch_tune(batch.handle, int(trial_steps), C.byref(r)))
     return {k: getattr(r, k) for k, _ in TuneReport._fields_}
+
+
+def fciqmc_batch_set_persistent(batch: Batch, on: bool = True):
+    _check(lib().fciqmc_batch_set_persistent(batch.handle, int(bool(on))))
 
 
 def fciqmc_batch_profile(batch: Batch, enable: bool = True):

@@ -47,9 +47,14 @@ def _free(pairs, batch=None):
         F.fciqmc_free_system(sysd)
 
 
-def test_batch_members_follow_their_solo_trajectories():
+@pytest.mark.parametrize("persistent", [True, False])
+def test_batch_members_follow_their_solo_trajectories(persistent):
+    """Every member's trajectory in the batch is its solo trajectory, with
+    the step as one cooperative launch per group (generator chosen per
+    member) or as separate launches per phase."""
     pairs = _pairs(MEMBERS)
     batch = F.fciqmc_batch_create()
+    F.fciqmc_batch_set_persistent(batch, persistent)
     for _, rb, _ in pairs:
         F.fciqmc_batch_add(batch, rb)
     assert F.fciqmc_batch_size(batch) == len(MEMBERS)
@@ -87,7 +92,8 @@ def test_batch_member_matches_oracle():
     _free(others)
 
 
-def test_capacity_growth_inside_a_batch():
+@pytest.mark.parametrize("persistent", [True, False])
+def test_capacity_growth_inside_a_batch(persistent):
     """A member with two buckets and a 100-record spawn buffer overflows and
     replays its steps alone; neither it nor its neighbour changes trajectory."""
     s = inputs.molecule_8o8e()
@@ -96,6 +102,7 @@ def test_capacity_growth_inside_a_batch():
     _, rs = make_gpu_run(s, sysd=sysd, **kw)
     other = _pairs(MEMBERS[2:3])
     batch = F.fciqmc_batch_create()
+    F.fciqmc_batch_set_persistent(batch, persistent)
     F.fciqmc_batch_add(batch, rb)
     F.fciqmc_batch_add(batch, other[0][1])
     bst = F.fciqmc_batch_step(batch, 200)
@@ -112,6 +119,33 @@ def test_capacity_growth_inside_a_batch():
     F.fciqmc_free_run(rs)
     F.fciqmc_free_system(sysd)
     _free(other)
+
+
+def test_single_generator_persistent_batch():
+    """Twelve uniform-generator molecules of 8 to 14 orbitals (the fixed-
+    generator form of the cooperative launch): each member equals its solo
+    run after 300 steps, and the persistent and per-phase forms give the same
+    populations."""
+    members = [(lambda n=n, i=i: inputs.synthetic_molecule(n, n // 2, n // 2, seed=40 + i),
+                dict(tau=0.004, target=5e3 * (1 + i % 4), seed=10 + i))
+               for i, n in enumerate([8, 9, 10, 11, 12, 13, 14, 8, 10, 12, 9, 11])]
+    pairs = _pairs(members)
+    batch = F.fciqmc_batch_create()
+    F.fciqmc_batch_set_persistent(batch, True)
+    for _, rb, _ in pairs:
+        F.fciqmc_batch_add(batch, rb)
+    bst = F.fciqmc_batch_step(batch, 150)
+    F.fciqmc_batch_set_persistent(batch, False)
+    bst += F.fciqmc_batch_step(batch, 50)
+    F.fciqmc_batch_set_persistent(batch, True)
+    bst += F.fciqmc_batch_step(batch, 100)
+    for m, (_, rb, rs) in enumerate(pairs):
+        sst = F.fciqmc_step(rs, 300)
+        for s_ in range(300):
+            assert_same_gpu_stats(bst[s_][m], sst[s_])
+        assert_same_gpu_walkers(rb, rs)
+    assert all(bst[-1][m]["nw"] > 1000 for m in range(len(members)))
+    _free(pairs, batch)
 
 
 def test_tuning_keeps_trajectories():
