@@ -100,6 +100,7 @@ def lib():
         L.orc_run_excitations.restype = i64
         L.orc_run_excitations.argtypes = [vp]
         L.orc_pair_rdm_step.argtypes = [vp, vp, pdbl]
+        L.orc_run_get_proj.argtypes = [vp, pu64, pu64]
         _lib = L
     return _lib
 
@@ -109,7 +110,7 @@ class OrcParams(C.Structure):
                 ("c_min", C.c_double), ("zeta", C.c_double), ("p_single", C.c_double),
                 ("p_opp", C.c_double), ("interval", C.c_int), ("mode", C.c_int),
                 ("gen", C.c_int), ("seed", C.c_uint64), ("replica", C.c_uint64),
-                ("xi", C.c_double), ("adaptive", C.c_int)]
+                ("xi", C.c_double), ("adaptive", C.c_int), ("rechoose", C.c_int)]
 
 
 class OrcStats(C.Structure):
@@ -235,7 +236,7 @@ class System:
 
 DEFAULTS = dict(tau=0.01, target=1e4, n_a=-1.0, c_min=1.0, zeta=0.05, p_single=-1.0,
                 p_opp=-1.0, interval=10, mode=MODE_INTEGER, gen=GEN_UNIFORM, seed=1, replica=0,
-                xi=-1.0, adaptive=0)
+                xi=-1.0, adaptive=0, rechoose=0)
 
 
 class Run:
@@ -349,6 +350,12 @@ class Run:
         """Keep the population each step starts from and every excitation it
         generates (for the replica 2-RDM)."""
         lib().orc_run_log_excitations(self.ptr, int(bool(on)))
+
+    def projection_reference(self):
+        """The determinant the projected energy is taken against (alpha, beta)."""
+        a, b = C.c_uint64(), C.c_uint64()
+        lib().orc_run_get_proj(self.ptr, C.byref(a), C.byref(b))
+        return a.value, b.value
 
     def excitations(self):
         return int(lib().orc_run_excitations(self.ptr))

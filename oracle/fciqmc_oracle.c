@@ -546,6 +546,7 @@ typedef struct {
     uint64_t seed, replica;
     double xi; /* restoring strength of the shift update; < 0: zeta^2/4 */
     int adaptive; /* adaptive shift for non-initiators (Sec. "Adaptive Shift") */
+    int rechoose; /* re-choose the reference when the shift starts varying */
 } orc_params;
 
 typedef struct {
@@ -557,7 +558,8 @@ typedef struct {
 typedef struct {
     const orc_sys *s;
     orc_params p;
-    det_t ref;
+    det_t ref;     /* energy zero: H_00 = <ref|H|ref> */
+    det_t proj;    /* reference of the projected energy (Sec. IV), always an initiator */
     double h00;
     int64_t t;
     double S;
@@ -674,6 +676,7 @@ orc_run *orc_run_create(const orc_sys *s, const orc_params *p, uint64_t ref_a, u
         ref_b = (s->nb == 64) ? ~0ULL : ((1ULL << s->nb) - 1);
     }
     r->ref.a = ref_a; r->ref.b = ref_b;
+    r->proj = r->ref;
     r->h00 = orc_hdiag_det(s, r->ref);
     r->cap = 16;
     r->list = (ent_t *)malloc(sizeof(ent_t) * r->cap);
@@ -1016,6 +1019,12 @@ double orc_rdm_energy(const orc_sys *s, const double *G, double *norm)
 }
 
 void orc_run_log_excitations(orc_run *r, int on) { r->log_exc = on; }
+
+void orc_run_get_proj(const orc_run *r, uint64_t *a, uint64_t *b)
+{
+    *a = r->proj.a;
+    *b = r->proj.b;
+}
 int64_t orc_run_excitations(const orc_run *r) { return r->nexc; }
 
 static double prev_value(const orc_run *r, det_t d)
@@ -1131,7 +1140,7 @@ int orc_run_step(orc_run *r, orc_stats *st)
         int64_t m = integer ? (int64_t)aC : (int64_t)ceil(aC);
         /* initiator: |C_i| above n_a (Sec. I); Reading: the reference always
          * counts as one; a negative n_a switches the approximation off. */
-        int init = (p->n_a < 0.0) || (aC > p->n_a) || det_eq(e->d, r->ref);
+        int init = (p->n_a < 0.0) || (aC > p->n_a) || det_eq(e->d, r->proj);
         int pcore = r->nc > 0 && core_find(r, e->d) >= 0;
         if (pcore) init = 1;
         st->attempts += m;
@@ -1248,7 +1257,7 @@ int orc_run_step(orc_run *r, orc_stats *st)
         double Sx = r->S;
         if (p->adaptive) {
             double ax = fabs(e->v);
-            int ini = (p->n_a < 0.0) || (ax > p->n_a) || det_eq(e->d, r->ref);
+            int ini = (p->n_a < 0.0) || (ax > p->n_a) || det_eq(e->d, r->proj);
             double f = 1.0;
             if (!ini && all_w[x] > 0) {
                 f = (double)acc_w[x] / (double)all_w[x];
@@ -1375,10 +1384,10 @@ int orc_run_step(orc_run *r, orc_stats *st)
     for (int64_t x = 0; x < r->n; ++x) {
         const ent_t *e = &r->list[x];
         nw = nw + fabs(e->v);
-        if (det_eq(e->d, r->ref)) { nref = e->v; continue; }
-        int lvl = __builtin_popcountll(e->d.a ^ r->ref.a) + __builtin_popcountll(e->d.b ^ r->ref.b);
+        if (det_eq(e->d, r->proj)) { nref = e->v; continue; }
+        int lvl = __builtin_popcountll(e->d.a ^ r->proj.a) + __builtin_popcountll(e->d.b ^ r->proj.b);
         if (lvl == 2 || lvl == 4) {
-            double h = orc_hij_det(s, r->ref, e->d);
+            double h = orc_hij_det(s, r->proj, e->d);
             double c = h * e->v;
             en = en + c;
         }
@@ -1396,6 +1405,7 @@ int orc_run_step(orc_run *r, orc_stats *st)
      * leaves S unchanged. */
     int64_t T = r->t;
     int64_t A = (int64_t)p->interval;
+    int was_vary = r->vary;
     if (!r->vary) {
         if (nw >= p->target) {
             r->vary = 1;
@@ -1426,6 +1436,20 @@ int orc_run_step(orc_run *r, orc_stats *st)
         r->nw_last = nw;
     }
     r->nw_ring[T % (A + 1)] = nw;
+
+    /* Reference of the projected energy (Sec. IV: "an appropriate reference
+     * determinant").  Reading: with re-choice on, when the shift starts
+     * varying the most populated determinant becomes the reference for the
+     * following steps (largest |C|; ties: ascending alpha, then beta
+     * string); H_00 stays the energy zero of the diagonal and the shift. */
+    if (p->rechoose && !was_vary && r->vary && r->n > 0) {
+        int64_t best = 0;
+        for (int64_t x = 1; x < r->n; ++x) {
+            double ax = fabs(r->list[x].v), ab = fabs(r->list[best].v);
+            if (ax > ab) best = x;  /* the list is ascending: the first of equals wins */
+        }
+        r->proj = r->list[best].d;
+    }
 
     st->nw = nw; st->nref = nref; st->enum_ = en; st->shift = r->S;
     st->ndets = r->n; st->vary = r->vary;
@@ -1908,10 +1932,10 @@ void orc_run_estimate(const orc_run *r, double *nw_out, double *nref_out, double
     for (int64_t x = 0; x < r->n; ++x) {
         const ent_t *e = &r->list[x];
         nw = nw + fabs(e->v);
-        if (det_eq(e->d, r->ref)) { nref = e->v; continue; }
-        int lvl = __builtin_popcountll(e->d.a ^ r->ref.a) + __builtin_popcountll(e->d.b ^ r->ref.b);
+        if (det_eq(e->d, r->proj)) { nref = e->v; continue; }
+        int lvl = __builtin_popcountll(e->d.a ^ r->proj.a) + __builtin_popcountll(e->d.b ^ r->proj.b);
         if (lvl == 2 || lvl == 4) {
-            double h = orc_hij_det(r->s, r->ref, e->d);
+            double h = orc_hij_det(r->s, r->proj, e->d);
             double c = h * e->v;
             en = en + c;
         }

@@ -980,3 +980,43 @@ def test_rdm_step_expectation(oracle_mod, gen, mode):
     off = ~np.isclose(want, 0.0) & (se > 0)
     z2 = np.abs(2.0 * mean - want)[off] / np.maximum(2.0 * se[off], 1e-9)
     assert np.max(z2) > 5.0
+
+
+def test_rechosen_reference_gives_the_exact_energy(oracle_mod):
+    """Started from a poor reference (a doubly excited determinant of small
+    weight), with re-choice on: when the shift starts varying the projection
+    reference becomes the most populated determinant (checked against the
+    population: largest |C|, ties to the smallest (alpha, beta)), and the
+    projected energy H_PP + <sum_j H_Pj C_j> / <C_P> equals exact
+    diagonalisation within its error bar, with H_00 of the original
+    reference still the energy zero of the shift."""
+    s = inputs.synthetic_molecule(6, 3, 3, seed=14)
+    osys = oracle_mod.System.from_inputs(s)
+    dets = brute.basis(6, 3, 3)
+    H = brute.oracle_dense_h(osys, dets)
+    w, V = np.linalg.eigh(H)
+    e0 = w[0]
+    # the poor reference: the basis determinant of smallest ground-state weight
+    bad = dets[int(np.argmin(np.abs(V[:, 0])))]
+    run = oracle_mod.Run(osys, ref=bad, tau=0.01, target=3000.0, seed=2, zeta=0.1, rechoose=1)
+    run.set_walkers([bad[0]], [bad[1]], [10.0])
+    st = []
+    while not (st and st[-1]["vary"]):
+        st += run.step(1)
+    a, b, v, _ = run.get_walkers()
+    order = sorted(range(len(v)), key=lambda i: (-abs(v[i]), int(a[i]), int(b[i])))
+    want = (int(a[order[0]]), int(b[order[0]]))
+    assert run.projection_reference() == want != bad
+    st = []
+    for _ in range(12):
+        st += run.step(1000)
+    keep = st[2000:]
+    En = np.array([x["enum_"] for x in keep])
+    Nr = np.array([x["nref"] for x in keep])
+    hpp = osys.hdiag(*want)
+    blk = len(En) // 32
+    rs = [En[i * blk:(i + 1) * blk].mean() / Nr[i * blk:(i + 1) * blk].mean() for i in range(32)]
+    er = np.std(rs, ddof=1) / np.sqrt(32)
+    assert abs(hpp + En.mean() / Nr.mean() - e0) < 4 * er + 1e-3, (hpp + En.mean() / Nr.mean(), e0, er)
+    ms, es = brute.blocked_error(np.array([x["shift"] for x in keep]))
+    assert abs(run.h00 + ms - e0) < 4 * es + 1e-3
