@@ -103,6 +103,14 @@ typedef struct fciqmc_params {
                                |H_ij|/|H_jj - E_0| of their spawns this step, E_0 the shift;
                                f_i = 1 without spawns); runs with it step alone (no
                                batch) and take no deterministic space                      */
+    int ref_rechoose;       /* 1: ceil(1/tau) steps after the shift starts varying, the most
+                               populated determinant (ties: ascending alpha, then beta)
+                               becomes the reference of the projected energy (Sec. IV: an
+                               appropriate reference determinant) and the determinant that
+                               always counts as an initiator, for the following steps (the
+                               energy report uses only those); H_00 of ref_alpha/ref_beta
+                               stays the energy zero of the diagonal and the shift.  Not with
+                               replica pairs (EINVAL at fciqmc_pair_create)                   */
 } fciqmc_params;
 
 /* Per-step diagnostics (after the step). */
@@ -110,9 +118,10 @@ typedef struct fciqmc_step_stats {
     int64_t iter;           /* number of completed steps                                  */
     double nw;              /* walker number N_w = sum |C_i|                              */
     double nref;            /* C_ref, the reference coefficient                           */
-    double enum_;           /* sum_{j != ref} H_ref,j C_j                                 */
+    double enum_;           /* sum_{j != P} H_Pj C_j (P: see e_proj)                      */
     double shift;           /* S after this step's update (relative to H_00)              */
-    double e_proj;          /* H_00 + e_core + enum_/nref (absolute)                      */
+    double e_proj;          /* H_PP + e_core + enum_/nref (absolute; P the reference of the
+                               projected energy, the initial reference unless re-chosen)   */
     int64_t ndets;          /* occupied determinants                                      */
     int64_t attempts;       /* spawn attempts made in this step                           */
     int64_t spawns;         /* spawn records emitted in this step                         */
@@ -196,6 +205,9 @@ int fciqmc_set_core(fciqmc_run *run, int64_t n_core, int64_t *n_out);
  * capacity determinants as (alpha, beta) mask pairs, ascending. */
 int fciqmc_get_core(const fciqmc_run *run, uint64_t *dets, int64_t capacity, int64_t *n_out,
                     int64_t *nnz_out);
+/* The current reference of the projected energy (alpha, beta masks) and its
+ * H_PP + e_core (any output may be NULL). */
+int fciqmc_get_reference(const fciqmc_run *run, uint64_t *alpha, uint64_t *beta, double *e_ref);
 int fciqmc_get_checkpoint(const fciqmc_run *run, fciqmc_checkpoint *out);
 int fciqmc_set_checkpoint(fciqmc_run *run, const fciqmc_checkpoint *in);
 

@@ -560,6 +560,7 @@ typedef struct {
     orc_params p;
     det_t ref;     /* energy zero: H_00 = <ref|H|ref> */
     det_t proj;    /* reference of the projected energy (Sec. IV), always an initiator */
+    int64_t t_vary; /* step at which the shift started varying (-1: not yet) */
     double h00;
     int64_t t;
     double S;
@@ -677,6 +678,7 @@ orc_run *orc_run_create(const orc_sys *s, const orc_params *p, uint64_t ref_a, u
     }
     r->ref.a = ref_a; r->ref.b = ref_b;
     r->proj = r->ref;
+    r->t_vary = -1;
     r->h00 = orc_hdiag_det(s, r->ref);
     r->cap = 16;
     r->list = (ent_t *)malloc(sizeof(ent_t) * r->cap);
@@ -1405,7 +1407,6 @@ int orc_run_step(orc_run *r, orc_stats *st)
      * leaves S unchanged. */
     int64_t T = r->t;
     int64_t A = (int64_t)p->interval;
-    int was_vary = r->vary;
     if (!r->vary) {
         if (nw >= p->target) {
             r->vary = 1;
@@ -1421,6 +1422,7 @@ int orc_run_step(orc_run *r, orc_stats *st)
             }
             r->t_last = T;
             r->nw_last = nw;
+            r->t_vary = T;
         }
     } else if (T - r->t_last == A && nw > 0.0) {
         double at = (double)p->interval * p->tau;
@@ -1437,12 +1439,13 @@ int orc_run_step(orc_run *r, orc_stats *st)
     }
     r->nw_ring[T % (A + 1)] = nw;
 
-    /* Reference of the projected energy (Sec. IV: "an appropriate reference
-     * determinant").  Reading: with re-choice on, when the shift starts
-     * varying the most populated determinant becomes the reference for the
-     * following steps (largest |C|; ties: ascending alpha, then beta
-     * string); H_00 stays the energy zero of the diagonal and the shift. */
-    if (p->rechoose && !was_vary && r->vary && r->n > 0) {
+    /* Reference of the projected energy (Sec. IV: an appropriate reference
+     * determinant).  Reading: with re-choice on, once the population has
+     * relaxed for ceil(1/dtau) steps after the shift started varying, the
+     * most populated determinant becomes the reference for the following
+     * steps (largest |C|; ties: ascending alpha, then beta string); H_00
+     * stays the energy zero of the diagonal and the shift. */
+    if (p->rechoose && r->t_vary >= 0 && T == r->t_vary + (int64_t)ceil(1.0 / p->tau) && r->n > 0) {
         int64_t best = 0;
         for (int64_t x = 1; x < r->n; ++x) {
             double ax = fabs(r->list[x].v), ab = fabs(r->list[best].v);

@@ -245,6 +245,10 @@ struct EngineBase {
     // replica 2-RDM: every excitation of the last step (RdmRec<W>, rdm_count
     // attempt slots)
     virtual int set_rdm(bool on) = 0;
+    // reference of the projected energy and initiator rule (the energy
+    // zero H_00 is unchanged); the most populated determinant of the store
+    virtual int set_reference(uint64_t a, uint64_t b) = 0;
+    virtual int most_populated(uint64_t& a, uint64_t& b, double& v) = 0;
     virtual const void* rdm_records() const = 0;
     virtual int64_t rdm_count() const = 0;
 };
@@ -855,6 +859,36 @@ template <int W, class V> struct Engine : EngineBase {
         CHECK(dalloc(arena, &rej, (size_t)cap_rej));
         return alloc_rej_index();
     }
+    int set_reference(uint64_t a, uint64_t b) override {
+        CHECK(discard_pending());  // a queued spawn applied the old reference's initiator rule
+        rs.ref_a = a;
+        rs.ref_b = b;
+        return 0;
+    }
+    int most_populated(uint64_t& a, uint64_t& b, double& v) override {
+        CHECK(refuse_if_broken());
+        const int G = std::min(B, 1024);
+        Arena tmp;
+        double* bv = nullptr;
+        uint64_t* bk = nullptr;
+        CHECK(dalloc(tmp, &bv, (size_t)G));
+        CHECK(dalloc(tmp, &bk, (size_t)2 * G));
+        hipLaunchKernelGGL((k_most_populated<W, V>), dim3(G), dim3(kThreads), 0, stream, st[cur], R, B, bv, bk);
+        HIP_OK(hipGetLastError());
+        std::vector<double> hv((size_t)G);
+        std::vector<uint64_t> hk((size_t)2 * G);
+        HIP_OK(hipMemcpyAsync(hv.data(), bv, sizeof(double) * G, hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipMemcpyAsync(hk.data(), bk, sizeof(uint64_t) * 2 * G, hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipStreamSynchronize(stream));
+        v = -1.0;
+        a = b = ~0ULL;
+        for (int g = 0; g < G; ++g) {
+            const double x = hv[(size_t)g];
+            const uint64_t xa = hk[(size_t)(2 * g)], xb = hk[(size_t)(2 * g + 1)];
+            if (x > v || (x == v && (xa < a || (xa == a && xb < b)))) { v = x; a = xa; b = xb; }
+        }
+        return 0;
+    }
     int set_rdm(bool on) override {
         CHECK(discard_pending());  // a queued spawn would not log its draws
         rdm_on = on;
@@ -1110,6 +1144,10 @@ struct fciqmc_run {
     std::unique_ptr<EngineBase> eng;
     double h00 = 0.0;
     uint64_t ref_a = 0, ref_b = 0;
+    // reference of the projected energy (re-chosen if asked) and
+    // H_PP - H_00 of it
+    uint64_t proj_a = 0, proj_b = 0;
+    double hproj = 0.0;
     int64_t t = 0;
     double S = 0.0;
     int vary = 0;
@@ -1123,6 +1161,7 @@ struct fciqmc_run {
     fciqmc_batch* batch = nullptr;  // set while the run steps inside a batch
     int batch_slot = -1;            // its position among the batch's members
     fciqmc_pair* pair = nullptr;    // set while the run is one replica of a pair
+    bool rechoose_pending = false;  // the reference is re-chosen before the next step
     ~fciqmc_run() {
         eng.reset();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -1176,6 +1215,31 @@ static void shift_update(fciqmc_run* r, double nw) {
 
 // Advance the run's clock by the completed step: shift update and the
 // recorded per-step estimators.
+static int device_diag(const fciqmc_system* sys, hipStream_t stream, uint64_t a, uint64_t b, double* out);
+
+// Reference of the projected energy (Sec. IV).  Reading: with re-choice on,
+// once the population has relaxed for ceil(1/dtau) steps after the shift
+// started varying, the most populated determinant takes over for the
+// following steps (ties: ascending alpha, then beta); H_00 stays the energy
+// zero.
+static int rechoose_reference(fciqmc_run* run) {
+    uint64_t a = 0, b = 0;
+    double v = 0.0;
+    CHECK(run->eng->most_populated(a, b, v));
+    if (v <= 0.0 || (a == run->proj_a && b == run->proj_b)) return 0;
+    double hpp = 0.0;
+    CHECK(device_diag(run->sys, run->eng->get_stream(), a, b, &hpp));
+    CHECK(run->eng->set_reference(a, b));
+    run->proj_a = a;
+    run->proj_b = b;
+    run->hproj = hpp - run->h00;
+    return 0;
+}
+
+static int64_t rechoose_step(const fciqmc_run* run) {
+    return run->t_vary + (int64_t)std::ceil(1.0 / run->p.tau);
+}
+
 static void record_step(fciqmc_run* run, const Ctl& c, int retries, int64_t attempts, fciqmc_step_stats* out) {
     run->t += 1;
     shift_update(run, c.nw);
@@ -1187,7 +1251,7 @@ static void record_step(fciqmc_run* run, const Ctl& c, int retries, int64_t atte
     s.shift = run->S;
     const double eref = run->h00 + run->sys->e_core;
     const double q = c.enum_ / c.nref;
-    s.e_proj = eref + q;
+    s.e_proj = (eref + run->hproj) + q;
     s.ndets = c.ndets;
     s.attempts = attempts;
     s.spawns = c.nrec_out;
@@ -1195,6 +1259,7 @@ static void record_step(fciqmc_run* run, const Ctl& c, int retries, int64_t atte
     s.retries = retries;
     run->hist.push_back(s);
     if (out) *out = s;
+    if (run->p.ref_rechoose && run->t_vary >= 0 && run->t == rechoose_step(run)) run->rechoose_pending = true;
 }
 
 // ---------------------------------------------------------------------------
@@ -1278,6 +1343,10 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
         ftot = 0;
         flds = 0;
         for (size_t i = 0; i < n; ++i) {
+            if (runs[i]->rechoose_pending) {
+                CHECK(rechoose_reference(runs[i]));
+                runs[i]->rechoose_pending = false;
+            }
             CHECK(eng(i)->batch_prepare(runs[i]->t, runs[i]->S, hi[i], chunks[i]));
             bf[i] = btot;
             btot += eng(i)->B;
@@ -1730,6 +1799,7 @@ int fciqmc_init(const fciqmc_system* csys, const fciqmc_params* p, void* stream,
     }
     if (!valid_det(sys, ra, rb)) return fail(FCIQMC_EINVAL, "reference determinant is not a valid determinant");
     r->ref_a = ra; r->ref_b = rb;
+    r->proj_a = ra; r->proj_b = rb;
     if (p->excitgen == FCIQMC_GEN_PCHB) CHECK(build_pchb(sys, r->stream));
     CHECK(device_diag(sys, r->stream, ra, rb, &r->h00));
     RunScalars rs{};
@@ -1995,6 +2065,10 @@ int fciqmc_step(fciqmc_run* run, int n_steps, fciqmc_step_stats* stats) {
         Ctl c{};
         int retries = 0;
         int64_t attempts = 0;
+        if (run->rechoose_pending) {
+            CHECK(rechoose_reference(run));
+            run->rechoose_pending = false;
+        }
         CHECK(run->eng->step_once(run->t, run->S, c, retries, attempts));
         record_step(run, c, retries, attempts, stats ? stats + i : nullptr);
     }
@@ -2071,7 +2145,8 @@ int fciqmc_energy(const fciqmc_run* run, fciqmc_energy_report* out) {
     const int64_t after = run->t - run->t_vary;
     int64_t equil = run->p.equil_steps;
     if (equil < 0) equil = std::max<int64_t>((int64_t)std::ceil(1.0 / run->p.tau), after / 5);
-    const int64_t first = run->t_vary + equil;  // first step number used
+    int64_t first = run->t_vary + equil;  // first step number used
+    if (run->p.ref_rechoose) first = std::max(first, rechoose_step(run));  // one reference throughout
     std::vector<double> S, E, Nr;
     for (const auto& h : run->hist)
         if (h.iter > first) { S.push_back(h.shift); E.push_back(h.enum_); Nr.push_back(h.nref); }
@@ -2084,7 +2159,7 @@ int fciqmc_energy(const fciqmc_run* run, fciqmc_energy_report* out) {
     blocking(E, Nr, me, dummy, mn, r, er);
     out->shift = eref + ms;
     out->shift_err = es;
-    out->e_proj = eref + r;
+    out->e_proj = (eref + run->hproj) + r;
     out->e_proj_err = er;
     out->converged = std::fabs(out->shift - out->e_proj) < run->p.conv_tol && es < run->p.conv_tol &&
                      er < run->p.conv_tol;
@@ -2152,6 +2227,14 @@ int fciqmc_get_core(const fciqmc_run* run, uint64_t* dets, int64_t capacity, int
         const int64_t m = std::min(n, capacity);
         std::copy(c.begin(), c.begin() + 2 * m, dets);
     }
+    return 0;
+}
+
+int fciqmc_get_reference(const fciqmc_run* run, uint64_t* alpha, uint64_t* beta, double* e_ref) {
+    if (!run) return fail(FCIQMC_EINVAL, "null argument");
+    if (alpha) *alpha = run->proj_a;
+    if (beta) *beta = run->proj_b;
+    if (e_ref) *e_ref = (run->h00 + run->sys->e_core) + run->hproj;
     return 0;
 }
 
@@ -2518,6 +2601,8 @@ int fciqmc_pair_create(fciqmc_run* r1, fciqmc_run* r2, fciqmc_pair** out) {
     if (r1->sys != r2->sys || r1->eng->kind() != r2->eng->kind() || r1->p.tau != r2->p.tau ||
         r1->ref_a != r2->ref_a || r1->ref_b != r2->ref_b)
         return fail(FCIQMC_EINVAL, "replicas need the same system, layout, time step and reference");
+    if (r1->p.ref_rechoose || r2->p.ref_rechoose)
+        return fail(FCIQMC_EINVAL, "replicas keep one reference: no re-choice (ref_rechoose)");
     if (r1->p.seed == r2->p.seed && r1->p.replica_id == r2->p.replica_id)
         return fail(FCIQMC_EINVAL, "replicas need different random streams (replica_id or seed)");
     std::unique_ptr<fciqmc_pair> p(new fciqmc_pair());

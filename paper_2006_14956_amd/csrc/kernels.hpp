@@ -1519,6 +1519,54 @@ __global__ __launch_bounds__(kThreads, 6) void k_batch_step(const Inst<W, V>* __
     }
 }
 
+// Most populated determinant of a store: largest |C|, ties to the smallest
+// (alpha, beta) pair; one candidate per workgroup (value, alpha, beta),
+// reduced on the host.  The order of comparison makes the winner unique.
+__device__ __forceinline__ bool more_populated(double v, uint64_t a, uint64_t b, double w, uint64_t c, uint64_t d) {
+    if (v != w) return v > w;
+    if (a != c) return a < c;
+    return b < d;
+}
+
+template <int W, class V>
+__global__ __launch_bounds__(kThreads) void k_most_populated(Store<V> st, int R, int B, double* __restrict__ bv,
+                                                             uint64_t* __restrict__ bk) {
+    __shared__ double sv[kThreads];
+    __shared__ uint64_t sa[kThreads], sb[kThreads];
+    double v = -1.0;
+    uint64_t a = ~0ULL, b = ~0ULL;
+    for (int bk_ = blockIdx.x; bk_ < B; bk_ += gridDim.x) {
+        const int cnt = st.count[bk_];
+        for (int e = threadIdx.x; e < cnt; e += kThreads) {
+            const int64_t x = (int64_t)bk_ * R + e;
+            const Key<W> key = load_key<W>(st.keys + x * W);
+            const double av = vabs(st.vals[x]);
+            const uint64_t ka = key_alpha<W>(key), kb = key_beta<W>(key);
+            if (more_populated(av, ka, kb, v, a, b)) { v = av; a = ka; b = kb; }
+        }
+    }
+    sv[threadIdx.x] = v;
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            const int j = threadIdx.x + o;
+            if (more_populated(sv[j], sa[j], sb[j], sv[threadIdx.x], sa[threadIdx.x], sb[threadIdx.x])) {
+                sv[threadIdx.x] = sv[j];
+                sa[threadIdx.x] = sa[j];
+                sb[threadIdx.x] = sb[j];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        bv[blockIdx.x] = sv[0];
+        bk[2 * blockIdx.x] = sa[0];
+        bk[2 * blockIdx.x + 1] = sb[0];
+    }
+}
+
 // Copy the store to flat arrays (offsets from a count scan).
 template <int W, class V>
 __global__ __launch_bounds__(kThreads) void k_extract(Store<V> st, int R, const int64_t* __restrict__ off,

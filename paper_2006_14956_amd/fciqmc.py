@@ -35,7 +35,8 @@ class Params(C.Structure):
                 ("shift_interval", C.c_int), ("ref_alpha", C.c_uint64), ("ref_beta", C.c_uint64),
                 ("max_dets", C.c_int64), ("max_spawns", C.c_int64),
                 ("hbm_budget_bytes", C.c_int64), ("buckets_log2", C.c_int), ("det_words", C.c_int),
-                ("conv_tol", C.c_double), ("equil_steps", C.c_int), ("adaptive_shift", C.c_int)]
+                ("conv_tol", C.c_double), ("equil_steps", C.c_int), ("adaptive_shift", C.c_int),
+                ("ref_rechoose", C.c_int)]
 
 
 class StepStats(C.Structure):
@@ -74,6 +75,7 @@ class TuneReport(C.Structure):
 
 EXPORTS = ["fciqmc_params_default", "fciqmc_load_integrals", "fciqmc_init", "fciqmc_step",
            "fciqmc_energy", "fciqmc_get_walkers", "fciqmc_set_walkers", "fciqmc_get_checkpoint",
+           "fciqmc_get_reference",
            "fciqmc_set_checkpoint", "fciqmc_matrix_elements", "fciqmc_matrix_elements_noalloc",
            "fciqmc_pchb_row",
            "fciqmc_run_device_bytes",
@@ -119,6 +121,7 @@ def lib():
         L.fciqmc_set_core.argtypes = [vp, i64, C.POINTER(i64)]
         L.fciqmc_get_core.argtypes = [vp, pu64, i64, C.POINTER(i64), C.POINTER(i64)]
         L.fciqmc_get_checkpoint.argtypes = [vp, C.POINTER(Checkpoint)]
+        L.fciqmc_get_reference.argtypes = [vp, C.POINTER(u64), C.POINTER(u64), pdbl]
         L.fciqmc_set_checkpoint.argtypes = [vp, C.POINTER(Checkpoint)]
         L.fciqmc_matrix_elements.argtypes = [vp, pu64, pu64, i64, pdbl]
         L.fciqmc_matrix_elements_noalloc.argtypes = [vp, pu64, pu64, i64, pdbl]
@@ -324,6 +327,13 @@ def fciqmc_pair_rdm(pair: Pair, matrix: bool = True) -> dict:
 
 def fciqmc_pair_free(pair: Pair):
     pair.free()
+
+
+def fciqmc_get_reference(run: Run):
+    """(alpha, beta, H_PP + e_core) of the projected energy's reference."""
+    a, b, e = C.c_uint64(), C.c_uint64(), C.c_double()
+    _check(lib().fciqmc_get_reference(run.handle, C.byref(a), C.byref(b), C.byref(e)))
+    return a.value, b.value, e.value
 
 
 def fciqmc_energy(run: Run) -> dict:

@@ -21,39 +21,42 @@ def ref_of(s):
 def make_gpu_run(s, tau, target, gen="uniform", n_a=-1.0, mode="integer", seed=1, zeta=0.05,
                  interval=10, c_min=1.0, det_words=0, n_initial=10.0, p_single=-1.0, p_opp=-1.0,
                  buckets_log2=0, max_spawns=0, stream=None, replica=0, sysd=None, max_dets=0,
-                 adaptive=0):
+                 adaptive=0, rechoose=0, ref=None):
     """(system handle, gpu_run) started from n_initial walkers on the reference."""
     g, _ = GEN[gen]
     m = F.MODE_INTEGER if mode == "integer" else F.MODE_REAL
     if sysd is None:
         sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
-    ra, rb = ref_of(s)
+    ra, rb = ref if ref is not None else ref_of(s)
     p = F.fciqmc_params_default(tau=tau, walker_target=target, initiator_na=n_a, mode=m,
                                 excitgen=g, seed=seed, shift_damping=zeta, shift_interval=interval,
                                 c_min=c_min, det_words=det_words, n_initial=n_initial,
                                 ref_alpha=ra, ref_beta=rb, p_single=p_single, p_opp=p_opp,
                                 buckets_log2=buckets_log2, max_spawns=max_spawns,
-                                replica_id=replica, max_dets=max_dets, adaptive_shift=adaptive)
+                                replica_id=replica, max_dets=max_dets, adaptive_shift=adaptive,
+                                ref_rechoose=rechoose)
     return sysd, F.fciqmc_init(sysd, p, stream=stream)
 
 
 def make_pair(s, tau, target, gen="uniform", n_a=-1.0, mode="integer", seed=1, zeta=0.05,
               interval=10, c_min=1.0, det_words=0, n_initial=10.0, p_single=-1.0, p_opp=-1.0,
-              buckets_log2=0, max_spawns=0, stream=None, replica=0, max_dets=0, adaptive=0):
+              buckets_log2=0, max_spawns=0, stream=None, replica=0, max_dets=0, adaptive=0, rechoose=0,
+              ref=None):
     """(gpu_run, oracle_run) started from n_initial walkers on the reference."""
     _, o = GEN[gen]
     sysd, run = make_gpu_run(s, tau, target, gen=gen, n_a=n_a, mode=mode, seed=seed, zeta=zeta,
                              interval=interval, c_min=c_min, det_words=det_words,
                              n_initial=n_initial, p_single=p_single, p_opp=p_opp,
                              buckets_log2=buckets_log2, max_spawns=max_spawns, stream=stream,
-                             replica=replica, max_dets=max_dets, adaptive=adaptive)
-    ra, rb = ref_of(s)
+                             replica=replica, max_dets=max_dets, adaptive=adaptive, rechoose=rechoose,
+                             ref=ref)
+    ra, rb = ref if ref is not None else ref_of(s)
     words = det_words if det_words else (1 if s.n_orb <= 32 else 2)
     osys = oracle.System.from_inputs(s, words=words)
     orun = oracle.Run(osys, ref=(ra, rb), tau=tau, target=target, n_a=n_a, c_min=c_min,
                       zeta=zeta, p_single=p_single, p_opp=p_opp, interval=interval,
                       mode=oracle.MODE_INTEGER if mode == "integer" else oracle.MODE_REAL,
-                      gen=o, seed=seed, replica=replica, adaptive=adaptive)
+                      gen=o, seed=seed, replica=replica, adaptive=adaptive, rechoose=rechoose)
     orun.set_walkers([ra], [rb], [n_initial])
     return sysd, run, orun
 

@@ -983,13 +983,14 @@ def test_rdm_step_expectation(oracle_mod, gen, mode):
 
 
 def test_rechosen_reference_gives_the_exact_energy(oracle_mod):
-    """Started from a poor reference (a doubly excited determinant of small
-    weight), with re-choice on: when the shift starts varying the projection
-    reference becomes the most populated determinant (checked against the
-    population: largest |C|, ties to the smallest (alpha, beta)), and the
-    projected energy H_PP + <sum_j H_Pj C_j> / <C_P> equals exact
-    diagonalisation within its error bar, with H_00 of the original
-    reference still the energy zero of the shift."""
+    """Started from a poor reference (the determinant of smallest
+    ground-state weight), with re-choice on: 1/dtau steps after the shift
+    starts varying the projection reference becomes the most populated
+    determinant (checked against the population: largest |C|, ties to the
+    smallest (alpha, beta)), and the projected energy
+    H_PP + <sum_j H_Pj C_j> / <C_P> equals exact diagonalisation within its
+    error bar, with H_00 of the original reference still the energy zero of
+    the shift."""
     s = inputs.synthetic_molecule(6, 3, 3, seed=14)
     osys = oracle_mod.System.from_inputs(s)
     dets = brute.basis(6, 3, 3)
@@ -1003,6 +1004,9 @@ def test_rechosen_reference_gives_the_exact_energy(oracle_mod):
     st = []
     while not (st and st[-1]["vary"]):
         st += run.step(1)
+    run.step(99)
+    assert run.projection_reference() == bad
+    run.step(1)  # the 100th step after the shift started varying (dtau = 0.01)
     a, b, v, _ = run.get_walkers()
     order = sorted(range(len(v)), key=lambda i: (-abs(v[i]), int(a[i]), int(b[i])))
     want = (int(a[order[0]]), int(b[order[0]]))
