@@ -599,7 +599,7 @@ def measure_pt2(F, np, torch, steps):
     paired = (time.perf_counter() - t0) / steps
     rep = F.fciqmc_pair_pt2(pair)
     # the variational energy the correction applies to: the replica 2-RDM
-    # sampled over as many further paired steps (Sec. "Reduced density matrices")
+    # sampled over as many further paired steps (Sec. "Density matrix sampling and pure expectation values")
     F.fciqmc_pair_rdm_enable(pair, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -161,9 +161,18 @@ int fciqmc_load_integrals(int n_orb, int n_alpha, int n_beta, double e_core,
                           const double *h1, const double *eri_packed, int64_t eri_len,
                           fciqmc_system **out);
 
-/* Create a walker population: n_initial walkers on the reference.  stream:
- * a hipStream_t to launch on (e.g. torch.cuda.current_stream().cuda_stream),
- * NULL for a library-owned stream.  Builds PCHB tables on first use. */
+/* Create a walker population: n_initial walkers on the reference (the
+ * starting determinant fixes the m_s sector of the walk, Sec. "Symmetries
+ * and spin-adapted FCIQMC"; Reading: the paper gives no initial state
+ * beyond that, so the reference carries the first walkers and the
+ * population grows until the shift controls it, Sec. I).  stream: a
+ * hipStream_t to launch on (e.g.
+ * torch.cuda.current_stream().cuda_stream), NULL for a library-owned stream.
+ * Builds PCHB tables on first use.  EINVAL for a non-positive tau or
+ * n_initial, an unknown mode or generator, a reference that is not a
+ * determinant of the system, a lattice generator on a system with
+ * off-site two-electron integrals, or a layout too narrow for n_orb;
+ * ENOMEM if the initial store does not fit hbm_budget_bytes. */
 int fciqmc_init(const fciqmc_system *sys, const fciqmc_params *p, void *stream,
                 fciqmc_run **out);
 
@@ -173,7 +182,13 @@ int fciqmc_init(const fciqmc_system *sys, const fciqmc_params *p, void *stream,
  * buffers and replay the step, which reproduces it exactly. */
 int fciqmc_step(fciqmc_run *run, int n_steps, fciqmc_step_stats *stats);
 
-/* Blocking analysis of the recorded per-step estimators (host only). */
+/* Energies from the recorded per-step estimators (host only): the shift
+ * (Sec. I) and the projected energy of Eq. (proje) (Sec. IV) as a ratio of
+ * means over the steps after the shift started varying, less an
+ * equilibration of max(equil_steps or ceil(1/tau), 20 % of them).  Reading:
+ * the paper prints results with error bars without the analysis; errors
+ * are Flyvbjerg-Petersen blocking estimates (delta method for the ratio),
+ * taken at the plateau of the blocking curve. */
 int fciqmc_energy(const fciqmc_run *run, fciqmc_energy_report *out);
 
 /* Diagnostics / checkpoint.  dets: host, 2 uint64 per determinant (alpha,
@@ -410,9 +425,9 @@ int fciqmc_pair_step(fciqmc_pair *pair, int n_steps, fciqmc_step_stats *stats1,
                      fciqmc_step_stats *stats2, double *de2);
 int fciqmc_pair_pt2(const fciqmc_pair *pair, int64_t skip, double *mean, double *err, int64_t *n);
 
-/* ---- Replica 2-RDM and the variational energy (Sec. "Reduced density
- * matrices", Eq. (FCI2RDM); Sec. "Perturbative correction": the energy the
- * PT2 correction corrects) ----
+/* ---- Replica 2-RDM and the variational energy (Sec. "Density matrix
+ * sampling and pure expectation values", Eq. (FCI2RDM); Sec. "Perturbative
+ * correction": the energy the PT2 correction corrects) ----
  * Gamma_{kl,mn} = sum_{i,j} C_i^1 C_j^2 <D_i| a+_k a+_l a_n a_m |D_j> over
  * spin orbitals (canonical index: alpha orbital p -> p, beta p -> N + p),
  * kept for k < l, m < n: pair index P(k,l) = k(2K-k-1)/2 + l-k-1 of the

@@ -588,9 +588,9 @@ typedef struct {
     det_t *f_det;
     double *f_val;
     int64_t nf;
-    /* 2-RDM sampling (Sec. "Reduced density matrices"): the population the
-     * last step started from, and every non-null excitation it generated
-     * with the weight C_i / (m_i p_gen) */
+    /* 2-RDM sampling (Sec. "Density matrix sampling and pure expectation
+     * values"): the population the last step started from, and every
+     * non-null excitation it generated with the weight C_i / (m_i p_gen) */
     int log_exc;
     ent_t *prev;
     int64_t nprev;
@@ -886,8 +886,8 @@ double orc_pair_overlap(const orc_run *r1, const orc_run *r2)
 }
 
 /* ------------------------------------------------------------------------- */
-/* Two-body reduced density matrix (Sec. "Reduced density matrices", Eq.      */
-/* (FCI2RDM)):                                                                 */
+/* Two-body reduced density matrix (Sec. "Density matrix sampling and pure   */
+/* expectation values", Eq. (FCI2RDM)):                                        */
 /*   Gamma_{kl,mn} = sum_{i,j} C_i^A C_j^B <D_i| a+_k a+_l a_n a_m |D_j>      */
 /* over spin orbitals in canonical order.  It is antisymmetric in (k,l) and  */
 /* in (m,n), so only k < l, m < n are kept: pair index                        */
@@ -1035,9 +1035,9 @@ static double prev_value(const orc_run *r, det_t d)
     return at >= 0 ? r->prev[at].v : 0.0;
 }
 
-/* One paired step's sample of the replica 2-RDM (Sec. "Reduced density
- * matrices": the replica trick makes the estimate bilinear in two
- * independent populations), added to G:
+/* One paired step's sample of the replica 2-RDM (Sec. "Density matrix
+ * sampling and pure expectation values": the replica trick makes the
+ * estimate bilinear in two independent populations), added to G:
  *  - the diagonal terms i = j exactly: C_i^1 C_i^2 over the determinants
  *    occupied in both populations the step started from;
  *  - the off-diagonal terms from the excitations the step generated: an

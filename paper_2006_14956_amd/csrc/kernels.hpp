@@ -1907,8 +1907,8 @@ __global__ __launch_bounds__(kThreads) void k_sum2(const double* __restrict__ pa
 }
 
 // ---------------------------------------------------------------------------
-// Replica 2-RDM (Sec. "Reduced density matrices", Eq. (FCI2RDM)) over
-// spin-orbital pairs: canonical index so = spin * N + orbital, pair index
+// Replica 2-RDM (Sec. "Density matrix sampling and pure expectation
+// values", Eq. (FCI2RDM)) over spin-orbital pairs: canonical index so = spin * N + orbital, pair index
 // P(k,l) = k(2K-k-1)/2 + l-k-1 for k < l (K = 2N), matrix G[P(k,l) M +
 // P(m,n)] of M = K(K-1)/2 rows.  Per paired step: an open-addressing table
 // of each replica's population at tau, the exact diagonal terms

@@ -1,4 +1,4 @@
-"""GPU parity of the replica 2-RDM (Sec. "Reduced density matrices", Eq.
+"""GPU parity of the replica 2-RDM (Sec. "Density matrix sampling and pure expectation values", Eq.
 (FCI2RDM)) and its variational energy against the oracle: both replicas
 follow the oracle bit for bit (integer walkers), so both sides sample the
 same excitations; the accumulated matrices differ only by the order of

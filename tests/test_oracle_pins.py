@@ -840,7 +840,7 @@ def test_long_run_matches_exact_diagonalisation(oracle_mod):
     assert 0.5 * 3000 < nw.mean() < 2.0 * 3000
 
 
-# --- replica 2-RDM (Sec. "Reduced density matrices", Eq. (FCI2RDM)) -------------------
+# --- replica 2-RDM (Sec. "Density matrix sampling and pure expectation values", Eq. (FCI2RDM)) -------------------
 
 def _sorted_basis(n_orb, na, nb):
     dets = sorted(brute.basis(n_orb, na, nb))
