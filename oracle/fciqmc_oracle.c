@@ -1106,7 +1106,7 @@ static double round_cmin(double x, double cmin, double u)
     return 0.0;
 }
 
-int orc_pchb_gen(const orc_sys *s, det_t d, const uint64_t r1[4], const uint64_t r2[4],
+int orc_pchb_gen(const orc_sys *s, det_t d, const uint64_t r1[4],
                  double p_single, double p_opp, det_t *tgt, double *pgen);
 int orc_cs_gen(const orc_sys *s, det_t d, const uint64_t r1[4], const uint64_t r2[4],
                double p_single, double p_opp, int exact, det_t *tgt, double *pgen);
@@ -1154,13 +1154,11 @@ int orc_run_step(orc_run *r, orc_stats *st)
             int ok;
             if (p->gen == GEN_UNIFORM) ok = gen_uniform(s, e->d, rr, p->p_single, &tgt, &pgen);
             else if (p->gen == GEN_LATTICE) ok = gen_lattice(s, e->d, rr, &tgt, &pgen);
+            else if (p->gen == GEN_PCHB) ok = orc_pchb_gen(s, e->d, rr, p->p_single, p->p_opp, &tgt, &pgen);
             else {
                 uint64_t r2[4] = {0, 0, 0, 0};
                 draw_block(r, e->d, t, (uint64_t)k, PURPOSE_SPAWN2, r2);  /* words 0-1 */
-                if (p->gen == GEN_PCHB)
-                    ok = orc_pchb_gen(s, e->d, rr, r2, p->p_single, p->p_opp, &tgt, &pgen);
-                else
-                    ok = orc_cs_gen(s, e->d, rr, r2, p->p_single, p->p_opp, p->gen == GEN_PE, &tgt, &pgen);
+                ok = orc_cs_gen(s, e->d, rr, r2, p->p_single, p->p_opp, p->gen == GEN_PE, &tgt, &pgen);
             }
             if (!ok) continue;
             if (r->log_exc) {
@@ -1472,8 +1470,9 @@ int orc_run_step(orc_run *r, orc_stats *st)
 /* Electron pairs are uniform within their class; the class is opposite spin */
 /* with probability p_opp.  A draw is null if a hole is occupied or if the    */
 /* row sums to zero.  Singles are uniform, as in the uniform generator.       */
-/* Random lanes: block SPAWN [0] single/double, [1] electron pair,            */
-/* [2] alias column, [3] acceptance; block SPAWN2 [0] alias coin, [1] class.  */
+/* Random words (two blocks): [0] single/double and, beyond p_single, the    */
+/* pair class; [1] electron pair; [2] alias column and, from the fraction    */
+/* its pick leaves, the alias coin; [3] acceptance.                           */
 /* ------------------------------------------------------------------------- */
 
 /* Alias table by Vose's construction with LIFO work lists filled in
@@ -1563,19 +1562,27 @@ void orc_pchb_build(orc_sys *s)
     free(small); free(large); free(scaled);
 }
 
-/* Alias draw: column c uniform, kept with probability prob_c, else alias_c. */
-static int alias_draw(const double *prob, const int *alias, int K, uint64_t xc, double coin)
+/* Alias draw from one 64-bit word x: column c = floor(x K / 2^64), uniform
+ * over the K columns; the coin is the fraction this leaves, the low 64 bits
+ * of x K taken as a 53-bit uniform (for fixed c they run over a grid of step
+ * K / 2^64 covering [0, 1), so the coin is uniform and independent of c to
+ * that resolution).  Column c is kept with probability prob_c, else the
+ * draw goes to alias_c. */
+static int alias_draw(const double *prob, const int *alias, int K, uint64_t xc)
 {
     int c = (int)pick(xc, (uint64_t)K);
+    uint64_t frac = xc * (uint64_t)K;
+    double coin = unif(frac);
     return coin < prob[c] ? c : alias[c];
 }
 
-int orc_pchb_gen(const orc_sys *s, det_t d, const uint64_t r1[4], const uint64_t r2[4],
+int orc_pchb_gen(const orc_sys *s, det_t d, const uint64_t r1[4],
                  double p_single, double p_opp, det_t *tgt, double *pgen)
 {
     int N = s->N;
     int n = s->na + s->nb;
-    if (unif(r1[0]) < p_single) {
+    double u0 = unif(r1[0]);
+    if (u0 < p_single) {
         uint64_t idx1 = pick(r1[1], (uint64_t)n);
         uint64_t c2 = orc_uniform_count2(s, d, 1, idx1);
         if (c2 == 0) return 0;
@@ -1591,8 +1598,11 @@ int orc_pchb_gen(const orc_sys *s, det_t d, const uint64_t r1[4], const uint64_t
     uint64_t npb = (uint64_t)nb * (uint64_t)(nb - (nb > 0)) / 2;
     uint64_t n_same = npa + npb;
     double pd = 1.0 - p_single;
-    int opp = unif(r2[1]) < p_opp;
-    double coin = unif(r2[0]);
+    /* the pair class from the same uniform: beyond p_single the first
+     * p_double p_opp of it is the opposite-spin class */
+    double pdo = pd * p_opp;
+    double thr = p_single + pdo;
+    int opp = u0 < thr;
     if (opp) {
         if (n_opp == 0) return 0;
         uint64_t q = pick(r1[1], n_opp);
@@ -1600,7 +1610,7 @@ int orc_pchb_gen(const orc_sys *s, det_t d, const uint64_t r1[4], const uint64_t
         double sum = s->hb_sum_opp[I * N + J];
         if (sum == 0.0) return 0;
         size_t row = (size_t)(I * N + J) * N * N;
-        int c = alias_draw(s->hb_p_opp + row, s->hb_a_opp + row, N * N, r1[2], coin);
+        int c = alias_draw(s->hb_p_opp + row, s->hb_a_opp + row, N * N, r1[2]);
         double wc = s->hb_w_opp[row + c];
         if (wc == 0.0) return 0;
         int A = c / N, B = c % N;
@@ -1633,7 +1643,7 @@ int orc_pchb_gen(const orc_sys *s, det_t d, const uint64_t r1[4], const uint64_t
     double sum = s->hb_sum_same[ij];
     if (sum == 0.0) return 0;
     size_t row = (size_t)ij * np;
-    int c = alias_draw(s->hb_p_same + row, s->hb_a_same + row, np, r1[2], coin);
+    int c = alias_draw(s->hb_p_same + row, s->hb_a_same + row, np, r1[2]);
     double wc = s->hb_w_same[row + c];
     if (wc == 0.0) return 0;
     int A = -1, B = -1, cnt = 0;
@@ -1890,13 +1900,11 @@ int orc_generate(const orc_run *r, uint64_t a, uint64_t b, int64_t t, uint64_t k
     int ok;
     if (r->p.gen == GEN_UNIFORM) ok = gen_uniform(r->s, d, rr, r->p.p_single, &tgt, pgen);
     else if (r->p.gen == GEN_LATTICE) ok = gen_lattice(r->s, d, rr, &tgt, pgen);
+    else if (r->p.gen == GEN_PCHB) ok = orc_pchb_gen(r->s, d, rr, r->p.p_single, r->p.p_opp, &tgt, pgen);
     else {
         uint64_t r2[4] = {0, 0, 0, 0};
         draw_block(r, d, t, k, PURPOSE_SPAWN2, r2);  /* words 0-1 */
-        if (r->p.gen == GEN_PCHB)
-            ok = orc_pchb_gen(r->s, d, rr, r2, r->p.p_single, r->p.p_opp, &tgt, pgen);
-        else
-            ok = orc_cs_gen(r->s, d, rr, r2, r->p.p_single, r->p.p_opp, r->p.gen == GEN_PE, &tgt, pgen);
+        ok = orc_cs_gen(r->s, d, rr, r2, r->p.p_single, r->p.p_opp, r->p.gen == GEN_PE, &tgt, pgen);
     }
     if (!ok) return 0;
     *ta = tgt.a; *tb = tgt.b;

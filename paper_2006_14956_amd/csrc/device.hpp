@@ -39,7 +39,10 @@ __device__ __forceinline__ R2 philox4x32(uint32_t c0, uint32_t c1, uint32_t c2, 
                                          uint32_t k1) {
     constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
     constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
-#pragma unroll
+    // rounds kept as a loop: the key schedule then stays two scalar adds per
+    // round instead of twenty hoisted round keys per stream spilled to
+    // vector lanes
+#pragma unroll 1
     for (int r = 0; r < 10; ++r) {
         const uint32_t h0 = __umulhi(M0, c0), l0 = M0 * c0;
         const uint32_t h1 = __umulhi(M1, c2), l1 = M1 * c2;
@@ -415,78 +418,83 @@ __device__ __forceinline__ bool gen_lattice(const SysView& s, uint64_t a, uint64
 }
 
 // Pre-computed heat-bath doubles (Appendix A.3, Eq. (hbs)) with Walker alias
-// tables; uniform singles.  Block r: 0 single/double, 1 electrons, 2 alias
-// column, 3 acceptance; block r2: 0 alias coin, 1 pair class.
+// tables; uniform singles.  Words of r: 0 single/double and, beyond
+// p_single, the pair class (the first p_double p_opp of it: opposite
+// spins); 1 electrons; 2 alias column and, from the fraction its pick
+// leaves (the low 64 bits of x K, a uniform on a grid of step K / 2^64 for
+// every column), the alias coin; 3 acceptance.
+// The two pair classes run one code path with per-lane choices (electron
+// pair, row, table, column decoding and spins), so that a wave whose lanes
+// draw both classes executes it once; each class's arithmetic is the one it
+// has on its own.
 __device__ __forceinline__ bool gen_pchb(const SysView& s, uint64_t a, uint64_t b, const R4& r,
-                                         const R2& r2, double p_single, double p_double,
-                                         double p_opp, Exc& out) {
+                                         double p_single, double p_double, double p_opp, Exc& out) {
     const int N = s.N, na = s.na, nb = s.nb;
-    if (unif(r.x[0]) < p_single) return gen_uniform(s, a, b, r, p_single, p_double, out);
+    const double u0 = unif(r.x[0]);
+    if (u0 < p_single) return gen_uniform(s, a, b, r, p_single, p_double, out);
     const uint64_t n_opp = (uint64_t)na * (uint64_t)nb;
     const uint64_t npa = (uint64_t)na * (uint64_t)(na > 0 ? na - 1 : 0) / 2;
     const uint64_t npb = (uint64_t)nb * (uint64_t)(nb > 0 ? nb - 1 : 0) / 2;
     const uint64_t n_same = npa + npb;
-    const bool opp = unif(r2.x[1]) < p_opp;
-    const double coin = unif(r2.x[0]);
-    if (opp) {
-        if (n_opp == 0) return false;
-        const uint64_t q = pick(r.x[1], n_opp);
-        const int I = select64(a, (int)(q / (uint64_t)nb));
-        const int J = select64(b, (int)(q % (uint64_t)nb));
-        const int row = I * N + J;
-        const int K = N * N;
-        const size_t base = (size_t)row * (size_t)K;
-        const int c0 = (int)pick(r.x[2], (uint64_t)K);
-        // p(ab|ij) = w_ab / sum_row with w_ab = |v|; a zero weight (or a
-        // zero row) is a null draw
-        const HbEntry en = s.hb_opp[base + c0];
-        const bool self = coin < en.prob;
-        const int c = self ? c0 : en.alias;
-        const double v = self ? en.v_self : en.v_alias;
-        const double wc = fabs(v);
-        if (wc == 0.0) return false;
-        const int A = c / N, Bo = c % N;
-        if (((a >> A) & 1ULL) || ((b >> Bo) & 1ULL)) return false;
-        const double sum = s.hb_sum_opp[row];
-        const double p1 = p_double * p_opp;
-        const double p2 = p1 / (double)n_opp;
-        const double pab = wc / sum;
-        out.pgen = p2 * pab;
-        out.H = double_parity(a, b, 0, I, 1, J, 0, A, 1, Bo) ? -v : v;
-        out.ta = (a & ~(1ULL << I)) | (1ULL << A);
-        out.tb = (b & ~(1ULL << J)) | (1ULL << Bo);
-        return true;
-    }
-    if (n_same == 0) return false;
-    uint64_t q = pick(r.x[1], n_same);
-    const int sg = q >= npa ? 1 : 0;
-    if (sg) q -= npa;
-    const uint64_t occ = sg ? b : a;
+    const double pdo = p_double * p_opp;
+    const double thr = p_single + pdo;
+    const bool opp = u0 < thr;
+    const uint64_t ncls = opp ? n_opp : n_same;
+    if (ncls == 0) return false;
+    const uint64_t q0 = pick(r.x[1], ncls);  // < 2^32
+    // electron pair: opposite spins (alpha index q / n_beta, beta q % n_beta);
+    // equal spins (pair q of the alpha pairs, then of the beta pairs)
+    const int sg = (!opp && q0 >= npa) ? 1 : 0;
+    const uint32_t q = (uint32_t)(sg ? q0 - npa : q0);
     int e1, e2;
-    pair_decode(q, sg ? nb : na, e1, e2);
-    const int I = select64(occ, e1), J = select64(occ, e2);
-    const int row = I * (2 * N - I - 1) / 2 + (J - I - 1);
-    const int K = N * (N - 1) / 2;
-    const size_t base = (size_t)row * (size_t)K;
+    if (opp) {
+        e1 = (int)(q / (uint32_t)nb);
+        e2 = (int)(q - (uint32_t)e1 * (uint32_t)nb);
+    } else {
+        pair_decode(q, sg ? nb : na, e1, e2);
+    }
+    const uint64_t occ = sg ? b : a;
+    const int sI = opp ? 0 : sg, sJ = opp ? 1 : sg;
+    const int I = select64(opp ? a : occ, e1);
+    const int J = select64(opp ? b : occ, e2);
+    const int row = opp ? I * N + J : I * (2 * N - I - 1) / 2 + (J - I - 1);
+    const int K = opp ? N * N : N * (N - 1) / 2;
+    const HbEntry* tab = opp ? s.hb_opp : s.hb_same;
     const int c0 = (int)pick(r.x[2], (uint64_t)K);
-    const HbEntry en = s.hb_same[base + c0];
+    const double coin = unif(r.x[2] * (uint64_t)K);
+    // p(ab|ij) = w_ab / sum_row with w_ab = |v|; a zero weight (or a zero
+    // row) is a null draw
+    const HbEntry en = tab[(size_t)row * (size_t)K + c0];
     const bool self = coin < en.prob;
     const int c = self ? c0 : en.alias;
     const double v = self ? en.v_self : en.v_alias;
     const double wc = fabs(v);
     if (wc == 0.0) return false;
-    const int ab = s.pair_of[c];
-    const int A = ab >> 6, Bo = ab & 63;
-    if (((occ >> A) & 1ULL) || ((occ >> Bo) & 1ULL)) return false;
-    const double sum = s.hb_sum_same[row];
-    const double p1 = p_double * (1.0 - p_opp);
-    const double p2 = p1 / (double)n_same;
+    int A, Bo;
+    if (opp) {
+        A = c / N;
+        Bo = c - A * N;
+    } else {
+        const int ab = s.pair_of[c];
+        A = ab >> 6;
+        Bo = ab & 63;
+    }
+    const int sA = sI, sB = sJ;
+    const uint64_t mA = sA ? b : a, mB = sB ? b : a;
+    if (((mA >> A) & 1ULL) || ((mB >> Bo) & 1ULL)) return false;
+    const double sum = (opp ? s.hb_sum_opp : s.hb_sum_same)[row];
+    const double p1 = p_double * (opp ? p_opp : 1.0 - p_opp);
+    const double p2 = p1 / (double)ncls;
     const double pab = wc / sum;
     out.pgen = p2 * pab;
-    out.H = double_parity(a, b, sg, I, sg, J, sg, A, sg, Bo) ? -v : v;
-    const uint64_t m = (occ & ~(1ULL << I) & ~(1ULL << J)) | (1ULL << A) | (1ULL << Bo);
-    out.ta = sg ? a : m;
-    out.tb = sg ? m : b;
+    out.H = double_parity(a, b, sI, I, sJ, J, sA, A, sB, Bo) ? -v : v;
+    uint64_t TA = a, TB = b;
+    clear_so(TA, TB, sI, I);
+    clear_so(TA, TB, sJ, J);
+    set_so(TA, TB, sA, A);
+    set_so(TA, TB, sB, Bo);
+    out.ta = TA;
+    out.tb = TB;
     return true;
 }
 

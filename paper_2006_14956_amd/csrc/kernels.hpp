@@ -231,10 +231,8 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
             bool ok;
             if constexpr (GEN == 0) ok = gen_uniform(sys, da, db, r, sc.p_single, sc.p_double, x);
             else if constexpr (GEN == 1) ok = gen_lattice(sys, da, db, r, x);
-            else if constexpr (GEN == 2) {
-                const R2 r2 = draw2<W>(key, sc.t, k, kSpawn2, sc.seed, sc.replica);
-                ok = gen_pchb(sys, da, db, r, r2, sc.p_single, sc.p_double, sc.p_opp, x);
-            } else {
+            else if constexpr (GEN == 2) ok = gen_pchb(sys, da, db, r, sc.p_single, sc.p_double, sc.p_opp, x);
+            else {
                 const R2 r2 = draw2<W>(key, sc.t, k, kSpawn2, sc.seed, sc.replica);
                 ok = gen_cs<GEN == 4>(sys, tJ, tSK, da, db, r, r2, sc.p_single, sc.p_double, sc.p_opp, x);
             }
