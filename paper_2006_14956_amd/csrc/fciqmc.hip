@@ -292,8 +292,9 @@ template <int W, class V> struct Engine : EngineBase {
     Rec<W, V>* rec2 = nullptr;  // per-bucket record slabs
     long long cap = 0;
     long long rec_need = 0;     // slab capacity the next step reserves
-    int32_t* scount = nullptr;  // records per sub-slab, B*kSub (zero between steps)
+    int32_t* scount = nullptr;  // records per sub-slab when slabs are rebuilt, B*kSub (zero between uses)
     int64_t* soff = nullptr;    // sub-slab offsets, B*kSub+1
+    uint64_t* scur = nullptr;   // sub-slab cursor words (end << 32 | next place), B*kSub
     int64_t* rel = nullptr;     // next step's sub-slab offsets within their bucket, B*kSub
     int64_t* need_b = nullptr;  // next step's slab size per bucket, B
     int64_t* recs_b = nullptr;  // records per bucket this step, B
@@ -394,12 +395,14 @@ template <int W, class V> struct Engine : EngineBase {
         ++klaunch;
         return 0;
     }
-    // Drop a queued spawn launch: wait for it, clear the record counters and
-    // the step accumulators it touched (the slab offsets stay valid).
+    // Drop a queued spawn launch: wait for it, rewind the sub-slab cursors
+    // and clear the step accumulators it touched (the slab offsets stay valid).
     int discard_pending() {
         if (!pending) return 0;
         HIP_OK(hipStreamSynchronize(stream));
-        HIP_OK(hipMemsetAsync(scount, 0, sizeof(int32_t) * B * kSub, stream));
+        hipLaunchKernelGGL(k_slab_rewind, dim3((unsigned)std::min<int64_t>(4096, ((int64_t)B * kSub + 255) / 256)),
+                           dim3(256), 0, stream, scur, (const int64_t*)soff, B * kSub);
+        HIP_OK(hipGetLastError());
         HIP_OK(hipMemsetAsync(ctl, 0, offsetof(Ctl, nw), stream));
         pending = false;
         return 0;
@@ -443,8 +446,10 @@ template <int W, class V> struct Engine : EngineBase {
         CHECK(dalloc(arena, &recs_b, (size_t)B));
         CHECK(dalloc(arena, &part, (size_t)(B + kPostSpan - 1) / kPostSpan));
         CHECK(dalloc(arena, &soff, (size_t)B * kSub + 1));
+        CHECK(dalloc(arena, &scur, (size_t)B * kSub));
         HIP_OK(hipMemsetAsync(scount, 0, sizeof(int32_t) * B * kSub, stream));
         HIP_OK(hipMemsetAsync(soff, 0, sizeof(int64_t) * (B * kSub + 1), stream));
+        HIP_OK(hipMemsetAsync(scur, 0, sizeof(uint64_t) * B * kSub, stream));
         CHECK(dalloc(arena, &nw_b, (size_t)B));
         CHECK(dalloc(arena, &en_b, (size_t)B));
         if (!sys->onsite) {
@@ -468,7 +473,7 @@ template <int W, class V> struct Engine : EngineBase {
     void free_buckets() {
         free_store(st[0]);
         free_store(st[1]);
-        arena.release(scount); arena.release(soff);
+        arena.release(scount); arena.release(soff); arena.release(scur);
         arena.release(rel); arena.release(need_b); arena.release(recs_b); arena.release(part);
         rel = nullptr; need_b = nullptr; recs_b = nullptr; part = nullptr;
         arena.release(rej_off); arena.release(rej_cnt);
@@ -477,7 +482,7 @@ template <int W, class V> struct Engine : EngineBase {
         ada_acc = nullptr; ada_all = nullptr;
         arena.release(nw_b); arena.release(en_b);
         arena.release(fpos); arena.release(fcnt);
-        scount = nullptr; soff = nullptr; nw_b = en_b = nullptr;
+        scount = nullptr; soff = nullptr; scur = nullptr; nw_b = en_b = nullptr;
         fpos = nullptr; fcnt = nullptr;
     }
     // Replace buffer p by one of n elements (contents are not kept): the new
@@ -511,6 +516,15 @@ template <int W, class V> struct Engine : EngineBase {
             CHECK(regrow(rec_h, (size_t)nc));
         }
         cap = nc;
+        return cursor_range();
+    }
+    // Record places are 32-bit in the sub-slab cursor words: the slabs plus
+    // two steps of attempts (a spawn queued behind a failed step counts on)
+    // stay below 2^32, about 1.3e9 attempts per step.
+    int cursor_range() const {
+        if ((uint64_t)cap + 2ULL * (uint64_t)cap_cmap * kChunk >= (1ULL << 32))
+            return fail(FCIQMC_EOVERFLOW, "%lld record places and %lld spawn chunks per step exceed the 32-bit "
+                        "record cursors", (long long)cap, (long long)cap_cmap);
         return 0;
     }
     // The discarded-spawn buffer follows the slab capacity, but is replaced
@@ -541,7 +555,7 @@ template <int W, class V> struct Engine : EngineBase {
         CHECK(ensure_slabs(spawn_cap));
         cap_cmap = std::max<int64_t>(1 << 16, spawn_cap / kChunk + 4 * (int64_t)B);
         CHECK(dalloc(arena, &cmap, (size_t)cap_cmap));
-        return 0;
+        return cursor_range();
     }
     // Room in the chunk map for the next step; after growth the map is
     // rebuilt from the chunk prefix the post work left in st[cur].
@@ -554,7 +568,7 @@ template <int W, class V> struct Engine : EngineBase {
         hipLaunchKernelGGL(k_chunk_map, dim3((unsigned)std::min<int64_t>((B + 255) / 256, 4096)), dim3(256), 0, stream,
                            st[cur].aoff, B, cmap);
         HIP_OK(hipGetLastError());
-        return 0;
+        return cursor_range();
     }
 
     StepScalars scalars(int64_t t, double S, int import_mode) const {
@@ -610,17 +624,17 @@ template <int W, class V> struct Engine : EngineBase {
                 hipLaunchKernelGGL((k_ada_zero<V>), dim3(ga), dim3(kThreads), 0, stream, in, R, B, ada_acc, ada_all);
             ada_clean = false;
             hipLaunchKernelGGL((k_ada_weights<W, V>), dim3(ga), dim3(kThreads), 0, stream, v, in, sc, rec2, soff,
-                               scount, ctl);
+                               scur, ctl);
         }
         if (ncore > 0 && !sc.import_mode)
             hipLaunchKernelGGL(k_core_spmv, dim3((unsigned)((ncore + 3) / 4)), dim3(kThreads), 0, stream, core_rowp,
                                core_col, core_val, core_cdiag, core_cv[cur], core_dv, ncore, rs.tau, sc.S);
         if (ext())
             hipLaunchKernelGGL((k_annihilate<W, V, true>), dim3(gb), dim3(kThreads), 0, stream, v, in, out, sc,
-                               rec2, soff, scount, rel, need_b, recs_b, nw_b, en_b, fpos, fcnt, ctl);
+                               rec2, soff, scur, rel, need_b, recs_b, nw_b, en_b, fpos, fcnt, ctl);
         else
             hipLaunchKernelGGL((k_annihilate<W, V, false>), dim3(gb), dim3(kThreads), 0, stream, v, in, out, sc,
-                               rec2, soff, scount, rel, need_b, recs_b, nw_b, en_b, fpos, fcnt, ctl);
+                               rec2, soff, scur, rel, need_b, recs_b, nw_b, en_b, fpos, fcnt, ctl);
         if (!sys->onsite) {
             const int64_t items = fresh_items(B);
             hipLaunchKernelGGL((k_fresh<W, V>), dim3((unsigned)std::min<int64_t>(items, 4096)), dim3(kThreads),
@@ -629,19 +643,19 @@ template <int W, class V> struct Engine : EngineBase {
         mark(set, 2);
         if (sc.import_mode) {
             // slabs of the first step after an import: from the imported counts
-            hipLaunchKernelGGL(k_import_slabs, dim3((B + 255) / 256), dim3(256), 0, stream, scount, B, rel,
+            hipLaunchKernelGGL(k_import_slabs, dim3((B + 255) / 256), dim3(256), 0, stream, scur, soff, B, rel,
                                need_b);
         }
         if (B <= 4 * kPostSpan) {
             hipLaunchKernelGGL(k_post, dim3(1), dim3(kPostThreads), 0, stream, out.batt, out.count, nw_b, en_b,
-                               B, out.aoff, rel, need_b, recs_b, soff, cmap, cap_cmap, ctl, hctl);
+                               B, out.aoff, rel, need_b, recs_b, soff, scur, cmap, cap_cmap, ctl, hctl);
         } else {
             const int G = (B + kPostSpan - 1) / kPostSpan;
             hipLaunchKernelGGL(k_post_a, dim3(G), dim3(256), 0, stream, out.batt, out.count, nw_b, en_b, need_b,
                                recs_b, B, part, ctl);
             hipLaunchKernelGGL(k_post_b, dim3(1), dim3(256), 0, stream, part, G, B, out.aoff, soff, ctl, hctl);
             hipLaunchKernelGGL(k_post_c, dim3(G), dim3(256), 0, stream, out.batt, rel, need_b, B, part, out.aoff,
-                               soff, cmap, cap_cmap, ctl);
+                               soff, scur, cmap, cap_cmap, ctl);
         }
         mark(set, 3);
         HIP_OK(hipGetLastError());
@@ -652,10 +666,13 @@ template <int W, class V> struct Engine : EngineBase {
 
     // After a step that stopped on a flag: clear the per-step accumulators and
     // rebuild the slabs from the counts the stopped step reached (the exact
-    // record numbers per bucket), which leaves scount zero again.
+    // record numbers per sub-slab, from its cursor), which leaves scount zero
+    // again.
     int recover() {
         HIP_OK(hipMemsetAsync(ctl, 0, offsetof(Ctl, nw), stream));
-        hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, stream, scount, B * kSub, 1, soff, ctl);
+        hipLaunchKernelGGL(k_slab_counts, dim3((unsigned)std::min<int64_t>(4096, ((int64_t)B * kSub + 255) / 256)),
+                           dim3(256), 0, stream, (const uint64_t*)scur, (const int64_t*)soff, B * kSub, scount);
+        hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, stream, scount, B * kSub, 1, soff, scur, ctl);
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
         HIP_OK(hipStreamSynchronize(stream));
@@ -701,10 +718,10 @@ template <int W, class V> struct Engine : EngineBase {
             if (n > 0)
                 hipLaunchKernelGGL((k_bucketize<W, V>), dim3(gs), dim3(kThreads), 0, stream, rec, (long long)n, B,
                                    scount);
-            hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, stream, scount, B * kSub, 0, soff, ctl);
+            hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, stream, scount, B * kSub, 0, soff, scur, ctl);
             if (n > 0)
-                hipLaunchKernelGGL((k_scatter<W, V>), dim3(gs), dim3(kThreads), 0, stream, rec, (long long)n, rec2,
-                                   soff, scount);
+                hipLaunchKernelGGL((k_scatter<W, V>), dim3(gs), dim3(kThreads), 0, stream, rec, (long long)n, B, rec2,
+                                   scur);
             HIP_OK(hipGetLastError());
             StepScalars sc = scalars(0, 0.0, 1);
             CHECK(merge_and_post(sc));
@@ -966,10 +983,10 @@ template <int W, class V> struct Engine : EngineBase {
         const size_t lds = (GEN >= 3 && v.N <= kCsLdsMaxN) ? 2 * sizeof(double) * (size_t)v.N * (size_t)v.N : 0;
         if (ext())
             hipLaunchKernelGGL((k_spawn<W, V, GEN, true>), dim3(blocks), dim3(kThreads), lds, stream, v, in, sc,
-                               rec2, soff, scount, ctl, cmap, cap_cmap);
+                               rec2, scur, ctl, cmap, cap_cmap);
         else
             hipLaunchKernelGGL((k_spawn<W, V, GEN, false>), dim3(blocks), dim3(kThreads), lds, stream, v, in, sc,
-                               rec2, soff, scount, ctl, cmap, cap_cmap);
+                               rec2, scur, ctl, cmap, cap_cmap);
     }
     // Spawn from store `in` with `grid` workgroups (the kernel reads the
     // chunk count from the device and strides over it).
@@ -1100,8 +1117,8 @@ template <int W, class V> struct Engine : EngineBase {
         d.in = st[cur];
         d.out = st[1 - cur];
         d.sc = scalars(t, S, 0);
-        d.rec2 = rec2; d.soff = soff; d.rel = rel; d.need_b = need_b; d.recs_b = recs_b;
-        d.scount = scount; d.nw_b = nw_b; d.en_b = en_b; d.fpos = fpos; d.fcnt = fcnt; d.ctl = ctl;
+        d.rec2 = rec2; d.soff = soff; d.scur = scur; d.rel = rel; d.need_b = need_b; d.recs_b = recs_b;
+        d.nw_b = nw_b; d.en_b = en_b; d.fpos = fpos; d.fcnt = fcnt; d.ctl = ctl;
         d.cmap = cmap; d.cmap_cap = cap_cmap;
         chunks = chunk_next;
         return 0;

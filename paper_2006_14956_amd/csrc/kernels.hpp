@@ -44,7 +44,7 @@ __host__ __device__ inline int64_t chunks_of(int64_t attempts) { return (attempt
 template <int W, class V> struct Rec {
     uint64_t k[W];
     V v;
-    uint32_t flag;  // bit 0: parent is an initiator; bits 1..: target bucket
+    uint32_t flag;  // bit 0: parent is an initiator; bits 1..31: low bits of the key's hash
 };
 
 template <class V> struct Store {
@@ -87,6 +87,16 @@ __device__ __forceinline__ int64_t slab_size(int32_t c) {
 }
 
 template <class V> __device__ __forceinline__ double vabs(V v) { return v < 0 ? -(double)v : (double)v; }
+
+// a / C_min, the keep probability of the C_min rounding; at the usual
+// C_min = 1 the quotient is a itself (exact), and the wave-uniform branch
+// skips the division.  The empty asm keeps the compiler from computing the
+// quotient ahead of the branch and selecting afterwards.
+__device__ __forceinline__ double over_cmin(double a, double c_min) {
+    if (c_min == 1.0) return a;
+    asm volatile("" : "+v"(a));
+    return a / c_min;
+}
 
 // Attempts a determinant makes: |C| walkers (integer) or ceil(|C|) (real).
 template <class V> __device__ __forceinline__ int64_t n_attempts(V v) {
@@ -176,15 +186,15 @@ template <int W> __device__ __forceinline__ int64_t core_find(const StepScalars&
 // ---------------------------------------------------------------------------
 template <int W, class V, int GEN, bool EXT>
 __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& st, const StepScalars& sc,
-                                            Rec<W, V>* __restrict__ rec2, const int64_t* __restrict__ soff,
-                                            int32_t* __restrict__ scount, Ctl* ctl,
+                                            Rec<W, V>* __restrict__ rec2, uint64_t* __restrict__ scur, Ctl* ctl,
                                             const int64_t* __restrict__ cmap, int64_t g, int32_t* smpre,
                                             const double* __restrict__ tJ, const double* __restrict__ tSK) {
     // Chunk g is local chunk c of bucket b (cmap[g] = b << 32 | c): the
     // bucket's attempts [c*kChunk, (c+1)*kChunk), one per lane.  The
     // bucket's attempt prefixes are read once into LDS; each lane finds its
     // determinant there.  A record takes the next place of sub-slab
-    // j = b'*kSub + g mod kSub of its target bucket b', rec2[soff[j] .. soff[j+1]).
+    // j = b'*kSub + g mod kSub of its target bucket b': one atomic add on the
+    // sub-slab's cursor word (end << 32 | next place) returns both.
     const Key<W> ref = make_key<W>(sc.ref_a, sc.ref_b);
     const int64_t m = cmap[g];
     const int b = (int)(m >> 32);
@@ -199,6 +209,7 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
         Rec<W, V> out;
         int64_t out_parent = -1;  // adaptive shift: non-initiator parent's store index
         double out_h = 0.0;
+        uint32_t out_bk = 0;      // target bucket
         RdmRec<W> rdm;            // replica 2-RDM: this slot's draw (w = 0: none)
         rdm.w = 0.0;
         if (local < natt) {
@@ -270,7 +281,7 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
                     double amp = -(x2 / d1);
                     const double aa = fabs(amp);
                     if (aa < sc.c_min) {
-                        const double pr = aa / sc.c_min;
+                        const double pr = over_cmin(aa, sc.c_min);
                         amp = (u < pr) ? (amp < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
                     }
                     if (amp != 0.0) { out.v = (V)amp; emit = true; }
@@ -283,8 +294,9 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
                     const Key<W> tk = make_key<W>(x.ta, x.tb);
 #pragma unroll
                     for (int w = 0; w < W; ++w) out.k[w] = tk.w[w];
-                    const uint32_t bk = bucket_of(key_hash<W>(tk), (uint32_t)sc.B);
-                    out.flag = (init ? 1u : 0u) | (bk << 1);
+                    const uint64_t h = key_hash<W>(tk);
+                    out_bk = bucket_of(h, (uint32_t)sc.B);
+                    out.flag = (init ? 1u : 0u) | ((uint32_t)h << 1);
                 }
             }
         }
@@ -296,13 +308,14 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
             }
         }
         if (emit) {
-            const uint32_t j = (out.flag >> 1) * kSub + (uint32_t)(g & (kSub - 1));
-            const int64_t pos = (int64_t)atomicAdd(&scount[j], 1);
-            if (soff[j] + pos < soff[j + 1] && soff[j] + pos < sc.spawn_cap) {
-                rec2[soff[j] + pos] = out;
+            const uint32_t j = out_bk * kSub + (uint32_t)(g & (kSub - 1));
+            const uint64_t cw = atomicAdd((unsigned long long*)&scur[j], 1ULL);
+            const int64_t pos = (int64_t)(uint32_t)cw;
+            if (pos < (int64_t)(cw >> 32) && pos < sc.spawn_cap) {
+                rec2[pos] = out;
                 if (EXT && sc.rec_par) {
-                    sc.rec_par[soff[j] + pos] = (out_parent < 0) ? -1 : out_parent;
-                    sc.rec_h[soff[j] + pos] = out_h;
+                    sc.rec_par[pos] = (out_parent < 0) ? -1 : out_parent;
+                    sc.rec_h[pos] = out_h;
                 }
             } else {
                 atomicOr(&ctl->flags, kFlagSpawnCap);
@@ -320,8 +333,7 @@ constexpr int kCsLdsMaxN = 45;
 template <int W, class V, int GEN, bool EXT>
 __global__ __launch_bounds__(kThreads) void k_spawn(SysView sys, Store<V> st, StepScalars sc,
                                                     Rec<W, V>* __restrict__ rec2,
-                                                    const int64_t* __restrict__ soff,
-                                                    int32_t* __restrict__ scount, Ctl* ctl,
+                                                    uint64_t* __restrict__ scur, Ctl* ctl,
                                                     const int64_t* __restrict__ cmap, int64_t cmap_cap) {
     // the chunk count of this step comes from the post work of the previous
     // one, so a launch may be queued before the host has read it
@@ -344,11 +356,11 @@ __global__ __launch_bounds__(kThreads) void k_spawn(SysView sys, Store<V> st, St
         }
         __syncthreads();
         for (int64_t g = blockIdx.x; g < n; g += gridDim.x)
-            spawn_chunk<W, V, GEN, EXT>(sys, st, sc, rec2, soff, scount, ctl, cmap, g, smpre, cs_tab, cs_tab + nn);
+            spawn_chunk<W, V, GEN, EXT>(sys, st, sc, rec2, scur, ctl, cmap, g, smpre, cs_tab, cs_tab + nn);
         return;
     }
     for (int64_t g = blockIdx.x; g < n; g += gridDim.x)
-        spawn_chunk<W, V, GEN, EXT>(sys, st, sc, rec2, soff, scount, ctl, cmap, g, smpre, sys.J, sys.SK);
+        spawn_chunk<W, V, GEN, EXT>(sys, st, sc, rec2, scur, ctl, cmap, g, smpre, sys.J, sys.SK);
 }
 
 // Records uploaded from the host (population import): assign buckets.
@@ -360,18 +372,20 @@ __global__ __launch_bounds__(kThreads) void k_bucketize(Rec<W, V>* rec, long lon
         Key<W> k;
 #pragma unroll
         for (int w = 0; w < W; ++w) k.w[w] = rec[i].k[w];
-        const uint32_t b = bucket_of(key_hash<W>(k), (uint32_t)B);
-        rec[i].flag = (rec[i].flag & 1u) | (b << 1);
+        const uint64_t h = key_hash<W>(k);
+        const uint32_t b = bucket_of(h, (uint32_t)B);
+        rec[i].flag = (rec[i].flag & 1u) | ((uint32_t)h << 1);
         atomicAdd(&scount[b * kSub + (uint32_t)(i & (kSub - 1))], 1);
     }
 }
 
 // Record slabs from per-bucket counts (one workgroup of 1024 threads, each
 // scanning a contiguous segment): soff = exclusive prefix of the counts, or
-// of slab_size(count) when `headroom` is set; the counts are then zeroed.
+// of slab_size(count) when `headroom` is set; the counts are then zeroed
+// and the cursor words set (end << 32 | start).
 __device__ __forceinline__ void offsets_from_counts(int32_t* __restrict__ cnt, int B, int headroom,
-                                                    int64_t* __restrict__ off, long long* total_out,
-                                                    long long* count_out, int64_t* sh) {
+                                                    int64_t* __restrict__ off, uint64_t* __restrict__ cur,
+                                                    long long* total_out, long long* count_out, int64_t* sh) {
     const int T = 1024;
     const int per = (B + T - 1) / T;
     const int s0 = threadIdx.x * per;
@@ -387,7 +401,9 @@ __device__ __forceinline__ void offsets_from_counts(int32_t* __restrict__ cnt, i
     (void)block_excl_scan<1024, int64_t>(raw, rtot, sh);
     for (int i = s0; i < s1; ++i) {
         off[i] = run;
-        run += headroom ? slab_size(cnt[i]) : (int64_t)cnt[i];
+        const int64_t e = run + (headroom ? slab_size(cnt[i]) : (int64_t)cnt[i]);
+        cur[i] = ((uint64_t)e << 32) | (uint64_t)run;
+        run = e;
         cnt[i] = 0;
     }
     if (threadIdx.x == 0) {
@@ -398,9 +414,24 @@ __device__ __forceinline__ void offsets_from_counts(int32_t* __restrict__ cnt, i
 }
 
 __global__ __launch_bounds__(1024) void k_offsets(int32_t* __restrict__ cnt, int B, int headroom,
-                                                  int64_t* __restrict__ off, Ctl* ctl) {
+                                                  int64_t* __restrict__ off, uint64_t* __restrict__ cur, Ctl* ctl) {
     __shared__ int64_t sh[16];
-    offsets_from_counts(cnt, B, headroom, off, &ctl->rec_need, (long long*)nullptr, sh);
+    offsets_from_counts(cnt, B, headroom, off, cur, &ctl->rec_need, (long long*)nullptr, sh);
+}
+
+// Cursors back to their sub-slab starts (the end halves are untouched by a
+// spawn), after a queued spawn launch is dropped.
+__global__ void k_slab_rewind(uint64_t* __restrict__ cur, const int64_t* __restrict__ off, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        cur[i] = (cur[i] & 0xFFFFFFFF00000000ULL) | (uint64_t)(uint32_t)off[i];
+}
+
+// Records each sub-slab received (cursor minus start; a full sub-slab's
+// cursor counts on past its end), for slabs rebuilt after an overflow.
+__global__ void k_slab_counts(const uint64_t* __restrict__ cur, const int64_t* __restrict__ off, int n,
+                              int32_t* __restrict__ cnt) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        cnt[i] = (int32_t)((uint32_t)cur[i] - (uint32_t)off[i]);
 }
 
 // Exclusive prefix of counts into offsets without modifying the counts.
@@ -421,15 +452,17 @@ __global__ __launch_bounds__(1024) void k_count_offsets(const int32_t* __restric
 
 // Imported records (flat array, buckets assigned) into their slabs.
 template <int W, class V>
-__global__ __launch_bounds__(kThreads) void k_scatter(const Rec<W, V>* __restrict__ rec, long long n,
+__global__ __launch_bounds__(kThreads) void k_scatter(const Rec<W, V>* __restrict__ rec, long long n, int B,
                                                       Rec<W, V>* __restrict__ rec2,
-                                                      const int64_t* __restrict__ soff,
-                                                      int32_t* __restrict__ scount) {
+                                                      uint64_t* __restrict__ scur) {
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n;
          i += (long long)gridDim.x * kThreads) {
         const Rec<W, V> r = rec[i];
-        const uint32_t j = (r.flag >> 1) * kSub + (uint32_t)(i & (kSub - 1));
-        const int64_t pos = soff[j] + atomicAdd(&scount[j], 1);
+        Key<W> k;
+#pragma unroll
+        for (int w = 0; w < W; ++w) k.w[w] = r.k[w];
+        const uint32_t j = bucket_of(key_hash<W>(k), (uint32_t)B) * kSub + (uint32_t)(i & (kSub - 1));
+        const int64_t pos = (int64_t)(uint32_t)atomicAdd((unsigned long long*)&scur[j], 1ULL);
         rec2[pos] = r;
     }
 }
@@ -515,6 +548,15 @@ template <class V> __device__ __forceinline__ void lds_add(V* p, V v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Sub-slab j of bucket b holds records [base + r[j], base + r[j+1]) (r[kSub]
+// = need, the bucket's slab size): its start, and its cursor word for the
+// spawn (end << 32 | start).
+__device__ __forceinline__ void set_subslab(int64_t* __restrict__ soff, uint64_t* __restrict__ scur, int b, int j,
+                                            int64_t start, int64_t end) {
+    soff[(int64_t)b * kSub + j] = start;
+    scur[(int64_t)b * kSub + j] = ((uint64_t)end << 32) | (uint64_t)start;
+}
+
 // ---------------------------------------------------------------------------
 // Global sums and next-step offsets (attempt prefix over buckets, record
 // sub-slab offsets), executed by one workgroup of NT threads, then the step
@@ -530,6 +572,7 @@ __device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, cons
                                           const int64_t* __restrict__ rel, const int64_t* __restrict__ need_b,
                                           const int64_t* __restrict__ recs_b, int B,
                                           int64_t* __restrict__ aoff, int64_t* __restrict__ soff,
+                                          uint64_t* __restrict__ scur,
                                           int64_t* __restrict__ cmap, int64_t cmap_cap, Ctl* ctl,
                                           Ctl* __restrict__ host, int64_t* sh, double* shd, int64_t* shm,
                                           unsigned* shf) {
@@ -592,7 +635,8 @@ __device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, cons
                 for (int64_t c = 0; c < nk && run + c < cmap_cap; ++c) cmap[run + c] = ((int64_t)b << 32) | c;
                 run += nk;
 #pragma unroll
-                for (int j = 0; j < kSub; ++j) soff[(int64_t)b * kSub + j] = base + hrel[i][j];
+                for (int j = 0; j < kSub; ++j)
+                    set_subslab(soff, scur, b, j, base + hrel[i][j], base + (j + 1 < kSub ? hrel[i][j + 1] : hneed[i]));
                 base += hneed[i];
             }
         }
@@ -601,7 +645,12 @@ __device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, cons
             const int64_t nk = chunks_of(batt[b]);
             for (int64_t c = 0; c < nk && run + c < cmap_cap; ++c) cmap[run + c] = ((int64_t)b << 32) | c;
             run += nk;
-            for (int j = 0; j < kSub; ++j) soff[(int64_t)b * kSub + j] = base + rel[(int64_t)b * kSub + j];
+            int64_t r0 = rel[(int64_t)b * kSub];
+            for (int j = 0; j < kSub; ++j) {
+                const int64_t r1 = j + 1 < kSub ? rel[(int64_t)b * kSub + j + 1] : need_b[b];
+                set_subslab(soff, scur, b, j, base + r0, base + r1);
+                r0 = r1;
+            }
             base += need_b[b];
         }
     }
@@ -662,7 +711,7 @@ __device__ __forceinline__ unsigned wg_flags(const Ctl* ctl, unsigned* sh) {
 template <int W, class V, bool EXT>
 __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Store<V>& in, const Store<V>& out,
                                                   const StepScalars& sc, const Rec<W, V>* __restrict__ rec2,
-                                                  int64_t* __restrict__ soff, int32_t* __restrict__ scount,
+                                                  const int64_t* __restrict__ soff, const uint64_t* __restrict__ scur,
                                                   int64_t* __restrict__ rel, int64_t* __restrict__ need_b,
                                                   int64_t* __restrict__ recs_b, double* __restrict__ nw_b,
                                                   double* __restrict__ en_b, uint16_t* __restrict__ fpos,
@@ -679,7 +728,7 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
 #pragma unroll
     for (int j = 0; j < kSub; ++j) {
         lo[j] = soff[(int64_t)b * kSub + j];
-        cj[j] = scount[(int64_t)b * kSub + j];
+        cj[j] = (int32_t)((uint32_t)scur[(int64_t)b * kSub + j] - (uint32_t)lo[j]);
         cum[j + 1] = cum[j] + cj[j];
     }
     // LDS table sized to the bucket: keys <= determinants + records, load <= 3/4
@@ -760,7 +809,7 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
                 const double ax = fabs(xv);
                 double y = xv;
                 if (ax < sc.c_min && xv != 0.0) {
-                    const double pr = ax / sc.c_min;
+                    const double pr = over_cmin(ax, sc.c_min);
                     y = (u < pr) ? (xv < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
                 }
                 post = (V)y;
@@ -784,7 +833,7 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
 #pragma unroll
         for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
         const bool init = (x.flag & 1u) != 0;
-        const int s = lds_find<W>(L.t, key, key_hash<W>(key), mask, init);
+        const int s = lds_find<W>(L.t, key, (uint64_t)(x.flag >> 1), mask, init);
         if (s == -1) continue;
         if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); continue; }
         if (init || L.t.idx[s] >= 0) lds_add<V>(&L.t.val[s], x.v);
@@ -810,7 +859,7 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
                     Key<W> key;
 #pragma unroll
                     for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
-                    dropped = lds_find<W>(L.t, key, key_hash<W>(key), mask, false) == -1;
+                    dropped = lds_find<W>(L.t, key, (uint64_t)(x.flag >> 1), mask, false) == -1;
                 }
             }
             int64_t tot;
@@ -823,20 +872,27 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
             sc.rej_cnt[b] = (int32_t)nb;
         }
     }
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < kSub) {
         // slabs of the next step: this step's counts plus headroom, relative
-        // to the bucket's base (set by the post work); counters restart at 0
+        // to the bucket's base (the post work places them and sets the
+        // cursors).  Lane j sizes sub-slab j; an 8-lane scan places them.
+        const int j = (int)threadIdx.x;
         if (!sc.import_mode) {
-            int64_t acc = 0;
+            int32_t c = 0;
 #pragma unroll
-            for (int j = 0; j < kSub; ++j) {
-                rel[(int64_t)b * kSub + j] = acc;
-                acc += slab_size(cj[j]);
-                scount[(int64_t)b * kSub + j] = 0;
+            for (int i = 0; i < kSub; ++i)
+                if (i == j) c = cj[i];
+            const long long sz = slab_size(c);
+            long long inc = sz;
+#pragma unroll
+            for (int o = 1; o < kSub; o <<= 1) {
+                const long long t = __shfl_up(inc, o, kSub);
+                if (j >= o) inc += t;
             }
-            need_b[b] = acc;
+            rel[(int64_t)b * kSub + j] = inc - sz;
+            if (j == kSub - 1) need_b[b] = inc;
         }
-        recs_b[b] = cum[kSub];
+        if (j == 0) recs_b[b] = cum[kSub];
     }
     // compaction: (1) each thread rounds its run of nslots / kThreads
     // consecutive slots in place (small real amplitudes) and drops what it
@@ -860,7 +916,7 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
                 key.w[0] = k0;
                 if constexpr (W == 2) key.w[1] = L.t.key1[s];
                 const double u = unif(draw2<W>(key, sc.t, 0, kAnn, sc.seed, sc.replica).x[0]);
-                const double pr = av / sc.c_min;
+                const double pr = over_cmin(av, sc.c_min);
                 v = (u < pr) ? (v < 0.0 ? -sc.c_min : sc.c_min) : 0.0;
                 L.t.val[s] = v;
             }
@@ -969,8 +1025,8 @@ template <int W, class V, bool EXT>
 __global__ __launch_bounds__(kThreads, 6) void k_annihilate(SysView sys, Store<V> in, Store<V> out,
                                                          StepScalars sc,
                                                          const Rec<W, V>* __restrict__ rec2,
-                                                         int64_t* __restrict__ soff,
-                                                         int32_t* __restrict__ scount,
+                                                         const int64_t* __restrict__ soff,
+                                                         const uint64_t* __restrict__ scur,
                                                          int64_t* __restrict__ rel,
                                                          int64_t* __restrict__ need_b,
                                                          int64_t* __restrict__ recs_b,
@@ -982,7 +1038,7 @@ __global__ __launch_bounds__(kThreads, 6) void k_annihilate(SysView sys, Store<V
     __shared__ unsigned fl;
     if (wg_flags(ctl, &fl)) return;
     for (int b = blockIdx.x; b < sc.B; b += gridDim.x)
-        annihilate_bucket<W, V, EXT>(sys, in, out, sc, rec2, soff, scount, rel, need_b, recs_b, nw_b, en_b, fpos, fcnt,
+        annihilate_bucket<W, V, EXT>(sys, in, out, sc, rec2, soff, scur, rel, need_b, recs_b, nw_b, en_b, fpos, fcnt,
                                 ctl, b, L);
 }
 
@@ -1183,6 +1239,7 @@ __global__ __launch_bounds__(256) void k_post_c(const int64_t* __restrict__ batt
                                                 const int64_t* __restrict__ need_b, int B,
                                                 const PostPart* __restrict__ part,
                                                 int64_t* __restrict__ aoff, int64_t* __restrict__ soff,
+                                                uint64_t* __restrict__ scur,
                                                 int64_t* __restrict__ cmap, int64_t cmap_cap, const Ctl* ctl) {
     if (ctl->flags) return;
     __shared__ int64_t sh[4];
@@ -1199,22 +1256,27 @@ __global__ __launch_bounds__(256) void k_post_c(const int64_t* __restrict__ batt
         const int64_t nk = chunks_of(batt[b]);
         for (int64_t c = 0; c < nk && rk + c < cmap_cap; ++c) cmap[rk + c] = ((int64_t)b << 32) | c;
         rk += nk;
-        for (int j = 0; j < kSub; ++j) soff[(int64_t)b * kSub + j] = rn + rel[(int64_t)b * kSub + j];
+        int64_t r0 = rel[(int64_t)b * kSub];
+        for (int j = 0; j < kSub; ++j) {
+            const int64_t r1 = j + 1 < kSub ? rel[(int64_t)b * kSub + j + 1] : need_b[b];
+            set_subslab(soff, scur, b, j, rn + r0, rn + r1);
+            r0 = r1;
+        }
         rn += need_b[b];
     }
 }
 
-// After an import the per-bucket kernel leaves the counters alone; size the
-// next step's slabs from the imported counts and restart the counters.
-__global__ void k_import_slabs(int32_t* __restrict__ scount, int B, int64_t* __restrict__ rel,
-                               int64_t* __restrict__ need_b) {
+// After an import the per-bucket kernel leaves the slabs alone; size the
+// next step's slabs from the imported counts (cursor minus start).
+__global__ void k_import_slabs(const uint64_t* __restrict__ scur, const int64_t* __restrict__ soff, int B,
+                               int64_t* __restrict__ rel, int64_t* __restrict__ need_b) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     int64_t acc = 0;
     for (int j = 0; j < kSub; ++j) {
-        rel[(int64_t)b * kSub + j] = acc;
-        acc += slab_size(scount[(int64_t)b * kSub + j]);
-        scount[(int64_t)b * kSub + j] = 0;
+        const int64_t i = (int64_t)b * kSub + j;
+        rel[i] = acc;
+        acc += slab_size((int32_t)((uint32_t)scur[i] - (uint32_t)soff[i]));
     }
     need_b[b] = acc;
 }
@@ -1228,12 +1290,13 @@ __global__ __launch_bounds__(kPostThreads) void k_post(const int64_t* __restrict
                                                const int64_t* __restrict__ rel,
                                                const int64_t* __restrict__ need_b,
                                                const int64_t* __restrict__ recs_b,
-                                               int64_t* __restrict__ soff, int64_t* __restrict__ cmap,
+                                               int64_t* __restrict__ soff, uint64_t* __restrict__ scur,
+                                               int64_t* __restrict__ cmap,
                                                int64_t cmap_cap, Ctl* ctl, Ctl* __restrict__ host) {
     __shared__ int64_t sh[4 * kPostThreads / 64], shm[kPostThreads / 64];
     __shared__ double shd[2 * kPostThreads / 64];
     __shared__ unsigned shf;
-    post_work<kPostThreads>(batt, count, nw_b, en_b, rel, need_b, recs_b, B, aoff, soff, cmap, cmap_cap, ctl, host,
+    post_work<kPostThreads>(batt, count, nw_b, en_b, rel, need_b, recs_b, B, aoff, soff, scur, cmap, cmap_cap, ctl, host,
                             sh, shd, shm, &shf);
 }
 
@@ -1296,7 +1359,7 @@ template <int W, class V> struct Inst {
     StepScalars sc;
     Rec<W, V>* rec2;
     int64_t *soff, *rel, *need_b, *recs_b;
-    int32_t* scount;
+    uint64_t* scur;
     double *nw_b, *en_b;
     uint16_t* fpos;
     int32_t* fcnt;
@@ -1323,7 +1386,7 @@ __global__ __launch_bounds__(kThreads) void k_spawn_batch(const Inst<W, V>* __re
     for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
         const int i = owner_of(first, k, g);
         const Inst<W, V>& I = inst[i];
-        spawn_chunk<W, V, GEN, false>(I.sys, I.in, I.sc, I.rec2, I.soff, I.scount, I.ctl, I.cmap, g - first[i], smpre,
+        spawn_chunk<W, V, GEN, false>(I.sys, I.in, I.sc, I.rec2, I.scur, I.ctl, I.cmap, g - first[i], smpre,
                                       I.sys.J, I.sys.SK);
     }
 }
@@ -1338,7 +1401,7 @@ __global__ __launch_bounds__(kThreads, 6) void k_annihilate_batch(const Inst<W, 
         const int i = owner_of(first, k, g);
         const Inst<W, V>& I = inst[i];
         if (wg_flags(I.ctl, &fl)) continue;  // this instance replays its step alone
-        annihilate_bucket<W, V, false>(I.sys, I.in, I.out, I.sc, I.rec2, I.soff, I.scount, I.rel, I.need_b, I.recs_b,
+        annihilate_bucket<W, V, false>(I.sys, I.in, I.out, I.sc, I.rec2, I.soff, I.scur, I.rel, I.need_b, I.recs_b,
                                 I.nw_b, I.en_b, I.fpos, I.fcnt, I.ctl, (int)(g - first[i]), L);
     }
 }
@@ -1370,7 +1433,8 @@ __global__ __launch_bounds__(kPostThreads) void k_post_batch(const Inst<W, V>* _
     __shared__ unsigned fl;
     const Inst<W, V>& I = inst[blockIdx.x];
     post_work<kPostThreads>(I.out.batt, I.out.count, I.nw_b, I.en_b, I.rel, I.need_b, I.recs_b, I.sc.B,
-                            I.out.aoff, I.soff, I.cmap, I.cmap_cap, I.ctl, ctl_out + blockIdx.x, sh, shd, shm, &fl);
+                            I.out.aoff, I.soff, I.scur, I.cmap, I.cmap_cap, I.ctl, ctl_out + blockIdx.x, sh, shd, shm,
+                            &fl);
 }
 
 // ---------------------------------------------------------------------------
@@ -1448,7 +1512,7 @@ __device__ __forceinline__ bool grid_barrier(GridBar* bar, unsigned* shok) {
 template <int W, class V, int GEN>
 __device__ __forceinline__ void spawn_member_chunk(const Inst<W, V>& I, int64_t g, int32_t* smpre) {
     if constexpr (GEN >= 0) {
-        spawn_chunk<W, V, GEN, false>(I.sys, I.in, I.sc, I.rec2, I.soff, I.scount, I.ctl, I.cmap, g, smpre, I.sys.J,
+        spawn_chunk<W, V, GEN, false>(I.sys, I.in, I.sc, I.rec2, I.scur, I.ctl, I.cmap, g, smpre, I.sys.J,
                                       I.sys.SK);
     } else {
         switch (I.gen) {
@@ -1495,7 +1559,7 @@ __global__ __launch_bounds__(kThreads, 6) void k_batch_step(const Inst<W, V>* __
         const int i = owner_of(bfirst, k, g);
         const Inst<W, V>& I = inst[i];
         if (wg_flags(I.ctl, &fl)) continue;  // this member replays its step alone
-        annihilate_bucket<W, V, false>(I.sys, I.in, I.out, I.sc, I.rec2, I.soff, I.scount, I.rel, I.need_b,
+        annihilate_bucket<W, V, false>(I.sys, I.in, I.out, I.sc, I.rec2, I.soff, I.scur, I.rel, I.need_b,
                                        I.recs_b, I.nw_b, I.en_b, I.fpos, I.fcnt, I.ctl, (int)(g - bfirst[i]), U.L);
     }
     if (!grid_barrier(bar, &ok)) return;
@@ -1512,7 +1576,7 @@ __global__ __launch_bounds__(kThreads, 6) void k_batch_step(const Inst<W, V>* __
     for (int i = blockIdx.x; i < k; i += gridDim.x) {
         const Inst<W, V>& I = inst[i];
         post_work<kThreads, 0>(I.out.batt, I.out.count, I.nw_b, I.en_b, I.rel, I.need_b, I.recs_b, I.sc.B,
-                               I.out.aoff, I.soff, I.cmap, I.cmap_cap, I.ctl, ctl_out + i, U.post.sh, U.post.shd,
+                               I.out.aoff, I.soff, I.scur, I.cmap, I.cmap_cap, I.ctl, ctl_out + i, U.post.sh, U.post.shd,
                                U.post.shm, &fl);
     }
 }
@@ -1639,7 +1703,7 @@ template <int W, class V>
 __global__ __launch_bounds__(kThreads) void k_ada_weights(SysView sys, Store<V> in, StepScalars sc,
                                                           const Rec<W, V>* __restrict__ rec2,
                                                           const int64_t* __restrict__ soff,
-                                                          const int32_t* __restrict__ scount, Ctl* ctl) {
+                                                          const uint64_t* __restrict__ scur, Ctl* ctl) {
     __shared__ AdaTable<W> T;
     for (int b = blockIdx.x; b < sc.B; b += gridDim.x) {
         const int64_t eb = (int64_t)b * sc.R;
@@ -1664,7 +1728,7 @@ __global__ __launch_bounds__(kThreads) void k_ada_weights(SysView sys, Store<V> 
 #pragma unroll
         for (int j = 0; j < kSub; ++j) {
             lo[j] = soff[(int64_t)b * kSub + j];
-            cum[j + 1] = cum[j] + scount[(int64_t)b * kSub + j];
+            cum[j + 1] = cum[j] + (int32_t)((uint32_t)scur[(int64_t)b * kSub + j] - (uint32_t)lo[j]);
         }
         for (int64_t q = threadIdx.x; q < cum[kSub]; q += kThreads) {
             int64_t src = 0;
