@@ -41,14 +41,19 @@ __device__ __forceinline__ R2 philox4x32(uint32_t c0, uint32_t c1, uint32_t c2, 
     constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
     // rounds kept as a loop: the key schedule then stays two scalar adds per
     // round instead of twenty hoisted round keys per stream spilled to
-    // vector lanes
+    // vector lanes.  Two rounds per pass, so that the words land back in
+    // their own registers without moves.
 #pragma unroll 1
-    for (int r = 0; r < 10; ++r) {
+    for (int r = 0; r < 5; ++r) {
         const uint32_t h0 = __umulhi(M0, c0), l0 = M0 * c0;
         const uint32_t h1 = __umulhi(M1, c2), l1 = M1 * c2;
-        const uint32_t n0 = h1 ^ c1 ^ k0;
-        const uint32_t n2 = h0 ^ c3 ^ k1;
-        c0 = n0; c1 = l1; c2 = n2; c3 = l0;
+        const uint32_t a0 = h1 ^ c1 ^ k0, a1 = l1;
+        const uint32_t a2 = h0 ^ c3 ^ k1, a3 = l0;
+        k0 += W0; k1 += W1;
+        const uint32_t g0 = __umulhi(M0, a0), m0 = M0 * a0;
+        const uint32_t g1 = __umulhi(M1, a2), m1 = M1 * a2;
+        c0 = g1 ^ a1 ^ k0; c1 = m1;
+        c2 = g0 ^ a3 ^ k1; c3 = m0;
         k0 += W0; k1 += W1;
     }
     R2 o;

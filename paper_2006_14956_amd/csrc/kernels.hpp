@@ -88,6 +88,18 @@ __device__ __forceinline__ int64_t slab_size(int32_t c) {
 
 template <class V> __device__ __forceinline__ double vabs(V v) { return v < 0 ? -(double)v : (double)v; }
 
+// Store of data nobody reads again in this launch (spawn records): marked
+// non-temporal, so the scattered lines stream out instead of displacing the
+// cached heat-bath tables and parent data.
+template <class T> __device__ __forceinline__ void store_stream(T* dst, const T& v) {
+    static_assert(sizeof(T) % 8 == 0, "8-byte words");
+    uint64_t w[sizeof(T) / 8];
+    __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 8); ++i)
+        __builtin_nontemporal_store(w[i], reinterpret_cast<uint64_t*>(dst) + i);
+}
+
 // a / C_min, the keep probability of the C_min rounding; at the usual
 // C_min = 1 the quotient is a itself (exact), and the wave-uniform branch
 // skips the division.  The empty asm keeps the compiler from computing the
@@ -312,7 +324,7 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
             const uint64_t cw = atomicAdd((unsigned long long*)&scur[j], 1ULL);
             const int64_t pos = (int64_t)(uint32_t)cw;
             if (pos < (int64_t)(cw >> 32) && pos < sc.spawn_cap) {
-                rec2[pos] = out;
+                store_stream(&rec2[pos], out);
                 if (EXT && sc.rec_par) {
                     sc.rec_par[pos] = (out_parent < 0) ? -1 : out_parent;
                     sc.rec_h[pos] = out_h;
