@@ -638,7 +638,7 @@ template <int W, class V> struct Engine : EngineBase {
         if (!sys->onsite) {
             const int64_t items = fresh_items(B);
             hipLaunchKernelGGL((k_fresh<W, V>), dim3((unsigned)std::min<int64_t>(items, 4096)), dim3(kThreads),
-                               fresh_lds_bytes(sys->N), stream, v, out, sc, fpos, fcnt, ctl);
+                               fresh_lds_bytes(sys->N, v.na + v.nb), stream, v, out, sc, fpos, fcnt, ctl);
         }
         mark(set, 2);
         if (sc.import_mode) {
@@ -1370,7 +1370,7 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
             ff[i] = ftot;
             if (!hi[i].sys.onsite) {
                 ftot += fresh_items(eng(i)->B);
-                flds = std::max(flds, fresh_lds_bytes(hi[i].sys.N));
+                flds = std::max(flds, fresh_lds_bytes(hi[i].sys.N, hi[i].sys.na + hi[i].sys.nb));
             }
         }
         bf[n] = btot;

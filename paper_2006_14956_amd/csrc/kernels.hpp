@@ -1076,7 +1076,40 @@ __host__ __device__ inline int64_t fresh_items(int B) {
     return (B + s - 1) / s;
 }
 
-__host__ __device__ inline size_t fresh_lds_bytes(int N) { return sizeof(double) * ((size_t)N + 2 * (size_t)N * N); }
+// h_pp, X and J (doubles), then each lane's occupied orbitals (one byte each,
+// lane-interleaved) for the n_el electrons.
+__host__ __device__ inline size_t fresh_lds_bytes(int N, int nel) {
+    return sizeof(double) * ((size_t)N + 2 * (size_t)N * N) + (size_t)nel * kThreads;
+}
+
+// The diagonal of h_diag_tab (same terms, same order) from the determinant's
+// occupied orbitals listed in LDS, alpha then beta, ascending: o[i * kThreads]
+// is the i-th.  Each term is an index read, a table read and an add, where
+// the bit-mask walk spent a dozen instructions finding the next orbital.
+__device__ __forceinline__ double h_diag_list(const double* hd, const double* X, const double* J, int N, int na,
+                                              int nb, const uint8_t* o) {
+    const int n = na + nb;
+    double acc = 0.0;
+    // unrolled by four: the index and table reads of four terms are in
+    // flight together, ahead of their (ordered) adds
+#pragma unroll 4
+    for (int i = 0; i < n; ++i) acc = acc + hd[o[i * kThreads]];
+    for (int i = 0; i < na; ++i) {
+        const int p = o[i * kThreads];
+        const double* xr = X + p * N;
+        const double* jr = J + p * N;
+#pragma unroll 4
+        for (int k = i + 1; k < na; ++k) acc = acc + xr[o[k * kThreads]];
+#pragma unroll 4
+        for (int k = na; k < n; ++k) acc = acc + jr[o[k * kThreads]];
+    }
+    for (int i = na; i < n; ++i) {
+        const double* xr = X + o[i * kThreads] * N;
+#pragma unroll 4
+        for (int k = i + 1; k < n; ++k) acc = acc + xr[o[k * kThreads]];
+    }
+    return acc;
+}
 
 template <int W, class V>
 __device__ __forceinline__ void fresh_item(const SysView& sys, const Store<V>& out, double h00, int R, int B,
@@ -1089,6 +1122,7 @@ __device__ __forceinline__ void fresh_item(const SysView& sys, const Store<V>& o
     double* hd = tabs;
     double* xt = tabs + N;
     double* jt = xt + N * N;
+    uint8_t* occ = reinterpret_cast<uint8_t*>(jt + N * N) + threadIdx.x;
     for (int i = threadIdx.x; i < N * N; i += kThreads) { xt[i] = sys.X[i]; jt[i] = sys.J[i]; }
     for (int i = threadIdx.x; i < N; i += kThreads) hd[i] = sys.Hd[i];
     if (threadIdx.x < nb) pre[threadIdx.x + 1] = fcnt[b0 + threadIdx.x];
@@ -1108,7 +1142,11 @@ __device__ __forceinline__ void fresh_item(const SysView& sys, const Store<V>& o
         const int64_t base = (int64_t)(b0 + lo) * R;
         const int64_t e = base + fpos[base + (t - pre[lo])];
         const Key<W> key = load_key<W>(out.keys + e * W);
-        const double h = h_diag_tab(hd, xt, jt, N, key_alpha<W>(key), key_beta<W>(key));
+        // every determinant of the store has na alpha and nb beta electrons
+        int i = 0;
+        for (uint64_t x = key_alpha<W>(key); x; x &= x - 1) occ[(i++) * kThreads] = (uint8_t)ctz64(x);
+        for (uint64_t x = key_beta<W>(key); x; x &= x - 1) occ[(i++) * kThreads] = (uint8_t)ctz64(x);
+        const double h = h_diag_list(hd, xt, jt, N, sys.na, sys.nb, occ);
         out.diag[e] = h - h00;
     }
     __syncthreads();
