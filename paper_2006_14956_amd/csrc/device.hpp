@@ -180,17 +180,14 @@ __device__ __forceinline__ void pair_decode(uint64_t q, int n, int& x, int& y) {
 // --------------------------------------------------------------------------
 // Integrals.
 // --------------------------------------------------------------------------
-// One column of a heat-bath alias table, packed so that a draw reads a
-// single aligned 32-byte entry: the alias threshold and column, and for
-// both outcomes (this column and its alias) the signed two-electron value v
-// whose magnitude is the column's weight: (AI|BJ) for opposite spins,
-// (AI|BJ) - (AJ|BI) for equal spins, 0 where the weight is zeroed.  |v|
-// gives p(ab|ij) with the row sum, and v gives H_ij up to the fermion sign.
-struct alignas(32) HbEntry {
-    double prob;
-    double v_self;
-    double v_alias;
-    int32_t alias;
+// One column of a heat-bath alias table, one aligned 16-byte entry: the
+// alias threshold and column.  A draw reads one entry; the drawn column's
+// signed two-electron value v (whose magnitude is its weight) comes from the
+// packed integrals, a table small enough to stay in L2, so the alias tables
+// take half the memory of entries that carry both outcomes' values.
+struct alignas(16) HbEntry {
+    double prob;     // alias threshold of the column
+    int32_t alias;   // the column's alias
     int32_t pad;
 };
 
@@ -467,14 +464,8 @@ __device__ __forceinline__ bool gen_pchb(const SysView& s, uint64_t a, uint64_t 
     const HbEntry* tab = opp ? s.hb_opp : s.hb_same;
     const int c0 = (int)pick(r.x[2], (uint64_t)K);
     const double coin = unif(r.x[2] * (uint64_t)K);
-    // p(ab|ij) = w_ab / sum_row with w_ab = |v|; a zero weight (or a zero
-    // row) is a null draw
     const HbEntry en = tab[(size_t)row * (size_t)K + c0];
-    const bool self = coin < en.prob;
-    const int c = self ? c0 : en.alias;
-    const double v = self ? en.v_self : en.v_alias;
-    const double wc = fabs(v);
-    if (wc == 0.0) return false;
+    const int c = coin < en.prob ? c0 : en.alias;
     int A, Bo;
     if (opp) {
         A = c / N;
@@ -487,6 +478,16 @@ __device__ __forceinline__ bool gen_pchb(const SysView& s, uint64_t a, uint64_t 
     const int sA = sI, sB = sJ;
     const uint64_t mA = sA ? b : a, mB = sB ? b : a;
     if (((mA >> A) & 1ULL) || ((mB >> Bo) & 1ULL)) return false;
+    // the column's signed two-electron value, the integral its weight was
+    // built from: (AI|BJ), less (AJ|BI) for equal spins, zero where the hole
+    // pair meets the electron pair.  p(ab|ij) = w_ab / sum_row with
+    // w_ab = |v|; a zero weight (or a zero row) is a null draw.
+    const bool z = A == I || Bo == J || (!opp && (A == J || Bo == I));
+    const double d = eri(s, A, I, Bo, J);
+    const double e = opp ? 0.0 : eri(s, A, J, Bo, I);
+    const double v = z ? 0.0 : d - e;
+    const double wc = fabs(v);
+    if (wc == 0.0) return false;
     const double sum = (opp ? s.hb_sum_opp : s.hb_sum_same)[row];
     const double p1 = p_double * (opp ? p_opp : 1.0 - p_opp);
     const double p2 = p1 / (double)ncls;

@@ -186,10 +186,11 @@ static int build_pchb(fciqmc_system* s, hipStream_t stream) {
     const int rows = NN + np;
     hipLaunchKernelGGL(k_pchb_build, dim3((rows + 63) / 64), dim3(64), 0, stream, v, w_opp, p_opp, a_opp,
                        s->hb_sum_opp, w_same, p_same, a_same, s->hb_sum_same, scaled, small, large);
-    hipLaunchKernelGGL(k_pchb_pack, dim3(4096), dim3(256), 0, stream, v, true, p_opp, a_opp, NN, NN, s->hb_opp);
+    hipLaunchKernelGGL(k_pchb_pack, dim3(4096), dim3(256), 0, stream, (const double*)p_opp, (const int*)a_opp, ko,
+                       s->hb_opp);
     if (np > 0)
-        hipLaunchKernelGGL(k_pchb_pack, dim3(4096), dim3(256), 0, stream, v, false, p_same, a_same, np, np,
-                           s->hb_same);
+        hipLaunchKernelGGL(k_pchb_pack, dim3(4096), dim3(256), 0, stream, (const double*)p_same, (const int*)a_same,
+                           ks, s->hb_same);
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(stream));
     tmp.clear();
@@ -2361,10 +2362,29 @@ extern "C" int fciqmc_pchb_row(const fciqmc_system* csys, int opp, int64_t row, 
     const HbEntry* src = (opp ? sys->hb_opp : sys->hb_same) + (size_t)row * (size_t)K;
     HIP_OK(hipMemcpy(h.data(), src, sizeof(HbEntry) * K, hipMemcpyDeviceToHost));
     HIP_OK(hipMemcpy(sum, (opp ? sys->hb_sum_opp : sys->hb_sum_same) + row, sizeof(double), hipMemcpyDeviceToHost));
+    // the weights from the integrals, as the construction forms them: row
+    // (I alpha, J beta) or I < J; column (A, B) ordered, or A < B in
+    // lexicographic order
+    auto eri = [&](int64_t p, int64_t q, int64_t r, int64_t t) {
+        auto tri = [](int64_t x, int64_t y) { return x >= y ? x * (x + 1) / 2 + y : y * (y + 1) / 2 + x; };
+        const int64_t X = tri(p, q), Y = tri(r, t);
+        return sys->eri_host[(size_t)tri(X, Y)];
+    };
+    auto pair = [N](int64_t k, int64_t& x, int64_t& y) {
+        for (x = 0; k >= N - 1 - x; ++x) k -= N - 1 - x;
+        y = x + 1 + k;
+    };
+    int64_t I, J;
+    if (opp) { I = row / N; J = row % N; } else pair(row, I, J);
     for (int64_t c = 0; c < K; ++c) {
         prob[c] = h[(size_t)c].prob;
         alias[c] = h[(size_t)c].alias;
-        weight[c] = std::fabs(h[(size_t)c].v_self);
+        int64_t A, B;
+        if (opp) { A = c / N; B = c % N; } else pair(c, A, B);
+        double v;
+        if (opp) v = (A == I || B == J) ? 0.0 : eri(A, I, B, J);
+        else v = (A == I || A == J || B == I || B == J) ? 0.0 : eri(A, I, B, J) - eri(A, J, B, I);
+        weight[c] = std::fabs(v);
     }
     return 0;
 }

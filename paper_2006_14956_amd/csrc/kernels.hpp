@@ -1357,39 +1357,16 @@ __global__ void k_chunk_map(const int64_t* __restrict__ aoff, int B, int64_t* __
         for (int64_t c = aoff[b]; c < aoff[b + 1]; ++c) cmap[c] = ((int64_t)b << 32) | (c - aoff[b]);
 }
 
-// Pack the heat-bath tables into 32-byte entries: alias threshold and column
-// from the construction, and the signed two-electron value of the column
-// and of its alias (the same integrals and the same zeroing as the weights).
-__device__ __forceinline__ double hb_value(const SysView& s, bool opp, int I, int J, int col) {
-    const int N = s.N;
-    if (opp) {
-        const int A = col / N, B = col % N;
-        if (A == I || B == J) return 0.0;
-        return eri(s, A, I, B, J);
-    }
-    const int ab = s.pair_of[col];
-    const int A = ab >> 6, B = ab & 63;
-    if (A == I || A == J || B == I || B == J) return 0.0;
-    const double d = eri(s, A, I, B, J);
-    const double e = eri(s, A, J, B, I);
-    return d - e;
-}
-
-__global__ void k_pchb_pack(SysView sys, bool opp, const double* __restrict__ p, const int* __restrict__ a,
-                            int rows, int K, HbEntry* __restrict__ out) {
-    const int N = sys.N;
-    const size_t n = (size_t)rows * (size_t)K;
+// Pack the heat-bath tables into 16-byte entries: alias threshold and column
+// from the construction (the generator takes the drawn column's value from
+// the integrals).
+__global__ void k_pchb_pack(const double* __restrict__ p, const int* __restrict__ a, size_t n,
+                            HbEntry* __restrict__ out) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const int row = (int)(i / (size_t)K), col = (int)(i % (size_t)K);
-        int I, J;
-        if (opp) { I = row / N; J = row % N; }
-        else pair_decode((uint64_t)row, N, I, J);
         HbEntry e;
         e.prob = p[i];
         e.alias = a[i];
         e.pad = 0;
-        e.v_self = hb_value(sys, opp, I, J, col);
-        e.v_alias = hb_value(sys, opp, I, J, a[i]);
         out[i] = e;
     }
 }
