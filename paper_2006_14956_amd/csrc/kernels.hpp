@@ -342,8 +342,14 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
 // global memory.
 constexpr int kCsLdsMaxN = 45;
 
+// Waves per SIMD the spawn kernel is compiled for: the table-driven
+// generators fit eight (its latency-bound gathers want every wave the SIMD
+// holds), at the price of a few scalar registers kept in vector lanes; the
+// on-the-fly generators keep the compiler's own choice rather than spill.
+template <int GEN> constexpr int kSpawnWaves = GEN <= 2 ? 8 : 1;
+
 template <int W, class V, int GEN, bool EXT>
-__global__ __launch_bounds__(kThreads) void k_spawn(SysView sys, Store<V> st, StepScalars sc,
+__global__ __launch_bounds__(kThreads, kSpawnWaves<GEN>) void k_spawn(SysView sys, Store<V> st, StepScalars sc,
                                                     Rec<W, V>* __restrict__ rec2,
                                                     uint64_t* __restrict__ scur, Ctl* ctl,
                                                     const int64_t* __restrict__ cmap, int64_t cmap_cap) {
