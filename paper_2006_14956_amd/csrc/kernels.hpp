@@ -716,6 +716,19 @@ __device__ __forceinline__ void post_work(const int64_t* __restrict__ batt, cons
 // ---------------------------------------------------------------------------
 constexpr int64_t kM40 = (1LL << 40) - 1;
 
+// Place in the record buffer of a bucket's q-th record, its sub-slabs
+// walked as one sequence: cum[j] records precede sub-slab j (ascending), and
+// base[j] is the sub-slab's start less cum[j].  Each sub-slab's range is
+// tested on its own (unrolled selects of register values; a select of the
+// last sub-slab with cum[j] <= q compiles to an indexed private-memory load).
+__device__ __forceinline__ int64_t rec_place(const int64_t* base, const int32_t* cum, int32_t q) {
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kSub; ++j)
+        if (q >= cum[j] && q < cum[j + 1]) s = base[j];
+    return s + q;
+}
+
 // The step's flag word, read once for the whole workgroup so that every wave
 // takes the same branch (another workgroup may set a flag meanwhile).
 __device__ __forceinline__ unsigned wg_flags(const Ctl* ctl, unsigned* sh) {
@@ -739,23 +752,25 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
     const int64_t eb = (int64_t)b * sc.R;
     const int cnt = sc.import_mode ? 0 : in.count[b];
     // the bucket's records: its kSub sub-slabs, walked as one sequence
-    // (cumulative counts and starts held in registers, selected unrolled)
-    int64_t cum[kSub + 1], lo[kSub];
-    int32_t cj[kSub];
+    // (cumulative counts and starts held in registers)
+    int64_t lo[kSub], base[kSub];
+    int32_t cj[kSub], cum[kSub + 1];
     cum[0] = 0;
 #pragma unroll
     for (int j = 0; j < kSub; ++j) {
         lo[j] = soff[(int64_t)b * kSub + j];
         cj[j] = (int32_t)((uint32_t)scur[(int64_t)b * kSub + j] - (uint32_t)lo[j]);
         cum[j + 1] = cum[j] + cj[j];
+        base[j] = lo[j] - cum[j];
     }
+    const int32_t nrec = cum[kSub];
     // LDS table sized to the bucket: keys <= determinants + records, load <= 3/4
-    const int64_t want = ((int64_t)cnt + cum[kSub]) * 4 / 3 + 1;
+    const int64_t want = ((int64_t)cnt + nrec) * 4 / 3 + 1;
     int nslots = kThreads;
     while (nslots < want && nslots < kSlots) nslots <<= 1;
     const uint64_t mask = (uint64_t)(nslots - 1);
-    // this thread's first determinant and first record are loaded now, so
-    // their latency overlaps the table reset (and the death pass)
+    // this thread's first determinant and first two records are loaded now,
+    // so their latency overlaps the table reset and the death pass
     const int e0 = (int)threadIdx.x;
     Key<W> pk;
     V pC = (V)0;
@@ -765,14 +780,9 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
         pC = in.vals[eb + e0];
         pd = in.diag[eb + e0];
     }
-    Rec<W, V> prec;
-    if ((int64_t)e0 < cum[kSub]) {
-        int64_t src = 0;
-#pragma unroll
-        for (int j = 0; j < kSub; ++j)
-            if (e0 >= cum[j] && e0 < cum[j + 1]) src = lo[j] + (e0 - cum[j]);
-        prec = rec2[src];
-    }
+    Rec<W, V> prec, prec2;
+    if (e0 < nrec) prec = rec2[rec_place(base, cum, e0)];
+    if (e0 + kThreads < nrec) prec2 = rec2[rec_place(base, cum, e0 + kThreads)];
     for (int i = threadIdx.x; i < nslots; i += kThreads) {
         L.t.key0[i] = kEmpty;
         if constexpr (W == 2) L.t.key1[i] = kEmpty;
@@ -782,20 +792,9 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
     if (threadIdx.x == 0) L.nfresh = 0;
     __syncthreads();
     // (b) death of the walkers occupied at tau: x = (1 - dtau (d_i - S)) C_i,
-    // stochastically rounded; the slot is marked as occupied at tau.
-    for (int e = e0; e < cnt; e += kThreads) {
-        Key<W> key;
-        V C;
-        double d;
-        if (e == e0) {
-            key = pk;
-            C = pC;
-            d = pd;
-        } else {
-            key = load_key<W>(in.keys + (eb + e) * W);
-            C = in.vals[eb + e];
-            d = in.diag[eb + e];
-        }
+    // stochastically rounded; the slot is marked as occupied at tau.  The
+    // first determinant is the prefetched one.
+    auto death = [&](const Key<W>& key, const V C, const double d, const int e) {
         V post;
         if (EXT && sc.ncore > 0 && is_core(d)) {
             // deterministic space: P^D C, diagonal included, unrounded
@@ -834,28 +833,30 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
             }
         }
         const int s = lds_find<W>(L.t, key, key_hash<W>(key), mask, true);
-        if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); continue; }
+        if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); return; }
         L.t.val[s] = post;
         L.t.idx[s] = e;
-    }
+    };
+    if (e0 < cnt) death(pk, pC, pd, e0);
+    for (int e = e0 + kThreads; e < cnt; e += kThreads)
+        death(load_key<W>(in.keys + (eb + e) * W), in.vals[eb + e], in.diag[eb + e], e);
     __syncthreads();
     // (c) annihilation: a target occupied at tau takes every contribution;
-    // an unoccupied one only those of initiator parents (Sec. I).
-    for (int64_t q = e0; q < cum[kSub]; q += kThreads) {
-        int64_t src = 0;
-#pragma unroll
-        for (int j = 0; j < kSub; ++j)
-            if (q >= cum[j] && q < cum[j + 1]) src = lo[j] + (q - cum[j]);
-        const Rec<W, V> x = q == e0 ? prec : rec2[src];
+    // an unoccupied one only those of initiator parents (Sec. I).  The first
+    // two records are the prefetched ones.
+    auto merge = [&](const Rec<W, V>& x) {
         Key<W> key;
 #pragma unroll
         for (int w = 0; w < W; ++w) key.w[w] = x.k[w];
         const bool init = (x.flag & 1u) != 0;
         const int s = lds_find<W>(L.t, key, (uint64_t)(x.flag >> 1), mask, init);
-        if (s == -1) continue;
-        if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); continue; }
+        if (s == -1) return;
+        if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); return; }
         if (init || L.t.idx[s] >= 0) lds_add<V>(&L.t.val[s], x.v);
-    }
+    };
+    if (e0 < nrec) merge(prec);
+    if (e0 + kThreads < nrec) merge(prec2);
+    for (int32_t q = e0 + 2 * kThreads; q < nrec; q += kThreads) merge(rec2[rec_place(base, cum, q)]);
     __syncthreads();
     if (EXT && sc.rej != nullptr && !sc.import_mode) {
         // discarded spawns: non-initiator records whose target is in neither
@@ -863,16 +864,12 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
         // it), kept in record order in the bucket's region of the buffer
         Rec<W, V>* rej = static_cast<Rec<W, V>*>(sc.rej);
         int64_t nb = 0;
-        for (int64_t q0 = 0; q0 < cum[kSub]; q0 += kThreads) {
-            const int64_t q = q0 + threadIdx.x;
+        for (int32_t q0 = 0; q0 < nrec; q0 += kThreads) {
+            const int32_t q = q0 + (int32_t)threadIdx.x;
             bool dropped = false;
             Rec<W, V> x;
-            if (q < cum[kSub]) {
-                int64_t src = 0;
-#pragma unroll
-                for (int j = 0; j < kSub; ++j)
-                    if (q >= cum[j] && q < cum[j + 1]) src = lo[j] + (q - cum[j]);
-                x = rec2[src];
+            if (q < nrec) {
+                x = rec2[rec_place(base, cum, q)];
                 if (!(x.flag & 1u)) {
                     Key<W> key;
 #pragma unroll
@@ -910,7 +907,7 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
             rel[(int64_t)b * kSub + j] = inc - sz;
             if (j == kSub - 1) need_b[b] = inc;
         }
-        if (j == 0) recs_b[b] = cum[kSub];
+        if (j == 0) recs_b[b] = nrec;
     }
     // compaction: (1) each thread rounds its run of nslots / kThreads
     // consecutive slots in place (small real amplitudes) and drops what it
