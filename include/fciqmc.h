@@ -204,13 +204,17 @@ int fciqmc_set_walkers(fciqmc_run *run, const uint64_t *dets, const double *vals
  * n_core determinants of largest |C| in the current population (ties:
  * ascending alpha, then beta mask) the deterministic space D.  From the
  * next step on, the projector's elements between determinants of D are
- * applied exactly (a sparse product with H^D, built here on the device by
- * testing all pairs) and only the rest is sampled: spawns from D into D are
+ * applied exactly (a sparse product with H^D, built here on the device from
+ * removal keys: two determinants are connected exactly when taking one or
+ * two electrons out of each leaves the same strings, so pairs are found by
+ * hashing those keys, in time linear in |D|) and only the rest is sampled
+ * (the paper builds H^D with the fast scheme it cites): spawns from D into D are
  * dropped, the determinants of D have no stochastic death, are never
  * compressed to C_min, stay in the population at any value (zero included)
  * and count as initiators.  Calling it again re-selects D from the current
  * population; n_core = 0 removes it.  Real mode only (EINVAL otherwise);
- * 0 <= n_core <= 131072 (EINVAL); a run in a batch: ESTATE, and a run with
+ * 0 <= n_core <= 8388608 (EINVAL; the device memory budget may bind first:
+ * ENOMEM); a run in a batch: ESTATE, and a run with
  * a deterministic space cannot join a batch.  *n_out (may be NULL)
  * receives |D| = min(n_core, determinants). */
 int fciqmc_set_core(fciqmc_run *run, int64_t n_core, int64_t *n_out);
@@ -220,6 +224,13 @@ int fciqmc_set_core(fciqmc_run *run, int64_t n_core, int64_t *n_out);
  * capacity determinants as (alpha, beta) mask pairs, ascending. */
 int fciqmc_get_core(const fciqmc_run *run, uint64_t *dets, int64_t capacity, int64_t *n_out,
                     int64_t *nnz_out);
+/* Row k of H^D (0 <= k < |D|, determinants in the order fciqmc_get_core
+ * gives), for parity checks: *n_out (may be NULL) = its off-diagonal
+ * nonzeros; cols and vals (host, may be NULL) receive up to cap of them,
+ * the column's index in D and H_kj = <D_k|H|D_j>, in no particular order.
+ * EINVAL for k out of range. */
+int fciqmc_get_core_row(const fciqmc_run *run, int64_t k, int32_t *cols, double *vals, int64_t cap,
+                        int64_t *n_out);
 /* The current reference of the projected energy (alpha, beta masks) and its
  * H_PP + e_core (any output may be NULL). */
 int fciqmc_get_reference(const fciqmc_run *run, uint64_t *alpha, uint64_t *beta, double *e_ref);

@@ -51,6 +51,9 @@ def lib():
         L.orc_hdiag.argtypes = [vp, u64, u64]
         L.orc_hij.restype = dbl
         L.orc_hij.argtypes = [vp, u64, u64, u64, u64]
+        L.orc_hij_row.restype = None
+        L.orc_hij_row.argtypes = [vp, u64, u64, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.c_int64,
+                                  C.POINTER(dbl)]
         L.orc_uniform_apply_flat.argtypes = [vp, u64, u64, C.c_int, u64, u64, dbl, pu64, pu64, pdbl]
         L.orc_uniform_count2_flat.restype = u64
         L.orc_uniform_count2_flat.argtypes = [vp, u64, u64, C.c_int, u64]
@@ -163,6 +166,16 @@ class System:
 
     def hij(self, a1, b1, a2, b2):
         return lib().orc_hij(self.ptr, int(a1), int(b1), int(a2), int(b2))
+
+    def hij_row(self, ar, br, a, b):
+        """<D_row|H|D_j> for every (a[j], b[j]) (0 where D_j = D_row), the
+        orientation of the deterministic-space matrix."""
+        a = np.ascontiguousarray(a, dtype=np.uint64)
+        b = np.ascontiguousarray(b, dtype=np.uint64)
+        out = np.zeros(len(a), dtype=np.float64)
+        lib().orc_hij_row(self.ptr, int(ar), int(br), _p(a, C.c_uint64), _p(b, C.c_uint64), len(a),
+                          _p(out, C.c_double))
+        return out
 
     def build_pchb(self):
         if not self._pchb:

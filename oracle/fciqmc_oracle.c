@@ -1889,6 +1889,19 @@ double orc_hij(const orc_sys *s, uint64_t a1, uint64_t b1, uint64_t a2, uint64_t
     return orc_hij_det(s, d1, d2);
 }
 
+/* One row of the deterministic-space matrix, as orc_run_set_core fills it:
+ * out[j] = <D_row|H|D_j> = orc_hij(D_j, D_row) for the n determinants
+ * (a[j], b[j]) (out[j] = 0 where D_j = D_row). */
+void orc_hij_row(const orc_sys *s, uint64_t ar, uint64_t br, const uint64_t *a, const uint64_t *b, int64_t n,
+                 double *out)
+{
+    det_t dr = {ar, br};
+    for (int64_t j = 0; j < n; ++j) {
+        det_t dj = {a[j], b[j]};
+        out[j] = (a[j] == ar && b[j] == br) ? 0.0 : orc_hij_det(s, dj, dr);
+    }
+}
+
 /* Draw-level generator entry (for frequency tests): returns 1 and the target
  * for a null-free draw from the Philox block of (det, t, k). */
 int orc_generate(const orc_run *r, uint64_t a, uint64_t b, int64_t t, uint64_t k,

@@ -235,6 +235,7 @@ struct EngineBase {
     virtual int64_t core_size() const = 0;
     virtual int64_t core_nnz() const = 0;
     virtual const std::vector<uint64_t>& core_dets() const = 0;
+    virtual int core_row(int64_t k, int32_t* cols, double* vals, int64_t cap, int64_t* n_out) = 0;
     // discarded spawns of each step, kept for a replica pair's PT2 correction
     virtual int set_collect(bool on) = 0;
     virtual void* rej_records() const = 0;
@@ -255,7 +256,11 @@ struct EngineBase {
 };
 
 // Largest deterministic space: H^D is built by testing all N_D^2 pairs.
-constexpr int64_t kMaxCore = 1 << 17;
+constexpr int64_t kMaxCore = 1 << 23;
+// Removal-key entries a pass of the H^D construction takes at most (its hash
+// table has four slots per entry); a class with more entries is split into
+// passes by the hash's bits.
+constexpr int64_t kRkPerPass = 1 << 24;
 
 // Engines of one kind share batched launches: 0 = (1 word, int32),
 // 1 = (1 word, FP64), 2 = (2 words, int32), 3 = (2 words, FP64).
@@ -838,29 +843,118 @@ template <int W, class V> struct Engine : EngineBase {
         hipLaunchKernelGGL((k_core_hash<W>), dim3(g), dim3(256), 0, stream, core_keys, nc, core_hkeys, core_hidx,
                            core_hmask);
         hipLaunchKernelGGL((k_core_diag<W>), dim3(g), dim3(256), 0, stream, v, core_keys, nc, rs.h00, core_cdiag);
-        // H^D: row counts, their prefix on the host, then the rows
-        int64_t* cnt = nullptr;
-        Arena tmp;
-        CHECK(dalloc(tmp, &cnt, (size_t)nc));
-        const unsigned gr = (unsigned)std::min<int64_t>(nc, 65536);
-        hipLaunchKernelGGL((k_core_rows<W>), dim3(gr), dim3(kThreads), 0, stream, v, core_keys, nc,
-                           (const int64_t*)nullptr, (int32_t*)nullptr, (double*)nullptr, cnt);
-        HIP_OK(hipGetLastError());
-        std::vector<int64_t> hc((size_t)nc), rp((size_t)nc + 1, 0);
-        HIP_OK(hipMemcpyAsync(hc.data(), cnt, sizeof(int64_t) * nc, hipMemcpyDeviceToHost, stream));
-        HIP_OK(hipStreamSynchronize(stream));
-        for (int64_t k = 0; k < nc; ++k) rp[(size_t)k + 1] = rp[(size_t)k] + hc[(size_t)k];
-        nnz = rp[(size_t)nc];
-        CHECK(dalloc(arena, &core_col, (size_t)std::max<int64_t>(nnz, 1)));
-        CHECK(dalloc(arena, &core_val, (size_t)std::max<int64_t>(nnz, 1)));
-        HIP_OK(hipMemcpyAsync(core_rowp, rp.data(), sizeof(int64_t) * (nc + 1), hipMemcpyHostToDevice, stream));
-        hipLaunchKernelGGL((k_core_rows<W>), dim3(gr), dim3(kThreads), 0, stream, v, core_keys, nc,
-                           (const int64_t*)core_rowp, core_col, core_val, (int64_t*)nullptr);
-        HIP_OK(hipGetLastError());
-        HIP_OK(hipStreamSynchronize(stream));
-        tmp.clear();
+        CHECK(build_hd(nc));
         ncore = nc;
         return tag_core();
+    }
+    // H^D between the space's determinants, by removal keys: for each of the
+    // five classes (and hash partition), count the keys, gather the repeated
+    // ones into groups and test their pairs; a counting sweep gives the row
+    // sizes, their prefix on the host the row starts, and a filling sweep the
+    // entries (a row's order is the order its pairs were found in).
+    int build_hd(int64_t nc) {
+        const SysView v = sys->view();
+        const int na = v.na, nb = v.nb;
+        auto removals = [&](int c) -> int64_t {
+            switch (c) {
+                case 0: return nb;
+                case 1: return (int64_t)nb * (nb - 1) / 2;
+                case 2: return na;
+                case 3: return (int64_t)na * (na - 1) / 2;
+                default: return (int64_t)na * nb;
+            }
+        };
+        Arena tmp;
+        struct Release {
+            Arena& a;
+            hipStream_t s;
+            ~Release() { (void)hipStreamSynchronize(s); a.clear(); }
+        } release{tmp, stream};
+        unsigned long long *cnt = nullptr, *rfill = nullptr, *totals = nullptr;
+        unsigned* err = nullptr;
+        CHECK(dalloc(tmp, &cnt, (size_t)nc));
+        CHECK(dalloc(tmp, &rfill, (size_t)nc));
+        CHECK(dalloc(tmp, &totals, 2));
+        CHECK(dalloc(tmp, &err, 1));
+        HIP_OK(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * nc, stream));
+        HIP_OK(hipMemsetAsync(rfill, 0, sizeof(unsigned long long) * nc, stream));
+        HIP_OK(hipMemsetAsync(err, 0, sizeof(unsigned), stream));
+        int64_t emax = 0;
+        for (int c = 0; c < 5; ++c) emax = std::max(emax, nc * removals(c));
+        const int64_t per = std::min(emax, kRkPerPass);
+        const int64_t slots = (int64_t)next_pow2((uint64_t)(4 * per + 64));
+        uint64_t* th = nullptr;
+        uint32_t *tc = nullptr, *gsize = nullptr, *gfill = nullptr;
+        int32_t* tg = nullptr;
+        int64_t* gstart = nullptr;
+        uint64_t* gm = nullptr;
+        int64_t gcap = per + 64, gmcap = 2 * per + 64;
+        CHECK(dalloc(tmp, &th, (size_t)slots));
+        CHECK(dalloc(tmp, &tc, (size_t)slots));
+        CHECK(dalloc(tmp, &tg, (size_t)slots));
+        CHECK(dalloc(tmp, &gstart, (size_t)gcap));
+        CHECK(dalloc(tmp, &gsize, (size_t)gcap));
+        CHECK(dalloc(tmp, &gfill, (size_t)gcap));
+        CHECK(dalloc(tmp, &gm, (size_t)gmcap));
+        int64_t* rowp_h = nullptr;
+        std::vector<int64_t> rp((size_t)nc + 1, 0);
+        for (int sweep = 0; sweep < 2; ++sweep) {
+            if (sweep == 1) {
+                std::vector<unsigned long long> hc((size_t)nc);
+                HIP_OK(hipMemcpyAsync(hc.data(), cnt, sizeof(unsigned long long) * nc, hipMemcpyDeviceToHost, stream));
+                HIP_OK(hipStreamSynchronize(stream));
+                for (int64_t k = 0; k < nc; ++k) rp[(size_t)k + 1] = rp[(size_t)k] + (int64_t)hc[(size_t)k];
+                nnz = rp[(size_t)nc];
+                CHECK(dalloc(arena, &core_col, (size_t)std::max<int64_t>(nnz, 1)));
+                CHECK(dalloc(arena, &core_val, (size_t)std::max<int64_t>(nnz, 1)));
+                HIP_OK(hipMemcpyAsync(core_rowp, rp.data(), sizeof(int64_t) * (nc + 1), hipMemcpyHostToDevice,
+                                      stream));
+                rowp_h = core_rowp;
+            }
+            for (int c = 0; c < 5 && nc >= 2; ++c) {
+                const int64_t M = removals(c);
+                if (M == 0) continue;
+                const int64_t E = nc * M;
+                const int nparts = (int)((E + per - 1) / per);
+                for (int part = 0; part < nparts; ++part) {
+                    const int64_t pe = (E + nparts - 1) / nparts;
+                    const int64_t ps = (int64_t)next_pow2((uint64_t)(4 * pe + 64));
+                    RkPass P{c, na, nb, part, nparts, nc, M, (uint64_t)ps - 1};
+                    HIP_OK(hipMemsetAsync(th, 0xFF, sizeof(uint64_t) * ps, stream));
+                    HIP_OK(hipMemsetAsync(tc, 0, sizeof(uint32_t) * ps, stream));
+                    HIP_OK(hipMemsetAsync(totals, 0, sizeof(unsigned long long) * 2, stream));
+                    const unsigned ge = (unsigned)std::min<int64_t>((E + 255) / 256, 65536);
+                    const unsigned gs = (unsigned)std::min<int64_t>((ps + 255) / 256, 65536);
+                    hipLaunchKernelGGL((k_rk_count<W>), dim3(ge), dim3(256), 0, stream, core_keys, P, th, tc, err);
+                    hipLaunchKernelGGL(k_rk_groups, dim3(gs), dim3(256), 0, stream, (const uint32_t*)tc, (uint64_t)ps,
+                                       tg, gstart, gsize, gcap, totals, err);
+                    unsigned long long ht[2];
+                    unsigned herr = 0;
+                    HIP_OK(hipMemcpyAsync(ht, totals, sizeof(ht), hipMemcpyDeviceToHost, stream));
+                    HIP_OK(hipMemcpyAsync(&herr, err, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+                    HIP_OK(hipStreamSynchronize(stream));
+                    if (herr || (int64_t)ht[0] > gcap || (int64_t)ht[1] > gmcap)
+                        return fail(FCIQMC_EOVERFLOW, "H^D construction: %llu groups of %llu entries exceed the "
+                                    "pass capacity (%lld, %lld) or its table (flags %u)", ht[0], ht[1],
+                                    (long long)gcap, (long long)gmcap, herr);
+                    if (ht[0] == 0) continue;
+                    HIP_OK(hipMemsetAsync(gfill, 0, sizeof(uint32_t) * ht[0], stream));
+                    hipLaunchKernelGGL((k_rk_scatter<W>), dim3(ge), dim3(256), 0, stream, core_keys, P,
+                                       (const uint64_t*)th, (const int32_t*)tg, (const int64_t*)gstart, gfill, gm,
+                                       gmcap);
+                    const unsigned gp = (unsigned)std::min<unsigned long long>((ht[0] + 3) / 4, 65536);
+                    hipLaunchKernelGGL((k_rk_pairs<W>), dim3(gp), dim3(256), 0, stream, v, core_keys, P,
+                                       (const int64_t*)gstart, (const uint32_t*)gsize, (int64_t)ht[0],
+                                       (const uint64_t*)gm, cnt, (const int64_t*)rowp_h, rfill, core_col, core_val);
+                    HIP_OK(hipGetLastError());
+                }
+            }
+        }
+        HIP_OK(hipStreamSynchronize(stream));
+        unsigned herr = 0;
+        HIP_OK(hipMemcpy(&herr, err, sizeof(unsigned), hipMemcpyDeviceToHost));
+        if (herr) return fail(FCIQMC_EDEVICE, "H^D construction: table overflow (flags %u)", herr);
+        return 0;
     }
     int set_collect(bool on) override {
         if (on == keep_rej) return 0;
@@ -940,6 +1034,17 @@ template <int W, class V> struct Engine : EngineBase {
     int64_t core_size() const override { return ncore; }
     int64_t core_nnz() const override { return nnz; }
     const std::vector<uint64_t>& core_dets() const override { return core_host; }
+    int core_row(int64_t k, int32_t* cols, double* vals, int64_t cap, int64_t* n_out) override {
+        if (k < 0 || k >= ncore)
+            return fail(FCIQMC_EINVAL, "row %lld out of range [0, %lld)", (long long)k, (long long)ncore);
+        int64_t r[2];
+        HIP_OK(hipMemcpy(r, core_rowp + k, sizeof(r), hipMemcpyDeviceToHost));
+        const int64_t n = r[1] - r[0], m = std::min(n, std::max<int64_t>(cap, 0));
+        if (n_out) *n_out = n;
+        if (cols && m > 0) HIP_OK(hipMemcpy(cols, core_col + r[0], sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+        if (vals && m > 0) HIP_OK(hipMemcpy(vals, core_val + r[0], sizeof(double) * m, hipMemcpyDeviceToHost));
+        return 0;
+    }
 
     int get_walkers(std::vector<uint64_t>& ab, std::vector<double>& vals) override {
         CHECK(refuse_if_broken());
@@ -2245,6 +2350,12 @@ int fciqmc_get_core(const fciqmc_run* run, uint64_t* dets, int64_t capacity, int
         const int64_t m = std::min(n, capacity);
         std::copy(c.begin(), c.begin() + 2 * m, dets);
     }
+    return 0;
+}
+
+int fciqmc_get_core_row(const fciqmc_run* run, int64_t k, int32_t* cols, double* vals, int64_t cap, int64_t* n_out) {
+    if (!run || !run->eng) return fail(FCIQMC_ESTATE, "run not initialised");
+    CHECK(run->eng->core_row(k, cols, vals, cap, n_out));
     return 0;
 }
 

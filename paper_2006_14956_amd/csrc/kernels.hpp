@@ -2163,36 +2163,202 @@ __global__ void k_core_hash(const uint64_t* __restrict__ keys, int64_t n, uint64
     }
 }
 
-// Row k of H^D: the nonzero H_kj = <D_k|H|D_j>, j != k, in ascending j (one
-// workgroup per row, positions by block scans).  With col == nullptr only
-// the counts are written.
+// H^D by removal keys.  Two distinct determinants of the space are connected
+// (a single or a double excitation) exactly when, in one of five classes,
+// taking electrons out of each leaves the same pair of strings:
+//   0: equal alpha, beta single (one beta out)    1: equal alpha, beta double (two beta out)
+//   2: equal beta, alpha single (one alpha out)   3: equal beta, alpha double (two alpha out)
+//   4: alpha single and beta single (one of each out)
+// and the strings left are the two determinants' intersection, so a
+// connected pair shares exactly one key of exactly one class (its class
+// test below rejects the pairs that share a key of a class not theirs).
+// Each class is processed on its own: every (determinant, removal) entry is
+// hashed into an open-addressing table of counts, entries whose key occurs
+// twice or more are gathered into groups, and the pairs of each group are
+// tested exactly (the strings themselves, not the hash) and evaluated.  The
+// work is linear in the entries (at most C(n,2) per determinant and class)
+// plus the pairs within groups, instead of quadratic in the space.
+__device__ __forceinline__ int rk_removals(int c, int na, int nb) {
+    switch (c) {
+        case 0: return nb;
+        case 1: return nb * (nb - 1) / 2;
+        case 2: return na;
+        case 3: return na * (na - 1) / 2;
+        default: return na * nb;
+    }
+}
+
+// Removal m of class c from (a, b): the strings left.
+__device__ __forceinline__ void rk_removal(int c, uint64_t a, uint64_t b, int m, int nb, uint64_t& ra, uint64_t& rb) {
+    ra = a;
+    rb = b;
+    int x, y;
+    switch (c) {
+        case 0: rb &= ~(1ULL << select64(b, m)); break;
+        case 1:
+            pair_decode((uint64_t)m, popc64(b), x, y);
+            rb &= ~((1ULL << select64(b, x)) | (1ULL << select64(b, y)));
+            break;
+        case 2: ra &= ~(1ULL << select64(a, m)); break;
+        case 3:
+            pair_decode((uint64_t)m, popc64(a), x, y);
+            ra &= ~((1ULL << select64(a, x)) | (1ULL << select64(a, y)));
+            break;
+        default:
+            ra &= ~(1ULL << select64(a, m / nb));
+            rb &= ~(1ULL << select64(b, m % nb));
+            break;
+    }
+}
+
+// The pair belongs to class c (given equal removal keys of that class).
+__device__ __forceinline__ bool rk_class_pair(int c, uint64_t a1, uint64_t b1, uint64_t a2, uint64_t b2) {
+    const int da = popc64(a1 ^ a2), db = popc64(b1 ^ b2);
+    switch (c) {
+        case 0: return da == 0 && db == 2;
+        case 1: return da == 0 && db == 4;
+        case 2: return db == 0 && da == 2;
+        case 3: return db == 0 && da == 4;
+        default: return da == 2 && db == 2;
+    }
+}
+
+__device__ __forceinline__ uint64_t rk_hash(uint64_t ra, uint64_t rb) {
+    uint64_t h = mix64(ra ^ mix64(rb + 0x2545F4914F6CDD1DULL));
+    return h == kEmpty ? kEmpty - 2 : h;
+}
+
+struct RkPass {
+    int cls, na, nb, part, nparts;
+    int64_t n, m;        // determinants, removals per determinant
+    uint64_t mask;       // table slots - 1
+};
+
+__device__ __forceinline__ bool rk_mine(const RkPass& P, uint64_t h) {
+    return P.nparts == 1 || (int)((h >> 40) % (uint64_t)P.nparts) == P.part;
+}
+
+// Count the entries of this pass's keys (th preset to kEmpty, tc to 0).
 template <int W>
-__global__ __launch_bounds__(kThreads) void k_core_rows(SysView sys, const uint64_t* __restrict__ keys, int64_t n,
-                                                        const int64_t* __restrict__ rowp, int32_t* __restrict__ col,
-                                                        double* __restrict__ val, int64_t* __restrict__ cnt) {
-    __shared__ int64_t sh[kThreads / 64];
-    for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
-        const Key<W> kk = load_key<W>(keys + k * W);
-        const uint64_t ak = key_alpha<W>(kk), bk = key_beta<W>(kk);
-        int64_t base = 0;
-        for (int64_t j0 = 0; j0 < n; j0 += kThreads) {
-            const int64_t j = j0 + threadIdx.x;
-            double h = 0.0;
-            if (j < n && j != k) {
-                const Key<W> kj = load_key<W>(keys + j * W);
-                const uint64_t aj = key_alpha<W>(kj), bj = key_beta<W>(kj);
-                if (popc64(ak ^ aj) + popc64(bk ^ bj) <= 4) h = h_offdiag(sys, aj, bj, ak, bk);
-            }
-            const bool nz = h != 0.0;
-            int64_t tot;
-            const int64_t ex = block_excl_scan<kThreads, int64_t>(nz ? 1 : 0, tot, sh);
-            if (nz && col) {
-                col[rowp[k] + base + ex] = (int32_t)j;
-                val[rowp[k] + base + ex] = h;
-            }
-            base += tot;
+__global__ void k_rk_count(const uint64_t* __restrict__ keys, RkPass P, uint64_t* __restrict__ th,
+                           uint32_t* __restrict__ tc, unsigned* __restrict__ err) {
+    const int64_t total = P.n * P.m;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e / P.m;
+        const Key<W> key = load_key<W>(keys + k * W);
+        uint64_t ra, rb;
+        rk_removal(P.cls, key_alpha<W>(key), key_beta<W>(key), (int)(e - k * P.m), P.nb, ra, rb);
+        const uint64_t h = rk_hash(ra, rb);
+        if (!rk_mine(P, h)) continue;
+        uint64_t s = h & P.mask;
+        for (uint64_t probe = 0;; ++probe) {
+            if (probe > P.mask) { atomicOr(err, 1u); break; }
+            const uint64_t old = atomicCAS((unsigned long long*)&th[s], kEmpty, h);
+            if (old == kEmpty || old == h) { atomicAdd(&tc[s], 1u); break; }
+            s = (s + 1) & P.mask;
         }
-        if (!col && threadIdx.x == 0) cnt[k] = base;
+    }
+}
+
+// Groups: the slots counted twice or more get a group (index in tg, start
+// and size), the others -1.
+__global__ void k_rk_groups(const uint32_t* __restrict__ tc, uint64_t slots, int32_t* __restrict__ tg,
+                            int64_t* __restrict__ gstart, uint32_t* __restrict__ gsize, int64_t gcap,
+                            unsigned long long* __restrict__ totals, unsigned* __restrict__ err) {
+    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots; s += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = tc[s];
+        int32_t g = -1;
+        if (c >= 2) {
+            const unsigned long long gi = atomicAdd(&totals[0], 1ULL);
+            const unsigned long long st = atomicAdd(&totals[1], (unsigned long long)c);
+            if ((int64_t)gi < gcap) {
+                g = (int32_t)gi;
+                gstart[gi] = (int64_t)st;
+                gsize[gi] = c;
+            } else {
+                atomicOr(err, 2u);
+            }
+        }
+        tg[s] = g;
+    }
+}
+
+// Entries of grouped keys into their group's range of gm (k << 32 | m).
+template <int W>
+__global__ void k_rk_scatter(const uint64_t* __restrict__ keys, RkPass P, const uint64_t* __restrict__ th,
+                             const int32_t* __restrict__ tg, const int64_t* __restrict__ gstart,
+                             uint32_t* __restrict__ gfill, uint64_t* __restrict__ gm, int64_t gmcap) {
+    const int64_t total = P.n * P.m;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e / P.m;
+        const Key<W> key = load_key<W>(keys + k * W);
+        const int m = (int)(e - k * P.m);
+        uint64_t ra, rb;
+        rk_removal(P.cls, key_alpha<W>(key), key_beta<W>(key), m, P.nb, ra, rb);
+        const uint64_t h = rk_hash(ra, rb);
+        if (!rk_mine(P, h)) continue;
+        uint64_t s = h & P.mask;
+        for (uint64_t probe = 0; probe <= P.mask && th[s] != h; ++probe) s = (s + 1) & P.mask;
+        if (th[s] != h) continue;  // counted above, so present; a table error is flagged there
+        const int32_t g = tg[s];
+        if (g < 0) continue;
+        const int64_t pos = gstart[g] + (int64_t)atomicAdd(&gfill[g], 1u);
+        if (pos < gmcap) gm[pos] = ((uint64_t)k << 32) | (uint32_t)m;
+    }
+}
+
+// The pairs of each group, one wave per group: equal removal keys (the
+// strings, exactly) and the class test make a connected pair, found once.
+// Row x gets H_xy = <D_x|H|D_y> and row y gets H_yx, each where nonzero:
+// counted into cnt (rowp == nullptr) or stored at the row's next place.
+template <int W>
+__global__ __launch_bounds__(256) void k_rk_pairs(SysView sys, const uint64_t* __restrict__ keys, RkPass P,
+                                                  const int64_t* __restrict__ gstart,
+                                                  const uint32_t* __restrict__ gsize, int64_t ngroups,
+                                                  const uint64_t* __restrict__ gm,
+                                                  unsigned long long* __restrict__ cnt,
+                                                  const int64_t* __restrict__ rowp,
+                                                  unsigned long long* __restrict__ rfill,
+                                                  int32_t* __restrict__ col, double* __restrict__ val) {
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t g = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); g < ngroups; g += waves) {
+        const int64_t L = gsize[g], g0 = gstart[g];
+        for (int64_t x = 0; x + 1 < L; ++x) {
+            // entry x is the wave's; its partners y > x are spread over the lanes
+            const uint64_t ex = gm[g0 + x];
+            const int64_t kx = (int64_t)(ex >> 32);
+            const Key<W> Kx = load_key<W>(keys + kx * W);
+            const uint64_t ax = key_alpha<W>(Kx), bx = key_beta<W>(Kx);
+            uint64_t rax, rbx;
+            rk_removal(P.cls, ax, bx, (int)(uint32_t)ex, P.nb, rax, rbx);
+          for (int64_t y = x + 1 + lane_id(); y < L; y += 64) {
+            const uint64_t ey = gm[g0 + y];
+            const int64_t ky = (int64_t)(ey >> 32);
+            if (kx == ky) continue;
+            const Key<W> Ky = load_key<W>(keys + ky * W);
+            const uint64_t ay = key_alpha<W>(Ky), by = key_beta<W>(Ky);
+            uint64_t ray, rby;
+            rk_removal(P.cls, ay, by, (int)(uint32_t)ey, P.nb, ray, rby);
+            if (rax != ray || rbx != rby || !rk_class_pair(P.cls, ax, bx, ay, by)) continue;
+            const double hxy = h_offdiag(sys, ay, by, ax, bx);
+            const double hyx = h_offdiag(sys, ax, bx, ay, by);
+            if (!rowp) {
+                if (hxy != 0.0) atomicAdd(&cnt[kx], 1ULL);
+                if (hyx != 0.0) atomicAdd(&cnt[ky], 1ULL);
+            } else {
+                // the counting sweep found the same pairs, so each row fills
+                // exactly its count; the bound only guards the buffer
+                if (hxy != 0.0) {
+                    const int64_t p = rowp[kx] + (int64_t)atomicAdd(&rfill[kx], 1ULL);
+                    if (p < rowp[kx + 1]) { col[p] = (int32_t)ky; val[p] = hxy; }
+                }
+                if (hyx != 0.0) {
+                    const int64_t p = rowp[ky] + (int64_t)atomicAdd(&rfill[ky], 1ULL);
+                    if (p < rowp[ky + 1]) { col[p] = (int32_t)kx; val[p] = hyx; }
+                }
+            }
+          }
+        }
     }
 }
 

@@ -84,7 +84,7 @@ EXPORTS = ["fciqmc_params_default", "fciqmc_load_integrals", "fciqmc_init", "fci
            "fciqmc_batch_set_persistent",
            "fciqmc_batch_free", "fciqmc_estimate_bytes", "fciqmc_server_create",
            "fciqmc_server_submit", "fciqmc_server_poll", "fciqmc_server_info",
-           "fciqmc_server_clock", "fciqmc_server_free", "fciqmc_set_core", "fciqmc_get_core",
+           "fciqmc_server_clock", "fciqmc_server_free", "fciqmc_set_core", "fciqmc_get_core", "fciqmc_get_core_row",
            "fciqmc_pair_create", "fciqmc_pair_step", "fciqmc_pair_pt2", "fciqmc_pair_free",
            "fciqmc_pair_rdm_enable", "fciqmc_pair_rdm",
            "fciqmc_free_run", "fciqmc_free_system", "fciqmc_last_error"]
@@ -120,6 +120,8 @@ def lib():
         L.fciqmc_set_walkers.argtypes = [vp, pu64, pdbl, i64]
         L.fciqmc_set_core.argtypes = [vp, i64, C.POINTER(i64)]
         L.fciqmc_get_core.argtypes = [vp, pu64, i64, C.POINTER(i64), C.POINTER(i64)]
+        L.fciqmc_get_core_row.argtypes = [vp, i64, C.POINTER(C.c_int32), C.POINTER(C.c_double), i64,
+                                          C.POINTER(i64)]
         L.fciqmc_get_checkpoint.argtypes = [vp, C.POINTER(Checkpoint)]
         L.fciqmc_get_reference.argtypes = [vp, C.POINTER(u64), C.POINTER(u64), pdbl]
         L.fciqmc_set_checkpoint.argtypes = [vp, C.POINTER(Checkpoint)]
@@ -381,6 +383,16 @@ def fciqmc_get_core(run: Run):
     _check(lib().fciqmc_get_core(run.handle, _p(d, C.c_uint64), n.value, None, None))
     d = d[:2 * n.value].reshape(-1, 2)
     return d[:, 0].copy(), d[:, 1].copy(), nnz.value
+
+
+def fciqmc_get_core_row(run: Run, k: int):
+    """(column indices into D, H_kj) of row k of H^D, in the library's order."""
+    n = C.c_int64(0)
+    _check(lib().fciqmc_get_core_row(run.handle, int(k), None, None, 0, C.byref(n)))
+    cols = np.zeros(max(n.value, 1), dtype=np.int32)
+    vals = np.zeros(max(n.value, 1), dtype=np.float64)
+    _check(lib().fciqmc_get_core_row(run.handle, int(k), _p(cols, C.c_int32), _p(vals, C.c_double), n.value, None))
+    return cols[:n.value].copy(), vals[:n.value].copy()
 
 
 def fciqmc_get_checkpoint(run: Run) -> dict:

@@ -9,7 +9,7 @@ import pytest
 from paper_2006_14956_amd import fciqmc as F
 from paper_2006_14956_amd import inputs
 from tests import brute
-from tests.gpu_helpers import assert_same_walkers, make_pair, ref_of
+from tests.gpu_helpers import assert_same_walkers, make_gpu_run, make_pair, ref_of
 
 pytestmark = pytest.mark.gpu
 
@@ -118,4 +118,84 @@ def test_deterministic_space_rules():
     F.fciqmc_set_walkers(run2, a, b, v)
     assert F.fciqmc_get_core(run2)[0].size == 0
     F.fciqmc_free_run(run2)
+    F.fciqmc_free_system(sysd)
+
+
+def _space_population(s, n_orb, na, nb, seed):
+    """Every determinant of the space, with seeded real coefficients whose
+    magnitudes are distinct (so the n most populated are unambiguous)."""
+    dets = brute.basis(n_orb, na, nb)
+    a = np.array([d[0] for d in dets], dtype=np.uint64)
+    b = np.array([d[1] for d in dets], dtype=np.uint64)
+    rng = np.random.default_rng(seed)
+    v = 0.5 + 10.0 * rng.permutation(len(dets)).astype(np.float64) / len(dets)
+    v *= rng.choice([-1.0, 1.0], size=len(dets))
+    return a, b, v
+
+
+def _oracle_row(osys, ca, cb, k):
+    """Row k of H^D from the oracle: (column indices, values) of its nonzeros."""
+    h = osys.hij_row(ca[k], cb[k], ca, cb)
+    j = np.nonzero(h)[0]
+    return j, h[j]
+
+
+def _gpu_row(run, k):
+    c, v = F.fciqmc_get_core_row(run, k)
+    o = np.argsort(c, kind="stable")
+    return c[o].astype(np.int64), v[o]
+
+
+def test_hd_rows_equal_the_oracle_whole_space():
+    """Every row of H^D over the whole 3136-determinant space of an 8-orbital
+    molecule (3 alpha, 3 beta): the columns and values found from removal
+    keys are those of the oracle's all-pairs matrix, bit for bit."""
+    import oracle
+    s = inputs.synthetic_molecule(8, 3, 3, seed=31)
+    sysd, run = make_gpu_run(s, tau=0.01, target=1e12, mode="real", seed=1)
+    a, b, v = _space_population(s, 8, 3, 3, seed=4)
+    F.fciqmc_set_walkers(run, a, b, v)
+    assert F.fciqmc_set_core(run, len(a)) == len(a)
+    ca, cb, nnz = F.fciqmc_get_core(run)
+    osys = oracle.System.from_inputs(s, words=1)
+    total = 0
+    for k in range(len(ca)):
+        gj, gv = _gpu_row(run, k)
+        oj, ov = _oracle_row(osys, ca, cb, k)
+        assert np.array_equal(gj, oj), k
+        assert np.array_equal(gv, ov), k
+        total += len(oj)
+    assert nnz == total
+    F.fciqmc_free_run(run)
+    F.fciqmc_free_system(sysd)
+
+
+def test_hd_beyond_the_all_pairs_size():
+    """A deterministic space of 300000 determinants (the 12-orbital, 5+5
+    electron space has 627264), twice the largest the all-pairs construction
+    took: the space is the 300000 largest |C|, and sampled rows of H^D (the
+    first, the last and 40 seeded ones) equal the oracle's bit for bit."""
+    import oracle
+    s = inputs.synthetic_molecule(12, 5, 5, seed=37)
+    sysd, run = make_gpu_run(s, tau=0.01, target=1e12, mode="real", seed=1)
+    a, b, v = _space_population(s, 12, 5, 5, seed=6)
+    F.fciqmc_set_walkers(run, a, b, v)
+    n = 300000
+    assert F.fciqmc_set_core(run, n) == n
+    ca, cb, nnz = F.fciqmc_get_core(run)
+    # the space is the n largest |C| (all distinct), ordered by determinant
+    top = np.argsort(-np.abs(v), kind="stable")[:n]
+    want = sorted(zip(a[top].tolist(), b[top].tolist()))
+    assert list(zip(ca.tolist(), cb.tolist())) == want
+    osys = oracle.System.from_inputs(s, words=1)
+    rows = [0, n - 1] + list(np.random.default_rng(8).choice(n, size=40, replace=False))
+    for k in rows:
+        gj, gv = _gpu_row(run, int(k))
+        oj, ov = _oracle_row(osys, ca, cb, int(k))
+        assert np.array_equal(gj, oj), k
+        assert np.array_equal(gv, ov), k
+    sizes = [F.fciqmc_get_core_row(run, k)[0].size for k in range(0, n, 997)]
+    assert all(x > 0 for x in sizes)
+    assert nnz > 100 * n
+    F.fciqmc_free_run(run)
     F.fciqmc_free_system(sysd)
