@@ -802,6 +802,9 @@ def main():
                     help="only run the semi-stochastic comparison")
     ap.add_argument("--generators-only", action="store_true",
                     help="only run the generator comparison")
+    ap.add_argument("--hd-build", type=int, default=1000000, metavar="N_CORE",
+                    help="after the timed steps, time making the N_CORE most populated determinants of the "
+                         "headline population a deterministic space (H^D from removal keys); 0 to skip")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 5 device-to-device copies of BYTES (the known-size copy "
                          "that scales rocprofv3 FETCH_SIZE/WRITE_SIZE readings)")
@@ -853,6 +856,20 @@ def main():
     attempts = int(st["attempts"].sum())
     value = attempts / wall
     roof_ann = roofline(kern, "annihilate", args.workload)
+    hd_build = None
+    if args.hd_build and desc.get("walkers") == "real":
+        # the deterministic space of the settled population: selection of the
+        # most populated (host), then H^D on the device; timed end to end
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n_core = F.fciqmc_set_core(run, args.hd_build)
+        t1 = time.perf_counter()
+        _, _, nnz = F.fciqmc_get_core(run)
+        hd_build = {"n_core": int(n_core), "nnz": int(nnz), "seconds": t1 - t0,
+                    "from_dets": int(desc.get("dets_mean", 0)),
+                    "note": "fciqmc_set_core on the headline population after its timed steps: "
+                            "selection of the most populated determinants and H^D by removal keys"}
+        log(f"H^D of {n_core} determinants: {nnz} nonzeros in {t1 - t0:.2f} s")
     F.fciqmc_free_run(run)
     F.fciqmc_free_system(sysd)
     run = sysd = None
@@ -922,6 +939,7 @@ def main():
         "roofline": roof,
         "roofline_annihilate": roof_ann,
         "cpu_baseline": cpu,
+        "hd_build": hd_build,
         "second_workload": second,
         "generators": generators,
         "semistoch": semistoch,

@@ -807,12 +807,14 @@ template <int W, class V> struct Engine : EngineBase {
         if (nc == 0) return 0;
         std::vector<int64_t> ord((size_t)n);
         for (int64_t i = 0; i < n; ++i) ord[(size_t)i] = i;
-        std::partial_sort(ord.begin(), ord.begin() + nc, ord.end(), [&](int64_t x, int64_t y) {
+        // the nc first under a strict total order (a selection, linear in n)
+        auto before = [&](int64_t x, int64_t y) {
             const double ax = std::fabs(vals[(size_t)x]), ay = std::fabs(vals[(size_t)y]);
             if (ax != ay) return ax > ay;
             if (ab[2 * x] != ab[2 * y]) return ab[2 * x] < ab[2 * y];
             return ab[2 * x + 1] < ab[2 * y + 1];
-        });
+        };
+        if (nc < n) std::nth_element(ord.begin(), ord.begin() + nc, ord.end(), before);
         std::vector<std::pair<uint64_t, uint64_t>> dets((size_t)nc);
         for (int64_t k = 0; k < nc; ++k) dets[(size_t)k] = {ab[2 * ord[(size_t)k]], ab[2 * ord[(size_t)k] + 1]};
         std::sort(dets.begin(), dets.end());
