@@ -1420,6 +1420,7 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
     int64_t btot = 0;
     int64_t ftot = 0;           // work items of the new-diagonal kernel
     size_t flds = 0;            // its LDS bytes (largest molecular member)
+    size_t flds_tab = 0;        // the same without the orbital lists (persistent launch)
 
     Arena arena_bar;            // holds bar (kept across reserve())
     ~BatchGroup() override {
@@ -1467,6 +1468,7 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
         btot = 0;
         ftot = 0;
         flds = 0;
+        flds_tab = 0;
         for (size_t i = 0; i < n; ++i) {
             if (runs[i]->rechoose_pending) {
                 CHECK(rechoose_reference(runs[i]));
@@ -1479,6 +1481,7 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
             if (!hi[i].sys.onsite) {
                 ftot += fresh_items(eng(i)->B);
                 flds = std::max(flds, fresh_lds_bytes(hi[i].sys.N, hi[i].sys.na + hi[i].sys.nb));
+                flds_tab = std::max(flds_tab, fresh_lds_bytes(hi[i].sys.N, 0));
             }
         }
         bf[n] = btot;
@@ -1540,7 +1543,7 @@ template <int W, class V> struct BatchGroup : BatchGroupBase {
             default: fn = reinterpret_cast<const void*>(&k_batch_step<W, V, -1>); break;
         }
         // dynamic LDS: the new-diagonal tables of the largest molecular member
-        const size_t lds = std::max<size_t>(flds, sizeof(double));
+        const size_t lds = std::max<size_t>(flds_tab, sizeof(double));
         int& mb = max_blocks[gen + 1];
         if (mb == 0 || mb_lds[gen + 1] != lds) {
             int per_cu = 0, cus = 0, dev = 0;

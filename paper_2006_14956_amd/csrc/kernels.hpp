@@ -1114,7 +1114,10 @@ __device__ __forceinline__ double h_diag_list(const double* hd, const double* X,
     return acc;
 }
 
-template <int W, class V>
+// With LISTS the lanes' orbital lists follow the tables in `tabs`
+// (fresh_lds_bytes); without, the sums walk the bit masks (the persistent
+// batch kernel, whose LDS would otherwise cost it a workgroup per CU).
+template <int W, class V, bool LISTS = true>
 __device__ __forceinline__ void fresh_item(const SysView& sys, const Store<V>& out, double h00, int R, int B,
                                            const uint16_t* __restrict__ fpos, const int32_t* __restrict__ fcnt,
                                            int64_t g, double* tabs, int* pre) {
@@ -1145,11 +1148,16 @@ __device__ __forceinline__ void fresh_item(const SysView& sys, const Store<V>& o
         const int64_t base = (int64_t)(b0 + lo) * R;
         const int64_t e = base + fpos[base + (t - pre[lo])];
         const Key<W> key = load_key<W>(out.keys + e * W);
-        // every determinant of the store has na alpha and nb beta electrons
-        int i = 0;
-        for (uint64_t x = key_alpha<W>(key); x; x &= x - 1) occ[(i++) * kThreads] = (uint8_t)ctz64(x);
-        for (uint64_t x = key_beta<W>(key); x; x &= x - 1) occ[(i++) * kThreads] = (uint8_t)ctz64(x);
-        const double h = h_diag_list(hd, xt, jt, N, sys.na, sys.nb, occ);
+        double h;
+        if constexpr (LISTS) {
+            // every determinant of the store has na alpha and nb beta electrons
+            int i = 0;
+            for (uint64_t x = key_alpha<W>(key); x; x &= x - 1) occ[(i++) * kThreads] = (uint8_t)ctz64(x);
+            for (uint64_t x = key_beta<W>(key); x; x &= x - 1) occ[(i++) * kThreads] = (uint8_t)ctz64(x);
+            h = h_diag_list(hd, xt, jt, N, sys.na, sys.nb, occ);
+        } else {
+            h = h_diag_tab(hd, xt, jt, N, key_alpha<W>(key), key_beta<W>(key));
+        }
         out.diag[e] = h - h00;
     }
     __syncthreads();
@@ -1599,7 +1607,7 @@ __global__ __launch_bounds__(kThreads, 6) void k_batch_step(const Inst<W, V>* __
         const Inst<W, V>& I = inst[i];
         if (I.sys.onsite) continue;
         if (wg_flags(I.ctl, &fl)) continue;
-        fresh_item<W, V>(I.sys, I.out, I.sc.h00, I.sc.R, I.sc.B, I.fpos, I.fcnt, g - ffirst[i], tabs, pre);
+        fresh_item<W, V, false>(I.sys, I.out, I.sc.h00, I.sc.R, I.sc.B, I.fpos, I.fcnt, g - ffirst[i], tabs, pre);
     }
     if (!grid_barrier(bar, &ok)) return;
     // post work, one workgroup per member
