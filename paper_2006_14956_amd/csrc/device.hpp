@@ -169,13 +169,25 @@ __device__ __forceinline__ void set_so(uint64_t& A, uint64_t& B, int s, int p) {
     if (s == 0) A |= (1ULL << p); else B |= (1ULL << p);
 }
 
-// Decode a lexicographic pair index q over C(n,2) pairs (x<y) of n items.
-__device__ __forceinline__ void pair_decode(uint64_t q, int n, int& x, int& y) {
-    int e = 0;
-    uint64_t row = (uint64_t)(n - 1);
-    while (row > 0 && q >= row) { q -= row; ++e; --row; }
-    x = e; y = e + 1 + (int)q;
+// Decode a lexicographic pair index q over C(n,2) pairs (x<y) of n items
+// (n <= 128): x is the last row whose first index off(x) = x(2n-x-1)/2 is
+// <= q, from the quadratic's root in single precision, then set exactly by
+// comparing with off(x) and off(x+1).
+__device__ __forceinline__ void pair_decode(uint64_t q64, int n, int& x, int& y) {
+    const int q = (int)q64;
+    const int m = 2 * n - 1;
+    int e = (int)(((float)m - sqrtf((float)(m * m - 8 * q))) * 0.5f);
+    e = e < 0 ? 0 : (e > n - 2 ? n - 2 : e);
+    if (e * (m - e) / 2 > q) --e;
+    if ((e + 1) * (m - e - 1) / 2 <= q) ++e;
+    x = e;
+    y = e + 1 + (q - e * (m - e) / 2);
 }
+
+// floor(q / d) for q < 4096 and 1 <= d <= 64 from m = ceil(2^20 / d): exact,
+// since q d < 2^20, and q m < 2^32 (Granlund and Montgomery's division by
+// invariant integers; the pair and column indices of N <= 64 orbitals).
+__device__ __forceinline__ uint32_t div_small(uint32_t q, uint32_t m) { return (q * m) >> 20; }
 
 // --------------------------------------------------------------------------
 // Integrals.
@@ -215,6 +227,7 @@ struct SysView {
     const double* hb_sum_opp;   // row sums of the weights
     const double* hb_sum_same;
     const int* pair_of;   // same-spin column index -> A*64+B
+    uint32_t mN, mnb;     // ceil(2^20 / N), ceil(2^20 / nb) (0 for nb = 0): div_small multipliers
 };
 
 __device__ __forceinline__ int tri(int p, int q) { return p >= q ? p * (p + 1) / 2 + q : q * (q + 1) / 2 + p; }
@@ -429,8 +442,11 @@ __device__ __forceinline__ bool gen_lattice(const SysView& s, uint64_t a, uint64
 // pair, row, table, column decoding and spins), so that a wave whose lanes
 // draw both classes executes it once; each class's arithmetic is the one it
 // has on its own.
+// p2o, p2s: the class factors p_double p_opp / (n_alpha n_beta) and
+// p_double (1 - p_opp) / n_equal-spin-pairs, formed once per step.
 __device__ __forceinline__ bool gen_pchb(const SysView& s, uint64_t a, uint64_t b, const R4& r,
-                                         double p_single, double p_double, double p_opp, Exc& out) {
+                                         double p_single, double p_double, double p_opp, double p2o, double p2s,
+                                         Exc& out) {
     const int N = s.N, na = s.na, nb = s.nb;
     const double u0 = unif(r.x[0]);
     if (u0 < p_single) return gen_uniform(s, a, b, r, p_single, p_double, out);
@@ -450,7 +466,7 @@ __device__ __forceinline__ bool gen_pchb(const SysView& s, uint64_t a, uint64_t 
     const uint32_t q = (uint32_t)(sg ? q0 - npa : q0);
     int e1, e2;
     if (opp) {
-        e1 = (int)(q / (uint32_t)nb);
+        e1 = (int)div_small(q, s.mnb);
         e2 = (int)(q - (uint32_t)e1 * (uint32_t)nb);
     } else {
         pair_decode(q, sg ? nb : na, e1, e2);
@@ -468,7 +484,7 @@ __device__ __forceinline__ bool gen_pchb(const SysView& s, uint64_t a, uint64_t 
     const int c = coin < en.prob ? c0 : en.alias;
     int A, Bo;
     if (opp) {
-        A = c / N;
+        A = (int)div_small((uint32_t)c, s.mN);
         Bo = c - A * N;
     } else {
         const int ab = s.pair_of[c];
@@ -489,8 +505,7 @@ __device__ __forceinline__ bool gen_pchb(const SysView& s, uint64_t a, uint64_t 
     const double wc = fabs(v);
     if (wc == 0.0) return false;
     const double sum = (opp ? s.hb_sum_opp : s.hb_sum_same)[row];
-    const double p1 = p_double * (opp ? p_opp : 1.0 - p_opp);
-    const double p2 = p1 / (double)ncls;
+    const double p2 = opp ? p2o : p2s;
     const double pab = wc / sum;
     out.pgen = p2 * pab;
     out.H = double_parity(a, b, sI, I, sJ, J, sA, A, sB, Bo) ? -v : v;

@@ -150,6 +150,8 @@ struct fciqmc_system {
         v.hb_sum_opp = hb_sum_opp;
         v.hb_sum_same = hb_sum_same;
         v.pair_of = pair_of;
+        v.mN = N > 0 ? (uint32_t)(((1u << 20) + N - 1) / N) : 0u;
+        v.mnb = nb > 0 ? (uint32_t)(((1u << 20) + nb - 1) / nb) : 0u;
         return v;
     }
     ~fciqmc_system() { arena.clear(); }
@@ -581,6 +583,16 @@ template <int W, class V> struct Engine : EngineBase {
         StepScalars sc{};
         sc.t = t; sc.seed = rs.seed; sc.replica = rs.replica;
         sc.tau = rs.tau; sc.p_single = rs.p_single; sc.p_double = rs.p_double; sc.p_opp = rs.p_opp;
+        {
+            // the heat-bath generator's class factors, as it would form them per draw
+            const double na = sys->na, nb = sys->nb;
+            const double n_opp = na * nb;
+            const double n_same = na * (na > 0 ? na - 1 : 0) / 2 + nb * (nb > 0 ? nb - 1 : 0) / 2;
+            const double p1o = rs.p_double * rs.p_opp;
+            const double p1s = rs.p_double * (1.0 - rs.p_opp);
+            sc.p2_opp = n_opp > 0 ? p1o / n_opp : 0.0;
+            sc.p2_same = n_same > 0 ? p1s / n_same : 0.0;
+        }
         sc.n_a = rs.n_a; sc.c_min = rs.c_min; sc.S = S; sc.h00 = rs.h00;
         sc.ref_a = rs.ref_a; sc.ref_b = rs.ref_b;
         sc.B = B; sc.R = R; sc.spawn_cap = cap; sc.import_mode = import_mode;

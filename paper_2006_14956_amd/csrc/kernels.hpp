@@ -120,6 +120,7 @@ struct StepScalars {
     int64_t t;
     uint64_t seed, replica;
     double tau, p_single, p_double, p_opp, n_a, c_min, S, h00;
+    double p2_opp, p2_same;  // heat-bath class factors: p_double p_opp / (n_a n_b), p_double (1 - p_opp) / n_pairs
     uint64_t ref_a, ref_b;
     int B, R;
     long long spawn_cap;
@@ -254,7 +255,8 @@ __device__ __forceinline__ void spawn_chunk(const SysView& sys, const Store<V>& 
             bool ok;
             if constexpr (GEN == 0) ok = gen_uniform(sys, da, db, r, sc.p_single, sc.p_double, x);
             else if constexpr (GEN == 1) ok = gen_lattice(sys, da, db, r, x);
-            else if constexpr (GEN == 2) ok = gen_pchb(sys, da, db, r, sc.p_single, sc.p_double, sc.p_opp, x);
+            else if constexpr (GEN == 2)
+                ok = gen_pchb(sys, da, db, r, sc.p_single, sc.p_double, sc.p_opp, sc.p2_opp, sc.p2_same, x);
             else {
                 const R2 r2 = draw2<W>(key, sc.t, k, kSpawn2, sc.seed, sc.replica);
                 ok = gen_cs<GEN == 4>(sys, tJ, tSK, da, db, r, r2, sc.p_single, sc.p_double, sc.p_opp, x);
