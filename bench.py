@@ -482,7 +482,7 @@ def measure_generators(F, np, torch, n_dets, reps):
     sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
     N = s.n_orb
     npair = N * (N - 1) // 2
-    table_bytes = {"pchb": 32 * (N ** 4 + npair * npair) + 8 * (N * N + npair),
+    table_bytes = {"pchb": 16 * (N ** 4 + npair * npair) + 8 * (N * N + npair),
                    "cs": 8 * N * N, "pe": 8 * N * N}
     out = {}
     for name, g in (("pchb", F.GEN_PCHB), ("cs", F.GEN_CS), ("pe", F.GEN_PE)):
