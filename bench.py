@@ -482,8 +482,11 @@ def measure_generators(F, np, torch, n_dets, reps):
     sysd = F.fciqmc_load_integrals(s.n_orb, s.n_alpha, s.n_beta, s.e_core, s.h1, s.eri)
     N = s.n_orb
     npair = N * (N - 1) // 2
+    # heat-bath: 8-byte packed entries (what a draw reads), the exact FP64
+    # thresholds beside them (read on a 48-bit tie only) and the row sums
     table_bytes = {"pchb": 16 * (N ** 4 + npair * npair) + 8 * (N * N + npair),
                    "cs": 8 * N * N, "pe": 8 * N * N}
+    draw_bytes = {"pchb": 8 * (N ** 4 + npair * npair), "cs": 8 * N * N, "pe": 8 * N * N}
     out = {}
     for name, g in (("pchb", F.GEN_PCHB), ("cs", F.GEN_CS), ("pe", F.GEN_PE)):
         p = F.fciqmc_params_default(tau=0.0012, walker_target=1e12, initiator_na=3.0,
@@ -507,7 +510,8 @@ def measure_generators(F, np, torch, n_dets, reps):
                      "dets_after_step": int(st[0]["ndets"]), "spawn_ms_per_launch": sp,
                      "other_kernels_ms_per_launch": other,
                      "spawn_attempts_per_s": att / (sp * 1e-3) if sp > 0 else None,
-                     "generator_table_bytes": table_bytes[name], "sampled_steps": nsteps}
+                     "generator_table_bytes": table_bytes[name],
+                     "generator_draw_table_bytes": draw_bytes[name], "sampled_steps": nsteps}
         log(f"[generators] {name}: {att} attempts, spawn {sp:.3f} ms/launch "
             f"({out[name]['spawn_attempts_per_s']:.3e} attempts/s), "
             f"{out[name]['spawns_per_step']} spawns, {out[name]['dets_after_step']} dets, other "

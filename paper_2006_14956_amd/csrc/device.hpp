@@ -192,16 +192,19 @@ __device__ __forceinline__ uint32_t div_small(uint32_t q, uint32_t m) { return (
 // --------------------------------------------------------------------------
 // Integrals.
 // --------------------------------------------------------------------------
-// One column of a heat-bath alias table, one aligned 16-byte entry: the
-// alias threshold and column.  A draw reads one entry; the drawn column's
-// signed two-electron value v (whose magnitude is its weight) comes from the
-// packed integrals, a table small enough to stay in L2, so the alias tables
-// take half the memory of entries that carry both outcomes' values.
-struct alignas(16) HbEntry {
-    double prob;     // alias threshold of the column
-    int32_t alias;   // the column's alias
-    int32_t pad;
-};
+// One column of a heat-bath alias table, one 8-byte word: the alias
+// threshold prob (in [0, 1]) as T = floor(prob 2^48) in bits 15..63 and the
+// column's alias in bits 0..14.  A draw's 53-bit coin f (the table is taken
+// when f < prob 2^53) is decided by its top 48 bits against T; only when
+// those equal T (probability 2^-48) does the draw read the exact FP64
+// threshold, kept beside the table.  The drawn column's signed two-electron
+// value v (whose magnitude is its weight) comes from the packed integrals,
+// a table small enough to stay in L2.  The rows a population draws from
+// most (pairs of the orbitals most determinants occupy) then take a few MB.
+constexpr int kHbAliasBits = 15;
+__host__ __device__ __forceinline__ uint64_t hb_pack(double prob, int alias) {
+    return ((uint64_t)(prob * 0x1p48) << kHbAliasBits) | (uint64_t)alias;
+}
 
 struct SysView {
     int N, na, nb, n;
@@ -222,8 +225,10 @@ struct SysView {
     const double* lat_pz;
     // pre-computed heat-bath tables (see the PCHB generator)
     const double* SK;     // SK[p*N+q] = sqrt(|(pq|qp)|), the Cauchy-Schwarz hole weights
-    const HbEntry* hb_opp;   // rows (I alpha, J beta), N^2 columns each
-    const HbEntry* hb_same;  // rows I < J, N(N-1)/2 columns each
+    const uint64_t* hb_opp;   // rows (I alpha, J beta), N^2 columns each
+    const uint64_t* hb_same;  // rows I < J, N(N-1)/2 columns each
+    const double* hbp_opp;    // their exact alias thresholds, same layout
+    const double* hbp_same;
     const double* hb_sum_opp;   // row sums of the weights
     const double* hb_sum_same;
     const int* pair_of;   // same-spin column index -> A*64+B
@@ -278,6 +283,25 @@ __device__ __forceinline__ int double_parity(uint64_t a, uint64_t b, int si, int
     par += below(A, B, sb, pb);
     set_so(A, B, sb, pb);
     par += below(A, B, sa, pa);
+    return par & 1;
+}
+
+// The same sign where A takes the spin of I and B that of J (the heat-bath
+// draw), 1 if odd.  a_I passes a_J and a+_B (B is empty, so B != I), which
+// makes the operator (a+_A a_I)(a+_B a_J): the move J -> B on D_i, then
+// I -> A on what it leaves.  A move p -> h inside one spin string w flips
+// the sign once per occupied orbital strictly between p and h;
+// popc(w & (low(p) ^ low(h))) counts those and, when p < h, p itself.  The
+// second move sees J gone and B present, which changes its count only
+// where both pairs share a spin and J or B lies between I and A.  Equal to
+// double_parity(a, b, sI, I, sJ, J, sI, A, sJ, B) for every valid move.
+__device__ __forceinline__ int move_pair_parity(uint64_t a, uint64_t b, int sI, int I, int sJ, int J, int A,
+                                                int B) {
+    const uint64_t mI = low_mask(I) ^ low_mask(A);
+    const uint64_t mJ = low_mask(J) ^ low_mask(B);
+    const uint64_t wI = sI ? b : a, wJ = sJ ? b : a;
+    int par = popc64((wI & mI) ^ (wJ & mJ)) + (I < A ? 1 : 0) + (J < B ? 1 : 0);
+    if (sI == sJ) par += (int)(((mI >> J) ^ (mI >> B)) & 1ULL);
     return par & 1;
 }
 
@@ -477,11 +501,15 @@ __device__ __forceinline__ bool gen_pchb(const SysView& s, uint64_t a, uint64_t 
     const int J = select64(opp ? b : occ, e2);
     const int row = opp ? I * N + J : I * (2 * N - I - 1) / 2 + (J - I - 1);
     const int K = opp ? N * N : N * (N - 1) / 2;
-    const HbEntry* tab = opp ? s.hb_opp : s.hb_same;
+    const uint64_t* tab = opp ? s.hb_opp : s.hb_same;
     const int c0 = (int)pick(r.x[2], (uint64_t)K);
-    const double coin = unif(r.x[2] * (uint64_t)K);
-    const HbEntry en = tab[(size_t)row * (size_t)K + c0];
-    const int c = coin < en.prob ? c0 : en.alias;
+    const uint64_t fx = r.x[2] * (uint64_t)K;  // coin unif(fx): f = fx >> 11
+    const size_t at = (size_t)row * (size_t)K + (size_t)c0;
+    const uint64_t en = tab[at];
+    const uint64_t T = en >> kHbAliasBits, f48 = fx >> 16;
+    bool keep = f48 < T;
+    if (f48 == T) keep = unif(fx) < (opp ? s.hbp_opp : s.hbp_same)[at];
+    const int c = keep ? c0 : (int)(en & ((1u << kHbAliasBits) - 1u));
     int A, Bo;
     if (opp) {
         A = (int)div_small((uint32_t)c, s.mN);
@@ -508,7 +536,7 @@ __device__ __forceinline__ bool gen_pchb(const SysView& s, uint64_t a, uint64_t 
     const double p2 = opp ? p2o : p2s;
     const double pab = wc / sum;
     out.pgen = p2 * pab;
-    out.H = double_parity(a, b, sI, I, sJ, J, sA, A, sB, Bo) ? -v : v;
+    out.H = move_pair_parity(a, b, sI, I, sJ, J, A, Bo) ? -v : v;
     uint64_t TA = a, TB = b;
     clear_so(TA, TB, sI, I);
     clear_so(TA, TB, sJ, J);

@@ -134,7 +134,8 @@ struct fciqmc_system {
     double *lat_pe = nullptr, *lat_pz = nullptr;
     bool pchb = false;
     std::vector<double> h1_host, eri_host;  // host copies (variational energy of an RDM)
-    HbEntry *hb_opp = nullptr, *hb_same = nullptr;  // packed alias tables
+    uint64_t *hb_opp = nullptr, *hb_same = nullptr;  // packed alias tables
+    double *hbp_opp = nullptr, *hbp_same = nullptr;  // their exact thresholds
     double *hb_sum_opp = nullptr, *hb_sum_same = nullptr;  // their row sums
     int device = 0;
 
@@ -147,6 +148,8 @@ struct fciqmc_system {
         v.lat_pe = lat_pe; v.lat_pz = lat_pz;
         v.hb_opp = hb_opp;
         v.hb_same = hb_same;
+        v.hbp_opp = hbp_opp;
+        v.hbp_same = hbp_same;
         v.hb_sum_opp = hb_sum_opp;
         v.hb_sum_same = hb_sum_same;
         v.pair_of = pair_of;
@@ -161,17 +164,20 @@ static int build_pchb(fciqmc_system* s, hipStream_t stream) {
     if (s->pchb) return 0;
     const int N = s->N, NN = N * N, np = N * (N - 1) / 2;
     const size_t ko = (size_t)NN * NN, ks = (size_t)np * np;
-    // weights, alias thresholds, alias columns and row sums (scratch), then
-    // the packed tables the generator reads
+    // weights, alias columns (scratch), alias thresholds and row sums, then
+    // the packed tables the generator reads; a column index must fit the
+    // packed entry's alias field
+    if (NN > (1 << kHbAliasBits)) return fail(FCIQMC_EINVAL, "heat-bath tables take at most %d columns", 1 << kHbAliasBits);
     Arena tmp;
-    double *w_opp = nullptr, *p_opp = nullptr, *w_same = nullptr, *p_same = nullptr;
+    double *w_opp = nullptr, *w_same = nullptr;
     int *a_opp = nullptr, *a_same = nullptr;
     CHECK(dalloc(tmp, &w_opp, ko));
-    CHECK(dalloc(tmp, &p_opp, ko));
     CHECK(dalloc(tmp, &a_opp, ko));
     CHECK(dalloc(tmp, &w_same, ks + 1));
-    CHECK(dalloc(tmp, &p_same, ks + 1));
     CHECK(dalloc(tmp, &a_same, ks + 1));
+    CHECK(dalloc(s->arena, &s->hbp_opp, ko));
+    CHECK(dalloc(s->arena, &s->hbp_same, ks + 1));
+    double *p_opp = s->hbp_opp, *p_same = s->hbp_same;
     CHECK(dalloc(s->arena, &s->hb_sum_opp, NN));
     CHECK(dalloc(s->arena, &s->hb_sum_same, np + 1));
     CHECK(dalloc(s->arena, &s->hb_opp, ko));
@@ -2486,9 +2492,10 @@ extern "C" int fciqmc_pchb_row(const fciqmc_system* csys, int opp, int64_t row, 
     const int64_t K = opp ? N * N : N * (N - 1) / 2;
     if (row < 0 || row >= K) return fail(FCIQMC_EINVAL, "row %lld out of range [0, %lld)", (long long)row, (long long)K);
     CHECK(build_pchb(sys, nullptr));
-    std::vector<HbEntry> h((size_t)K);
-    const HbEntry* src = (opp ? sys->hb_opp : sys->hb_same) + (size_t)row * (size_t)K;
-    HIP_OK(hipMemcpy(h.data(), src, sizeof(HbEntry) * K, hipMemcpyDeviceToHost));
+    std::vector<uint64_t> h((size_t)K);
+    const size_t at = (size_t)row * (size_t)K;
+    HIP_OK(hipMemcpy(h.data(), (opp ? sys->hb_opp : sys->hb_same) + at, sizeof(uint64_t) * K, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(prob, (opp ? sys->hbp_opp : sys->hbp_same) + at, sizeof(double) * K, hipMemcpyDeviceToHost));
     HIP_OK(hipMemcpy(sum, (opp ? sys->hb_sum_opp : sys->hb_sum_same) + row, sizeof(double), hipMemcpyDeviceToHost));
     // the weights from the integrals, as the construction forms them: row
     // (I alpha, J beta) or I < J; column (A, B) ordered, or A < B in
@@ -2505,8 +2512,7 @@ extern "C" int fciqmc_pchb_row(const fciqmc_system* csys, int opp, int64_t row, 
     int64_t I, J;
     if (opp) { I = row / N; J = row % N; } else pair(row, I, J);
     for (int64_t c = 0; c < K; ++c) {
-        prob[c] = h[(size_t)c].prob;
-        alias[c] = h[(size_t)c].alias;
+        alias[c] = (int32_t)(h[(size_t)c] & ((1u << kHbAliasBits) - 1u));
         int64_t A, B;
         if (opp) { A = c / N; B = c % N; } else pair(c, A, B);
         double v;

@@ -564,6 +564,25 @@ __device__ __forceinline__ int lds_find(T& tab, const Key<W>& key, uint64_t h, u
     }
 }
 
+// Insert `key`, known to differ from every key inserted before or alongside
+// it, into an LDS table that no lane reads until the next barrier: the
+// first empty slot of its probe sequence, taken by one compare-and-swap of
+// the first word (the second is a plain store, visible after the barrier).
+// Returns the slot, -2 if the table is full.
+template <int W, class T>
+__device__ __forceinline__ int lds_insert_new(T& tab, const Key<W>& key, uint64_t h, uint64_t mask) {
+    int s = (int)(h & mask);
+    for (int probes = 0; probes <= (int)mask; ++probes) {
+        const uint64_t old = atomicCAS((unsigned long long*)&tab.key0[s], kEmpty, key.w[0]);
+        if (old == kEmpty) {
+            if constexpr (W == 2) tab.key1[s] = key.w[1];
+            return s;
+        }
+        s = (s + 1) & (int)mask;
+    }
+    return -2;
+}
+
 template <class V> __device__ __forceinline__ void lds_add(V* p, V v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -834,8 +853,9 @@ __device__ __forceinline__ void annihilate_bucket(const SysView& sys, const Stor
                 post = (V)y;
             }
         }
-        const int s = lds_find<W>(L.t, key, key_hash<W>(key), mask, true);
-        if (s < 0) { atomicOr(&ctl->flags, s == -2 ? kFlagTable : kFlagSpin); return; }
+        // the bucket's walkers are distinct determinants
+        const int s = lds_insert_new<W>(L.t, key, key_hash<W>(key), mask);
+        if (s < 0) { atomicOr(&ctl->flags, kFlagTable); return; }
         L.t.val[s] = post;
         L.t.idx[s] = e;
     };
@@ -1370,18 +1390,13 @@ __global__ void k_chunk_map(const int64_t* __restrict__ aoff, int B, int64_t* __
         for (int64_t c = aoff[b]; c < aoff[b + 1]; ++c) cmap[c] = ((int64_t)b << 32) | (c - aoff[b]);
 }
 
-// Pack the heat-bath tables into 16-byte entries: alias threshold and column
-// from the construction (the generator takes the drawn column's value from
-// the integrals).
+// Pack the heat-bath tables into 8-byte entries: 48-bit alias threshold and
+// column from the construction (the exact thresholds stay beside them; the
+// generator takes the drawn column's value from the integrals).
 __global__ void k_pchb_pack(const double* __restrict__ p, const int* __restrict__ a, size_t n,
-                            HbEntry* __restrict__ out) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        HbEntry e;
-        e.prob = p[i];
-        e.alias = a[i];
-        e.pad = 0;
-        out[i] = e;
-    }
+                            uint64_t* __restrict__ out) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = hb_pack(p[i], a[i]);
 }
 
 // ---------------------------------------------------------------------------
