@@ -42,18 +42,18 @@ __device__ __forceinline__ R2 philox4x32(uint32_t c0, uint32_t c1, uint32_t c2, 
     // rounds kept as a loop: the key schedule then stays two scalar adds per
     // round instead of twenty hoisted round keys per stream spilled to
     // vector lanes.  Two rounds per pass, so that the words land back in
-    // their own registers without moves.
+    // their own registers without moves.  Each product is formed as one
+    // 32x32 -> 64-bit multiply (one v_mad_u64_u32 gives both halves, where a
+    // separate high and low product take two quarter-rate instructions).
 #pragma unroll 1
     for (int r = 0; r < 5; ++r) {
-        const uint32_t h0 = __umulhi(M0, c0), l0 = M0 * c0;
-        const uint32_t h1 = __umulhi(M1, c2), l1 = M1 * c2;
-        const uint32_t a0 = h1 ^ c1 ^ k0, a1 = l1;
-        const uint32_t a2 = h0 ^ c3 ^ k1, a3 = l0;
+        const uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
+        const uint32_t a0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, a1 = (uint32_t)p1;
+        const uint32_t a2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1, a3 = (uint32_t)p0;
         k0 += W0; k1 += W1;
-        const uint32_t g0 = __umulhi(M0, a0), m0 = M0 * a0;
-        const uint32_t g1 = __umulhi(M1, a2), m1 = M1 * a2;
-        c0 = g1 ^ a1 ^ k0; c1 = m1;
-        c2 = g0 ^ a3 ^ k1; c3 = m0;
+        const uint64_t q0 = (uint64_t)M0 * a0, q1 = (uint64_t)M1 * a2;
+        c0 = (uint32_t)(q1 >> 32) ^ a1 ^ k0; c1 = (uint32_t)q1;
+        c2 = (uint32_t)(q0 >> 32) ^ a3 ^ k1; c3 = (uint32_t)q0;
         k0 += W0; k1 += W1;
     }
     R2 o;
