@@ -753,10 +753,14 @@ def measured_traffic(workload, kernel):
 
 def roofline(kern, k, workload=None):
     ab = kern[k]["algorithmic_bytes"]
-    achieved = ab / (kern[k]["ms_per_launch"] * 1e-3) / 1e9
+    sec = kern[k]["ms_per_launch"] * 1e-3
+    achieved = ab / sec / 1e9
+    traffic = measured_traffic(workload, k) if workload else None
+    # the measured traffic (L2 fills and write-backs, from the profile) over
+    # the same event-timed launch: what the memory system actually moves
     return {"bound": "hbm", "kernel": k, "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(workload, k) if workload else None,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_GBps": traffic / sec / 1e9 if traffic else None,
             "algorithmic_bytes_per_launch": ab, "ms_per_launch": kern[k]["ms_per_launch"]}
 
 
