@@ -17,6 +17,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import math
 import json
 import os
 import sys
@@ -112,8 +113,11 @@ def measure(F, np, torch, stream, name, steps, warmup):
         f"N_w={st[-1]['nw']:.4g} dets={st[-1]['ndets']} S={st[-1]['shift']:.4f}")
     if warmup:
         st = F.fciqmc_step(run, warmup)
+        ep = st[-1]["e_proj"]
+        eps = (f"E_proj={ep:.5f}" if math.isfinite(ep) else
+               "E_proj undefined (no walkers on the reference this step)")
         log(f"[{name}] warmup {warmup}: N_w={st[-1]['nw']:.4g} dets={st[-1]['ndets']} "
-            f"S={st[-1]['shift']:.4f} E_proj={st[-1]['e_proj']:.5f}")
+            f"S={st[-1]['shift']:.4f} {eps}")
     F.fciqmc_profile(run, True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
