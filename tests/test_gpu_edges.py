@@ -21,13 +21,15 @@ def _steps(run, orun, n, block):
     return g
 
 
-@pytest.mark.parametrize("n_orb,words,gen", [(63, 2, "uniform"), (63, 2, "pe"), (63, 2, "cs"), (32, 1, "uniform"),
-                                             (32, 1, "pchb"), (45, 2, "cs"), (46, 2, "cs")])
+@pytest.mark.parametrize("n_orb,words,gen", [(63, 2, "uniform"), (63, 2, "pe"), (63, 2, "cs"), (63, 2, "pchb"),
+                                             (32, 1, "uniform"), (32, 1, "pchb"), (45, 2, "cs"), (46, 2, "cs")])
 def test_largest_orbital_counts(n_orb, words, gen):
     """63 orbitals (every bit but the top of both words) and 32 orbitals (the
     full one-word layout): a random population, one step and five more.  45
     and 46 orbitals bracket the largest system whose Cauchy-Schwarz tables
-    the spawn kernel keeps in LDS."""
+    the spawn kernel keeps in LDS; at 63 orbitals the heat-bath tables have
+    their most columns (3969 per opposite-spin row), the widest alias field
+    of a packed entry."""
     s = inputs.synthetic_molecule(n_orb, 3, 2, seed=31, rank=6)
     sysd, run, orun = make_pair(s, tau=0.002, target=1e9, gen=gen, det_words=words, seed=5, n_a=2.0)
     ra, rb = ref_of(s)
